@@ -1,0 +1,191 @@
+/*
+ * maxwell.h -- C ABI of the MI355X (gfx950) encoding-operator library for
+ * Maxwell parallel imaging (Francavilla, Lefkimmiatis, Villena, Polimeridis,
+ * "Maxwell Parallel Imaging").
+ *
+ * The library computes, for every receive coil j = 0..J-1,
+ *
+ *     E(x, c)_j = F_s( (B c_j) (.) x )                  paper Sec. II-B, Eq. (5)
+ *
+ * and its Jacobian adjoint (Sec. II-B, the expression for J_G^H), the
+ * data-fidelity loss and its gradient.  Notation: x is the image (the
+ * paper's density p, N = n0*n1[*n2] voxels), c_j in C^K the basis
+ * coefficients of coil j (the paper's alpha_k, K its q), B the N x K basis
+ * (the paper's Maxwell basis U_h, Sec. II-D), dense or Tucker-factored
+ * (Sec. II-E), and F_s the undersampled Fourier operator (Sec. II-A, Eq. (1)):
+ * a centred unitary DFT followed by a Cartesian mask gather, or a
+ * Kaiser-Bessel NUFFT for non-Cartesian trajectories (Sec. III-B).  M is the
+ * number of k-space samples per coil (the paper's K).
+ *
+ * Conventions for every call
+ * --------------------------
+ * - Complex data are interleaved {float re, im} (maxwell_complex64; the same
+ *   bytes as torch.complex64 / float2), 8-byte aligned at least, C-order
+ *   (last index fastest).  Image arrays are [n0][n1] or [n0][n1][n2];
+ *   per-coil arrays are [J][...].
+ * - All array arguments of compute calls are DEVICE pointers on the device
+ *   that was current when the plan was created.  The caller owns every
+ *   buffer it passes.  The plan owns only private tables (mask, twiddles,
+ *   sample bins, deapodisation, split-BF16 copies of the basis).
+ * - The basis arrays named in maxwell_basis_desc are device pointers owned
+ *   by the caller; they must stay valid and unchanged for the plan's life.
+ * - Compute calls validate every argument on the host before any HIP call
+ *   and return a status; nothing aborts or throws across the ABI.  They are
+ *   asynchronous on `stream` (a hipStream_t; NULL = the null stream).  A
+ *   kernel fault surfaces as MAXWELL_ERR_HIP from a later call or from the
+ *   caller's own synchronisation, as HIP reports it.
+ * - Outputs must not overlap inputs (checked by address range).
+ * - Compute calls allocate nothing: all scratch comes from the caller's
+ *   workspace `ws` of `ws_bytes` bytes (>= maxwell_plan_workspace_size;
+ *   256-byte aligned).  plan_create / plan_destroy are the only calls that
+ *   allocate or free device memory.
+ * - maxwell_last_error() returns a thread-local message describing the most
+ *   recent non-OK status on the calling thread.
+ */
+#ifndef MAXWELL_H
+#define MAXWELL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { float re, im; } maxwell_complex64;
+
+typedef struct maxwell_plan_s* maxwell_plan_t;
+
+typedef enum {
+  MAXWELL_OK = 0,
+  MAXWELL_ERR_INVALID_ARGUMENT = -1,   /* null/misaligned pointer, bad size, overlap, bad mask */
+  MAXWELL_ERR_UNSUPPORTED = -2,        /* valid request this build does not implement        */
+  MAXWELL_ERR_OUT_OF_MEMORY = -3,      /* plan_create could not allocate its tables           */
+  MAXWELL_ERR_HIP = -4,                /* a HIP runtime call failed                           */
+  MAXWELL_ERR_WORKSPACE_TOO_SMALL = -5 /* ws_bytes < maxwell_plan_workspace_size()            */
+} maxwell_status;
+
+typedef enum { MAXWELL_BASIS_DENSE = 0, MAXWELL_BASIS_TUCKER = 1 } maxwell_basis_kind;
+
+/* Arithmetic of the basis contractions.  FP32: FP32 MFMA products with FP32
+ * accumulation.  BF16_SPLIT: each FP32 operand a is split as hi = bf16(a),
+ * lo = bf16(a - hi) (round to nearest even) and a*b is formed as
+ * hi_a hi_b + hi_a lo_b + lo_a hi_b on BF16 MFMA with FP32 accumulation.
+ * FFT, NUFFT and elementwise steps are FP32 in both; the loss is FP64.     */
+typedef enum { MAXWELL_FP32 = 0, MAXWELL_BF16_SPLIT = 1 } maxwell_precision;
+
+typedef enum { MAXWELL_CARTESIAN = 0, MAXWELL_NONCARTESIAN = 1 } maxwell_sampling_kind;
+
+/* Basis descriptor (paper Sec. II-B Eq. (5): s_j = B c_j; Sec. II-E: Tucker form).
+ * DENSE : `dense` is B, N x K row-major (row = C-order voxel index).
+ * TUCKER: column k of B reshaped to (n0, n1, n2) is
+ *         core[:, :, :, k] x_1 U[0] x_2 U[1] x_3 U[2], with the k-mode product
+ *         (A x_m U)[.., i, ..] = sum_p A[.., p, ..] U[i, p]  (Sec. II-E).
+ *         U[m] is n_m x r[m] row-major; core is r[0] x r[1] x r[2] x K row-major.
+ *         3D images only.                                                         */
+typedef struct {
+  maxwell_basis_kind kind;
+  int64_t K;
+  const maxwell_complex64* dense;
+  int64_t r[3];
+  const maxwell_complex64* U[3];
+  const maxwell_complex64* core;
+} maxwell_basis_desc;
+
+/* Problem geometry (paper Sec. II-A, Eq. (1): y = F S p + n, F = I_C (x) F_s).
+ * ndim      2 or 3; n[d] image size along axis d (even; prime factors 2, 3, 5 only;
+ *           every n[d] <= 4096).
+ * J         number of coils (>= 1).
+ * sampling  CARTESIAN: `mask_idx` holds M strictly ascending linear indices into the
+ *             centred k-space grid (C-order; grid index i on axis d <-> frequency
+ *             i - n[d]/2).  Host pointer, copied into the plan.
+ *           NONCARTESIAN (2D only): `traj` holds M x ndim floats in cycles/FOV,
+ *             column d paired with axis d, each in [-n[d]/2, n[d]/2).  Host pointer,
+ *             copied.  kb_width W (2..8), oversamp sigma (sigma*n[d] even), kb_beta
+ *             (<= 0: Beatty-Nishimura-Pauly, pi sqrt((W/sigma)^2 (sigma-1/2)^2 - 0.8)).
+ * weights   optional M nonnegative data weights w_m (host pointer, copied) used by
+ *           maxwell_forward_loss / maxwell_grad; NULL means w = 1.  They never enter
+ *           maxwell_encode or maxwell_adjoint.                                      */
+typedef struct {
+  int32_t ndim;
+  int64_t n[3];
+  int32_t J;
+  maxwell_precision precision;
+  maxwell_sampling_kind sampling;
+  int64_t M;
+  const int64_t* mask_idx;
+  const float* traj;
+  const float* weights;
+  int32_t kb_width;
+  float oversamp;
+  float kb_beta;
+} maxwell_plan_desc;
+
+/* Build a plan: validates the geometry, copies host tables, builds twiddle
+ * and sampling tables on the device, and (BF16_SPLIT) a split copy of the
+ * basis.  Allocates device memory; not capturable.                          */
+maxwell_status maxwell_plan_create(const maxwell_plan_desc* desc, const maxwell_basis_desc* basis,
+                                   maxwell_plan_t* plan_out);
+
+/* Release everything the plan allocated.  NULL is a no-op.  The caller must
+ * ensure no call using the plan is still running on any stream.             */
+void maxwell_plan_destroy(maxwell_plan_t plan);
+
+/* Workspace bytes every compute call of this plan needs.                    */
+maxwell_status maxwell_plan_workspace_size(maxwell_plan_t plan, size_t* bytes);
+
+/* S[j] = B c_j  (paper Sec. II-B Eq. (5), s_k ~ U alpha_k).  c: [J][K], S: [J][N]. */
+maxwell_status maxwell_basis_apply(maxwell_plan_t plan, const maxwell_complex64* c,
+                                   maxwell_complex64* S, void* ws, size_t ws_bytes, void* stream);
+
+/* c[j] = B^H S_j  (the basis block of J_G^H, Sec. II-B).  S: [J][N], c: [J][K]. */
+maxwell_status maxwell_basis_apply_adjoint(maxwell_plan_t plan, const maxwell_complex64* S,
+                                           maxwell_complex64* c, void* ws, size_t ws_bytes,
+                                           void* stream);
+
+/* y[j] = F_s((B c_j) (.) x)  (Sec. II-B Eq. (5)).  x: [N], c: [J][K], y: [J][M]. */
+maxwell_status maxwell_encode(maxwell_plan_t plan, const maxwell_complex64* x,
+                              const maxwell_complex64* c, maxwell_complex64* y, void* ws,
+                              size_t ws_bytes, void* stream);
+
+/* Jacobian adjoint at (x, c) applied to s*y, s = alpha * (*scale_dev) (or alpha when
+ * scale_dev is NULL; scale_dev is a device float, read inside the kernels so no host
+ * synchronisation is needed).  (Sec. II-B, J_G^H):
+ *     gx   = s * sum_j conj(B c_j) (.) F_s^H y_j                 gx: [N]
+ *     gc_j = s * B^H( conj(x) (.) F_s^H y_j )                    gc: [J][K]
+ * Either output may be NULL (not computed).  B c is recomputed from c here; no
+ * per-coil maps are kept between calls.  Weights are not applied.             */
+maxwell_status maxwell_adjoint(maxwell_plan_t plan, const maxwell_complex64* x,
+                               const maxwell_complex64* c, const maxwell_complex64* y,
+                               float alpha, const float* scale_dev, maxwell_complex64* gx,
+                               maxwell_complex64* gc, void* ws, size_t ws_bytes, void* stream);
+
+/* Data-fidelity forward pass (Sec. II-B, Eq. (6) data term, without its 1/2):
+ *     r_j  = w (.) (E(x, c)_j - y_j)                           r: [J][M] (may be NULL)
+ *     loss = sum_j sum_m w_m |E(x,c)_jm - y_jm|^2              one double (may be NULL)
+ * accumulated in FP64 and written to device memory.                           */
+maxwell_status maxwell_forward_loss(maxwell_plan_t plan, const maxwell_complex64* x,
+                                    const maxwell_complex64* c, const maxwell_complex64* y,
+                                    maxwell_complex64* r, double* loss_dev, void* ws,
+                                    size_t ws_bytes, void* stream);
+
+/* Loss and its packed real gradient (d/dRe + i d/dIm, the PyTorch convention)
+ * in one call:  f = sum w |E - y|^2,  (gx, gc) = 2 J^H (w (.) (E - y)).
+ * Equivalent to maxwell_forward_loss followed by maxwell_adjoint with alpha = 2,
+ * B c recomputed for the adjoint.  gx, gc, loss_dev may each be NULL.          */
+maxwell_status maxwell_grad(maxwell_plan_t plan, const maxwell_complex64* x,
+                            const maxwell_complex64* c, const maxwell_complex64* y,
+                            maxwell_complex64* gx, maxwell_complex64* gc, double* loss_dev,
+                            void* ws, size_t ws_bytes, void* stream);
+
+/* Thread-local text for the last non-OK status returned on this thread.       */
+const char* maxwell_last_error(void);
+
+/* Library version string, e.g. "maxwell-gfx950 0.1".                          */
+const char* maxwell_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MAXWELL_H */

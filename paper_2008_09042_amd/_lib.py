@@ -1,0 +1,111 @@
+"""ctypes declarations of the C ABI in include/maxwell.h (argument marshalling only)."""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmaxwell.so")
+
+MAXWELL_OK = 0
+MAXWELL_ERR_INVALID_ARGUMENT = -1
+MAXWELL_ERR_UNSUPPORTED = -2
+MAXWELL_ERR_OUT_OF_MEMORY = -3
+MAXWELL_ERR_HIP = -4
+MAXWELL_ERR_WORKSPACE_TOO_SMALL = -5
+
+MAXWELL_BASIS_DENSE = 0
+MAXWELL_BASIS_TUCKER = 1
+MAXWELL_FP32 = 0
+MAXWELL_BF16_SPLIT = 1
+MAXWELL_CARTESIAN = 0
+MAXWELL_NONCARTESIAN = 1
+
+STATUS_NAMES = {
+    0: "MAXWELL_OK", -1: "MAXWELL_ERR_INVALID_ARGUMENT", -2: "MAXWELL_ERR_UNSUPPORTED",
+    -3: "MAXWELL_ERR_OUT_OF_MEMORY", -4: "MAXWELL_ERR_HIP", -5: "MAXWELL_ERR_WORKSPACE_TOO_SMALL",
+}
+
+# Every entry point declared in include/maxwell.h.
+EXPORTS = [
+    "maxwell_plan_create", "maxwell_plan_destroy", "maxwell_plan_workspace_size",
+    "maxwell_basis_apply", "maxwell_basis_apply_adjoint", "maxwell_encode", "maxwell_adjoint",
+    "maxwell_forward_loss", "maxwell_grad", "maxwell_last_error", "maxwell_version",
+]
+
+
+class BasisDesc(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int),
+        ("K", ctypes.c_int64),
+        ("dense", ctypes.c_void_p),
+        ("r", ctypes.c_int64 * 3),
+        ("U", ctypes.c_void_p * 3),
+        ("core", ctypes.c_void_p),
+    ]
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int32),
+        ("n", ctypes.c_int64 * 3),
+        ("J", ctypes.c_int32),
+        ("precision", ctypes.c_int),
+        ("sampling", ctypes.c_int),
+        ("M", ctypes.c_int64),
+        ("mask_idx", ctypes.c_void_p),
+        ("traj", ctypes.c_void_p),
+        ("weights", ctypes.c_void_p),
+        ("kb_width", ctypes.c_int32),
+        ("oversamp", ctypes.c_float),
+        ("kb_beta", ctypes.c_float),
+    ]
+
+
+class MaxwellError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libmaxwell.so; raise if it has not been built (no fallback path exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2008_09042_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, sz, i64 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int64
+    st = ctypes.c_int
+    lib.maxwell_plan_create.argtypes = [ctypes.POINTER(PlanDesc), ctypes.POINTER(BasisDesc), ctypes.POINTER(vp)]
+    lib.maxwell_plan_create.restype = st
+    lib.maxwell_plan_destroy.argtypes = [vp]
+    lib.maxwell_plan_destroy.restype = None
+    lib.maxwell_plan_workspace_size.argtypes = [vp, ctypes.POINTER(sz)]
+    lib.maxwell_plan_workspace_size.restype = st
+    lib.maxwell_basis_apply.argtypes = [vp, vp, vp, vp, sz, vp]
+    lib.maxwell_basis_apply.restype = st
+    lib.maxwell_basis_apply_adjoint.argtypes = [vp, vp, vp, vp, sz, vp]
+    lib.maxwell_basis_apply_adjoint.restype = st
+    lib.maxwell_encode.argtypes = [vp, vp, vp, vp, vp, sz, vp]
+    lib.maxwell_encode.restype = st
+    lib.maxwell_adjoint.argtypes = [vp, vp, vp, vp, ctypes.c_float, vp, vp, vp, vp, sz, vp]
+    lib.maxwell_adjoint.restype = st
+    lib.maxwell_forward_loss.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.maxwell_forward_loss.restype = st
+    lib.maxwell_grad.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.maxwell_grad.restype = st
+    lib.maxwell_last_error.argtypes = []
+    lib.maxwell_last_error.restype = ctypes.c_char_p
+    lib.maxwell_version.argtypes = []
+    lib.maxwell_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def check(status: int):
+    if status != MAXWELL_OK:
+        msg = _lib.maxwell_last_error().decode() if _lib is not None else ""
+        raise MaxwellError(status, msg)

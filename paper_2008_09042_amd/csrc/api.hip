@@ -1,0 +1,348 @@
+// Host side of the C ABI declared in include/maxwell.h: plan construction,
+// argument validation, workspace layout, and the enqueue sequences of the
+// encoding operator (paper Sec. II-B, Eq. (5)), its Jacobian adjoint
+// (Sec. II-B, J_G^H), and the data-fidelity loss and gradient.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/maxwell.h"
+#include "common.h"
+#include "plan.h"
+
+using namespace mx;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+maxwell_status fail(maxwell_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+maxwell_status hip_fail(hipError_t e, const char* where) {
+  g_last_error = std::string("HIP error in ") + where + ": " + hipGetErrorString(e);
+  return MAXWELL_ERR_HIP;
+}
+
+#define HIP_TRY(expr, where)                      \
+  do {                                            \
+    hipError_t _e = (expr);                       \
+    if (_e != hipSuccess) return hip_fail(_e, where); \
+  } while (0)
+
+bool aligned8(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+
+bool overlap(const void* a, size_t abytes, const void* b, size_t bbytes) {
+  if (!a || !b || abytes == 0 || bbytes == 0) return false;
+  const uintptr_t a0 = reinterpret_cast<uintptr_t>(a), b0 = reinterpret_cast<uintptr_t>(b);
+  return a0 < b0 + bbytes && b0 < a0 + abytes;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+}  // namespace
+
+// ------------------------------------------------------------------ plan
+namespace mx {
+
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+static maxwell_status validate_desc(const maxwell_plan_desc* d, const maxwell_basis_desc* b) {
+  if (!d || !b) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "null descriptor");
+  if (d->ndim != 2 && d->ndim != 3) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "ndim must be 2 or 3");
+  int64_t N = 1;
+  for (int i = 0; i < d->ndim; ++i) {
+    if (d->n[i] < 2 || d->n[i] > 4096)
+      return fail(MAXWELL_ERR_INVALID_ARGUMENT, "image size must be in [2, 4096] on every axis");
+    if (d->n[i] & 1) return fail(MAXWELL_ERR_UNSUPPORTED, "odd image sizes are not supported");
+    int rad[12];
+    if (!fft_factorise(d->n[i], rad))
+      return fail(MAXWELL_ERR_UNSUPPORTED, "image sizes must factor into 2, 3 and 5");
+    N *= d->n[i];
+  }
+  if (N > (int64_t(1) << 30)) return fail(MAXWELL_ERR_UNSUPPORTED, "image larger than 2^30 voxels");
+  if (d->J < 1) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "J must be >= 1");
+  if (d->precision != MAXWELL_FP32 && d->precision != MAXWELL_BF16_SPLIT)
+    return fail(MAXWELL_ERR_INVALID_ARGUMENT, "unknown precision");
+  if (b->K < 1) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "K must be >= 1");
+  if (b->kind == MAXWELL_BASIS_DENSE) {
+    if (!b->dense || !aligned8(b->dense)) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "dense basis pointer null or misaligned");
+  } else if (b->kind == MAXWELL_BASIS_TUCKER) {
+    if (d->ndim != 3) return fail(MAXWELL_ERR_UNSUPPORTED, "Tucker bases need a 3D image");
+    for (int m = 0; m < 3; ++m) {
+      if (b->r[m] < 1 || b->r[m] > d->n[m])
+        return fail(MAXWELL_ERR_INVALID_ARGUMENT, "Tucker rank must be in [1, n_m]");
+      if (!b->U[m] || !aligned8(b->U[m])) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "Tucker factor pointer null or misaligned");
+    }
+    if (!b->core || !aligned8(b->core)) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "Tucker core pointer null or misaligned");
+  } else {
+    return fail(MAXWELL_ERR_INVALID_ARGUMENT, "unknown basis kind");
+  }
+  if (d->M < 0) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "M must be >= 0");
+  if (d->sampling == MAXWELL_CARTESIAN) {
+    if (d->M > N) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "more mask samples than grid points");
+    if (d->M > 0 && !d->mask_idx) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "mask_idx is null");
+    for (int64_t m = 0; m < d->M; ++m) {
+      const int64_t v = d->mask_idx[m];
+      if (v < 0 || v >= N) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "mask index out of range");
+      if (m > 0 && v <= d->mask_idx[m - 1])
+        return fail(MAXWELL_ERR_INVALID_ARGUMENT, "mask indices must be strictly ascending (no duplicates)");
+    }
+  } else if (d->sampling == MAXWELL_NONCARTESIAN) {
+    if (d->ndim != 2) return fail(MAXWELL_ERR_UNSUPPORTED, "non-Cartesian sampling is 2D only");
+    if (d->M > 0 && !d->traj) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "traj is null");
+    if (d->kb_width < 2 || d->kb_width > 8) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "kb_width must be in [2, 8]");
+    if (!(d->oversamp >= 1.0f) || !std::isfinite(d->oversamp))
+      return fail(MAXWELL_ERR_INVALID_ARGUMENT, "oversamp must be finite and >= 1");
+    if (!std::isfinite(d->kb_beta)) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "kb_beta must be finite");
+    for (int i = 0; i < 2; ++i) {
+      const double g = (double)d->oversamp * (double)d->n[i];
+      const int64_t gi = (int64_t)std::llround(g);
+      if (std::fabs(g - (double)gi) > 1e-6 || (gi & 1))
+        return fail(MAXWELL_ERR_INVALID_ARGUMENT, "oversamp * n must be an even integer");
+      int rad[12];
+      if (!fft_factorise(gi, rad)) return fail(MAXWELL_ERR_UNSUPPORTED, "oversampled grid must factor into 2, 3, 5 and be <= 4096");
+    }
+    for (int64_t m = 0; m < d->M * d->ndim; ++m) {
+      const float v = d->traj[m];
+      const int ax = (int)(m % d->ndim);
+      if (!std::isfinite(v) || v < -0.5f * (float)d->n[ax] || v >= 0.5f * (float)d->n[ax])
+        return fail(MAXWELL_ERR_INVALID_ARGUMENT, "trajectory point outside [-n/2, n/2)");
+    }
+  } else {
+    return fail(MAXWELL_ERR_INVALID_ARGUMENT, "unknown sampling kind");
+  }
+  if (d->weights) {
+    for (int64_t m = 0; m < d->M; ++m)
+      if (!std::isfinite(d->weights[m]) || d->weights[m] < 0.f)
+        return fail(MAXWELL_ERR_INVALID_ARGUMENT, "weights must be finite and >= 0");
+  }
+  return MAXWELL_OK;
+}
+
+}  // namespace mx
+
+extern "C" {
+
+const char* maxwell_last_error(void) { return g_last_error.c_str(); }
+
+const char* maxwell_version(void) { return "maxwell-gfx950 0.1"; }
+
+maxwell_status maxwell_plan_create(const maxwell_plan_desc* desc, const maxwell_basis_desc* basis,
+                                   maxwell_plan_t* plan_out) {
+  if (!plan_out) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "plan_out is null");
+  *plan_out = nullptr;
+  maxwell_status s = validate_desc(desc, basis);
+  if (s != MAXWELL_OK) return s;
+  Plan* p = new (std::nothrow) Plan();
+  if (!p) return fail(MAXWELL_ERR_OUT_OF_MEMORY, "host allocation failed");
+  s = plan_build(*p, *desc, *basis);
+  if (s != MAXWELL_OK) {
+    plan_release(*p);
+    delete p;
+    return s;
+  }
+  *plan_out = reinterpret_cast<maxwell_plan_t>(p);
+  return MAXWELL_OK;
+}
+
+void maxwell_plan_destroy(maxwell_plan_t plan) {
+  if (!plan) return;
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  plan_release(*p);
+  delete p;
+}
+
+maxwell_status maxwell_plan_workspace_size(maxwell_plan_t plan, size_t* bytes) {
+  if (!plan || !bytes) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "null plan or bytes pointer");
+  *bytes = reinterpret_cast<Plan*>(plan)->ws_bytes;
+  return MAXWELL_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ compute calls
+namespace {
+
+struct Check {
+  const Plan* p;
+  maxwell_status st = MAXWELL_OK;
+  std::vector<std::pair<const void*, size_t>> ins, outs;
+  explicit Check(const Plan* pp) : p(pp) {}
+  bool in(const void* ptr, size_t bytes, const char* name, bool required = true) {
+    if (st != MAXWELL_OK) return false;
+    if (!ptr) {
+      if (required && bytes) { st = fail(MAXWELL_ERR_INVALID_ARGUMENT, std::string(name) + " is null"); return false; }
+      return true;
+    }
+    if (!aligned8(ptr)) { st = fail(MAXWELL_ERR_INVALID_ARGUMENT, std::string(name) + " is not 8-byte aligned"); return false; }
+    ins.push_back({ptr, bytes});
+    return true;
+  }
+  bool out(const void* ptr, size_t bytes, const char* name, bool required = true) {
+    if (st != MAXWELL_OK) return false;
+    if (!ptr) {
+      if (required && bytes) { st = fail(MAXWELL_ERR_INVALID_ARGUMENT, std::string(name) + " is null"); return false; }
+      return true;
+    }
+    if (!aligned8(ptr)) { st = fail(MAXWELL_ERR_INVALID_ARGUMENT, std::string(name) + " is not 8-byte aligned"); return false; }
+    outs.push_back({ptr, bytes});
+    return true;
+  }
+  bool ws(const void* w, size_t bytes) {
+    if (st != MAXWELL_OK) return false;
+    if (bytes < p->ws_bytes) {
+      st = fail(MAXWELL_ERR_WORKSPACE_TOO_SMALL, "workspace smaller than maxwell_plan_workspace_size");
+      return false;
+    }
+    if (p->ws_bytes && !w) { st = fail(MAXWELL_ERR_INVALID_ARGUMENT, "workspace is null"); return false; }
+    if (w && (reinterpret_cast<uintptr_t>(w) & 255u)) {
+      st = fail(MAXWELL_ERR_INVALID_ARGUMENT, "workspace must be 256-byte aligned");
+      return false;
+    }
+    outs.push_back({w, p->ws_bytes});
+    return true;
+  }
+  maxwell_status finish() {
+    if (st != MAXWELL_OK) return st;
+    for (size_t i = 0; i < outs.size(); ++i) {
+      for (auto& in : ins)
+        if (overlap(outs[i].first, outs[i].second, in.first, in.second))
+          return fail(MAXWELL_ERR_INVALID_ARGUMENT, "an output overlaps an input");
+      for (size_t k = i + 1; k < outs.size(); ++k)
+        if (overlap(outs[i].first, outs[i].second, outs[k].first, outs[k].second))
+          return fail(MAXWELL_ERR_INVALID_ARGUMENT, "two outputs overlap");
+    }
+    return MAXWELL_OK;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+maxwell_status maxwell_basis_apply(maxwell_plan_t plan, const maxwell_complex64* c, maxwell_complex64* S,
+                                   void* ws, size_t ws_bytes, void* stream) {
+  if (!plan) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "plan is null");
+  const Plan* p = reinterpret_cast<const Plan*>(plan);
+  Check ck(p);
+  ck.in(c, p->bytes_c(), "c");
+  ck.out(S, p->bytes_S(), "S");
+  ck.ws(ws, ws_bytes);
+  maxwell_status s = ck.finish();
+  if (s != MAXWELL_OK) return s;
+  HIP_TRY(run_basis_apply(*p, reinterpret_cast<const float2*>(c), reinterpret_cast<float2*>(S), ws,
+                          (hipStream_t)stream),
+          "basis_apply");
+  return MAXWELL_OK;
+}
+
+maxwell_status maxwell_basis_apply_adjoint(maxwell_plan_t plan, const maxwell_complex64* S,
+                                           maxwell_complex64* c, void* ws, size_t ws_bytes, void* stream) {
+  if (!plan) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "plan is null");
+  const Plan* p = reinterpret_cast<const Plan*>(plan);
+  Check ck(p);
+  ck.in(S, p->bytes_S(), "S");
+  ck.out(c, p->bytes_c(), "c");
+  ck.ws(ws, ws_bytes);
+  maxwell_status s = ck.finish();
+  if (s != MAXWELL_OK) return s;
+  HIP_TRY(run_basis_adjoint(*p, reinterpret_cast<const float2*>(S), reinterpret_cast<float2*>(c), 1.0f,
+                            nullptr, ws, (hipStream_t)stream),
+          "basis_apply_adjoint");
+  return MAXWELL_OK;
+}
+
+maxwell_status maxwell_encode(maxwell_plan_t plan, const maxwell_complex64* x, const maxwell_complex64* c,
+                              maxwell_complex64* y, void* ws, size_t ws_bytes, void* stream) {
+  if (!plan) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "plan is null");
+  const Plan* p = reinterpret_cast<const Plan*>(plan);
+  Check ck(p);
+  ck.in(x, p->bytes_x(), "x");
+  ck.in(c, p->bytes_c(), "c");
+  ck.out(y, p->bytes_y(), "y");
+  ck.ws(ws, ws_bytes);
+  maxwell_status s = ck.finish();
+  if (s != MAXWELL_OK) return s;
+  HIP_TRY(run_encode(*p, reinterpret_cast<const float2*>(x), reinterpret_cast<const float2*>(c),
+                     reinterpret_cast<float2*>(y), ws, (hipStream_t)stream),
+          "encode");
+  return MAXWELL_OK;
+}
+
+maxwell_status maxwell_adjoint(maxwell_plan_t plan, const maxwell_complex64* x, const maxwell_complex64* c,
+                               const maxwell_complex64* y, float alpha, const float* scale_dev,
+                               maxwell_complex64* gx, maxwell_complex64* gc, void* ws, size_t ws_bytes,
+                               void* stream) {
+  if (!plan) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "plan is null");
+  const Plan* p = reinterpret_cast<const Plan*>(plan);
+  if (!std::isfinite(alpha)) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "alpha must be finite");
+  Check ck(p);
+  ck.in(x, p->bytes_x(), "x");
+  ck.in(c, p->bytes_c(), "c");
+  ck.in(y, p->bytes_y(), "y");
+  if (scale_dev && (reinterpret_cast<uintptr_t>(scale_dev) & 3u))
+    return fail(MAXWELL_ERR_INVALID_ARGUMENT, "scale_dev must be 4-byte aligned");
+  if (scale_dev) ck.ins.push_back({scale_dev, sizeof(float)});
+  ck.out(gx, p->bytes_x(), "gx", false);
+  ck.out(gc, p->bytes_c(), "gc", false);
+  ck.ws(ws, ws_bytes);
+  maxwell_status s = ck.finish();
+  if (s != MAXWELL_OK) return s;
+  if (!gx && !gc) return MAXWELL_OK;
+  HIP_TRY(run_adjoint(*p, reinterpret_cast<const float2*>(x), reinterpret_cast<const float2*>(c),
+                      reinterpret_cast<const float2*>(y), alpha, scale_dev, reinterpret_cast<float2*>(gx),
+                      reinterpret_cast<float2*>(gc), ws, (hipStream_t)stream, false),
+          "adjoint");
+  return MAXWELL_OK;
+}
+
+maxwell_status maxwell_forward_loss(maxwell_plan_t plan, const maxwell_complex64* x, const maxwell_complex64* c,
+                                    const maxwell_complex64* y, maxwell_complex64* r, double* loss_dev, void* ws,
+                                    size_t ws_bytes, void* stream) {
+  if (!plan) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "plan is null");
+  const Plan* p = reinterpret_cast<const Plan*>(plan);
+  Check ck(p);
+  ck.in(x, p->bytes_x(), "x");
+  ck.in(c, p->bytes_c(), "c");
+  ck.in(y, p->bytes_y(), "y");
+  ck.out(r, p->bytes_y(), "r", false);
+  ck.out(loss_dev, sizeof(double), "loss_dev", false);
+  ck.ws(ws, ws_bytes);
+  maxwell_status s = ck.finish();
+  if (s != MAXWELL_OK) return s;
+  if (!r && !loss_dev) return MAXWELL_OK;
+  HIP_TRY(run_forward_loss(*p, reinterpret_cast<const float2*>(x), reinterpret_cast<const float2*>(c),
+                           reinterpret_cast<const float2*>(y), reinterpret_cast<float2*>(r), loss_dev, ws,
+                           (hipStream_t)stream),
+          "forward_loss");
+  return MAXWELL_OK;
+}
+
+maxwell_status maxwell_grad(maxwell_plan_t plan, const maxwell_complex64* x, const maxwell_complex64* c,
+                            const maxwell_complex64* y, maxwell_complex64* gx, maxwell_complex64* gc,
+                            double* loss_dev, void* ws, size_t ws_bytes, void* stream) {
+  if (!plan) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "plan is null");
+  const Plan* p = reinterpret_cast<const Plan*>(plan);
+  Check ck(p);
+  ck.in(x, p->bytes_x(), "x");
+  ck.in(c, p->bytes_c(), "c");
+  ck.in(y, p->bytes_y(), "y");
+  ck.out(gx, p->bytes_x(), "gx", false);
+  ck.out(gc, p->bytes_c(), "gc", false);
+  ck.out(loss_dev, sizeof(double), "loss_dev", false);
+  ck.ws(ws, ws_bytes);
+  maxwell_status s = ck.finish();
+  if (s != MAXWELL_OK) return s;
+  HIP_TRY(run_grad(*p, reinterpret_cast<const float2*>(x), reinterpret_cast<const float2*>(c),
+                   reinterpret_cast<const float2*>(y), reinterpret_cast<float2*>(gx), reinterpret_cast<float2*>(gc),
+                   loss_dev, ws, (hipStream_t)stream),
+          "grad");
+  return MAXWELL_OK;
+}
+
+}  // extern "C"

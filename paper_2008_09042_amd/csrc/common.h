@@ -1,0 +1,80 @@
+// Internal declarations shared by the HIP translation units of libmaxwell.
+// Nothing here crosses the C ABI (see include/maxwell.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+namespace mx {
+
+// ---------------------------------------------------------------- complex helpers
+struct cf { float x, y; };  // interleaved complex64, same bytes as maxwell_complex64
+
+__host__ __device__ inline float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline float2 cmulc(float2 a, float2 b) {  // conj(a) * b
+  return make_float2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__host__ __device__ inline float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__host__ __device__ inline float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+
+// ---------------------------------------------------------------- GEMM
+// C[b][m][n] = alpha * sum_k opA(b, m, k) * opB(b, k, n)  (+ C when accumulate)
+// All strides in complex elements.  conjA / conjB conjugate the operand.
+struct GemmArgs {
+  int64_t M, N, K, batch;
+  const float2* A; int64_t a_bs, a_ms, a_ks; int conjA;
+  const float2* B; int64_t b_bs, b_ks, b_ns; int conjB;
+  float2* C; int64_t c_bs, c_ms, c_ns;
+  float alpha;
+  const float* alpha_dev;  // optional device scalar multiplying alpha
+  int accumulate;
+};
+
+// Bytes of workspace the GEMM needs for split-K partials for these sizes.
+size_t gemm_workspace_bytes(const GemmArgs& g);
+// Enqueue.  `ws` must hold gemm_workspace_bytes(g) bytes (may be null if 0).
+hipError_t gemm_launch(const GemmArgs& g, int precision, void* ws, hipStream_t st);
+
+// BF16 split of an FP32 complex array into hi/lo planes (used for constant bases).
+hipError_t split_bf16_launch(const float2* src, int64_t count, uint16_t* hi, uint16_t* lo,
+                             hipStream_t st);
+
+// ---------------------------------------------------------------- FFT
+// Transform along one axis of data laid out [outer][n][inner] (complex elements).
+// centred unitary DFT; dir = -1 forward (exp(-2 pi i ...)), +1 inverse.
+struct FftAxisArgs {
+  float2* data;           // in/out (in place)
+  const float2* src;      // input (may equal data)
+  int64_t n, inner, outer;
+  int dir;
+  const float2* twiddle;  // n entries, exp(-2 pi i t / n)
+  int nrad; int radix[12];
+  // optional image premultiply (forward, first axis pass): m = x[img_index] * src
+  const float2* premul; int64_t outer_per_coil;
+};
+hipError_t fft_axis_launch(const FftAxisArgs& a, hipStream_t st);
+int fft_factorise(int64_t n, int* radix);  // returns number of passes, 0 if unsupported
+
+// ---------------------------------------------------------------- elementwise / sampling
+hipError_t gather_launch(const float2* kspace, int64_t N, const int32_t* idx, int64_t M, int J,
+                         float2* y, hipStream_t st);
+hipError_t scatter_launch(const float2* y, int64_t M, const int32_t* inv_mask, int64_t N, int J,
+                          float2* kspace, hipStream_t st);
+// r = w (.) (E - y); partial FP64 sums of w |E - y|^2 into part[nblocks]; returns nblocks.
+int residual_blocks(int64_t total);
+hipError_t residual_launch(const float2* E, const float2* y, const float* w, int64_t M, int J,
+                           float2* r, double* part, hipStream_t st);
+hipError_t reduce_loss_launch(const double* part, int nblocks, double* loss, hipStream_t st);
+// gx[n] = s sum_j conj(S[j][n]) g[j][n] ; g[j][n] <- s conj(x[n]) g[j][n] (when h_inplace)
+hipError_t adjoint_combine_launch(const float2* S, float2* g, const float2* x, int64_t N, int J,
+                                  float alpha, const float* scale_dev, float2* gx, int want_h,
+                                  hipStream_t st);
+hipError_t scale_copy_launch(const float2* src, float2* dst, int64_t count, float alpha,
+                             const float* scale_dev, hipStream_t st);
+
+}  // namespace mx

@@ -1,0 +1,61 @@
+// Plan object and the enqueue sequences behind the C ABI.
+#pragma once
+
+#include <string>
+
+#include "../../include/maxwell.h"
+#include "common.h"
+
+namespace mx {
+
+struct Plan {
+  // geometry
+  int ndim = 0;
+  int64_t n[3] = {1, 1, 1};
+  int64_t N = 0;
+  int J = 0;
+  int64_t K = 0, M = 0;
+  int precision = 0, sampling = 0;
+  // basis (caller-owned device pointers)
+  int basis_kind = 0;
+  const float2* dense = nullptr;
+  int64_t r[3] = {0, 0, 0};
+  const float2* U[3] = {nullptr, nullptr, nullptr};
+  const float2* core = nullptr;
+  // device tables owned by the plan
+  int32_t* d_mask = nullptr;   // [M] linear k-space index of each sample
+  int32_t* d_inv = nullptr;    // [N] sample position of each grid point, -1 if unsampled
+  float* d_w = nullptr;        // [M] data weights or null (w = 1)
+  float2* d_tw[3] = {nullptr, nullptr, nullptr};  // twiddle tables per axis
+  int nrad[3] = {0, 0, 0};
+  int radix[3][12];
+  // workspace layout (byte offsets into the caller's workspace)
+  size_t ws_bytes = 0;
+  size_t off_S = 0, off_K = 0, off_tA = 0, off_tB = 0, off_E = 0, off_gemm = 0, off_part = 0;
+  int part_blocks = 0;
+
+  size_t bytes_x() const { return (size_t)N * 8; }
+  size_t bytes_c() const { return (size_t)J * (size_t)K * 8; }
+  size_t bytes_S() const { return (size_t)J * (size_t)N * 8; }
+  size_t bytes_y() const { return (size_t)J * (size_t)M * 8; }
+};
+
+// Records the thread-local message returned by maxwell_last_error().
+void set_last_error(const std::string& msg);
+
+maxwell_status plan_build(Plan& p, const maxwell_plan_desc& d, const maxwell_basis_desc& b);
+void plan_release(Plan& p);
+
+hipError_t run_basis_apply(const Plan& p, const float2* c, float2* S, void* ws, hipStream_t st);
+hipError_t run_basis_adjoint(const Plan& p, const float2* S, float2* c, float alpha, const float* alpha_dev,
+                             void* ws, hipStream_t st);
+hipError_t run_encode(const Plan& p, const float2* x, const float2* c, float2* y, void* ws, hipStream_t st);
+hipError_t run_adjoint(const Plan& p, const float2* x, const float2* c, const float2* y, float alpha,
+                       const float* scale_dev, float2* gx, float2* gc, void* ws, hipStream_t st,
+                       bool maps_ready);
+hipError_t run_forward_loss(const Plan& p, const float2* x, const float2* c, const float2* y, float2* r,
+                            double* loss, void* ws, hipStream_t st);
+hipError_t run_grad(const Plan& p, const float2* x, const float2* c, const float2* y, float2* gx, float2* gc,
+                    double* loss, void* ws, hipStream_t st);
+
+}  // namespace mx

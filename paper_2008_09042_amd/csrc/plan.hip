@@ -1,0 +1,327 @@
+// Plan construction and the enqueue sequences of the general path.
+//
+// General path (any geometry the plan accepts):
+//   encode   S = B c (MFMA GEMM chain)  ->  m = x (.) S fused into the first
+//            FFT pass  ->  centred unitary DFT, one LDS-staged pass per axis
+//            ->  mask gather  ->  y                         (Sec. II-B, Eq. (5))
+//   adjoint  zero-filled scatter  ->  inverse DFT per axis  ->
+//            gx = s sum_j conj(S_j) (.) g_j,  h_j = s conj(x) (.) g_j  ->
+//            gc = B^H h                                      (Sec. II-B, J_G^H)
+// The per-coil maps S live only in the caller's workspace for the duration
+// of one call.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "plan.h"
+
+namespace mx {
+
+namespace {
+
+size_t al(size_t v) { return (v + 255) & ~size_t(255); }
+
+GemmArgs gemm0() {
+  GemmArgs g;
+  std::memset(&g, 0, sizeof(g));
+  g.batch = 1;
+  g.alpha = 1.0f;
+  return g;
+}
+
+// ---- dense basis
+GemmArgs dense_apply_args(const Plan& p, const float2* c, float2* S) {
+  GemmArgs g = gemm0();
+  g.M = p.J; g.N = p.N; g.K = p.K;
+  g.A = c; g.a_ms = p.K; g.a_ks = 1;
+  g.B = p.dense; g.b_ks = 1; g.b_ns = p.K;
+  g.C = S; g.c_ms = p.N; g.c_ns = 1;
+  return g;
+}
+
+GemmArgs dense_adjoint_args(const Plan& p, const float2* h, float2* c) {
+  GemmArgs g = gemm0();
+  g.M = p.J; g.N = p.K; g.K = p.N;
+  g.A = h; g.a_ms = p.N; g.a_ks = 1;
+  g.B = p.dense; g.b_ks = p.K; g.b_ns = 1; g.conjB = 1;
+  g.C = c; g.c_ms = p.K; g.c_ns = 1;
+  return g;
+}
+
+// ---- Tucker basis: the chain of k-mode products (Sec. II-E)
+void tucker_apply_args(const Plan& p, const float2* c, float2* tA, float2* tB, float2* S, GemmArgs* g) {
+  const int64_t r0 = p.r[0], r1 = p.r[1], r2 = p.r[2], n0 = p.n[0], n1 = p.n[1], n2 = p.n[2];
+  const int64_t R = r0 * r1 * r2, Q = r1 * r2, J = p.J;
+  // (1) T1[j][rho] = sum_k c[j][k] core[rho][k]
+  g[0] = gemm0();
+  g[0].M = J; g[0].N = R; g[0].K = p.K;
+  g[0].A = c; g[0].a_ms = p.K; g[0].a_ks = 1;
+  g[0].B = p.core; g[0].b_ks = 1; g[0].b_ns = p.K;
+  g[0].C = tA; g[0].c_ms = R; g[0].c_ns = 1;
+  // (2) T2[j][i0][q] = sum_p0 U0[i0][p0] T1[j][p0][q]
+  g[1] = gemm0();
+  g[1].batch = J; g[1].M = n0; g[1].N = Q; g[1].K = r0;
+  g[1].A = p.U[0]; g[1].a_ms = r0; g[1].a_ks = 1;
+  g[1].B = tA; g[1].b_bs = R; g[1].b_ks = Q; g[1].b_ns = 1;
+  g[1].C = tB; g[1].c_bs = n0 * Q; g[1].c_ms = Q; g[1].c_ns = 1;
+  // (3) T3[j i0][i1][p2] = sum_p1 U1[i1][p1] T2[j i0][p1][p2]
+  g[2] = gemm0();
+  g[2].batch = J * n0; g[2].M = n1; g[2].N = r2; g[2].K = r1;
+  g[2].A = p.U[1]; g[2].a_ms = r1; g[2].a_ks = 1;
+  g[2].B = tB; g[2].b_bs = Q; g[2].b_ks = r2; g[2].b_ns = 1;
+  g[2].C = tA; g[2].c_bs = n1 * r2; g[2].c_ms = r2; g[2].c_ns = 1;
+  // (4) S[j i0 i1][i2] = sum_p2 T3[j i0 i1][p2] U2[i2][p2]
+  g[3] = gemm0();
+  g[3].M = J * n0 * n1; g[3].N = n2; g[3].K = r2;
+  g[3].A = tA; g[3].a_ms = r2; g[3].a_ks = 1;
+  g[3].B = p.U[2]; g[3].b_ks = 1; g[3].b_ns = r2;
+  g[3].C = S; g[3].c_ms = n2; g[3].c_ns = 1;
+}
+
+void tucker_adjoint_args(const Plan& p, const float2* h, float2* tA, float2* tB, float2* c, GemmArgs* g) {
+  const int64_t r0 = p.r[0], r1 = p.r[1], r2 = p.r[2], n0 = p.n[0], n1 = p.n[1], n2 = p.n[2];
+  const int64_t R = r0 * r1 * r2, Q = r1 * r2, J = p.J;
+  // (4') Q3[j i0 i1][p2] = sum_i2 h[j i0 i1][i2] conj(U2[i2][p2])
+  g[0] = gemm0();
+  g[0].M = J * n0 * n1; g[0].N = r2; g[0].K = n2;
+  g[0].A = h; g[0].a_ms = n2; g[0].a_ks = 1;
+  g[0].B = p.U[2]; g[0].b_ks = r2; g[0].b_ns = 1; g[0].conjB = 1;
+  g[0].C = tA; g[0].c_ms = r2; g[0].c_ns = 1;
+  // (3') Q2[j i0][p1][p2] = sum_i1 conj(U1[i1][p1]) Q3[j i0][i1][p2]
+  g[1] = gemm0();
+  g[1].batch = J * n0; g[1].M = r1; g[1].N = r2; g[1].K = n1;
+  g[1].A = p.U[1]; g[1].a_ms = 1; g[1].a_ks = r1; g[1].conjA = 1;
+  g[1].B = tA; g[1].b_bs = n1 * r2; g[1].b_ks = r2; g[1].b_ns = 1;
+  g[1].C = tB; g[1].c_bs = Q; g[1].c_ms = r2; g[1].c_ns = 1;
+  // (2') Q1[j][p0][q] = sum_i0 conj(U0[i0][p0]) Q2[j][i0][q]
+  g[2] = gemm0();
+  g[2].batch = J; g[2].M = r0; g[2].N = Q; g[2].K = n0;
+  g[2].A = p.U[0]; g[2].a_ms = 1; g[2].a_ks = r0; g[2].conjA = 1;
+  g[2].B = tB; g[2].b_bs = n0 * Q; g[2].b_ks = Q; g[2].b_ns = 1;
+  g[2].C = tA; g[2].c_bs = R; g[2].c_ms = Q; g[2].c_ns = 1;
+  // (1') c[j][k] = sum_rho conj(core[rho][k]) Q1[j][rho]
+  g[3] = gemm0();
+  g[3].M = J; g[3].N = p.K; g[3].K = R;
+  g[3].A = tA; g[3].a_ms = R; g[3].a_ks = 1;
+  g[3].B = p.core; g[3].b_ks = p.K; g[3].b_ns = 1; g[3].conjB = 1;
+  g[3].C = c; g[3].c_ms = p.K; g[3].c_ns = 1;
+}
+
+template <typename T>
+T* wsp(void* ws, size_t off) { return reinterpret_cast<T*>(reinterpret_cast<char*>(ws) + off); }
+
+hipError_t fft_image(const Plan& p, const float2* src, float2* dst, int dir, const float2* premul,
+                     hipStream_t st) {
+  const float2* cur = src;
+  for (int t = 0; t < p.ndim; ++t) {
+    const int d = p.ndim - 1 - t;
+    int64_t inner = 1, opc = 1;
+    for (int e = d + 1; e < p.ndim; ++e) inner *= p.n[e];
+    for (int e = 0; e < d; ++e) opc *= p.n[e];
+    FftAxisArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.data = dst;
+    a.src = cur;
+    a.n = p.n[d];
+    a.inner = inner;
+    a.outer = (int64_t)p.J * opc;
+    a.outer_per_coil = opc;
+    a.dir = dir;
+    a.twiddle = p.d_tw[d];
+    a.nrad = p.nrad[d];
+    for (int q = 0; q < p.nrad[d]; ++q) a.radix[q] = p.radix[d][q];
+    a.premul = (t == 0) ? premul : nullptr;
+    hipError_t e = fft_axis_launch(a, st);
+    if (e != hipSuccess) return e;
+    cur = dst;
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+maxwell_status plan_build(Plan& p, const maxwell_plan_desc& d, const maxwell_basis_desc& b) {
+  p.ndim = d.ndim;
+  p.N = 1;
+  for (int i = 0; i < 3; ++i) p.n[i] = i < d.ndim ? d.n[i] : 1;
+  for (int i = 0; i < d.ndim; ++i) p.N *= d.n[i];
+  p.J = d.J;
+  p.K = b.K;
+  p.M = d.M;
+  p.precision = d.precision;
+  p.sampling = d.sampling;
+  p.basis_kind = b.kind;
+  p.dense = reinterpret_cast<const float2*>(b.dense);
+  for (int m = 0; m < 3; ++m) {
+    p.r[m] = b.r[m];
+    p.U[m] = reinterpret_cast<const float2*>(b.U[m]);
+  }
+  p.core = reinterpret_cast<const float2*>(b.core);
+
+  if (d.sampling != MAXWELL_CARTESIAN) {
+    set_last_error("non-Cartesian sampling is not available in this build");
+    return MAXWELL_ERR_UNSUPPORTED;
+  }
+
+  auto hip_err = [&](hipError_t e) {
+    set_last_error(std::string("HIP error during plan creation: ") + hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? MAXWELL_ERR_OUT_OF_MEMORY : MAXWELL_ERR_HIP;
+  };
+  hipError_t e;
+  // twiddle tables, exp(-2 pi i t / n), computed in FP64 and rounded
+  for (int ax = 0; ax < p.ndim; ++ax) {
+    p.nrad[ax] = fft_factorise(p.n[ax], p.radix[ax]);
+    std::vector<float2> tw(p.n[ax]);
+    for (int64_t t = 0; t < p.n[ax]; ++t) {
+      const double ang = -2.0 * M_PI * (double)t / (double)p.n[ax];
+      tw[t] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+    }
+    if ((e = hipMalloc(&p.d_tw[ax], tw.size() * sizeof(float2))) != hipSuccess) return hip_err(e);
+    if ((e = hipMemcpy(p.d_tw[ax], tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess)
+      return hip_err(e);
+  }
+  // mask tables
+  {
+    std::vector<int32_t> idx(p.M), inv(p.N, -1);
+    for (int64_t m = 0; m < p.M; ++m) {
+      idx[m] = (int32_t)d.mask_idx[m];
+      inv[d.mask_idx[m]] = (int32_t)m;
+    }
+    if (p.M > 0) {
+      if ((e = hipMalloc(&p.d_mask, p.M * sizeof(int32_t))) != hipSuccess) return hip_err(e);
+      if ((e = hipMemcpy(p.d_mask, idx.data(), p.M * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_err(e);
+    }
+    if ((e = hipMalloc(&p.d_inv, p.N * sizeof(int32_t))) != hipSuccess) return hip_err(e);
+    if ((e = hipMemcpy(p.d_inv, inv.data(), p.N * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess)
+      return hip_err(e);
+  }
+  if (d.weights && p.M > 0) {
+    if ((e = hipMalloc(&p.d_w, p.M * sizeof(float))) != hipSuccess) return hip_err(e);
+    if ((e = hipMemcpy(p.d_w, d.weights, p.M * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess)
+      return hip_err(e);
+  }
+
+  // workspace layout
+  const size_t JN = (size_t)p.J * (size_t)p.N * 8;
+  size_t off = 0;
+  p.off_S = off; off += al(JN);
+  p.off_K = off; off += al(JN);
+  size_t gemm_ws = 0;
+  if (p.basis_kind == MAXWELL_BASIS_TUCKER) {
+    const size_t R = (size_t)(p.r[0] * p.r[1] * p.r[2]);
+    size_t tA = std::max((size_t)p.J * R, (size_t)p.J * p.n[0] * p.n[1] * p.r[2]) * 8;
+    size_t tB = (size_t)p.J * p.n[0] * p.r[1] * p.r[2] * 8;
+    p.off_tA = off; off += al(tA);
+    p.off_tB = off; off += al(tB);
+    GemmArgs g[4];
+    tucker_apply_args(p, nullptr, nullptr, nullptr, nullptr, g);
+    for (int i = 0; i < 4; ++i) gemm_ws = std::max(gemm_ws, gemm_workspace_bytes(g[i]));
+    tucker_adjoint_args(p, nullptr, nullptr, nullptr, nullptr, g);
+    for (int i = 0; i < 4; ++i) gemm_ws = std::max(gemm_ws, gemm_workspace_bytes(g[i]));
+  } else {
+    gemm_ws = std::max(gemm_workspace_bytes(dense_apply_args(p, nullptr, nullptr)),
+                       gemm_workspace_bytes(dense_adjoint_args(p, nullptr, nullptr)));
+  }
+  p.off_E = off; off += al((size_t)p.J * (size_t)p.M * 8);
+  p.off_gemm = off; off += al(gemm_ws);
+  p.part_blocks = residual_blocks((int64_t)p.J * p.M);
+  p.off_part = off; off += al((size_t)p.part_blocks * sizeof(double));
+  p.ws_bytes = off;
+  return MAXWELL_OK;
+}
+
+void plan_release(Plan& p) {
+  for (int ax = 0; ax < 3; ++ax) {
+    if (p.d_tw[ax]) (void)hipFree(p.d_tw[ax]);
+    p.d_tw[ax] = nullptr;
+  }
+  if (p.d_mask) (void)hipFree(p.d_mask);
+  if (p.d_inv) (void)hipFree(p.d_inv);
+  if (p.d_w) (void)hipFree(p.d_w);
+  p.d_mask = nullptr;
+  p.d_inv = nullptr;
+  p.d_w = nullptr;
+}
+
+hipError_t run_basis_apply(const Plan& p, const float2* c, float2* S, void* ws, hipStream_t st) {
+  void* gws = wsp<void>(ws, p.off_gemm);
+  if (p.basis_kind == MAXWELL_BASIS_DENSE) return gemm_launch(dense_apply_args(p, c, S), p.precision, gws, st);
+  GemmArgs g[4];
+  tucker_apply_args(p, c, wsp<float2>(ws, p.off_tA), wsp<float2>(ws, p.off_tB), S, g);
+  for (int i = 0; i < 4; ++i) {
+    hipError_t e = gemm_launch(g[i], p.precision, gws, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t run_basis_adjoint(const Plan& p, const float2* S, float2* c, float alpha, const float* alpha_dev,
+                             void* ws, hipStream_t st) {
+  void* gws = wsp<void>(ws, p.off_gemm);
+  if (p.basis_kind == MAXWELL_BASIS_DENSE) {
+    GemmArgs g = dense_adjoint_args(p, S, c);
+    g.alpha = alpha;
+    g.alpha_dev = alpha_dev;
+    return gemm_launch(g, p.precision, gws, st);
+  }
+  GemmArgs g[4];
+  tucker_adjoint_args(p, S, wsp<float2>(ws, p.off_tA), wsp<float2>(ws, p.off_tB), c, g);
+  g[3].alpha = alpha;
+  g[3].alpha_dev = alpha_dev;
+  for (int i = 0; i < 4; ++i) {
+    hipError_t e = gemm_launch(g[i], p.precision, gws, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t run_encode(const Plan& p, const float2* x, const float2* c, float2* y, void* ws, hipStream_t st) {
+  float2* S = wsp<float2>(ws, p.off_S);
+  float2* Kb = wsp<float2>(ws, p.off_K);
+  hipError_t e = run_basis_apply(p, c, S, ws, st);
+  if (e != hipSuccess) return e;
+  if ((e = fft_image(p, S, Kb, -1, x, st)) != hipSuccess) return e;
+  return gather_launch(Kb, p.N, p.d_mask, p.M, p.J, y, st);
+}
+
+hipError_t run_forward_loss(const Plan& p, const float2* x, const float2* c, const float2* y, float2* r,
+                            double* loss, void* ws, hipStream_t st) {
+  float2* E = wsp<float2>(ws, p.off_E);
+  hipError_t e = run_encode(p, x, c, E, ws, st);
+  if (e != hipSuccess) return e;
+  double* part = wsp<double>(ws, p.off_part);
+  if ((e = residual_launch(E, y, p.d_w, p.M, p.J, r, part, st)) != hipSuccess) return e;
+  if (loss) return reduce_loss_launch(part, p.part_blocks, loss, st);
+  return hipSuccess;
+}
+
+hipError_t run_adjoint(const Plan& p, const float2* x, const float2* c, const float2* y, float alpha,
+                       const float* scale_dev, float2* gx, float2* gc, void* ws, hipStream_t st,
+                       bool maps_ready) {
+  float2* S = wsp<float2>(ws, p.off_S);
+  float2* Kb = wsp<float2>(ws, p.off_K);
+  hipError_t e;
+  if (gx && !maps_ready) {
+    if ((e = run_basis_apply(p, c, S, ws, st)) != hipSuccess) return e;
+  }
+  if ((e = scatter_launch(y, p.M, p.d_inv, p.N, p.J, Kb, st)) != hipSuccess) return e;
+  if ((e = fft_image(p, Kb, Kb, +1, nullptr, st)) != hipSuccess) return e;
+  if ((e = adjoint_combine_launch(S, Kb, x, p.N, p.J, alpha, scale_dev, gx, gc ? 1 : 0, st)) != hipSuccess)
+    return e;
+  if (gc) return run_basis_adjoint(p, Kb, gc, 1.0f, nullptr, ws, st);
+  return hipSuccess;
+}
+
+hipError_t run_grad(const Plan& p, const float2* x, const float2* c, const float2* y, float2* gx, float2* gc,
+                    double* loss, void* ws, hipStream_t st) {
+  float2* E = wsp<float2>(ws, p.off_E);
+  hipError_t e = run_forward_loss(p, x, c, y, E, loss, ws, st);
+  if (e != hipSuccess) return e;
+  if (!gx && !gc) return hipSuccess;
+  return run_adjoint(p, x, c, E, 2.0f, nullptr, gx, gc, ws, st, true);
+}
+
+}  // namespace mx

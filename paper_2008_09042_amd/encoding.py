@@ -1,0 +1,257 @@
+"""Python binding of libmaxwell: a plan object and two autograd Functions.
+
+PyTorch supplies device memory and the current stream; every step of the
+operator runs in the library's HIP kernels.  There is no fallback: if
+libmaxwell.so is missing or no GPU is present, construction raises.
+
+    plan = MaxwellPlan(dims, J, B=B, mask_idx=mask, precision="bf16_split")
+    y = MaxwellEncode.apply(x, c, plan)                 # E(x, c), backward = J^H
+    f = MaxwellDataFidelity.apply(x, c, y_meas, plan)   # sum w |E - y|^2, backward = 2 J^H (w r)
+
+Paper: Sec. II-B, Eq. (5) (operator), the J_G^H expression (adjoint) and
+Eq. (6) (data term).
+"""
+import ctypes
+import math
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_PRECISIONS = {"fp32": L.MAXWELL_FP32, "bf16_split": L.MAXWELL_BF16_SPLIT}
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class MaxwellPlan:
+    """One operator geometry on one GPU.
+
+    dims      image shape (2 or 3 axes, C-order)
+    J         number of coils
+    B         dense basis (N, K) (numpy or torch, converted to complex64 on the device)
+    U, core   Tucker factors [(n_m, r_m)] and core (r0, r1, r2, K) instead of B
+    mask_idx  sorted unique int64 linear indices into the centred k-space grid (Cartesian)
+    traj      (M, 2) trajectory in cycles/FOV (non-Cartesian, 2D)
+    weights   optional (M,) data weights for the loss and its gradient
+    precision "fp32" or "bf16_split" for the basis contractions
+    """
+
+    def __init__(self, dims: Sequence[int], J: int, *, B=None, U=None, core=None, mask_idx=None, traj=None,
+                 weights=None, precision: str = "fp32", kb_width: int = 6, oversamp: float = 2.0,
+                 kb_beta: float = 0.0, device="cuda:0"):
+        self.lib = L.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("MaxwellPlan needs a ROCm GPU; none is visible")
+        self.device = torch.device(device)
+        self.dims = tuple(int(n) for n in dims)
+        self.ndim = len(self.dims)
+        self.N = int(np.prod(self.dims))
+        self.J = int(J)
+        self.precision = precision
+        dev = self.device
+
+        def dtensor(a):
+            t = torch.as_tensor(a)
+            return t.to(device=dev, dtype=torch.complex64).contiguous()
+
+        bd = L.BasisDesc()
+        if B is not None:
+            self.B = dtensor(B)
+            if self.B.ndim != 2 or self.B.shape[0] != self.N:
+                raise ValueError("B must be (N, K)")
+            self.K = int(self.B.shape[1])
+            bd.kind = L.MAXWELL_BASIS_DENSE
+            bd.dense = self.B.data_ptr()
+            self._basis_refs = [self.B]
+        else:
+            self.U = [dtensor(u) for u in U]
+            self.core = dtensor(core)
+            self.K = int(self.core.shape[-1])
+            bd.kind = L.MAXWELL_BASIS_TUCKER
+            for m in range(3):
+                bd.r[m] = int(self.U[m].shape[1])
+                bd.U[m] = self.U[m].data_ptr()
+            bd.core = self.core.data_ptr()
+            self._basis_refs = self.U + [self.core]
+        bd.K = self.K
+
+        pd = L.PlanDesc()
+        pd.ndim = self.ndim
+        for d in range(self.ndim):
+            pd.n[d] = self.dims[d]
+        pd.J = self.J
+        pd.precision = _PRECISIONS[precision]
+        keep = []
+        if traj is None:
+            mask = np.ascontiguousarray(np.asarray(mask_idx, dtype=np.int64))
+            keep.append(mask)
+            pd.sampling = L.MAXWELL_CARTESIAN
+            pd.M = mask.size
+            pd.mask_idx = mask.ctypes.data
+        else:
+            tr = np.ascontiguousarray(np.asarray(traj, dtype=np.float32))
+            keep.append(tr)
+            pd.sampling = L.MAXWELL_NONCARTESIAN
+            pd.M = tr.shape[0]
+            pd.traj = tr.ctypes.data
+        if weights is not None:
+            w = np.ascontiguousarray(np.asarray(weights, dtype=np.float32))
+            keep.append(w)
+            pd.weights = w.ctypes.data
+        pd.kb_width = kb_width
+        pd.oversamp = oversamp
+        pd.kb_beta = kb_beta
+        self.M = int(pd.M)
+        self.has_weights = weights is not None
+
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(dev):
+            L.check(self.lib.maxwell_plan_create(ctypes.byref(pd), ctypes.byref(bd), ctypes.byref(handle)))
+        self.handle = handle
+        nbytes = ctypes.c_size_t()
+        L.check(self.lib.maxwell_plan_workspace_size(self.handle, ctypes.byref(nbytes)))
+        self.ws_bytes = int(nbytes.value)
+        raw = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=dev)
+        off = (-raw.data_ptr()) % 256
+        self._ws_raw = raw
+        self.ws = raw[off:off + self.ws_bytes] if self.ws_bytes else raw[:0]
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            try:
+                torch.cuda.synchronize(self.device)
+            except Exception:
+                pass
+            self.lib.maxwell_plan_destroy(h)
+            self.handle = None
+
+    # ---- argument checks (shape / dtype / device / contiguity)
+    def _in(self, t: torch.Tensor, shape, name):
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch tensor")
+        if t.dtype != torch.complex64 or t.device != self.device:
+            raise ValueError(f"{name} must be complex64 on {self.device}")
+        if tuple(t.shape) != tuple(shape) and t.numel() != int(np.prod(shape)):
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+        return t.contiguous()
+
+    def _new(self, shape):
+        return torch.empty(shape, dtype=torch.complex64, device=self.device)
+
+    def _wsargs(self):
+        return ctypes.c_void_p(self.ws.data_ptr()) if self.ws_bytes else None, self.ws_bytes
+
+    # ---- the C-ABI calls
+    def basis_apply(self, c):
+        c = self._in(c, (self.J, self.K), "c")
+        S = self._new((self.J, self.N))
+        ws, nb = self._wsargs()
+        L.check(self.lib.maxwell_basis_apply(self.handle, _ptr(c), _ptr(S), ws, nb, _stream()))
+        return S
+
+    def basis_adjoint(self, S):
+        S = self._in(S, (self.J, self.N), "S")
+        c = self._new((self.J, self.K))
+        ws, nb = self._wsargs()
+        L.check(self.lib.maxwell_basis_apply_adjoint(self.handle, _ptr(S), _ptr(c), ws, nb, _stream()))
+        return c
+
+    def encode(self, x, c):
+        x = self._in(x, self.dims, "x")
+        c = self._in(c, (self.J, self.K), "c")
+        y = self._new((self.J, self.M))
+        ws, nb = self._wsargs()
+        L.check(self.lib.maxwell_encode(self.handle, _ptr(x), _ptr(c), _ptr(y), ws, nb, _stream()))
+        return y
+
+    def adjoint(self, x, c, y, alpha: float = 1.0, scale: Optional[torch.Tensor] = None,
+                want_gx: bool = True, want_gc: bool = True):
+        x = self._in(x, self.dims, "x")
+        c = self._in(c, (self.J, self.K), "c")
+        y = self._in(y, (self.J, self.M), "y")
+        if scale is not None:
+            if scale.dtype != torch.float32 or scale.device != self.device or scale.numel() != 1:
+                raise ValueError("scale must be one float32 on the plan device")
+            scale = scale.contiguous()
+        gx = self._new(self.dims) if want_gx else None
+        gc = self._new((self.J, self.K)) if want_gc else None
+        ws, nb = self._wsargs()
+        L.check(self.lib.maxwell_adjoint(self.handle, _ptr(x), _ptr(c), _ptr(y), ctypes.c_float(alpha),
+                                         _ptr(scale), _ptr(gx), _ptr(gc), ws, nb, _stream()))
+        return gx, gc
+
+    def forward_loss(self, x, c, y, want_r: bool = True):
+        x = self._in(x, self.dims, "x")
+        c = self._in(c, (self.J, self.K), "c")
+        y = self._in(y, (self.J, self.M), "y")
+        r = self._new((self.J, self.M)) if want_r else None
+        loss = torch.empty((), dtype=torch.float64, device=self.device)
+        ws, nb = self._wsargs()
+        L.check(self.lib.maxwell_forward_loss(self.handle, _ptr(x), _ptr(c), _ptr(y), _ptr(r), _ptr(loss),
+                                              ws, nb, _stream()))
+        return r, loss
+
+    def grad(self, x, c, y):
+        x = self._in(x, self.dims, "x")
+        c = self._in(c, (self.J, self.K), "c")
+        y = self._in(y, (self.J, self.M), "y")
+        gx = self._new(self.dims)
+        gc = self._new((self.J, self.K))
+        loss = torch.empty((), dtype=torch.float64, device=self.device)
+        ws, nb = self._wsargs()
+        L.check(self.lib.maxwell_grad(self.handle, _ptr(x), _ptr(c), _ptr(y), _ptr(gx), _ptr(gc), _ptr(loss),
+                                      ws, nb, _stream()))
+        return loss, gx, gc
+
+
+class MaxwellEncode(torch.autograd.Function):
+    """y = E(x, c); backward applies the Jacobian adjoint J^H to the incoming gradient.
+
+    E is complex-linear in each argument, so in PyTorch's convention the
+    vector-Jacobian product is exactly (J_x^H gy, J_c^H gy).  B c is
+    recomputed inside the adjoint call; no per-coil maps are stored."""
+
+    @staticmethod
+    def forward(ctx, x, c, plan):
+        ctx.plan = plan
+        ctx.save_for_backward(x, c)
+        return plan.encode(x, c)
+
+    @staticmethod
+    def backward(ctx, gy):
+        x, c = ctx.saved_tensors
+        gx, gc = ctx.plan.adjoint(x, c, gy.contiguous(), want_gx=ctx.needs_input_grad[0],
+                                  want_gc=ctx.needs_input_grad[1])
+        return gx, gc, None
+
+
+class MaxwellDataFidelity(torch.autograd.Function):
+    """f = sum_j sum_m w_m |E(x, c)_jm - y_jm|^2 (FP64 scalar).
+
+    Forward keeps the weighted residual r = w (.) (E - y) ([J][M]); backward
+    runs the adjoint at (x, c) on r with scale 2 * grad_output (read on the
+    device), recomputing B c."""
+
+    @staticmethod
+    def forward(ctx, x, c, y, plan):
+        r, loss = plan.forward_loss(x, c, y)
+        ctx.plan = plan
+        ctx.save_for_backward(x, c, r)
+        return loss
+
+    @staticmethod
+    def backward(ctx, gloss):
+        x, c, r = ctx.saved_tensors
+        scale = gloss.detach().to(torch.float32).reshape(1)
+        gx, gc = ctx.plan.adjoint(x, c, r, alpha=2.0, scale=scale, want_gx=ctx.needs_input_grad[0],
+                                  want_gc=ctx.needs_input_grad[1])
+        return gx, gc, None, None
