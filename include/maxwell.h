@@ -134,6 +134,14 @@ void maxwell_plan_destroy(maxwell_plan_t plan);
 /* Workspace bytes every compute call of this plan needs.                    */
 maxwell_status maxwell_plan_workspace_size(maxwell_plan_t plan, size_t* bytes);
 
+/* Which kernel sequence the plan runs (a static string owned by the library):
+ *   "fused-tucker-lines"  3D Tucker basis, mask made of full lines along the last
+ *                         axis, n0 and n1 multiples of 16 and <= 128, n2 <= 256,
+ *                         r0, r1 <= 64: per-plane fused kernels, no [J][N] arrays;
+ *   "general"             any other geometry: basis apply, per-axis FFT, gather.
+ * NULL for a NULL plan.                                                       */
+const char* maxwell_plan_path(maxwell_plan_t plan);
+
 /* S[j] = B c_j  (paper Sec. II-B Eq. (5), s_k ~ U alpha_k).  c: [J][K], S: [J][N]. */
 maxwell_status maxwell_basis_apply(maxwell_plan_t plan, const maxwell_complex64* c,
                                    maxwell_complex64* S, void* ws, size_t ws_bytes, void* stream);

@@ -26,7 +26,7 @@ STATUS_NAMES = {
 
 # Every entry point declared in include/maxwell.h.
 EXPORTS = [
-    "maxwell_plan_create", "maxwell_plan_destroy", "maxwell_plan_workspace_size",
+    "maxwell_plan_create", "maxwell_plan_destroy", "maxwell_plan_workspace_size", "maxwell_plan_path",
     "maxwell_basis_apply", "maxwell_basis_apply_adjoint", "maxwell_encode", "maxwell_adjoint",
     "maxwell_forward_loss", "maxwell_grad", "maxwell_last_error", "maxwell_version",
 ]
@@ -85,6 +85,8 @@ def load(path: str = LIB_PATH):
     lib.maxwell_plan_destroy.restype = None
     lib.maxwell_plan_workspace_size.argtypes = [vp, ctypes.POINTER(sz)]
     lib.maxwell_plan_workspace_size.restype = st
+    lib.maxwell_plan_path.argtypes = [vp]
+    lib.maxwell_plan_path.restype = ctypes.c_char_p
     lib.maxwell_basis_apply.argtypes = [vp, vp, vp, vp, sz, vp]
     lib.maxwell_basis_apply.restype = st
     lib.maxwell_basis_apply_adjoint.argtypes = [vp, vp, vp, vp, sz, vp]

@@ -157,6 +157,11 @@ void maxwell_plan_destroy(maxwell_plan_t plan) {
   delete p;
 }
 
+const char* maxwell_plan_path(maxwell_plan_t plan) {
+  if (!plan) return nullptr;
+  return reinterpret_cast<Plan*>(plan)->fused ? "fused-tucker-lines" : "general";
+}
+
 maxwell_status maxwell_plan_workspace_size(maxwell_plan_t plan, size_t* bytes) {
   if (!plan || !bytes) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "null plan or bytes pointer");
   *bytes = reinterpret_cast<Plan*>(plan)->ws_bytes;

@@ -1,0 +1,169 @@
+// Device-side building blocks of the LDS-staged FFT (radix 2, 3, 4, 5, 8
+// butterflies and one self-sorting Stockham pass), shared by the per-axis FFT
+// kernel and the fused plane kernels.
+//
+// Each pass of radix R over `T` lines of length n held in LDS: every thread
+// loads its butterflies' R inputs (stride n/R), applies the twiddles
+// w^(k r) with w = exp(-+2 pi i / (Ns R)) and k = j mod Ns, runs the R-point DFT
+// and, after a barrier, stores the outputs at (j div Ns) Ns R + (j mod Ns) + r Ns.
+// After all passes the line holds its DFT in natural order (Stockham autosort).
+#pragma once
+
+#include "common.h"
+
+namespace mx {
+
+template <int R>
+__device__ inline void dft_small(float2 (&v)[R], int dir);
+
+template <>
+__device__ inline void dft_small<2>(float2 (&v)[2], int) {
+  float2 a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+
+// a * (-i) for the forward direction (dir = -1), a * (+i) for the inverse.
+__device__ inline float2 mul_mi(float2 a, int dir) {
+  return dir < 0 ? make_float2(a.y, -a.x) : make_float2(-a.y, a.x);
+}
+
+template <>
+__device__ inline void dft_small<4>(float2 (&v)[4], int dir) {
+  float2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+  float2 t2 = cadd(v[1], v[3]), t3 = mul_mi(csub(v[1], v[3]), dir);
+  v[0] = cadd(t0, t2);
+  v[2] = csub(t0, t2);
+  v[1] = cadd(t1, t3);
+  v[3] = csub(t1, t3);
+}
+
+template <>
+__device__ inline void dft_small<8>(float2 (&v)[8], int dir) {
+  float2 e[4] = {v[0], v[2], v[4], v[6]};
+  float2 o[4] = {v[1], v[3], v[5], v[7]};
+  dft_small<4>(e, dir);
+  dft_small<4>(o, dir);
+  const float h = 0.70710678118654752440f;  // 1/sqrt(2)
+  const float hd = dir < 0 ? -h : h;
+  // o[k] * exp(dir i pi k / 4)
+  float2 o1 = cmul(o[1], make_float2(h, hd));
+  float2 o2 = mul_mi(o[2], dir);
+  float2 o3 = cmul(o[3], make_float2(-h, hd));
+  v[0] = cadd(e[0], o[0]); v[4] = csub(e[0], o[0]);
+  v[1] = cadd(e[1], o1);   v[5] = csub(e[1], o1);
+  v[2] = cadd(e[2], o2);   v[6] = csub(e[2], o2);
+  v[3] = cadd(e[3], o3);   v[7] = csub(e[3], o3);
+}
+
+template <>
+__device__ inline void dft_small<3>(float2 (&v)[3], int dir) {
+  const float s = 0.86602540378443864676f;  // sin(2 pi / 3)
+  float2 t1 = cadd(v[1], v[2]);
+  float2 t2 = make_float2(v[0].x - 0.5f * t1.x, v[0].y - 0.5f * t1.y);
+  float2 rd = mul_mi(cscale(csub(v[1], v[2]), s), dir);
+  v[0] = cadd(v[0], t1);
+  v[1] = cadd(t2, rd);
+  v[2] = csub(t2, rd);
+}
+
+template <>
+__device__ inline void dft_small<5>(float2 (&v)[5], int dir) {
+  const float c1 = 0.30901699437494742410f;   // cos(2 pi/5)
+  const float c2 = -0.80901699437494742410f;  // cos(4 pi/5)
+  const float s1 = 0.95105651629515357212f;   // sin(2 pi/5)
+  const float s2 = 0.58778525229247312917f;   // sin(4 pi/5)
+  float2 b1 = cadd(v[1], v[4]), b2 = cadd(v[2], v[3]);
+  float2 d1 = csub(v[1], v[4]), d2 = csub(v[2], v[3]);
+  float2 a0 = v[0];
+  float2 t1 = make_float2(a0.x + c1 * b1.x + c2 * b2.x, a0.y + c1 * b1.y + c2 * b2.y);
+  float2 t2 = make_float2(a0.x + c2 * b1.x + c1 * b2.x, a0.y + c2 * b1.y + c1 * b2.y);
+  float2 u1 = make_float2(s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y);
+  float2 u2 = make_float2(s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y);
+  float2 ru1 = mul_mi(u1, dir), ru2 = mul_mi(u2, dir);
+  v[0] = cadd(a0, cadd(b1, b2));
+  v[1] = cadd(t1, ru1);
+  v[4] = csub(t1, ru1);
+  v[2] = cadd(t2, ru2);
+  v[3] = csub(t2, ru2);
+}
+
+// Line geometry of a tile held in LDS: element i of line l sits at l*LS + i*ES.
+struct LdsLines {
+  int T;       // number of lines
+  int LS, ES;  // strides of line and element (complex elements)
+};
+
+// One Stockham pass of radix R over lines [l0, l0 + Tc) of the tile.  NTHREADS
+// threads cooperate; CHUNK bounds Tc*n, so each thread holds at most
+// ceil(CHUNK / (R NTHREADS)) butterflies in registers between the two barriers.
+// Consecutive threads take consecutive lines.
+template <int R, int NTHREADS, int CHUNK>
+__device__ inline void stockham_pass(float2* lds, const LdsLines& tg, int l0, int Tc, int n, int Ns,
+                                     const float2* __restrict__ tw, int dir) {
+  constexpr int MAXQ = (CHUNK / R + NTHREADS - 1) / NTHREADS;
+  const int nR = n / R;
+  const int nb = Tc * nR;
+  const int stride_tw = n / (Ns * R);
+  float2 v[MAXQ][R];
+#pragma unroll
+  for (int q = 0; q < MAXQ; ++q) {
+    const int bf = threadIdx.x + q * NTHREADS;
+    if (bf < nb) {
+      const int l = l0 + bf % Tc, j = bf / Tc;
+      const int base = l * tg.LS;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = lds[base + (j + r * nR) * tg.ES];
+      const int k = j % Ns;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        float2 w = tw[k * r * stride_tw];
+        if (dir > 0) w.y = -w.y;
+        v[q][r] = cmul(v[q][r], w);
+      }
+      dft_small<R>(v[q], dir);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < MAXQ; ++q) {
+    const int bf = threadIdx.x + q * NTHREADS;
+    if (bf < nb) {
+      const int l = l0 + bf % Tc, j = bf / Tc;
+      const int base = l * tg.LS;
+      const int idxD = (j / Ns) * Ns * R + (j % Ns);
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[base + (idxD + r * Ns) * tg.ES] = v[q][r];
+    }
+  }
+  __syncthreads();
+}
+
+// All passes of one transform over every line of `tg`, CHUNK elements of lines at
+// a time (lines are independent, so a pass may finish one group of lines before
+// the next starts).  The caller has synchronised after filling the tile; on
+// return the tile is synchronised again.
+template <int NTHREADS, int CHUNK>
+__device__ inline void lds_fft_lines(float2* lds, const LdsLines& tg, int n, const int* radix, int nrad,
+                                     const float2* __restrict__ tw, int dir) {
+  int Tc = CHUNK / n;
+  if (Tc < 1) Tc = 1;
+  if (Tc > tg.T) Tc = tg.T;
+  int Ns = 1;
+  for (int p = 0; p < nrad; ++p) {
+    const int R = radix[p];
+    for (int l0 = 0; l0 < tg.T; l0 += Tc) {
+      const int tc = (tg.T - l0) < Tc ? (tg.T - l0) : Tc;
+      switch (R) {
+        case 8: stockham_pass<8, NTHREADS, CHUNK>(lds, tg, l0, tc, n, Ns, tw, dir); break;
+        case 4: stockham_pass<4, NTHREADS, CHUNK>(lds, tg, l0, tc, n, Ns, tw, dir); break;
+        case 2: stockham_pass<2, NTHREADS, CHUNK>(lds, tg, l0, tc, n, Ns, tw, dir); break;
+        case 3: stockham_pass<3, NTHREADS, CHUNK>(lds, tg, l0, tc, n, Ns, tw, dir); break;
+        default: stockham_pass<5, NTHREADS, CHUNK>(lds, tg, l0, tc, n, Ns, tw, dir); break;
+      }
+    }
+    Ns *= R;
+  }
+}
+
+}  // namespace mx

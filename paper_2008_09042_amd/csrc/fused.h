@@ -1,0 +1,56 @@
+// Arguments and launchers of the fused 3D Tucker / line-sampling path.
+#pragma once
+
+#include "common.h"
+
+namespace mx {
+
+struct PlaneArgs {
+  int n0, n1, n2, r0, r1, r0p, r1p;  // r0p, r1p: ranks rounded up to 16
+  int J, L, G;                       // coils, sampled lines, coils per workgroup
+  const float2* U0;                  // [n0][r0]
+  const float2* U1;                  // [n1][r1]
+  const float2* T3;                  // [J][n2][r0][r1]  (core x_4 c x_3 U2)
+  const float2* xt;                  // [n2][n0][n1]     image, readout axis first
+  const int32_t* pos;                // [L]  k0 * n1 + k1 of each sampled line
+  float2* Z;                         // [J][n2][L]  plane-DFT samples (fwd out / adj in)
+  float2* T3b;                       // [J][n2][r0][r1] adjoint out (or null)
+  float2* gxpart;                    // [ngroups][n2][n0][n1] adjoint out (or null)
+  const float2* tw0;                 // twiddles for n0, n1
+  const float2* tw1;
+  int nrad0, nrad1;
+  int rad0[12], rad1[12];
+  int precision;
+  const uint16_t* U0s;               // BF16 split planes of U0, U1 (hi re, lo re, hi im, lo im)
+  const uint16_t* U1s;
+};
+
+struct LineArgs {
+  int J, n2;
+  int64_t L, M;                      // M = L * n2
+  const float2* Z;                   // fwd in  [J][n2][L]
+  float2* out;                       // fwd out [J][M]: E (y == null) or w (.) (E - y)
+  const float2* y;                   // measured data or null
+  const float* w;                    // weights or null
+  double* part;                      // per-block loss partials or null
+  const float2* yin;                 // adj in [J][M]
+  float2* Zw;                        // adj out [J][n2][L]
+  float gscale;                      // prod_d (-1)^(n_d/2) / sqrt(n0 n1 n2)
+  float alpha;                       // adjoint scale alpha * (*scale_dev)
+  const float* scale_dev;
+  const float2* tw2;
+  int nrad2;
+  int rad2[12];
+};
+
+bool fused_supported(int64_t n0, int64_t n1, int64_t n2, int64_t r0, int64_t r1);
+hipError_t plane_fwd_launch(const PlaneArgs& a, hipStream_t st);
+hipError_t plane_adj_launch(const PlaneArgs& a, hipStream_t st);
+int line_blocks(int J, int64_t L);
+hipError_t line_fwd_launch(const LineArgs& a, hipStream_t st);
+hipError_t line_adj_launch(const LineArgs& a, hipStream_t st);
+hipError_t transpose_launch(const float2* x, int64_t R, int64_t C, float2* xt, hipStream_t st);
+hipError_t reduce_transpose_launch(const float2* part, int ngrp, int64_t R, int64_t C, float2* gx,
+                                   hipStream_t st);
+
+}  // namespace mx

@@ -29,9 +29,16 @@ struct Plan {
   float2* d_tw[3] = {nullptr, nullptr, nullptr};  // twiddle tables per axis
   int nrad[3] = {0, 0, 0};
   int radix[3][12];
+  // fused 3D Tucker path (Cartesian mask made of full lines along the last axis)
+  bool fused = false;
+  int64_t L = 0;               // sampled lines
+  int32_t* d_pos = nullptr;    // [L] plane index k0 * n1 + k1 of each line
+  int G_fwd = 2, G_adj = 4;    // coils per plane workgroup
+  float gscale = 1.0f;         // prod_d (-1)^(n_d/2) / sqrt(N)
   // workspace layout (byte offsets into the caller's workspace)
   size_t ws_bytes = 0;
   size_t off_S = 0, off_K = 0, off_tA = 0, off_tB = 0, off_E = 0, off_gemm = 0, off_part = 0;
+  size_t off_T1 = 0, off_T3 = 0, off_xt = 0, off_Z = 0, off_gxp = 0, off_T3b = 0, off_T1b = 0;
   int part_blocks = 0;
 
   size_t bytes_x() const { return (size_t)N * 8; }

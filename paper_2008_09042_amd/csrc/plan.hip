@@ -15,6 +15,7 @@
 #include <string>
 #include <vector>
 
+#include "fused.h"
 #include "plan.h"
 
 namespace mx {
@@ -140,6 +141,75 @@ hipError_t fft_image(const Plan& p, const float2* src, float2* dst, int dir, con
   return hipSuccess;
 }
 
+// ---- fused path GEMMs
+// T3[j][i2][p0 p1] = sum_p2 U2[i2][p2] T1[j][p0 p1][p2]
+GemmArgs fused_T3_args(const Plan& p, const float2* T1, float2* T3) {
+  const int64_t R01 = p.r[0] * p.r[1], R = R01 * p.r[2];
+  GemmArgs g = gemm0();
+  g.batch = p.J; g.M = p.n[2]; g.N = R01; g.K = p.r[2];
+  g.A = p.U[2]; g.a_ms = p.r[2]; g.a_ks = 1;
+  g.B = T1; g.b_bs = R; g.b_ks = 1; g.b_ns = p.r[2];
+  g.C = T3; g.c_bs = p.n[2] * R01; g.c_ms = R01; g.c_ns = 1;
+  return g;
+}
+
+// T1b[j][p0 p1][p2] = sum_i2 T3b[j][i2][p0 p1] conj(U2[i2][p2])
+GemmArgs fused_T1b_args(const Plan& p, const float2* T3b, float2* T1b) {
+  const int64_t R01 = p.r[0] * p.r[1], R = R01 * p.r[2];
+  GemmArgs g = gemm0();
+  g.batch = p.J; g.M = R01; g.N = p.r[2]; g.K = p.n[2];
+  g.A = T3b; g.a_bs = p.n[2] * R01; g.a_ms = 1; g.a_ks = R01;
+  g.B = p.U[2]; g.b_ks = p.r[2]; g.b_ns = 1; g.conjB = 1;
+  g.C = T1b; g.c_bs = R; g.c_ms = p.r[2]; g.c_ns = 1;
+  return g;
+}
+
+bool detect_lines(const maxwell_plan_desc& d, std::vector<int32_t>& pos) {
+  const int64_t n2 = d.n[2];
+  if (d.M <= 0 || d.M % n2) return false;
+  const int64_t L = d.M / n2;
+  pos.resize(L);
+  for (int64_t l = 0; l < L; ++l) {
+    const int64_t base = d.mask_idx[l * n2];
+    if (base % n2) return false;
+    for (int64_t t = 1; t < n2; ++t)
+      if (d.mask_idx[l * n2 + t] != base + t) return false;
+    pos[l] = (int32_t)(base / n2);
+  }
+  return true;
+}
+
+PlaneArgs plane_args(const Plan& p, void* ws, int G) {
+  PlaneArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.n0 = (int)p.n[0]; a.n1 = (int)p.n[1]; a.n2 = (int)p.n[2];
+  a.r0 = (int)p.r[0]; a.r1 = (int)p.r[1];
+  a.r0p = (a.r0 + 15) / 16 * 16; a.r1p = (a.r1 + 15) / 16 * 16;
+  a.J = p.J; a.L = (int)p.L; a.G = G;
+  a.U0 = p.U[0]; a.U1 = p.U[1];
+  a.T3 = wsp<float2>(ws, p.off_T3);
+  a.xt = wsp<float2>(ws, p.off_xt);
+  a.pos = p.d_pos;
+  a.Z = wsp<float2>(ws, p.off_Z);
+  a.tw0 = p.d_tw[0]; a.tw1 = p.d_tw[1];
+  a.nrad0 = p.nrad[0]; a.nrad1 = p.nrad[1];
+  for (int q = 0; q < 12; ++q) { a.rad0[q] = p.radix[0][q]; a.rad1[q] = p.radix[1][q]; }
+  a.precision = p.precision;
+  return a;
+}
+
+LineArgs line_args(const Plan& p) {
+  LineArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.J = p.J; a.n2 = (int)p.n[2]; a.L = p.L; a.M = p.M;
+  a.gscale = p.gscale;
+  a.alpha = 1.0f;
+  a.tw2 = p.d_tw[2];
+  a.nrad2 = p.nrad[2];
+  for (int q = 0; q < 12; ++q) a.rad2[q] = p.radix[2][q];
+  return a;
+}
+
 }  // namespace
 
 maxwell_status plan_build(Plan& p, const maxwell_plan_desc& d, const maxwell_basis_desc& b) {
@@ -171,6 +241,7 @@ maxwell_status plan_build(Plan& p, const maxwell_plan_desc& d, const maxwell_bas
   };
   hipError_t e;
   // twiddle tables, exp(-2 pi i t / n), computed in FP64 and rounded
+  double gs = 1.0;
   for (int ax = 0; ax < p.ndim; ++ax) {
     p.nrad[ax] = fft_factorise(p.n[ax], p.radix[ax]);
     std::vector<float2> tw(p.n[ax]);
@@ -181,9 +252,21 @@ maxwell_status plan_build(Plan& p, const maxwell_plan_desc& d, const maxwell_bas
     if ((e = hipMalloc(&p.d_tw[ax], tw.size() * sizeof(float2))) != hipSuccess) return hip_err(e);
     if ((e = hipMemcpy(p.d_tw[ax], tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess)
       return hip_err(e);
+    gs *= (((p.n[ax] / 2) & 1) ? -1.0 : 1.0) / std::sqrt((double)p.n[ax]);
   }
-  // mask tables
-  {
+  p.gscale = (float)gs;
+  // fused 3D Tucker path?
+  std::vector<int32_t> pos;
+  if (p.basis_kind == MAXWELL_BASIS_TUCKER && p.ndim == 3 &&
+      fused_supported(p.n[0], p.n[1], p.n[2], p.r[0], p.r[1]) && detect_lines(d, pos)) {
+    p.fused = true;
+    p.L = (int64_t)pos.size();
+    if ((e = hipMalloc(&p.d_pos, pos.size() * sizeof(int32_t))) != hipSuccess) return hip_err(e);
+    if ((e = hipMemcpy(p.d_pos, pos.data(), pos.size() * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess)
+      return hip_err(e);
+  }
+  // mask tables (general path)
+  if (!p.fused) {
     std::vector<int32_t> idx(p.M), inv(p.N, -1);
     for (int64_t m = 0; m < p.M; ++m) {
       idx[m] = (int32_t)d.mask_idx[m];
@@ -205,11 +288,13 @@ maxwell_status plan_build(Plan& p, const maxwell_plan_desc& d, const maxwell_bas
   }
 
   // workspace layout
-  const size_t JN = (size_t)p.J * (size_t)p.N * 8;
+  const size_t JN = (size_t)p.J * (size_t)p.N * 8, JM = (size_t)p.J * (size_t)p.M * 8;
   size_t off = 0;
-  p.off_S = off; off += al(JN);
-  p.off_K = off; off += al(JN);
   size_t gemm_ws = 0;
+  if (!p.fused) {
+    p.off_S = off; off += al(JN);
+    p.off_K = off; off += al(JN);
+  }
   if (p.basis_kind == MAXWELL_BASIS_TUCKER) {
     const size_t R = (size_t)(p.r[0] * p.r[1] * p.r[2]);
     size_t tA = std::max((size_t)p.J * R, (size_t)p.J * p.n[0] * p.n[1] * p.r[2]) * 8;
@@ -225,9 +310,24 @@ maxwell_status plan_build(Plan& p, const maxwell_plan_desc& d, const maxwell_bas
     gemm_ws = std::max(gemm_workspace_bytes(dense_apply_args(p, nullptr, nullptr)),
                        gemm_workspace_bytes(dense_adjoint_args(p, nullptr, nullptr)));
   }
-  p.off_E = off; off += al((size_t)p.J * (size_t)p.M * 8);
+  if (p.fused) {
+    const size_t R = (size_t)(p.r[0] * p.r[1] * p.r[2]);
+    const size_t T3 = (size_t)p.J * p.n[2] * p.r[0] * p.r[1] * 8;
+    const int ngrp = (p.J + p.G_adj - 1) / p.G_adj;
+    p.off_T1 = off; off += al((size_t)p.J * R * 8);
+    p.off_T3 = off; off += al(T3);
+    p.off_xt = off; off += al((size_t)p.N * 8);
+    p.off_Z = off; off += al(JM);
+    p.off_gxp = off; off += al((size_t)ngrp * p.N * 8);
+    p.off_T3b = off; off += al(T3);
+    p.off_T1b = off; off += al((size_t)p.J * R * 8);
+    gemm_ws = std::max(gemm_ws, gemm_workspace_bytes(fused_T3_args(p, nullptr, nullptr)));
+    gemm_ws = std::max(gemm_ws, gemm_workspace_bytes(fused_T1b_args(p, nullptr, nullptr)));
+  }
+  p.off_E = off; off += al(JM);
   p.off_gemm = off; off += al(gemm_ws);
   p.part_blocks = residual_blocks((int64_t)p.J * p.M);
+  if (p.fused) p.part_blocks = std::max(p.part_blocks, line_blocks(p.J, p.L));
   p.off_part = off; off += al((size_t)p.part_blocks * sizeof(double));
   p.ws_bytes = off;
   return MAXWELL_OK;
@@ -241,9 +341,11 @@ void plan_release(Plan& p) {
   if (p.d_mask) (void)hipFree(p.d_mask);
   if (p.d_inv) (void)hipFree(p.d_inv);
   if (p.d_w) (void)hipFree(p.d_w);
+  if (p.d_pos) (void)hipFree(p.d_pos);
   p.d_mask = nullptr;
   p.d_inv = nullptr;
   p.d_w = nullptr;
+  p.d_pos = nullptr;
 }
 
 hipError_t run_basis_apply(const Plan& p, const float2* c, float2* S, void* ws, hipStream_t st) {
@@ -278,7 +380,71 @@ hipError_t run_basis_adjoint(const Plan& p, const float2* S, float2* c, float al
   return hipSuccess;
 }
 
+// ---- fused path pieces
+static hipError_t fused_prepare(const Plan& p, const float2* x, const float2* c, void* ws, hipStream_t st) {
+  void* gws = wsp<void>(ws, p.off_gemm);
+  GemmArgs g[4];
+  tucker_apply_args(p, c, wsp<float2>(ws, p.off_T1), nullptr, nullptr, g);
+  hipError_t e = gemm_launch(g[0], p.precision, gws, st);  // T1 = core x_4 c
+  if (e != hipSuccess) return e;
+  e = gemm_launch(fused_T3_args(p, wsp<float2>(ws, p.off_T1), wsp<float2>(ws, p.off_T3)), p.precision, gws, st);
+  if (e != hipSuccess) return e;
+  return transpose_launch(x, p.n[0] * p.n[1], p.n[2], wsp<float2>(ws, p.off_xt), st);
+}
+
+static hipError_t fused_forward(const Plan& p, const float2* x, const float2* c, const float2* y, float2* out,
+                                double* part, void* ws, hipStream_t st) {
+  hipError_t e = fused_prepare(p, x, c, ws, st);
+  if (e != hipSuccess) return e;
+  PlaneArgs pa = plane_args(p, ws, p.G_fwd);
+  if ((e = plane_fwd_launch(pa, st)) != hipSuccess) return e;
+  LineArgs la = line_args(p);
+  la.Z = wsp<float2>(ws, p.off_Z);
+  la.out = out;
+  la.y = y;
+  la.w = y ? p.d_w : nullptr;
+  la.part = part;
+  return line_fwd_launch(la, st);
+}
+
+static hipError_t fused_adjoint(const Plan& p, const float2* x, const float2* c, const float2* y, float alpha,
+                                const float* scale_dev, float2* gx, float2* gc, void* ws, hipStream_t st,
+                                bool prepared) {
+  hipError_t e;
+  if (!prepared) {
+    if (gx) {
+      if ((e = fused_prepare(p, x, c, ws, st)) != hipSuccess) return e;
+    } else {
+      if ((e = transpose_launch(x, p.n[0] * p.n[1], p.n[2], wsp<float2>(ws, p.off_xt), st)) != hipSuccess) return e;
+    }
+  }
+  LineArgs la = line_args(p);
+  la.yin = y;
+  la.Zw = wsp<float2>(ws, p.off_Z);
+  la.alpha = alpha;
+  la.scale_dev = scale_dev;
+  if ((e = line_adj_launch(la, st)) != hipSuccess) return e;
+  PlaneArgs pa = plane_args(p, ws, p.G_adj);
+  pa.gxpart = gx ? wsp<float2>(ws, p.off_gxp) : nullptr;
+  pa.T3b = gc ? wsp<float2>(ws, p.off_T3b) : nullptr;
+  if ((e = plane_adj_launch(pa, st)) != hipSuccess) return e;
+  if (gx) {
+    const int ngrp = (p.J + p.G_adj - 1) / p.G_adj;
+    if ((e = reduce_transpose_launch(pa.gxpart, ngrp, p.n[0] * p.n[1], p.n[2], gx, st)) != hipSuccess) return e;
+  }
+  if (gc) {
+    void* gws = wsp<void>(ws, p.off_gemm);
+    if ((e = gemm_launch(fused_T1b_args(p, pa.T3b, wsp<float2>(ws, p.off_T1b)), p.precision, gws, st)) != hipSuccess)
+      return e;
+    GemmArgs g[4];
+    tucker_adjoint_args(p, nullptr, wsp<float2>(ws, p.off_T1b), nullptr, gc, g);
+    if ((e = gemm_launch(g[3], p.precision, gws, st)) != hipSuccess) return e;  // gc = core^H T1b
+  }
+  return hipSuccess;
+}
+
 hipError_t run_encode(const Plan& p, const float2* x, const float2* c, float2* y, void* ws, hipStream_t st) {
+  if (p.fused) return fused_forward(p, x, c, nullptr, y, nullptr, ws, st);
   float2* S = wsp<float2>(ws, p.off_S);
   float2* Kb = wsp<float2>(ws, p.off_K);
   hipError_t e = run_basis_apply(p, c, S, ws, st);
@@ -289,18 +455,24 @@ hipError_t run_encode(const Plan& p, const float2* x, const float2* c, float2* y
 
 hipError_t run_forward_loss(const Plan& p, const float2* x, const float2* c, const float2* y, float2* r,
                             double* loss, void* ws, hipStream_t st) {
-  float2* E = wsp<float2>(ws, p.off_E);
-  hipError_t e = run_encode(p, x, c, E, ws, st);
-  if (e != hipSuccess) return e;
   double* part = wsp<double>(ws, p.off_part);
+  hipError_t e;
+  if (p.fused) {
+    if ((e = fused_forward(p, x, c, y, r, part, ws, st)) != hipSuccess) return e;
+    if (loss) return reduce_loss_launch(part, line_blocks(p.J, p.L), loss, st);
+    return hipSuccess;
+  }
+  float2* E = wsp<float2>(ws, p.off_E);
+  if ((e = run_encode(p, x, c, E, ws, st)) != hipSuccess) return e;
   if ((e = residual_launch(E, y, p.d_w, p.M, p.J, r, part, st)) != hipSuccess) return e;
-  if (loss) return reduce_loss_launch(part, p.part_blocks, loss, st);
+  if (loss) return reduce_loss_launch(part, residual_blocks((int64_t)p.J * p.M), loss, st);
   return hipSuccess;
 }
 
 hipError_t run_adjoint(const Plan& p, const float2* x, const float2* c, const float2* y, float alpha,
                        const float* scale_dev, float2* gx, float2* gc, void* ws, hipStream_t st,
                        bool maps_ready) {
+  if (p.fused) return fused_adjoint(p, x, c, y, alpha, scale_dev, gx, gc, ws, st, maps_ready);
   float2* S = wsp<float2>(ws, p.off_S);
   float2* Kb = wsp<float2>(ws, p.off_K);
   hipError_t e;

@@ -119,6 +119,7 @@ class MaxwellPlan:
         nbytes = ctypes.c_size_t()
         L.check(self.lib.maxwell_plan_workspace_size(self.handle, ctypes.byref(nbytes)))
         self.ws_bytes = int(nbytes.value)
+        self.path = self.lib.maxwell_plan_path(self.handle).decode()
         raw = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=dev)
         off = (-raw.data_ptr()) % 256
         self._ws_raw = raw

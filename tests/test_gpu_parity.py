@@ -26,7 +26,16 @@ CASES = {
                                      basis="tucker", mask="random"),
     "tucker3d_32x32x32_r12_K70_J4": dict(seed=106, dims=(32, 32, 32), ranks=(12, 12, 12), J=4, K=70,
                                          basis="tucker", mask="lines3d", frac=0.25),
+    # fused plane path: n0, n1 multiples of 16; ragged coil groups, radix-5 plane axis, rank padding
+    "fused_48x32x20_r9x13x5_K23_J5": dict(seed=109, dims=(48, 32, 20), ranks=(9, 13, 5), J=5, K=23,
+                                          basis="tucker", mask="lines3d", frac=0.3, weights=True),
+    "fused_16x80x12_r3x17x4_K11_J3": dict(seed=110, dims=(16, 80, 12), ranks=(3, 17, 4), J=3, K=11,
+                                          basis="tucker", mask="lines3d", frac=0.2),
+    "fused_128x128x64_r40_K60_J2": dict(seed=111, dims=(128, 128, 64), ranks=(40, 40, 40), J=2, K=60,
+                                        basis="tucker", mask="lines3d", frac=0.125),
 }
+FUSED = {"tucker3d_32x32x32_r12_K70_J4", "fused_48x32x20_r9x13x5_K23_J5", "fused_16x80x12_r3x17x4_K11_J3",
+         "fused_128x128x64_r40_K60_J2"}
 
 _cache = {}
 
@@ -72,6 +81,7 @@ def test_encode_adjoint_grad(name, prec):
     cs = get_case(name)
     print(f"[case] {name} {prec}", flush=True)
     plan = cs.plan(prec)
+    assert plan.path == ("fused-tucker-lines" if name in FUSED else "general")
     tol = TOL[prec]
     x, c, y = T(cs.x0), T(cs.c0), T(cs.y)
     # encode
@@ -92,7 +102,8 @@ def test_encode_adjoint_grad(name, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16_split"])
-@pytest.mark.parametrize("name", ["dense2d_48x40_J5_K37", "tucker3d_24x20x18_r7x5x6_K13"])
+@pytest.mark.parametrize("name", ["dense2d_48x40_J5_K37", "tucker3d_24x20x18_r7x5x6_K13",
+                                  "fused_48x32x20_r9x13x5_K23_J5"])
 def test_autograd_data_fidelity(name, prec):
     """torch.autograd.Function: forward = loss, backward = adjoint with B c recomputed."""
     from paper_2008_09042_amd.encoding import MaxwellDataFidelity, MaxwellEncode
@@ -147,9 +158,10 @@ def test_edge_full_and_empty_mask():
     assert float(gx.abs().max().item()) == 0.0 and float(gc.abs().max().item()) == 0.0
 
 
-def test_repeatable_bitwise():
+@pytest.mark.parametrize("name", ["tucker3d_24x20x18_r7x5x6_K13", "fused_48x32x20_r9x13x5_K23_J5"])
+def test_repeatable_bitwise(name):
     """No atomics anywhere: two runs give identical bits."""
-    cs = get_case("tucker3d_24x20x18_r7x5x6_K13")
+    cs = get_case(name)
     plan = cs.plan()
     x, c, y = T(cs.x0), T(cs.c0), T(cs.y)
     a = plan.grad(x, c, y)
