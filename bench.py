@@ -70,8 +70,34 @@ def time_steps(step, steps, warmup, torch):
     return e0.elapsed_time(e1) / steps, wall
 
 
-def cpu_baseline(p, coils=2):
-    """The FP64 oracle on host cores: one gradient evaluation over a subset of coils."""
+def kernel_work(name, p, prec):
+    """Algorithmic work of one launch of a kernel of the fused 3D Tucker path.
+
+    Returns (bound, unit, amount, peak).  Contractions count 8 real flops per complex
+    multiply-accumulate (CMAC) over the mode products the kernel performs; memory-bound
+    kernels count the bytes they must move (complex64 = 8 B, FP32 weights = 4 B)."""
+    n0, n1, n2 = p.dims
+    r0, r1, r2 = (u.shape[1] for u in p.U)
+    J, K, M = p.J, p.K, p.M
+    planes = J * n2
+    # the plane kernels issue FP32 MFMAs (16x16x4) in both precisions; the BF16-split
+    # plan changes only the GEMM kernel around them
+    mfma_peak = PEAKS_TFLOPS["fp32"]
+    v_p = r0 * r1 * n1 + n0 * r0 * n1          # V = W U1^T, P = U0 V  per coil-plane
+    y_w = n0 * n1 * r1 + r0 * n0 * r1          # Y = h conj(U1), Wb = U0^H Y
+    table = {
+        "plane_fwd": ("mfma", "TFLOP/s", 8.0 * planes * v_p, mfma_peak),
+        "plane_adj": ("mfma", "TFLOP/s", 8.0 * planes * (v_p + y_w), mfma_peak),
+        "line_fwd": ("hbm", "GB/s", 8.0 * J * M * 3 + 4.0 * M, HBM_PEAK_GBS),
+        "line_adj": ("hbm", "GB/s", 8.0 * J * M * 2, HBM_PEAK_GBS),
+        "gemm_core_coef": ("hbm", "GB/s", 8.0 * (r0 * r1 * r2 * K + J * K + J * r0 * r1 * r2), HBM_PEAK_GBS),
+        "gemm_core_adjoint": ("hbm", "GB/s", 8.0 * (r0 * r1 * r2 * K + J * K + J * r0 * r1 * r2), HBM_PEAK_GBS),
+    }
+    return table.get(name)
+
+
+def cpu_baseline(p, coils=32, repeats=2):
+    """The FP64 oracle on host cores: `repeats` gradient evaluations over `coils` coils."""
     import threadpoolctl
     from oracle import Oracle
     ncores = len(os.sched_getaffinity(0))
@@ -82,10 +108,11 @@ def cpu_baseline(p, coils=2):
         rng = np.random.default_rng(0)
         y = rng.normal(size=(coils, p.M)) + 1j * rng.normal(size=(coils, p.M))
         t0 = time.perf_counter()
-        op.loss_and_grad(p.x0, p.c0[:coils], y)
+        for _ in range(repeats):
+            op.loss_and_grad(p.x0, p.c0[:coils], y)
         dt = time.perf_counter() - t0
-    return {"value": coils / dt, "unit": "coil-images/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"one FP64 gradient evaluation over {coils} of the 32 coils at 128^3 "
+    return {"value": repeats * coils / dt, "unit": "coil-images/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{repeats} FP64 gradient evaluations over {coils} of the 32 coils at 128^3 "
                       f"(Tucker 40^3 x 300, 262,144 samples/coil): {dt:.1f} s; NumPy FFT single-threaded, "
                       f"BLAS threads = {threads}"}
 
@@ -135,6 +162,16 @@ def main():
         results[prec] = ms
         grads[prec] = (x.grad.clone(), c.grad.clone())
         log(f"[bench] {prec}: {ms:.3f} ms/step ({p.J * 1000.0 / ms:.0f} coil-images/s), wall {wall:.2f}s")
+        if prec == args.precision:
+            # same K steps again with per-kernel HIP events recorded by the library on the launch stream
+            plan.set_timing(True)
+            ms_t, _ = time_steps(step, args.steps, 0, torch)
+            kt = plan.timing()
+            plan.set_timing(False)
+            kernels = {k: {"launches": n, "avg_us": 1000.0 * t / n} for k, (n, t) in kt.items() if n}
+            log(f"[bench] kernel timing pass: {ms_t:.3f} ms/step; " +
+                ", ".join(f"{k} {v['avg_us']:.1f}us x{v['launches']}" for k, v in
+                          sorted(kernels.items(), key=lambda kv: -kv[1]["avg_us"] * kv[1]["launches"])))
 
     prec = args.precision
     ms = results[prec]
@@ -162,6 +199,16 @@ def main():
         out["bf16_split_vs_fp32_rel_diff"] = {
             "gx": float(torch.linalg.vector_norm(gxs - gx32) / torch.linalg.vector_norm(gx32)),
             "gc": float(torch.linalg.vector_norm(gcs - gc32) / torch.linalg.vector_norm(gc32))}
+    dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"])
+    work = kernel_work(dom, p, prec)
+    if work is not None:
+        bound, unit, amount, peak = work
+        avg_s = kernels[dom]["avg_us"] * 1e-6
+        achieved = amount / avg_s / (1e12 if unit == "TFLOP/s" else 1e9)
+        out["roofline"] = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+                           "frac": achieved / peak, "traffic": None,
+                           "per_launch": amount, "avg_launch_us": kernels[dom]["avg_us"]}
+    out["kernels"] = kernels
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on the host (bounded sample) ...")
         out["cpu_baseline"] = cpu_baseline(p)

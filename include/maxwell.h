@@ -186,6 +186,21 @@ maxwell_status maxwell_grad(maxwell_plan_t plan, const maxwell_complex64* x,
                             maxwell_complex64* gx, maxwell_complex64* gc, double* loss_dev,
                             void* ws, size_t ws_bytes, void* stream);
 
+/* Kernel timing for benchmarks.  enable != 0 clears the plan's records and
+ * starts recording: every kernel launch made by a compute call of this plan is
+ * then bracketed by two HIP events recorded on the call's stream (event objects
+ * are created on first use and reused).  enable == 0 stops recording.  Not for
+ * use under graph capture.                                                     */
+maxwell_status maxwell_plan_set_timing(maxwell_plan_t plan, int enable);
+
+/* Summary of the records since the last maxwell_plan_set_timing(plan, 1):
+ * synchronises the recorded events, then for kernel index i (0 <= i < *count)
+ * returns its name (static string), number of launches and summed duration in
+ * milliseconds.  `count` may be queried alone with the other pointers NULL;
+ * an i outside [0, *count) with a non-NULL name returns INVALID_ARGUMENT.      */
+maxwell_status maxwell_plan_timing(maxwell_plan_t plan, int i, int* count, const char** name,
+                                   int64_t* launches, double* total_ms);
+
 /* Thread-local text for the last non-OK status returned on this thread.       */
 const char* maxwell_last_error(void);
 

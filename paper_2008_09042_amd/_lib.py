@@ -29,6 +29,7 @@ EXPORTS = [
     "maxwell_plan_create", "maxwell_plan_destroy", "maxwell_plan_workspace_size", "maxwell_plan_path",
     "maxwell_basis_apply", "maxwell_basis_apply_adjoint", "maxwell_encode", "maxwell_adjoint",
     "maxwell_forward_loss", "maxwell_grad", "maxwell_last_error", "maxwell_version",
+    "maxwell_plan_set_timing", "maxwell_plan_timing",
 ]
 
 
@@ -99,6 +100,12 @@ def load(path: str = LIB_PATH):
     lib.maxwell_forward_loss.restype = st
     lib.maxwell_grad.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.maxwell_grad.restype = st
+    lib.maxwell_plan_set_timing.argtypes = [vp, ctypes.c_int]
+    lib.maxwell_plan_set_timing.restype = st
+    lib.maxwell_plan_timing.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                        ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(i64),
+                                        ctypes.POINTER(ctypes.c_double)]
+    lib.maxwell_plan_timing.restype = st
     lib.maxwell_last_error.argtypes = []
     lib.maxwell_last_error.restype = ctypes.c_char_p
     lib.maxwell_version.argtypes = []

@@ -157,6 +157,44 @@ void maxwell_plan_destroy(maxwell_plan_t plan) {
   delete p;
 }
 
+maxwell_status maxwell_plan_set_timing(maxwell_plan_t plan, int enable) {
+  if (!plan) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "plan is null");
+  Timing& t = reinterpret_cast<Plan*>(plan)->timing;
+  if (enable) {
+    t.recs.clear();
+    t.names.clear();
+  }
+  t.on = enable != 0;
+  return MAXWELL_OK;
+}
+
+maxwell_status maxwell_plan_timing(maxwell_plan_t plan, int i, int* count, const char** name, int64_t* launches,
+                                   double* total_ms) {
+  if (!plan) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "plan is null");
+  Timing& t = reinterpret_cast<Plan*>(plan)->timing;
+  if (count) *count = (int)t.names.size();
+  if (!name && !launches && !total_ms) return MAXWELL_OK;
+  if (i < 0 || i >= (int)t.names.size()) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "timing index out of range");
+  if (!t.recs.empty()) {
+    hipError_t e = hipEventSynchronize(t.ev_stop[t.recs.back().ev]);
+    if (e != hipSuccess) return hip_fail(e, "plan_timing");
+  }
+  int64_t n = 0;
+  double ms = 0.0;
+  for (const auto& r : t.recs) {
+    if (r.name != i) continue;
+    float f = 0.f;
+    hipError_t e = hipEventElapsedTime(&f, t.ev_start[r.ev], t.ev_stop[r.ev]);
+    if (e != hipSuccess) return hip_fail(e, "plan_timing");
+    ms += f;
+    ++n;
+  }
+  if (name) *name = t.names[i];
+  if (launches) *launches = n;
+  if (total_ms) *total_ms = ms;
+  return MAXWELL_OK;
+}
+
 const char* maxwell_plan_path(maxwell_plan_t plan) {
   if (!plan) return nullptr;
   return reinterpret_cast<Plan*>(plan)->fused ? "fused-tucker-lines" : "general";

@@ -2,13 +2,24 @@
 #pragma once
 
 #include <string>
+#include <vector>
 
 #include "../../include/maxwell.h"
 #include "common.h"
 
 namespace mx {
 
+// Optional per-kernel timing (HIP events on the launch stream).
+struct Timing {
+  bool on = false;
+  struct Rec { int name; int ev; };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> ev_start, ev_stop;   // pool, reused across sessions
+  std::vector<const char*> names;
+};
+
 struct Plan {
+  mutable Timing timing;
   // geometry
   int ndim = 0;
   int64_t n[3] = {1, 1, 1};
@@ -49,6 +60,15 @@ struct Plan {
 
 // Records the thread-local message returned by maxwell_last_error().
 void set_last_error(const std::string& msg);
+
+// Brackets one kernel launch with timing events when timing is on.
+struct Span {
+  const Plan& p;
+  hipStream_t st;
+  int ev = -1;
+  Span(const Plan& plan, const char* name, hipStream_t stream);
+  ~Span();
+};
 
 maxwell_status plan_build(Plan& p, const maxwell_plan_desc& d, const maxwell_basis_desc& b);
 void plan_release(Plan& p);

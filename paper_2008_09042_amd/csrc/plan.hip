@@ -20,6 +20,32 @@
 
 namespace mx {
 
+Span::Span(const Plan& plan, const char* name, hipStream_t stream) : p(plan), st(stream) {
+  Timing& t = p.timing;
+  if (!t.on) return;
+  int id = -1;
+  for (size_t i = 0; i < t.names.size(); ++i)
+    if (std::strcmp(t.names[i], name) == 0) id = (int)i;
+  if (id < 0) { t.names.push_back(name); id = (int)t.names.size() - 1; }
+  const size_t k = t.recs.size();
+  if (k >= t.ev_start.size()) {
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return;
+    if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
+    t.ev_start.push_back(a);
+    t.ev_stop.push_back(b);
+  }
+  if (hipEventRecord(t.ev_start[k], st) != hipSuccess) return;
+  t.recs.push_back({id, (int)k});
+  ev = (int)k;
+}
+
+Span::~Span() {
+  if (ev >= 0) (void)hipEventRecord(p.timing.ev_stop[ev], st);
+}
+
+#define TIMED(name, expr) ([&]() { Span _span(p, name, st); return (expr); }())
+
 namespace {
 
 size_t al(size_t v) { return (v + 255) & ~size_t(255); }
@@ -134,7 +160,7 @@ hipError_t fft_image(const Plan& p, const float2* src, float2* dst, int dir, con
     a.nrad = p.nrad[d];
     for (int q = 0; q < p.nrad[d]; ++q) a.radix[q] = p.radix[d][q];
     a.premul = (t == 0) ? premul : nullptr;
-    hipError_t e = fft_axis_launch(a, st);
+    hipError_t e = TIMED("fft_axis", fft_axis_launch(a, st));
     if (e != hipSuccess) return e;
     cur = dst;
   }
@@ -334,6 +360,9 @@ maxwell_status plan_build(Plan& p, const maxwell_plan_desc& d, const maxwell_bas
 }
 
 void plan_release(Plan& p) {
+  for (auto e : p.timing.ev_start) (void)hipEventDestroy(e);
+  for (auto e : p.timing.ev_stop) (void)hipEventDestroy(e);
+  p.timing = Timing();
   for (int ax = 0; ax < 3; ++ax) {
     if (p.d_tw[ax]) (void)hipFree(p.d_tw[ax]);
     p.d_tw[ax] = nullptr;
@@ -350,11 +379,12 @@ void plan_release(Plan& p) {
 
 hipError_t run_basis_apply(const Plan& p, const float2* c, float2* S, void* ws, hipStream_t st) {
   void* gws = wsp<void>(ws, p.off_gemm);
-  if (p.basis_kind == MAXWELL_BASIS_DENSE) return gemm_launch(dense_apply_args(p, c, S), p.precision, gws, st);
+  if (p.basis_kind == MAXWELL_BASIS_DENSE)
+    return TIMED("gemm_dense_apply", gemm_launch(dense_apply_args(p, c, S), p.precision, gws, st));
   GemmArgs g[4];
   tucker_apply_args(p, c, wsp<float2>(ws, p.off_tA), wsp<float2>(ws, p.off_tB), S, g);
   for (int i = 0; i < 4; ++i) {
-    hipError_t e = gemm_launch(g[i], p.precision, gws, st);
+    hipError_t e = TIMED("gemm_tucker_chain", gemm_launch(g[i], p.precision, gws, st));
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -367,14 +397,14 @@ hipError_t run_basis_adjoint(const Plan& p, const float2* S, float2* c, float al
     GemmArgs g = dense_adjoint_args(p, S, c);
     g.alpha = alpha;
     g.alpha_dev = alpha_dev;
-    return gemm_launch(g, p.precision, gws, st);
+    return TIMED("gemm_dense_adjoint", gemm_launch(g, p.precision, gws, st));
   }
   GemmArgs g[4];
   tucker_adjoint_args(p, S, wsp<float2>(ws, p.off_tA), wsp<float2>(ws, p.off_tB), c, g);
   g[3].alpha = alpha;
   g[3].alpha_dev = alpha_dev;
   for (int i = 0; i < 4; ++i) {
-    hipError_t e = gemm_launch(g[i], p.precision, gws, st);
+    hipError_t e = TIMED("gemm_tucker_adjoint_chain", gemm_launch(g[i], p.precision, gws, st));
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -385,11 +415,12 @@ static hipError_t fused_prepare(const Plan& p, const float2* x, const float2* c,
   void* gws = wsp<void>(ws, p.off_gemm);
   GemmArgs g[4];
   tucker_apply_args(p, c, wsp<float2>(ws, p.off_T1), nullptr, nullptr, g);
-  hipError_t e = gemm_launch(g[0], p.precision, gws, st);  // T1 = core x_4 c
+  hipError_t e = TIMED("gemm_core_coef", gemm_launch(g[0], p.precision, gws, st));  // T1 = core x_4 c
   if (e != hipSuccess) return e;
-  e = gemm_launch(fused_T3_args(p, wsp<float2>(ws, p.off_T1), wsp<float2>(ws, p.off_T3)), p.precision, gws, st);
+  e = TIMED("gemm_mode3", gemm_launch(fused_T3_args(p, wsp<float2>(ws, p.off_T1), wsp<float2>(ws, p.off_T3)),
+                                      p.precision, gws, st));
   if (e != hipSuccess) return e;
-  return transpose_launch(x, p.n[0] * p.n[1], p.n[2], wsp<float2>(ws, p.off_xt), st);
+  return TIMED("transpose_x", transpose_launch(x, p.n[0] * p.n[1], p.n[2], wsp<float2>(ws, p.off_xt), st));
 }
 
 static hipError_t fused_forward(const Plan& p, const float2* x, const float2* c, const float2* y, float2* out,
@@ -397,14 +428,14 @@ static hipError_t fused_forward(const Plan& p, const float2* x, const float2* c,
   hipError_t e = fused_prepare(p, x, c, ws, st);
   if (e != hipSuccess) return e;
   PlaneArgs pa = plane_args(p, ws, p.G_fwd);
-  if ((e = plane_fwd_launch(pa, st)) != hipSuccess) return e;
+  if ((e = TIMED("plane_fwd", plane_fwd_launch(pa, st))) != hipSuccess) return e;
   LineArgs la = line_args(p);
   la.Z = wsp<float2>(ws, p.off_Z);
   la.out = out;
   la.y = y;
   la.w = y ? p.d_w : nullptr;
   la.part = part;
-  return line_fwd_launch(la, st);
+  return TIMED("line_fwd", line_fwd_launch(la, st));
 }
 
 static hipError_t fused_adjoint(const Plan& p, const float2* x, const float2* c, const float2* y, float alpha,
@@ -415,7 +446,8 @@ static hipError_t fused_adjoint(const Plan& p, const float2* x, const float2* c,
     if (gx) {
       if ((e = fused_prepare(p, x, c, ws, st)) != hipSuccess) return e;
     } else {
-      if ((e = transpose_launch(x, p.n[0] * p.n[1], p.n[2], wsp<float2>(ws, p.off_xt), st)) != hipSuccess) return e;
+      e = TIMED("transpose_x", transpose_launch(x, p.n[0] * p.n[1], p.n[2], wsp<float2>(ws, p.off_xt), st));
+      if (e != hipSuccess) return e;
     }
   }
   LineArgs la = line_args(p);
@@ -423,22 +455,25 @@ static hipError_t fused_adjoint(const Plan& p, const float2* x, const float2* c,
   la.Zw = wsp<float2>(ws, p.off_Z);
   la.alpha = alpha;
   la.scale_dev = scale_dev;
-  if ((e = line_adj_launch(la, st)) != hipSuccess) return e;
+  if ((e = TIMED("line_adj", line_adj_launch(la, st))) != hipSuccess) return e;
   PlaneArgs pa = plane_args(p, ws, p.G_adj);
   pa.gxpart = gx ? wsp<float2>(ws, p.off_gxp) : nullptr;
   pa.T3b = gc ? wsp<float2>(ws, p.off_T3b) : nullptr;
-  if ((e = plane_adj_launch(pa, st)) != hipSuccess) return e;
+  if ((e = TIMED("plane_adj", plane_adj_launch(pa, st))) != hipSuccess) return e;
   if (gx) {
     const int ngrp = (p.J + p.G_adj - 1) / p.G_adj;
-    if ((e = reduce_transpose_launch(pa.gxpart, ngrp, p.n[0] * p.n[1], p.n[2], gx, st)) != hipSuccess) return e;
+    e = TIMED("gx_reduce", reduce_transpose_launch(pa.gxpart, ngrp, p.n[0] * p.n[1], p.n[2], gx, st));
+    if (e != hipSuccess) return e;
   }
   if (gc) {
     void* gws = wsp<void>(ws, p.off_gemm);
-    if ((e = gemm_launch(fused_T1b_args(p, pa.T3b, wsp<float2>(ws, p.off_T1b)), p.precision, gws, st)) != hipSuccess)
-      return e;
+    e = TIMED("gemm_mode3_adjoint",
+              gemm_launch(fused_T1b_args(p, pa.T3b, wsp<float2>(ws, p.off_T1b)), p.precision, gws, st));
+    if (e != hipSuccess) return e;
     GemmArgs g[4];
     tucker_adjoint_args(p, nullptr, wsp<float2>(ws, p.off_T1b), nullptr, gc, g);
-    if ((e = gemm_launch(g[3], p.precision, gws, st)) != hipSuccess) return e;  // gc = core^H T1b
+    e = TIMED("gemm_core_adjoint", gemm_launch(g[3], p.precision, gws, st));  // gc = core^H T1b
+    if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -450,7 +485,7 @@ hipError_t run_encode(const Plan& p, const float2* x, const float2* c, float2* y
   hipError_t e = run_basis_apply(p, c, S, ws, st);
   if (e != hipSuccess) return e;
   if ((e = fft_image(p, S, Kb, -1, x, st)) != hipSuccess) return e;
-  return gather_launch(Kb, p.N, p.d_mask, p.M, p.J, y, st);
+  return TIMED("gather", gather_launch(Kb, p.N, p.d_mask, p.M, p.J, y, st));
 }
 
 hipError_t run_forward_loss(const Plan& p, const float2* x, const float2* c, const float2* y, float2* r,
@@ -459,13 +494,13 @@ hipError_t run_forward_loss(const Plan& p, const float2* x, const float2* c, con
   hipError_t e;
   if (p.fused) {
     if ((e = fused_forward(p, x, c, y, r, part, ws, st)) != hipSuccess) return e;
-    if (loss) return reduce_loss_launch(part, line_blocks(p.J, p.L), loss, st);
+    if (loss) return TIMED("reduce_loss", reduce_loss_launch(part, line_blocks(p.J, p.L), loss, st));
     return hipSuccess;
   }
   float2* E = wsp<float2>(ws, p.off_E);
   if ((e = run_encode(p, x, c, E, ws, st)) != hipSuccess) return e;
-  if ((e = residual_launch(E, y, p.d_w, p.M, p.J, r, part, st)) != hipSuccess) return e;
-  if (loss) return reduce_loss_launch(part, residual_blocks((int64_t)p.J * p.M), loss, st);
+  if ((e = TIMED("residual", residual_launch(E, y, p.d_w, p.M, p.J, r, part, st))) != hipSuccess) return e;
+  if (loss) return TIMED("reduce_loss", reduce_loss_launch(part, residual_blocks((int64_t)p.J * p.M), loss, st));
   return hipSuccess;
 }
 
@@ -479,10 +514,10 @@ hipError_t run_adjoint(const Plan& p, const float2* x, const float2* c, const fl
   if (gx && !maps_ready) {
     if ((e = run_basis_apply(p, c, S, ws, st)) != hipSuccess) return e;
   }
-  if ((e = scatter_launch(y, p.M, p.d_inv, p.N, p.J, Kb, st)) != hipSuccess) return e;
+  if ((e = TIMED("scatter", scatter_launch(y, p.M, p.d_inv, p.N, p.J, Kb, st))) != hipSuccess) return e;
   if ((e = fft_image(p, Kb, Kb, +1, nullptr, st)) != hipSuccess) return e;
-  if ((e = adjoint_combine_launch(S, Kb, x, p.N, p.J, alpha, scale_dev, gx, gc ? 1 : 0, st)) != hipSuccess)
-    return e;
+  e = TIMED("adjoint_combine", adjoint_combine_launch(S, Kb, x, p.N, p.J, alpha, scale_dev, gx, gc ? 1 : 0, st));
+  if (e != hipSuccess) return e;
   if (gc) return run_basis_adjoint(p, Kb, gc, 1.0f, nullptr, ws, st);
   return hipSuccess;
 }

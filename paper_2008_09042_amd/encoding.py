@@ -135,6 +135,24 @@ class MaxwellPlan:
             self.lib.maxwell_plan_destroy(h)
             self.handle = None
 
+    # ---- per-kernel timing (HIP events on the launch stream)
+    def set_timing(self, enable: bool):
+        L.check(self.lib.maxwell_plan_set_timing(self.handle, 1 if enable else 0))
+
+    def timing(self):
+        """{kernel name: (launches, total ms)} recorded since set_timing(True)."""
+        n = ctypes.c_int()
+        L.check(self.lib.maxwell_plan_timing(self.handle, 0, ctypes.byref(n), None, None, None))
+        out = {}
+        for i in range(n.value):
+            name = ctypes.c_char_p()
+            cnt = ctypes.c_int64()
+            ms = ctypes.c_double()
+            L.check(self.lib.maxwell_plan_timing(self.handle, i, None, ctypes.byref(name), ctypes.byref(cnt),
+                                                 ctypes.byref(ms)))
+            out[name.value.decode()] = (int(cnt.value), float(ms.value))
+        return out
+
     # ---- argument checks (shape / dtype / device / contiguity)
     def _in(self, t: torch.Tensor, shape, name):
         if not isinstance(t, torch.Tensor):
