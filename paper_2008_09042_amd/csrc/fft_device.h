@@ -56,6 +56,40 @@ __device__ inline void dft_small<8>(float2 (&v)[8], int dir) {
   v[3] = cadd(e[3], o3);   v[7] = csub(e[3], o3);
 }
 
+// 16-point DFT as 4 x 4: DFT4 over n1 for each n2 (n = 4 n1 + n2), twiddle
+// w16^(n2 k1), DFT4 over n2 for each k1; output index k = k1 + 4 k2.
+template <>
+__device__ inline void dft_small<16>(float2 (&v)[16], int dir) {
+  float2 a[4][4];  // a[n2][k1]
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    float2 t[4] = {v[n2], v[4 + n2], v[8 + n2], v[12 + n2]};
+    dft_small<4>(t, dir);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) a[n2][k1] = t[k1];
+  }
+  const float c1 = 0.92387953251128675613f, s1 = 0.38268343236508977173f;  // cos, sin of pi/8
+  const float h = 0.70710678118654752440f;
+  const float sg = dir < 0 ? -1.f : 1.f;
+  // w16^m = (cos(2 pi m/16), sg * sin(2 pi m/16)) for m = n2 * k1
+  a[1][1] = cmul(a[1][1], make_float2(c1, sg * s1));
+  a[1][2] = cmul(a[1][2], make_float2(h, sg * h));
+  a[1][3] = cmul(a[1][3], make_float2(s1, sg * c1));
+  a[2][1] = cmul(a[2][1], make_float2(h, sg * h));
+  a[2][2] = mul_mi(a[2][2], dir);
+  a[2][3] = cmul(a[2][3], make_float2(-h, sg * h));
+  a[3][1] = cmul(a[3][1], make_float2(s1, sg * c1));
+  a[3][2] = cmul(a[3][2], make_float2(-h, sg * h));
+  a[3][3] = cmul(a[3][3], make_float2(-c1, -sg * s1));
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    float2 t[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+    dft_small<4>(t, dir);
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[k2];
+  }
+}
+
 template <>
 __device__ inline void dft_small<3>(float2 (&v)[3], int dir) {
   const float s = 0.86602540378443864676f;  // sin(2 pi / 3)
@@ -164,6 +198,69 @@ __device__ inline void lds_fft_lines(float2* lds, const LdsLines& tg, int n, con
     }
     Ns *= R;
   }
+}
+
+
+// ---------------------------------------------------------------- compile-time sizes
+// Radix plan for the sizes the fused kernels specialise on.
+template <int N> struct CtPlan;
+template <> struct CtPlan<256> { static constexpr int P = 2, R0 = 16, R1 = 16; };
+template <> struct CtPlan<128> { static constexpr int P = 2, R0 = 16, R1 = 8; };
+template <> struct CtPlan<64> { static constexpr int P = 2, R0 = 8, R1 = 8; };
+template <> struct CtPlan<32> { static constexpr int P = 2, R0 = 8, R1 = 4; };
+template <> struct CtPlan<16> { static constexpr int P = 1, R0 = 16, R1 = 1; };
+
+// One Stockham pass with compile-time size, radix and stride.  `tw` holds
+// exp(-2 pi i t / N), t < N (in LDS).  T lines, CH elements per register chunk.
+template <int N, int R, int Ns, int NTHREADS, int CH>
+__device__ inline void stockham_pass_ct(float2* lds, int T, int LS, int ES, const float2* tw, int dir) {
+  constexpr int nR = N / R;
+  constexpr int Tc = CH / N;
+  constexpr int MAXQ = (Tc * nR + NTHREADS - 1) / NTHREADS;
+  constexpr int STW = N / (Ns * R);
+  for (int l0 = 0; l0 < T; l0 += Tc) {
+    float2 v[MAXQ][R];
+#pragma unroll
+    for (int q = 0; q < MAXQ; ++q) {
+      const int bf = threadIdx.x + q * NTHREADS;
+      const int l = l0 + bf % Tc, j = bf / Tc;
+      if (bf < Tc * nR && l < T) {
+        const int base = l * LS;
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[q][r] = lds[base + (j + r * nR) * ES];
+        if (Ns > 1) {
+          const int k = j % Ns;
+#pragma unroll
+          for (int r = 1; r < R; ++r) {
+            float2 w = tw[k * r * STW];
+            if (dir > 0) w.y = -w.y;
+            v[q][r] = cmul(v[q][r], w);
+          }
+        }
+        dft_small<R>(v[q], dir);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MAXQ; ++q) {
+      const int bf = threadIdx.x + q * NTHREADS;
+      const int l = l0 + bf % Tc, j = bf / Tc;
+      if (bf < Tc * nR && l < T) {
+        const int base = l * LS;
+        const int idxD = (j / Ns) * Ns * R + (j % Ns);
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds[base + (idxD + r * Ns) * ES] = v[q][r];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int N, int NTHREADS, int CH>
+__device__ inline void lds_fft_ct(float2* lds, int T, int LS, int ES, const float2* tw, int dir) {
+  using P = CtPlan<N>;
+  stockham_pass_ct<N, P::R0, 1, NTHREADS, CH>(lds, T, LS, ES, tw, dir);
+  if constexpr (P::P > 1) stockham_pass_ct<N, P::R1, P::R0, NTHREADS, CH>(lds, T, LS, ES, tw, dir);
 }
 
 }  // namespace mx

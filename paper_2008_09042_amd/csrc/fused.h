@@ -21,8 +21,11 @@ struct PlaneArgs {
   int nrad0, nrad1;
   int rad0[12], rad1[12];
   int precision;
-  const uint16_t* U0s;               // BF16 split planes of U0, U1 (hi re, lo re, hi im, lo im)
-  const uint16_t* U1s;
+  // BF16-split operand planes built at plan time (real-block form, hi / lo):
+  const unsigned short* U0A;         // [2][n0][KP0]   A operand of P = U0 V
+  const unsigned short* U1B;         // [4][n1][KP1]   B operand of V = W U1^T
+  const unsigned short* U1C;         // [4][r1p][2 n1] B operand of Y = h conj(U1)
+  const unsigned short* U0H;         // [2][r0p][2 n0] A operand of Wb = U0^H Y
 };
 
 struct LineArgs {
@@ -43,7 +46,10 @@ struct LineArgs {
   int rad2[12];
 };
 
-bool fused_supported(int64_t n0, int64_t n1, int64_t n2, int64_t r0, int64_t r1);
+bool fused_supported(int64_t n0, int64_t n1, int64_t n2, int64_t r0, int64_t r1, int precision);
+// Real-block split of a complex matrix (see tucker_fused.hip); returns the launch status.
+hipError_t split_operand_launch(const float2* src, int rows, int cols, int64_t sm, int64_t sk, int conj, int mode,
+                                int rows_pad, int kp, uint16_t* dst, hipStream_t st);
 hipError_t plane_fwd_launch(const PlaneArgs& a, hipStream_t st);
 hipError_t plane_adj_launch(const PlaneArgs& a, hipStream_t st);
 int line_blocks(int J, int64_t L);

@@ -44,6 +44,8 @@ struct Plan {
   bool fused = false;
   int64_t L = 0;               // sampled lines
   int32_t* d_pos = nullptr;    // [L] plane index k0 * n1 + k1 of each line
+  uint16_t* d_split = nullptr; // BF16-split factor operands (one allocation)
+  const uint16_t *U0A = nullptr, *U1B = nullptr, *U1C = nullptr, *U0H = nullptr;
   int G_fwd = 2, G_adj = 4;    // coils per plane workgroup
   float gscale = 1.0f;         // prod_d (-1)^(n_d/2) / sqrt(N)
   // workspace layout (byte offsets into the caller's workspace)

@@ -31,11 +31,13 @@ CASES = {
                                           basis="tucker", mask="lines3d", frac=0.3, weights=True),
     "fused_16x80x12_r3x17x4_K11_J3": dict(seed=110, dims=(16, 80, 12), ranks=(3, 17, 4), J=3, K=11,
                                           basis="tucker", mask="lines3d", frac=0.2),
-    "fused_128x128x64_r40_K60_J2": dict(seed=111, dims=(128, 128, 64), ranks=(40, 40, 40), J=2, K=60,
+    "fused_128x128x64_r40_K60_J5": dict(seed=111, dims=(128, 128, 64), ranks=(40, 40, 40), J=5, K=60,
                                         basis="tucker", mask="lines3d", frac=0.125),
+    "fused_64x64x32_r20_K30_J3": dict(seed=112, dims=(64, 64, 32), ranks=(20, 20, 7), J=3, K=30,
+                                      basis="tucker", mask="lines3d", frac=0.2, weights=True),
 }
 FUSED = {"tucker3d_32x32x32_r12_K70_J4", "fused_48x32x20_r9x13x5_K23_J5", "fused_16x80x12_r3x17x4_K11_J3",
-         "fused_128x128x64_r40_K60_J2"}
+         "fused_128x128x64_r40_K60_J5", "fused_64x64x32_r20_K30_J3"}
 
 _cache = {}
 
