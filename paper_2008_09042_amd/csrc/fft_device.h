@@ -14,22 +14,22 @@
 namespace mx {
 
 template <int R>
-__device__ inline void dft_small(float2 (&v)[R], int dir);
+__device__ __forceinline__ void dft_small(float2 (&v)[R], int dir);
 
 template <>
-__device__ inline void dft_small<2>(float2 (&v)[2], int) {
+__device__ __forceinline__ void dft_small<2>(float2 (&v)[2], int) {
   float2 a = v[0], b = v[1];
   v[0] = cadd(a, b);
   v[1] = csub(a, b);
 }
 
 // a * (-i) for the forward direction (dir = -1), a * (+i) for the inverse.
-__device__ inline float2 mul_mi(float2 a, int dir) {
+__device__ __forceinline__ float2 mul_mi(float2 a, int dir) {
   return dir < 0 ? make_float2(a.y, -a.x) : make_float2(-a.y, a.x);
 }
 
 template <>
-__device__ inline void dft_small<4>(float2 (&v)[4], int dir) {
+__device__ __forceinline__ void dft_small<4>(float2 (&v)[4], int dir) {
   float2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
   float2 t2 = cadd(v[1], v[3]), t3 = mul_mi(csub(v[1], v[3]), dir);
   v[0] = cadd(t0, t2);
@@ -39,7 +39,7 @@ __device__ inline void dft_small<4>(float2 (&v)[4], int dir) {
 }
 
 template <>
-__device__ inline void dft_small<8>(float2 (&v)[8], int dir) {
+__device__ __forceinline__ void dft_small<8>(float2 (&v)[8], int dir) {
   float2 e[4] = {v[0], v[2], v[4], v[6]};
   float2 o[4] = {v[1], v[3], v[5], v[7]};
   dft_small<4>(e, dir);
@@ -59,7 +59,7 @@ __device__ inline void dft_small<8>(float2 (&v)[8], int dir) {
 // 16-point DFT as 4 x 4: DFT4 over n1 for each n2 (n = 4 n1 + n2), twiddle
 // w16^(n2 k1), DFT4 over n2 for each k1; output index k = k1 + 4 k2.
 template <>
-__device__ inline void dft_small<16>(float2 (&v)[16], int dir) {
+__device__ __forceinline__ void dft_small<16>(float2 (&v)[16], int dir) {
   float2 a[4][4];  // a[n2][k1]
 #pragma unroll
   for (int n2 = 0; n2 < 4; ++n2) {
@@ -91,7 +91,7 @@ __device__ inline void dft_small<16>(float2 (&v)[16], int dir) {
 }
 
 template <>
-__device__ inline void dft_small<3>(float2 (&v)[3], int dir) {
+__device__ __forceinline__ void dft_small<3>(float2 (&v)[3], int dir) {
   const float s = 0.86602540378443864676f;  // sin(2 pi / 3)
   float2 t1 = cadd(v[1], v[2]);
   float2 t2 = make_float2(v[0].x - 0.5f * t1.x, v[0].y - 0.5f * t1.y);
@@ -102,7 +102,7 @@ __device__ inline void dft_small<3>(float2 (&v)[3], int dir) {
 }
 
 template <>
-__device__ inline void dft_small<5>(float2 (&v)[5], int dir) {
+__device__ __forceinline__ void dft_small<5>(float2 (&v)[5], int dir) {
   const float c1 = 0.30901699437494742410f;   // cos(2 pi/5)
   const float c2 = -0.80901699437494742410f;  // cos(4 pi/5)
   const float s1 = 0.95105651629515357212f;   // sin(2 pi/5)
@@ -133,7 +133,7 @@ struct LdsLines {
 // ceil(CHUNK / (R NTHREADS)) butterflies in registers between the two barriers.
 // Consecutive threads take consecutive lines.
 template <int R, int NTHREADS, int CHUNK>
-__device__ inline void stockham_pass(float2* lds, const LdsLines& tg, int l0, int Tc, int n, int Ns,
+__device__ __forceinline__ void stockham_pass(float2* lds, const LdsLines& tg, int l0, int Tc, int n, int Ns,
                                      const float2* __restrict__ tw, int dir) {
   constexpr int MAXQ = (CHUNK / R + NTHREADS - 1) / NTHREADS;
   const int nR = n / R;
@@ -178,7 +178,7 @@ __device__ inline void stockham_pass(float2* lds, const LdsLines& tg, int l0, in
 // the next starts).  The caller has synchronised after filling the tile; on
 // return the tile is synchronised again.
 template <int NTHREADS, int CHUNK>
-__device__ inline void lds_fft_lines(float2* lds, const LdsLines& tg, int n, const int* radix, int nrad,
+__device__ __forceinline__ void lds_fft_lines(float2* lds, const LdsLines& tg, int n, const int* radix, int nrad,
                                      const float2* __restrict__ tw, int dir) {
   int Tc = CHUNK / n;
   if (Tc < 1) Tc = 1;
@@ -213,7 +213,7 @@ template <> struct CtPlan<16> { static constexpr int P = 1, R0 = 16, R1 = 1; };
 // One Stockham pass with compile-time size, radix and stride.  `tw` holds
 // exp(-2 pi i t / N), t < N (in LDS).  T lines, CH elements per register chunk.
 template <int N, int R, int Ns, int NTHREADS, int CH>
-__device__ inline void stockham_pass_ct(float2* lds, int T, int LS, int ES, const float2* tw, int dir) {
+__device__ __forceinline__ void stockham_pass_ct(float2* lds, int T, int LS, int ES, const float2* tw, int dir) {
   constexpr int nR = N / R;
   constexpr int Tc = CH / N;
   constexpr int MAXQ = (Tc * nR + NTHREADS - 1) / NTHREADS;
@@ -257,7 +257,7 @@ __device__ inline void stockham_pass_ct(float2* lds, int T, int LS, int ES, cons
 }
 
 template <int N, int NTHREADS, int CH>
-__device__ inline void lds_fft_ct(float2* lds, int T, int LS, int ES, const float2* tw, int dir) {
+__device__ __forceinline__ void lds_fft_ct(float2* lds, int T, int LS, int ES, const float2* tw, int dir) {
   using P = CtPlan<N>;
   stockham_pass_ct<N, P::R0, 1, NTHREADS, CH>(lds, T, LS, ES, tw, dir);
   if constexpr (P::P > 1) stockham_pass_ct<N, P::R1, P::R0, NTHREADS, CH>(lds, T, LS, ES, tw, dir);

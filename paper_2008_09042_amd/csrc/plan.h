@@ -48,10 +48,22 @@ struct Plan {
   const uint16_t *U0A = nullptr, *U1B = nullptr, *U1C = nullptr, *U0H = nullptr;
   int G_fwd = 2, G_adj = 4;    // coils per plane workgroup
   float gscale = 1.0f;         // prod_d (-1)^(n_d/2) / sqrt(N)
+  // non-Cartesian sampling (Kaiser-Bessel NUFFT, 2D)
+  int g[2] = {0, 0};             // oversampled grid
+  int W = 0;                     // kernel width
+  float kscale = 1.0f;           // sqrt(g0 g1 / N)
+  float* d_iphi = nullptr;       // [n0 + n1] inverse deapodisation per axis
+  int2* d_base = nullptr;        // [M] first tap per axis (wrapped grid index)
+  float* d_wts = nullptr;        // [M][2][W] tap weights
+  int32_t* d_tptr = nullptr;     // spread tiles (CSR)
+  int32_t* d_tidx = nullptr;
+  float2* d_twg[2] = {nullptr, nullptr};  // grid twiddles
+  int nradg[2] = {0, 0};
+  int radixg[2][12];
   // workspace layout (byte offsets into the caller's workspace)
   size_t ws_bytes = 0;
   size_t off_S = 0, off_K = 0, off_tA = 0, off_tB = 0, off_E = 0, off_gemm = 0, off_part = 0;
-  size_t off_T1 = 0, off_T3 = 0, off_xt = 0, off_Z = 0, off_gxp = 0, off_T3b = 0, off_T1b = 0;
+  size_t off_T1 = 0, off_T3 = 0, off_xt = 0, off_Z = 0, off_gxp = 0, off_T3b = 0, off_T1b = 0, off_G = 0;
   int part_blocks = 0;
 
   size_t bytes_x() const { return (size_t)N * 8; }

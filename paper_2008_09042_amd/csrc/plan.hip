@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "fused.h"
+#include "nufft.h"
 #include "plan.h"
 
 namespace mx {
@@ -139,32 +140,68 @@ void tucker_adjoint_args(const Plan& p, const float2* h, float2* tA, float2* tB,
 template <typename T>
 T* wsp(void* ws, size_t off) { return reinterpret_cast<T*>(reinterpret_cast<char*>(ws) + off); }
 
-hipError_t fft_image(const Plan& p, const float2* src, float2* dst, int dir, const float2* premul,
-                     hipStream_t st) {
+// Centred unitary DFT over every axis of J stacked arrays of shape dims[0..nd).
+hipError_t fft_dims(const Plan& p, const float2* src, float2* dst, int dir, const float2* premul, int nd,
+                    const int64_t* dims, float2* const* tw, const int* nrad, const int (*radix)[12], hipStream_t st) {
   const float2* cur = src;
-  for (int t = 0; t < p.ndim; ++t) {
-    const int d = p.ndim - 1 - t;
+  for (int t = 0; t < nd; ++t) {
+    const int d = nd - 1 - t;
     int64_t inner = 1, opc = 1;
-    for (int e = d + 1; e < p.ndim; ++e) inner *= p.n[e];
-    for (int e = 0; e < d; ++e) opc *= p.n[e];
+    for (int e = d + 1; e < nd; ++e) inner *= dims[e];
+    for (int e = 0; e < d; ++e) opc *= dims[e];
     FftAxisArgs a;
     std::memset(&a, 0, sizeof(a));
     a.data = dst;
     a.src = cur;
-    a.n = p.n[d];
+    a.n = dims[d];
     a.inner = inner;
     a.outer = (int64_t)p.J * opc;
     a.outer_per_coil = opc;
     a.dir = dir;
-    a.twiddle = p.d_tw[d];
-    a.nrad = p.nrad[d];
-    for (int q = 0; q < p.nrad[d]; ++q) a.radix[q] = p.radix[d][q];
+    a.twiddle = tw[d];
+    a.nrad = nrad[d];
+    for (int q = 0; q < nrad[d]; ++q) a.radix[q] = radix[d][q];
     a.premul = (t == 0) ? premul : nullptr;
     hipError_t e = TIMED("fft_axis", fft_axis_launch(a, st));
     if (e != hipSuccess) return e;
     cur = dst;
   }
   return hipSuccess;
+}
+
+hipError_t fft_image(const Plan& p, const float2* src, float2* dst, int dir, const float2* premul,
+                     hipStream_t st) {
+  return fft_dims(p, src, dst, dir, premul, p.ndim, p.n, p.d_tw, p.nrad, p.radix, st);
+}
+
+hipError_t fft_grid(const Plan& p, float2* data, int dir, hipStream_t st) {
+  const int64_t dims[2] = {p.g[0], p.g[1]};
+  return fft_dims(p, data, data, dir, nullptr, 2, dims, p.d_twg, p.nradg, p.radixg, st);
+}
+
+NufftArgs nufft_args(const Plan& p) {
+  NufftArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.n0 = (int)p.n[0]; a.n1 = (int)p.n[1];
+  a.g0 = p.g[0]; a.g1 = p.g[1];
+  a.J = p.J; a.W = p.W; a.M = p.M;
+  a.iphi0 = p.d_iphi; a.iphi1 = p.d_iphi + p.n[0];
+  a.base = p.d_base; a.wts = p.d_wts;
+  a.tile_ptr = p.d_tptr; a.tile_idx = p.d_tidx;
+  a.cscale = p.kscale;
+  return a;
+}
+
+// Modified Bessel function I0 from its power series sum_k ((x/2)^(2k)) / (k!)^2.
+double bessel_i0(double x) {
+  const double q = 0.25 * x * x;
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 200; ++k) {
+    term *= q / ((double)k * (double)k);
+    sum += term;
+    if (term < 1e-17 * sum) break;
+  }
+  return sum;
 }
 
 // ---- fused path GEMMs
@@ -242,6 +279,99 @@ LineArgs line_args(const Plan& p) {
 
 }  // namespace
 
+// Kaiser-Bessel NUFFT tables (host, FP64): oversampled grid, twiddles, inverse
+// deapodisation per axis, per-sample first tap and weights, and the spread-tile
+// sample lists.  Kernel phi(t) = I0(beta sqrt(1 - (2t/W)^2)) / W on |t| <= W/2,
+// its Fourier transform Phi(nu) = sinh(sqrt(beta^2 - (pi W nu)^2)) / sqrt(...)
+// (sin form when the radicand is negative); beta defaults to Beatty, Nishimura
+// and Pauly: pi sqrt((W/sigma)^2 (sigma - 1/2)^2 - 0.8).
+static maxwell_status nufft_build(Plan& p, const maxwell_plan_desc& d) {
+  auto hip_err = [&](hipError_t e) {
+    set_last_error(std::string("HIP error during plan creation: ") + hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? MAXWELL_ERR_OUT_OF_MEMORY : MAXWELL_ERR_HIP;
+  };
+  const int W = d.kb_width;
+  const double sigma = d.oversamp;
+  double beta = d.kb_beta;
+  if (beta <= 0.0) beta = M_PI * std::sqrt((W / sigma) * (W / sigma) * (sigma - 0.5) * (sigma - 0.5) - 0.8);
+  p.W = W;
+  for (int ax = 0; ax < 2; ++ax) p.g[ax] = (int)std::llround(sigma * (double)p.n[ax]);
+  p.kscale = (float)std::sqrt((double)p.g[0] * p.g[1] / ((double)p.n[0] * p.n[1]));
+  hipError_t e;
+  for (int ax = 0; ax < 2; ++ax) {
+    const int G = p.g[ax];
+    p.nradg[ax] = fft_factorise(G, p.radixg[ax]);
+    std::vector<float2> tw(G);
+    for (int t = 0; t < G; ++t) {
+      const double ang = -2.0 * M_PI * (double)t / (double)G;
+      tw[t] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+    }
+    if ((e = hipMalloc(&p.d_twg[ax], G * sizeof(float2))) != hipSuccess) return hip_err(e);
+    if ((e = hipMemcpy(p.d_twg[ax], tw.data(), G * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess)
+      return hip_err(e);
+  }
+  auto Phi = [&](double nu) {
+    const double z2 = beta * beta - (M_PI * W * nu) * (M_PI * W * nu);
+    if (z2 > 0) { const double z = std::sqrt(z2); return std::sinh(z) / z; }
+    if (z2 < 0) { const double z = std::sqrt(-z2); return std::sin(z) / z; }
+    return 1.0;
+  };
+  auto phi = [&](double t) {
+    const double a = 1.0 - (2.0 * t / W) * (2.0 * t / W);
+    return a >= 0 ? bessel_i0(beta * std::sqrt(a)) / W : 0.0;
+  };
+  std::vector<float> iphi(p.n[0] + p.n[1]);
+  for (int ax = 0, o = 0; ax < 2; o += (int)p.n[ax], ++ax)
+    for (int r = 0; r < p.n[ax]; ++r) iphi[o + r] = (float)(1.0 / Phi((double)(r - p.n[ax] / 2) / (double)p.g[ax]));
+  const int64_t M = p.M;
+  std::vector<int2> base(M);
+  std::vector<float> wts((size_t)M * 2 * W);
+  const int TE = nufft_tile_edge();
+  const int tiles0 = (p.g[0] + TE - 1) / TE, tiles1 = (p.g[1] + TE - 1) / TE;
+  std::vector<std::vector<int32_t>> lists((size_t)tiles0 * tiles1);
+  for (int64_t m = 0; m < M; ++m) {
+    int b[2];
+    for (int ax = 0; ax < 2; ++ax) {
+      const double u = sigma * (double)d.traj[m * 2 + ax];
+      const double g0 = std::ceil(u - 0.5 * W);
+      for (int t = 0; t < W; ++t) wts[(size_t)m * 2 * W + ax * W + t] = (float)phi(u - (g0 + t));
+      const int G = p.g[ax];
+      b[ax] = (int)((((int64_t)g0 + G / 2) % G + G) % G);
+    }
+    base[m] = make_int2(b[0], b[1]);
+    // tiles met by the W x W footprint (periodic)
+    int tr[8], tc[8], nr = 0, nc = 0;
+    for (int t = 0; t < W; ++t) {
+      const int r = ((b[0] + t) % p.g[0]) / TE, c = ((b[1] + t) % p.g[1]) / TE;
+      bool seen = false;
+      for (int q = 0; q < nr; ++q) seen |= tr[q] == r;
+      if (!seen) tr[nr++] = r;
+      seen = false;
+      for (int q = 0; q < nc; ++q) seen |= tc[q] == c;
+      if (!seen) tc[nc++] = c;
+    }
+    for (int i = 0; i < nr; ++i)
+      for (int k = 0; k < nc; ++k) lists[(size_t)tr[i] * tiles1 + tc[k]].push_back((int32_t)m);
+  }
+  std::vector<int32_t> tptr(lists.size() + 1, 0), tidx;
+  for (size_t t = 0; t < lists.size(); ++t) {
+    tptr[t + 1] = tptr[t] + (int32_t)lists[t].size();
+    tidx.insert(tidx.end(), lists[t].begin(), lists[t].end());
+  }
+  if (tidx.empty()) tidx.push_back(0);
+  auto up = [&](void** dst, const void* src, size_t bytes) -> hipError_t {
+    hipError_t r = hipMalloc(dst, bytes ? bytes : 8);
+    if (r != hipSuccess || !bytes) return r;
+    return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+  };
+  if ((e = up((void**)&p.d_iphi, iphi.data(), iphi.size() * sizeof(float))) != hipSuccess) return hip_err(e);
+  if ((e = up((void**)&p.d_base, base.data(), base.size() * sizeof(int2))) != hipSuccess) return hip_err(e);
+  if ((e = up((void**)&p.d_wts, wts.data(), wts.size() * sizeof(float))) != hipSuccess) return hip_err(e);
+  if ((e = up((void**)&p.d_tptr, tptr.data(), tptr.size() * sizeof(int32_t))) != hipSuccess) return hip_err(e);
+  if ((e = up((void**)&p.d_tidx, tidx.data(), tidx.size() * sizeof(int32_t))) != hipSuccess) return hip_err(e);
+  return MAXWELL_OK;
+}
+
 maxwell_status plan_build(Plan& p, const maxwell_plan_desc& d, const maxwell_basis_desc& b) {
   p.ndim = d.ndim;
   p.N = 1;
@@ -260,10 +390,6 @@ maxwell_status plan_build(Plan& p, const maxwell_plan_desc& d, const maxwell_bas
   }
   p.core = reinterpret_cast<const float2*>(b.core);
 
-  if (d.sampling != MAXWELL_CARTESIAN) {
-    set_last_error("non-Cartesian sampling is not available in this build");
-    return MAXWELL_ERR_UNSUPPORTED;
-  }
 
   auto hip_err = [&](hipError_t e) {
     set_last_error(std::string("HIP error during plan creation: ") + hipGetErrorString(e));
@@ -318,8 +444,12 @@ maxwell_status plan_build(Plan& p, const maxwell_plan_desc& d, const maxwell_bas
       if ((e = hipStreamSynchronize(0)) != hipSuccess) return hip_err(e);
     }
   }
-  // mask tables (general path)
-  if (!p.fused) {
+  if (p.sampling == MAXWELL_NONCARTESIAN) {
+    maxwell_status ns = nufft_build(p, d);
+    if (ns != MAXWELL_OK) return ns;
+  }
+  // mask tables (general Cartesian path)
+  if (!p.fused && p.sampling == MAXWELL_CARTESIAN) {
     std::vector<int32_t> idx(p.M), inv(p.N, -1);
     for (int64_t m = 0; m < p.M; ++m) {
       idx[m] = (int32_t)d.mask_idx[m];
@@ -377,6 +507,10 @@ maxwell_status plan_build(Plan& p, const maxwell_plan_desc& d, const maxwell_bas
     gemm_ws = std::max(gemm_ws, gemm_workspace_bytes(fused_T3_args(p, nullptr, nullptr)));
     gemm_ws = std::max(gemm_ws, gemm_workspace_bytes(fused_T1b_args(p, nullptr, nullptr)));
   }
+  if (p.sampling == MAXWELL_NONCARTESIAN) {
+    p.off_G = off;
+    off += al((size_t)p.J * p.g[0] * p.g[1] * 8);
+  }
   p.off_E = off; off += al(JM);
   p.off_gemm = off; off += al(gemm_ws);
   p.part_blocks = residual_blocks((int64_t)p.J * p.M);
@@ -387,6 +521,20 @@ maxwell_status plan_build(Plan& p, const maxwell_plan_desc& d, const maxwell_bas
 }
 
 void plan_release(Plan& p) {
+  for (int ax = 0; ax < 2; ++ax) {
+    if (p.d_twg[ax]) (void)hipFree(p.d_twg[ax]);
+    p.d_twg[ax] = nullptr;
+  }
+  if (p.d_iphi) (void)hipFree(p.d_iphi);
+  if (p.d_base) (void)hipFree(p.d_base);
+  if (p.d_wts) (void)hipFree(p.d_wts);
+  if (p.d_tptr) (void)hipFree(p.d_tptr);
+  if (p.d_tidx) (void)hipFree(p.d_tidx);
+  p.d_iphi = nullptr;
+  p.d_base = nullptr;
+  p.d_wts = nullptr;
+  p.d_tptr = nullptr;
+  p.d_tidx = nullptr;
   for (auto e : p.timing.ev_start) (void)hipEventDestroy(e);
   for (auto e : p.timing.ev_stop) (void)hipEventDestroy(e);
   p.timing = Timing();
@@ -513,6 +661,13 @@ hipError_t run_encode(const Plan& p, const float2* x, const float2* c, float2* y
   float2* Kb = wsp<float2>(ws, p.off_K);
   hipError_t e = run_basis_apply(p, c, S, ws, st);
   if (e != hipSuccess) return e;
+  if (p.sampling == MAXWELL_NONCARTESIAN) {
+    const NufftArgs na = nufft_args(p);
+    float2* G = wsp<float2>(ws, p.off_G);
+    if ((e = TIMED("nufft_pad", pad_deapod_launch(na, S, x, G, st))) != hipSuccess) return e;
+    if ((e = fft_grid(p, G, -1, st)) != hipSuccess) return e;
+    return TIMED("nufft_degrid", degrid_launch(na, G, y, st));
+  }
   if ((e = fft_image(p, S, Kb, -1, x, st)) != hipSuccess) return e;
   return TIMED("gather", gather_launch(Kb, p.N, p.d_mask, p.M, p.J, y, st));
 }
@@ -543,8 +698,18 @@ hipError_t run_adjoint(const Plan& p, const float2* x, const float2* c, const fl
   if (gx && !maps_ready) {
     if ((e = run_basis_apply(p, c, S, ws, st)) != hipSuccess) return e;
   }
-  if ((e = TIMED("scatter", scatter_launch(y, p.M, p.d_inv, p.N, p.J, Kb, st))) != hipSuccess) return e;
-  if ((e = fft_image(p, Kb, Kb, +1, nullptr, st)) != hipSuccess) return e;
+  if (p.sampling == MAXWELL_NONCARTESIAN) {
+    const NufftArgs na = nufft_args(p);
+    float2* G = wsp<float2>(ws, p.off_G);
+    if ((e = TIMED("nufft_spread", spread_launch(na, y, alpha, scale_dev, G, st))) != hipSuccess) return e;
+    if ((e = fft_grid(p, G, +1, st)) != hipSuccess) return e;
+    if ((e = TIMED("nufft_crop", crop_deapod_launch(na, G, Kb, st))) != hipSuccess) return e;
+    alpha = 1.0f;  // the scale was applied by the spread
+    scale_dev = nullptr;
+  } else {
+    if ((e = TIMED("scatter", scatter_launch(y, p.M, p.d_inv, p.N, p.J, Kb, st))) != hipSuccess) return e;
+    if ((e = fft_image(p, Kb, Kb, +1, nullptr, st)) != hipSuccess) return e;
+  }
   e = TIMED("adjoint_combine", adjoint_combine_launch(S, Kb, x, p.N, p.J, alpha, scale_dev, gx, gc ? 1 : 0, st));
   if (e != hipSuccess) return e;
   if (gc) return run_basis_adjoint(p, Kb, gc, 1.0f, nullptr, ws, st);

@@ -58,9 +58,9 @@ constexpr int FFT_CHUNK = PMAX * PMAX / 2;       // elements per register chunk 
 constexpr int W_OFF = 0;                         // W  [r0p][r1p]  (<= 64 x 64)
 constexpr int V_OFF = 64 * 64;                   // V  [r0p][n1]   (<= 64 x 128)
 
-__device__ inline f32x4 z4() { return f32x4{0.f, 0.f, 0.f, 0.f}; }
+__device__ __forceinline__ f32x4 z4() { return f32x4{0.f, 0.f, 0.f, 0.f}; }
 
-__device__ inline void cmfma(f32x4& cr, f32x4& ci, float2 a, float2 b) {
+__device__ __forceinline__ void cmfma(f32x4& cr, f32x4& ci, float2 a, float2 b) {
   cr = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, cr, 0, 0, 0);
   cr = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.y, b.y, cr, 0, 0, 0);
   ci = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.y, ci, 0, 0, 0);
@@ -68,14 +68,14 @@ __device__ inline void cmfma(f32x4& cr, f32x4& ci, float2 a, float2 b) {
 }
 
 // ---------------------------------------------------------------- BF16 split helpers
-__device__ inline unsigned short bf16_rne(float f) {
+__device__ __forceinline__ unsigned short bf16_rne(float f) {
   unsigned u = __float_as_uint(f);
   u += 0x7fffu + ((u >> 16) & 1u);
   return (unsigned short)(u >> 16);
 }
-__device__ inline float bf16_f32(unsigned short h) { return __uint_as_float(((unsigned)h) << 16); }
+__device__ __forceinline__ float bf16_f32(unsigned short h) { return __uint_as_float(((unsigned)h) << 16); }
 
-__device__ inline void split8(const float (&v)[8], u16x8& hi, u16x8& lo) {
+__device__ __forceinline__ void split8(const float (&v)[8], u16x8& hi, u16x8& lo) {
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
     const unsigned short h = bf16_rne(v[e]);
@@ -84,10 +84,10 @@ __device__ inline void split8(const float (&v)[8], u16x8& hi, u16x8& lo) {
   }
 }
 
-__device__ inline bf16x8 asbf(u16x8 v) { return __builtin_bit_cast(bf16x8, v); }
+__device__ __forceinline__ bf16x8 asbf(u16x8 v) { return __builtin_bit_cast(bf16x8, v); }
 
 // c += a * b over one 32-wide k' step for both real-block halves (6 MFMAs).
-__device__ inline void mfma6(f32x4& cr, f32x4& ci, u16x8 ah, u16x8 al, u16x8 brh, u16x8 brl, u16x8 bih,
+__device__ __forceinline__ void mfma6(f32x4& cr, f32x4& ci, u16x8 ah, u16x8 al, u16x8 brh, u16x8 brl, u16x8 bih,
                              u16x8 bil) {
   cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(asbf(ah), asbf(brh), cr, 0, 0, 0);
   cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(asbf(ah), asbf(brl), cr, 0, 0, 0);
@@ -97,13 +97,13 @@ __device__ inline void mfma6(f32x4& cr, f32x4& ci, u16x8 ah, u16x8 al, u16x8 brh
   ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(asbf(al), asbf(bih), ci, 0, 0, 0);
 }
 
-__device__ inline u16x8 ld8(const unsigned short* p) { return *reinterpret_cast<const u16x8*>(p); }
-__device__ inline void st8(unsigned short* p, u16x8 v) { *reinterpret_cast<u16x8*>(p) = v; }
+__device__ __forceinline__ u16x8 ld8(const unsigned short* p) { return *reinterpret_cast<const u16x8*>(p); }
+__device__ __forceinline__ void st8(unsigned short* p, u16x8 v) { *reinterpret_cast<u16x8*>(p) = v; }
 
 // Store one accumulator block as a B operand [n][k'] (k' = 2 * row + {0, 1}) in the
 // real-block form: br = (Re, -Im), bi = (Im, Re), each split hi / lo.  The lane's four
 // rows are consecutive, so its eight k' values are one 16-byte store per array.
-__device__ inline void store_bop(unsigned short* brh, unsigned short* brl, unsigned short* bih,
+__device__ __forceinline__ void store_bop(unsigned short* brh, unsigned short* brl, unsigned short* bih,
                                  unsigned short* bil, int ld, int n, int kp0, const f32x4& cr,
                                  const f32x4& ci) {
   float vr[8], vi[8];
@@ -140,7 +140,7 @@ struct Geo {
 };
 
 template <int N0, int N1>
-__device__ inline void load_twiddles(const PlaneArgs& a, const Geo<N0, N1>& g, float2* lds) {
+__device__ __forceinline__ void load_twiddles(const PlaneArgs& a, const Geo<N0, N1>& g, float2* lds) {
   float2* tw0 = lds + PLANE_ELEMS;
   float2* tw1 = tw0 + PMAX;
   for (int e = threadIdx.x; e < g.n0; e += PT) tw0[e] = a.tw0[e];
@@ -149,7 +149,7 @@ __device__ inline void load_twiddles(const PlaneArgs& a, const Geo<N0, N1>& g, f
 
 // 2D centred DFT of the plane (chessboard signs applied by the caller).
 template <int N0, int N1>
-__device__ inline void plane_fft(const PlaneArgs& a, const Geo<N0, N1>& g, float2* lds, int dir) {
+__device__ __forceinline__ void plane_fft(const PlaneArgs& a, const Geo<N0, N1>& g, float2* lds, int dir) {
   const float2* tw0 = lds + PLANE_ELEMS;
   const float2* tw1 = tw0 + PMAX;
   auto rows = [&]() {
@@ -174,7 +174,7 @@ __device__ inline void plane_fft(const PlaneArgs& a, const Geo<N0, N1>& g, float
 // ---------------------------------------------------------------- FP32 contractions
 // V = W U1^T ([r0p][n1] in LDS) from W = T3[j][i2] (zero-padded r0p x r1p in LDS).
 template <int N0, int N1>
-__device__ inline void coilmap_V_f32(const PlaneArgs& a, const Geo<N0, N1>& g, int j, int i2, float2* lds) {
+__device__ __forceinline__ void coilmap_V_f32(const PlaneArgs& a, const Geo<N0, N1>& g, int j, int i2, float2* lds) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const float2* src = a.T3 + ((size_t)j * g.n2 + i2) * g.r0 * g.r1;
   for (int e = threadIdx.x; e < g.r0p * g.r1p; e += PT) {
@@ -204,7 +204,7 @@ __device__ inline void coilmap_V_f32(const PlaneArgs& a, const Geo<N0, N1>& g, i
 
 // P = U0 V, this wave's 16 rows, all n1 columns, into registers.
 template <int N0, int N1>
-__device__ inline void coilmap_P_f32(const PlaneArgs& a, const Geo<N0, N1>& g, const float2* lds, f32x4 (&pr)[8],
+__device__ __forceinline__ void coilmap_P_f32(const PlaneArgs& a, const Geo<N0, N1>& g, const float2* lds, f32x4 (&pr)[8],
                                      f32x4 (&pi)[8]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nbl = g.n1 / 16;
@@ -231,7 +231,7 @@ __device__ inline void coilmap_P_f32(const PlaneArgs& a, const Geo<N0, N1>& g, c
 
 // Y = h conj(U1) (h in the plane) for this wave's rows; Wb = U0^H Y -> T3b.
 template <int N0, int N1>
-__device__ inline void adjoint_W_f32(const PlaneArgs& a, const Geo<N0, N1>& g, int j, int i2, float2* lds) {
+__device__ __forceinline__ void adjoint_W_f32(const PlaneArgs& a, const Geo<N0, N1>& g, int j, int i2, float2* lds) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   f32x4 yr[4], yi[4];
 #pragma unroll
@@ -296,10 +296,10 @@ __device__ inline void adjoint_W_f32(const PlaneArgs& a, const Geo<N0, N1>& g, i
 // LDS (unsigned short view of the plane region) during the coil-map phase:
 //   WA hi/lo     [r0p][KS1]  A operand of V = W U1^T   (KS1 = KP1 + 8, padded row)
 //   VB r/i hi/lo [n1][KS0]   B operand of P = U0 V     (KS0 = KP0 + 8)
-__device__ inline int kpad(int r) { return (2 * r + 31) / 32 * 32; }
+__device__ __forceinline__ int kpad(int r) { return (2 * r + 31) / 32 * 32; }
 
 template <int N0, int N1>
-__device__ inline void coilmap_V_bf(const PlaneArgs& a, const Geo<N0, N1>& g, int j, int i2, float2* lds) {
+__device__ __forceinline__ void coilmap_V_bf(const PlaneArgs& a, const Geo<N0, N1>& g, int j, int i2, float2* lds) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int KP1 = kpad(g.r1), KS1 = KP1 + 8, KP0 = kpad(g.r0), KS0 = KP0 + 8;
   unsigned short* u = reinterpret_cast<unsigned short*>(lds);
@@ -363,7 +363,7 @@ __device__ inline void coilmap_V_bf(const PlaneArgs& a, const Geo<N0, N1>& g, in
 }
 
 template <int N0, int N1>
-__device__ inline void coilmap_P_bf(const PlaneArgs& a, const Geo<N0, N1>& g, const float2* lds, f32x4 (&pr)[8],
+__device__ __forceinline__ void coilmap_P_bf(const PlaneArgs& a, const Geo<N0, N1>& g, const float2* lds, f32x4 (&pr)[8],
                                     f32x4 (&pi)[8]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int KP1 = kpad(g.r1), KS1 = KP1 + 8, KP0 = kpad(g.r0), KS0 = KP0 + 8;
@@ -401,7 +401,7 @@ __device__ inline void coilmap_P_bf(const PlaneArgs& a, const Geo<N0, N1>& g, co
 // Y = h conj(U1) with h (FP32 plane) split on the fly and U1's split copy staged through
 // LDS one 32-wide k' chunk at a time; then Wb = U0^H Y -> T3b.
 template <int N0, int N1>
-__device__ inline void adjoint_W_bf(const PlaneArgs& a, const Geo<N0, N1>& g, int j, int i2, float2* lds) {
+__device__ __forceinline__ void adjoint_W_bf(const PlaneArgs& a, const Geo<N0, N1>& g, int j, int i2, float2* lds) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nbr = g.r1p / 16, K2 = 2 * g.n1;
   unsigned short* stage = reinterpret_cast<unsigned short*>(lds + PLANE_ELEMS);
@@ -480,7 +480,7 @@ __device__ inline void adjoint_W_bf(const PlaneArgs& a, const Geo<N0, N1>& g, in
 
 // ---------------------------------------------------------------- plane kernels
 template <int PREC, int N0, int N1>
-__device__ inline void coil_map(const PlaneArgs& a, const Geo<N0, N1>& g, int j, int i2, float2* lds,
+__device__ __forceinline__ void coil_map(const PlaneArgs& a, const Geo<N0, N1>& g, int j, int i2, float2* lds,
                                 f32x4 (&pr)[8], f32x4 (&pi)[8]) {
   if constexpr (PREC == 1) {
     coilmap_V_bf(a, g, j, i2, lds);
@@ -610,7 +610,7 @@ constexpr int LNT = 256;   // threads
 constexpr int LMAXN = 256; // max n2 on this path
 
 template <int N2>
-__device__ inline void line_fft(const LineArgs& a, float2* tile, const float2* tw, int n, int dir) {
+__device__ __forceinline__ void line_fft(const LineArgs& a, float2* tile, const float2* tw, int n, int dir) {
   if constexpr (N2 != 0) {
     lds_fft_ct<N2, LNT, LMAXN * LT / 2>(tile, LT, 1, LT + 1, tw, dir);
   } else {

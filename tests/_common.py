@@ -4,8 +4,8 @@ import math
 import numpy as np
 
 from oracle import Oracle
-from synth import (coefficients, complex_normal, phantom, rng_for, smooth_dense_basis, tucker_basis,
-                   plane_mask_to_lines)
+from synth import (coefficients, complex_normal, golden_angle_radial, phantom, ramp_dcf, rng_for,
+                   smooth_dense_basis, tucker_basis, plane_mask_to_lines)
 
 TOL = {"fp32": 1e-5, "bf16_split": 1e-4}
 
@@ -26,7 +26,7 @@ class Case:
     """A seeded problem with complex64-rounded inputs and its FP64 oracle."""
 
     def __init__(self, seed, dims, J, K, basis="dense", ranks=None, mask="random", frac=0.35,
-                 weights=False, degree=4, kmax=2.0):
+                 weights=False, degree=4, kmax=2.0, spokes=None, n_read=None):
         self.dims = tuple(dims)
         self.N = int(np.prod(dims))
         self.J, self.K = J, K
@@ -40,7 +40,15 @@ class Case:
             self.core = c64(core)
             self.B = None
         rs = rng_for(seed, 4)
-        if mask == "random":
+        self.traj = None
+        if mask == "radial":
+            nr = n_read if n_read is not None else 2 * max(dims)
+            # both sides see the float32-rounded trajectory
+            self.traj = golden_angle_radial(dims, spokes, nr).astype(np.float32).astype(np.float64)
+            self.mask = None
+            self.M = self.traj.shape[0]
+            self.w = ramp_dcf(self.traj, dims, nr).astype(np.float32).astype(np.float64) if weights else None
+        elif mask == "random":
             M = int(round(frac * self.N))
             self.mask = np.sort(rs.choice(self.N, size=M, replace=False)).astype(np.int64)
         elif mask == "lines3d":
@@ -52,14 +60,15 @@ class Case:
             self.mask = np.zeros(0, dtype=np.int64)
         else:
             self.mask = np.asarray(mask, dtype=np.int64)
-        self.M = int(self.mask.size)
-        self.w = rs.uniform(0.2, 1.0, size=self.M).astype(np.float32).astype(np.float64) if weights else None
+        if self.traj is None:
+            self.M = int(self.mask.size)
+            self.w = rs.uniform(0.2, 1.0, size=self.M).astype(np.float32).astype(np.float64) if weights else None
         self.x_true = c64(phantom(rng_for(seed, 1), dims))
         self.c_true = c64(coefficients(rng_for(seed, 3), J, K))
         re = rng_for(seed, 6)
         self.x0 = c64(phantom(re, dims) + 0.1 * complex_normal(re, dims))
         self.c0 = c64(coefficients(re, J, K))
-        self.op = Oracle(dims, B=self.B, U=self.U, core=self.core, mask_idx=self.mask)
+        self.op = Oracle(dims, B=self.B, U=self.U, core=self.core, mask_idx=self.mask, traj=self.traj)
         y_clean = self.op.encode(self.x_true, self.c_true)
         noise = complex_normal(rng_for(seed, 5), (J, self.M))
         scale = 0.01 * np.linalg.norm(y_clean) / max(np.linalg.norm(noise), 1e-300)
@@ -67,7 +76,7 @@ class Case:
 
     def plan(self, precision="fp32"):
         from paper_2008_09042_amd.encoding import MaxwellPlan
-        kw = dict(mask_idx=self.mask, weights=self.w, precision=precision)
+        kw = dict(mask_idx=self.mask, traj=self.traj, weights=self.w, precision=precision)
         if self.B is not None:
             return MaxwellPlan(self.dims, self.J, B=self.B, **kw)
         return MaxwellPlan(self.dims, self.J, U=self.U, core=self.core, **kw)

@@ -35,6 +35,11 @@ CASES = {
                                         basis="tucker", mask="lines3d", frac=0.125),
     "fused_64x64x32_r20_K30_J3": dict(seed=112, dims=(64, 64, 32), ranks=(20, 20, 7), J=3, K=30,
                                       basis="tucker", mask="lines3d", frac=0.2, weights=True),
+    # radial sampling (KB NUFFT, W = 6, sigma = 2, ramp density compensation in the loss)
+    "radial_32x24_J3_K9_7spokes": dict(seed=113, dims=(32, 24), J=3, K=9, mask="radial", spokes=7, weights=True),
+    "radial_40x30_J2_K6_5spokes": dict(seed=114, dims=(40, 30), J=2, K=6, mask="radial", spokes=5, n_read=48),
+    "radial_256_J2_K20_64spokes": dict(seed=115, dims=(256, 256), J=2, K=20, mask="radial", spokes=64,
+                                       n_read=512, weights=True),
 }
 FUSED = {"tucker3d_32x32x32_r12_K70_J4", "fused_48x32x20_r9x13x5_K23_J5", "fused_16x80x12_r3x17x4_K11_J3",
          "fused_128x128x64_r40_K60_J5", "fused_64x64x32_r20_K30_J3"}
@@ -170,3 +175,33 @@ def test_repeatable_bitwise(name):
     b = plan.grad(x, c, y)
     for u, v in zip(a, b):
         assert torch.equal(u, v)
+
+
+def test_radial_encode_close_to_exact_ndft():
+    """With J = 1, K = 1 and B = 1/sqrt(N), c = sqrt(N), E is the KB NUFFT of x; it must
+    match the plain non-uniform DFT within the NUFFT's approximation error (W = 6, sigma = 2)."""
+    from paper_2008_09042_amd.encoding import MaxwellPlan
+    from oracle import ndft
+    from synth import golden_angle_radial
+    dims = (48, 40)
+    N = 48 * 40
+    traj = golden_angle_radial(dims, 9, 96).astype(np.float32).astype(np.float64)
+    B = np.full((N, 1), 1 / math.sqrt(N), dtype=complex)
+    plan = MaxwellPlan(dims, 1, B=B, traj=traj)
+    x = c64(np.random.default_rng(5).normal(size=dims) + 1j * np.random.default_rng(6).normal(size=dims))
+    y = H(plan.encode(T(x), T(np.array([[math.sqrt(N)]]))))[0]
+    assert rel(y, ndft(x, traj)) <= 1e-4
+
+
+def test_radial_adjoint_identity_on_gpu():
+    """<E_c z, y> = <z, E_c^H y> for the GPU operator itself (FP32 consistency)."""
+    cs = get_case("radial_32x24_J3_K9_7spokes")
+    plan = cs.plan()
+    rng = np.random.default_rng(9)
+    z = c64(rng.normal(size=cs.dims) + 1j * rng.normal(size=cs.dims))
+    y = c64(rng.normal(size=(cs.J, cs.M)) + 1j * rng.normal(size=(cs.J, cs.M)))
+    Ez = H(plan.encode(T(z), T(cs.c0)))
+    gx, _ = plan.adjoint(T(cs.x0), T(cs.c0), T(y), want_gc=False)
+    lhs = np.vdot(Ez.reshape(-1), y.reshape(-1))
+    rhs = np.vdot(z.reshape(-1), H(gx).reshape(-1))
+    assert abs(lhs - rhs) / abs(lhs) < 1e-5
