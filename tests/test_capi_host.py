@@ -1,0 +1,209 @@
+"""Host-side tests of the C ABI (no GPU needed).
+
+The library must load on a GPU-less host, export every entry point the public
+header declares, and reject invalid requests with a status and a message
+before touching the HIP runtime.  Only invalid descriptors are passed here, so
+no device memory is ever touched.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2008_09042_amd._lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "maxwell.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(L.LIB_PATH):
+        from paper_2008_09042_amd.build import build
+        build()
+    return L.load()
+
+
+def header_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(maxwell_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_function(lib):
+    declared = header_functions()
+    assert len(declared) >= 12
+    missing = [f for f in declared if not hasattr(lib, f)]
+    assert not missing, missing
+    assert sorted(L.EXPORTS) == declared
+
+
+def test_version_string(lib):
+    assert lib.maxwell_version().decode().startswith("maxwell-gfx950")
+
+
+FAKE = 0x10000  # aligned, never dereferenced: every descriptor below fails validation first
+
+
+def dense_basis(K=4):
+    b = L.BasisDesc()
+    b.kind = L.MAXWELL_BASIS_DENSE
+    b.K = K
+    b.dense = FAKE
+    return b
+
+
+def tucker_basis(r=(2, 2, 2), K=3):
+    b = L.BasisDesc()
+    b.kind = L.MAXWELL_BASIS_TUCKER
+    b.K = K
+    for m in range(3):
+        b.r[m] = r[m]
+        b.U[m] = FAKE
+    b.core = FAKE
+    return b
+
+
+def cart_desc(dims=(8, 6), J=2, mask=None, weights=None):
+    d = L.PlanDesc()
+    d.ndim = len(dims)
+    for i, n in enumerate(dims):
+        d.n[i] = n
+    d.J = J
+    d.precision = L.MAXWELL_FP32
+    d.sampling = L.MAXWELL_CARTESIAN
+    m = np.arange(5, dtype=np.int64) if mask is None else np.asarray(mask, dtype=np.int64)
+    d._keep = [m]
+    d.M = m.size
+    d.mask_idx = m.ctypes.data if m.size else None
+    if weights is not None:
+        w = np.asarray(weights, dtype=np.float32)
+        d._keep.append(w)
+        d.weights = w.ctypes.data
+    return d
+
+
+def radial_desc(dims=(8, 8), traj=None, width=6, oversamp=2.0):
+    d = L.PlanDesc()
+    d.ndim = len(dims)
+    for i, n in enumerate(dims):
+        d.n[i] = n
+    d.J = 1
+    d.sampling = L.MAXWELL_NONCARTESIAN
+    t = np.zeros((3, len(dims)), dtype=np.float32) if traj is None else np.asarray(traj, dtype=np.float32)
+    d._keep = [t]
+    d.M = t.shape[0]
+    d.traj = t.ctypes.data
+    d.kb_width = width
+    d.oversamp = oversamp
+    d.kb_beta = 0.0
+    return d
+
+
+def create(lib, desc, basis):
+    h = ctypes.c_void_p()
+    st = lib.maxwell_plan_create(ctypes.byref(desc) if desc is not None else None,
+                                 ctypes.byref(basis) if basis is not None else None, ctypes.byref(h))
+    return st, h, lib.maxwell_last_error().decode()
+
+
+@pytest.mark.parametrize("mutate,status,needle", [
+    (lambda d, b: setattr(d, "ndim", 4), L.MAXWELL_ERR_INVALID_ARGUMENT, "ndim"),
+    (lambda d, b: d.n.__setitem__(0, 7), L.MAXWELL_ERR_UNSUPPORTED, "odd"),
+    (lambda d, b: d.n.__setitem__(0, 14), L.MAXWELL_ERR_UNSUPPORTED, "factor"),
+    (lambda d, b: d.n.__setitem__(1, 8192), L.MAXWELL_ERR_INVALID_ARGUMENT, "4096"),
+    (lambda d, b: setattr(d, "J", 0), L.MAXWELL_ERR_INVALID_ARGUMENT, "J must"),
+    (lambda d, b: setattr(b, "K", 0), L.MAXWELL_ERR_INVALID_ARGUMENT, "K must"),
+    (lambda d, b: setattr(b, "dense", None), L.MAXWELL_ERR_INVALID_ARGUMENT, "dense basis"),
+    (lambda d, b: setattr(b, "dense", FAKE + 4), L.MAXWELL_ERR_INVALID_ARGUMENT, "misaligned"),
+    (lambda d, b: setattr(d, "precision", 7), L.MAXWELL_ERR_INVALID_ARGUMENT, "precision"),
+    (lambda d, b: setattr(b, "kind", 5), L.MAXWELL_ERR_INVALID_ARGUMENT, "basis kind"),
+    (lambda d, b: setattr(d, "sampling", 9), L.MAXWELL_ERR_INVALID_ARGUMENT, "sampling"),
+])
+def test_plan_create_rejects(lib, mutate, status, needle):
+    d, b = cart_desc(), dense_basis()
+    mutate(d, b)
+    st, h, msg = create(lib, d, b)
+    assert st == status and not h.value
+    assert needle in msg
+
+
+@pytest.mark.parametrize("mask,needle", [
+    ([3, 1, 2], "ascending"),
+    ([1, 1, 2], "ascending"),
+    ([0, 5, 48], "out of range"),
+    ([-1, 2], "out of range"),
+    (list(range(49)), "more mask samples"),
+])
+def test_bad_masks(lib, mask, needle):
+    st, h, msg = create(lib, cart_desc(mask=mask), dense_basis())
+    assert st == L.MAXWELL_ERR_INVALID_ARGUMENT and needle in msg
+
+
+def test_bad_weights(lib):
+    for w in ([1, -1, 0, 0, 0], [1, float("nan"), 0, 0, 0]):
+        st, h, msg = create(lib, cart_desc(weights=w), dense_basis())
+        assert st == L.MAXWELL_ERR_INVALID_ARGUMENT and "weights" in msg
+
+
+def test_tucker_validation(lib):
+    st, _, msg = create(lib, cart_desc(dims=(8, 6)), tucker_basis())
+    assert st == L.MAXWELL_ERR_UNSUPPORTED and "3D" in msg
+    st, _, msg = create(lib, cart_desc(dims=(8, 6, 4)), tucker_basis(r=(2, 9, 2)))
+    assert st == L.MAXWELL_ERR_INVALID_ARGUMENT and "rank" in msg
+    b = tucker_basis()
+    b.core = None
+    st, _, msg = create(lib, cart_desc(dims=(8, 6, 4)), b)
+    assert st == L.MAXWELL_ERR_INVALID_ARGUMENT and "core" in msg
+
+
+def test_radial_validation(lib):
+    st, _, msg = create(lib, radial_desc(dims=(8, 8, 8)), dense_basis())
+    assert st == L.MAXWELL_ERR_UNSUPPORTED and "2D" in msg
+    st, _, msg = create(lib, radial_desc(traj=[[0.0, 4.0]]), dense_basis())  # k = n/2 is outside [-n/2, n/2)
+    assert st == L.MAXWELL_ERR_INVALID_ARGUMENT and "trajectory" in msg
+    st, _, msg = create(lib, radial_desc(traj=[[0.0, float("nan")]]), dense_basis())
+    assert st == L.MAXWELL_ERR_INVALID_ARGUMENT and "trajectory" in msg
+    st, _, msg = create(lib, radial_desc(width=9), dense_basis())
+    assert st == L.MAXWELL_ERR_INVALID_ARGUMENT and "kb_width" in msg
+    st, _, msg = create(lib, radial_desc(oversamp=1.3), dense_basis())  # 1.3 * 8 is not an even integer
+    assert st == L.MAXWELL_ERR_INVALID_ARGUMENT and "oversamp" in msg
+
+
+def test_null_arguments(lib):
+    st, _, _ = create(lib, None, dense_basis())
+    assert st == L.MAXWELL_ERR_INVALID_ARGUMENT
+    assert lib.maxwell_plan_create(None, None, None) == L.MAXWELL_ERR_INVALID_ARGUMENT
+    sz = ctypes.c_size_t()
+    assert lib.maxwell_plan_workspace_size(None, ctypes.byref(sz)) == L.MAXWELL_ERR_INVALID_ARGUMENT
+    assert lib.maxwell_plan_path(None) is None
+    lib.maxwell_plan_destroy(None)  # no-op
+    z = ctypes.c_void_p(FAKE)
+    assert lib.maxwell_encode(None, z, z, z, None, 0, None) == L.MAXWELL_ERR_INVALID_ARGUMENT
+    assert lib.maxwell_grad(None, z, z, z, z, z, None, None, 0, None) == L.MAXWELL_ERR_INVALID_ARGUMENT
+    assert lib.maxwell_adjoint(None, z, z, z, 1.0, None, z, z, None, 0, None) == L.MAXWELL_ERR_INVALID_ARGUMENT
+    assert lib.maxwell_forward_loss(None, z, z, z, z, None, None, 0, None) == L.MAXWELL_ERR_INVALID_ARGUMENT
+    assert lib.maxwell_basis_apply(None, z, z, None, 0, None) == L.MAXWELL_ERR_INVALID_ARGUMENT
+    assert lib.maxwell_basis_apply_adjoint(None, z, z, None, 0, None) == L.MAXWELL_ERR_INVALID_ARGUMENT
+    assert lib.maxwell_plan_set_timing(None, 1) == L.MAXWELL_ERR_INVALID_ARGUMENT
+    assert "plan is null" in lib.maxwell_last_error().decode()
+
+
+def test_missing_library_fails_loudly():
+    saved = L._lib
+    try:
+        L._lib = None
+        with pytest.raises(RuntimeError, match="missing"):
+            L.load("/nonexistent/libmaxwell.so")
+    finally:
+        L._lib = saved
+
+
+def test_plan_needs_a_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    from paper_2008_09042_amd.encoding import MaxwellPlan
+    with pytest.raises(RuntimeError, match="GPU"):
+        MaxwellPlan((8, 8), 1, B=np.ones((64, 1)), mask_idx=np.arange(4))
