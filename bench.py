@@ -80,9 +80,12 @@ def kernel_work(name, p, prec):
     r0, r1, r2 = (u.shape[1] for u in p.U)
     J, K, M = p.J, p.K, p.M
     planes = J * n2
-    # the plane kernels issue FP32 MFMAs (16x16x4) in both precisions; the BF16-split
-    # plan changes only the GEMM kernel around them
-    mfma_peak = PEAKS_TFLOPS["fp32"]
+    # FP32 plans issue 16x16x4 FP32 MFMAs; BF16-split plans issue 16x16x32 BF16 MFMAs,
+    # three per algorithmic product (hi*hi + hi*lo + lo*hi), so their fraction of the
+    # published BF16 peak is at most 1/3 when counted in algorithmic flops as here.
+    mfma_peak = PEAKS_TFLOPS["bf16" if prec == "bf16_split" else "fp32"]
+    R = r0 * r1 * r2
+    core_bytes = 8.0 * (R * K + J * K + J * R)
     v_p = r0 * r1 * n1 + n0 * r0 * n1          # V = W U1^T, P = U0 V  per coil-plane
     y_w = n0 * n1 * r1 + r0 * n0 * r1          # Y = h conj(U1), Wb = U0^H Y
     table = {
@@ -90,8 +93,12 @@ def kernel_work(name, p, prec):
         "plane_adj": ("mfma", "TFLOP/s", 8.0 * planes * (v_p + y_w), mfma_peak),
         "line_fwd": ("hbm", "GB/s", 8.0 * J * M * 3 + 4.0 * M, HBM_PEAK_GBS),
         "line_adj": ("hbm", "GB/s", 8.0 * J * M * 2, HBM_PEAK_GBS),
-        "gemm_core_coef": ("hbm", "GB/s", 8.0 * (r0 * r1 * r2 * K + J * K + J * r0 * r1 * r2), HBM_PEAK_GBS),
-        "gemm_core_adjoint": ("hbm", "GB/s", 8.0 * (r0 * r1 * r2 * K + J * K + J * r0 * r1 * r2), HBM_PEAK_GBS),
+        "core_fwd": ("hbm", "GB/s", core_bytes, HBM_PEAK_GBS),
+        "core_adj": ("hbm", "GB/s", core_bytes, HBM_PEAK_GBS),
+        "gemm_core_coef": ("hbm", "GB/s", core_bytes, HBM_PEAK_GBS),
+        "gemm_core_adjoint": ("hbm", "GB/s", core_bytes, HBM_PEAK_GBS),
+        "gemm_mode3": ("hbm", "GB/s", 8.0 * (J * R + J * n2 * r0 * r1 + n2 * r2), HBM_PEAK_GBS),
+        "gemm_mode3_adjoint": ("hbm", "GB/s", 8.0 * (J * R + J * n2 * r0 * r1 + n2 * r2), HBM_PEAK_GBS),
     }
     return table.get(name)
 

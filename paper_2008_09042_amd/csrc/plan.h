@@ -6,6 +6,7 @@
 
 #include "../../include/maxwell.h"
 #include "common.h"
+#include "core.h"
 
 namespace mx {
 
@@ -46,6 +47,10 @@ struct Plan {
   int32_t* d_pos = nullptr;    // [L] plane index k0 * n1 + k1 of each line
   uint16_t* d_split = nullptr; // BF16-split factor operands (one allocation)
   const uint16_t *U0A = nullptr, *U1B = nullptr, *U1C = nullptr, *U0H = nullptr;
+  // dedicated core contraction kernels (Tucker basis, J <= 64)
+  bool core_direct = false;
+  CoreGeom cg{};
+  uint16_t* d_core_split = nullptr;  // BF16-split core planes (BF16_SPLIT plans only)
   int G_fwd = 2, G_adj = 4;    // coils per plane workgroup
   float gscale = 1.0f;         // prod_d (-1)^(n_d/2) / sqrt(N)
   // non-Cartesian sampling (Kaiser-Bessel NUFFT, 2D)
@@ -63,7 +68,7 @@ struct Plan {
   // workspace layout (byte offsets into the caller's workspace)
   size_t ws_bytes = 0;
   size_t off_S = 0, off_K = 0, off_tA = 0, off_tB = 0, off_E = 0, off_gemm = 0, off_part = 0;
-  size_t off_T1 = 0, off_T3 = 0, off_xt = 0, off_Z = 0, off_gxp = 0, off_T3b = 0, off_T1b = 0, off_G = 0;
+  size_t off_T1 = 0, off_T3 = 0, off_xt = 0, off_Z = 0, off_gxp = 0, off_T3b = 0, off_T1b = 0, off_G = 0, off_cpart = 0;
   int part_blocks = 0;
 
   size_t bytes_x() const { return (size_t)N * 8; }

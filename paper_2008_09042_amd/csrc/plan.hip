@@ -444,6 +444,15 @@ maxwell_status plan_build(Plan& p, const maxwell_plan_desc& d, const maxwell_bas
       if ((e = hipStreamSynchronize(0)) != hipSuccess) return hip_err(e);
     }
   }
+  if (p.basis_kind == MAXWELL_BASIS_TUCKER && core_supported(p.J)) {
+    p.core_direct = true;
+    p.cg = core_geom(p.r[0] * p.r[1] * p.r[2], (int)p.K);
+    if (p.precision == MAXWELL_BF16_SPLIT) {
+      if ((e = hipMalloc(&p.d_core_split, p.cg.total_elems() * sizeof(uint16_t))) != hipSuccess) return hip_err(e);
+      if ((e = core_split_launch(p.core, p.cg, p.d_core_split, 0)) != hipSuccess) return hip_err(e);
+      if ((e = hipStreamSynchronize(0)) != hipSuccess) return hip_err(e);
+    }
+  }
   if (p.sampling == MAXWELL_NONCARTESIAN) {
     maxwell_status ns = nufft_build(p, d);
     if (ns != MAXWELL_OK) return ns;
@@ -511,6 +520,10 @@ maxwell_status plan_build(Plan& p, const maxwell_plan_desc& d, const maxwell_bas
     p.off_G = off;
     off += al((size_t)p.J * p.g[0] * p.g[1] * 8);
   }
+  if (p.core_direct) {
+    p.off_cpart = off;
+    off += al(core_adj_part_bytes(p.cg.R, p.cg.K, p.J));
+  }
   p.off_E = off; off += al(JM);
   p.off_gemm = off; off += al(gemm_ws);
   p.part_blocks = residual_blocks((int64_t)p.J * p.M);
@@ -548,10 +561,50 @@ void plan_release(Plan& p) {
   if (p.d_pos) (void)hipFree(p.d_pos);
   if (p.d_split) (void)hipFree(p.d_split);
   p.d_split = nullptr;
+  if (p.d_core_split) (void)hipFree(p.d_core_split);
+  p.d_core_split = nullptr;
   p.d_mask = nullptr;
   p.d_inv = nullptr;
   p.d_w = nullptr;
   p.d_pos = nullptr;
+}
+
+static CoreArgs core_args(const Plan& p, const float2* in, float2* out, void* ws) {
+  CoreArgs a{};
+  a.g = p.cg;
+  a.J = p.J;
+  a.core = p.core;
+  if (p.d_core_split) {
+    const size_t nf = p.cg.fwd_elems(), na = p.cg.adj_elems();
+    a.fwd_hi = p.d_core_split;
+    a.fwd_lo = p.d_core_split + nf;
+    a.adj_hi = p.d_core_split + 2 * nf;
+    a.adj_lo = p.d_core_split + 2 * nf + na;
+  }
+  a.in = in;
+  a.out = out;
+  a.part = wsp<float2>(ws, p.off_cpart);
+  return a;
+}
+
+// T1 = core x_4 c  (first product of the Tucker chain)
+static hipError_t core_forward(const Plan& p, const float2* c, float2* T1, void* ws, hipStream_t st) {
+  if (p.core_direct) return TIMED("core_fwd", core_fwd_launch(core_args(p, c, T1, ws), p.precision, st));
+  GemmArgs g[4];
+  tucker_apply_args(p, c, T1, nullptr, nullptr, g);
+  return TIMED("gemm_core_coef", gemm_launch(g[0], p.precision, wsp<void>(ws, p.off_gemm), st));
+}
+
+// gc = alpha (*alpha_dev) core^H T1b  (last product of the adjoint chain)
+static hipError_t core_adjoint(const Plan& p, const float2* T1b, float2* gc, float alpha, const float* alpha_dev,
+                               void* ws, hipStream_t st) {
+  if (p.core_direct)
+    return TIMED("core_adj", core_adj_launch(core_args(p, T1b, gc, ws), p.precision, alpha, alpha_dev, st));
+  GemmArgs g[4];
+  tucker_adjoint_args(p, nullptr, const_cast<float2*>(T1b), nullptr, gc, g);
+  g[3].alpha = alpha;
+  g[3].alpha_dev = alpha_dev;
+  return TIMED("gemm_core_adjoint", gemm_launch(g[3], p.precision, wsp<void>(ws, p.off_gemm), st));
 }
 
 hipError_t run_basis_apply(const Plan& p, const float2* c, float2* S, void* ws, hipStream_t st) {
@@ -560,7 +613,9 @@ hipError_t run_basis_apply(const Plan& p, const float2* c, float2* S, void* ws, 
     return TIMED("gemm_dense_apply", gemm_launch(dense_apply_args(p, c, S), p.precision, gws, st));
   GemmArgs g[4];
   tucker_apply_args(p, c, wsp<float2>(ws, p.off_tA), wsp<float2>(ws, p.off_tB), S, g);
-  for (int i = 0; i < 4; ++i) {
+  hipError_t e0 = core_forward(p, c, wsp<float2>(ws, p.off_tA), ws, st);
+  if (e0 != hipSuccess) return e0;
+  for (int i = 1; i < 4; ++i) {
     hipError_t e = TIMED("gemm_tucker_chain", gemm_launch(g[i], p.precision, gws, st));
     if (e != hipSuccess) return e;
   }
@@ -578,21 +633,17 @@ hipError_t run_basis_adjoint(const Plan& p, const float2* S, float2* c, float al
   }
   GemmArgs g[4];
   tucker_adjoint_args(p, S, wsp<float2>(ws, p.off_tA), wsp<float2>(ws, p.off_tB), c, g);
-  g[3].alpha = alpha;
-  g[3].alpha_dev = alpha_dev;
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < 3; ++i) {
     hipError_t e = TIMED("gemm_tucker_adjoint_chain", gemm_launch(g[i], p.precision, gws, st));
     if (e != hipSuccess) return e;
   }
-  return hipSuccess;
+  return core_adjoint(p, wsp<float2>(ws, p.off_tA), c, alpha, alpha_dev, ws, st);
 }
 
 // ---- fused path pieces
 static hipError_t fused_prepare(const Plan& p, const float2* x, const float2* c, void* ws, hipStream_t st) {
   void* gws = wsp<void>(ws, p.off_gemm);
-  GemmArgs g[4];
-  tucker_apply_args(p, c, wsp<float2>(ws, p.off_T1), nullptr, nullptr, g);
-  hipError_t e = TIMED("gemm_core_coef", gemm_launch(g[0], p.precision, gws, st));  // T1 = core x_4 c
+  hipError_t e = core_forward(p, c, wsp<float2>(ws, p.off_T1), ws, st);
   if (e != hipSuccess) return e;
   e = TIMED("gemm_mode3", gemm_launch(fused_T3_args(p, wsp<float2>(ws, p.off_T1), wsp<float2>(ws, p.off_T3)),
                                       p.precision, gws, st));
@@ -647,10 +698,7 @@ static hipError_t fused_adjoint(const Plan& p, const float2* x, const float2* c,
     e = TIMED("gemm_mode3_adjoint",
               gemm_launch(fused_T1b_args(p, pa.T3b, wsp<float2>(ws, p.off_T1b)), p.precision, gws, st));
     if (e != hipSuccess) return e;
-    GemmArgs g[4];
-    tucker_adjoint_args(p, nullptr, wsp<float2>(ws, p.off_T1b), nullptr, gc, g);
-    e = TIMED("gemm_core_adjoint", gemm_launch(g[3], p.precision, gws, st));  // gc = core^H T1b
-    if (e != hipSuccess) return e;
+    if ((e = core_adjoint(p, wsp<float2>(ws, p.off_T1b), gc, 1.0f, nullptr, ws, st)) != hipSuccess) return e;
   }
   return hipSuccess;
 }

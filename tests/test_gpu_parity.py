@@ -35,6 +35,14 @@ CASES = {
                                         basis="tucker", mask="lines3d", frac=0.125),
     "fused_64x64x32_r20_K30_J3": dict(seed=112, dims=(64, 64, 32), ranks=(20, 20, 7), J=3, K=30,
                                       basis="tucker", mask="lines3d", frac=0.2, weights=True),
+    # core contraction kernels: several rho chunks with a ragged tail, two k groups, 3 and 4
+    # coil blocks; J = 65 takes the GEMM fallback
+    "tucker3d_16x16x12_r9x10x11_K150_J37": dict(seed=116, dims=(16, 16, 12), ranks=(9, 10, 11), J=37, K=150,
+                                                basis="tucker", mask="random", frac=0.3, weights=True),
+    "fused_32x32x16_r9x10x11_K150_J64": dict(seed=117, dims=(32, 32, 16), ranks=(9, 10, 11), J=64, K=150,
+                                             basis="tucker", mask="lines3d", frac=0.3),
+    "tucker3d_12x10x8_r5x4x3_K20_J65": dict(seed=118, dims=(12, 10, 8), ranks=(5, 4, 3), J=65, K=20,
+                                            basis="tucker", mask="lines3d", frac=0.3),
     # radial sampling (KB NUFFT, W = 6, sigma = 2, ramp density compensation in the loss)
     "radial_32x24_J3_K9_7spokes": dict(seed=113, dims=(32, 24), J=3, K=9, mask="radial", spokes=7, weights=True),
     "radial_40x30_J2_K6_5spokes": dict(seed=114, dims=(40, 30), J=2, K=6, mask="radial", spokes=5, n_read=48),
@@ -42,7 +50,7 @@ CASES = {
                                        n_read=512, weights=True),
 }
 FUSED = {"tucker3d_32x32x32_r12_K70_J4", "fused_48x32x20_r9x13x5_K23_J5", "fused_16x80x12_r3x17x4_K11_J3",
-         "fused_128x128x64_r40_K60_J5", "fused_64x64x32_r20_K30_J3"}
+         "fused_128x128x64_r40_K60_J5", "fused_64x64x32_r20_K30_J3", "fused_32x32x16_r9x10x11_K150_J64"}
 
 _cache = {}
 
