@@ -212,8 +212,11 @@ template <> struct CtPlan<16> { static constexpr int P = 1, R0 = 16, R1 = 1; };
 
 // One Stockham pass with compile-time size, radix and stride.  `tw` holds
 // exp(-2 pi i t / N), t < N (in LDS).  T lines, CH elements per register chunk.
+// tid is the thread's index in the workgroup (callers may pass it through an opaque
+// copy so that the pass's addresses are recomputed where used, not held in registers).
 template <int N, int R, int Ns, int NTHREADS, int CH>
-__device__ __forceinline__ void stockham_pass_ct(float2* lds, int T, int LS, int ES, const float2* tw, int dir) {
+__device__ __forceinline__ void stockham_pass_ct(float2* lds, int T, int LS, int ES, const float2* tw, int dir,
+                                                 int tid) {
   constexpr int nR = N / R;
   constexpr int Tc = CH / N;
   constexpr int MAXQ = (Tc * nR + NTHREADS - 1) / NTHREADS;
@@ -222,7 +225,7 @@ __device__ __forceinline__ void stockham_pass_ct(float2* lds, int T, int LS, int
     float2 v[MAXQ][R];
 #pragma unroll
     for (int q = 0; q < MAXQ; ++q) {
-      const int bf = threadIdx.x + q * NTHREADS;
+      const int bf = tid + q * NTHREADS;
       const int l = l0 + bf % Tc, j = bf / Tc;
       if (bf < Tc * nR && l < T) {
         const int base = l * LS;
@@ -243,7 +246,7 @@ __device__ __forceinline__ void stockham_pass_ct(float2* lds, int T, int LS, int
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < MAXQ; ++q) {
-      const int bf = threadIdx.x + q * NTHREADS;
+      const int bf = tid + q * NTHREADS;
       const int l = l0 + bf % Tc, j = bf / Tc;
       if (bf < Tc * nR && l < T) {
         const int base = l * LS;
@@ -257,10 +260,12 @@ __device__ __forceinline__ void stockham_pass_ct(float2* lds, int T, int LS, int
 }
 
 template <int N, int NTHREADS, int CH>
-__device__ __forceinline__ void lds_fft_ct(float2* lds, int T, int LS, int ES, const float2* tw, int dir) {
+__device__ __forceinline__ void lds_fft_ct(float2* lds, int T, int LS, int ES, const float2* tw, int dir,
+                                           int tid = -1) {
   using P = CtPlan<N>;
-  stockham_pass_ct<N, P::R0, 1, NTHREADS, CH>(lds, T, LS, ES, tw, dir);
-  if constexpr (P::P > 1) stockham_pass_ct<N, P::R1, P::R0, NTHREADS, CH>(lds, T, LS, ES, tw, dir);
+  if (tid < 0) tid = threadIdx.x;
+  stockham_pass_ct<N, P::R0, 1, NTHREADS, CH>(lds, T, LS, ES, tw, dir, tid);
+  if constexpr (P::P > 1) stockham_pass_ct<N, P::R1, P::R0, NTHREADS, CH>(lds, T, LS, ES, tw, dir, tid);
 }
 
 }  // namespace mx

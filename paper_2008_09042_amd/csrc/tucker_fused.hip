@@ -44,19 +44,15 @@ namespace {
 constexpr int PT = 512;                          // threads per plane workgroup
 constexpr int NWAVE = PT / 64;
 constexpr int PMAX = 128;                        // max n0, n1 on this path
+constexpr int RMAX = 48;                         // max r0, r1 on this path (three K16 blocks)
 constexpr int PLANE_ELEMS = PMAX * (PMAX + 1);   // padded plane: 16,512 complex = 132 KB
-constexpr int TW_ELEMS = 2 * PMAX;               // twiddles for n0 and n1
-constexpr int SL = 40;                           // staged U1 row: 32 k' + 8 pad (bf16)
-constexpr int SARR = 48 * SL;                    // one staged array (<= 48 columns)
-constexpr int STAGE_ELEMS = 2 * 4 * SARR / 4;    // double-buffered chunk, in complex slots
-// The twiddles and the adjoint's staging buffer share the region after the plane:
-// they are never live at the same time (twiddles are reloaded for every coil).
-constexpr int EXTRA_ELEMS = TW_ELEMS > STAGE_ELEMS ? TW_ELEMS : STAGE_ELEMS;
-constexpr int LDS_ELEMS = PLANE_ELEMS + EXTRA_ELEMS;
+constexpr int TW_OFF = PLANE_ELEMS;              // twiddles of n0 and n1 (2 x PMAX)
+constexpr int WS_OFF = TW_OFF + 2 * PMAX;        // the current coil's W (A operand of V = W U1^T)
+constexpr int KSW = 2 * RMAX + 8;                // staged BF16 W row: 2 r1 real values + pad
+constexpr int WS_ELEMS = 2 * RMAX * KSW / 4;     // BF16 hi + lo planes, in complex slots
+static_assert(RMAX * (RMAX + 1) <= WS_ELEMS, "FP32 W must fit the staging region");
+constexpr int LDS_ELEMS = WS_OFF + WS_ELEMS;
 constexpr int FFT_CHUNK = PMAX * PMAX / 2;       // elements per register chunk of a pass
-// FP32 phase layout inside the plane region
-constexpr int W_OFF = 0;                         // W  [r0p][r1p]  (<= 64 x 64)
-constexpr int V_OFF = 64 * 64;                   // V  [r0p][n1]   (<= 64 x 128)
 
 __device__ __forceinline__ f32x4 z4() { return f32x4{0.f, 0.f, 0.f, 0.f}; }
 
@@ -123,38 +119,136 @@ __device__ __forceinline__ void store_bop(unsigned short* brh, unsigned short* b
   st8(bil + n * ld + kp0, l);
 }
 
+// ---------------------------------------------------------------- matrix-core tiles
+// A K16 block spans 16 complex reduction indices.  In both precisions lane l (tile row
+// or column l % 16, group g = l / 16) holds the operand values of k = 4 g + t, t < 4,
+// and an accumulator tile holds D[4 g + r][l % 16].  A result tile is therefore, as it
+// stands, the lane's B operand of one K16 block of a following product whose reduction
+// runs over the result's rows: no LDS round trip between chained products.
+template <int PREC>
+struct Tile;
+
+template <>
+struct Tile<1> {  // BF16 split in the real-block form (file header)
+  struct A { u16x8 h, l; };
+  struct B { u16x8 rh, rl, ih, il; };
+  static __device__ __forceinline__ A make_a(const float2 (&v)[4]) {
+    float f[8];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      f[2 * t] = v[t].x;
+      f[2 * t + 1] = v[t].y;
+    }
+    A a;
+    split8(f, a.h, a.l);
+    return a;
+  }
+  static __device__ __forceinline__ B make_b(const float2 (&v)[4]) {
+    float fr[8], fi[8];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      fr[2 * t] = v[t].x;
+      fr[2 * t + 1] = -v[t].y;
+      fi[2 * t] = v[t].y;
+      fi[2 * t + 1] = v[t].x;
+    }
+    B b;
+    split8(fr, b.rh, b.rl);
+    split8(fi, b.ih, b.il);
+    return b;
+  }
+  // fragments of operands split at plan time: planes of `plane` entries, offset o
+  static __device__ __forceinline__ A load_a(const unsigned short* p, size_t plane, size_t o) {
+    return A{ld8(p + o), ld8(p + plane + o)};
+  }
+  static __device__ __forceinline__ B load_b(const unsigned short* p, size_t plane, size_t o) {
+    return B{ld8(p + o), ld8(p + plane + o), ld8(p + 2 * plane + o), ld8(p + 3 * plane + o)};
+  }
+  static __device__ __forceinline__ void mma(f32x4& cr, f32x4& ci, const A& a, const B& b) {
+    mfma6(cr, ci, a.h, a.l, b.rh, b.rl, b.ih, b.il);
+  }
+};
+
+template <>
+struct Tile<0> {  // FP32: four real products per complex product; sub-step t uses k = 4 g + t
+  struct A { float2 v[4]; };
+  struct B { float2 v[4]; };
+  static __device__ __forceinline__ A make_a(const float2 (&v)[4]) { return A{{v[0], v[1], v[2], v[3]}}; }
+  static __device__ __forceinline__ B make_b(const float2 (&v)[4]) { return B{{v[0], v[1], v[2], v[3]}}; }
+  static __device__ __forceinline__ void mma(f32x4& cr, f32x4& ci, const A& a, const B& b) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) cmfma(cr, ci, a.v[t], b.v[t]);
+  }
+};
+
+template <int PREC>
+__device__ __forceinline__ typename Tile<PREC>::B tile_as_b(const f32x4& cr, const f32x4& ci) {
+  float2 v[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) v[t] = make_float2(cr[t], ci[t]);
+  return Tile<PREC>::make_b(v);
+}
+
+__device__ __forceinline__ int kpad(int r) { return (2 * r + 31) / 32 * 32; }
+
 // ---------------------------------------------------------------- plane geometry
 template <int N0, int N1>
 struct Geo {
-  int n0, n1, n2, r0, r1, r0p, r1p, PS;
+  int n0, n1, n2, r0, r1, PS;
+  int n0b, n1b, r0b, r1b;  // 16-blocks of each extent
+  int KP0, KP1;            // BF16 real-block reduction lengths of r0, r1
   __device__ Geo(const PlaneArgs& a) {
     n0 = N0 ? N0 : a.n0;
     n1 = N1 ? N1 : a.n1;
     n2 = a.n2;
     r0 = a.r0;
     r1 = a.r1;
-    r0p = a.r0p;
-    r1p = a.r1p;
     PS = n1 + 1;
+    n0b = n0 / 16;
+    n1b = n1 / 16;
+    r0b = a.r0p / 16;
+    r1b = a.r1p / 16;
+    KP0 = kpad(r0);
+    KP1 = kpad(r1);
   }
 };
 
+// The wave's share of the plane in the coil-map and pointwise phases: column block cb
+// and row blocks part, part + q, ...  Every (row block, column block) tile has one owner.
+struct Share {
+  int cb, part, q;
+  bool on;
+};
+
+template <int N0, int N1>
+__device__ __forceinline__ Share plane_share(const Geo<N0, N1>& g) {
+  const int wave = threadIdx.x >> 6;
+  Share s;
+  s.q = NWAVE / g.n1b;
+  s.cb = wave % g.n1b;
+  s.part = wave / g.n1b;
+  s.on = s.part < s.q;
+  return s;
+}
+
 template <int N0, int N1>
 __device__ __forceinline__ void load_twiddles(const PlaneArgs& a, const Geo<N0, N1>& g, float2* lds) {
-  float2* tw0 = lds + PLANE_ELEMS;
+  float2* tw0 = lds + TW_OFF;
   float2* tw1 = tw0 + PMAX;
   for (int e = threadIdx.x; e < g.n0; e += PT) tw0[e] = a.tw0[e];
   for (int e = threadIdx.x; e < g.n1; e += PT) tw1[e] = a.tw1[e];
 }
 
-// 2D centred DFT of the plane (chessboard signs applied by the caller).
+// 2D centred DFT of the plane (chessboard signs applied by the caller); ends synchronised.
 template <int N0, int N1>
 __device__ __forceinline__ void plane_fft(const PlaneArgs& a, const Geo<N0, N1>& g, float2* lds, int dir) {
-  const float2* tw0 = lds + PLANE_ELEMS;
+  const float2* tw0 = lds + TW_OFF;
   const float2* tw1 = tw0 + PMAX;
+  int tid = threadIdx.x;  // opaque: the passes' addresses are not hoisted out of the coil loop
+  asm volatile("" : "+v"(tid));
   auto rows = [&]() {
     if constexpr (N1 != 0) {
-      lds_fft_ct<N1, PT, FFT_CHUNK>(lds, g.n0, g.PS, 1, tw1, dir);
+      lds_fft_ct<N1, PT, FFT_CHUNK>(lds, g.n0, g.PS, 1, tw1, dir, tid);
     } else {
       LdsLines t{g.n0, g.PS, 1};
       lds_fft_lines<PT, FFT_CHUNK>(lds, t, g.n1, a.rad1, a.nrad1, tw1, dir);
@@ -162,7 +256,7 @@ __device__ __forceinline__ void plane_fft(const PlaneArgs& a, const Geo<N0, N1>&
   };
   auto cols = [&]() {
     if constexpr (N0 != 0) {
-      lds_fft_ct<N0, PT, FFT_CHUNK>(lds, g.n1, 1, g.PS, tw0, dir);
+      lds_fft_ct<N0, PT, FFT_CHUNK>(lds, g.n1, 1, g.PS, tw0, dir, tid);
     } else {
       LdsLines t{g.n1, 1, g.PS};
       lds_fft_lines<PT, FFT_CHUNK>(lds, t, g.n0, a.rad0, a.nrad0, tw0, dir);
@@ -171,354 +265,273 @@ __device__ __forceinline__ void plane_fft(const PlaneArgs& a, const Geo<N0, N1>&
   if (dir < 0) { rows(); cols(); } else { cols(); rows(); }
 }
 
-// ---------------------------------------------------------------- FP32 contractions
-// V = W U1^T ([r0p][n1] in LDS) from W = T3[j][i2] (zero-padded r0p x r1p in LDS).
-template <int N0, int N1>
-__device__ __forceinline__ void coilmap_V_f32(const PlaneArgs& a, const Geo<N0, N1>& g, int j, int i2, float2* lds) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+// ---------------------------------------------------------------- operand fragments
+// W = T3[j][i2] (r0 x r1, zero-padded to whole blocks) into the staging region.
+template <int PREC, int N0, int N1>
+__device__ __forceinline__ void stage_w(const PlaneArgs& a, const Geo<N0, N1>& g, int j, int i2, float2* lds) {
   const float2* src = a.T3 + ((size_t)j * g.n2 + i2) * g.r0 * g.r1;
-  for (int e = threadIdx.x; e < g.r0p * g.r1p; e += PT) {
-    const int p0 = e / g.r1p, p1 = e % g.r1p;
-    lds[W_OFF + e] = (p0 < g.r0 && p1 < g.r1) ? src[p0 * g.r1 + p1] : make_float2(0.f, 0.f);
-  }
-  __syncthreads();
-  const int mbl = g.r0p / 16, nbl = g.n1 / 16;
-  for (int blk = wave; blk < mbl * nbl; blk += NWAVE) {
-    const int mb = blk / nbl, nb = blk % nbl;
-    const int row = 16 * mb + (lane & 15), col = 16 * nb + (lane & 15);
-    float2 bv[16];
+  if constexpr (PREC == 1) {
+    unsigned short* wh = reinterpret_cast<unsigned short*>(lds + WS_OFF);
+    unsigned short* wl = wh + RMAX * KSW;
+    const float* f = reinterpret_cast<const float*>(src);
+    const int ch = g.KP1 / 8;
+    for (int e = threadIdx.x; e < 16 * g.r0b * ch; e += PT) {
+      const int p0 = e / ch, c8 = (e % ch) * 8;
+      float v[8];
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      const int kk = 4 * s + (lane >> 4);
-      bv[s] = (4 * s < g.r1p && kk < g.r1) ? a.U1[(size_t)col * g.r1 + kk] : make_float2(0.f, 0.f);
+      for (int t = 0; t < 8; ++t) v[t] = (p0 < g.r0 && c8 + t < 2 * g.r1) ? f[(size_t)p0 * 2 * g.r1 + c8 + t] : 0.f;
+      u16x8 h, l;
+      split8(v, h, l);
+      st8(wh + p0 * KSW + c8, h);
+      st8(wl + p0 * KSW + c8, l);
     }
-    f32x4 cr = z4(), ci = z4();
-#pragma unroll
-    for (int s = 0; s < 16; ++s)
-      if (4 * s < g.r1p) cmfma(cr, ci, lds[W_OFF + row * g.r1p + 4 * s + (lane >> 4)], bv[s]);
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-      lds[V_OFF + (16 * mb + 4 * (lane >> 4) + r) * g.n1 + col] = make_float2(cr[r], ci[r]);
-  }
-}
-
-// P = U0 V, this wave's 16 rows, all n1 columns, into registers.
-template <int N0, int N1>
-__device__ __forceinline__ void coilmap_P_f32(const PlaneArgs& a, const Geo<N0, N1>& g, const float2* lds, f32x4 (&pr)[8],
-                                     f32x4 (&pi)[8]) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nbl = g.n1 / 16;
-#pragma unroll
-  for (int nb = 0; nb < 8; ++nb) { pr[nb] = z4(); pi[nb] = z4(); }
-  if (wave >= g.n0 / 16) return;
-  const int row = 16 * wave + (lane & 15);
-  float2 av[16];
-#pragma unroll
-  for (int s = 0; s < 16; ++s) {
-    const int kk = 4 * s + (lane >> 4);
-    av[s] = (4 * s < g.r0p && kk < g.r0) ? a.U0[(size_t)row * g.r0 + kk] : make_float2(0.f, 0.f);
-  }
-#pragma unroll
-  for (int s = 0; s < 16; ++s) {
-    if (4 * s < g.r0p) {
-      const int kk = 4 * s + (lane >> 4);
-#pragma unroll
-      for (int nb = 0; nb < 8; ++nb)
-        if (nb < nbl) cmfma(pr[nb], pi[nb], av[s], lds[V_OFF + kk * g.n1 + 16 * nb + (lane & 15)]);
+  } else {
+    float2* w = lds + WS_OFF;
+    const int rp = 16 * g.r1b;
+    for (int e = threadIdx.x; e < 16 * g.r0b * rp; e += PT) {
+      const int p0 = e / rp, p1 = e % rp;
+      w[p0 * (RMAX + 1) + p1] = (p0 < g.r0 && p1 < g.r1) ? src[(size_t)p0 * g.r1 + p1] : make_float2(0.f, 0.f);
     }
   }
 }
 
-// Y = h conj(U1) (h in the plane) for this wave's rows; Wb = U0^H Y -> T3b.
-template <int N0, int N1>
-__device__ __forceinline__ void adjoint_W_f32(const PlaneArgs& a, const Geo<N0, N1>& g, int j, int i2, float2* lds) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  f32x4 yr[4], yi[4];
+// A fragment of W: rows p0 of block mb, K16 block s over p1.
+template <int PREC, int N0, int N1>
+__device__ __forceinline__ typename Tile<PREC>::A frag_w(int lane, const Geo<N0, N1>&, const float2* lds, int mb, int s) {
+  const int row = 16 * mb + (lane & 15), grp = lane >> 4;
+  if constexpr (PREC == 1) {
+    const unsigned short* wh = reinterpret_cast<const unsigned short*>(lds + WS_OFF);
+    const int o = row * KSW + 32 * s + 8 * grp;
+    return typename Tile<1>::A{ld8(wh + o), ld8(wh + RMAX * KSW + o)};
+  } else {
+    float2 v[4];
 #pragma unroll
-  for (int nb = 0; nb < 4; ++nb) { yr[nb] = z4(); yi[nb] = z4(); }
-  const int nbr = g.r1p / 16;
-  if (wave < g.n0 / 16) {
-    const int row = 16 * wave + (lane & 15);
-    for (int k = 0; k < g.n1; k += 16) {
-      float2 bv[4][4];
+    for (int t = 0; t < 4; ++t) v[t] = lds[WS_OFF + row * (RMAX + 1) + 16 * s + 4 * grp + t];
+    return Tile<0>::make_a(v);
+  }
+}
+
+// B fragment of U1^T: K16 block s over p1, column block cb over i1.
+template <int PREC, int N0, int N1>
+__device__ __forceinline__ typename Tile<PREC>::B frag_u1t(int lane, const PlaneArgs& a, const Geo<N0, N1>& g, int s, int cb) {
+  const int grp = lane >> 4, i1 = 16 * cb + (lane & 15);
+  if constexpr (PREC == 1) {
+    return Tile<1>::load_b(a.U1B, (size_t)g.n1 * g.KP1, (size_t)i1 * g.KP1 + 32 * s + 8 * grp);
+  } else {
+    float2 v[4];
 #pragma unroll
-      for (int s = 0; s < 4; ++s)
+    for (int t = 0; t < 4; ++t) {
+      const int p1 = 16 * s + 4 * grp + t;
+      v[t] = p1 < g.r1 ? a.U1[(size_t)i1 * g.r1 + p1] : make_float2(0.f, 0.f);
+    }
+    return Tile<0>::make_b(v);
+  }
+}
+
+// A fragment of U0: row block rb over i0, K16 block s over p0.
+template <int PREC, int N0, int N1>
+__device__ __forceinline__ typename Tile<PREC>::A frag_u0(int lane, const PlaneArgs& a, const Geo<N0, N1>& g, int rb, int s) {
+  const int grp = lane >> 4, i0 = 16 * rb + (lane & 15);
+  if constexpr (PREC == 1) {
+    return Tile<1>::load_a(a.U0A, (size_t)g.n0 * g.KP0, (size_t)i0 * g.KP0 + 32 * s + 8 * grp);
+  } else {
+    float2 v[4];
 #pragma unroll
-        for (int nb = 0; nb < 4; ++nb) {
-          const int kk = k + 4 * s + (lane >> 4), col = 16 * nb + (lane & 15);
-          bv[s][nb] = (nb < nbr && col < g.r1) ? cconj(a.U1[(size_t)kk * g.r1 + col]) : make_float2(0.f, 0.f);
-        }
+    for (int t = 0; t < 4; ++t) {
+      const int p0 = 16 * s + 4 * grp + t;
+      v[t] = p0 < g.r0 ? a.U0[(size_t)i0 * g.r0 + p0] : make_float2(0.f, 0.f);
+    }
+    return Tile<0>::make_a(v);
+  }
+}
+
+// B fragment of conj(U1): K16 block s over i1, column block nb over p1.
+template <int PREC, int N0, int N1>
+__device__ __forceinline__ typename Tile<PREC>::B frag_u1c(int lane, const PlaneArgs& a, const Geo<N0, N1>& g, int s, int nb) {
+  const int grp = lane >> 4, p1 = 16 * nb + (lane & 15);
+  if constexpr (PREC == 1) {
+    return Tile<1>::load_b(a.U1C, (size_t)16 * g.r1b * 2 * g.n1, (size_t)p1 * 2 * g.n1 + 32 * s + 8 * grp);
+  } else {
+    float2 v[4];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const float2 av = lds[row * g.PS + k + 4 * s + (lane >> 4)];
+    for (int t = 0; t < 4; ++t) {
+      const int i1 = 16 * s + 4 * grp + t;
+      v[t] = p1 < g.r1 ? cconj(a.U1[(size_t)i1 * g.r1 + p1]) : make_float2(0.f, 0.f);
+    }
+    return Tile<0>::make_b(v);
+  }
+}
+
+// A fragment of U0^H: row block mb over p0, K16 block s over i0.
+template <int PREC, int N0, int N1>
+__device__ __forceinline__ typename Tile<PREC>::A frag_u0h(int lane, const PlaneArgs& a, const Geo<N0, N1>& g, int mb, int s) {
+  const int grp = lane >> 4, p0 = 16 * mb + (lane & 15);
+  if constexpr (PREC == 1) {
+    return Tile<1>::load_a(a.U0H, (size_t)16 * g.r0b * 2 * g.n0, (size_t)p0 * 2 * g.n0 + 32 * s + 8 * grp);
+  } else {
+    float2 v[4];
 #pragma unroll
-        for (int nb = 0; nb < 4; ++nb)
-          if (nb < nbr) cmfma(yr[nb], yi[nb], av, bv[s][nb]);
-      }
+    for (int t = 0; t < 4; ++t) {
+      const int i0 = 16 * s + 4 * grp + t;
+      v[t] = p0 < g.r0 ? cconj(a.U0[(size_t)i0 * g.r0 + p0]) : make_float2(0.f, 0.f);
+    }
+    return Tile<0>::make_a(v);
+  }
+}
+
+// Y (copy q of the partial sums over i1) in the plane region, as the B operand of Wb.
+template <int PREC, int N0, int N1>
+__device__ __forceinline__ void y_store(int lane, const Geo<N0, N1>& g, float2* lds, int q, int yb, int nb, const f32x4& cr,
+                                        const f32x4& ci) {
+  const int grp = lane >> 4;
+  if constexpr (PREC == 1) {
+    const int KS = 2 * g.n0 + 8, R1P = 16 * g.r1b;
+    unsigned short* base = reinterpret_cast<unsigned short*>(lds) + (size_t)q * 4 * R1P * KS;
+    store_bop(base, base + R1P * KS, base + 2 * R1P * KS, base + 3 * R1P * KS, KS, 16 * nb + (lane & 15),
+              2 * (16 * yb + 4 * grp), cr, ci);
+  } else {
+    const int YS = 16 * g.r1b + 1;
+    float2* base = lds + (size_t)q * g.n0 * YS;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) base[(16 * yb + 4 * grp + r) * YS + 16 * nb + (lane & 15)] = make_float2(cr[r], ci[r]);
+  }
+}
+
+template <int PREC, int N0, int N1>
+__device__ __forceinline__ typename Tile<PREC>::B frag_y(int lane, const Geo<N0, N1>& g, const float2* lds, int q, int s, int nb) {
+  const int grp = lane >> 4;
+  if constexpr (PREC == 1) {
+    const int KS = 2 * g.n0 + 8, R1P = 16 * g.r1b;
+    const unsigned short* base = reinterpret_cast<const unsigned short*>(lds) + (size_t)q * 4 * R1P * KS;
+    return Tile<1>::load_b(base, (size_t)R1P * KS, (size_t)(16 * nb + (lane & 15)) * KS + 32 * s + 8 * grp);
+  } else {
+    const int YS = 16 * g.r1b + 1;
+    const float2* base = lds + (size_t)q * g.n0 * YS;
+    float2 v[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) v[t] = base[(16 * s + 4 * grp + t) * YS + 16 * nb + (lane & 15)];
+    return Tile<0>::make_b(v);
+  }
+}
+
+// ---------------------------------------------------------------- coil map
+// V = W U1^T for column block cb, kept as the B operands of P = U0 V (one per K16
+// block over p0).  W must be staged.
+template <int PREC, int N0, int N1>
+__device__ __forceinline__ void coil_v(int lane, const PlaneArgs& a, const Geo<N0, N1>& g, const float2* lds, int cb,
+                                       typename Tile<PREC>::B (&vb)[3]) {
+  f32x4 cr[3], ci[3];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) { cr[m] = z4(); ci[m] = z4(); }
+#pragma unroll
+  for (int s = 0; s < 3; ++s)
+    if (s < g.r1b) {
+      const typename Tile<PREC>::B b = frag_u1t<PREC>(lane, a, g, s, cb);
+#pragma unroll
+      for (int m = 0; m < 3; ++m)
+        if (m < g.r0b) Tile<PREC>::mma(cr[m], ci[m], frag_w<PREC>(lane, g, lds, m, s), b);
+    }
+#pragma unroll
+  for (int m = 0; m < 3; ++m) vb[m] = tile_as_b<PREC>(cr[m], ci[m]);
+}
+
+// P tile (rb, cb) = U0 V: lane holds P[16 rb + 4 g + r][16 cb + l % 16].
+template <int PREC, int N0, int N1>
+__device__ __forceinline__ void coil_p(int lane, const PlaneArgs& a, const Geo<N0, N1>& g, int rb,
+                                       const typename Tile<PREC>::B (&vb)[3], f32x4& pr, f32x4& pi) {
+  pr = z4();
+  pi = z4();
+#pragma unroll
+  for (int s = 0; s < 3; ++s)
+    if (s < g.r0b) Tile<PREC>::mma(pr, pi, frag_u0<PREC>(lane, a, g, rb, s), vb[s]);
+}
+
+// ---------------------------------------------------------------- adjoint contraction
+// Y = h conj(U1) with h in the plane, then Wb = U0^H Y -> T3b[j][i2].  Wave w takes Y row
+// block w % n0b over a 1 / q share of the i1 blocks; the q partial copies of Y are stored
+// side by side and Wb sums over them as extra reduction blocks.  Ends synchronised.
+template <int PREC, int N0, int N1>
+__device__ __forceinline__ void adjoint_w(int lane, const PlaneArgs& a, const Geo<N0, N1>& g, int j, int i2, float2* lds) {
+  const int wave = threadIdx.x >> 6, grp = lane >> 4;
+  const int qy = NWAVE / g.n0b, yb = wave % g.n0b, kq = wave / g.n0b;
+  const bool on = kq < qy;
+  f32x4 yr[3], yi[3];
+#pragma unroll
+  for (int nb = 0; nb < 3; ++nb) { yr[nb] = z4(); yi[nb] = z4(); }
+  if (on) {
+    const int i0 = 16 * yb + (lane & 15);
+    for (int s = kq; s < g.n1b; s += qy) {
+      float2 hv[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) hv[t] = lds[i0 * g.PS + 16 * s + 4 * grp + t];
+      const typename Tile<PREC>::A av = Tile<PREC>::make_a(hv);
+#pragma unroll
+      for (int nb = 0; nb < 3; ++nb)
+        if (nb < g.r1b) Tile<PREC>::mma(yr[nb], yi[nb], av, frag_u1c<PREC>(lane, a, g, s, nb));
     }
   }
-  __syncthreads();
-  if (wave < g.n0 / 16) {
+  __syncthreads();  // h is consumed; Y takes its place
+  if (on) {
 #pragma unroll
-    for (int nb = 0; nb < 4; ++nb)
-      if (nb < nbr)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          lds[(16 * wave + 4 * (lane >> 4) + r) * g.r1p + 16 * nb + (lane & 15)] = make_float2(yr[nb][r], yi[nb][r]);
+    for (int nb = 0; nb < 3; ++nb)
+      if (nb < g.r1b) y_store<PREC>(lane, g, lds, kq, yb, nb, yr[nb], yi[nb]);
   }
   __syncthreads();
-  const int mbl = g.r0p / 16;
   float2* wo = a.T3b + ((size_t)j * g.n2 + i2) * g.r0 * g.r1;
-  for (int blk = wave; blk < mbl * nbr; blk += NWAVE) {
-    const int mb = blk / nbr, nb = blk % nbr;
+  for (int blk = wave; blk < g.r0b * g.r1b; blk += NWAVE) {
+    const int mb = blk / g.r1b, nb = blk % g.r1b;
     f32x4 cr = z4(), ci = z4();
-    const int p0 = 16 * mb + (lane & 15);
-    for (int k = 0; k < g.n0; k += 16) {
-      float2 av[4];
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int kk = k + 4 * s + (lane >> 4);
-        av[s] = p0 < g.r0 ? cconj(a.U0[(size_t)kk * g.r0 + p0]) : make_float2(0.f, 0.f);
-      }
-#pragma unroll
-      for (int s = 0; s < 4; ++s)
-        cmfma(cr, ci, av[s], lds[(k + 4 * s + (lane >> 4)) * g.r1p + 16 * nb + (lane & 15)]);
+    for (int s = 0; s < g.n0b; ++s) {
+      const typename Tile<PREC>::A av = frag_u0h<PREC>(lane, a, g, mb, s);
+      for (int q = 0; q < qy; ++q) Tile<PREC>::mma(cr, ci, av, frag_y<PREC>(lane, g, lds, q, s, nb));
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int q0 = 16 * mb + 4 * (lane >> 4) + r, q1 = 16 * nb + (lane & 15);
+      const int q0 = 16 * mb + 4 * grp + r, q1 = 16 * nb + (lane & 15);
       if (q0 < g.r0 && q1 < g.r1) wo[q0 * g.r1 + q1] = make_float2(cr[r], ci[r]);
     }
   }
-}
-
-// ---------------------------------------------------------------- BF16-split contractions
-// LDS (unsigned short view of the plane region) during the coil-map phase:
-//   WA hi/lo     [r0p][KS1]  A operand of V = W U1^T   (KS1 = KP1 + 8, padded row)
-//   VB r/i hi/lo [n1][KS0]   B operand of P = U0 V     (KS0 = KP0 + 8)
-__device__ __forceinline__ int kpad(int r) { return (2 * r + 31) / 32 * 32; }
-
-template <int N0, int N1>
-__device__ __forceinline__ void coilmap_V_bf(const PlaneArgs& a, const Geo<N0, N1>& g, int j, int i2, float2* lds) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int KP1 = kpad(g.r1), KS1 = KP1 + 8, KP0 = kpad(g.r0), KS0 = KP0 + 8;
-  unsigned short* u = reinterpret_cast<unsigned short*>(lds);
-  unsigned short* wah = u;
-  unsigned short* wal = wah + g.r0p * KS1;
-  unsigned short* vbrh = wal + g.r0p * KS1;
-  unsigned short* vbrl = vbrh + g.n1 * KS0;
-  unsigned short* vbih = vbrl + g.n1 * KS0;
-  unsigned short* vbil = vbih + g.n1 * KS0;
-  // W rows as interleaved real pairs (the real-block A operand), split, zero-padded
-  const float* src = reinterpret_cast<const float*>(a.T3 + ((size_t)j * g.n2 + i2) * g.r0 * g.r1);
-  const int chunks = KP1 / 8;
-  for (int e = threadIdx.x; e < g.r0p * chunks; e += PT) {
-    const int p0 = e / chunks, c8 = (e % chunks) * 8;
-    float v[8];
-#pragma unroll
-    for (int t = 0; t < 8; ++t) v[t] = (p0 < g.r0 && c8 + t < 2 * g.r1) ? src[p0 * 2 * g.r1 + c8 + t] : 0.f;
-    u16x8 h, l;
-    split8(v, h, l);
-    st8(wah + p0 * KS1 + c8, h);
-    st8(wal + p0 * KS1 + c8, l);
-  }
-  // zero the padded k' tail of the V operand (k' from 2 r0p to KP0)
-  const int tail = KP0 - 2 * g.r0p;
-  for (int e = threadIdx.x; e < g.n1 * tail; e += PT) {
-    const int n = e / tail, k = 2 * g.r0p + e % tail;
-    vbrh[n * KS0 + k] = 0;
-    vbrl[n * KS0 + k] = 0;
-    vbih[n * KS0 + k] = 0;
-    vbil[n * KS0 + k] = 0;
-  }
   __syncthreads();
-  // V blocks: B operand of U1^T from the plan's split copy [n1][KP1]
-  const int mbl = g.r0p / 16, nbl = g.n1 / 16, ks = KP1 / 32;
-  for (int nb = wave; nb < nbl; nb += NWAVE) {
-    const int col = 16 * nb + (lane & 15);
-    u16x8 brh[4], brl[4], bih[4], bil[4];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      if (s < ks) {
-        const size_t o = (size_t)col * KP1 + 32 * s + 8 * (lane >> 4);
-        brh[s] = ld8(a.U1B + 0 * (size_t)g.n1 * KP1 + o);
-        brl[s] = ld8(a.U1B + 1 * (size_t)g.n1 * KP1 + o);
-        bih[s] = ld8(a.U1B + 2 * (size_t)g.n1 * KP1 + o);
-        bil[s] = ld8(a.U1B + 3 * (size_t)g.n1 * KP1 + o);
-      }
-    }
-    for (int mb = 0; mb < mbl; ++mb) {
-      f32x4 cr = z4(), ci = z4();
-      const int row = 16 * mb + (lane & 15);
-#pragma unroll
-      for (int s = 0; s < 4; ++s)
-        if (s < ks) {
-          const int ko = row * KS1 + 32 * s + 8 * (lane >> 4);
-          mfma6(cr, ci, ld8(wah + ko), ld8(wal + ko), brh[s], brl[s], bih[s], bil[s]);
-        }
-      // V rows 16 mb + 4 (lane / 16) + r -> B operand of P at k' = 2 * row
-      store_bop(vbrh, vbrl, vbih, vbil, KS0, col, 2 * (16 * mb + 4 * (lane >> 4)), cr, ci);
-    }
-  }
-}
-
-template <int N0, int N1>
-__device__ __forceinline__ void coilmap_P_bf(const PlaneArgs& a, const Geo<N0, N1>& g, const float2* lds, f32x4 (&pr)[8],
-                                    f32x4 (&pi)[8]) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int KP1 = kpad(g.r1), KS1 = KP1 + 8, KP0 = kpad(g.r0), KS0 = KP0 + 8;
-  const unsigned short* u = reinterpret_cast<const unsigned short*>(lds);
-  const unsigned short* vbrh = u + 2 * g.r0p * KS1;
-  const unsigned short* vbrl = vbrh + g.n1 * KS0;
-  const unsigned short* vbih = vbrl + g.n1 * KS0;
-  const unsigned short* vbil = vbih + g.n1 * KS0;
-  const int nbl = g.n1 / 16, ks = KP0 / 32;
-#pragma unroll
-  for (int nb = 0; nb < 8; ++nb) { pr[nb] = z4(); pi[nb] = z4(); }
-  if (wave >= g.n0 / 16) return;
-  const int row = 16 * wave + (lane & 15);
-  u16x8 ah[4], al[4];
-#pragma unroll
-  for (int s = 0; s < 4; ++s)
-    if (s < ks) {
-      const size_t o = (size_t)row * KP0 + 32 * s + 8 * (lane >> 4);
-      ah[s] = ld8(a.U0A + o);
-      al[s] = ld8(a.U0A + (size_t)g.n0 * KP0 + o);
-    }
-#pragma unroll
-  for (int nb = 0; nb < 8; ++nb)
-    if (nb < nbl) {
-      const int col = 16 * nb + (lane & 15);
-#pragma unroll
-      for (int s = 0; s < 4; ++s)
-        if (s < ks) {
-          const int ko = col * KS0 + 32 * s + 8 * (lane >> 4);
-          mfma6(pr[nb], pi[nb], ah[s], al[s], ld8(vbrh + ko), ld8(vbrl + ko), ld8(vbih + ko), ld8(vbil + ko));
-        }
-    }
-}
-
-// Y = h conj(U1) with h (FP32 plane) split on the fly and U1's split copy staged through
-// LDS one 32-wide k' chunk at a time; then Wb = U0^H Y -> T3b.
-template <int N0, int N1>
-__device__ __forceinline__ void adjoint_W_bf(const PlaneArgs& a, const Geo<N0, N1>& g, int j, int i2, float2* lds) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nbr = g.r1p / 16, K2 = 2 * g.n1;
-  unsigned short* stage = reinterpret_cast<unsigned short*>(lds + PLANE_ELEMS);
-  f32x4 yr[4], yi[4];
-#pragma unroll
-  for (int nb = 0; nb < 4; ++nb) { yr[nb] = z4(); yi[nb] = z4(); }
-  auto stage_chunk = [&](int s, int buf) {
-    unsigned short* dst = stage + buf * 4 * SARR;
-    for (int e = threadIdx.x; e < 4 * g.r1p * 4; e += PT) {
-      const int arr = e / (g.r1p * 4), rem = e % (g.r1p * 4), p1 = rem / 4, c8 = (rem % 4) * 8;
-      st8(dst + arr * SARR + p1 * SL + c8, ld8(a.U1C + (size_t)arr * g.r1p * K2 + (size_t)p1 * K2 + 32 * s + c8));
-    }
-  };
-  const int ksteps = K2 / 32;
-  stage_chunk(0, 0);
-  __syncthreads();
-  for (int s = 0; s < ksteps; ++s) {
-    if (s + 1 < ksteps) stage_chunk(s + 1, (s + 1) & 1);
-    if (wave < g.n0 / 16) {
-      const int row = 16 * wave + (lane & 15);
-      const int c0 = (32 * s + 8 * (lane >> 4)) / 2;  // first complex column of this lane's 8 k'
-      float v[8];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const float2 h = lds[row * g.PS + c0 + t];
-        v[2 * t] = h.x;
-        v[2 * t + 1] = h.y;
-      }
-      u16x8 ah, al;
-      split8(v, ah, al);
-      const unsigned short* src = stage + (s & 1) * 4 * SARR;
-#pragma unroll
-      for (int nb = 0; nb < 4; ++nb)
-        if (nb < nbr) {
-          const int ko = (16 * nb + (lane & 15)) * SL + 8 * (lane >> 4);
-          mfma6(yr[nb], yi[nb], ah, al, ld8(src + ko), ld8(src + SARR + ko), ld8(src + 2 * SARR + ko),
-                ld8(src + 3 * SARR + ko));
-        }
-    }
-    __syncthreads();
-  }
-  // Y -> B operand of Wb, [r1p][KS] with k' = 2 i0 + {0, 1}
-  const int KS = 2 * g.n0 + 8;
-  unsigned short* u = reinterpret_cast<unsigned short*>(lds);
-  unsigned short* ybrh = u;
-  unsigned short* ybrl = ybrh + g.r1p * KS;
-  unsigned short* ybih = ybrl + g.r1p * KS;
-  unsigned short* ybil = ybih + g.r1p * KS;
-  if (wave < g.n0 / 16) {
-#pragma unroll
-    for (int nb = 0; nb < 4; ++nb)
-      if (nb < nbr)
-        store_bop(ybrh, ybrl, ybih, ybil, KS, 16 * nb + (lane & 15), 2 * (16 * wave + 4 * (lane >> 4)), yr[nb],
-                  yi[nb]);
-  }
-  __syncthreads();
-  const int mbl = g.r0p / 16, K0 = 2 * g.n0;
-  float2* wo = a.T3b + ((size_t)j * g.n2 + i2) * g.r0 * g.r1;
-  for (int blk = wave; blk < mbl * nbr; blk += NWAVE) {
-    const int mb = blk / nbr, nb = blk % nbr;
-    f32x4 cr = z4(), ci = z4();
-    const int p0 = 16 * mb + (lane & 15), p1 = 16 * nb + (lane & 15);
-    for (int s = 0; s < K0 / 32; ++s) {
-      const size_t ao = (size_t)p0 * K0 + 32 * s + 8 * (lane >> 4);
-      const int ko = p1 * KS + 32 * s + 8 * (lane >> 4);
-      mfma6(cr, ci, ld8(a.U0H + ao), ld8(a.U0H + (size_t)g.r0p * K0 + ao), ld8(ybrh + ko), ld8(ybrl + ko),
-            ld8(ybih + ko), ld8(ybil + ko));
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int q0 = 16 * mb + 4 * (lane >> 4) + r;
-      if (q0 < g.r0 && p1 < g.r1) wo[q0 * g.r1 + p1] = make_float2(cr[r], ci[r]);
-    }
-  }
 }
 
 // ---------------------------------------------------------------- plane kernels
 template <int PREC, int N0, int N1>
-__device__ __forceinline__ void coil_map(const PlaneArgs& a, const Geo<N0, N1>& g, int j, int i2, float2* lds,
-                                f32x4 (&pr)[8], f32x4 (&pi)[8]) {
-  if constexpr (PREC == 1) {
-    coilmap_V_bf(a, g, j, i2, lds);
-    __syncthreads();
-    coilmap_P_bf(a, g, lds, pr, pi);
-  } else {
-    coilmap_V_f32(a, g, j, i2, lds);
-    __syncthreads();
-    coilmap_P_f32(a, g, lds, pr, pi);
-  }
-  __syncthreads();
-}
-
-template <int PREC, int N0, int N1>
 __global__ __launch_bounds__(PT) void plane_fwd_kernel(PlaneArgs a) {
   __shared__ float2 lds[LDS_ELEMS];
   const Geo<N0, N1> g(a);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane0 = threadIdx.x & 63;
   const int ngrp = (a.J + a.G - 1) / a.G;
-  const int i2 = blockIdx.x / ngrp, grp = blockIdx.x % ngrp;
-  const int nbl = g.n1 / 16;
+  const int i2 = blockIdx.x / ngrp, gi = blockIdx.x % ngrp;
   const float2* xp = a.xt + (size_t)i2 * g.n0 * g.n1;
+  const Share sh = plane_share(g);
   load_twiddles(a, g, lds);
-  for (int j = grp * a.G; j < a.J && j < (grp + 1) * a.G; ++j) {
-    f32x4 pr[8], pi[8];
-    coil_map<PREC>(a, g, j, i2, lds, pr, pi);
-    // m = x (.) P with the input chessboard sign, into the padded plane
-    if (wave < g.n0 / 16) {
+  for (int j = gi * a.G; j < a.J && j < (gi + 1) * a.G; ++j) {
+    // lane through an empty asm: keeps fragment addresses from being hoisted out of the
+    // coil loop and held (spilled) across the transform
+    int lane = lane0;
+    asm volatile("" : "+v"(lane));
+    const int grp = lane >> 4, i1 = 16 * sh.cb + (lane & 15);
+    stage_w<PREC>(a, g, j, i2, lds);
+    __syncthreads();  // W staged; the previous coil's gather is done with the plane
+    if (sh.on) {
+      typename Tile<PREC>::B vb[3];
+      coil_v<PREC>(lane, a, g, lds, sh.cb, vb);
 #pragma unroll
-      for (int nb = 0; nb < 8; ++nb)
-        if (nb < nbl)
+      for (int i = 0; i < 8; ++i) {
+        const int rb = sh.part + i * sh.q;
+        if (rb < g.n0b) {
+          f32x4 pr, pi;
+          coil_p<PREC>(lane, a, g, rb, vb, pr, pi);
+          // m = x (.) P with the input chessboard sign
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int i0 = 16 * wave + 4 * (lane >> 4) + r, i1 = 16 * nb + (lane & 15);
-            float2 v = cmul(make_float2(pr[nb][r], pi[nb][r]), xp[i0 * g.n1 + i1]);
+            const int i0 = 16 * rb + 4 * grp + r;
+            float2 v = cmul(make_float2(pr[r], pi[r]), xp[i0 * g.n1 + i1]);
             if ((i0 + i1) & 1) v = make_float2(-v.x, -v.y);
             lds[i0 * g.PS + i1] = v;
           }
+        }
+      }
     }
     __syncthreads();
     plane_fft(a, g, lds, -1);
@@ -530,7 +543,6 @@ __global__ __launch_bounds__(PT) void plane_fwd_kernel(PlaneArgs a) {
       if ((k0 + k1) & 1) v = make_float2(-v.x, -v.y);
       zo[l] = v;
     }
-    __syncthreads();
   }
 }
 
@@ -538,22 +550,25 @@ template <int PREC, int N0, int N1>
 __global__ __launch_bounds__(PT) void plane_adj_kernel(PlaneArgs a) {
   __shared__ float2 lds[LDS_ELEMS];
   const Geo<N0, N1> g(a);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane0 = threadIdx.x & 63;
   const int ngrp = (a.J + a.G - 1) / a.G;
-  const int i2 = blockIdx.x / ngrp, grp = blockIdx.x % ngrp;
-  const int nbl = g.n1 / 16;
+  const int i2 = blockIdx.x / ngrp, gi = blockIdx.x % ngrp;
   const float2* xp = a.xt + (size_t)i2 * g.n0 * g.n1;
   const bool want_gx = a.gxpart != nullptr;
-  f32x4 gr[8], gi[8];
+  const Share sh = plane_share(g);
+  f32x4 gr[8], gim[8];
 #pragma unroll
-  for (int nb = 0; nb < 8; ++nb) { gr[nb] = z4(); gi[nb] = z4(); }
-  for (int j = grp * a.G; j < a.J && j < (grp + 1) * a.G; ++j) {
-    f32x4 pr[8], pi[8];
-    if (want_gx) coil_map<PREC>(a, g, j, i2, lds, pr, pi);  // B c recomputed
-    // zero-filled scatter of this plane's samples (with the chessboard sign)
-    load_twiddles(a, g, lds);
+  for (int i = 0; i < 8; ++i) { gr[i] = z4(); gim[i] = z4(); }
+  load_twiddles(a, g, lds);
+  for (int j = gi * a.G; j < a.J && j < (gi + 1) * a.G; ++j) {
+    int lane = lane0;  // opaque per coil, as in the forward kernel
+    asm volatile("" : "+v"(lane));
+    const int grp = lane >> 4, i1 = 16 * sh.cb + (lane & 15);
+    // zero-filled plane; W of this coil (B c recomputed)
     for (int e = threadIdx.x; e < g.n0 * g.PS; e += PT) lds[e] = make_float2(0.f, 0.f);
+    if (want_gx) stage_w<PREC>(a, g, j, i2, lds);
     __syncthreads();
+    // scatter of this plane's samples (with the chessboard sign)
     const float2* zi = a.Z + ((size_t)j * g.n2 + i2) * a.L;
     for (int l = threadIdx.x; l < a.L; l += PT) {
       const int q = a.pos[l];
@@ -564,43 +579,47 @@ __global__ __launch_bounds__(PT) void plane_adj_kernel(PlaneArgs a) {
     }
     __syncthreads();
     plane_fft(a, g, lds, +1);
-    // g (output chessboard sign); gx += conj(P) g; h = conj(x) g back into the plane
-    if (wave < g.n0 / 16) {
+    // g (output chessboard sign); gx += conj(P) g in registers; h = conj(x) g into the plane
+    if (sh.on) {
+      typename Tile<PREC>::B vb[3];
+      if (want_gx) coil_v<PREC>(lane, a, g, lds, sh.cb, vb);
 #pragma unroll
-      for (int nb = 0; nb < 8; ++nb)
-        if (nb < nbl)
+      for (int i = 0; i < 8; ++i) {
+        const int rb = sh.part + i * sh.q;
+        if (rb < g.n0b) {
+          f32x4 pr = z4(), pi = z4();
+          if (want_gx) coil_p<PREC>(lane, a, g, rb, vb, pr, pi);
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int i0 = 16 * wave + 4 * (lane >> 4) + r, i1 = 16 * nb + (lane & 15);
+            const int i0 = 16 * rb + 4 * grp + r;
             float2 gv = lds[i0 * g.PS + i1];
             if ((i0 + i1) & 1) gv = make_float2(-gv.x, -gv.y);
             if (want_gx) {
-              const float2 c = cmulc(make_float2(pr[nb][r], pi[nb][r]), gv);
-              gr[nb][r] += c.x;
-              gi[nb][r] += c.y;
+              const float2 c = cmulc(make_float2(pr[r], pi[r]), gv);
+              gr[i][r] += c.x;
+              gim[i][r] += c.y;
             }
             lds[i0 * g.PS + i1] = cmulc(xp[i0 * g.n1 + i1], gv);
           }
+        }
+      }
     }
     __syncthreads();
-    if (a.T3b) {
-      if constexpr (PREC == 1)
-        adjoint_W_bf(a, g, j, i2, lds);
-      else
-        adjoint_W_f32(a, g, j, i2, lds);
-    }
-    __syncthreads();
+    if (a.T3b) adjoint_w<PREC>(lane, a, g, j, i2, lds);
   }
-  if (want_gx && wave < g.n0 / 16) {
-    float2* gxp = a.gxpart + ((size_t)grp * g.n2 + i2) * g.n0 * g.n1;
+  if (want_gx && sh.on) {
+    const int grp = lane0 >> 4, i1 = 16 * sh.cb + (lane0 & 15);
+    float2* gxp = a.gxpart + ((size_t)gi * g.n2 + i2) * g.n0 * g.n1;
 #pragma unroll
-    for (int nb = 0; nb < 8; ++nb)
-      if (nb < nbl)
+    for (int i = 0; i < 8; ++i) {
+      const int rb = sh.part + i * sh.q;
+      if (rb < g.n0b)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int i0 = 16 * wave + 4 * (lane >> 4) + r, i1 = 16 * nb + (lane & 15);
-          gxp[i0 * g.n1 + i1] = make_float2(gr[nb][r], gi[nb][r]);
+          const int i0 = 16 * rb + 4 * grp + r;
+          gxp[i0 * g.n1 + i1] = make_float2(gr[i][r], gim[i][r]);
         }
+    }
   }
 }
 
@@ -827,10 +846,8 @@ hipError_t split_operand_launch(const float2* src, int rows, int cols, int64_t s
   return hipGetLastError();
 }
 
-bool fused_supported(int64_t n0, int64_t n1, int64_t n2, int64_t r0, int64_t r1, int precision) {
-  if (!(n0 % 16 == 0 && n1 % 16 == 0 && n0 <= PMAX && n1 <= PMAX && n2 <= LMAXN)) return false;
-  if (precision == 1) return r0 <= 48 && r1 <= 48;  // split operands must fit the plane region
-  return r0 <= 64 && r1 <= 64;
+bool fused_supported(int64_t n0, int64_t n1, int64_t n2, int64_t r0, int64_t r1, int) {
+  return n0 % 16 == 0 && n1 % 16 == 0 && n0 <= PMAX && n1 <= PMAX && n2 <= LMAXN && r0 <= RMAX && r1 <= RMAX;
 }
 
 }  // namespace mx
