@@ -8,8 +8,6 @@ namespace mx {
 struct PlaneArgs {
   int n0, n1, n2, r0, r1, r0p, r1p;  // r0p, r1p: ranks rounded up to 16
   int J, L, G;                       // coils, sampled lines, coils per workgroup
-  const float2* U0;                  // [n0][r0]
-  const float2* U1;                  // [n1][r1]
   const float2* T3;                  // [J][n2][r0][r1]  (core x_4 c x_3 U2)
   const float2* xt;                  // [n2][n0][n1]     image, readout axis first
   const int32_t* pos;                // [L]  k0 * n1 + k1 of each sampled line
@@ -21,11 +19,11 @@ struct PlaneArgs {
   int nrad0, nrad1;
   int rad0[12], rad1[12];
   int precision;
-  // BF16-split operand planes built at plan time (real-block form, hi / lo):
-  const unsigned short* U0A;         // [2][n0][KP0]   A operand of P = U0 V
-  const unsigned short* U1B;         // [4][n1][KP1]   B operand of V = W U1^T
-  const unsigned short* U1C;         // [4][r1p][2 n1] B operand of Y = h conj(U1)
-  const unsigned short* U0H;         // [2][r0p][2 n0] A operand of Wb = U0^H Y
+  // Factor operands in matrix-core fragment order, built at plan time (frag_operand_launch):
+  const void* U0F;                   // A of P = U0 V:        A(i0, p0) = U0[i0][p0]
+  const void* U1TF;                  // B of V = W U1^T:      B(p1, i1) = U1[i1][p1]
+  const void* U1CF;                  // B of Y = h conj(U1):  B(i1, p1) = conj(U1[i1][p1])
+  const void* U0HF;                  // A of Wb = U0^H Y:     A(p0, i0) = conj(U0[i0][p0])
 };
 
 struct LineArgs {
@@ -47,9 +45,11 @@ struct LineArgs {
 };
 
 bool fused_supported(int64_t n0, int64_t n1, int64_t n2, int64_t r0, int64_t r1, int precision);
-// Real-block split of a complex matrix (see tucker_fused.hip); returns the launch status.
-hipError_t split_operand_launch(const float2* src, int rows, int cols, int64_t sm, int64_t sk, int conj, int mode,
-                                int rows_pad, int kp, uint16_t* dst, hipStream_t st);
+// Fragment-ordered copy (see tucker_fused.hip) of O(o, k) = src[o * so + k * sk], conjugated
+// if conj, zero for o >= no or k >= nk, as an A (is_b = 0) or B (is_b = 1) operand.
+size_t frag_operand_bytes(int no, int nk, int is_b, int precision);
+hipError_t frag_operand_launch(const float2* src, int no, int nk, int64_t so, int64_t sk, int conj, int is_b,
+                               int precision, void* dst, hipStream_t st);
 hipError_t plane_fwd_launch(const PlaneArgs& a, hipStream_t st);
 hipError_t plane_adj_launch(const PlaneArgs& a, hipStream_t st);
 int line_blocks(int J, int64_t L);

@@ -45,8 +45,8 @@ struct Plan {
   bool fused = false;
   int64_t L = 0;               // sampled lines
   int32_t* d_pos = nullptr;    // [L] plane index k0 * n1 + k1 of each line
-  uint16_t* d_split = nullptr; // BF16-split factor operands (one allocation)
-  const uint16_t *U0A = nullptr, *U1B = nullptr, *U1C = nullptr, *U0H = nullptr;
+  void* d_frag = nullptr;      // fragment-ordered factor operands (one allocation)
+  const void *U0F = nullptr, *U1TF = nullptr, *U1CF = nullptr, *U0HF = nullptr;
   // dedicated core contraction kernels (Tucker basis, J <= 64)
   bool core_direct = false;
   CoreGeom cg{};

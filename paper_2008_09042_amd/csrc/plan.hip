@@ -249,7 +249,6 @@ PlaneArgs plane_args(const Plan& p, void* ws, int G) {
   a.r0 = (int)p.r[0]; a.r1 = (int)p.r[1];
   a.r0p = (a.r0 + 15) / 16 * 16; a.r1p = (a.r1 + 15) / 16 * 16;
   a.J = p.J; a.L = (int)p.L; a.G = G;
-  a.U0 = p.U[0]; a.U1 = p.U[1];
   a.T3 = wsp<float2>(ws, p.off_T3);
   a.xt = wsp<float2>(ws, p.off_xt);
   a.pos = p.d_pos;
@@ -258,10 +257,10 @@ PlaneArgs plane_args(const Plan& p, void* ws, int G) {
   a.nrad0 = p.nrad[0]; a.nrad1 = p.nrad[1];
   for (int q = 0; q < 12; ++q) { a.rad0[q] = p.radix[0][q]; a.rad1[q] = p.radix[1][q]; }
   a.precision = p.precision;
-  a.U0A = p.U0A;
-  a.U1B = p.U1B;
-  a.U1C = p.U1C;
-  a.U0H = p.U0H;
+  a.U0F = p.U0F;
+  a.U1TF = p.U1TF;
+  a.U1CF = p.U1CF;
+  a.U0HF = p.U0HF;
   return a;
 }
 
@@ -420,29 +419,22 @@ maxwell_status plan_build(Plan& p, const maxwell_plan_desc& d, const maxwell_bas
     if ((e = hipMalloc(&p.d_pos, pos.size() * sizeof(int32_t))) != hipSuccess) return hip_err(e);
     if ((e = hipMemcpy(p.d_pos, pos.data(), pos.size() * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess)
       return hip_err(e);
-    if (p.precision == MAXWELL_BF16_SPLIT) {
-      // real-block BF16 hi/lo copies of the factor operands of the plane kernels
-      const int n0 = (int)p.n[0], n1 = (int)p.n[1], r0 = (int)p.r[0], r1 = (int)p.r[1];
-      const int r0p = (r0 + 15) / 16 * 16, r1p = (r1 + 15) / 16 * 16;
-      const int KP0 = (2 * r0 + 31) / 32 * 32, KP1 = (2 * r1 + 31) / 32 * 32;
-      const size_t nU0A = 2 * (size_t)n0 * KP0, nU1B = 4 * (size_t)n1 * KP1;
-      const size_t nU1C = 4 * (size_t)r1p * 2 * n1, nU0H = 2 * (size_t)r0p * 2 * n0;
-      if ((e = hipMalloc(&p.d_split, (nU0A + nU1B + nU1C + nU0H) * sizeof(uint16_t))) != hipSuccess)
-        return hip_err(e);
-      uint16_t* q = p.d_split;
-      p.U0A = q; q += nU0A;
-      p.U1B = q; q += nU1B;
-      p.U1C = q; q += nU1C;
-      p.U0H = q;
-      // U0A: A(i0, p0) = U0[i0][p0];  U1B: B(p1, i1) = U1[i1][p1];
-      // U1C: B(i1, p1) = conj(U1[i1][p1]);  U0H: A(p0, i0) = conj(U0[i0][p0])
-      if ((e = split_operand_launch(p.U[0], n0, r0, r0, 1, 0, 0, n0, KP0, const_cast<uint16_t*>(p.U0A), 0)) ||
-          (e = split_operand_launch(p.U[1], n1, r1, r1, 1, 0, 1, n1, KP1, const_cast<uint16_t*>(p.U1B), 0)) ||
-          (e = split_operand_launch(p.U[1], r1, n1, 1, r1, 1, 1, r1p, 2 * n1, const_cast<uint16_t*>(p.U1C), 0)) ||
-          (e = split_operand_launch(p.U[0], r0, n0, 1, r0, 1, 0, r0p, 2 * n0, const_cast<uint16_t*>(p.U0H), 0)))
-        return hip_err(e);
-      if ((e = hipStreamSynchronize(0)) != hipSuccess) return hip_err(e);
-    }
+    // factor operands of the plane kernels in fragment order
+    const int n0 = (int)p.n[0], n1 = (int)p.n[1], r0 = (int)p.r[0], r1 = (int)p.r[1], pr = p.precision;
+    const size_t bU0F = frag_operand_bytes(n0, r0, 0, pr), bU1TF = frag_operand_bytes(n1, r1, 1, pr);
+    const size_t bU1CF = frag_operand_bytes(r1, n1, 1, pr), bU0HF = frag_operand_bytes(r0, n0, 0, pr);
+    if ((e = hipMalloc(&p.d_frag, bU0F + bU1TF + bU1CF + bU0HF)) != hipSuccess) return hip_err(e);
+    char* q = reinterpret_cast<char*>(p.d_frag);
+    p.U0F = q; q += bU0F;
+    p.U1TF = q; q += bU1TF;
+    p.U1CF = q; q += bU1CF;
+    p.U0HF = q;
+    if ((e = frag_operand_launch(p.U[0], n0, r0, r0, 1, 0, 0, pr, const_cast<void*>(p.U0F), 0)) ||
+        (e = frag_operand_launch(p.U[1], n1, r1, r1, 1, 0, 1, pr, const_cast<void*>(p.U1TF), 0)) ||
+        (e = frag_operand_launch(p.U[1], r1, n1, 1, r1, 1, 1, pr, const_cast<void*>(p.U1CF), 0)) ||
+        (e = frag_operand_launch(p.U[0], r0, n0, 1, r0, 1, 0, pr, const_cast<void*>(p.U0HF), 0)))
+      return hip_err(e);
+    if ((e = hipStreamSynchronize(0)) != hipSuccess) return hip_err(e);
   }
   if (p.basis_kind == MAXWELL_BASIS_TUCKER && core_supported(p.J)) {
     p.core_direct = true;
@@ -559,8 +551,8 @@ void plan_release(Plan& p) {
   if (p.d_inv) (void)hipFree(p.d_inv);
   if (p.d_w) (void)hipFree(p.d_w);
   if (p.d_pos) (void)hipFree(p.d_pos);
-  if (p.d_split) (void)hipFree(p.d_split);
-  p.d_split = nullptr;
+  if (p.d_frag) (void)hipFree(p.d_frag);
+  p.d_frag = nullptr;
   if (p.d_core_split) (void)hipFree(p.d_core_split);
   p.d_core_split = nullptr;
   p.d_mask = nullptr;

@@ -47,12 +47,11 @@ constexpr int PMAX = 128;                        // max n0, n1 on this path
 constexpr int RMAX = 48;                         // max r0, r1 on this path (three K16 blocks)
 constexpr int PLANE_ELEMS = PMAX * (PMAX + 1);   // padded plane: 16,512 complex = 132 KB
 constexpr int TW_OFF = PLANE_ELEMS;              // twiddles of n0 and n1 (2 x PMAX)
-constexpr int WS_OFF = TW_OFF + 2 * PMAX;        // the current coil's W (A operand of V = W U1^T)
-constexpr int KSW = 2 * RMAX + 8;                // staged BF16 W row: 2 r1 real values + pad
-constexpr int WS_ELEMS = 2 * RMAX * KSW / 4;     // BF16 hi + lo planes, in complex slots
-static_assert(RMAX * (RMAX + 1) <= WS_ELEMS, "FP32 W must fit the staging region");
-constexpr int LDS_ELEMS = WS_OFF + WS_ELEMS;
+constexpr int STAGE_OFF = TW_OFF + 2 * PMAX;     // W of the current coil, or two K16 steps of conj(U1)
+constexpr int STAGE_ELEMS = 3072;                // 24 KB
+constexpr int LDS_ELEMS = STAGE_OFF + STAGE_ELEMS;
 constexpr int FFT_CHUNK = PMAX * PMAX / 2;       // elements per register chunk of a pass
+constexpr int SCAT = 4;                          // samples per thread loaded ahead of the scatter
 
 __device__ __forceinline__ f32x4 z4() { return f32x4{0.f, 0.f, 0.f, 0.f}; }
 
@@ -124,7 +123,7 @@ __device__ __forceinline__ void store_bop(unsigned short* brh, unsigned short* b
 // or column l % 16, group g = l / 16) holds the operand values of k = 4 g + t, t < 4,
 // and an accumulator tile holds D[4 g + r][l % 16].  A result tile is therefore, as it
 // stands, the lane's B operand of one K16 block of a following product whose reduction
-// runs over the result's rows: no LDS round trip between chained products.
+// runs over the result's rows.
 template <int PREC>
 struct Tile;
 
@@ -157,13 +156,6 @@ struct Tile<1> {  // BF16 split in the real-block form (file header)
     split8(fi, b.ih, b.il);
     return b;
   }
-  // fragments of operands split at plan time: planes of `plane` entries, offset o
-  static __device__ __forceinline__ A load_a(const unsigned short* p, size_t plane, size_t o) {
-    return A{ld8(p + o), ld8(p + plane + o)};
-  }
-  static __device__ __forceinline__ B load_b(const unsigned short* p, size_t plane, size_t o) {
-    return B{ld8(p + o), ld8(p + plane + o), ld8(p + 2 * plane + o), ld8(p + 3 * plane + o)};
-  }
   static __device__ __forceinline__ void mma(f32x4& cr, f32x4& ci, const A& a, const B& b) {
     mfma6(cr, ci, a.h, a.l, b.rh, b.rl, b.ih, b.il);
   }
@@ -181,22 +173,98 @@ struct Tile<0> {  // FP32: four real products per complex product; sub-step t us
   }
 };
 
+// ---------------------------------------------------------------- fragment order
+// An operand O(o, k) (o: tile row of an A operand or tile column of a B operand, k: the
+// reduction index) is kept in fragment order: one (o block, K16 step) fragment is the 64
+// lanes' operand registers, stored lane-contiguously, so a wave loads it as one contiguous
+// 1 KiB run per array and a fragment store from registers is conflict-free in LDS.
+//   A type: [o block][step][hi, lo][lane][8 bf16]             FP32: [o block][step][lane][4 complex]
+//   B type: [step][br hi, br lo, bi hi, bi lo][o block][lane][8 bf16]
+//                                                             FP32: [step][o block][lane][4 complex]
+// One K16 step of a B operand is one contiguous block (it is staged through LDS whole).
+constexpr int FRAG_U16 = 512;  // bf16 entries of one array of one fragment
+
 template <int PREC>
-__device__ __forceinline__ typename Tile<PREC>::B tile_as_b(const f32x4& cr, const f32x4& ci) {
+__device__ __forceinline__ typename Tile<PREC>::A frag_a(const void* base, int ks, int ob, int s, int lane) {
+  const size_t f = (size_t)ob * ks + s;
+  if constexpr (PREC == 1) {
+    const unsigned short* p = reinterpret_cast<const unsigned short*>(base) + f * 2 * FRAG_U16 + lane * 8;
+    return typename Tile<1>::A{ld8(p), ld8(p + FRAG_U16)};
+  } else {
+    const float4* p = reinterpret_cast<const float4*>(base) + (f * 64 + lane) * 2;
+    const float4 u = p[0], w = p[1];
+    return typename Tile<0>::A{{make_float2(u.x, u.y), make_float2(u.z, u.w), make_float2(w.x, w.y),
+                                make_float2(w.z, w.w)}};
+  }
+}
+
+template <int PREC>
+__device__ __forceinline__ typename Tile<PREC>::B frag_b(const void* base, int obs, int ob, int s, int lane) {
+  if constexpr (PREC == 1) {
+    const size_t arr = (size_t)obs * FRAG_U16;
+    const unsigned short* p =
+        reinterpret_cast<const unsigned short*>(base) + (size_t)s * 4 * arr + (size_t)ob * FRAG_U16 + lane * 8;
+    return typename Tile<1>::B{ld8(p), ld8(p + arr), ld8(p + 2 * arr), ld8(p + 3 * arr)};
+  } else {
+    const float4* p = reinterpret_cast<const float4*>(base) + (((size_t)s * obs + ob) * 64 + lane) * 2;
+    const float4 u = p[0], w = p[1];
+    return typename Tile<0>::B{{make_float2(u.x, u.y), make_float2(u.z, u.w), make_float2(w.x, w.y),
+                                make_float2(w.z, w.w)}};
+  }
+}
+
+// Store a fragment built from four complex values per lane.
+template <int PREC>
+__device__ __forceinline__ void put_frag_a(void* base, int ks, int ob, int s, int lane, const float2 (&v)[4]) {
+  const size_t f = (size_t)ob * ks + s;
+  if constexpr (PREC == 1) {
+    const typename Tile<1>::A a = Tile<1>::make_a(v);
+    unsigned short* p = reinterpret_cast<unsigned short*>(base) + f * 2 * FRAG_U16 + lane * 8;
+    st8(p, a.h);
+    st8(p + FRAG_U16, a.l);
+  } else {
+    float4* p = reinterpret_cast<float4*>(base) + (f * 64 + lane) * 2;
+    p[0] = make_float4(v[0].x, v[0].y, v[1].x, v[1].y);
+    p[1] = make_float4(v[2].x, v[2].y, v[3].x, v[3].y);
+  }
+}
+
+template <int PREC>
+__device__ __forceinline__ void put_frag_b(void* base, int obs, int ob, int s, int lane, const float2 (&v)[4]) {
+  if constexpr (PREC == 1) {
+    const typename Tile<1>::B b = Tile<1>::make_b(v);
+    const size_t arr = (size_t)obs * FRAG_U16;
+    unsigned short* p = reinterpret_cast<unsigned short*>(base) + (size_t)s * 4 * arr + (size_t)ob * FRAG_U16 + lane * 8;
+    st8(p, b.rh);
+    st8(p + arr, b.rl);
+    st8(p + 2 * arr, b.ih);
+    st8(p + 3 * arr, b.il);
+  } else {
+    float4* p = reinterpret_cast<float4*>(base) + (((size_t)s * obs + ob) * 64 + lane) * 2;
+    p[0] = make_float4(v[0].x, v[0].y, v[1].x, v[1].y);
+    p[1] = make_float4(v[2].x, v[2].y, v[3].x, v[3].y);
+  }
+}
+
+// An accumulator tile as the B fragment of step s (its rows become the reduction index).
+template <int PREC>
+__device__ __forceinline__ void put_tile_b(void* base, int obs, int ob, int s, int lane, const f32x4& cr,
+                                           const f32x4& ci) {
   float2 v[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) v[t] = make_float2(cr[t], ci[t]);
-  return Tile<PREC>::make_b(v);
+  put_frag_b<PREC>(base, obs, ob, s, lane, v);
 }
 
-__device__ __forceinline__ int kpad(int r) { return (2 * r + 31) / 32 * 32; }
+// Bytes of one K16 step of a B-type operand with obs o blocks.
+template <int PREC>
+__host__ __device__ constexpr int frag_b_step_bytes(int obs) { return obs * (PREC == 1 ? 4 * 1024 : 2048); }
 
 // ---------------------------------------------------------------- plane geometry
 template <int N0, int N1>
 struct Geo {
   int n0, n1, n2, r0, r1, PS;
   int n0b, n1b, r0b, r1b;  // 16-blocks of each extent
-  int KP0, KP1;            // BF16 real-block reduction lengths of r0, r1
   __device__ Geo(const PlaneArgs& a) {
     n0 = N0 ? N0 : a.n0;
     n1 = N1 ? N1 : a.n1;
@@ -208,15 +276,13 @@ struct Geo {
     n1b = n1 / 16;
     r0b = a.r0p / 16;
     r1b = a.r1p / 16;
-    KP0 = kpad(r0);
-    KP1 = kpad(r1);
   }
 };
 
-// The wave's share of the plane in the coil-map and pointwise phases: column block cb
-// and row blocks part, part + q, ...  Every (row block, column block) tile has one owner.
+// The wave's share of the plane: row block rb and column blocks part, part + q, ...
+// (every (row block, column block) tile has exactly one owner).
 struct Share {
-  int cb, part, q;
+  int rb, part, q;
   bool on;
 };
 
@@ -224,9 +290,9 @@ template <int N0, int N1>
 __device__ __forceinline__ Share plane_share(const Geo<N0, N1>& g) {
   const int wave = threadIdx.x >> 6;
   Share s;
-  s.q = NWAVE / g.n1b;
-  s.cb = wave % g.n1b;
-  s.part = wave / g.n1b;
+  s.q = NWAVE / g.n0b;
+  s.rb = wave % g.n0b;
+  s.part = wave / g.n0b;
   s.on = s.part < s.q;
   return s;
 }
@@ -265,226 +331,162 @@ __device__ __forceinline__ void plane_fft(const PlaneArgs& a, const Geo<N0, N1>&
   if (dir < 0) { rows(); cols(); } else { cols(); rows(); }
 }
 
-// ---------------------------------------------------------------- operand fragments
-// W = T3[j][i2] (r0 x r1, zero-padded to whole blocks) into the staging region.
-template <int PREC, int N0, int N1>
-__device__ __forceinline__ void stage_w(const PlaneArgs& a, const Geo<N0, N1>& g, int j, int i2, float2* lds) {
-  const float2* src = a.T3 + ((size_t)j * g.n2 + i2) * g.r0 * g.r1;
-  if constexpr (PREC == 1) {
-    unsigned short* wh = reinterpret_cast<unsigned short*>(lds + WS_OFF);
-    unsigned short* wl = wh + RMAX * KSW;
-    const float* f = reinterpret_cast<const float*>(src);
-    const int ch = g.KP1 / 8;
-    for (int e = threadIdx.x; e < 16 * g.r0b * ch; e += PT) {
-      const int p0 = e / ch, c8 = (e % ch) * 8;
-      float v[8];
-#pragma unroll
-      for (int t = 0; t < 8; ++t) v[t] = (p0 < g.r0 && c8 + t < 2 * g.r1) ? f[(size_t)p0 * 2 * g.r1 + c8 + t] : 0.f;
-      u16x8 h, l;
-      split8(v, h, l);
-      st8(wh + p0 * KSW + c8, h);
-      st8(wl + p0 * KSW + c8, l);
-    }
-  } else {
-    float2* w = lds + WS_OFF;
-    const int rp = 16 * g.r1b;
-    for (int e = threadIdx.x; e < 16 * g.r0b * rp; e += PT) {
-      const int p0 = e / rp, p1 = e % rp;
-      w[p0 * (RMAX + 1) + p1] = (p0 < g.r0 && p1 < g.r1) ? src[(size_t)p0 * g.r1 + p1] : make_float2(0.f, 0.f);
-    }
-  }
-}
-
-// A fragment of W: rows p0 of block mb, K16 block s over p1.
-template <int PREC, int N0, int N1>
-__device__ __forceinline__ typename Tile<PREC>::A frag_w(int lane, const Geo<N0, N1>&, const float2* lds, int mb, int s) {
-  const int row = 16 * mb + (lane & 15), grp = lane >> 4;
-  if constexpr (PREC == 1) {
-    const unsigned short* wh = reinterpret_cast<const unsigned short*>(lds + WS_OFF);
-    const int o = row * KSW + 32 * s + 8 * grp;
-    return typename Tile<1>::A{ld8(wh + o), ld8(wh + RMAX * KSW + o)};
-  } else {
-    float2 v[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) v[t] = lds[WS_OFF + row * (RMAX + 1) + 16 * s + 4 * grp + t];
-    return Tile<0>::make_a(v);
-  }
-}
-
-// B fragment of U1^T: K16 block s over p1, column block cb over i1.
-template <int PREC, int N0, int N1>
-__device__ __forceinline__ typename Tile<PREC>::B frag_u1t(int lane, const PlaneArgs& a, const Geo<N0, N1>& g, int s, int cb) {
-  const int grp = lane >> 4, i1 = 16 * cb + (lane & 15);
-  if constexpr (PREC == 1) {
-    return Tile<1>::load_b(a.U1B, (size_t)g.n1 * g.KP1, (size_t)i1 * g.KP1 + 32 * s + 8 * grp);
-  } else {
-    float2 v[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int p1 = 16 * s + 4 * grp + t;
-      v[t] = p1 < g.r1 ? a.U1[(size_t)i1 * g.r1 + p1] : make_float2(0.f, 0.f);
-    }
-    return Tile<0>::make_b(v);
-  }
-}
-
-// A fragment of U0: row block rb over i0, K16 block s over p0.
-template <int PREC, int N0, int N1>
-__device__ __forceinline__ typename Tile<PREC>::A frag_u0(int lane, const PlaneArgs& a, const Geo<N0, N1>& g, int rb, int s) {
-  const int grp = lane >> 4, i0 = 16 * rb + (lane & 15);
-  if constexpr (PREC == 1) {
-    return Tile<1>::load_a(a.U0A, (size_t)g.n0 * g.KP0, (size_t)i0 * g.KP0 + 32 * s + 8 * grp);
-  } else {
-    float2 v[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int p0 = 16 * s + 4 * grp + t;
-      v[t] = p0 < g.r0 ? a.U0[(size_t)i0 * g.r0 + p0] : make_float2(0.f, 0.f);
-    }
-    return Tile<0>::make_a(v);
-  }
-}
-
-// B fragment of conj(U1): K16 block s over i1, column block nb over p1.
-template <int PREC, int N0, int N1>
-__device__ __forceinline__ typename Tile<PREC>::B frag_u1c(int lane, const PlaneArgs& a, const Geo<N0, N1>& g, int s, int nb) {
-  const int grp = lane >> 4, p1 = 16 * nb + (lane & 15);
-  if constexpr (PREC == 1) {
-    return Tile<1>::load_b(a.U1C, (size_t)16 * g.r1b * 2 * g.n1, (size_t)p1 * 2 * g.n1 + 32 * s + 8 * grp);
-  } else {
-    float2 v[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int i1 = 16 * s + 4 * grp + t;
-      v[t] = p1 < g.r1 ? cconj(a.U1[(size_t)i1 * g.r1 + p1]) : make_float2(0.f, 0.f);
-    }
-    return Tile<0>::make_b(v);
-  }
-}
-
-// A fragment of U0^H: row block mb over p0, K16 block s over i0.
-template <int PREC, int N0, int N1>
-__device__ __forceinline__ typename Tile<PREC>::A frag_u0h(int lane, const PlaneArgs& a, const Geo<N0, N1>& g, int mb, int s) {
-  const int grp = lane >> 4, p0 = 16 * mb + (lane & 15);
-  if constexpr (PREC == 1) {
-    return Tile<1>::load_a(a.U0H, (size_t)16 * g.r0b * 2 * g.n0, (size_t)p0 * 2 * g.n0 + 32 * s + 8 * grp);
-  } else {
-    float2 v[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int i0 = 16 * s + 4 * grp + t;
-      v[t] = p0 < g.r0 ? cconj(a.U0[(size_t)i0 * g.r0 + p0]) : make_float2(0.f, 0.f);
-    }
-    return Tile<0>::make_a(v);
-  }
-}
-
-// Y (copy q of the partial sums over i1) in the plane region, as the B operand of Wb.
-template <int PREC, int N0, int N1>
-__device__ __forceinline__ void y_store(int lane, const Geo<N0, N1>& g, float2* lds, int q, int yb, int nb, const f32x4& cr,
-                                        const f32x4& ci) {
-  const int grp = lane >> 4;
-  if constexpr (PREC == 1) {
-    const int KS = 2 * g.n0 + 8, R1P = 16 * g.r1b;
-    unsigned short* base = reinterpret_cast<unsigned short*>(lds) + (size_t)q * 4 * R1P * KS;
-    store_bop(base, base + R1P * KS, base + 2 * R1P * KS, base + 3 * R1P * KS, KS, 16 * nb + (lane & 15),
-              2 * (16 * yb + 4 * grp), cr, ci);
-  } else {
-    const int YS = 16 * g.r1b + 1;
-    float2* base = lds + (size_t)q * g.n0 * YS;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) base[(16 * yb + 4 * grp + r) * YS + 16 * nb + (lane & 15)] = make_float2(cr[r], ci[r]);
-  }
-}
-
-template <int PREC, int N0, int N1>
-__device__ __forceinline__ typename Tile<PREC>::B frag_y(int lane, const Geo<N0, N1>& g, const float2* lds, int q, int s, int nb) {
-  const int grp = lane >> 4;
-  if constexpr (PREC == 1) {
-    const int KS = 2 * g.n0 + 8, R1P = 16 * g.r1b;
-    const unsigned short* base = reinterpret_cast<const unsigned short*>(lds) + (size_t)q * 4 * R1P * KS;
-    return Tile<1>::load_b(base, (size_t)R1P * KS, (size_t)(16 * nb + (lane & 15)) * KS + 32 * s + 8 * grp);
-  } else {
-    const int YS = 16 * g.r1b + 1;
-    const float2* base = lds + (size_t)q * g.n0 * YS;
-    float2 v[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) v[t] = base[(16 * s + 4 * grp + t) * YS + 16 * nb + (lane & 15)];
-    return Tile<0>::make_b(v);
-  }
-}
-
 // ---------------------------------------------------------------- coil map
-// V = W U1^T for column block cb, kept as the B operands of P = U0 V (one per K16
-// block over p0).  W must be staged.
+// W = T3[j][i2] (r0 x r1) as the A operand of V = W U1^T: each thread gathers the values
+// of at most two fragment lanes into registers (issued early), then stores them split.
+struct WPrefetch {
+  float2 v[2][4];
+};
+
+template <int N0, int N1>
+__device__ __forceinline__ void w_load(const PlaneArgs& a, const Geo<N0, N1>& g, int j, int i2, int tid,
+                                       WPrefetch& w) {
+  const float2* src = a.T3 + ((size_t)j * g.n2 + i2) * g.r0 * g.r1;
+  const int nfl = g.r0b * g.r1b * 64;  // (o block, step, lane) entries
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int e = tid + q * PT;
+    const int f = e / 64, lane = e % 64;
+    const int mb = f / g.r1b, s = f % g.r1b;
+    const int p0 = 16 * mb + (lane & 15);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int p1 = 16 * s + 4 * (lane >> 4) + t;
+      w.v[q][t] = (e < nfl && p0 < g.r0 && p1 < g.r1) ? src[(size_t)p0 * g.r1 + p1] : make_float2(0.f, 0.f);
+    }
+  }
+}
+
 template <int PREC, int N0, int N1>
-__device__ __forceinline__ void coil_v(int lane, const PlaneArgs& a, const Geo<N0, N1>& g, const float2* lds, int cb,
-                                       typename Tile<PREC>::B (&vb)[3]) {
+__device__ __forceinline__ void w_store(const Geo<N0, N1>& g, float2* lds, int tid, const WPrefetch& w) {
+  const int nfl = g.r0b * g.r1b * 64;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int e = tid + q * PT;
+    if (e < nfl) {
+      const int f = e / 64, lane = e % 64;
+      put_frag_a<PREC>(lds + STAGE_OFF, g.r1b, f / g.r1b, f % g.r1b, lane, w.v[q]);
+    }
+  }
+}
+
+// V = W U1^T (W staged) for column block cb = wave, stored as the B operand of P = U0 V
+// (steps over p0, o blocks over i1) in the plane region.
+template <int PREC, int N0, int N1>
+__device__ __forceinline__ void coil_v(const PlaneArgs& a, const Geo<N0, N1>& g, float2* lds, int lane) {
+  const int cb = threadIdx.x >> 6;
+  if (cb >= g.n1b) return;
   f32x4 cr[3], ci[3];
 #pragma unroll
   for (int m = 0; m < 3; ++m) { cr[m] = z4(); ci[m] = z4(); }
 #pragma unroll
   for (int s = 0; s < 3; ++s)
     if (s < g.r1b) {
-      const typename Tile<PREC>::B b = frag_u1t<PREC>(lane, a, g, s, cb);
+      const typename Tile<PREC>::B b = frag_b<PREC>(a.U1TF, g.n1b, cb, s, lane);
 #pragma unroll
       for (int m = 0; m < 3; ++m)
-        if (m < g.r0b) Tile<PREC>::mma(cr[m], ci[m], frag_w<PREC>(lane, g, lds, m, s), b);
+        if (m < g.r0b) Tile<PREC>::mma(cr[m], ci[m], frag_a<PREC>(lds + STAGE_OFF, g.r1b, m, s, lane), b);
     }
 #pragma unroll
-  for (int m = 0; m < 3; ++m) vb[m] = tile_as_b<PREC>(cr[m], ci[m]);
+  for (int m = 0; m < 3; ++m)
+    if (m < g.r0b) put_tile_b<PREC>(lds, g.n1b, cb, m, lane, cr[m], ci[m]);
 }
 
-// P tile (rb, cb) = U0 V: lane holds P[16 rb + 4 g + r][16 cb + l % 16].
+// P tiles of the wave's share: P[rb][cb] = sum_s U0[rb][s] V[s][cb] (V staged).
 template <int PREC, int N0, int N1>
-__device__ __forceinline__ void coil_p(int lane, const PlaneArgs& a, const Geo<N0, N1>& g, int rb,
-                                       const typename Tile<PREC>::B (&vb)[3], f32x4& pr, f32x4& pi) {
-  pr = z4();
-  pi = z4();
+__device__ __forceinline__ void coil_p(const Geo<N0, N1>& g, const float2* lds, const Share& sh, int lane,
+                                       const typename Tile<PREC>::A (&u0)[3], f32x4 (&pr)[8], f32x4 (&pi)[8]) {
 #pragma unroll
-  for (int s = 0; s < 3; ++s)
-    if (s < g.r0b) Tile<PREC>::mma(pr, pi, frag_u0<PREC>(lane, a, g, rb, s), vb[s]);
+  for (int i = 0; i < 8; ++i) {
+    pr[i] = z4();
+    pi[i] = z4();
+    const int cb = sh.part + i * sh.q;
+    if (sh.on && cb < g.n1b) {
+#pragma unroll
+      for (int s = 0; s < 3; ++s)
+        if (s < g.r0b) Tile<PREC>::mma(pr[i], pi[i], u0[s], frag_b<PREC>(lds, g.n1b, cb, s, lane));
+    }
+  }
 }
 
 // ---------------------------------------------------------------- adjoint contraction
 // Y = h conj(U1) with h in the plane, then Wb = U0^H Y -> T3b[j][i2].  Wave w takes Y row
-// block w % n0b over a 1 / q share of the i1 blocks; the q partial copies of Y are stored
-// side by side and Wb sums over them as extra reduction blocks.  Ends synchronised.
+// block w % n0b over a 1 / q share of the K16 steps over i1; the q partial copies of Y
+// are stored side by side as extra reduction steps of Wb.  conj(U1) is staged through
+// LDS one K16 step at a time from registers loaded at the start.  Ends synchronised.
+constexpr int YPF = 12;  // 16-byte pieces of conj(U1) per thread (n1b * r1b / 2 in BF16)
+
 template <int PREC, int N0, int N1>
-__device__ __forceinline__ void adjoint_w(int lane, const PlaneArgs& a, const Geo<N0, N1>& g, int j, int i2, float2* lds) {
+__device__ __forceinline__ void adjoint_w(const PlaneArgs& a, const Geo<N0, N1>& g, int j, int i2, float2* lds,
+                                          int lane, int tid) {
   const int wave = threadIdx.x >> 6, grp = lane >> 4;
   const int qy = NWAVE / g.n0b, yb = wave % g.n0b, kq = wave / g.n0b;
   const bool on = kq < qy;
+  const int step_pieces = frag_b_step_bytes<PREC>(g.r1b) / 16;
+  const int total = step_pieces * g.n1b;
+  const float4* src = reinterpret_cast<const float4*>(a.U1CF);
+  float4 pf[YPF];
+#pragma unroll
+  for (int k = 0; k < YPF; ++k) {
+    const int e = tid + k * PT;
+    if (e < total) pf[k] = src[e];
+  }
+  float4* stage = reinterpret_cast<float4*>(lds + STAGE_OFF);
+  auto put_step = [&](int s) {
+    const int lo = s * step_pieces, hi = lo + step_pieces;
+#pragma unroll
+    for (int k = 0; k < YPF; ++k) {
+      const int e = tid + k * PT;
+      if (e >= lo && e < hi && e < total) stage[(s & 1) * step_pieces + (e - lo)] = pf[k];
+    }
+  };
   f32x4 yr[3], yi[3];
 #pragma unroll
   for (int nb = 0; nb < 3; ++nb) { yr[nb] = z4(); yi[nb] = z4(); }
-  if (on) {
-    const int i0 = 16 * yb + (lane & 15);
-    for (int s = kq; s < g.n1b; s += qy) {
+  put_step(0);
+  __syncthreads();
+  const int i0 = 16 * yb + (lane & 15);
+  for (int s = 0; s < g.n1b; ++s) {
+    if (s + 1 < g.n1b) put_step(s + 1);
+    if (on && (s % qy) == kq) {
       float2 hv[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) hv[t] = lds[i0 * g.PS + 16 * s + 4 * grp + t];
       const typename Tile<PREC>::A av = Tile<PREC>::make_a(hv);
+      const float4* buf = stage + (s & 1) * step_pieces;
 #pragma unroll
       for (int nb = 0; nb < 3; ++nb)
-        if (nb < g.r1b) Tile<PREC>::mma(yr[nb], yi[nb], av, frag_u1c<PREC>(lane, a, g, s, nb));
+        if (nb < g.r1b) Tile<PREC>::mma(yr[nb], yi[nb], av, frag_b<PREC>(buf, g.r1b, nb, 0, lane));
     }
+    __syncthreads();
   }
-  __syncthreads();  // h is consumed; Y takes its place
+  // the first Wb tile's U0^H fragments, in flight across the Y store
+  const int mb0 = wave / g.r1b;
+  typename Tile<PREC>::A ua[8];
+  if (wave < g.r0b * g.r1b) {
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+      if (s < g.n0b) ua[s] = frag_a<PREC>(a.U0HF, g.n0b, mb0, s, lane);
+  }
   if (on) {
 #pragma unroll
     for (int nb = 0; nb < 3; ++nb)
-      if (nb < g.r1b) y_store<PREC>(lane, g, lds, kq, yb, nb, yr[nb], yi[nb]);
+      if (nb < g.r1b) put_tile_b<PREC>(lds, g.r1b, nb, kq * g.n0b + yb, lane, yr[nb], yi[nb]);
   }
   __syncthreads();
   float2* wo = a.T3b + ((size_t)j * g.n2 + i2) * g.r0 * g.r1;
   for (int blk = wave; blk < g.r0b * g.r1b; blk += NWAVE) {
     const int mb = blk / g.r1b, nb = blk % g.r1b;
-    f32x4 cr = z4(), ci = z4();
-    for (int s = 0; s < g.n0b; ++s) {
-      const typename Tile<PREC>::A av = frag_u0h<PREC>(lane, a, g, mb, s);
-      for (int q = 0; q < qy; ++q) Tile<PREC>::mma(cr, ci, av, frag_y<PREC>(lane, g, lds, q, s, nb));
+    if (blk != wave) {
+#pragma unroll
+      for (int s = 0; s < 8; ++s)
+        if (s < g.n0b) ua[s] = frag_a<PREC>(a.U0HF, g.n0b, mb, s, lane);
     }
+    f32x4 cr = z4(), ci = z4();
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+      if (s < g.n0b)
+        for (int q = 0; q < qy; ++q) Tile<PREC>::mma(cr, ci, ua[s], frag_b<PREC>(lds, g.r1b, nb, q * g.n0b + s, lane));
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int q0 = 16 * mb + 4 * grp + r, q1 = 16 * nb + (lane & 15);
@@ -495,38 +497,53 @@ __device__ __forceinline__ void adjoint_w(int lane, const PlaneArgs& a, const Ge
 }
 
 // ---------------------------------------------------------------- plane kernels
+// Per coil: W (and in the adjoint the coil's samples) loaded early, W staged, V = W U1^T
+// into the plane region, then the wave's P tiles into registers.
+template <int PREC, int N0, int N1>
+__device__ __forceinline__ void coil_map(const PlaneArgs& a, const Geo<N0, N1>& g, float2* lds, const Share& sh,
+                                         int lane, int tid, const WPrefetch& w, f32x4 (&pr)[8], f32x4 (&pi)[8]) {
+  typename Tile<PREC>::A u0[3];  // the wave's U0 row block, in flight across the W store
+#pragma unroll
+  for (int s = 0; s < 3; ++s)
+    if (s < g.r0b) u0[s] = frag_a<PREC>(a.U0F, g.r0b, sh.rb, s, lane);
+  w_store<PREC>(g, lds, tid, w);
+  __syncthreads();
+  coil_v<PREC>(a, g, lds, lane);
+  __syncthreads();
+  coil_p<PREC>(g, lds, sh, lane, u0, pr, pi);
+  __syncthreads();  // V is consumed; the plane region is free
+}
+
 template <int PREC, int N0, int N1>
 __global__ __launch_bounds__(PT) void plane_fwd_kernel(PlaneArgs a) {
   __shared__ float2 lds[LDS_ELEMS];
   const Geo<N0, N1> g(a);
-  const int lane0 = threadIdx.x & 63;
   const int ngrp = (a.J + a.G - 1) / a.G;
   const int i2 = blockIdx.x / ngrp, gi = blockIdx.x % ngrp;
   const float2* xp = a.xt + (size_t)i2 * g.n0 * g.n1;
   const Share sh = plane_share(g);
   load_twiddles(a, g, lds);
   for (int j = gi * a.G; j < a.J && j < (gi + 1) * a.G; ++j) {
-    // lane through an empty asm: keeps fragment addresses from being hoisted out of the
-    // coil loop and held (spilled) across the transform
-    int lane = lane0;
-    asm volatile("" : "+v"(lane));
-    const int grp = lane >> 4, i1 = 16 * sh.cb + (lane & 15);
-    stage_w<PREC>(a, g, j, i2, lds);
-    __syncthreads();  // W staged; the previous coil's gather is done with the plane
+    // lane and thread index through an empty asm: per-coil addresses are recomputed
+    // here rather than hoisted out of the coil loop and held across the transform
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int lane = tid & 63, grp = lane >> 4;
+    WPrefetch w;
+    w_load(a, g, j, i2, tid, w);
+    f32x4 pr[8], pi[8];
+    coil_map<PREC>(a, g, lds, sh, lane, tid, w, pr, pi);
+    // m = x (.) P with the input chessboard sign
     if (sh.on) {
-      typename Tile<PREC>::B vb[3];
-      coil_v<PREC>(lane, a, g, lds, sh.cb, vb);
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
-        const int rb = sh.part + i * sh.q;
-        if (rb < g.n0b) {
-          f32x4 pr, pi;
-          coil_p<PREC>(lane, a, g, rb, vb, pr, pi);
-          // m = x (.) P with the input chessboard sign
+        const int cb = sh.part + i * sh.q;
+        if (cb < g.n1b) {
+          const int i1 = 16 * cb + (lane & 15);
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int i0 = 16 * rb + 4 * grp + r;
-            float2 v = cmul(make_float2(pr[r], pi[r]), xp[i0 * g.n1 + i1]);
+            const int i0 = 16 * sh.rb + 4 * grp + r;
+            float2 v = cmul(make_float2(pr[i][r], pi[i][r]), xp[i0 * g.n1 + i1]);
             if ((i0 + i1) & 1) v = make_float2(-v.x, -v.y);
             lds[i0 * g.PS + i1] = v;
           }
@@ -536,13 +553,14 @@ __global__ __launch_bounds__(PT) void plane_fwd_kernel(PlaneArgs a) {
     __syncthreads();
     plane_fft(a, g, lds, -1);
     float2* zo = a.Z + ((size_t)j * g.n2 + i2) * a.L;
-    for (int l = threadIdx.x; l < a.L; l += PT) {
+    for (int l = tid; l < a.L; l += PT) {
       const int q = a.pos[l];
       const int k0 = q / g.n1, k1 = q - k0 * g.n1;
       float2 v = lds[k0 * g.PS + k1];
       if ((k0 + k1) & 1) v = make_float2(-v.x, -v.y);
       zo[l] = v;
     }
+    __syncthreads();  // the gather is done with the plane
   }
 }
 
@@ -550,7 +568,6 @@ template <int PREC, int N0, int N1>
 __global__ __launch_bounds__(PT) void plane_adj_kernel(PlaneArgs a) {
   __shared__ float2 lds[LDS_ELEMS];
   const Geo<N0, N1> g(a);
-  const int lane0 = threadIdx.x & 63;
   const int ngrp = (a.J + a.G - 1) / a.G;
   const int i2 = blockIdx.x / ngrp, gi = blockIdx.x % ngrp;
   const float2* xp = a.xt + (size_t)i2 * g.n0 * g.n1;
@@ -561,16 +578,37 @@ __global__ __launch_bounds__(PT) void plane_adj_kernel(PlaneArgs a) {
   for (int i = 0; i < 8; ++i) { gr[i] = z4(); gim[i] = z4(); }
   load_twiddles(a, g, lds);
   for (int j = gi * a.G; j < a.J && j < (gi + 1) * a.G; ++j) {
-    int lane = lane0;  // opaque per coil, as in the forward kernel
-    asm volatile("" : "+v"(lane));
-    const int grp = lane >> 4, i1 = 16 * sh.cb + (lane & 15);
-    // zero-filled plane; W of this coil (B c recomputed)
-    for (int e = threadIdx.x; e < g.n0 * g.PS; e += PT) lds[e] = make_float2(0.f, 0.f);
-    if (want_gx) stage_w<PREC>(a, g, j, i2, lds);
-    __syncthreads();
-    // scatter of this plane's samples (with the chessboard sign)
+    int tid = threadIdx.x;  // opaque per coil, as in the forward kernel
+    asm volatile("" : "+v"(tid));
+    const int lane = tid & 63, grp = lane >> 4;
+    // this plane's samples (at most SCAT per thread) and W, loaded early
     const float2* zi = a.Z + ((size_t)j * g.n2 + i2) * a.L;
-    for (int l = threadIdx.x; l < a.L; l += PT) {
+    float2 zv[SCAT];
+    int zq[SCAT];
+#pragma unroll
+    for (int k = 0; k < SCAT; ++k) {
+      const int l = tid + k * PT;
+      zq[k] = l < a.L ? a.pos[l] : -1;
+      zv[k] = l < a.L ? zi[l] : make_float2(0.f, 0.f);
+    }
+    f32x4 pr[8], pi[8];
+    if (want_gx) {
+      WPrefetch w;
+      w_load(a, g, j, i2, tid, w);
+      coil_map<PREC>(a, g, lds, sh, lane, tid, w, pr, pi);  // B c recomputed
+    }
+    // zero-filled scatter (with the chessboard sign)
+    for (int e = tid; e < g.n0 * g.PS; e += PT) lds[e] = make_float2(0.f, 0.f);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < SCAT; ++k)
+      if (zq[k] >= 0) {
+        const int k0 = zq[k] / g.n1, k1 = zq[k] - k0 * g.n1;
+        float2 v = zv[k];
+        if ((k0 + k1) & 1) v = make_float2(-v.x, -v.y);
+        lds[k0 * g.PS + k1] = v;
+      }
+    for (int l = tid + SCAT * PT; l < a.L; l += PT) {  // beyond the prefetched samples
       const int q = a.pos[l];
       const int k0 = q / g.n1, k1 = q - k0 * g.n1;
       float2 v = zi[l];
@@ -581,21 +619,18 @@ __global__ __launch_bounds__(PT) void plane_adj_kernel(PlaneArgs a) {
     plane_fft(a, g, lds, +1);
     // g (output chessboard sign); gx += conj(P) g in registers; h = conj(x) g into the plane
     if (sh.on) {
-      typename Tile<PREC>::B vb[3];
-      if (want_gx) coil_v<PREC>(lane, a, g, lds, sh.cb, vb);
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
-        const int rb = sh.part + i * sh.q;
-        if (rb < g.n0b) {
-          f32x4 pr = z4(), pi = z4();
-          if (want_gx) coil_p<PREC>(lane, a, g, rb, vb, pr, pi);
+        const int cb = sh.part + i * sh.q;
+        if (cb < g.n1b) {
+          const int i1 = 16 * cb + (lane & 15);
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int i0 = 16 * rb + 4 * grp + r;
+            const int i0 = 16 * sh.rb + 4 * grp + r;
             float2 gv = lds[i0 * g.PS + i1];
             if ((i0 + i1) & 1) gv = make_float2(-gv.x, -gv.y);
             if (want_gx) {
-              const float2 c = cmulc(make_float2(pr[r], pi[r]), gv);
+              const float2 c = cmulc(make_float2(pr[i][r], pi[i][r]), gv);
               gr[i][r] += c.x;
               gim[i][r] += c.y;
             }
@@ -605,21 +640,43 @@ __global__ __launch_bounds__(PT) void plane_adj_kernel(PlaneArgs a) {
       }
     }
     __syncthreads();
-    if (a.T3b) adjoint_w<PREC>(lane, a, g, j, i2, lds);
+    if (a.T3b) adjoint_w<PREC>(a, g, j, i2, lds, lane, tid);
   }
   if (want_gx && sh.on) {
-    const int grp = lane0 >> 4, i1 = 16 * sh.cb + (lane0 & 15);
+    const int lane = threadIdx.x & 63, grp = lane >> 4;
     float2* gxp = a.gxpart + ((size_t)gi * g.n2 + i2) * g.n0 * g.n1;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      const int rb = sh.part + i * sh.q;
-      if (rb < g.n0b)
+      const int cb = sh.part + i * sh.q;
+      if (cb < g.n1b)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int i0 = 16 * rb + 4 * grp + r;
+          const int i0 = 16 * sh.rb + 4 * grp + r, i1 = 16 * cb + (lane & 15);
           gxp[i0 * g.n1 + i1] = make_float2(gr[i][r], gim[i][r]);
         }
     }
+  }
+}
+
+// Plan-time fragment-ordered copy of O(o, k) = src[o * so + k * sk] (conjugated if conj),
+// zero for o >= no or k >= nk.  One thread per (o block, step, lane).
+template <int PREC>
+__global__ void frag_operand_kernel(const float2* __restrict__ src, int no, int nk, int64_t so, int64_t sk, int conj,
+                                    int is_b, void* dst) {
+  const int obs = (no + 15) / 16, ks = (nk + 15) / 16;
+  const int total = obs * ks * 64;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+    const int lane = e % 64, f = e / 64, ob = f / ks, s = f % ks;
+    const int o = 16 * ob + (lane & 15);
+    float2 v[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int k = 16 * s + 4 * (lane >> 4) + t;
+      v[t] = (o < no && k < nk) ? src[(int64_t)o * so + (int64_t)k * sk] : make_float2(0.f, 0.f);
+      if (conj) v[t].y = -v[t].y;
+    }
+    if (is_b) put_frag_b<PREC>(dst, obs, ob, s, lane, v);
+    else put_frag_a<PREC>(dst, ks, ob, s, lane, v);
   }
 }
 
@@ -751,35 +808,6 @@ __global__ void reduce_transpose_kernel(const float2* __restrict__ part, int ngr
   }
 }
 
-// Plan-time split of a complex matrix into the real-block operand planes.
-//   mode 0 (A operand): dst[m][k'] = (Re, Im) of src(m, k) at k' = 2k, 2k+1; planes hi, lo
-//   mode 1 (B operand): br[n][k'] = (Re, -Im), bi[n][k'] = (Im, Re) of src(n, k); planes
-//                       br hi, br lo, bi hi, bi lo
-// src(m, k) = src[m * sm + k * sk], optionally conjugated; zero beyond (rows, cols).
-__global__ void split_operand_kernel(const float2* __restrict__ src, int rows, int cols, int64_t sm, int64_t sk,
-                                     int conj, int mode, int rows_pad, int kp, unsigned short* __restrict__ dst) {
-  const int64_t total = (int64_t)rows_pad * kp;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int m = (int)(e / kp), kq = (int)(e % kp), k = kq / 2, c = kq & 1;
-    float2 v = make_float2(0.f, 0.f);
-    if (m < rows && k < cols) v = src[(int64_t)m * sm + (int64_t)k * sk];
-    if (conj) v.y = -v.y;
-    if (mode == 0) {
-      const float f = c ? v.y : v.x;
-      const unsigned short h = bf16_rne(f);
-      dst[e] = h;
-      dst[total + e] = bf16_rne(f - bf16_f32(h));
-    } else {
-      const float fr = c ? -v.y : v.x, fi = c ? v.x : v.y;
-      const unsigned short hr = bf16_rne(fr), hi = bf16_rne(fi);
-      dst[e] = hr;
-      dst[total + e] = bf16_rne(fr - bf16_f32(hr));
-      dst[2 * total + e] = hi;
-      dst[3 * total + e] = bf16_rne(fi - bf16_f32(hi));
-    }
-  }
-}
-
 template <int PREC>
 hipError_t plane_launch_prec(const PlaneArgs& a, bool adj, hipStream_t st) {
   const int ngrp = (a.J + a.G - 1) / a.G;
@@ -836,13 +864,17 @@ hipError_t reduce_transpose_launch(const float2* part, int ngrp, int64_t R, int6
   return hipGetLastError();
 }
 
-hipError_t split_operand_launch(const float2* src, int rows, int cols, int64_t sm, int64_t sk, int conj, int mode,
-                                int rows_pad, int kp, uint16_t* dst, hipStream_t st) {
-  int64_t total = (int64_t)rows_pad * kp;
-  int64_t blocks = (total + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(split_operand_kernel, dim3((unsigned)blocks), dim3(256), 0, st, src, rows, cols, sm, sk, conj,
-                     mode, rows_pad, kp, reinterpret_cast<unsigned short*>(dst));
+size_t frag_operand_bytes(int no, int nk, int is_b, int precision) {
+  const size_t blocks = (size_t)((no + 15) / 16) * ((nk + 15) / 16);
+  return blocks * ((precision == 1 && is_b) ? 4096 : 2048);
+}
+
+hipError_t frag_operand_launch(const float2* src, int no, int nk, int64_t so, int64_t sk, int conj, int is_b,
+                               int precision, void* dst, hipStream_t st) {
+  const int total = ((no + 15) / 16) * ((nk + 15) / 16) * 64;
+  const dim3 grid((unsigned)((total + 255) / 256)), block(256);
+  if (precision == 1) hipLaunchKernelGGL(frag_operand_kernel<1>, grid, block, 0, st, src, no, nk, so, sk, conj, is_b, dst);
+  else hipLaunchKernelGGL(frag_operand_kernel<0>, grid, block, 0, st, src, no, nk, so, sk, conj, is_b, dst);
   return hipGetLastError();
 }
 
