@@ -413,52 +413,66 @@ __device__ __forceinline__ void coil_p(const Geo<N0, N1>& g, const float2* lds, 
 // Y = h conj(U1) with h in the plane, then Wb = U0^H Y -> T3b[j][i2].  Wave w takes Y row
 // block w % n0b over a 1 / q share of the K16 steps over i1; the q partial copies of Y
 // are stored side by side as extra reduction steps of Wb.  conj(U1) is staged through
-// LDS one K16 step at a time from registers loaded at the start.  Ends synchronised.
-constexpr int YPF = 12;  // 16-byte pieces of conj(U1) per thread (n1b * r1b / 2 in BF16)
-
+// two LDS step buffers, each thread carrying the pieces of the next two steps in
+// registers (loads issued two steps ahead).  Ends synchronised.
 template <int PREC, int N0, int N1>
 __device__ __forceinline__ void adjoint_w(const PlaneArgs& a, const Geo<N0, N1>& g, int j, int i2, float2* lds,
                                           int lane, int tid) {
   const int wave = threadIdx.x >> 6, grp = lane >> 4;
   const int qy = NWAVE / g.n0b, yb = wave % g.n0b, kq = wave / g.n0b;
   const bool on = kq < qy;
-  const int step_pieces = frag_b_step_bytes<PREC>(g.r1b) / 16;
-  const int total = step_pieces * g.n1b;
+  const int sp = frag_b_step_bytes<PREC>(g.r1b) / 16;  // 16-byte pieces of one step (<= 2 PT)
+  const bool two = tid + PT < sp;
   const float4* src = reinterpret_cast<const float4*>(a.U1CF);
-  float4 pf[YPF];
-#pragma unroll
-  for (int k = 0; k < YPF; ++k) {
-    const int e = tid + k * PT;
-    if (e < total) pf[k] = src[e];
-  }
   float4* stage = reinterpret_cast<float4*>(lds + STAGE_OFF);
-  auto put_step = [&](int s) {
-    const int lo = s * step_pieces, hi = lo + step_pieces;
-#pragma unroll
-    for (int k = 0; k < YPF; ++k) {
-      const int e = tid + k * PT;
-      if (e >= lo && e < hi && e < total) stage[(s & 1) * step_pieces + (e - lo)] = pf[k];
+  struct Pieces { float4 p0, p1; };
+  auto fetch = [&](Pieces& r, int s) {
+    if (s < g.n1b) {
+      const float4* q = src + (size_t)s * sp;
+      if (tid < sp) r.p0 = q[tid];
+      if (two) r.p1 = q[tid + PT];
+    }
+  };
+  auto put = [&](const Pieces& r, int s) {
+    if (s < g.n1b) {
+      float4* q = stage + (s & 1) * sp;
+      if (tid < sp) q[tid] = r.p0;
+      if (two) q[tid + PT] = r.p1;
     }
   };
   f32x4 yr[3], yi[3];
 #pragma unroll
   for (int nb = 0; nb < 3; ++nb) { yr[nb] = z4(); yi[nb] = z4(); }
-  put_step(0);
-  __syncthreads();
   const int i0 = 16 * yb + (lane & 15);
-  for (int s = 0; s < g.n1b; ++s) {
-    if (s + 1 < g.n1b) put_step(s + 1);
+  auto compute = [&](int s) {
     if (on && (s % qy) == kq) {
       float2 hv[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) hv[t] = lds[i0 * g.PS + 16 * s + 4 * grp + t];
       const typename Tile<PREC>::A av = Tile<PREC>::make_a(hv);
-      const float4* buf = stage + (s & 1) * step_pieces;
+      const float4* buf = stage + (s & 1) * sp;
 #pragma unroll
       for (int nb = 0; nb < 3; ++nb)
         if (nb < g.r1b) Tile<PREC>::mma(yr[nb], yi[nb], av, frag_b<PREC>(buf, g.r1b, nb, 0, lane));
     }
+  };
+  Pieces odd, even;  // the next odd and even steps
+  fetch(even, 0);
+  put(even, 0);
+  fetch(odd, 1);
+  fetch(even, 2);
+  __syncthreads();
+  for (int s = 0; s < g.n1b; s += 2) {
+    put(odd, s + 1);
+    fetch(odd, s + 3);
+    compute(s);
     __syncthreads();
+    if (s + 1 < g.n1b) {
+      put(even, s + 2);
+      fetch(even, s + 4);
+      compute(s + 1);
+      __syncthreads();
+    }
   }
   // the first Wb tile's U0^H fragments, in flight across the Y store
   const int mb0 = wave / g.r1b;
@@ -522,6 +536,9 @@ __global__ __launch_bounds__(PT) void plane_fwd_kernel(PlaneArgs a) {
   const int i2 = blockIdx.x / ngrp, gi = blockIdx.x % ngrp;
   const float2* xp = a.xt + (size_t)i2 * g.n0 * g.n1;
   const Share sh = plane_share(g);
+  int pq[SCAT];  // sampled plane positions, the same for every coil
+#pragma unroll
+  for (int k = 0; k < SCAT; ++k) pq[k] = (int)threadIdx.x + k * PT < a.L ? a.pos[threadIdx.x + k * PT] : -1;
   load_twiddles(a, g, lds);
   for (int j = gi * a.G; j < a.J && j < (gi + 1) * a.G; ++j) {
     // lane and thread index through an empty asm: per-coil addresses are recomputed
@@ -553,7 +570,15 @@ __global__ __launch_bounds__(PT) void plane_fwd_kernel(PlaneArgs a) {
     __syncthreads();
     plane_fft(a, g, lds, -1);
     float2* zo = a.Z + ((size_t)j * g.n2 + i2) * a.L;
-    for (int l = tid; l < a.L; l += PT) {
+#pragma unroll
+    for (int k = 0; k < SCAT; ++k)
+      if (pq[k] >= 0) {
+        const int k0 = pq[k] / g.n1, k1 = pq[k] - k0 * g.n1;
+        float2 v = lds[k0 * g.PS + k1];
+        if ((k0 + k1) & 1) v = make_float2(-v.x, -v.y);
+        zo[tid + k * PT] = v;
+      }
+    for (int l = tid + SCAT * PT; l < a.L; l += PT) {  // beyond the preloaded positions
       const int q = a.pos[l];
       const int k0 = q / g.n1, k1 = q - k0 * g.n1;
       float2 v = lds[k0 * g.PS + k1];
@@ -573,6 +598,9 @@ __global__ __launch_bounds__(PT) void plane_adj_kernel(PlaneArgs a) {
   const float2* xp = a.xt + (size_t)i2 * g.n0 * g.n1;
   const bool want_gx = a.gxpart != nullptr;
   const Share sh = plane_share(g);
+  int zq[SCAT];  // sampled plane positions, the same for every coil
+#pragma unroll
+  for (int k = 0; k < SCAT; ++k) zq[k] = (int)threadIdx.x + k * PT < a.L ? a.pos[threadIdx.x + k * PT] : -1;
   f32x4 gr[8], gim[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) { gr[i] = z4(); gim[i] = z4(); }
@@ -584,13 +612,8 @@ __global__ __launch_bounds__(PT) void plane_adj_kernel(PlaneArgs a) {
     // this plane's samples (at most SCAT per thread) and W, loaded early
     const float2* zi = a.Z + ((size_t)j * g.n2 + i2) * a.L;
     float2 zv[SCAT];
-    int zq[SCAT];
 #pragma unroll
-    for (int k = 0; k < SCAT; ++k) {
-      const int l = tid + k * PT;
-      zq[k] = l < a.L ? a.pos[l] : -1;
-      zv[k] = l < a.L ? zi[l] : make_float2(0.f, 0.f);
-    }
+    for (int k = 0; k < SCAT; ++k) zv[k] = zq[k] >= 0 ? zi[tid + k * PT] : make_float2(0.f, 0.f);
     f32x4 pr[8], pi[8];
     if (want_gx) {
       WPrefetch w;
@@ -617,24 +640,38 @@ __global__ __launch_bounds__(PT) void plane_adj_kernel(PlaneArgs a) {
     }
     __syncthreads();
     plane_fft(a, g, lds, +1);
-    // g (output chessboard sign); gx += conj(P) g in registers; h = conj(x) g into the plane
+    // g (output chessboard sign); gx += conj(P) g in registers; h = conj(x) g into the plane.
+    // x in two batches of four tiles, each batch's loads issued together.
     if (sh.on) {
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int cb = sh.part + i * sh.q;
-        if (cb < g.n1b) {
-          const int i1 = 16 * cb + (lane & 15);
+      for (int hb = 0; hb < 2; ++hb) {
+        float2 xv[4][4];
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int i0 = 16 * sh.rb + 4 * grp + r;
-            float2 gv = lds[i0 * g.PS + i1];
-            if ((i0 + i1) & 1) gv = make_float2(-gv.x, -gv.y);
-            if (want_gx) {
-              const float2 c = cmulc(make_float2(pr[i][r], pi[i][r]), gv);
-              gr[i][r] += c.x;
-              gim[i][r] += c.y;
+        for (int ii = 0; ii < 4; ++ii) {
+          const int cb = sh.part + (4 * hb + ii) * sh.q;
+          if (cb < g.n1b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) xv[ii][r] = xp[(16 * sh.rb + 4 * grp + r) * g.n1 + 16 * cb + (lane & 15)];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) {
+          const int i = 4 * hb + ii;
+          const int cb = sh.part + i * sh.q;
+          if (cb < g.n1b) {
+            const int i1 = 16 * cb + (lane & 15);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int i0 = 16 * sh.rb + 4 * grp + r;
+              float2 gv = lds[i0 * g.PS + i1];
+              if ((i0 + i1) & 1) gv = make_float2(-gv.x, -gv.y);
+              if (want_gx) {
+                const float2 c = cmulc(make_float2(pr[i][r], pi[i][r]), gv);
+                gr[i][r] += c.x;
+                gim[i][r] += c.y;
+              }
+              lds[i0 * g.PS + i1] = cmulc(xv[ii][r], gv);
             }
-            lds[i0 * g.PS + i1] = cmulc(xp[i0 * g.n1 + i1], gv);
           }
         }
       }
