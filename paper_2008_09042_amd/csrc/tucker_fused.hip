@@ -425,19 +425,18 @@ __device__ __forceinline__ void adjoint_w(const PlaneArgs& a, const Geo<N0, N1>&
   const bool two = tid + PT < sp;
   const float4* src = reinterpret_cast<const float4*>(a.U1CF);
   float4* stage = reinterpret_cast<float4*>(lds + STAGE_OFF);
-  struct Pieces { float4 p0, p1; };
-  auto fetch = [&](Pieces& r, int s) {
+  auto fetch = [&](float4& p0, float4& p1, int s) {
     if (s < g.n1b) {
       const float4* q = src + (size_t)s * sp;
-      if (tid < sp) r.p0 = q[tid];
-      if (two) r.p1 = q[tid + PT];
+      if (tid < sp) p0 = q[tid];
+      if (two) p1 = q[tid + PT];
     }
   };
-  auto put = [&](const Pieces& r, int s) {
+  auto put = [&](const float4& p0, const float4& p1, int s) {
     if (s < g.n1b) {
       float4* q = stage + (s & 1) * sp;
-      if (tid < sp) q[tid] = r.p0;
-      if (two) q[tid + PT] = r.p1;
+      if (tid < sp) q[tid] = p0;
+      if (two) q[tid + PT] = p1;
     }
   };
   f32x4 yr[3], yi[3];
@@ -453,23 +452,26 @@ __device__ __forceinline__ void adjoint_w(const PlaneArgs& a, const Geo<N0, N1>&
       const float4* buf = stage + (s & 1) * sp;
 #pragma unroll
       for (int nb = 0; nb < 3; ++nb)
-        if (nb < g.r1b) Tile<PREC>::mma(yr[nb], yi[nb], av, frag_b<PREC>(buf, g.r1b, nb, 0, lane));
+        if (nb < g.r1b) {
+          Tile<PREC>::mma(yr[nb], yi[nb], av, frag_b<PREC>(buf, g.r1b, nb, 0, lane));
+          __builtin_amdgcn_sched_barrier(0);  // one B fragment live at a time
+        }
     }
   };
-  Pieces odd, even;  // the next odd and even steps
-  fetch(even, 0);
-  put(even, 0);
-  fetch(odd, 1);
-  fetch(even, 2);
+  float4 o0, o1, e0, e1;  // pieces of the next odd and even steps
+  fetch(e0, e1, 0);
+  put(e0, e1, 0);
+  fetch(o0, o1, 1);
+  fetch(e0, e1, 2);
   __syncthreads();
   for (int s = 0; s < g.n1b; s += 2) {
-    put(odd, s + 1);
-    fetch(odd, s + 3);
+    put(o0, o1, s + 1);
+    fetch(o0, o1, s + 3);
     compute(s);
     __syncthreads();
     if (s + 1 < g.n1b) {
-      put(even, s + 2);
-      fetch(even, s + 4);
+      put(e0, e1, s + 2);
+      fetch(e0, e1, s + 4);
       compute(s + 1);
       __syncthreads();
     }
@@ -653,6 +655,14 @@ __global__ __launch_bounds__(PT) void plane_adj_kernel(PlaneArgs a) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) xv[ii][r] = xp[(16 * sh.rb + 4 * grp + r) * g.n1 + 16 * cb + (lane & 15)];
         }
+        float2 gvs[4][4];  // all of the batch's plane values read before any is rewritten
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) {
+          const int cb = sh.part + (4 * hb + ii) * sh.q;
+          if (cb < g.n1b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) gvs[ii][r] = lds[(16 * sh.rb + 4 * grp + r) * g.PS + 16 * cb + (lane & 15)];
+        }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int ii = 0; ii < 4; ++ii) {
@@ -663,7 +673,7 @@ __global__ __launch_bounds__(PT) void plane_adj_kernel(PlaneArgs a) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
               const int i0 = 16 * sh.rb + 4 * grp + r;
-              float2 gv = lds[i0 * g.PS + i1];
+              float2 gv = gvs[ii][r];
               if ((i0 + i1) & 1) gv = make_float2(-gv.x, -gv.y);
               if (want_gx) {
                 const float2 c = cmulc(make_float2(pr[i][r], pi[i][r]), gv);
