@@ -97,6 +97,8 @@ def kernel_work(name, p, prec):
         "core_adj": ("hbm", "GB/s", core_bytes, HBM_PEAK_GBS),
         "gemm_core_coef": ("hbm", "GB/s", core_bytes, HBM_PEAK_GBS),
         "gemm_core_adjoint": ("hbm", "GB/s", core_bytes, HBM_PEAK_GBS),
+        "mode3_fwd": ("hbm", "GB/s", 8.0 * (J * R + J * n2 * r0 * r1 + n2 * r2), HBM_PEAK_GBS),
+        "mode3_adj": ("hbm", "GB/s", 8.0 * (J * R + J * n2 * r0 * r1 + n2 * r2), HBM_PEAK_GBS),
         "gemm_mode3": ("hbm", "GB/s", 8.0 * (J * R + J * n2 * r0 * r1 + n2 * r2), HBM_PEAK_GBS),
         "gemm_mode3_adjoint": ("hbm", "GB/s", 8.0 * (J * R + J * n2 * r0 * r1 + n2 * r2), HBM_PEAK_GBS),
     }

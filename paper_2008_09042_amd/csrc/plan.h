@@ -47,11 +47,13 @@ struct Plan {
   int32_t* d_pos = nullptr;    // [L] plane index k0 * n1 + k1 of each line
   void* d_frag = nullptr;      // fragment-ordered factor operands (one allocation)
   const void *U0F = nullptr, *U1TF = nullptr, *U1CF = nullptr, *U0HF = nullptr;
+  bool mode3_direct = false;   // dedicated third-mode product kernels (r2 <= 64)
+  const void *U2F = nullptr, *U2CF = nullptr;
   // dedicated core contraction kernels (Tucker basis, J <= 64)
   bool core_direct = false;
   CoreGeom cg{};
   uint16_t* d_core_split = nullptr;  // BF16-split core planes (BF16_SPLIT plans only)
-  int G_fwd = 2, G_adj = 4;    // coils per plane workgroup
+  int G_fwd = 2, G_adj = 8;    // coils per plane workgroup
   float gscale = 1.0f;         // prod_d (-1)^(n_d/2) / sqrt(N)
   // non-Cartesian sampling (Kaiser-Bessel NUFFT, 2D)
   int g[2] = {0, 0};             // oversampled grid

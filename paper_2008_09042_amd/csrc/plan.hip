@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "fused.h"
+#include "mode3.h"
 #include "nufft.h"
 #include "plan.h"
 
@@ -227,6 +228,18 @@ GemmArgs fused_T1b_args(const Plan& p, const float2* T3b, float2* T1b) {
   return g;
 }
 
+Mode3Args mode3_args(const Plan& p) {
+  Mode3Args m;
+  std::memset(&m, 0, sizeof(m));
+  m.J = p.J;
+  m.Q = (int)(p.r[0] * p.r[1]);
+  m.n2 = (int)p.n[2];
+  m.r2 = (int)p.r[2];
+  m.U2F = p.U2F;
+  m.U2CF = p.U2CF;
+  return m;
+}
+
 bool detect_lines(const maxwell_plan_desc& d, std::vector<int32_t>& pos) {
   const int64_t n2 = d.n[2];
   if (d.M <= 0 || d.M % n2) return false;
@@ -423,16 +436,26 @@ maxwell_status plan_build(Plan& p, const maxwell_plan_desc& d, const maxwell_bas
     const int n0 = (int)p.n[0], n1 = (int)p.n[1], r0 = (int)p.r[0], r1 = (int)p.r[1], pr = p.precision;
     const size_t bU0F = frag_operand_bytes(n0, r0, 0, pr), bU1TF = frag_operand_bytes(n1, r1, 1, pr);
     const size_t bU1CF = frag_operand_bytes(r1, n1, 1, pr), bU0HF = frag_operand_bytes(r0, n0, 0, pr);
-    if ((e = hipMalloc(&p.d_frag, bU0F + bU1TF + bU1CF + bU0HF)) != hipSuccess) return hip_err(e);
+    const int n2 = (int)p.n[2], r2 = (int)p.r[2];
+    p.mode3_direct = mode3_supported(r2);
+    const size_t bU2F = p.mode3_direct ? frag_operand_bytes(n2, r2, 0, pr) : 0;
+    const size_t bU2CF = p.mode3_direct ? frag_operand_bytes(r2, n2, 1, pr) : 0;
+    if ((e = hipMalloc(&p.d_frag, bU0F + bU1TF + bU1CF + bU0HF + bU2F + bU2CF)) != hipSuccess) return hip_err(e);
     char* q = reinterpret_cast<char*>(p.d_frag);
     p.U0F = q; q += bU0F;
     p.U1TF = q; q += bU1TF;
     p.U1CF = q; q += bU1CF;
-    p.U0HF = q;
+    p.U0HF = q; q += bU0HF;
+    p.U2F = q; q += bU2F;
+    p.U2CF = q;
     if ((e = frag_operand_launch(p.U[0], n0, r0, r0, 1, 0, 0, pr, const_cast<void*>(p.U0F), 0)) ||
         (e = frag_operand_launch(p.U[1], n1, r1, r1, 1, 0, 1, pr, const_cast<void*>(p.U1TF), 0)) ||
         (e = frag_operand_launch(p.U[1], r1, n1, 1, r1, 1, 1, pr, const_cast<void*>(p.U1CF), 0)) ||
         (e = frag_operand_launch(p.U[0], r0, n0, 1, r0, 1, 0, pr, const_cast<void*>(p.U0HF), 0)))
+      return hip_err(e);
+    if (p.mode3_direct &&
+        ((e = frag_operand_launch(p.U[2], n2, r2, r2, 1, 0, 0, pr, const_cast<void*>(p.U2F), 0)) ||
+         (e = frag_operand_launch(p.U[2], r2, n2, 1, r2, 1, 1, pr, const_cast<void*>(p.U2CF), 0))))
       return hip_err(e);
     if ((e = hipStreamSynchronize(0)) != hipSuccess) return hip_err(e);
   }
@@ -637,8 +660,15 @@ static hipError_t fused_prepare(const Plan& p, const float2* x, const float2* c,
   void* gws = wsp<void>(ws, p.off_gemm);
   hipError_t e = core_forward(p, c, wsp<float2>(ws, p.off_T1), ws, st);
   if (e != hipSuccess) return e;
-  e = TIMED("gemm_mode3", gemm_launch(fused_T3_args(p, wsp<float2>(ws, p.off_T1), wsp<float2>(ws, p.off_T3)),
-                                      p.precision, gws, st));
+  if (p.mode3_direct) {
+    Mode3Args m = mode3_args(p);
+    m.T1 = wsp<float2>(ws, p.off_T1);
+    m.T3 = wsp<float2>(ws, p.off_T3);
+    e = TIMED("mode3_fwd", mode3_fwd_launch(m, p.precision, st));
+  } else {
+    e = TIMED("gemm_mode3", gemm_launch(fused_T3_args(p, wsp<float2>(ws, p.off_T1), wsp<float2>(ws, p.off_T3)),
+                                        p.precision, gws, st));
+  }
   if (e != hipSuccess) return e;
   return TIMED("transpose_x", transpose_launch(x, p.n[0] * p.n[1], p.n[2], wsp<float2>(ws, p.off_xt), st));
 }
@@ -686,9 +716,16 @@ static hipError_t fused_adjoint(const Plan& p, const float2* x, const float2* c,
     if (e != hipSuccess) return e;
   }
   if (gc) {
-    void* gws = wsp<void>(ws, p.off_gemm);
-    e = TIMED("gemm_mode3_adjoint",
-              gemm_launch(fused_T1b_args(p, pa.T3b, wsp<float2>(ws, p.off_T1b)), p.precision, gws, st));
+    if (p.mode3_direct) {
+      Mode3Args m = mode3_args(p);
+      m.T3b = pa.T3b;
+      m.T1b = wsp<float2>(ws, p.off_T1b);
+      e = TIMED("mode3_adj", mode3_adj_launch(m, p.precision, st));
+    } else {
+      void* gws = wsp<void>(ws, p.off_gemm);
+      e = TIMED("gemm_mode3_adjoint",
+                gemm_launch(fused_T1b_args(p, pa.T3b, wsp<float2>(ws, p.off_T1b)), p.precision, gws, st));
+    }
     if (e != hipSuccess) return e;
     if ((e = core_adjoint(p, wsp<float2>(ws, p.off_T1b), gc, 1.0f, nullptr, ws, st)) != hipSuccess) return e;
   }

@@ -22,22 +22,14 @@
 //             T1b = T3b x_3 U2^H,  gc = core^H T1b              (MFMA GEMM kernel)
 //             gx = sum of the per-group partials (fixed order, no atomics)
 //
-// Matrix-core arithmetic.  FP32: each complex product is four real products on
-// v_mfma_f32_16x16x4_f32.  BF16_SPLIT: the complex product over K is written as
-// two real products over 2K (real-block form): with a' = (Re a_0, Im a_0, Re a_1,
-// ...), Re c = a'.(Re b_0, -Im b_0, ...) and Im c = a'.(Im b_0, Re b_0, ...); every
-// real operand is split into hi = bf16(v), lo = bf16(v - hi) and each real product
-// is hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_bf16 with FP32 accumulation.
-// Constant factor operands are split once at plan time; W, V, h and Y are split
-// in the kernel.
+// Matrix-core arithmetic as in mfma_frag.h.  Constant factor operands are put in
+// fragment order (and split, in BF16_SPLIT plans) once at plan time; W, V, h and Y
+// are split in the kernel.
 #include "fft_device.h"
 #include "fused.h"
+#include "mfma_frag.h"
 
 namespace mx {
-
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
 namespace {
 
@@ -52,213 +44,6 @@ constexpr int STAGE_ELEMS = 3072;                // 24 KB
 constexpr int LDS_ELEMS = STAGE_OFF + STAGE_ELEMS;
 constexpr int FFT_CHUNK = PMAX * PMAX / 2;       // elements per register chunk of a pass
 constexpr int SCAT = 4;                          // samples per thread loaded ahead of the scatter
-
-__device__ __forceinline__ f32x4 z4() { return f32x4{0.f, 0.f, 0.f, 0.f}; }
-
-__device__ __forceinline__ void cmfma(f32x4& cr, f32x4& ci, float2 a, float2 b) {
-  cr = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, cr, 0, 0, 0);
-  cr = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.y, b.y, cr, 0, 0, 0);
-  ci = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.y, ci, 0, 0, 0);
-  ci = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.x, ci, 0, 0, 0);
-}
-
-// ---------------------------------------------------------------- BF16 split helpers
-__device__ __forceinline__ unsigned short bf16_rne(float f) {
-  unsigned u = __float_as_uint(f);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
-__device__ __forceinline__ float bf16_f32(unsigned short h) { return __uint_as_float(((unsigned)h) << 16); }
-
-__device__ __forceinline__ void split8(const float (&v)[8], u16x8& hi, u16x8& lo) {
-#pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const unsigned short h = bf16_rne(v[e]);
-    hi[e] = h;
-    lo[e] = bf16_rne(v[e] - bf16_f32(h));
-  }
-}
-
-__device__ __forceinline__ bf16x8 asbf(u16x8 v) { return __builtin_bit_cast(bf16x8, v); }
-
-// c += a * b over one 32-wide k' step for both real-block halves (6 MFMAs).
-__device__ __forceinline__ void mfma6(f32x4& cr, f32x4& ci, u16x8 ah, u16x8 al, u16x8 brh, u16x8 brl, u16x8 bih,
-                             u16x8 bil) {
-  cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(asbf(ah), asbf(brh), cr, 0, 0, 0);
-  cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(asbf(ah), asbf(brl), cr, 0, 0, 0);
-  cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(asbf(al), asbf(brh), cr, 0, 0, 0);
-  ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(asbf(ah), asbf(bih), ci, 0, 0, 0);
-  ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(asbf(ah), asbf(bil), ci, 0, 0, 0);
-  ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(asbf(al), asbf(bih), ci, 0, 0, 0);
-}
-
-__device__ __forceinline__ u16x8 ld8(const unsigned short* p) { return *reinterpret_cast<const u16x8*>(p); }
-__device__ __forceinline__ void st8(unsigned short* p, u16x8 v) { *reinterpret_cast<u16x8*>(p) = v; }
-
-// Store one accumulator block as a B operand [n][k'] (k' = 2 * row + {0, 1}) in the
-// real-block form: br = (Re, -Im), bi = (Im, Re), each split hi / lo.  The lane's four
-// rows are consecutive, so its eight k' values are one 16-byte store per array.
-__device__ __forceinline__ void store_bop(unsigned short* brh, unsigned short* brl, unsigned short* bih,
-                                 unsigned short* bil, int ld, int n, int kp0, const f32x4& cr,
-                                 const f32x4& ci) {
-  float vr[8], vi[8];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    vr[2 * r] = cr[r];
-    vr[2 * r + 1] = -ci[r];
-    vi[2 * r] = ci[r];
-    vi[2 * r + 1] = cr[r];
-  }
-  u16x8 h, l;
-  split8(vr, h, l);
-  st8(brh + n * ld + kp0, h);
-  st8(brl + n * ld + kp0, l);
-  split8(vi, h, l);
-  st8(bih + n * ld + kp0, h);
-  st8(bil + n * ld + kp0, l);
-}
-
-// ---------------------------------------------------------------- matrix-core tiles
-// A K16 block spans 16 complex reduction indices.  In both precisions lane l (tile row
-// or column l % 16, group g = l / 16) holds the operand values of k = 4 g + t, t < 4,
-// and an accumulator tile holds D[4 g + r][l % 16].  A result tile is therefore, as it
-// stands, the lane's B operand of one K16 block of a following product whose reduction
-// runs over the result's rows.
-template <int PREC>
-struct Tile;
-
-template <>
-struct Tile<1> {  // BF16 split in the real-block form (file header)
-  struct A { u16x8 h, l; };
-  struct B { u16x8 rh, rl, ih, il; };
-  static __device__ __forceinline__ A make_a(const float2 (&v)[4]) {
-    float f[8];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      f[2 * t] = v[t].x;
-      f[2 * t + 1] = v[t].y;
-    }
-    A a;
-    split8(f, a.h, a.l);
-    return a;
-  }
-  static __device__ __forceinline__ B make_b(const float2 (&v)[4]) {
-    float fr[8], fi[8];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      fr[2 * t] = v[t].x;
-      fr[2 * t + 1] = -v[t].y;
-      fi[2 * t] = v[t].y;
-      fi[2 * t + 1] = v[t].x;
-    }
-    B b;
-    split8(fr, b.rh, b.rl);
-    split8(fi, b.ih, b.il);
-    return b;
-  }
-  static __device__ __forceinline__ void mma(f32x4& cr, f32x4& ci, const A& a, const B& b) {
-    mfma6(cr, ci, a.h, a.l, b.rh, b.rl, b.ih, b.il);
-  }
-};
-
-template <>
-struct Tile<0> {  // FP32: four real products per complex product; sub-step t uses k = 4 g + t
-  struct A { float2 v[4]; };
-  struct B { float2 v[4]; };
-  static __device__ __forceinline__ A make_a(const float2 (&v)[4]) { return A{{v[0], v[1], v[2], v[3]}}; }
-  static __device__ __forceinline__ B make_b(const float2 (&v)[4]) { return B{{v[0], v[1], v[2], v[3]}}; }
-  static __device__ __forceinline__ void mma(f32x4& cr, f32x4& ci, const A& a, const B& b) {
-#pragma unroll
-    for (int t = 0; t < 4; ++t) cmfma(cr, ci, a.v[t], b.v[t]);
-  }
-};
-
-// ---------------------------------------------------------------- fragment order
-// An operand O(o, k) (o: tile row of an A operand or tile column of a B operand, k: the
-// reduction index) is kept in fragment order: one (o block, K16 step) fragment is the 64
-// lanes' operand registers, stored lane-contiguously, so a wave loads it as one contiguous
-// 1 KiB run per array and a fragment store from registers is conflict-free in LDS.
-//   A type: [o block][step][hi, lo][lane][8 bf16]             FP32: [o block][step][lane][4 complex]
-//   B type: [step][br hi, br lo, bi hi, bi lo][o block][lane][8 bf16]
-//                                                             FP32: [step][o block][lane][4 complex]
-// One K16 step of a B operand is one contiguous block (it is staged through LDS whole).
-constexpr int FRAG_U16 = 512;  // bf16 entries of one array of one fragment
-
-template <int PREC>
-__device__ __forceinline__ typename Tile<PREC>::A frag_a(const void* base, int ks, int ob, int s, int lane) {
-  const size_t f = (size_t)ob * ks + s;
-  if constexpr (PREC == 1) {
-    const unsigned short* p = reinterpret_cast<const unsigned short*>(base) + f * 2 * FRAG_U16 + lane * 8;
-    return typename Tile<1>::A{ld8(p), ld8(p + FRAG_U16)};
-  } else {
-    const float4* p = reinterpret_cast<const float4*>(base) + (f * 64 + lane) * 2;
-    const float4 u = p[0], w = p[1];
-    return typename Tile<0>::A{{make_float2(u.x, u.y), make_float2(u.z, u.w), make_float2(w.x, w.y),
-                                make_float2(w.z, w.w)}};
-  }
-}
-
-template <int PREC>
-__device__ __forceinline__ typename Tile<PREC>::B frag_b(const void* base, int obs, int ob, int s, int lane) {
-  if constexpr (PREC == 1) {
-    const size_t arr = (size_t)obs * FRAG_U16;
-    const unsigned short* p =
-        reinterpret_cast<const unsigned short*>(base) + (size_t)s * 4 * arr + (size_t)ob * FRAG_U16 + lane * 8;
-    return typename Tile<1>::B{ld8(p), ld8(p + arr), ld8(p + 2 * arr), ld8(p + 3 * arr)};
-  } else {
-    const float4* p = reinterpret_cast<const float4*>(base) + (((size_t)s * obs + ob) * 64 + lane) * 2;
-    const float4 u = p[0], w = p[1];
-    return typename Tile<0>::B{{make_float2(u.x, u.y), make_float2(u.z, u.w), make_float2(w.x, w.y),
-                                make_float2(w.z, w.w)}};
-  }
-}
-
-// Store a fragment built from four complex values per lane.
-template <int PREC>
-__device__ __forceinline__ void put_frag_a(void* base, int ks, int ob, int s, int lane, const float2 (&v)[4]) {
-  const size_t f = (size_t)ob * ks + s;
-  if constexpr (PREC == 1) {
-    const typename Tile<1>::A a = Tile<1>::make_a(v);
-    unsigned short* p = reinterpret_cast<unsigned short*>(base) + f * 2 * FRAG_U16 + lane * 8;
-    st8(p, a.h);
-    st8(p + FRAG_U16, a.l);
-  } else {
-    float4* p = reinterpret_cast<float4*>(base) + (f * 64 + lane) * 2;
-    p[0] = make_float4(v[0].x, v[0].y, v[1].x, v[1].y);
-    p[1] = make_float4(v[2].x, v[2].y, v[3].x, v[3].y);
-  }
-}
-
-template <int PREC>
-__device__ __forceinline__ void put_frag_b(void* base, int obs, int ob, int s, int lane, const float2 (&v)[4]) {
-  if constexpr (PREC == 1) {
-    const typename Tile<1>::B b = Tile<1>::make_b(v);
-    const size_t arr = (size_t)obs * FRAG_U16;
-    unsigned short* p = reinterpret_cast<unsigned short*>(base) + (size_t)s * 4 * arr + (size_t)ob * FRAG_U16 + lane * 8;
-    st8(p, b.rh);
-    st8(p + arr, b.rl);
-    st8(p + 2 * arr, b.ih);
-    st8(p + 3 * arr, b.il);
-  } else {
-    float4* p = reinterpret_cast<float4*>(base) + (((size_t)s * obs + ob) * 64 + lane) * 2;
-    p[0] = make_float4(v[0].x, v[0].y, v[1].x, v[1].y);
-    p[1] = make_float4(v[2].x, v[2].y, v[3].x, v[3].y);
-  }
-}
-
-// An accumulator tile as the B fragment of step s (its rows become the reduction index).
-template <int PREC>
-__device__ __forceinline__ void put_tile_b(void* base, int obs, int ob, int s, int lane, const f32x4& cr,
-                                           const f32x4& ci) {
-  float2 v[4];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) v[t] = make_float2(cr[t], ci[t]);
-  put_frag_b<PREC>(base, obs, ob, s, lane, v);
-}
-
-// Bytes of one K16 step of a B-type operand with obs o blocks.
-template <int PREC>
-__host__ __device__ constexpr int frag_b_step_bytes(int obs) { return obs * (PREC == 1 ? 4 * 1024 : 2048); }
 
 // ---------------------------------------------------------------- plane geometry
 template <int N0, int N1>

@@ -43,6 +43,9 @@ CASES = {
                                              basis="tucker", mask="lines3d", frac=0.3),
     "tucker3d_12x10x8_r5x4x3_K20_J65": dict(seed=118, dims=(12, 10, 8), ranks=(5, 4, 3), J=65, K=20,
                                             basis="tucker", mask="lines3d", frac=0.3),
+    # fused path with a readout rank above the third-mode kernels' limit (GEMM fallback)
+    "fused_32x16x80_r5x6x70_K9_J2": dict(seed=119, dims=(32, 16, 80), ranks=(5, 6, 70), J=2, K=9,
+                                         basis="tucker", mask="lines3d", frac=0.3),
     # radial sampling (KB NUFFT, W = 6, sigma = 2, ramp density compensation in the loss)
     "radial_32x24_J3_K9_7spokes": dict(seed=113, dims=(32, 24), J=3, K=9, mask="radial", spokes=7, weights=True),
     "radial_40x30_J2_K6_5spokes": dict(seed=114, dims=(40, 30), J=2, K=6, mask="radial", spokes=5, n_read=48),
@@ -50,7 +53,8 @@ CASES = {
                                        n_read=512, weights=True),
 }
 FUSED = {"tucker3d_32x32x32_r12_K70_J4", "fused_48x32x20_r9x13x5_K23_J5", "fused_16x80x12_r3x17x4_K11_J3",
-         "fused_128x128x64_r40_K60_J5", "fused_64x64x32_r20_K30_J3", "fused_32x32x16_r9x10x11_K150_J64"}
+         "fused_128x128x64_r40_K60_J5", "fused_64x64x32_r20_K30_J3", "fused_32x32x16_r9x10x11_K150_J64",
+         "fused_32x16x80_r5x6x70_K9_J2"}
 
 _cache = {}
 
