@@ -520,7 +520,7 @@ constexpr int LMAXN = 256; // max n2 on this path
 template <int N2>
 __device__ __forceinline__ void line_fft(const LineArgs& a, float2* tile, const float2* tw, int n, int dir) {
   if constexpr (N2 != 0) {
-    lds_fft_ct<N2, LNT, LMAXN * LT / 2>(tile, LT, 1, LT + 1, tw, dir);
+    lds_fft_ct<N2, LNT, N2 * LT>(tile, LT, 1, LT + 1, tw, dir);
   } else {
     LdsLines tg{LT, 1, LT + 1};
     lds_fft_lines<LNT, LMAXN * LT / 2>(tile, tg, n, a.rad2, a.nrad2, tw, dir);
@@ -529,8 +529,8 @@ __device__ __forceinline__ void line_fft(const LineArgs& a, float2* tile, const 
 
 template <int N2>
 __global__ __launch_bounds__(LNT) void line_fwd_kernel(LineArgs a) {
-  __shared__ float2 tile[LMAXN * (LT + 1)];
-  __shared__ float2 tw[LMAXN];
+  __shared__ float2 tile[(N2 ? N2 : LMAXN) * (LT + 1)];  // sized to the readout: more workgroups per CU
+  __shared__ float2 tw[N2 ? N2 : LMAXN];
   __shared__ double red[LNT];
   const int lblocks = (a.L + LT - 1) / LT;
   const int j = blockIdx.x / lblocks, l0 = (blockIdx.x % lblocks) * LT;
@@ -576,8 +576,8 @@ __global__ __launch_bounds__(LNT) void line_fwd_kernel(LineArgs a) {
 
 template <int N2>
 __global__ __launch_bounds__(LNT) void line_adj_kernel(LineArgs a) {
-  __shared__ float2 tile[LMAXN * (LT + 1)];
-  __shared__ float2 tw[LMAXN];
+  __shared__ float2 tile[(N2 ? N2 : LMAXN) * (LT + 1)];
+  __shared__ float2 tw[N2 ? N2 : LMAXN];
   const int lblocks = (a.L + LT - 1) / LT;
   const int j = blockIdx.x / lblocks, l0 = (blockIdx.x % lblocks) * LT;
   const int n = N2 ? N2 : a.n2, ES = LT + 1;
