@@ -42,7 +42,8 @@ constexpr int TW_OFF = PLANE_ELEMS;              // twiddles of n0 and n1 (2 x P
 constexpr int STAGE_OFF = TW_OFF + 2 * PMAX;     // W of the current coil, or two K16 steps of conj(U1)
 constexpr int STAGE_ELEMS = 3072;                // 24 KB
 constexpr int LDS_ELEMS = STAGE_OFF + STAGE_ELEMS;
-constexpr int FFT_CHUNK = PMAX * PMAX / 2;       // elements per register chunk of a pass
+constexpr int FFT_CHUNK_FWD = PMAX * PMAX;       // elements per register chunk of a transform pass
+constexpr int FFT_CHUNK_ADJ = PMAX * PMAX / 2;   // (the adjoint holds P and gx across it)
 constexpr int SCAT = 4;                          // samples per thread loaded ahead of the scatter
 
 // ---------------------------------------------------------------- plane geometry
@@ -91,7 +92,8 @@ __device__ __forceinline__ void load_twiddles(const PlaneArgs& a, const Geo<N0, 
 }
 
 // 2D centred DFT of the plane (chessboard signs applied by the caller); ends synchronised.
-template <int N0, int N1>
+// CH elements of a pass are held in registers at a time.
+template <int CH, int N0, int N1>
 __device__ __forceinline__ void plane_fft(const PlaneArgs& a, const Geo<N0, N1>& g, float2* lds, int dir) {
   const float2* tw0 = lds + TW_OFF;
   const float2* tw1 = tw0 + PMAX;
@@ -99,18 +101,18 @@ __device__ __forceinline__ void plane_fft(const PlaneArgs& a, const Geo<N0, N1>&
   asm volatile("" : "+v"(tid));
   auto rows = [&]() {
     if constexpr (N1 != 0) {
-      lds_fft_ct<N1, PT, FFT_CHUNK>(lds, g.n0, g.PS, 1, tw1, dir, tid);
+      lds_fft_ct<N1, PT, CH>(lds, g.n0, g.PS, 1, tw1, dir, tid);
     } else {
       LdsLines t{g.n0, g.PS, 1};
-      lds_fft_lines<PT, FFT_CHUNK>(lds, t, g.n1, a.rad1, a.nrad1, tw1, dir);
+      lds_fft_lines<PT, CH>(lds, t, g.n1, a.rad1, a.nrad1, tw1, dir);
     }
   };
   auto cols = [&]() {
     if constexpr (N0 != 0) {
-      lds_fft_ct<N0, PT, FFT_CHUNK>(lds, g.n1, 1, g.PS, tw0, dir, tid);
+      lds_fft_ct<N0, PT, CH>(lds, g.n1, 1, g.PS, tw0, dir, tid);
     } else {
       LdsLines t{g.n1, 1, g.PS};
-      lds_fft_lines<PT, FFT_CHUNK>(lds, t, g.n0, a.rad0, a.nrad0, tw0, dir);
+      lds_fft_lines<PT, CH>(lds, t, g.n0, a.rad0, a.nrad0, tw0, dir);
     }
   };
   if (dir < 0) { rows(); cols(); } else { cols(); rows(); }
@@ -327,16 +329,18 @@ __global__ __launch_bounds__(PT) void plane_fwd_kernel(PlaneArgs a) {
 #pragma unroll
   for (int k = 0; k < SCAT; ++k) pq[k] = (int)threadIdx.x + k * PT < a.L ? a.pos[threadIdx.x + k * PT] : -1;
   load_twiddles(a, g, lds);
-  for (int j = gi * a.G; j < a.J && j < (gi + 1) * a.G; ++j) {
+  const int j0 = gi * a.G, j1 = min(a.J, (gi + 1) * a.G);
+  WPrefetch w;  // W of the next coil, loaded one coil ahead
+  if (j0 < j1) w_load(a, g, j0, i2, threadIdx.x, w);
+  for (int j = j0; j < j1; ++j) {
     // lane and thread index through an empty asm: per-coil addresses are recomputed
     // here rather than hoisted out of the coil loop and held across the transform
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
     const int lane = tid & 63, grp = lane >> 4;
-    WPrefetch w;
-    w_load(a, g, j, i2, tid, w);
     f32x4 pr[8], pi[8];
     coil_map<PREC>(a, g, lds, sh, lane, tid, w, pr, pi);
+    if (j + 1 < j1) w_load(a, g, j + 1, i2, tid, w);
     // m = x (.) P with the input chessboard sign
     if (sh.on) {
 #pragma unroll
@@ -355,7 +359,7 @@ __global__ __launch_bounds__(PT) void plane_fwd_kernel(PlaneArgs a) {
       }
     }
     __syncthreads();
-    plane_fft(a, g, lds, -1);
+    plane_fft<FFT_CHUNK_FWD>(a, g, lds, -1);
     float2* zo = a.Z + ((size_t)j * g.n2 + i2) * a.L;
 #pragma unroll
     for (int k = 0; k < SCAT; ++k)
@@ -426,7 +430,7 @@ __global__ __launch_bounds__(PT) void plane_adj_kernel(PlaneArgs a) {
       lds[k0 * g.PS + k1] = v;
     }
     __syncthreads();
-    plane_fft(a, g, lds, +1);
+    plane_fft<FFT_CHUNK_ADJ>(a, g, lds, +1);
     // g (output chessboard sign); gx += conj(P) g in registers; h = conj(x) g into the plane.
     // x in two batches of four tiles, each batch's loads issued together.
     if (sh.on) {
