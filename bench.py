@@ -42,6 +42,11 @@ def parse():
     ap.add_argument("--precision", default="bf16_split", choices=["bf16_split", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the second-precision run")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="first run one plain device copy of MIB MiB (calibrates rocprofv3 byte counters)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) made with --copy-probe "
+                         "into the per-launch HBM traffic file under profiles/, then exit")
     return ap.parse_args()
 
 
@@ -68,6 +73,77 @@ def time_steps(step, steps, warmup, torch):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return e0.elapsed_time(e1) / steps, wall
+
+
+WORKLOAD = "cart3d_128_tucker40x300_j32"
+KERNEL_SOURCES = {  # sources whose change invalidates a recorded traffic figure
+    "plane_adj": ["tucker_fused.hip", "fused.h", "fft_device.h", "mfma_frag.h"],
+    "plane_fwd": ["tucker_fused.hip", "fused.h", "fft_device.h", "mfma_frag.h"],
+}
+KERNEL_SYMBOLS = {"plane_adj": "plane_adj_kernel<1, 128, 128>", "plane_fwd": "plane_fwd_kernel<1, 128, 128>"}
+
+
+def source_hash(kernel):
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES.get(kernel, []):
+        with open(os.path.join(ROOT, "paper_2008_09042_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_file(kernel):
+    return os.path.join(ROOT, "profiles", f"traffic_{kernel}_{WORKLOAD}.txt")
+
+
+def recorded_traffic(kernel):
+    """HBM bytes per launch from the recorded counter runs, or None if absent or stale."""
+    path = traffic_file(kernel)
+    if kernel not in KERNEL_SOURCES or not os.path.exists(path):
+        return None
+    kv = dict(l.strip().split("=", 1) for l in open(path) if "=" in l and not l.startswith("#"))
+    if kv.get("source_sha256_16") != source_hash(kernel):
+        return None
+    return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
+
+
+def traffic_from(fetch_dir, write_dir, probe_mib):
+    """Per-launch FETCH_SIZE / WRITE_SIZE of the dominant kernels, scaled by the copy probe."""
+    import csv
+    import glob
+
+    def per_kernel(d, counter):
+        f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
+        acc = {}
+        for r in csv.DictReader(open(f)):
+            if r["Counter_Name"] != counter:
+                continue
+            acc.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return acc
+
+    known = probe_mib * 2**20
+    out = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        acc = per_kernel(d, counter)
+        copies = [v for k, v in acc.items() if "MulFunctor" in k]
+        probe = max(max(v) for v in copies) * 1024.0  # KiB -> bytes; the probe is the largest multiply
+        factor = known / probe
+        for kernel, sym in KERNEL_SYMBOLS.items():
+            vals = [v for k, vs in acc.items() if sym in k for v in vs]
+            if vals:
+                out.setdefault(kernel, {})[counter] = (sum(vals) / len(vals) * 1024.0 * factor, factor, len(vals))
+    for kernel, c in out.items():
+        if "FETCH_SIZE" not in c or "WRITE_SIZE" not in c:
+            continue
+        with open(traffic_file(kernel), "w") as fh:
+            fh.write(f"# HBM traffic per launch of {KERNEL_SYMBOLS[kernel]}, workload {WORKLOAD}\n")
+            fh.write(f"# rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (KiB per dispatch), averaged over "
+                     f"{c['FETCH_SIZE'][2]} dispatches, scaled so that a {probe_mib} MiB streaming kernel (x 2) reads and "
+                     f"writes {probe_mib} MiB\n")
+            fh.write(f"fetch_scale={c['FETCH_SIZE'][1]:.4f}\nwrite_scale={c['WRITE_SIZE'][1]:.4f}\n")
+            fh.write(f"fetch_bytes_per_launch={c['FETCH_SIZE'][0]:.0f}\nwrite_bytes_per_launch={c['WRITE_SIZE'][0]:.0f}\n")
+            fh.write(f"source_sha256_16={source_hash(kernel)}\n")
+        log(f"[bench] wrote {traffic_file(kernel)}")
 
 
 def kernel_work(name, p, prec):
@@ -128,6 +204,9 @@ def cpu_baseline(p, coils=32, repeats=2):
 
 def main():
     args = parse()
+    if args.traffic_from:
+        traffic_from(args.traffic_from[0], args.traffic_from[1], args.copy_probe or 256)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1 "
                                    "(the coil-sharded multi-GPU design is documented but not built)"}))
@@ -136,6 +215,14 @@ def main():
     from paper_2008_09042_amd.encoding import MaxwellDataFidelity, MaxwellPlan
 
     dev = torch.device("cuda:0")
+    if args.copy_probe:
+        # one streaming kernel that reads and writes exactly MIB MiB (float32 scale by 2)
+        n = args.copy_probe * 2**20 // 4
+        src = torch.ones(n, device=dev)
+        dst = torch.empty_like(src)
+        torch.mul(src, 2.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     p = make_inputs()
     T = lambda a: torch.from_numpy(np.ascontiguousarray(np.asarray(a).astype(np.complex64))).to(dev)  # noqa: E731
     U = [T(u) for u in p.U]
@@ -215,7 +302,7 @@ def main():
         avg_s = kernels[dom]["avg_us"] * 1e-6
         achieved = amount / avg_s / (1e12 if unit == "TFLOP/s" else 1e9)
         out["roofline"] = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-                           "frac": achieved / peak, "traffic": None,
+                           "frac": achieved / peak, "traffic": recorded_traffic(dom),
                            "per_launch": amount, "avg_launch_us": kernels[dom]["avg_us"]}
     out["kernels"] = kernels
     if not args.no_cpu_baseline:
