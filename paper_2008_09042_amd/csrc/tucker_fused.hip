@@ -83,6 +83,19 @@ __device__ __forceinline__ Share plane_share(const Geo<N0, N1>& g) {
   return s;
 }
 
+// Workgroup -> (plane i2, coil group).  Consecutive workgroups are dispatched to the 8
+// XCDs in turn, each with its own L2; the mapping gives every XCD a contiguous range of
+// planes, so the groups of one plane share an L2 (and its x plane) while they run.
+constexpr int NXCD = 8;
+
+__device__ __forceinline__ void plane_block(int ngrp, int n2, int& i2, int& grp) {
+  const int nb = ngrp * n2;
+  int l = blockIdx.x;
+  if (nb % NXCD == 0) l = (blockIdx.x % NXCD) * (nb / NXCD) + blockIdx.x / NXCD;
+  i2 = l / ngrp;
+  grp = l % ngrp;
+}
+
 template <int N0, int N1>
 __device__ __forceinline__ void load_twiddles(const PlaneArgs& a, const Geo<N0, N1>& g, float2* lds) {
   float2* tw0 = lds + TW_OFF;
@@ -322,7 +335,8 @@ __global__ __launch_bounds__(PT) void plane_fwd_kernel(PlaneArgs a) {
   __shared__ float2 lds[LDS_ELEMS];
   const Geo<N0, N1> g(a);
   const int ngrp = (a.J + a.G - 1) / a.G;
-  const int i2 = blockIdx.x / ngrp, gi = blockIdx.x % ngrp;
+  int i2, gi;
+  plane_block(ngrp, g.n2, i2, gi);
   const float2* xp = a.xt + (size_t)i2 * g.n0 * g.n1;
   const Share sh = plane_share(g);
   int pq[SCAT];  // sampled plane positions, the same for every coil
@@ -385,7 +399,8 @@ __global__ __launch_bounds__(PT) void plane_adj_kernel(PlaneArgs a) {
   __shared__ float2 lds[LDS_ELEMS];
   const Geo<N0, N1> g(a);
   const int ngrp = (a.J + a.G - 1) / a.G;
-  const int i2 = blockIdx.x / ngrp, gi = blockIdx.x % ngrp;
+  int i2, gi;
+  plane_block(ngrp, g.n2, i2, gi);
   const float2* xp = a.xt + (size_t)i2 * g.n0 * g.n1;
   const bool want_gx = a.gxpart != nullptr;
   const Share sh = plane_share(g);
