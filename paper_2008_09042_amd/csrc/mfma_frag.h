@@ -186,6 +186,15 @@ __device__ __forceinline__ void put_frag_b(void* base, int obs, int ob, int s, i
   }
 }
 
+// An accumulator tile as the lane's B fragment of one K16 step (its rows become k).
+template <int PREC>
+__device__ __forceinline__ typename Tile<PREC>::B tile_as_b(const f32x4& cr, const f32x4& ci) {
+  float2 v[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) v[t] = make_float2(cr[t], ci[t]);
+  return Tile<PREC>::make_b(v);
+}
+
 // An accumulator tile as the B fragment of step s (its rows become the reduction index).
 template <int PREC>
 __device__ __forceinline__ void put_tile_b(void* base, int obs, int ob, int s, int lane, const f32x4& cr,

@@ -38,10 +38,12 @@ constexpr int NWAVE = PT / 64;
 constexpr int PMAX = 128;                        // max n0, n1 on this path
 constexpr int RMAX = 48;                         // max r0, r1 on this path (three K16 blocks)
 constexpr int PLANE_ELEMS = PMAX * (PMAX + 1);   // padded plane: 16,512 complex = 132 KB
-constexpr int TW_OFF = PLANE_ELEMS;              // twiddles of n0 and n1 (2 x PMAX)
-constexpr int STAGE_OFF = TW_OFF + 2 * PMAX;     // W of the current coil, or two K16 steps of conj(U1)
+constexpr int STAGE_OFF = PLANE_ELEMS;           // W of the current coil, or two K16 steps of conj(U1)
 constexpr int STAGE_ELEMS = 3072;                // 24 KB
-constexpr int LDS_ELEMS = STAGE_OFF + STAGE_ELEMS;
+constexpr int TW_OFF = STAGE_OFF + STAGE_ELEMS;  // twiddles of n0 and n1 (2 x PMAX), kept for the workgroup
+constexpr int LDS_ELEMS = TW_OFF + 2 * PMAX;
+// the adjoint's Wb partials (8 waves x 9 tiles x 256) overwrite the plane and staging regions
+static_assert(NWAVE * 9 * 256 <= PLANE_ELEMS + STAGE_ELEMS, "Wb partials must fit");
 constexpr int FFT_CHUNK_FWD = PMAX * PMAX;       // elements per register chunk of a transform pass
 constexpr int FFT_CHUNK_ADJ = PMAX * PMAX / 2;   // (the adjoint holds P and gx across it)
 constexpr int SCAT = 4;                          // samples per thread loaded ahead of the scatter
@@ -211,8 +213,7 @@ __device__ __forceinline__ void coil_p(const Geo<N0, N1>& g, const float2* lds, 
 
 // ---------------------------------------------------------------- adjoint contraction
 // Y = h conj(U1) with h in the plane, then Wb = U0^H Y -> T3b[j][i2].  Wave w takes Y row
-// block w % n0b over a 1 / q share of the K16 steps over i1; the q partial copies of Y
-// are stored side by side as extra reduction steps of Wb.  conj(U1) is staged through
+// block w % n0b over a 1 / q share of the K16 steps over i1.  conj(U1) is staged through
 // two LDS step buffers, each thread carrying the pieces of the next two steps in
 // registers (loads issued two steps ahead).  Ends synchronised.
 template <int PREC, int N0, int N1>
@@ -276,38 +277,39 @@ __device__ __forceinline__ void adjoint_w(const PlaneArgs& a, const Geo<N0, N1>&
       __syncthreads();
     }
   }
-  // the first Wb tile's U0^H fragments, in flight across the Y store
-  const int mb0 = wave / g.r1b;
-  typename Tile<PREC>::A ua[8];
-  if (wave < g.r0b * g.r1b) {
-#pragma unroll
-    for (int s = 0; s < 8; ++s)
-      if (s < g.n0b) ua[s] = frag_a<PREC>(a.U0HF, g.n0b, mb0, s, lane);
-  }
+  // Wb = U0^H Y.  The wave's Y tiles (rows = Y row block yb) are one K16 step of Wb: every
+  // wave forms Wb's partial over its rows and its share of i1, and the partials are summed
+  // in wave order through the plane and staging regions (free after the loop's last barrier).
   if (on) {
+    typename Tile<PREC>::B yf[3];
 #pragma unroll
     for (int nb = 0; nb < 3; ++nb)
-      if (nb < g.r1b) put_tile_b<PREC>(lds, g.r1b, nb, kq * g.n0b + yb, lane, yr[nb], yi[nb]);
+      if (nb < g.r1b) yf[nb] = tile_as_b<PREC>(yr[nb], yi[nb]);
+#pragma unroll
+    for (int mb = 0; mb < 3; ++mb)
+      if (mb < g.r0b) {
+        const typename Tile<PREC>::A ua = frag_a<PREC>(a.U0HF, g.n0b, mb, yb, lane);
+#pragma unroll
+        for (int nb = 0; nb < 3; ++nb)
+          if (nb < g.r1b) {
+            f32x4 wr = z4(), wi = z4();
+            Tile<PREC>::mma(wr, wi, ua, yf[nb]);
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              lds[((wave * 3 + mb) * 3 + nb) * 256 + (4 * grp + r) * 16 + (lane & 15)] = make_float2(wr[r], wi[r]);
+          }
+      }
   }
   __syncthreads();
+  const int nw = qy * g.n0b;  // waves with a share (the first nw)
+  const int c1 = 16 * g.r1b, nout = 16 * g.r0b * c1;
   float2* wo = a.T3b + ((size_t)j * g.n2 + i2) * g.r0 * g.r1;
-  for (int blk = wave; blk < g.r0b * g.r1b; blk += NWAVE) {
-    const int mb = blk / g.r1b, nb = blk % g.r1b;
-    if (blk != wave) {
-#pragma unroll
-      for (int s = 0; s < 8; ++s)
-        if (s < g.n0b) ua[s] = frag_a<PREC>(a.U0HF, g.n0b, mb, s, lane);
-    }
-    f32x4 cr = z4(), ci = z4();
-#pragma unroll
-    for (int s = 0; s < 8; ++s)
-      if (s < g.n0b)
-        for (int q = 0; q < qy; ++q) Tile<PREC>::mma(cr, ci, ua[s], frag_b<PREC>(lds, g.r1b, nb, q * g.n0b + s, lane));
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int q0 = 16 * mb + 4 * grp + r, q1 = 16 * nb + (lane & 15);
-      if (q0 < g.r0 && q1 < g.r1) wo[q0 * g.r1 + q1] = make_float2(cr[r], ci[r]);
-    }
+  for (int e = tid; e < nout; e += PT) {
+    const int q0 = e / c1, q1 = e % c1;
+    const int o = ((q0 >> 4) * 3 + (q1 >> 4)) * 256 + (q0 & 15) * 16 + (q1 & 15);
+    float2 acc = make_float2(0.f, 0.f);
+    for (int w = 0; w < nw; ++w) acc = cadd(acc, lds[w * 9 * 256 + o]);
+    if (q0 < g.r0 && q1 < g.r1) wo[q0 * g.r1 + q1] = acc;
   }
   __syncthreads();
 }
