@@ -232,11 +232,26 @@ __device__ __forceinline__ void stockham_pass_ct(float2* lds, int T, int LS, int
 #pragma unroll
         for (int r = 0; r < R; ++r) v[q][r] = lds[base + (j + r * nR) * ES];
         if (Ns > 1) {
+          // twiddles w^(k r), r < R, from the table entries for r = 1, 2, 4, 8: each is a
+          // product of at most three of them (a few ulp), which saves LDS reads
           const int k = j % Ns;
+          float2 wp[4];
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            if ((1 << b) < R) {
+              wp[b] = tw[k * (1 << b) * STW];
+              if (dir > 0) wp[b].y = -wp[b].y;
+            }
 #pragma unroll
           for (int r = 1; r < R; ++r) {
-            float2 w = tw[k * r * STW];
-            if (dir > 0) w.y = -w.y;
+            float2 w = make_float2(1.f, 0.f);
+            bool first = true;
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+              if (r & (1 << b)) {
+                w = first ? wp[b] : cmul(w, wp[b]);
+                first = false;
+              }
             v[q][r] = cmul(v[q][r], w);
           }
         }
