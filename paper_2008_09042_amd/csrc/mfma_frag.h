@@ -33,13 +33,17 @@ __device__ __forceinline__ unsigned short bf16_rne(float f) {
 }
 __device__ __forceinline__ float bf16_f32(unsigned short h) { return __uint_as_float(((unsigned)h) << 16); }
 
+// hi = bf16(v), lo = bf16(v - hi), both rounded to nearest even.  The conversions are the
+// hardware's packed FP32 -> BF16 converts (same rounding as bf16_rne for finite values).
 __device__ __forceinline__ void split8(const float (&v)[8], u16x8& hi, u16x8& lo) {
+  typedef float f32x8 __attribute__((ext_vector_type(8)));
+  f32x8 x;
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const unsigned short h = bf16_rne(v[e]);
-    hi[e] = h;
-    lo[e] = bf16_rne(v[e] - bf16_f32(h));
-  }
+  for (int e = 0; e < 8; ++e) x[e] = v[e];
+  const bf16x8 h = __builtin_convertvector(x, bf16x8);
+  const f32x8 r = x - __builtin_convertvector(h, f32x8);
+  hi = __builtin_bit_cast(u16x8, h);
+  lo = __builtin_bit_cast(u16x8, __builtin_convertvector(r, bf16x8));
 }
 
 __device__ __forceinline__ bf16x8 asbf(u16x8 v) { return __builtin_bit_cast(bf16x8, v); }
