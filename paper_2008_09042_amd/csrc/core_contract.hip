@@ -6,167 +6,115 @@
 //   adjoint  gc[j][k]   = s * sum_rho conj(core[rho][k]) T1b[j][rho]
 //
 // Both stream the core (R x K complex) from HBM once per call, as the matrix-core A
-// operand; the small per-call operand (c or T1b) is staged through double-buffered LDS
-// shared by the workgroup's four waves.
+// operand.
 //
-// FP32 kernels: v_mfma_f32_16x16x4_f32, four real products per complex product.
 // BF16-split kernels: real-block form over 2K on v_mfma_f32_16x16x32_bf16, six products
 // per complex tile (hi*hi, hi*lo, lo*hi for the real and imaginary parts).  The core's
 // hi / lo planes are built once per plan in fragment order (row-major for the forward,
-// conjugate-transposed for the adjoint); the per-call operand is split while staged.
+// conjugate-transposed for the adjoint).  Waves are independent: each loads its core
+// fragments and its lanes' entries of the small per-call operand (c or T1b, L2-resident)
+// itself, FD reduction steps ahead, and splits the latter in registers.  No LDS and no
+// barriers, so the loads of several steps stay in flight.
+// FP32 kernels: v_mfma_f32_16x16x4_f32, four real products per complex product, with the
+// per-call operand staged through double-buffered LDS shared by the workgroup's waves.
 // The adjoint reduces over rho in chunks whose partials are summed in a fixed order.
 #include "../../include/maxwell.h"
 #include "core.h"
+#include "mfma_frag.h"
 
 namespace mx {
-
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
 namespace {
 
 constexpr int NT = 256;     // four waves
 constexpr int MAXNB = 4;    // coil blocks of 16: J <= 64
-constexpr int RB = 2;       // row blocks of 16 per wave
+constexpr int RB = 2;       // FP32 kernels: row blocks of 16 per wave
 constexpr int RC = 512;     // adjoint: rho per workgroup chunk
-constexpr int SLB = 40;     // staged bf16 row: 32 k' + 8 pad
+// BF16-split kernels: reduction steps whose loads are in flight, and row blocks per wave
+// (more rows per load of the per-call operand where the accumulators of NB coil blocks
+// leave room).  Measured at R = 64000, K = 300, J = 32.
+constexpr int FWD_FD = 2, ADJ_FD = 3;
+constexpr int FWD_RB_FEW = 4, FWD_RB_MANY = 2;  // NB <= 2, NB > 2
+constexpr int ADJ_RB_FEW = 3, ADJ_RB_MANY = 2;
 
-__device__ __forceinline__ f32x4 z4() { return f32x4{0.f, 0.f, 0.f, 0.f}; }
-
-__device__ __forceinline__ void cmfma(f32x4& cr, f32x4& ci, float2 a, float2 b) {
-  cr = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, cr, 0, 0, 0);
-  cr = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.y, b.y, cr, 0, 0, 0);
-  ci = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.y, ci, 0, 0, 0);
-  ci = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.x, ci, 0, 0, 0);
-}
-
-__device__ __forceinline__ unsigned short bf16_rne(float f) {
-  unsigned u = __float_as_uint(f);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
-__device__ __forceinline__ float bf16_f32(unsigned short h) { return __uint_as_float(((unsigned)h) << 16); }
-__device__ __forceinline__ bf16x8 asbf(u16x8 v) { return __builtin_bit_cast(bf16x8, v); }
-__device__ __forceinline__ u16x8 ld8(const unsigned short* p) { return *reinterpret_cast<const u16x8*>(p); }
-__device__ __forceinline__ void st8(unsigned short* p, u16x8 v) { *reinterpret_cast<u16x8*>(p) = v; }
-__device__ __forceinline__ u16x8 zero8() { return u16x8{0, 0, 0, 0, 0, 0, 0, 0}; }
-
-__device__ __forceinline__ void mfma6(f32x4& cr, f32x4& ci, u16x8 ah, u16x8 al, u16x8 brh, u16x8 brl, u16x8 bih,
-                                      u16x8 bil) {
-  cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(asbf(ah), asbf(brh), cr, 0, 0, 0);
-  cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(asbf(ah), asbf(brl), cr, 0, 0, 0);
-  cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(asbf(al), asbf(brh), cr, 0, 0, 0);
-  ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(asbf(ah), asbf(bih), ci, 0, 0, 0);
-  ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(asbf(ah), asbf(bil), ci, 0, 0, 0);
-  ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(asbf(al), asbf(bih), ci, 0, 0, 0);
-}
-
-// Real-block B operand of four consecutive complex reduction entries b[t]:
-// br = (Re b, -Im b), bi = (Im b, Re b), each split into hi / lo.
-__device__ __forceinline__ void split_b4(const float2 (&v)[4], u16x8& brh, u16x8& brl, u16x8& bih, u16x8& bil) {
+// Lane operand of the per-call matrix src [rows][len] for one K16 step starting at e0:
+// src[j][e0 + 4 g + t], t < 4, j = 16 cb + lane % 16.  Rows past the last and entries
+// past len are clamped into the matrix; they meet zero core entries or are not stored.
+template <int NB>
+__device__ __forceinline__ void call_operand(const float2* const (&row)[NB], int64_t e0, int64_t len, int grp,
+                                             float2 (&v)[NB][4]) {
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const float q[4] = {v[t].x, -v[t].y, v[t].y, v[t].x};
-    unsigned short h[4], l[4];
+  for (int cb = 0; cb < NB; ++cb)
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      h[u] = bf16_rne(q[u]);
-      l[u] = bf16_rne(q[u] - bf16_f32(h[u]));
-    }
-    brh[2 * t] = h[0]; brh[2 * t + 1] = h[1];
-    brl[2 * t] = l[0]; brl[2 * t + 1] = l[1];
-    bih[2 * t] = h[2]; bih[2 * t + 1] = h[3];
-    bil[2 * t] = l[2]; bil[2 * t + 1] = l[3];
-  }
-}
-
-// Stages 16 complex reduction entries (one 32-wide k' step) of the J rows of `src`
-// (row stride ld, entries [e0, e0 + 16) clipped at len) into the four planes of sb.
-__device__ __forceinline__ void stage_split(unsigned short (*sb)[MAXNB * 16][SLB], const float2* __restrict__ src,
-                                            int J, int Jp, int64_t ld, int64_t e0, int64_t len) {
-  for (int e = threadIdx.x; e < Jp * 4; e += NT) {
-    const int j = e >> 2, q = e & 3;
-    float2 v[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int64_t k = e0 + 4 * q + t;
-      v[t] = (j < J && k < len) ? src[(int64_t)j * ld + k] : make_float2(0.f, 0.f);
-    }
-    u16x8 brh, brl, bih, bil;
-    split_b4(v, brh, brl, bih, bil);
-    st8(&sb[0][j][8 * q], brh);
-    st8(&sb[1][j][8 * q], brl);
-    st8(&sb[2][j][8 * q], bih);
-    st8(&sb[3][j][8 * q], bil);
-  }
+    for (int t = 0; t < 4; ++t) v[cb][t] = row[cb][min(e0 + 4 * grp + t, len - 1)];
 }
 
 // ---------------------------------------------------------------- forward, BF16-split
-// Workgroup: 8 row blocks (128 rho), all coils.
+// One wave: RB row blocks (16 RB rho) against all NB coil blocks.
+template <int NB, int RB, int FD = FWD_FD>
 __global__ __launch_bounds__(NT) void core_fwd_bf16_kernel(CoreArgs a) {
-  __shared__ __attribute__((aligned(16))) unsigned short sb[2][4][MAXNB * 16][SLB];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nb = (a.J + 15) / 16, Jp = nb * 16;
+  const int lane = threadIdx.x & 63, grp = lane >> 4;
   const int steps = a.g.KP / 32;
   const int64_t rbs = (a.g.R + 15) / 16;
-  const int64_t rb0 = (int64_t)blockIdx.x * (4 * RB) + wave * RB;
-  auto loadA = [&](int s, u16x8 (&ah)[RB], u16x8 (&al)[RB]) {
+  const int64_t rb0 = ((int64_t)blockIdx.x * (NT / 64) + (threadIdx.x >> 6)) * RB;
+  if (rb0 >= rbs) return;
+  int64_t oa[RB];
+#pragma unroll
+  for (int m = 0; m < RB; ++m) oa[m] = min(rb0 + m, rbs - 1) * steps * 512 + lane * 8;
+  const float2* row[NB];
+#pragma unroll
+  for (int cb = 0; cb < NB; ++cb) row[cb] = a.in + (int64_t)min(16 * cb + (lane & 15), a.J - 1) * a.g.K;
+  u16x8 ah[FD][RB], al[FD][RB];
+  float2 bv[FD][NB][4];
+  auto load = [&](int d, int s) {
+    s = min(s, steps - 1);
 #pragma unroll
     for (int m = 0; m < RB; ++m) {
-      if (rb0 + m < rbs) {
-        const int64_t o = ((rb0 + m) * steps + s) * 512 + lane * 8;
-        ah[m] = ld8(a.fwd_hi + o);
-        al[m] = ld8(a.fwd_lo + o);
-      } else {
-        ah[m] = zero8();
-        al[m] = zero8();
-      }
+      ah[d][m] = ld8(a.fwd_hi + oa[m] + (int64_t)s * 512);
+      al[d][m] = ld8(a.fwd_lo + oa[m] + (int64_t)s * 512);
     }
+    call_operand<NB>(row, 16 * (int64_t)s, a.g.K, grp, bv[d]);
   };
-  f32x4 cr[RB][MAXNB], ci[RB][MAXNB];
+  f32x4 cr[RB][NB], ci[RB][NB];
 #pragma unroll
   for (int m = 0; m < RB; ++m)
 #pragma unroll
-    for (int c = 0; c < MAXNB; ++c) { cr[m][c] = z4(); ci[m][c] = z4(); }
-  u16x8 ah[RB], al[RB], nh[RB], nl[RB];
-  stage_split(sb[0], a.in, a.J, Jp, a.g.K, 0, a.g.K);
-  loadA(0, ah, al);
-  __syncthreads();
-  for (int s = 0; s < steps; ++s) {
-    if (s + 1 < steps) {
-      stage_split(sb[(s + 1) & 1], a.in, a.J, Jp, a.g.K, 16 * (int64_t)(s + 1), a.g.K);
-      loadA(s + 1, nh, nl);
+    for (int c = 0; c < NB; ++c) { cr[m][c] = z4(); ci[m][c] = z4(); }
+  auto compute = [&](int d) {
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      const Tile<1>::B b = Tile<1>::make_b(bv[d][c]);
+#pragma unroll
+      for (int m = 0; m < RB; ++m) mfma6(cr[m][c], ci[m][c], ah[d][m], al[d][m], b.rh, b.rl, b.ih, b.il);
     }
-    const int buf = s & 1;
+  };
+  // FD stages in flight; the issue order of the stages' loads is kept, so the wait before
+  // a stage's products only covers that stage's loads.
 #pragma unroll
-    for (int c = 0; c < MAXNB; ++c) {
-      if (c < nb) {
-        const int n = 16 * c + (lane & 15), ko = 8 * (lane >> 4);
-        const u16x8 b0 = ld8(&sb[buf][0][n][ko]), b1 = ld8(&sb[buf][1][n][ko]);
-        const u16x8 b2 = ld8(&sb[buf][2][n][ko]), b3 = ld8(&sb[buf][3][n][ko]);
+  for (int d = 0; d < FD; ++d) load(d, d);
+  int s0 = 0;
+  for (; s0 + FD <= steps; s0 += FD) {
 #pragma unroll
-        for (int m = 0; m < RB; ++m) mfma6(cr[m][c], ci[m][c], ah[m], al[m], b0, b1, b2, b3);
-      }
-    }
-    __syncthreads();
-    if (s + 1 < steps) {
-#pragma unroll
-      for (int m = 0; m < RB; ++m) { ah[m] = nh[m]; al[m] = nl[m]; }
+    for (int d = 0; d < FD; ++d) {
+      compute(d);
+      load(d, s0 + d + FD);
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
+#pragma unroll
+  for (int d = 0; d + 1 < FD; ++d)
+    if (s0 + d < steps) compute(d);
   // D rows are rho, columns coils: T1[j][rho]
 #pragma unroll
   for (int m = 0; m < RB; ++m)
 #pragma unroll
-    for (int c = 0; c < MAXNB; ++c)
-      if (c < nb)
+    for (int c = 0; c < NB; ++c)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int64_t row = 16 * (rb0 + m) + 4 * (lane >> 4) + r;
-          const int j = 16 * c + (lane & 15);
-          if (row < a.g.R && j < a.J) a.out[(int64_t)j * a.g.R + row] = make_float2(cr[m][c][r], ci[m][c][r]);
-        }
+      for (int r = 0; r < 4; ++r) {
+        const int64_t rw = 16 * (rb0 + m) + 4 * grp + r;
+        const int j = 16 * c + (lane & 15);
+        if (rw < a.g.R && j < a.J) a.out[(int64_t)j * a.g.R + rw] = make_float2(cr[m][c][r], ci[m][c][r]);
+      }
 }
 
 // ---------------------------------------------------------------- forward, FP32
@@ -228,72 +176,77 @@ __global__ __launch_bounds__(NT) void core_fwd_f32_kernel(CoreArgs a) {
 }
 
 // ---------------------------------------------------------------- adjoint, BF16-split
-// Grid (rho chunks, k groups of 8 row blocks).  D rows are k, columns coils.
-__global__ __launch_bounds__(NT) void core_adj_bf16_kernel(CoreArgs a) {
-  __shared__ __attribute__((aligned(16))) unsigned short sb[2][4][MAXNB * 16][SLB];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nb = (a.J + 15) / 16, Jp = nb * 16;
+// Workgroup: one rho chunk of RC, one group of 4 RB k row blocks (RB per wave); D rows
+// are k, columns coils.  The k groups of one chunk are placed on one XCD (workgroups are
+// dispatched round-robin over the 8 XCDs), so the chunk's T1b is fetched into one L2.
+template <int NB, int RB, int FD = ADJ_FD>
+__global__ __launch_bounds__(NT) void core_adj_bf16_kernel(CoreArgs a, int nch, int kgroups) {
+  const int xcd = blockIdx.x % 8, i = blockIdx.x / 8;
+  const int ky = i % kgroups, ch = 8 * (i / kgroups) + xcd;
+  const int lane = threadIdx.x & 63, grp = lane >> 4, wave = threadIdx.x >> 6;
   const int mbl = a.g.Kp / 16;
-  const int mb0 = blockIdx.y * (4 * RB) + wave * RB;
-  const int64_t rho0 = (int64_t)blockIdx.x * RC;
+  const int mb0 = ky * (4 * RB) + wave * RB;
+  if (ch >= nch || mb0 >= mbl) return;
+  const int64_t rho0 = (int64_t)ch * RC;
   const int64_t steps_total = a.g.Rp / 16;
-  const int64_t sg0 = rho0 / 16;
   constexpr int steps = RC / 16;
-  auto loadA = [&](int s, u16x8 (&ah)[RB], u16x8 (&al)[RB]) {
+  int64_t oa[RB];
+#pragma unroll
+  for (int m = 0; m < RB; ++m) oa[m] = ((int64_t)min(mb0 + m, mbl - 1) * steps_total + rho0 / 16) * 512 + lane * 8;
+  const float2* row[NB];
+#pragma unroll
+  for (int cb = 0; cb < NB; ++cb) row[cb] = a.in + (int64_t)min(16 * cb + (lane & 15), a.J - 1) * a.g.R;
+  u16x8 ah[FD][RB], al[FD][RB];
+  float2 bv[FD][NB][4];
+  auto load = [&](int d, int s) {
+    s = min(s, steps - 1);
 #pragma unroll
     for (int m = 0; m < RB; ++m) {
-      if (mb0 + m < mbl) {
-        const int64_t o = ((int64_t)(mb0 + m) * steps_total + sg0 + s) * 512 + lane * 8;
-        ah[m] = ld8(a.adj_hi + o);
-        al[m] = ld8(a.adj_lo + o);
-      } else {
-        ah[m] = zero8();
-        al[m] = zero8();
-      }
+      ah[d][m] = ld8(a.adj_hi + oa[m] + (int64_t)s * 512);
+      al[d][m] = ld8(a.adj_lo + oa[m] + (int64_t)s * 512);
     }
+    call_operand<NB>(row, rho0 + 16 * s, a.g.R, grp, bv[d]);
   };
-  f32x4 cr[RB][MAXNB], ci[RB][MAXNB];
+  f32x4 cr[RB][NB], ci[RB][NB];
 #pragma unroll
   for (int m = 0; m < RB; ++m)
 #pragma unroll
-    for (int c = 0; c < MAXNB; ++c) { cr[m][c] = z4(); ci[m][c] = z4(); }
-  u16x8 ah[RB], al[RB], nh[RB], nl[RB];
-  stage_split(sb[0], a.in, a.J, Jp, a.g.R, rho0, a.g.R);
-  loadA(0, ah, al);
-  __syncthreads();
-  for (int s = 0; s < steps; ++s) {
-    if (s + 1 < steps) {
-      stage_split(sb[(s + 1) & 1], a.in, a.J, Jp, a.g.R, rho0 + 16 * (s + 1), a.g.R);
-      loadA(s + 1, nh, nl);
+    for (int c = 0; c < NB; ++c) { cr[m][c] = z4(); ci[m][c] = z4(); }
+  auto compute = [&](int d) {
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      const Tile<1>::B b = Tile<1>::make_b(bv[d][c]);
+#pragma unroll
+      for (int m = 0; m < RB; ++m) mfma6(cr[m][c], ci[m][c], ah[d][m], al[d][m], b.rh, b.rl, b.ih, b.il);
     }
-    const int buf = s & 1;
+  };
+  // FD stages in flight; the issue order of the stages' loads is kept, so the wait before
+  // a stage's products only covers that stage's loads.
 #pragma unroll
-    for (int c = 0; c < MAXNB; ++c) {
-      if (c < nb) {
-        const int n = 16 * c + (lane & 15), ko = 8 * (lane >> 4);
-        const u16x8 b0 = ld8(&sb[buf][0][n][ko]), b1 = ld8(&sb[buf][1][n][ko]);
-        const u16x8 b2 = ld8(&sb[buf][2][n][ko]), b3 = ld8(&sb[buf][3][n][ko]);
+  for (int d = 0; d < FD; ++d) load(d, d);
+  int s0 = 0;
+  for (; s0 + FD <= steps; s0 += FD) {
 #pragma unroll
-        for (int m = 0; m < RB; ++m) mfma6(cr[m][c], ci[m][c], ah[m], al[m], b0, b1, b2, b3);
-      }
-    }
-    __syncthreads();
-    if (s + 1 < steps) {
-#pragma unroll
-      for (int m = 0; m < RB; ++m) { ah[m] = nh[m]; al[m] = nl[m]; }
+    for (int d = 0; d < FD; ++d) {
+      compute(d);
+      load(d, s0 + d + FD);
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
-  float2* part = a.part + (int64_t)blockIdx.x * a.g.Kp * Jp;
+#pragma unroll
+  for (int d = 0; d + 1 < FD; ++d)
+    if (s0 + d < steps) compute(d);
+  const int Jp = 16 * ((a.J + 15) / 16);
+  float2* part = a.part + (int64_t)ch * a.g.Kp * Jp;
 #pragma unroll
   for (int m = 0; m < RB; ++m)
     if (mb0 + m < mbl)
 #pragma unroll
-      for (int c = 0; c < MAXNB; ++c)
-        if (c < nb)
+      for (int c = 0; c < NB; ++c)
 #pragma unroll
-          for (int r = 0; r < 4; ++r)
-            part[(int64_t)(16 * (mb0 + m) + 4 * (lane >> 4) + r) * Jp + 16 * c + (lane & 15)] =
-                make_float2(cr[m][c][r], ci[m][c][r]);
+        for (int r = 0; r < 4; ++r)
+          part[(int64_t)(16 * (mb0 + m) + 4 * grp + r) * Jp + 16 * c + (lane & 15)] =
+              make_float2(cr[m][c][r], ci[m][c][r]);
 }
 
 // ---------------------------------------------------------------- adjoint, FP32
@@ -448,18 +401,40 @@ hipError_t core_split_launch(const float2* core, const CoreGeom& g, uint16_t* ds
 }
 
 hipError_t core_fwd_launch(const CoreArgs& a, int precision, hipStream_t st) {
-  const dim3 grid((unsigned)((a.g.R + 64 * RB - 1) / (64 * RB))), block(NT);
-  if (precision == MAXWELL_BF16_SPLIT) hipLaunchKernelGGL(core_fwd_bf16_kernel, grid, block, 0, st, a);
-  else hipLaunchKernelGGL(core_fwd_f32_kernel, grid, block, 0, st, a);
+  const dim3 block(NT);
+  auto grid = [&](int rb) { return dim3((unsigned)((a.g.R + 64 * rb - 1) / (64 * rb))); };
+  if (precision == MAXWELL_BF16_SPLIT) {
+    constexpr int F = FWD_RB_FEW, M = FWD_RB_MANY;
+    switch ((a.J + 15) / 16) {
+      case 1: hipLaunchKernelGGL((core_fwd_bf16_kernel<1, F>), grid(F), block, 0, st, a); break;
+      case 2: hipLaunchKernelGGL((core_fwd_bf16_kernel<2, F>), grid(F), block, 0, st, a); break;
+      case 3: hipLaunchKernelGGL((core_fwd_bf16_kernel<3, M>), grid(M), block, 0, st, a); break;
+      default: hipLaunchKernelGGL((core_fwd_bf16_kernel<4, M>), grid(M), block, 0, st, a); break;
+    }
+  } else {
+    hipLaunchKernelGGL(core_fwd_f32_kernel, grid(RB), block, 0, st, a);
+  }
   return hipGetLastError();
 }
 
 hipError_t core_adj_launch(const CoreArgs& a, int precision, float alpha, const float* scale_dev, hipStream_t st) {
   const int nch = core_adj_chunks(a.g.R);
-  const int kgroups = (a.g.Kp / 16 + 4 * RB - 1) / (4 * RB);
-  const dim3 grid((unsigned)nch, (unsigned)kgroups), block(NT);
-  if (precision == MAXWELL_BF16_SPLIT) hipLaunchKernelGGL(core_adj_bf16_kernel, grid, block, 0, st, a);
-  else hipLaunchKernelGGL(core_adj_f32_kernel, grid, block, 0, st, a);
+  const int nb = (a.J + 15) / 16;
+  const dim3 block(NT);
+  auto kgroups = [&](int rb) { return (a.g.Kp / 16 + 4 * rb - 1) / (4 * rb); };
+  if (precision == MAXWELL_BF16_SPLIT) {
+    const int rb = nb <= 2 ? ADJ_RB_FEW : ADJ_RB_MANY, kg = kgroups(rb);
+    const dim3 grid((unsigned)(8 * kg * ((nch + 7) / 8)));
+    constexpr int F = ADJ_RB_FEW, M = ADJ_RB_MANY;
+    switch (nb) {
+      case 1: hipLaunchKernelGGL((core_adj_bf16_kernel<1, F>), grid, block, 0, st, a, nch, kg); break;
+      case 2: hipLaunchKernelGGL((core_adj_bf16_kernel<2, F>), grid, block, 0, st, a, nch, kg); break;
+      case 3: hipLaunchKernelGGL((core_adj_bf16_kernel<3, M>), grid, block, 0, st, a, nch, kg); break;
+      default: hipLaunchKernelGGL((core_adj_bf16_kernel<4, M>), grid, block, 0, st, a, nch, kg); break;
+    }
+  } else {
+    hipLaunchKernelGGL(core_adj_f32_kernel, dim3((unsigned)nch, (unsigned)kgroups(RB)), block, 0, st, a);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t plane = (int64_t)a.g.Kp * ((a.J + 15) / 16 * 16);
