@@ -177,10 +177,35 @@ maxwell_status maxwell_forward_loss(maxwell_plan_t plan, const maxwell_complex64
                                     maxwell_complex64* r, double* loss_dev, void* ws,
                                     size_t ws_bytes, void* stream);
 
+/* The data-fidelity forward pass of maxwell_forward_loss (Sec. II-B, Eq. (6) data term)
+ * with the weighted residual handed to the gradient in the plan's transfer layout:
+ *     t        [J][M] entries, laid out by the plan (required unless M == 0)
+ *     loss_dev as in maxwell_forward_loss (may be NULL)
+ * maxwell_adjoint_transfer(plan, x, c, t, ...) then equals maxwell_adjoint(plan, x, c, r, ...)
+ * for the weighted residual r = w (.) (E - y).  On the fused 3D Cartesian path
+ * (maxwell_plan_path() == "fused-tucker-lines", whose readout axis is fully sampled) t is
+ * r already taken back along the readout, the first factor of F_s^H in Eq. (5)'s adjoint,
+ * computed while each line is on chip; on every other path t is r itself.            */
+maxwell_status maxwell_forward_transfer(maxwell_plan_t plan, const maxwell_complex64* x,
+                                        const maxwell_complex64* c, const maxwell_complex64* y,
+                                        maxwell_complex64* t, double* loss_dev, void* ws,
+                                        size_t ws_bytes, void* stream);
+
+/* maxwell_adjoint (same alpha, scale_dev, outputs and errors) applied to a residual t
+ * written by maxwell_forward_transfer on the same plan.  B c is recomputed from c here;
+ * t is only read.                                                                     */
+maxwell_status maxwell_adjoint_transfer(maxwell_plan_t plan, const maxwell_complex64* x,
+                                        const maxwell_complex64* c, const maxwell_complex64* t,
+                                        float alpha, const float* scale_dev, maxwell_complex64* gx,
+                                        maxwell_complex64* gc, void* ws, size_t ws_bytes,
+                                        void* stream);
+
 /* Loss and its packed real gradient (d/dRe + i d/dIm, the PyTorch convention)
  * in one call:  f = sum w |E - y|^2,  (gx, gc) = 2 J^H (w (.) (E - y)).
- * Equivalent to maxwell_forward_loss followed by maxwell_adjoint with alpha = 2,
- * B c recomputed for the adjoint.  gx, gc, loss_dev may each be NULL.          */
+ * Equivalent to maxwell_forward_transfer followed by maxwell_adjoint_transfer with
+ * alpha = 2, except that within this one call the adjoint reuses the forward pass's
+ * B c (the maps on the unfused paths, their factor-space intermediates on the fused
+ * path); nothing is kept after it returns.  gx, gc, loss_dev may each be NULL.       */
 maxwell_status maxwell_grad(maxwell_plan_t plan, const maxwell_complex64* x,
                             const maxwell_complex64* c, const maxwell_complex64* y,
                             maxwell_complex64* gx, maxwell_complex64* gc, double* loss_dev,

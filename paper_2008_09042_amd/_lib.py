@@ -28,7 +28,8 @@ STATUS_NAMES = {
 EXPORTS = [
     "maxwell_plan_create", "maxwell_plan_destroy", "maxwell_plan_workspace_size", "maxwell_plan_path",
     "maxwell_basis_apply", "maxwell_basis_apply_adjoint", "maxwell_encode", "maxwell_adjoint",
-    "maxwell_forward_loss", "maxwell_grad", "maxwell_last_error", "maxwell_version",
+    "maxwell_forward_loss", "maxwell_forward_transfer", "maxwell_adjoint_transfer", "maxwell_grad",
+    "maxwell_last_error", "maxwell_version",
     "maxwell_plan_set_timing", "maxwell_plan_timing",
 ]
 
@@ -98,6 +99,10 @@ def load(path: str = LIB_PATH):
     lib.maxwell_adjoint.restype = st
     lib.maxwell_forward_loss.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.maxwell_forward_loss.restype = st
+    lib.maxwell_forward_transfer.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.maxwell_forward_transfer.restype = st
+    lib.maxwell_adjoint_transfer.argtypes = [vp, vp, vp, vp, ctypes.c_float, vp, vp, vp, vp, sz, vp]
+    lib.maxwell_adjoint_transfer.restype = st
     lib.maxwell_grad.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.maxwell_grad.restype = st
     lib.maxwell_plan_set_timing.argtypes = [vp, ctypes.c_int]

@@ -366,6 +366,54 @@ maxwell_status maxwell_forward_loss(maxwell_plan_t plan, const maxwell_complex64
   return MAXWELL_OK;
 }
 
+maxwell_status maxwell_forward_transfer(maxwell_plan_t plan, const maxwell_complex64* x, const maxwell_complex64* c,
+                                        const maxwell_complex64* y, maxwell_complex64* t, double* loss_dev, void* ws,
+                                        size_t ws_bytes, void* stream) {
+  if (!plan) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "plan is null");
+  const Plan* p = reinterpret_cast<const Plan*>(plan);
+  Check ck(p);
+  ck.in(x, p->bytes_x(), "x");
+  ck.in(c, p->bytes_c(), "c");
+  ck.in(y, p->bytes_y(), "y");
+  ck.out(t, p->bytes_y(), "t", true);
+  ck.out(loss_dev, sizeof(double), "loss_dev", false);
+  ck.ws(ws, ws_bytes);
+  maxwell_status s = ck.finish();
+  if (s != MAXWELL_OK) return s;
+  HIP_TRY(run_forward_loss(*p, reinterpret_cast<const float2*>(x), reinterpret_cast<const float2*>(c),
+                           reinterpret_cast<const float2*>(y), reinterpret_cast<float2*>(t), loss_dev, ws,
+                           (hipStream_t)stream, true),
+          "forward_transfer");
+  return MAXWELL_OK;
+}
+
+maxwell_status maxwell_adjoint_transfer(maxwell_plan_t plan, const maxwell_complex64* x, const maxwell_complex64* c,
+                                        const maxwell_complex64* t, float alpha, const float* scale_dev,
+                                        maxwell_complex64* gx, maxwell_complex64* gc, void* ws, size_t ws_bytes,
+                                        void* stream) {
+  if (!plan) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "plan is null");
+  const Plan* p = reinterpret_cast<const Plan*>(plan);
+  if (!std::isfinite(alpha)) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "alpha must be finite");
+  Check ck(p);
+  ck.in(x, p->bytes_x(), "x");
+  ck.in(c, p->bytes_c(), "c");
+  ck.in(t, p->bytes_y(), "t");
+  if (scale_dev && (reinterpret_cast<uintptr_t>(scale_dev) & 3u))
+    return fail(MAXWELL_ERR_INVALID_ARGUMENT, "scale_dev must be 4-byte aligned");
+  if (scale_dev) ck.ins.push_back({scale_dev, sizeof(float)});
+  ck.out(gx, p->bytes_x(), "gx", false);
+  ck.out(gc, p->bytes_c(), "gc", false);
+  ck.ws(ws, ws_bytes);
+  maxwell_status s = ck.finish();
+  if (s != MAXWELL_OK) return s;
+  if (!gx && !gc) return MAXWELL_OK;
+  HIP_TRY(run_adjoint(*p, reinterpret_cast<const float2*>(x), reinterpret_cast<const float2*>(c),
+                      reinterpret_cast<const float2*>(t), alpha, scale_dev, reinterpret_cast<float2*>(gx),
+                      reinterpret_cast<float2*>(gc), ws, (hipStream_t)stream, false, true),
+          "adjoint_transfer");
+  return MAXWELL_OK;
+}
+
 maxwell_status maxwell_grad(maxwell_plan_t plan, const maxwell_complex64* x, const maxwell_complex64* c,
                             const maxwell_complex64* y, maxwell_complex64* gx, maxwell_complex64* gc,
                             double* loss_dev, void* ws, size_t ws_bytes, void* stream) {

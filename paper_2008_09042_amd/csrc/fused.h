@@ -30,12 +30,13 @@ struct LineArgs {
   int J, n2;
   int64_t L, M;                      // M = L * n2
   const float2* Z;                   // fwd in  [J][n2][L]
-  float2* out;                       // fwd out [J][M]: E (y == null) or w (.) (E - y)
+  float2* out;                       // fwd out [J][M]: E (y == null) or w (.) (E - y), or null
   const float2* y;                   // measured data or null
   const float* w;                    // weights or null
   double* part;                      // per-block loss partials or null
   const float2* yin;                 // adj in [J][M]
-  float2* Zw;                        // adj out [J][n2][L]
+  float2* Zw;                        // adj out [J][n2][L]; in the forward (with y), the weighted
+                                     // residual taken back along the readout (transfer layout), or null
   float gscale;                      // prod_d (-1)^(n_d/2) / sqrt(n0 n1 n2)
   float alpha;                       // adjoint scale alpha * (*scale_dev)
   const float* scale_dev;
@@ -56,7 +57,7 @@ int line_blocks(int J, int64_t L);
 hipError_t line_fwd_launch(const LineArgs& a, hipStream_t st);
 hipError_t line_adj_launch(const LineArgs& a, hipStream_t st);
 hipError_t transpose_launch(const float2* x, int64_t R, int64_t C, float2* xt, hipStream_t st);
-hipError_t reduce_transpose_launch(const float2* part, int ngrp, int64_t R, int64_t C, float2* gx,
-                                   hipStream_t st);
+hipError_t reduce_transpose_launch(const float2* part, int ngrp, int64_t R, int64_t C, float alpha,
+                                   const float* scale_dev, float2* gx, hipStream_t st);
 
 }  // namespace mx

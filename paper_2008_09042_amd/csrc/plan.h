@@ -98,11 +98,14 @@ hipError_t run_basis_apply(const Plan& p, const float2* c, float2* S, void* ws, 
 hipError_t run_basis_adjoint(const Plan& p, const float2* S, float2* c, float alpha, const float* alpha_dev,
                              void* ws, hipStream_t st);
 hipError_t run_encode(const Plan& p, const float2* x, const float2* c, float2* y, void* ws, hipStream_t st);
+// transfer: the residual is (forward: written / adjoint: read) in the plan's transfer
+// layout, the weighted residual taken back along the readout on the fused path and the
+// residual itself elsewhere.
 hipError_t run_adjoint(const Plan& p, const float2* x, const float2* c, const float2* y, float alpha,
                        const float* scale_dev, float2* gx, float2* gc, void* ws, hipStream_t st,
-                       bool maps_ready);
+                       bool maps_ready, bool transfer = false);
 hipError_t run_forward_loss(const Plan& p, const float2* x, const float2* c, const float2* y, float2* r,
-                            double* loss, void* ws, hipStream_t st);
+                            double* loss, void* ws, hipStream_t st, bool transfer = false);
 hipError_t run_grad(const Plan& p, const float2* x, const float2* c, const float2* y, float2* gx, float2* gc,
                     double* loss, void* ws, hipStream_t st);
 

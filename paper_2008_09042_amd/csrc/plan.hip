@@ -673,24 +673,29 @@ static hipError_t fused_prepare(const Plan& p, const float2* x, const float2* c,
   return TIMED("transpose_x", transpose_launch(x, p.n[0] * p.n[1], p.n[2], wsp<float2>(ws, p.off_xt), st));
 }
 
+// out: E (y null) or the weighted residual; with `transfer` (y given) the residual goes out
+// in the transfer layout: taken back along the readout by the line kernel itself.
 static hipError_t fused_forward(const Plan& p, const float2* x, const float2* c, const float2* y, float2* out,
-                                double* part, void* ws, hipStream_t st) {
+                                double* part, void* ws, hipStream_t st, bool transfer) {
   hipError_t e = fused_prepare(p, x, c, ws, st);
   if (e != hipSuccess) return e;
   PlaneArgs pa = plane_args(p, ws, p.G_fwd);
   if ((e = TIMED("plane_fwd", plane_fwd_launch(pa, st))) != hipSuccess) return e;
   LineArgs la = line_args(p);
   la.Z = wsp<float2>(ws, p.off_Z);
-  la.out = out;
+  la.out = transfer ? nullptr : out;
+  la.Zw = transfer ? out : nullptr;
   la.y = y;
   la.w = y ? p.d_w : nullptr;
   la.part = part;
   return TIMED("line_fwd", line_fwd_launch(la, st));
 }
 
+// y: samples [J][M], or (transfer) a residual already in the transfer layout, in which
+// case the line kernel is skipped and the scale is applied where gx and gc are written.
 static hipError_t fused_adjoint(const Plan& p, const float2* x, const float2* c, const float2* y, float alpha,
                                 const float* scale_dev, float2* gx, float2* gc, void* ws, hipStream_t st,
-                                bool prepared) {
+                                bool prepared, bool transfer) {
   hipError_t e;
   if (!prepared) {
     if (gx) {
@@ -700,19 +705,27 @@ static hipError_t fused_adjoint(const Plan& p, const float2* x, const float2* c,
       if (e != hipSuccess) return e;
     }
   }
-  LineArgs la = line_args(p);
-  la.yin = y;
-  la.Zw = wsp<float2>(ws, p.off_Z);
-  la.alpha = alpha;
-  la.scale_dev = scale_dev;
-  if ((e = TIMED("line_adj", line_adj_launch(la, st))) != hipSuccess) return e;
+  // the scale: in the line kernel, or (transfer) where the outputs are written
+  const float end_alpha = transfer ? alpha : 1.0f;
+  const float* end_scale = transfer ? scale_dev : nullptr;
   PlaneArgs pa = plane_args(p, ws, p.G_adj);
+  if (transfer) {
+    pa.Z = const_cast<float2*>(y);  // read only by the adjoint plane kernel
+  } else {
+    LineArgs la = line_args(p);
+    la.yin = y;
+    la.Zw = wsp<float2>(ws, p.off_Z);
+    la.alpha = alpha;
+    la.scale_dev = scale_dev;
+    if ((e = TIMED("line_adj", line_adj_launch(la, st))) != hipSuccess) return e;
+  }
   pa.gxpart = gx ? wsp<float2>(ws, p.off_gxp) : nullptr;
   pa.T3b = gc ? wsp<float2>(ws, p.off_T3b) : nullptr;
   if ((e = TIMED("plane_adj", plane_adj_launch(pa, st))) != hipSuccess) return e;
   if (gx) {
     const int ngrp = (p.J + p.G_adj - 1) / p.G_adj;
-    e = TIMED("gx_reduce", reduce_transpose_launch(pa.gxpart, ngrp, p.n[0] * p.n[1], p.n[2], gx, st));
+    e = TIMED("gx_reduce", reduce_transpose_launch(pa.gxpart, ngrp, p.n[0] * p.n[1], p.n[2], end_alpha, end_scale,
+                                                   gx, st));
     if (e != hipSuccess) return e;
   }
   if (gc) {
@@ -727,13 +740,14 @@ static hipError_t fused_adjoint(const Plan& p, const float2* x, const float2* c,
                 gemm_launch(fused_T1b_args(p, pa.T3b, wsp<float2>(ws, p.off_T1b)), p.precision, gws, st));
     }
     if (e != hipSuccess) return e;
-    if ((e = core_adjoint(p, wsp<float2>(ws, p.off_T1b), gc, 1.0f, nullptr, ws, st)) != hipSuccess) return e;
+    if ((e = core_adjoint(p, wsp<float2>(ws, p.off_T1b), gc, end_alpha, end_scale, ws, st)) != hipSuccess)
+      return e;
   }
   return hipSuccess;
 }
 
 hipError_t run_encode(const Plan& p, const float2* x, const float2* c, float2* y, void* ws, hipStream_t st) {
-  if (p.fused) return fused_forward(p, x, c, nullptr, y, nullptr, ws, st);
+  if (p.fused) return fused_forward(p, x, c, nullptr, y, nullptr, ws, st, false);
   float2* S = wsp<float2>(ws, p.off_S);
   float2* Kb = wsp<float2>(ws, p.off_K);
   hipError_t e = run_basis_apply(p, c, S, ws, st);
@@ -750,11 +764,11 @@ hipError_t run_encode(const Plan& p, const float2* x, const float2* c, float2* y
 }
 
 hipError_t run_forward_loss(const Plan& p, const float2* x, const float2* c, const float2* y, float2* r,
-                            double* loss, void* ws, hipStream_t st) {
+                            double* loss, void* ws, hipStream_t st, bool transfer) {
   double* part = wsp<double>(ws, p.off_part);
   hipError_t e;
   if (p.fused) {
-    if ((e = fused_forward(p, x, c, y, r, part, ws, st)) != hipSuccess) return e;
+    if ((e = fused_forward(p, x, c, y, r, part, ws, st, transfer && r)) != hipSuccess) return e;
     if (loss) return TIMED("reduce_loss", reduce_loss_launch(part, line_blocks(p.J, p.L), loss, st));
     return hipSuccess;
   }
@@ -767,8 +781,8 @@ hipError_t run_forward_loss(const Plan& p, const float2* x, const float2* c, con
 
 hipError_t run_adjoint(const Plan& p, const float2* x, const float2* c, const float2* y, float alpha,
                        const float* scale_dev, float2* gx, float2* gc, void* ws, hipStream_t st,
-                       bool maps_ready) {
-  if (p.fused) return fused_adjoint(p, x, c, y, alpha, scale_dev, gx, gc, ws, st, maps_ready);
+                       bool maps_ready, bool transfer) {
+  if (p.fused) return fused_adjoint(p, x, c, y, alpha, scale_dev, gx, gc, ws, st, maps_ready, transfer);
   float2* S = wsp<float2>(ws, p.off_S);
   float2* Kb = wsp<float2>(ws, p.off_K);
   hipError_t e;
@@ -795,11 +809,14 @@ hipError_t run_adjoint(const Plan& p, const float2* x, const float2* c, const fl
 
 hipError_t run_grad(const Plan& p, const float2* x, const float2* c, const float2* y, float2* gx, float2* gc,
                     double* loss, void* ws, hipStream_t st) {
-  float2* E = wsp<float2>(ws, p.off_E);
-  hipError_t e = run_forward_loss(p, x, c, y, E, loss, ws, st);
+  const bool want = gx || gc;
+  // the residual in the transfer layout; on the fused path in place of the plane output
+  // (each line workgroup reads its lines before writing them)
+  float2* r = !want ? nullptr : p.fused ? wsp<float2>(ws, p.off_Z) : wsp<float2>(ws, p.off_E);
+  hipError_t e = run_forward_loss(p, x, c, y, r, loss, ws, st, true);
   if (e != hipSuccess) return e;
-  if (!gx && !gc) return hipSuccess;
-  return run_adjoint(p, x, c, E, 2.0f, nullptr, gx, gc, ws, st, true);
+  if (!want) return hipSuccess;
+  return run_adjoint(p, x, c, r, 2.0f, nullptr, gx, gc, ws, st, true, true);
 }
 
 }  // namespace mx

@@ -153,8 +153,14 @@ __device__ __forceinline__ void w_load(const PlaneArgs& a, const Geo<N0, N1>& g,
     const int p0 = 16 * mb + (lane & 15);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
+      // unconditional loads (an in-range address for the padding entries, zeroed by a
+      // multiply, which keeps the compiler from moving the load under a branch): a load
+      // under a branch would make every later wait a full drain
       const int p1 = 16 * s + 4 * (lane >> 4) + t;
-      w.v[q][t] = (e < nfl && p0 < g.r0 && p1 < g.r1) ? src[(size_t)p0 * g.r1 + p1] : make_float2(0.f, 0.f);
+      const bool in = e < nfl && p0 < g.r0 && p1 < g.r1;
+      const float2 v = src[in ? (size_t)p0 * g.r1 + p1 : 0];
+      const float m = in ? 1.f : 0.f;
+      w.v[q][t] = make_float2(v.x * m, v.y * m);
     }
   }
 }
@@ -173,9 +179,10 @@ __device__ __forceinline__ void w_store(const Geo<N0, N1>& g, float2* lds, int t
 }
 
 // V = W U1^T (W staged) for column block cb = wave, stored as the B operand of P = U0 V
-// (steps over p0, o blocks over i1) in the plane region.
+// (steps over p0, o blocks over i1) in the plane region.  u1: this wave's U1^T fragments.
 template <int PREC, int N0, int N1>
-__device__ __forceinline__ void coil_v(const PlaneArgs& a, const Geo<N0, N1>& g, float2* lds, int lane) {
+__device__ __forceinline__ void coil_v(const Geo<N0, N1>& g, float2* lds, int lane,
+                                       const typename Tile<PREC>::B (&u1)[3]) {
   const int cb = threadIdx.x >> 6;
   if (cb >= g.n1b) return;
   f32x4 cr[3], ci[3];
@@ -184,10 +191,9 @@ __device__ __forceinline__ void coil_v(const PlaneArgs& a, const Geo<N0, N1>& g,
 #pragma unroll
   for (int s = 0; s < 3; ++s)
     if (s < g.r1b) {
-      const typename Tile<PREC>::B b = frag_b<PREC>(a.U1TF, g.n1b, cb, s, lane);
 #pragma unroll
       for (int m = 0; m < 3; ++m)
-        if (m < g.r0b) Tile<PREC>::mma(cr[m], ci[m], frag_a<PREC>(lds + STAGE_OFF, g.r1b, m, s, lane), b);
+        if (m < g.r0b) Tile<PREC>::mma(cr[m], ci[m], frag_a<PREC>(lds + STAGE_OFF, g.r1b, m, s, lane), u1[s]);
     }
 #pragma unroll
   for (int m = 0; m < 3; ++m)
@@ -320,13 +326,18 @@ __device__ __forceinline__ void adjoint_w(const PlaneArgs& a, const Geo<N0, N1>&
 template <int PREC, int N0, int N1>
 __device__ __forceinline__ void coil_map(const PlaneArgs& a, const Geo<N0, N1>& g, float2* lds, const Share& sh,
                                          int lane, int tid, const WPrefetch& w, f32x4 (&pr)[8], f32x4 (&pi)[8]) {
-  typename Tile<PREC>::A u0[3];  // the wave's U0 row block, in flight across the W store
+  // the wave's U0 row block and U1^T column block, in flight across the W store
+  typename Tile<PREC>::A u0[3];
+  typename Tile<PREC>::B u1[3];
+  const int cb = threadIdx.x >> 6;
 #pragma unroll
-  for (int s = 0; s < 3; ++s)
+  for (int s = 0; s < 3; ++s) {
     if (s < g.r0b) u0[s] = frag_a<PREC>(a.U0F, g.r0b, sh.rb, s, lane);
+    if (s < g.r1b) u1[s] = frag_b<PREC>(a.U1TF, g.n1b, min(cb, g.n1b - 1), s, lane);
+  }
   w_store<PREC>(g, lds, tid, w);
   __syncthreads();
-  coil_v<PREC>(a, g, lds, lane);
+  coil_v<PREC>(g, lds, lane, u1);
   __syncthreads();
   coil_p<PREC>(g, lds, sh, lane, u0, pr, pi);
   __syncthreads();  // V is consumed; the plane region is free
@@ -421,7 +432,11 @@ __global__ __launch_bounds__(PT) void plane_adj_kernel(PlaneArgs a) {
     const float2* zi = a.Z + ((size_t)j * g.n2 + i2) * a.L;
     float2 zv[SCAT];
 #pragma unroll
-    for (int k = 0; k < SCAT; ++k) zv[k] = zq[k] >= 0 ? zi[tid + k * PT] : make_float2(0.f, 0.f);
+    for (int k = 0; k < SCAT; ++k) {  // unconditional loads (L >= 1 on this path), as in w_load
+      const float2 v = zi[min(tid + k * PT, (int)a.L - 1)];
+      const float m = zq[k] >= 0 ? 1.f : 0.f;
+      zv[k] = make_float2(v.x * m, v.y * m);
+    }
     f32x4 pr[8], pi[8];
     if (want_gx) {
       WPrefetch w;
@@ -579,7 +594,9 @@ __global__ __launch_bounds__(LNT) void line_fwd_kernel(LineArgs a) {
       const float2 d = csub(v, a.y[o]);
       const float wm = a.w ? a.w[m] : 1.0f;
       acc += (double)wm * ((double)d.x * d.x + (double)d.y * d.y);
-      if (a.out) a.out[o] = cscale(d, wm);
+      const float2 r = cscale(d, wm);
+      if (a.out) a.out[o] = r;
+      if (a.Zw) tile[k2 * ES + l] = (k2 & 1) ? make_float2(-r.x, -r.y) : r;  // each entry is this thread's
     } else {
       a.out[o] = v;
     }
@@ -592,6 +609,19 @@ __global__ __launch_bounds__(LNT) void line_fwd_kernel(LineArgs a) {
       __syncthreads();
     }
     if (threadIdx.x == 0) a.part[blockIdx.x] = red[0];
+  }
+  if (a.Zw) {
+    // transfer layout: the weighted residual taken back along the readout while the lines
+    // are on chip (the adjoint's first step, as the adjoint line kernel computes it, without
+    // the adjoint's scale, which the adjoint applies at its ends)
+    if (!a.part) __syncthreads();
+    line_fft<N2>(a, tile, tw, n, +1);
+    for (int e = threadIdx.x; e < n * LT; e += LNT) {
+      const int i2 = e / LT, l = e % LT;
+      if (l0 + l >= a.L) continue;
+      const float2 v = tile[i2 * ES + l];
+      a.Zw[((size_t)j * n + i2) * a.L + l0 + l] = cscale(v, (i2 & 1) ? -a.gscale : a.gscale);
+    }
   }
 }
 
@@ -643,7 +673,9 @@ __global__ void transpose_kernel(const float2* __restrict__ x, int64_t R, int64_
 
 // gx[r][c] = sum_g part[g][c][r] : part is ngrp x (C x R), gx is R x C
 __global__ void reduce_transpose_kernel(const float2* __restrict__ part, int ngrp, int64_t R, int64_t C,
-                                        float2* __restrict__ gx) {
+                                        float alpha, const float* __restrict__ scale_dev, float2* __restrict__ gx) {
+  float sc = alpha;
+  if (scale_dev) sc *= *scale_dev;
   __shared__ float2 t[TT][TT + 1];
   const int64_t tr = (int64_t)blockIdx.x * TT, tc = (int64_t)blockIdx.y * TT;
   const int tx = threadIdx.x % TT, ty = threadIdx.x / TT;
@@ -657,7 +689,7 @@ __global__ void reduce_transpose_kernel(const float2* __restrict__ part, int ngr
   __syncthreads();
   for (int k = ty; k < TT; k += 256 / TT) {
     const int64_t r = tr + k, c = tc + tx;
-    if (r < R && c < C) gx[r * C + c] = t[tx][k];
+    if (r < R && c < C) gx[r * C + c] = cscale(t[tx][k], sc);
   }
 }
 
@@ -710,10 +742,10 @@ hipError_t transpose_launch(const float2* x, int64_t R, int64_t C, float2* xt, h
   return hipGetLastError();
 }
 
-hipError_t reduce_transpose_launch(const float2* part, int ngrp, int64_t R, int64_t C, float2* gx,
-                                   hipStream_t st) {
+hipError_t reduce_transpose_launch(const float2* part, int ngrp, int64_t R, int64_t C, float alpha,
+                                   const float* scale_dev, float2* gx, hipStream_t st) {
   dim3 grid((unsigned)((R + TT - 1) / TT), (unsigned)((C + TT - 1) / TT));
-  hipLaunchKernelGGL(reduce_transpose_kernel, grid, dim3(256), 0, st, part, ngrp, R, C, gx);
+  hipLaunchKernelGGL(reduce_transpose_kernel, grid, dim3(256), 0, st, part, ngrp, R, C, alpha, scale_dev, gx);
   return hipGetLastError();
 }
 

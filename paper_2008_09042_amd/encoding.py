@@ -219,6 +219,35 @@ class MaxwellPlan:
                                               ws, nb, _stream()))
         return r, loss
 
+    def forward_transfer(self, x, c, y):
+        """Loss and the weighted residual in the plan's transfer layout (maxwell_forward_transfer)."""
+        x = self._in(x, self.dims, "x")
+        c = self._in(c, (self.J, self.K), "c")
+        y = self._in(y, (self.J, self.M), "y")
+        t = self._new((self.J, self.M))
+        loss = torch.empty((), dtype=torch.float64, device=self.device)
+        ws, nb = self._wsargs()
+        L.check(self.lib.maxwell_forward_transfer(self.handle, _ptr(x), _ptr(c), _ptr(y), _ptr(t), _ptr(loss),
+                                                  ws, nb, _stream()))
+        return t, loss
+
+    def adjoint_transfer(self, x, c, t, alpha: float = 1.0, scale: Optional[torch.Tensor] = None,
+                         want_gx: bool = True, want_gc: bool = True):
+        """maxwell_adjoint_transfer: the adjoint on a residual from forward_transfer."""
+        x = self._in(x, self.dims, "x")
+        c = self._in(c, (self.J, self.K), "c")
+        t = self._in(t, (self.J, self.M), "t")
+        if scale is not None:
+            if scale.dtype != torch.float32 or scale.device != self.device or scale.numel() != 1:
+                raise ValueError("scale must be one float32 on the plan device")
+            scale = scale.contiguous()
+        gx = self._new(self.dims) if want_gx else None
+        gc = self._new((self.J, self.K)) if want_gc else None
+        ws, nb = self._wsargs()
+        L.check(self.lib.maxwell_adjoint_transfer(self.handle, _ptr(x), _ptr(c), _ptr(t), ctypes.c_float(alpha),
+                                                  _ptr(scale), _ptr(gx), _ptr(gc), ws, nb, _stream()))
+        return gx, gc
+
     def grad(self, x, c, y):
         x = self._in(x, self.dims, "x")
         c = self._in(c, (self.J, self.K), "c")
@@ -256,21 +285,26 @@ class MaxwellEncode(torch.autograd.Function):
 class MaxwellDataFidelity(torch.autograd.Function):
     """f = sum_j sum_m w_m |E(x, c)_jm - y_jm|^2 (FP64 scalar).
 
-    Forward keeps the weighted residual r = w (.) (E - y) ([J][M]); backward
-    runs the adjoint at (x, c) on r with scale 2 * grad_output (read on the
-    device), recomputing B c."""
+    When a gradient is wanted, forward keeps the weighted residual r = w (.) (E - y)
+    ([J][M]) in the plan's transfer layout (on the fused 3D path already taken back
+    along the readout, the adjoint's first step); backward runs the adjoint at (x, c)
+    on it with scale 2 * grad_output (read on the device), recomputing B c.  Without
+    a wanted gradient, forward computes the loss alone."""
 
     @staticmethod
     def forward(ctx, x, c, y, plan):
-        r, loss = plan.forward_loss(x, c, y)
         ctx.plan = plan
-        ctx.save_for_backward(x, c, r)
+        if ctx.needs_input_grad[0] or ctx.needs_input_grad[1]:
+            t, loss = plan.forward_transfer(x, c, y)
+            ctx.save_for_backward(x, c, t)
+        else:
+            _, loss = plan.forward_loss(x, c, y, want_r=False)
         return loss
 
     @staticmethod
     def backward(ctx, gloss):
-        x, c, r = ctx.saved_tensors
+        x, c, t = ctx.saved_tensors
         scale = gloss.detach().to(torch.float32).reshape(1)
-        gx, gc = ctx.plan.adjoint(x, c, r, alpha=2.0, scale=scale, want_gx=ctx.needs_input_grad[0],
-                                  want_gc=ctx.needs_input_grad[1])
+        gx, gc = ctx.plan.adjoint_transfer(x, c, t, alpha=2.0, scale=scale, want_gx=ctx.needs_input_grad[0],
+                                           want_gc=ctx.needs_input_grad[1])
         return gx, gc, None, None

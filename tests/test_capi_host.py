@@ -184,6 +184,9 @@ def test_null_arguments(lib):
     assert lib.maxwell_grad(None, z, z, z, z, z, None, None, 0, None) == L.MAXWELL_ERR_INVALID_ARGUMENT
     assert lib.maxwell_adjoint(None, z, z, z, 1.0, None, z, z, None, 0, None) == L.MAXWELL_ERR_INVALID_ARGUMENT
     assert lib.maxwell_forward_loss(None, z, z, z, z, None, None, 0, None) == L.MAXWELL_ERR_INVALID_ARGUMENT
+    assert lib.maxwell_forward_transfer(None, z, z, z, z, None, None, 0, None) == L.MAXWELL_ERR_INVALID_ARGUMENT
+    assert (lib.maxwell_adjoint_transfer(None, z, z, z, 1.0, None, z, z, None, 0, None)
+            == L.MAXWELL_ERR_INVALID_ARGUMENT)
     assert lib.maxwell_basis_apply(None, z, z, None, 0, None) == L.MAXWELL_ERR_INVALID_ARGUMENT
     assert lib.maxwell_basis_apply_adjoint(None, z, z, None, 0, None) == L.MAXWELL_ERR_INVALID_ARGUMENT
     assert lib.maxwell_plan_set_timing(None, 1) == L.MAXWELL_ERR_INVALID_ARGUMENT

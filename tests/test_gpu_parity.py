@@ -118,13 +118,27 @@ def test_encode_adjoint_grad(name, prec):
     assert abs(float(loss.item()) - f_ref) / f_ref <= tol
     assert rel(H(gx), gx_ref) <= tol
     assert rel(H(gc), gc_ref) <= tol
+    # the transfer pair (residual in the plan's layout), with a device scale, one output each
+    t, loss_t = plan.forward_transfer(x, c, y)
+    assert abs(float(loss_t.item()) - f_ref) / f_ref <= tol
+    s = torch.full((1,), 0.5, dtype=torch.float32, device=DEV)
+    gx, _ = plan.adjoint_transfer(x, c, t, alpha=2.0, scale=s, want_gc=False)
+    _, gc = plan.adjoint_transfer(x, c, t, alpha=2.0, scale=s, want_gx=False)
+    assert rel(H(gx), 0.5 * gx_ref) <= tol
+    assert rel(H(gc), 0.5 * gc_ref) <= tol
+    # the sample-order residual and the plain adjoint give the same gradient
+    r, _ = plan.forward_loss(x, c, y)
+    gx, gc = plan.adjoint(x, c, r, alpha=2.0)
+    assert rel(H(gx), gx_ref) <= tol
+    assert rel(H(gc), gc_ref) <= tol
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16_split"])
 @pytest.mark.parametrize("name", ["dense2d_48x40_J5_K37", "tucker3d_24x20x18_r7x5x6_K13",
                                   "fused_48x32x20_r9x13x5_K23_J5"])
 def test_autograd_data_fidelity(name, prec):
-    """torch.autograd.Function: forward = loss, backward = adjoint with B c recomputed."""
+    """torch.autograd.Function: forward = loss (+ residual in the transfer layout), backward =
+    adjoint with B c recomputed; without a wanted gradient forward gives the same loss."""
     from paper_2008_09042_amd.encoding import MaxwellDataFidelity, MaxwellEncode
     cs = get_case(name)
     plan = cs.plan(prec)
@@ -137,6 +151,9 @@ def test_autograd_data_fidelity(name, prec):
     assert abs(float(f.item()) - f_ref) / f_ref <= tol
     assert rel(H(x.grad), 3.0 * gx_ref) <= tol
     assert rel(H(c.grad), 3.0 * gc_ref) <= tol
+    with torch.no_grad():
+        f0 = MaxwellDataFidelity.apply(T(cs.x0), T(cs.c0), T(cs.y), plan)
+    assert abs(float(f0.item()) - f_ref) / f_ref <= tol
     # MaxwellEncode's VJP is J^H gy
     x2 = T(cs.x0).requires_grad_(True)
     c2 = T(cs.c0).requires_grad_(True)
