@@ -274,6 +274,92 @@ __device__ __forceinline__ void stockham_pass_ct(float2* lds, int T, int LS, int
   }
 }
 
+// The same pass over the lines one wave owns: in each chunk of Tc = min(CH / N, TL) lines
+// (TL: the number of lines, known at compile time here), wave w
+// takes lines [w LPW, (w + 1) LPW), LPW = Tc / (NTHREADS / 64), lane -> (line lane % LPW,
+// butterfly column lane / LPW + (64 / LPW) q).  A wave's LDS accesses are performed in
+// program order, so the pass needs no workgroup barrier; the empty asm statements keep the
+// compiler from moving LDS accesses across the read / write phases.  The caller
+// synchronises the workgroup before the first pass (other waves' data) and after the last.
+template <int N, int R, int Ns, int NTHREADS, int CH, int TL>
+__device__ __forceinline__ void stockham_pass_wave(float2* lds, int LS, int ES, const float2* tw, int dir, int tid) {
+  constexpr int nR = N / R;
+  constexpr int NW = NTHREADS / 64;
+  constexpr int T = TL;
+  constexpr int Tc = CH / N < TL ? CH / N : TL;
+  constexpr int LPW = Tc / NW;
+  static_assert(Tc % NW == 0 && T % Tc == 0, "chunks split evenly over the waves");
+  static_assert(LPW >= 1 && LPW <= 64 && 64 % LPW == 0, "lines per wave must divide 64");
+  constexpr int JG = 64 / LPW;
+  constexpr int MAXQ = (nR + JG - 1) / JG;
+  constexpr int STW = N / (Ns * R);
+  const int wave = tid >> 6, lane = tid & 63;
+  const int lo = lane % LPW, jg = lane / LPW;
+  for (int l0 = 0; l0 < T; l0 += Tc) {
+    const int l = l0 + wave * LPW + lo;
+    const int base = l * LS;
+    float2 v[MAXQ][R];
+#pragma unroll
+    for (int q = 0; q < MAXQ; ++q) {
+      const int j = jg + JG * q;
+      if (j < nR && l < T) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[q][r] = lds[base + (j + r * nR) * ES];
+        if (Ns > 1) {
+          const int k = j % Ns;
+          float2 wp[4];
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            if ((1 << b) < R) {
+              wp[b] = tw[k * (1 << b) * STW];
+              if (dir > 0) wp[b].y = -wp[b].y;
+            }
+#pragma unroll
+          for (int r = 1; r < R; ++r) {
+            float2 w = make_float2(1.f, 0.f);
+            bool first = true;
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+              if (r & (1 << b)) {
+                w = first ? wp[b] : cmul(w, wp[b]);
+                first = false;
+              }
+            v[q][r] = cmul(v[q][r], w);
+          }
+        }
+        dft_small<R>(v[q], dir);
+      }
+    }
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int q = 0; q < MAXQ; ++q) {
+      const int j = jg + JG * q;
+      if (j < nR && l < T) {
+        const int idxD = (j / Ns) * Ns * R + (j % Ns);
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds[base + (idxD + r * Ns) * ES] = v[q][r];
+      }
+    }
+    asm volatile("" ::: "memory");
+  }
+}
+
+// Whether wave-owned passes are free of LDS bank conflicts for an odd line stride: a
+// quarter wave (16 lanes) then reads 16 different lines at one butterfly column.
+template <int N, int NTHREADS, int CH, int TL>
+constexpr bool wave_lines_fit() {
+  return (CH / N < TL ? CH / N : TL) / (NTHREADS / 64) >= 16;
+}
+
+// All passes of one transform over wave-owned lines (stockham_pass_wave): no workgroup
+// barrier inside; the caller synchronises before and after.
+template <int N, int NTHREADS, int CH, int TL>
+__device__ __forceinline__ void lds_fft_ct_wave(float2* lds, int LS, int ES, const float2* tw, int dir, int tid) {
+  using P = CtPlan<N>;
+  stockham_pass_wave<N, P::R0, 1, NTHREADS, CH, TL>(lds, LS, ES, tw, dir, tid);
+  if constexpr (P::P > 1) stockham_pass_wave<N, P::R1, P::R0, NTHREADS, CH, TL>(lds, LS, ES, tw, dir, tid);
+}
+
 template <int N, int NTHREADS, int CH>
 __device__ __forceinline__ void lds_fft_ct(float2* lds, int T, int LS, int ES, const float2* tw, int dir,
                                            int tid = -1) {

@@ -114,8 +114,13 @@ __device__ __forceinline__ void plane_fft(const PlaneArgs& a, const Geo<N0, N1>&
   const float2* tw1 = tw0 + PMAX;
   int tid = threadIdx.x;  // opaque: the passes' addresses are not hoisted out of the coil loop
   asm volatile("" : "+v"(tid));
+  // wave-owned lines (no barrier inside the transform of one axis) where a chunk holds at
+  // least 16 lines per wave; otherwise every pass synchronises the workgroup
   auto rows = [&]() {
-    if constexpr (N1 != 0) {
+    if constexpr (N1 != 0 && wave_lines_fit<N1, PT, CH, N0>()) {
+      lds_fft_ct_wave<N1, PT, CH, N0>(lds, g.PS, 1, tw1, dir, tid);
+      __syncthreads();
+    } else if constexpr (N1 != 0) {
       lds_fft_ct<N1, PT, CH>(lds, g.n0, g.PS, 1, tw1, dir, tid);
     } else {
       LdsLines t{g.n0, g.PS, 1};
@@ -123,7 +128,10 @@ __device__ __forceinline__ void plane_fft(const PlaneArgs& a, const Geo<N0, N1>&
     }
   };
   auto cols = [&]() {
-    if constexpr (N0 != 0) {
+    if constexpr (N0 != 0 && wave_lines_fit<N0, PT, CH, N1>()) {
+      lds_fft_ct_wave<N0, PT, CH, N1>(lds, 1, g.PS, tw0, dir, tid);
+      __syncthreads();
+    } else if constexpr (N0 != 0) {
       lds_fft_ct<N0, PT, CH>(lds, g.n1, 1, g.PS, tw0, dir, tid);
     } else {
       LdsLines t{g.n1, 1, g.PS};
