@@ -587,10 +587,25 @@ __global__ __launch_bounds__(LNT) void line_fwd_kernel(LineArgs a) {
     if (i2 & 1) v = make_float2(-v.x, -v.y);
     tile[i2 * ES + l] = v;
   }
+  // With the compile-time readout, the measured samples of this thread's outputs are
+  // loaded here, ahead of the transform (lines past L read line L - 1).
+  constexpr int YQ = N2 ? N2 * LT / LNT : 1;
+  float2 yv[YQ];
+  if constexpr (N2 != 0) {
+    if (a.y) {
+#pragma unroll
+      for (int q = 0; q < YQ; ++q) {
+        const int e = threadIdx.x + q * LNT, l = e / N2, k2 = e % N2;
+        yv[q] = a.y[(size_t)j * a.M + (size_t)min(l0 + l, (int)a.L - 1) * N2 + k2];
+      }
+    }
+  }
   __syncthreads();
   line_fft<N2>(a, tile, tw, n, -1);
   double acc = 0.0;
-  for (int e = threadIdx.x; e < n * LT; e += LNT) {
+#pragma unroll
+  for (int q = 0; q < (N2 ? YQ : 1); ++q)
+  for (int e = threadIdx.x + q * LNT; e < n * LT; e += (N2 ? n * LT : LNT)) {
     const int l = e / n, k2 = e % n;
     if (l0 + l >= a.L) continue;
     float2 v = tile[k2 * ES + l];
@@ -599,7 +614,7 @@ __global__ __launch_bounds__(LNT) void line_fwd_kernel(LineArgs a) {
     const size_t m = (size_t)(l0 + l) * n + k2;
     const size_t o = (size_t)j * a.M + m;
     if (a.y) {
-      const float2 d = csub(v, a.y[o]);
+      const float2 d = csub(v, N2 ? yv[q] : a.y[o]);
       const float wm = a.w ? a.w[m] : 1.0f;
       acc += (double)wm * ((double)d.x * d.x + (double)d.y * d.y);
       const float2 r = cscale(d, wm);
