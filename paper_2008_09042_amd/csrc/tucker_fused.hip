@@ -367,6 +367,17 @@ __global__ __launch_bounds__(PT) void plane_fwd_kernel(PlaneArgs a) {
   const int j0 = gi * a.G, j1 = min(a.J, (gi + 1) * a.G);
   WPrefetch w;  // W of the next coil, loaded one coil ahead
   if (j0 < j1) w_load(a, g, j0, i2, threadIdx.x, w);
+  // the x values of the wave's share, the same for every coil: loaded once
+  float2 xr[8][4];
+  {
+    const int lane = threadIdx.x & 63, grp = lane >> 4;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int cb = min(sh.part + i * sh.q, g.n1b - 1);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) xr[i][r] = xp[(16 * sh.rb + 4 * grp + r) * g.n1 + 16 * cb + (lane & 15)];
+    }
+  }
   for (int j = j0; j < j1; ++j) {
     // lane and thread index through an empty asm: per-coil addresses are recomputed
     // here rather than hoisted out of the coil loop and held across the transform
@@ -386,7 +397,7 @@ __global__ __launch_bounds__(PT) void plane_fwd_kernel(PlaneArgs a) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int i0 = 16 * sh.rb + 4 * grp + r;
-            float2 v = cmul(make_float2(pr[i][r], pi[i][r]), xp[i0 * g.n1 + i1]);
+            float2 v = cmul(make_float2(pr[i][r], pi[i][r]), xr[i][r]);
             if ((i0 + i1) & 1) v = make_float2(-v.x, -v.y);
             lds[i0 * g.PS + i1] = v;
           }
