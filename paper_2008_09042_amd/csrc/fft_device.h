@@ -348,7 +348,8 @@ __device__ __forceinline__ void stockham_pass_wave(float2* lds, int LS, int ES, 
 // quarter wave (16 lanes) then reads 16 different lines at one butterfly column.
 template <int N, int NTHREADS, int CH, int TL>
 constexpr bool wave_lines_fit() {
-  return (CH / N < TL ? CH / N : TL) / (NTHREADS / 64) >= 16;
+  constexpr int n = N > 0 ? N : 1;  // N = 0: a run-time size, never wave-owned
+  return N > 0 && (CH / n < TL ? CH / n : TL) / (NTHREADS / 64) >= 16;
 }
 
 // All passes of one transform over wave-owned lines (stockham_pass_wave): no workgroup

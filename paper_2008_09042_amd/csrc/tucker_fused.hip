@@ -67,10 +67,12 @@ struct Geo {
   }
 };
 
-// The wave's share of the plane: row block rb and column blocks part, part + q, ...
-// (every (row block, column block) tile has exactly one owner).
+// The wave's share of the plane: column block cb and row blocks part, part + q, ...
+// (every (row block, column block) tile has exactly one owner).  A whole column block per
+// wave lets the wave form its P tiles from its own V tiles (V = W U1^T for that column
+// block) held in registers.
 struct Share {
-  int rb, part, q;
+  int cb, part, q;
   bool on;
 };
 
@@ -78,9 +80,9 @@ template <int N0, int N1>
 __device__ __forceinline__ Share plane_share(const Geo<N0, N1>& g) {
   const int wave = threadIdx.x >> 6;
   Share s;
-  s.q = NWAVE / g.n0b;
-  s.rb = wave % g.n0b;
-  s.part = wave / g.n0b;
+  s.q = NWAVE / g.n1b;
+  s.cb = wave % g.n1b;
+  s.part = wave / g.n1b;
   s.on = s.part < s.q;
   return s;
 }
@@ -186,13 +188,11 @@ __device__ __forceinline__ void w_store(const Geo<N0, N1>& g, float2* lds, int t
   }
 }
 
-// V = W U1^T (W staged) for column block cb = wave, stored as the B operand of P = U0 V
-// (steps over p0, o blocks over i1) in the plane region.  u1: this wave's U1^T fragments.
+// V[:, cb] = W U1^T[:, cb] (W staged) for the wave's column block, as the B operands (one
+// per K16 step over p0) of P = U0 V.  u1: this column block's U1^T fragments.
 template <int PREC, int N0, int N1>
-__device__ __forceinline__ void coil_v(const Geo<N0, N1>& g, float2* lds, int lane,
-                                       const typename Tile<PREC>::B (&u1)[3]) {
-  const int cb = threadIdx.x >> 6;
-  if (cb >= g.n1b) return;
+__device__ __forceinline__ void coil_v(const Geo<N0, N1>& g, const float2* lds, int lane,
+                                       const typename Tile<PREC>::B (&u1)[3], typename Tile<PREC>::B (&vb)[3]) {
   f32x4 cr[3], ci[3];
 #pragma unroll
   for (int m = 0; m < 3; ++m) { cr[m] = z4(); ci[m] = z4(); }
@@ -204,23 +204,23 @@ __device__ __forceinline__ void coil_v(const Geo<N0, N1>& g, float2* lds, int la
         if (m < g.r0b) Tile<PREC>::mma(cr[m], ci[m], frag_a<PREC>(lds + STAGE_OFF, g.r1b, m, s, lane), u1[s]);
     }
 #pragma unroll
-  for (int m = 0; m < 3; ++m)
-    if (m < g.r0b) put_tile_b<PREC>(lds, g.n1b, cb, m, lane, cr[m], ci[m]);
+  for (int m = 0; m < 3; ++m) vb[m] = tile_as_b<PREC>(cr[m], ci[m]);
 }
 
-// P tiles of the wave's share: P[rb][cb] = sum_s U0[rb][s] V[s][cb] (V staged).
+// P tiles of the wave's share: P[rb][cb] = sum_s U0[rb][s] V[s][cb], U0 staged in the
+// plane region, V in registers.
 template <int PREC, int N0, int N1>
 __device__ __forceinline__ void coil_p(const Geo<N0, N1>& g, const float2* lds, const Share& sh, int lane,
-                                       const typename Tile<PREC>::A (&u0)[3], f32x4 (&pr)[8], f32x4 (&pi)[8]) {
+                                       const typename Tile<PREC>::B (&vb)[3], f32x4 (&pr)[8], f32x4 (&pi)[8]) {
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     pr[i] = z4();
     pi[i] = z4();
-    const int cb = sh.part + i * sh.q;
-    if (sh.on && cb < g.n1b) {
+    const int rb = sh.part + i * sh.q;
+    if (sh.on && rb < g.n0b) {
 #pragma unroll
       for (int s = 0; s < 3; ++s)
-        if (s < g.r0b) Tile<PREC>::mma(pr[i], pi[i], u0[s], frag_b<PREC>(lds, g.n1b, cb, s, lane));
+        if (s < g.r0b) Tile<PREC>::mma(pr[i], pi[i], frag_a<PREC>(lds, g.r0b, rb, s, lane), vb[s]);
     }
   }
 }
@@ -329,26 +329,29 @@ __device__ __forceinline__ void adjoint_w(const PlaneArgs& a, const Geo<N0, N1>&
 }
 
 // ---------------------------------------------------------------- plane kernels
-// Per coil: W (and in the adjoint the coil's samples) loaded early, W staged, V = W U1^T
-// into the plane region, then the wave's P tiles into registers.
+// Per coil: W (and in the adjoint the coil's samples) loaded early; U0 (fragment order,
+// the whole factor) staged in the plane region and W in the stage region; V = W U1^T for
+// the wave's column block into registers, then the wave's P tiles.
 template <int PREC, int N0, int N1>
 __device__ __forceinline__ void coil_map(const PlaneArgs& a, const Geo<N0, N1>& g, float2* lds, const Share& sh,
                                          int lane, int tid, const WPrefetch& w, f32x4 (&pr)[8], f32x4 (&pi)[8]) {
-  // the wave's U0 row block and U1^T column block, in flight across the W store
-  typename Tile<PREC>::A u0[3];
+  // the column block's U1^T fragments, in flight across the stores
   typename Tile<PREC>::B u1[3];
-  const int cb = threadIdx.x >> 6;
 #pragma unroll
-  for (int s = 0; s < 3; ++s) {
-    if (s < g.r0b) u0[s] = frag_a<PREC>(a.U0F, g.r0b, sh.rb, s, lane);
-    if (s < g.r1b) u1[s] = frag_b<PREC>(a.U1TF, g.n1b, min(cb, g.n1b - 1), s, lane);
+  for (int s = 0; s < 3; ++s)
+    if (s < g.r1b) u1[s] = frag_b<PREC>(a.U1TF, g.n1b, sh.cb, s, lane);
+  {
+    const int n = g.n0b * g.r0b * 128;  // 16-byte pieces of U0 in fragment order (2 KiB a fragment)
+    const uint4* src = reinterpret_cast<const uint4*>(a.U0F);
+    uint4* dst = reinterpret_cast<uint4*>(lds);
+    for (int e = tid; e < n; e += PT) dst[e] = src[e];
   }
   w_store<PREC>(g, lds, tid, w);
   __syncthreads();
-  coil_v<PREC>(g, lds, lane, u1);
-  __syncthreads();
-  coil_p<PREC>(g, lds, sh, lane, u0, pr, pi);
-  __syncthreads();  // V is consumed; the plane region is free
+  typename Tile<PREC>::B vb[3];
+  coil_v<PREC>(g, lds, lane, u1, vb);
+  coil_p<PREC>(g, lds, sh, lane, vb, pr, pi);
+  __syncthreads();  // U0 is consumed; the plane region is free
 }
 
 template <int PREC, int N0, int N1>
@@ -373,9 +376,9 @@ __global__ __launch_bounds__(PT) void plane_fwd_kernel(PlaneArgs a) {
     const int lane = threadIdx.x & 63, grp = lane >> 4;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      const int cb = min(sh.part + i * sh.q, g.n1b - 1);
+      const int rb = min(sh.part + i * sh.q, g.n0b - 1);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) xr[i][r] = xp[(16 * sh.rb + 4 * grp + r) * g.n1 + 16 * cb + (lane & 15)];
+      for (int r = 0; r < 4; ++r) xr[i][r] = xp[(16 * rb + 4 * grp + r) * g.n1 + 16 * sh.cb + (lane & 15)];
     }
   }
   for (int j = j0; j < j1; ++j) {
@@ -391,12 +394,12 @@ __global__ __launch_bounds__(PT) void plane_fwd_kernel(PlaneArgs a) {
     if (sh.on) {
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
-        const int cb = sh.part + i * sh.q;
-        if (cb < g.n1b) {
-          const int i1 = 16 * cb + (lane & 15);
+        const int rb = sh.part + i * sh.q;
+        if (rb < g.n0b) {
+          const int i1 = 16 * sh.cb + (lane & 15);
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int i0 = 16 * sh.rb + 4 * grp + r;
+            const int i0 = 16 * rb + 4 * grp + r;
             float2 v = cmul(make_float2(pr[i][r], pi[i][r]), xr[i][r]);
             if ((i0 + i1) & 1) v = make_float2(-v.x, -v.y);
             lds[i0 * g.PS + i1] = v;
@@ -490,29 +493,29 @@ __global__ __launch_bounds__(PT) void plane_adj_kernel(PlaneArgs a) {
         float2 xv[4][4];
 #pragma unroll
         for (int ii = 0; ii < 4; ++ii) {
-          const int cb = sh.part + (4 * hb + ii) * sh.q;
-          if (cb < g.n1b)
+          const int rb = sh.part + (4 * hb + ii) * sh.q;
+          if (rb < g.n0b)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) xv[ii][r] = xp[(16 * sh.rb + 4 * grp + r) * g.n1 + 16 * cb + (lane & 15)];
+            for (int r = 0; r < 4; ++r) xv[ii][r] = xp[(16 * rb + 4 * grp + r) * g.n1 + 16 * sh.cb + (lane & 15)];
         }
         float2 gvs[4][4];  // all of the batch's plane values read before any is rewritten
 #pragma unroll
         for (int ii = 0; ii < 4; ++ii) {
-          const int cb = sh.part + (4 * hb + ii) * sh.q;
-          if (cb < g.n1b)
+          const int rb = sh.part + (4 * hb + ii) * sh.q;
+          if (rb < g.n0b)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) gvs[ii][r] = lds[(16 * sh.rb + 4 * grp + r) * g.PS + 16 * cb + (lane & 15)];
+            for (int r = 0; r < 4; ++r) gvs[ii][r] = lds[(16 * rb + 4 * grp + r) * g.PS + 16 * sh.cb + (lane & 15)];
         }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int ii = 0; ii < 4; ++ii) {
           const int i = 4 * hb + ii;
-          const int cb = sh.part + i * sh.q;
-          if (cb < g.n1b) {
-            const int i1 = 16 * cb + (lane & 15);
+          const int rb = sh.part + i * sh.q;
+          if (rb < g.n0b) {
+            const int i1 = 16 * sh.cb + (lane & 15);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-              const int i0 = 16 * sh.rb + 4 * grp + r;
+              const int i0 = 16 * rb + 4 * grp + r;
               float2 gv = gvs[ii][r];
               if ((i0 + i1) & 1) gv = make_float2(-gv.x, -gv.y);
               if (want_gx) {
@@ -534,11 +537,11 @@ __global__ __launch_bounds__(PT) void plane_adj_kernel(PlaneArgs a) {
     float2* gxp = a.gxpart + ((size_t)gi * g.n2 + i2) * g.n0 * g.n1;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      const int cb = sh.part + i * sh.q;
-      if (cb < g.n1b)
+      const int rb = sh.part + i * sh.q;
+      if (rb < g.n0b)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int i0 = 16 * sh.rb + 4 * grp + r, i1 = 16 * cb + (lane & 15);
+          const int i0 = 16 * rb + 4 * grp + r, i1 = 16 * sh.cb + (lane & 15);
           gxp[i0 * g.n1 + i1] = make_float2(gr[i][r], gim[i][r]);
         }
     }
