@@ -55,6 +55,7 @@ extern "C" {
 typedef struct { float re, im; } maxwell_complex64;
 
 typedef struct maxwell_plan_s* maxwell_plan_t;
+typedef struct maxwell_batch_s* maxwell_batch_t;
 
 typedef enum {
   MAXWELL_OK = 0,
@@ -210,6 +211,34 @@ maxwell_status maxwell_grad(maxwell_plan_t plan, const maxwell_complex64* x,
                             const maxwell_complex64* c, const maxwell_complex64* y,
                             maxwell_complex64* gx, maxwell_complex64* gc, double* loss_dev,
                             void* ws, size_t ws_bytes, void* stream);
+
+/* Batches of independent slices (the batched serving form of the operator: many 2D
+ * problems of uneven sizes, each with its own plan, basis and sampling, Sec. II-B per
+ * slice).
+ * maxwell_batch_create: plans = host array of n >= 1 plan handles (copied; the plans must
+ *   outlive the batch); branches = concurrent branches in [1, 16] (0: 4, capped at n).  The
+ *   slices are assigned to branches at creation, longest first by an estimate of their work.
+ *   Creates the branches' streams (default priority) and events; the only batch call that
+ *   allocates.
+ * maxwell_batch_workspace_size: bytes of the batch workspace (the slices' plan workspaces
+ *   side by side, each 256-byte aligned).
+ * maxwell_batch_grad: maxwell_grad of every slice i on its own buffers x[i], c[i], y[i] ->
+ *   gx[i], gc[i], loss_dev[i] (x, c, y: host arrays of n device pointers; gx, gc, loss_dev:
+ *   host arrays of n device pointers or NULL, entries may be NULL).  Every slice is
+ *   validated as in maxwell_grad before anything is enqueued (errors name the slice).  The
+ *   branches are forked from `stream` by an event and joined back into it, so the whole call
+ *   can be captured into one hipGraph and replayed as a single launch.  Slices must not share
+ *   output buffers; calls on one batch must not overlap in time.
+ * maxwell_batch_destroy: releases the streams and events (not the plans).                  */
+maxwell_status maxwell_batch_create(const maxwell_plan_t* plans, int32_t n, int32_t branches,
+                                    maxwell_batch_t* out);
+maxwell_status maxwell_batch_workspace_size(maxwell_batch_t batch, size_t* bytes);
+maxwell_status maxwell_batch_grad(maxwell_batch_t batch, const maxwell_complex64* const* x,
+                                  const maxwell_complex64* const* c,
+                                  const maxwell_complex64* const* y, maxwell_complex64* const* gx,
+                                  maxwell_complex64* const* gc, double* const* loss_dev, void* ws,
+                                  size_t ws_bytes, void* stream);
+void maxwell_batch_destroy(maxwell_batch_t batch);
 
 /* Kernel timing for benchmarks.  enable != 0 clears the plan's records and
  * starts recording: every kernel launch made by a compute call of this plan is

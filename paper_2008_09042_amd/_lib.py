@@ -29,7 +29,8 @@ EXPORTS = [
     "maxwell_plan_create", "maxwell_plan_destroy", "maxwell_plan_workspace_size", "maxwell_plan_path",
     "maxwell_basis_apply", "maxwell_basis_apply_adjoint", "maxwell_encode", "maxwell_adjoint",
     "maxwell_forward_loss", "maxwell_forward_transfer", "maxwell_adjoint_transfer", "maxwell_grad",
-    "maxwell_last_error", "maxwell_version",
+    "maxwell_last_error", "maxwell_version", "maxwell_batch_create", "maxwell_batch_workspace_size",
+    "maxwell_batch_grad", "maxwell_batch_destroy",
     "maxwell_plan_set_timing", "maxwell_plan_timing",
 ]
 
@@ -103,6 +104,15 @@ def load(path: str = LIB_PATH):
     lib.maxwell_forward_transfer.restype = st
     lib.maxwell_adjoint_transfer.argtypes = [vp, vp, vp, vp, ctypes.c_float, vp, vp, vp, vp, sz, vp]
     lib.maxwell_adjoint_transfer.restype = st
+    lib.maxwell_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(vp)]
+    lib.maxwell_batch_create.restype = st
+    lib.maxwell_batch_workspace_size.argtypes = [vp, ctypes.POINTER(sz)]
+    lib.maxwell_batch_workspace_size.restype = st
+    pa = ctypes.POINTER(vp)
+    lib.maxwell_batch_grad.argtypes = [vp, pa, pa, pa, pa, pa, pa, vp, sz, vp]
+    lib.maxwell_batch_grad.restype = st
+    lib.maxwell_batch_destroy.argtypes = [vp]
+    lib.maxwell_batch_destroy.restype = None
     lib.maxwell_grad.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.maxwell_grad.restype = st
     lib.maxwell_plan_set_timing.argtypes = [vp, ctypes.c_int]

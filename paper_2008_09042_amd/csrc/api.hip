@@ -2,6 +2,7 @@
 // argument validation, workspace layout, and the enqueue sequences of the
 // encoding operator (paper Sec. II-B, Eq. (5)), its Jacobian adjoint
 // (Sec. II-B, J_G^H), and the data-fidelity loss and gradient.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -433,6 +434,145 @@ maxwell_status maxwell_grad(maxwell_plan_t plan, const maxwell_complex64* x, con
                    reinterpret_cast<const float2*>(y), reinterpret_cast<float2*>(gx), reinterpret_cast<float2*>(gc),
                    loss_dev, ws, (hipStream_t)stream),
           "grad");
+  return MAXWELL_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batches of slices
+// A batch runs the gradient of many independent problems (slices, each with its own plan,
+// basis and sampling) in one call: the slices are spread over `branches` internal streams
+// forked from and joined back into the caller's stream with events, so the call can be
+// captured into one hipGraph and replayed as a single launch.  Slices are assigned to
+// branches longest-first by an estimate of their work (basis GEMMs + transforms).
+namespace {
+
+struct Batch {
+  std::vector<const Plan*> plans;
+  std::vector<size_t> off;   // workspace offset of each slice (256-aligned)
+  size_t ws_total = 0;
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> join;
+  hipEvent_t fork = nullptr;
+  std::vector<std::vector<int>> branch;  // slice indices of each branch, in issue order
+};
+
+double slice_work(const Plan& p) {
+  const double N = (double)p.N, J = (double)p.J, K = (double)p.K, M = (double)p.M;
+  return 3.0 * N * J * K + 2.0 * 5.0 * N * J * std::log2(N > 2 ? N : 2) + 16.0 * J * M;
+}
+
+void batch_free(Batch* b) {
+  for (hipStream_t s : b->streams)
+    if (s) (void)hipStreamDestroy(s);
+  for (hipEvent_t e : b->join)
+    if (e) (void)hipEventDestroy(e);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  delete b;
+}
+
+}  // namespace
+
+extern "C" {
+
+maxwell_status maxwell_batch_create(const maxwell_plan_t* plans, int32_t n, int32_t branches,
+                                    maxwell_batch_t* out) {
+  if (!out) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "out is null");
+  *out = nullptr;
+  if (!plans || n < 1) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "plans must hold n >= 1 handles");
+  if (branches < 0 || branches > 16) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "branches must be in [0, 16]");
+  if (branches == 0) branches = 4;
+  if (branches > n) branches = n;
+  Batch* b = new Batch;
+  size_t off = 0;
+  for (int i = 0; i < n; ++i) {
+    if (!plans[i]) {
+      delete b;
+      return fail(MAXWELL_ERR_INVALID_ARGUMENT, "a plan handle is null");
+    }
+    const Plan* p = reinterpret_cast<const Plan*>(plans[i]);
+    b->plans.push_back(p);
+    b->off.push_back(off);
+    off += align256(p->ws_bytes);
+  }
+  b->ws_total = off;
+  // longest-processing-time assignment of slices to branches
+  std::vector<int> idx(n);
+  for (int i = 0; i < n; ++i) idx[i] = i;
+  std::sort(idx.begin(), idx.end(), [&](int u, int v) { return slice_work(*b->plans[u]) > slice_work(*b->plans[v]); });
+  std::vector<double> load(branches, 0.0);
+  b->branch.assign(branches, {});
+  for (int i : idx) {
+    const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    b->branch[k].push_back(i);
+    load[k] += slice_work(*b->plans[i]);
+  }
+  hipError_t e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+  for (int k = 0; e == hipSuccess && k < branches; ++k) {
+    hipStream_t s = nullptr;
+    hipEvent_t ev = nullptr;
+    e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);  // default priority
+    if (e == hipSuccess) b->streams.push_back(s);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) b->join.push_back(ev);
+  }
+  if (e != hipSuccess) {
+    batch_free(b);
+    return hip_fail(e, "batch_create");
+  }
+  *out = reinterpret_cast<maxwell_batch_t>(b);
+  return MAXWELL_OK;
+}
+
+void maxwell_batch_destroy(maxwell_batch_t batch) {
+  if (batch) batch_free(reinterpret_cast<Batch*>(batch));
+}
+
+maxwell_status maxwell_batch_workspace_size(maxwell_batch_t batch, size_t* bytes) {
+  if (!batch || !bytes) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "batch or bytes is null");
+  *bytes = reinterpret_cast<Batch*>(batch)->ws_total;
+  return MAXWELL_OK;
+}
+
+maxwell_status maxwell_batch_grad(maxwell_batch_t batch, const maxwell_complex64* const* x,
+                                  const maxwell_complex64* const* c, const maxwell_complex64* const* y,
+                                  maxwell_complex64* const* gx, maxwell_complex64* const* gc,
+                                  double* const* loss_dev, void* ws, size_t ws_bytes, void* stream) {
+  if (!batch) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "batch is null");
+  Batch* b = reinterpret_cast<Batch*>(batch);
+  if (!x || !c || !y) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "x, c and y must be arrays of n pointers");
+  if (ws_bytes < b->ws_total) return fail(MAXWELL_ERR_WORKSPACE_TOO_SMALL, "workspace smaller than maxwell_batch_workspace_size");
+  if (b->ws_total && !ws) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "workspace is null");
+  if (ws && (reinterpret_cast<uintptr_t>(ws) & 255u)) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "workspace must be 256-byte aligned");
+  const int n = (int)b->plans.size();
+  // every slice validated before anything is enqueued
+  for (int i = 0; i < n; ++i) {
+    const Plan* p = b->plans[i];
+    Check ck(p);
+    ck.in(x[i], p->bytes_x(), "x");
+    ck.in(c[i], p->bytes_c(), "c");
+    ck.in(y[i], p->bytes_y(), "y");
+    ck.out(gx ? gx[i] : nullptr, p->bytes_x(), "gx", false);
+    ck.out(gc ? gc[i] : nullptr, p->bytes_c(), "gc", false);
+    ck.out(loss_dev ? loss_dev[i] : nullptr, sizeof(double), "loss_dev", false);
+    ck.ws(static_cast<char*>(ws) + b->off[i], ws_bytes - b->off[i]);
+    const maxwell_status s = ck.finish();
+    if (s != MAXWELL_OK) return fail(s, "slice " + std::to_string(i) + ": " + g_last_error);
+  }
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipEventRecord(b->fork, st), "batch_grad fork");
+  for (size_t k = 0; k < b->streams.size(); ++k) {
+    hipStream_t bs = b->streams[k];
+    HIP_TRY(hipStreamWaitEvent(bs, b->fork, 0), "batch_grad fork");
+    for (int i : b->branch[k])
+      HIP_TRY(run_grad(*b->plans[i], reinterpret_cast<const float2*>(x[i]), reinterpret_cast<const float2*>(c[i]),
+                       reinterpret_cast<const float2*>(y[i]), gx ? reinterpret_cast<float2*>(gx[i]) : nullptr,
+                       gc ? reinterpret_cast<float2*>(gc[i]) : nullptr, loss_dev ? loss_dev[i] : nullptr,
+                       static_cast<char*>(ws) + b->off[i], bs),
+              "batch_grad");
+    HIP_TRY(hipEventRecord(b->join[k], bs), "batch_grad join");
+    HIP_TRY(hipStreamWaitEvent(st, b->join[k], 0), "batch_grad join");
+  }
   return MAXWELL_OK;
 }
 

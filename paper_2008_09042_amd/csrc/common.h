@@ -33,8 +33,14 @@ struct GemmArgs {
   float alpha;
   const float* alpha_dev;  // optional device scalar multiplying alpha
   int accumulate;
+  int splits;  // reduction split over workgroups: 0 = heuristic, otherwise as given (tuned)
 };
 
+// Split-K factor for g picked by timing candidates on the device (g's operand pointers must
+// be valid; ws must hold max_ws bytes).  The choice is cached per shape for the process; with
+// MAXWELL_GEMM_AUTOTUNE=0 in the environment the heuristic (0) is returned.  Synchronous: for
+// plan creation only.
+int gemm_autotune(const GemmArgs& g, int precision, void* ws, size_t max_ws, hipStream_t st);
 // Bytes of workspace the GEMM needs for split-K partials for these sizes.
 size_t gemm_workspace_bytes(const GemmArgs& g);
 // Enqueue.  `ws` must hold gemm_workspace_bytes(g) bytes (may be null if 0).

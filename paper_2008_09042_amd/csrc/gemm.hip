@@ -19,6 +19,12 @@
 // result is deterministic.
 #include "common.h"
 
+#include <array>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <vector>
+
 namespace mx {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -274,7 +280,9 @@ void choose_split(const GemmArgs& g, int bk, int& splits, int64_t& kchunk) {
   const int64_t tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN) * g.batch;
   splits = 1;
   const int64_t kblocks = (g.K + bk - 1) / bk;
-  if (tiles < 512 && kblocks >= 8) {
+  if (g.splits > 0) {
+    splits = (int)std::min<int64_t>(g.splits, std::max<int64_t>(kblocks, 1));
+  } else if (tiles < 512 && kblocks >= 8) {
     int64_t want = (1024 + tiles - 1) / tiles;
     int64_t maxs = kblocks / 4;
     if (want > maxs) want = maxs;
@@ -325,6 +333,50 @@ hipError_t gemm_launch(const GemmArgs& g, int precision, void* ws, hipStream_t s
   hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, st, g, splits,
                      partial);
   return hipGetLastError();
+}
+
+int gemm_autotune(const GemmArgs& g0, int precision, void* ws, size_t max_ws, hipStream_t st) {
+  const char* env = std::getenv("MAXWELL_GEMM_AUTOTUNE");
+  if (env && env[0] == '0') return 0;
+  if (g0.M <= 0 || g0.N <= 0 || g0.K <= 0 || g0.batch <= 0) return 0;
+  // the shape, strides and flags decide the timing; operand pointers do not
+  const std::array<int64_t, 16> key = {g0.M, g0.N, g0.K, g0.batch, g0.a_ms, g0.a_ks, g0.b_ks, g0.b_ns,
+                                       g0.c_ms, g0.c_ns, g0.conjA, g0.conjB, g0.accumulate, precision,
+                                       g0.alpha_dev != nullptr, 0};
+  static std::mutex mu;
+  static std::map<std::array<int64_t, 16>, int> cache;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+  }
+  const int bk = precision == 1 ? BKS : BK32;
+  const int64_t kblocks = (g0.K + bk - 1) / bk;
+  std::vector<int> cands = {0, 1};
+  for (int s = 2; s <= 1024 && s <= kblocks; s *= 2) cands.push_back(s);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return 0;
+  if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return 0; }
+  int best = 0;
+  float best_ms = 0.f;
+  for (int c : cands) {
+    GemmArgs g = g0;
+    g.splits = c;
+    if (gemm_workspace_bytes(g) > max_ws) continue;
+    bool ok = gemm_launch(g, precision, ws, st) == hipSuccess;  // warm-up
+    ok = ok && hipEventRecord(e0, st) == hipSuccess;
+    for (int r = 0; ok && r < 3; ++r) ok = gemm_launch(g, precision, ws, st) == hipSuccess;
+    ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+    float ms = 0.f;
+    if (!ok || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) break;
+    if (best_ms == 0.f || ms < best_ms) { best_ms = ms; best = c; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipGetLastError();
+  std::lock_guard<std::mutex> lk(mu);
+  cache[key] = best;
+  return best;
 }
 
 hipError_t split_bf16_launch(const float2* src, int64_t count, uint16_t* hi, uint16_t* lo,

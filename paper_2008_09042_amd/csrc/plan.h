@@ -54,6 +54,7 @@ struct Plan {
   CoreGeom cg{};
   uint16_t* d_core_split = nullptr;  // BF16-split core planes (BF16_SPLIT plans only)
   int G_fwd = 2, G_adj = 8;    // coils per plane workgroup (set at plan creation)
+  int split_apply = 0, split_adj = 0;  // dense basis GEMMs: split-K factors tuned at plan creation
   float gscale = 1.0f;         // prod_d (-1)^(n_d/2) / sqrt(N)
   // non-Cartesian sampling (Kaiser-Bessel NUFFT, 2D)
   int g[2] = {0, 0};             // oversampled grid

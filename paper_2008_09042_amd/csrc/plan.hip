@@ -67,6 +67,7 @@ GemmArgs dense_apply_args(const Plan& p, const float2* c, float2* S) {
   g.A = c; g.a_ms = p.K; g.a_ks = 1;
   g.B = p.dense; g.b_ks = 1; g.b_ns = p.K;
   g.C = S; g.c_ms = p.N; g.c_ns = 1;
+  g.splits = p.split_apply;
   return g;
 }
 
@@ -76,6 +77,7 @@ GemmArgs dense_adjoint_args(const Plan& p, const float2* h, float2* c) {
   g.A = h; g.a_ms = p.N; g.a_ks = 1;
   g.B = p.dense; g.b_ks = p.K; g.b_ns = 1; g.conjB = 1;
   g.C = c; g.c_ms = p.K; g.c_ns = 1;
+  g.splits = p.split_adj;
   return g;
 }
 
@@ -508,6 +510,30 @@ maxwell_status plan_build(Plan& p, const maxwell_plan_desc& d, const maxwell_bas
     if ((e = hipMalloc(&p.d_w, p.M * sizeof(float))) != hipSuccess) return hip_err(e);
     if ((e = hipMemcpy(p.d_w, d.weights, p.M * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess)
       return hip_err(e);
+  }
+
+  // dense basis: split-K factors of the two basis GEMMs picked by timing (gemm_autotune),
+  // on scratch operands of the plan's shapes; cached per shape for the process
+  if (p.basis_kind == MAXWELL_BASIS_DENSE && !p.fused && p.J > 0 && p.K > 0 && p.N > 0) {
+    const size_t nbuf = (size_t)p.J * std::max<int64_t>(p.N, p.K) * 8;  // c, S, h and gc all fit
+    const size_t max_ws = (size_t)256 << 20;
+    void *bufA = nullptr, *bufC = nullptr, *bufW = nullptr;
+    bool ok = hipMalloc(&bufA, nbuf) == hipSuccess && hipMalloc(&bufC, nbuf) == hipSuccess &&
+              hipMalloc(&bufW, max_ws) == hipSuccess && hipMemset(bufA, 0, nbuf) == hipSuccess &&
+              hipMemset(bufC, 0, nbuf) == hipSuccess;
+    if (ok) {
+      p.split_apply = gemm_autotune(dense_apply_args(p, reinterpret_cast<const float2*>(bufA),
+                                                     reinterpret_cast<float2*>(bufC)),
+                                    p.precision, bufW, max_ws, 0);
+      p.split_adj = gemm_autotune(dense_adjoint_args(p, reinterpret_cast<const float2*>(bufA),
+                                                     reinterpret_cast<float2*>(bufC)),
+                                  p.precision, bufW, max_ws, 0);
+    }
+    (void)hipStreamSynchronize(0);
+    if (bufA) (void)hipFree(bufA);
+    if (bufC) (void)hipFree(bufC);
+    if (bufW) (void)hipFree(bufW);
+    (void)hipGetLastError();
   }
 
   // workspace layout

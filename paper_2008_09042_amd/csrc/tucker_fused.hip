@@ -146,14 +146,18 @@ __device__ __forceinline__ void plane_fft(const PlaneArgs& a, const Geo<N0, N1>&
 // ---------------------------------------------------------------- coil map
 // W = T3[j][i2] (r0 x r1) as the A operand of V = W U1^T: each thread gathers the values
 // of at most two fragment lanes into registers (issued early), then stores them split.
+// The thread's element offsets in a W slab are the same for every coil: computed once per
+// workgroup (-1 for padding entries).
 struct WPrefetch {
   float2 v[2][4];
 };
+struct WSlots {
+  unsigned p[4];  // entry (q, t) in bits 16 (t & 1) of p[2 q + t / 2]; 0xffff for padding
+};
 
 template <int N0, int N1>
-__device__ __forceinline__ void w_load(const PlaneArgs& a, const Geo<N0, N1>& g, int j, int i2, int tid,
-                                       WPrefetch& w) {
-  const float2* src = a.T3 + ((size_t)j * g.n2 + i2) * g.r0 * g.r1;
+__device__ __forceinline__ WSlots w_slots(const Geo<N0, N1>& g, int tid) {
+  WSlots w;
   const int nfl = g.r0b * g.r1b * 64;  // (o block, step, lane) entries
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
@@ -162,17 +166,37 @@ __device__ __forceinline__ void w_load(const PlaneArgs& a, const Geo<N0, N1>& g,
     const int mb = f / g.r1b, s = f % g.r1b;
     const int p0 = 16 * mb + (lane & 15);
 #pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      unsigned pk = 0;
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int p1 = 16 * s + 4 * (lane >> 4) + 2 * h + b;
+        const unsigned o = (e < nfl && p0 < g.r0 && p1 < g.r1) ? (unsigned)(p0 * g.r1 + p1) : 0xffffu;
+        pk |= o << (16 * b);
+      }
+      w.p[2 * q + h] = pk;
+    }
+  }
+  return w;
+}
+
+template <int N0, int N1>
+__device__ __forceinline__ void w_load(const PlaneArgs& a, const Geo<N0, N1>& g, int j, int i2, const WSlots& sl,
+                                       WPrefetch& w) {
+  const float2* src = a.T3 + ((size_t)j * g.n2 + i2) * g.r0 * g.r1;
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
     for (int t = 0; t < 4; ++t) {
       // unconditional loads (an in-range address for the padding entries, zeroed by a
       // multiply, which keeps the compiler from moving the load under a branch): a load
       // under a branch would make every later wait a full drain
-      const int p1 = 16 * s + 4 * (lane >> 4) + t;
-      const bool in = e < nfl && p0 < g.r0 && p1 < g.r1;
-      const float2 v = src[in ? (size_t)p0 * g.r1 + p1 : 0];
-      const float m = in ? 1.f : 0.f;
+      const unsigned o = (sl.p[2 * q + t / 2] >> (16 * (t & 1))) & 0xffffu;
+      const bool pad = o == 0xffffu;
+      const float2 v = src[pad ? 0u : o];
+      const float m = pad ? 0.f : 1.f;
       w.v[q][t] = make_float2(v.x * m, v.y * m);
     }
-  }
 }
 
 template <int PREC, int N0, int N1>
@@ -368,8 +392,9 @@ __global__ __launch_bounds__(PT) void plane_fwd_kernel(PlaneArgs a) {
   for (int k = 0; k < SCAT; ++k) pq[k] = (int)threadIdx.x + k * PT < a.L ? a.pos[threadIdx.x + k * PT] : -1;
   load_twiddles(a, g, lds);
   const int j0 = gi * a.G, j1 = min(a.J, (gi + 1) * a.G);
+  const WSlots wsl = w_slots(g, (int)threadIdx.x);
   WPrefetch w;  // W of the next coil, loaded one coil ahead
-  if (j0 < j1) w_load(a, g, j0, i2, threadIdx.x, w);
+  if (j0 < j1) w_load(a, g, j0, i2, wsl, w);
   // the x values of the wave's share, the same for every coil: loaded once
   float2 xr[8][4];
   {
@@ -389,7 +414,7 @@ __global__ __launch_bounds__(PT) void plane_fwd_kernel(PlaneArgs a) {
     const int lane = tid & 63, grp = lane >> 4;
     f32x4 pr[8], pi[8];
     coil_map<PREC>(a, g, lds, sh, lane, tid, w, pr, pi);
-    if (j + 1 < j1) w_load(a, g, j + 1, i2, tid, w);
+    if (j + 1 < j1) w_load(a, g, j + 1, i2, wsl, w);
     // m = x (.) P with the input chessboard sign
     if (sh.on) {
 #pragma unroll
@@ -462,7 +487,7 @@ __global__ __launch_bounds__(PT) void plane_adj_kernel(PlaneArgs a) {
     f32x4 pr[8], pi[8];
     if (want_gx) {
       WPrefetch w;
-      w_load(a, g, j, i2, tid, w);
+      w_load(a, g, j, i2, w_slots(g, tid), w);  // offsets recomputed: no registers held across coils
       coil_map<PREC>(a, g, lds, sh, lane, tid, w, pr, pi);  // B c recomputed
     }
     // zero-filled scatter (with the chessboard sign)

@@ -261,6 +261,102 @@ class MaxwellPlan:
         return loss, gx, gc
 
 
+class MaxwellBatch:
+    """Gradients of many independent slices (each a MaxwellPlan) in one call.
+
+    grad(xs, cs, ys) runs maxwell_batch_grad eagerly.  capture(xs, cs, ys) records that
+    call into one CUDA/HIP graph on fixed buffers (the tensors passed in, whose contents the
+    caller may update in place, and outputs owned here); replay() launches the graph and
+    returns the same output tensors each time.  The slices run on `branches` concurrent
+    branches forked from the current stream."""
+
+    def __init__(self, plans, branches: int = 4):
+        self.plans = list(plans)
+        if not self.plans:
+            raise ValueError("a batch needs at least one plan")
+        self.device = self.plans[0].device
+        if any(p.device != self.device for p in self.plans):
+            raise ValueError("all plans of a batch must be on one device")
+        self.lib = self.plans[0].lib
+        n = len(self.plans)
+        arr = (ctypes.c_void_p * n)(*[p.handle.value for p in self.plans])
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            L.check(self.lib.maxwell_batch_create(arr, n, branches, ctypes.byref(handle)))
+        self.handle = handle
+        nbytes = ctypes.c_size_t()
+        L.check(self.lib.maxwell_batch_workspace_size(self.handle, ctypes.byref(nbytes)))
+        self.ws_bytes = int(nbytes.value)
+        raw = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-raw.data_ptr()) % 256
+        self._ws_raw = raw
+        self.ws = raw[off:off + self.ws_bytes]
+        self.graph = None
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            try:
+                torch.cuda.synchronize(self.device)
+            except Exception:
+                pass
+            self.lib.maxwell_batch_destroy(h)
+            self.handle = None
+
+    def _outputs(self):
+        gx = [p._new(p.dims) for p in self.plans]
+        gc = [p._new((p.J, p.K)) for p in self.plans]
+        loss = torch.zeros(len(self.plans), dtype=torch.float64, device=self.device)
+        return loss, gx, gc
+
+    def _call(self, xs, cs, ys, loss, gx, gc):
+        n = len(self.plans)
+        P = ctypes.c_void_p * n
+        ptrs = lambda ts: P(*[t.data_ptr() for t in ts])  # noqa: E731
+        lp = P(*[loss.data_ptr() + 8 * i for i in range(n)])
+        L.check(self.lib.maxwell_batch_grad(self.handle, ptrs(xs), ptrs(cs), ptrs(ys), ptrs(gx), ptrs(gc), lp,
+                                            ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes, _stream()))
+
+    def _inputs(self, xs, cs, ys):
+        if not (len(xs) == len(cs) == len(ys) == len(self.plans)):
+            raise ValueError("xs, cs and ys need one tensor per slice")
+        xs = [p._in(x, p.dims, "x") for p, x in zip(self.plans, xs)]
+        cs = [p._in(c, (p.J, p.K), "c") for p, c in zip(self.plans, cs)]
+        ys = [p._in(y, (p.J, p.M), "y") for p, y in zip(self.plans, ys)]
+        return xs, cs, ys
+
+    def grad(self, xs, cs, ys):
+        """(loss [n] FP64, [gx_i], [gc_i]) for every slice, as MaxwellPlan.grad."""
+        xs, cs, ys = self._inputs(xs, cs, ys)
+        loss, gx, gc = self._outputs()
+        self._call(xs, cs, ys, loss, gx, gc)
+        return loss, gx, gc
+
+    def capture(self, xs, cs, ys):
+        """Record the batch gradient on these buffers into one graph."""
+        given = list(xs) + list(cs) + list(ys)
+        xs, cs, ys = self._inputs(xs, cs, ys)
+        if any(t.data_ptr() != g.data_ptr() for t, g in zip(xs + cs + ys, given)):
+            raise ValueError("capture needs contiguous complex64 inputs (the graph reads them in place)")
+        self._bound = (xs, cs, ys)
+        self._out = self._outputs()
+        side = torch.cuda.Stream(device=self.device)
+        side.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.stream(side):  # warm-up outside the capture
+            self._call(xs, cs, ys, *self._out)
+        torch.cuda.current_stream(self.device).wait_stream(side)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self._call(xs, cs, ys, *self._out)
+        return self._out
+
+    def replay(self):
+        if self.graph is None:
+            raise RuntimeError("capture() first")
+        self.graph.replay()
+        return self._out
+
+
 class MaxwellEncode(torch.autograd.Function):
     """y = E(x, c); backward applies the Jacobian adjoint J^H to the incoming gradient.
 

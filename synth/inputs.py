@@ -42,6 +42,7 @@ __all__ = [
     "smooth_factor", "tucker_basis", "coefficients", "line_mask", "poisson_disc_plane",
     "plane_mask_to_lines", "plane_mask_to_indices", "golden_angle_radial", "ramp_dcf",
     "unit_noise", "noise_scale_for_snr", "Problem", "make_problem", "CONFIGS",
+    "BATCH", "slice_rng", "vd_random_mask", "slice_problems",
 ]
 
 
@@ -407,3 +408,76 @@ CONFIGS = {
             basis_kind="tucker", ranks=(40, 40, 40), degree=6, kmax=3.0, sampling="cartesian",
             mask="pd3d", R=8.0, centre=20),
 }
+
+
+# ---------------------------------------------------------------- batched slices
+# Many independent 2D problems of uneven sizes, each with its own dense basis, coils and
+# sampling (the batched serving form).  Slice i draws everything from
+# SeedSequence([config, role, i]).  Two departures from the single-problem recipe keep the
+# generation of 64 slices (3.8 GB of bases) to seconds: the bases are i.i.d. complex
+# Gaussian columns scaled by 1/sqrt(N) (near-orthonormal for N >> K; their content does not
+# change the work, their size does), and the Cartesian masks are variable-density random
+# (Bernoulli with a density falling as (1 - r)^2 over the normalised radius, plus a fully
+# sampled centre) rather than Poisson-disc.
+BATCH = dict(name="batch64_slices_dense", n_slices=64, sizes=(128, 192, 256, 320), Js=(8, 16, 32),
+             Ks=(64, 128, 256))
+
+
+def slice_rng(config: int, role: int, i: int) -> np.random.Generator:
+    return np.random.default_rng(np.random.SeedSequence([int(config), int(role), int(i)]))
+
+
+def vd_random_mask(rng: np.random.Generator, shape: Sequence[int], R: float, centre: int) -> np.ndarray:
+    """Sorted linear indices of a variable-density random 2D mask with about N/R samples."""
+    ny, nx = (int(n) for n in shape)
+    ky = (np.arange(ny) - ny // 2) / (ny / 2)
+    kx = (np.arange(nx) - nx // 2) / (nx / 2)
+    r = np.minimum(np.sqrt(ky[:, None] ** 2 + kx[None, :] ** 2), 1.0)
+    dens = (1.0 - r) ** 2
+    c0y, c0x = ny // 2 - centre // 2, nx // 2 - centre // 2
+    core = np.zeros((ny, nx), dtype=bool)
+    core[max(c0y, 0):c0y + centre, max(c0x, 0):c0x + centre] = True
+    want = max(ny * nx / R - core.sum(), 0.0)
+    lo, hi = 0.0, 1e6
+    for _ in range(60):  # scale s with sum(min(1, s dens)) = want outside the centre
+        s = 0.5 * (lo + hi)
+        if np.minimum(1.0, s * dens)[~core].sum() < want:
+            lo = s
+        else:
+            hi = s
+    p = np.minimum(1.0, hi * dens)
+    m = core | (rng.uniform(size=(ny, nx)) < p)
+    return np.flatnonzero(m.reshape(-1)).astype(np.int64)
+
+
+def slice_problems(config: int = 5, n_slices: int = 64, sizes=BATCH["sizes"], Js=BATCH["Js"],
+                   Ks=BATCH["Ks"], spokes=(32, 128)) -> List[Problem]:
+    """The batched-slices workload: n_slices seeded 2D problems (see the block comment)."""
+    out = []
+    for i in range(n_slices):
+        rp = slice_rng(config, ROLE_SAMPLING, i)
+        dims = (int(rp.choice(sizes)), int(rp.choice(sizes)))
+        J, K = int(rp.choice(Js)), int(rp.choice(Ks))
+        cart = bool(rp.uniform() < 0.5)
+        p = Problem(name=f"slice{i}", dims=dims, J=J, K=K, basis_kind="dense",
+                    sampling="cartesian" if cart else "radial")
+        N = dims[0] * dims[1]
+        rb = slice_rng(config, ROLE_BASIS, i)
+        p.B = ((rb.standard_normal((N, K), dtype=np.float32)
+                + 1j * rb.standard_normal((N, K), dtype=np.float32)) / np.float32(math.sqrt(2.0 * N)))
+        if cart:
+            R = float(rp.uniform(3.0, 8.0))
+            p.mask_idx = vd_random_mask(rp, dims, R, max(16, max(dims) // 10))
+        else:
+            ns = int(rp.integers(spokes[0], spokes[1] + 1))
+            nr = 2 * max(dims)
+            p.traj = golden_angle_radial(dims, ns, nr)
+            p.weights = ramp_dcf(p.traj, dims, nr)
+        p.x_true = phantom(slice_rng(config, ROLE_PHANTOM, i), dims)
+        p.c_true = coefficients(slice_rng(config, ROLE_CTRUE, i), J, K)
+        p.noise = unit_noise(slice_rng(config, ROLE_NOISE, i), J, p.M)
+        re = slice_rng(config, ROLE_EVAL, i)
+        p.x0 = phantom(re, dims)
+        p.c0 = coefficients(re, J, K)
+        out.append(p)
+    return out

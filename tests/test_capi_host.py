@@ -185,6 +185,18 @@ def test_null_arguments(lib):
     assert lib.maxwell_adjoint(None, z, z, z, 1.0, None, z, z, None, 0, None) == L.MAXWELL_ERR_INVALID_ARGUMENT
     assert lib.maxwell_forward_loss(None, z, z, z, z, None, None, 0, None) == L.MAXWELL_ERR_INVALID_ARGUMENT
     assert lib.maxwell_forward_transfer(None, z, z, z, z, None, None, 0, None) == L.MAXWELL_ERR_INVALID_ARGUMENT
+    out = ctypes.c_void_p()
+    assert lib.maxwell_batch_create(None, 1, 0, ctypes.byref(out)) == L.MAXWELL_ERR_INVALID_ARGUMENT
+    assert lib.maxwell_batch_create(None, 1, 0, None) == L.MAXWELL_ERR_INVALID_ARGUMENT
+    arr = (ctypes.c_void_p * 1)(None)
+    assert lib.maxwell_batch_create(arr, 1, 0, ctypes.byref(out)) == L.MAXWELL_ERR_INVALID_ARGUMENT
+    assert "null" in lib.maxwell_last_error().decode()
+    assert lib.maxwell_batch_create(arr, 1, 17, ctypes.byref(out)) == L.MAXWELL_ERR_INVALID_ARGUMENT
+    assert lib.maxwell_batch_workspace_size(None, ctypes.byref(sz)) == L.MAXWELL_ERR_INVALID_ARGUMENT
+    pz = (ctypes.c_void_p * 1)(FAKE)
+    assert (lib.maxwell_batch_grad(None, pz, pz, pz, None, None, None, None, 0, None)
+            == L.MAXWELL_ERR_INVALID_ARGUMENT)
+    lib.maxwell_batch_destroy(None)  # no-op
     assert (lib.maxwell_adjoint_transfer(None, z, z, z, 1.0, None, z, z, None, 0, None)
             == L.MAXWELL_ERR_INVALID_ARGUMENT)
     assert lib.maxwell_basis_apply(None, z, z, None, 0, None) == L.MAXWELL_ERR_INVALID_ARGUMENT
