@@ -102,7 +102,8 @@ typedef struct {
  *             i - n[d]/2).  Host pointer, copied into the plan.
  *           NONCARTESIAN (2D only): `traj` holds M x ndim floats in cycles/FOV,
  *             column d paired with axis d, each in [-n[d]/2, n[d]/2).  Host pointer,
- *             copied.  kb_width W (2..8), oversamp sigma (sigma*n[d] even), kb_beta
+ *             copied.  kb_width W (2..8), oversamp sigma (sigma*n[d] even and
+ *             >= W), kb_beta
  *             (<= 0: Beatty-Nishimura-Pauly, pi sqrt((W/sigma)^2 (sigma-1/2)^2 - 0.8)).
  * weights   optional M nonnegative data weights w_m (host pointer, copied) used by
  *           maxwell_forward_loss / maxwell_grad; NULL means w = 1.  They never enter

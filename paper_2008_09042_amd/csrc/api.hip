@@ -107,6 +107,7 @@ static maxwell_status validate_desc(const maxwell_plan_desc* d, const maxwell_ba
         return fail(MAXWELL_ERR_INVALID_ARGUMENT, "oversamp * n must be an even integer");
       int rad[12];
       if (!fft_factorise(gi, rad)) return fail(MAXWELL_ERR_UNSUPPORTED, "oversampled grid must factor into 2, 3, 5 and be <= 4096");
+      if (gi < d->kb_width) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "oversampled grid must be at least kb_width");
     }
     for (int64_t m = 0; m < d->M * d->ndim; ++m) {
       const float v = d->traj[m];

@@ -62,6 +62,7 @@ struct FftAxisArgs {
   int nrad; int radix[12];
   // optional image premultiply (forward, first axis pass): m = x[img_index] * src
   const float2* premul; int64_t outer_per_coil;
+  int lines;              // lines per workgroup (set by fft_axis_launch)
 };
 hipError_t fft_axis_launch(const FftAxisArgs& a, hipStream_t st);
 int fft_factorise(int64_t n, int* radix);  // returns number of passes, 0 if unsupported

@@ -22,27 +22,35 @@ namespace mx {
 namespace {
 
 constexpr int NT = 256;
-constexpr int TILE = 8192;          // complex elements per LDS tile (before padding)
-constexpr int LDS_ELEMS = TILE + 256;
+constexpr int TILE = 8192;          // complex elements per LDS tile at most (before padding)
+constexpr int TW_LDS_MAX = 1024;    // twiddle tables up to this length are staged in LDS
 
+// complex elements of the LDS tile for T lines of length n
+__host__ __device__ inline int tile_elems(int n, int T, bool contiguous) { return contiguous ? T * (n + 1) : T * n; }
+
+// TWL: the twiddle table is copied into LDS behind the tile.
+template <bool TWL>
 __global__ __launch_bounds__(NT) void fft_axis_kernel(FftAxisArgs a) {
-  __shared__ float2 lds[LDS_ELEMS];
+  extern __shared__ float2 lds[];
   const int n = (int)a.n;
+  const float2* tw = a.twiddle;
+  if constexpr (TWL) {
+    float2* twl = lds + tile_elems(n, a.lines, a.inner == 1);
+    for (int i = threadIdx.x; i < n; i += NT) twl[i] = a.twiddle[i];
+    tw = twl;
+  }
   LdsLines tg;
   int64_t o0, t0;
   int Tvalid;
   if (a.inner == 1) {
-    tg.T = TILE / n;
-    if (tg.T > 64) tg.T = 64;
+    tg.T = a.lines;
     tg.LS = n + 1;
     tg.ES = 1;
     o0 = (int64_t)blockIdx.x * tg.T;
     t0 = 0;
     Tvalid = (int)((a.outer - o0) < tg.T ? (a.outer - o0) : tg.T);
   } else {
-    tg.T = TILE / n;
-    if (tg.T > 64) tg.T = 64;
-    if (tg.T > a.inner) tg.T = (int)a.inner;
+    tg.T = a.lines;
     tg.LS = 1;
     tg.ES = tg.T;
     const int64_t chunks = (a.inner + tg.T - 1) / tg.T;
@@ -70,7 +78,7 @@ __global__ __launch_bounds__(NT) void fft_axis_kernel(FftAxisArgs a) {
     lds[l * tg.LS + i * tg.ES] = v;
   }
   __syncthreads();
-  lds_fft_lines<NT, TILE>(lds, tg, n, a.radix, a.nrad, a.twiddle, a.dir);
+  lds_fft_lines<NT, TILE>(lds, tg, n, a.radix, a.nrad, tw, a.dir);
   // ---- store with the output chessboard sign, global sign and n^{-1/2}
   const float scale = (((n / 2) & 1) ? -1.f : 1.f) * rsqrtf((float)n);
   for (int e = threadIdx.x; e < total; e += NT) {
@@ -104,19 +112,31 @@ int fft_factorise(int64_t n, int* radix) {
   return np;
 }
 
-hipError_t fft_axis_launch(const FftAxisArgs& a, hipStream_t st) {
+// Lines per workgroup: enough workgroups to spread a small transform over the whole
+// chip (about 1024), at most 64 lines or TILE elements per tile, and for strided lines
+// at least 8 adjacent ones (64-byte runs per load).
+hipError_t fft_axis_launch(const FftAxisArgs& args, hipStream_t st) {
+  FftAxisArgs a = args;
   const int n = (int)a.n;
-  int T = TILE / n;
-  if (T > 64) T = 64;
-  int64_t blocks;
-  if (a.inner == 1) {
-    blocks = (a.outer + T - 1) / T;
-  } else {
-    if (T > a.inner) T = (int)a.inner;
-    blocks = a.outer * ((a.inner + T - 1) / T);
-  }
+  const bool contiguous = a.inner == 1;
+  const bool twl = n <= TW_LDS_MAX;
+  int Tmax = (TILE - (twl ? n : 0)) / (contiguous ? n + 1 : n);
+  if (Tmax > 64) Tmax = 64;
+  if (Tmax < 1) Tmax = 1;
+  const int64_t lines = a.outer * a.inner;
+  int64_t T = (lines + 1023) / 1024;
+  if (!contiguous && T < 8) T = 8;
+  if (T > Tmax) T = Tmax;
+  if (!contiguous && T > a.inner) T = a.inner;
+  if (T < 1) T = 1;
+  a.lines = (int)T;
+  const int64_t blocks = contiguous ? (a.outer + T - 1) / T : a.outer * ((a.inner + T - 1) / T);
   if (blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(fft_axis_kernel, dim3((unsigned)blocks), dim3(NT), 0, st, a);
+  const size_t lds = (size_t)(tile_elems(n, a.lines, contiguous) + (twl ? n : 0)) * sizeof(float2);
+  if (twl)
+    hipLaunchKernelGGL(fft_axis_kernel<true>, dim3((unsigned)blocks), dim3(NT), lds, st, a);
+  else
+    hipLaunchKernelGGL(fft_axis_kernel<false>, dim3((unsigned)blocks), dim3(NT), lds, st, a);
   return hipGetLastError();
 }
 

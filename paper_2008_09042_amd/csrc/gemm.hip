@@ -250,20 +250,40 @@ __global__ __launch_bounds__(NT) void cgemm_bf16s_kernel(GemmArgs g, int splits,
   store_tile(g, t, b, sp, splits, partial, accR, accI);
 }
 
-__global__ void splitk_reduce_kernel(GemmArgs g, int splits, const float2* partial) {
+// C = alpha * sum_p partial[p] (+ C).  G threads per output element, each summing every G-th
+// split in four interleaved chains (independent loads), combined through LDS in a fixed
+// order: the result does not depend on timing.
+template <int G>
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs g, int splits, const float2* partial) {
+  constexpr int OPB = 256 / G;  // output elements per workgroup
+  __shared__ float2 red[G][OPB];
   const int64_t total = g.batch * g.M * g.N;
+  const int lo = threadIdx.x % OPB, grp = threadIdx.x / OPB;
+  const int64_t e = blockIdx.x * (int64_t)OPB + lo;
+  float2 s0 = make_float2(0.f, 0.f), s1 = s0, s2 = s0, s3 = s0;
+  if (e < total) {
+    const float2* pe = partial + e;
+    int p = grp;
+    for (; p + 3 * G < splits; p += 4 * G) {
+      s0 = cadd(s0, pe[(int64_t)p * total]);
+      s1 = cadd(s1, pe[(int64_t)(p + G) * total]);
+      s2 = cadd(s2, pe[(int64_t)(p + 2 * G) * total]);
+      s3 = cadd(s3, pe[(int64_t)(p + 3 * G) * total]);
+    }
+    for (; p < splits; p += G) s0 = cadd(s0, pe[(int64_t)p * total]);
+  }
+  red[grp][lo] = cadd(cadd(s0, s1), cadd(s2, s3));
+  __syncthreads();
+  if (grp != 0 || e >= total) return;
+  float2 s = red[0][lo];
+  for (int q = 1; q < G; ++q) s = cadd(s, red[q][lo]);
+  const int64_t n = e % g.N, m = (e / g.N) % g.M, b = e / (g.N * g.M);
   float alpha = g.alpha;
   if (g.alpha_dev) alpha *= *g.alpha_dev;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t n = e % g.N, m = (e / g.N) % g.M, b = e / (g.N * g.M);
-    float2 s = make_float2(0.f, 0.f);
-    for (int p = 0; p < splits; ++p) s = cadd(s, partial[((int64_t)p * g.batch + b) * g.M * g.N + m * g.N + n]);
-    float2* c = g.C + b * g.c_bs + m * g.c_ms + n * g.c_ns;
-    s = cscale(s, alpha);
-    if (g.accumulate) s = cadd(s, *c);
-    *c = s;
-  }
+  float2* c = g.C + b * g.c_bs + m * g.c_ms + n * g.c_ns;
+  s = cscale(s, alpha);
+  if (g.accumulate) s = cadd(s, *c);
+  *c = s;
 }
 
 __global__ void split_bf16_kernel(const float2* src, int64_t count, uint16_t* hi, uint16_t* lo) {
@@ -327,11 +347,18 @@ hipError_t gemm_launch(const GemmArgs& g, int precision, void* ws, hipStream_t s
     hipLaunchKernelGGL(cgemm_f32_kernel, grid, dim3(NT), 0, st, g, splits, kchunk, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || splits <= 1) return e;
+  // threads per output: enough workgroups (about 512) when there are few outputs
   const int64_t total = g.batch * g.M * g.N;
-  int64_t blocks = (total + 255) / 256;
-  if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, st, g, splits,
-                     partial);
+  int G = 1;
+  while (G < 16 && 2 * G <= splits && total * G < 512 * 256) G *= 2;
+  const unsigned blocks = (unsigned)((total + 256 / G - 1) / (256 / G));
+  switch (G) {
+    case 1: hipLaunchKernelGGL(splitk_reduce_kernel<1>, dim3(blocks), dim3(256), 0, st, g, splits, partial); break;
+    case 2: hipLaunchKernelGGL(splitk_reduce_kernel<2>, dim3(blocks), dim3(256), 0, st, g, splits, partial); break;
+    case 4: hipLaunchKernelGGL(splitk_reduce_kernel<4>, dim3(blocks), dim3(256), 0, st, g, splits, partial); break;
+    case 8: hipLaunchKernelGGL(splitk_reduce_kernel<8>, dim3(blocks), dim3(256), 0, st, g, splits, partial); break;
+    default: hipLaunchKernelGGL(splitk_reduce_kernel<16>, dim3(blocks), dim3(256), 0, st, g, splits, partial); break;
+  }
   return hipGetLastError();
 }
 

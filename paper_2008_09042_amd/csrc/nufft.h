@@ -14,17 +14,22 @@ struct NufftArgs {
   const float* iphi1;         // [n1]
   const int2* base;           // [M] grid index of the first tap on each axis (wrapped)
   const float* wts;           // [M][2][W] tap weights phi(u - g) per axis
-  const int32_t* tile_ptr;    // [ntiles + 1] CSR offsets of the spread tiles
-  const int32_t* tile_idx;    // samples whose footprint meets each tile
+  // the samples sorted by the cell (row-major) of their first tap, for the spread
+  const int32_t* cell_ptr;    // [g0 * g1 + 1] CSR offsets of the cells into the sorted order
+  const int32_t* s_perm;      // [M] original index of each sorted sample
+  const int32_t* s_col;       // [M] first-tap column of each sorted sample
+  const float* s_wts;         // [M][16] tap weights of each sorted sample: axis 0 in [0, W), axis 1 in [8, 8 + W)
   float cscale;               // sqrt(g0 g1 / (n0 n1)): unitary DFT -> the operator's scaling
 };
 
-int nufft_tiles(int g0, int g1);
-int nufft_tile_edge();
+// Coils per spread workgroup, and the bytes of the staging buffer the spread needs.
+int spread_group(int J);
+size_t spread_stage_bytes(int J, int64_t M);
 hipError_t pad_deapod_launch(const NufftArgs& a, const float2* S, const float2* x, float2* grid, hipStream_t st);
 hipError_t crop_deapod_launch(const NufftArgs& a, const float2* grid, float2* out, hipStream_t st);
 hipError_t degrid_launch(const NufftArgs& a, const float2* grid, float2* y, hipStream_t st);
-hipError_t spread_launch(const NufftArgs& a, const float2* y, float alpha, const float* scale_dev, float2* grid,
-                         hipStream_t st);
+// grid = alpha * (*scale_dev) * spread(y); ys is a staging buffer of spread_stage_bytes(J, M).
+hipError_t spread_launch(const NufftArgs& a, const float2* y, float alpha, const float* scale_dev, float2* ys,
+                         float2* grid, hipStream_t st);
 
 }  // namespace mx

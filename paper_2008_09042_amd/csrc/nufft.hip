@@ -10,11 +10,10 @@
 //   type 1 (samples -> image)   exact transpose: spread (grid kernel), inverse
 //                               DFT, crop and deapodise (crop kernel)
 //
-// The spread is output-stationary: the grid is cut into 32 x 32 tiles; at plan
-// time every sample is listed under each tile its footprint touches (with the
-// periodic wrap of the grid); a workgroup stages its tile's samples through
-// LDS and every thread sums the contributions to its own grid points in list
-// order.  No atomics, so results are bitwise reproducible.
+// The spread is output-stationary: every grid point gathers the samples whose
+// W x W footprint covers it, found through a plan-time sort of the samples by
+// grid cell, and sums them in a fixed order.  No atomics, so results are
+// bitwise reproducible.
 //
 // Per-sample tap weights phi(u - g) are computed on the host in FP64 at plan
 // time (I0 from its power series), so the kernels only multiply and add.
@@ -90,65 +89,157 @@ __global__ void degrid_kernel(NufftArgs a, const float2* __restrict__ grid, floa
   }
 }
 
-// Output-stationary spread: one workgroup per (coil, tile).
-constexpr int TILE = 32;            // tile edge (grid cells)
-constexpr int BATCH = 256;          // samples staged per LDS round
+// Spread, gather form.  Samples are sorted at plan time by the grid cell of their first
+// tap (row-major), with a CSR over the cells; grid point (r, c) receives the samples whose
+// first tap lies in rows r-W+1..r and columns c-W+1..c (periodic): for each row offset t0 a
+// window of W consecutive cells, which is one contiguous range of sorted samples (two at
+// the column wrap).  A staging pass first gathers the samples' values into sorted order,
+// coil-minor and padded to a whole number of coil groups, so a thread reads each sample's
+// JG values as one contiguous run.
+//
+// A workgroup covers one grid row, 64 columns and JG coils with W waves: wave t0 sums the
+// row window r - t0 for every lane's column, and the W partial sums are added in t0 order
+// through LDS.  Splitting the windows over waves shortens the longest chain of dependent
+// loads (the grid points near the centre of a radial trajectory see hundreds of samples).
+// Fixed summation order, no atomics.
+constexpr int SPC = 64;             // grid columns per workgroup (one per lane)
+constexpr int STG = 64;             // samples per staging workgroup
+constexpr int SREC = 16;            // floats per sorted-sample weight record: w0 [0, 8), w1 [8, 16)
 
-__global__ __launch_bounds__(NT) void spread_kernel(NufftArgs a, const float2* __restrict__ y, float alpha,
-                                                    const float* __restrict__ scale_dev, float2* __restrict__ grid) {
-  __shared__ int2 sb[BATCH];
-  __shared__ float sw[BATCH][2 * 8];
-  __shared__ float2 sy[BATCH];
-  const int tiles1 = (a.g1 + TILE - 1) / TILE;
-  const int ntiles = ((a.g0 + TILE - 1) / TILE) * tiles1;
-  const int j = blockIdx.x / ntiles, tile = blockIdx.x % ntiles;
-  const int ta = (tile / tiles1) * TILE, tb = (tile % tiles1) * TILE;
-  const int W = a.W;
-  float s = alpha * a.cscale;
-  if (scale_dev) s *= *scale_dev;
-  // each thread owns 4 grid points of the tile: rows ta + (threadIdx.x / 32) + 8 q, column tb + threadIdx.x % 32
-  const int cb = tb + (threadIdx.x % TILE);
-  float2 acc[4];
-  int ra[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    acc[q] = make_float2(0.f, 0.f);
-    ra[q] = ta + (threadIdx.x / TILE) + 8 * q;
-  }
-  const int beg = a.tile_ptr[tile], end = a.tile_ptr[tile + 1];
-  for (int b0 = beg; b0 < end; b0 += BATCH) {
-    const int nb = (end - b0) < BATCH ? (end - b0) : BATCH;
-    __syncthreads();
-    for (int e = threadIdx.x; e < nb; e += NT) {
-      const int m = a.tile_idx[b0 + e];
-      sb[e] = a.base[m];
-      for (int t = 0; t < 2 * W; ++t) sw[e][t] = a.wts[(int64_t)m * 2 * W + t];
-      sy[e] = y[(int64_t)j * a.M + m];
+// ys[s][j] = y[j][perm[s]] for j < J, 0 for J <= j < Jp
+__global__ __launch_bounds__(NT) void spread_stage_kernel(NufftArgs a, const float2* __restrict__ y, int Jp,
+                                                          float2* __restrict__ ys) {
+  __shared__ float2 t[STG][33];
+  const int64_t s0 = (int64_t)blockIdx.x * STG;
+  const int ls = threadIdx.x % STG, lj = threadIdx.x / STG;
+  const int64_t s = s0 + ls;
+  const int m = s < a.M ? a.s_perm[s] : 0;
+  for (int j0 = 0; j0 < Jp; j0 += 32) {
+    for (int jj = lj; jj < 32; jj += NT / STG) {
+      const int j = j0 + jj;
+      t[ls][jj] = (j < a.J && s < a.M) ? y[(int64_t)j * a.M + m] : make_float2(0.f, 0.f);
     }
     __syncthreads();
-    for (int e = 0; e < nb; ++e) {
-      const int2 b = sb[e];
-      int t1 = cb - b.y;
-      if (t1 < 0) t1 += a.g1;
-      if (t1 >= W) continue;
-      const float w1 = sw[e][W + t1];
-      const float2 yv = sy[e];
+    const int jj = threadIdx.x % 32;
+    for (int q = threadIdx.x / 32; q < STG; q += NT / 32) {
+      const int64_t sq = s0 + q;
+      if (sq < a.M && j0 + jj < Jp) ys[sq * Jp + j0 + jj] = t[q][jj];
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ float pick8(float4 lo, float4 hi, int t) {
+  float v = lo.x;
+  v = t == 1 ? lo.y : v;
+  v = t == 2 ? lo.z : v;
+  v = t == 3 ? lo.w : v;
+  v = t == 4 ? hi.x : v;
+  v = t == 5 ? hi.y : v;
+  v = t == 6 ? hi.z : v;
+  v = t == 7 ? hi.w : v;
+  return v;
+}
+
+// acc += sum over sorted samples s in [s, e) of w0[t0] w1[c - col] ys[s][jo .. jo + JG).  The
+// loads of U samples depend on s only and are all issued before any is used; the whole w1
+// record is loaded and the tap picked in registers (the empty asm keeps the compiler from
+// turning the pick back into a load that waits on col).
+template <int JG, int U>
+__device__ __forceinline__ void spread_range(const NufftArgs& a, const float2* __restrict__ ys, int Jp, int jo,
+                                             int c, int t0, int s, int e, float2 (&acc)[JG]) {
+  const float4* rec = reinterpret_cast<const float4*>(a.s_wts);
+  constexpr int YV = JG >= 2 ? JG / 2 : 1;
+  for (; s < e; s += U) {
+    int col[U];
+    float w0[U];
+    float4 w1l[U], w1h[U];
+    float4 yv[U][YV];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        int t0 = ra[q] - b.x;
-        if (t0 < 0) t0 += a.g0;
-        if (t0 < W) {
-          const float w = sw[e][t0] * w1;
-          acc[q].x += w * yv.x;
-          acc[q].y += w * yv.y;
+    for (int u = 0; u < U; ++u) {
+      const int su = min(s + u, e - 1);
+      col[u] = a.s_col[su];
+      w0[u] = a.s_wts[(int64_t)su * SREC + t0];
+      w1l[u] = rec[(int64_t)su * (SREC / 4) + 2];
+      w1h[u] = rec[(int64_t)su * (SREC / 4) + 3];
+      const float2* yr = ys + (int64_t)su * Jp + jo;
+      if constexpr (JG == 1) {
+        const float2 v = yr[0];
+        yv[u][0] = make_float4(v.x, v.y, 0.f, 0.f);
+      } else {
+#pragma unroll
+        for (int q = 0; q < YV; ++q) yv[u][q] = reinterpret_cast<const float4*>(yr)[q];
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      asm volatile("" : "+v"(w1l[u].x), "+v"(w1l[u].y), "+v"(w1l[u].z), "+v"(w1l[u].w));
+      asm volatile("" : "+v"(w1h[u].x), "+v"(w1h[u].y), "+v"(w1h[u].z), "+v"(w1h[u].w));
+      int t1 = c - col[u];
+      if (t1 < 0) t1 += a.g1;
+      const float w = (s + u < e ? w0[u] : 0.f) * pick8(w1l[u], w1h[u], t1);
+      if constexpr (JG == 1) {
+        acc[0].x += w * yv[u][0].x;
+        acc[0].y += w * yv[u][0].y;
+      } else {
+#pragma unroll
+        for (int q = 0; q < YV; ++q) {
+          acc[2 * q].x += w * yv[u][q].x;
+          acc[2 * q].y += w * yv[u][q].y;
+          acc[2 * q + 1].x += w * yv[u][q].z;
+          acc[2 * q + 1].y += w * yv[u][q].w;
         }
       }
     }
   }
-  const int64_t G = (int64_t)a.g0 * a.g1;
+}
+
+// One workgroup per (coil group, grid row, 64 columns): W waves, one per row window.
+template <int JG>
+__global__ __launch_bounds__(8 * SPC) void spread_kernel(NufftArgs a, const float2* __restrict__ ys, int Jp,
+                                                         float alpha, const float* __restrict__ scale_dev,
+                                                         float2* __restrict__ grid) {
+  __shared__ float2 part[8][JG][SPC];
+  const int bc = (a.g1 + SPC - 1) / SPC;
+  const int nblk = a.g0 * bc;
+  const int jg = blockIdx.x / nblk, blk = blockIdx.x % nblk;
+  const int r = blk / bc, c0 = (blk % bc) * SPC;
+  const int t0 = threadIdx.x / SPC, lane = threadIdx.x % SPC;
+  const int c = c0 + lane;
+  const int jo = jg * JG;
+  const int W = a.W;
+  float2 acc[JG];
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
-    if (ra[q] < a.g0 && cb < a.g1) grid[(int64_t)j * G + (int64_t)ra[q] * a.g1 + cb] = cscale(acc[q], s);
+  for (int q = 0; q < JG; ++q) acc[q] = make_float2(0.f, 0.f);
+  if (c < a.g1) {
+    int row = r - t0;
+    if (row < 0) row += a.g0;
+    const int32_t* cp = a.cell_ptr + (int64_t)row * a.g1;
+    const int lo = c - W + 1;
+    if (lo >= 0) {
+      spread_range<JG, 4>(a, ys, Jp, jo, c, t0, cp[lo], cp[c + 1], acc);
+    } else {
+      spread_range<JG, 4>(a, ys, Jp, jo, c, t0, cp[a.g1 + lo], cp[a.g1], acc);
+      spread_range<JG, 4>(a, ys, Jp, jo, c, t0, cp[0], cp[c + 1], acc);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < JG; ++q) part[t0][q][lane] = acc[q];
+  __syncthreads();
+  float sc = alpha * a.cscale;
+  if (scale_dev) sc *= *scale_dev;
+  const int64_t G = (int64_t)a.g0 * a.g1;
+  for (int o = threadIdx.x; o < JG * SPC; o += W * SPC) {
+    const int q = o / SPC, l = o % SPC;
+    if (c0 + l >= a.g1 || jo + q >= a.J) continue;
+    float2 v = part[0][q][l];
+    for (int t = 1; t < W; ++t) {
+      v.x += part[t][q][l].x;
+      v.y += part[t][q][l].y;
+    }
+    grid[(int64_t)(jo + q) * G + (int64_t)r * a.g1 + c0 + l] = cscale(v, sc);
+  }
 }
 
 inline unsigned grid_for(int64_t total) {
@@ -160,8 +251,12 @@ inline unsigned grid_for(int64_t total) {
 
 }  // namespace
 
-int nufft_tiles(int g0, int g1) { return ((g0 + TILE - 1) / TILE) * ((g1 + TILE - 1) / TILE); }
-int nufft_tile_edge() { return TILE; }
+int spread_group(int J) { return J >= 8 ? 8 : J > 2 ? 4 : J; }
+
+size_t spread_stage_bytes(int J, int64_t M) {
+  const int jg = spread_group(J);
+  return (size_t)M * (size_t)((J + jg - 1) / jg * jg) * sizeof(float2);
+}
 
 hipError_t pad_deapod_launch(const NufftArgs& a, const float2* S, const float2* x, float2* grid, hipStream_t st) {
   hipLaunchKernelGGL(pad_deapod_kernel, dim3(grid_for((int64_t)a.g0 * a.g1 * a.J)), dim3(NT), 0, st, a, S, x, grid);
@@ -179,10 +274,21 @@ hipError_t degrid_launch(const NufftArgs& a, const float2* grid, float2* y, hipS
   return hipGetLastError();
 }
 
-hipError_t spread_launch(const NufftArgs& a, const float2* y, float alpha, const float* scale_dev, float2* grid,
-                         hipStream_t st) {
-  const int nt = nufft_tiles(a.g0, a.g1);
-  hipLaunchKernelGGL(spread_kernel, dim3((unsigned)(nt * a.J)), dim3(NT), 0, st, a, y, alpha, scale_dev, grid);
+hipError_t spread_launch(const NufftArgs& a, const float2* y, float alpha, const float* scale_dev, float2* ys,
+                         float2* grid, hipStream_t st) {
+  const int jg = spread_group(a.J);
+  const int Jp = (a.J + jg - 1) / jg * jg;
+  if (a.W < 1 || a.W > 8) return hipErrorInvalidValue;
+  if (a.M > 0)
+    hipLaunchKernelGGL(spread_stage_kernel, dim3((unsigned)((a.M + STG - 1) / STG)), dim3(NT), 0, st, a, y, Jp, ys);
+  const unsigned nblk = (unsigned)((int64_t)a.g0 * ((a.g1 + SPC - 1) / SPC) * (Jp / jg));
+  const dim3 blk(SPC * a.W);
+  switch (jg) {
+    case 1: hipLaunchKernelGGL(spread_kernel<1>, dim3(nblk), blk, 0, st, a, ys, Jp, alpha, scale_dev, grid); break;
+    case 2: hipLaunchKernelGGL(spread_kernel<2>, dim3(nblk), blk, 0, st, a, ys, Jp, alpha, scale_dev, grid); break;
+    case 4: hipLaunchKernelGGL(spread_kernel<4>, dim3(nblk), blk, 0, st, a, ys, Jp, alpha, scale_dev, grid); break;
+    default: hipLaunchKernelGGL(spread_kernel<8>, dim3(nblk), blk, 0, st, a, ys, Jp, alpha, scale_dev, grid); break;
+  }
   return hipGetLastError();
 }
 

@@ -63,15 +63,17 @@ struct Plan {
   float* d_iphi = nullptr;       // [n0 + n1] inverse deapodisation per axis
   int2* d_base = nullptr;        // [M] first tap per axis (wrapped grid index)
   float* d_wts = nullptr;        // [M][2][W] tap weights
-  int32_t* d_tptr = nullptr;     // spread tiles (CSR)
-  int32_t* d_tidx = nullptr;
+  int32_t* d_cptr = nullptr;     // [g0 g1 + 1] samples sorted by first-tap cell (CSR)
+  int32_t* d_sperm = nullptr;    // [M] original index of each sorted sample
+  int32_t* d_scol = nullptr;     // [M] first-tap column of each sorted sample
+  float* d_swts = nullptr;       // [M][16] tap weights in sorted order (axis 1 from slot 8)
   float2* d_twg[2] = {nullptr, nullptr};  // grid twiddles
   int nradg[2] = {0, 0};
   int radixg[2][12];
   // workspace layout (byte offsets into the caller's workspace)
   size_t ws_bytes = 0;
   size_t off_S = 0, off_K = 0, off_tA = 0, off_tB = 0, off_E = 0, off_gemm = 0, off_part = 0;
-  size_t off_T1 = 0, off_T3 = 0, off_xt = 0, off_Z = 0, off_gxp = 0, off_T3b = 0, off_T1b = 0, off_G = 0, off_cpart = 0;
+  size_t off_T1 = 0, off_T3 = 0, off_xt = 0, off_Z = 0, off_gxp = 0, off_T3b = 0, off_T1b = 0, off_G = 0, off_Ys = 0, off_cpart = 0;
   int part_blocks = 0;
 
   size_t bytes_x() const { return (size_t)N * 8; }

@@ -190,7 +190,7 @@ NufftArgs nufft_args(const Plan& p) {
   a.J = p.J; a.W = p.W; a.M = p.M;
   a.iphi0 = p.d_iphi; a.iphi1 = p.d_iphi + p.n[0];
   a.base = p.d_base; a.wts = p.d_wts;
-  a.tile_ptr = p.d_tptr; a.tile_idx = p.d_tidx;
+  a.cell_ptr = p.d_cptr; a.s_perm = p.d_sperm; a.s_col = p.d_scol; a.s_wts = p.d_swts;
   a.cscale = p.kscale;
   return a;
 }
@@ -294,8 +294,8 @@ LineArgs line_args(const Plan& p) {
 }  // namespace
 
 // Kaiser-Bessel NUFFT tables (host, FP64): oversampled grid, twiddles, inverse
-// deapodisation per axis, per-sample first tap and weights, and the spread-tile
-// sample lists.  Kernel phi(t) = I0(beta sqrt(1 - (2t/W)^2)) / W on |t| <= W/2,
+// deapodisation per axis, per-sample first tap and weights, and the samples
+// sorted by first-tap cell for the spread.  Kernel phi(t) = I0(beta sqrt(1 - (2t/W)^2)) / W on |t| <= W/2,
 // its Fourier transform Phi(nu) = sinh(sqrt(beta^2 - (pi W nu)^2)) / sqrt(...)
 // (sin form when the radicand is negative); beta defaults to Beatty, Nishimura
 // and Pauly: pi sqrt((W/sigma)^2 (sigma - 1/2)^2 - 0.8).
@@ -340,9 +340,7 @@ static maxwell_status nufft_build(Plan& p, const maxwell_plan_desc& d) {
   const int64_t M = p.M;
   std::vector<int2> base(M);
   std::vector<float> wts((size_t)M * 2 * W);
-  const int TE = nufft_tile_edge();
-  const int tiles0 = (p.g[0] + TE - 1) / TE, tiles1 = (p.g[1] + TE - 1) / TE;
-  std::vector<std::vector<int32_t>> lists((size_t)tiles0 * tiles1);
+  std::vector<int32_t> cell((size_t)M);
   for (int64_t m = 0; m < M; ++m) {
     int b[2];
     for (int ax = 0; ax < 2; ++ax) {
@@ -353,26 +351,26 @@ static maxwell_status nufft_build(Plan& p, const maxwell_plan_desc& d) {
       b[ax] = (int)((((int64_t)g0 + G / 2) % G + G) % G);
     }
     base[m] = make_int2(b[0], b[1]);
-    // tiles met by the W x W footprint (periodic)
-    int tr[8], tc[8], nr = 0, nc = 0;
-    for (int t = 0; t < W; ++t) {
-      const int r = ((b[0] + t) % p.g[0]) / TE, c = ((b[1] + t) % p.g[1]) / TE;
-      bool seen = false;
-      for (int q = 0; q < nr; ++q) seen |= tr[q] == r;
-      if (!seen) tr[nr++] = r;
-      seen = false;
-      for (int q = 0; q < nc; ++q) seen |= tc[q] == c;
-      if (!seen) tc[nc++] = c;
+    cell[m] = b[0] * p.g[1] + b[1];
+  }
+  // counting sort of the samples by first-tap cell (stable: equal cells keep sample order)
+  const size_t ncell = (size_t)p.g[0] * p.g[1];
+  std::vector<int32_t> cptr(ncell + 1, 0), sperm((size_t)M), scol((size_t)M);
+  std::vector<float> swts((size_t)M * 16, 0.f);  // per sorted sample: w0 in [0, 8), w1 in [8, 16)
+  for (int64_t m = 0; m < M; ++m) ++cptr[(size_t)cell[m] + 1];
+  for (size_t q = 0; q < ncell; ++q) cptr[q + 1] += cptr[q];
+  {
+    std::vector<int32_t> fill(cptr.begin(), cptr.end() - 1);
+    for (int64_t m = 0; m < M; ++m) {
+      const int32_t s = fill[cell[m]]++;
+      sperm[s] = (int32_t)m;
+      scol[s] = base[m].y;
+      for (int t = 0; t < W; ++t) {
+        swts[(size_t)s * 16 + t] = wts[(size_t)m * 2 * W + t];
+        swts[(size_t)s * 16 + 8 + t] = wts[(size_t)m * 2 * W + W + t];
+      }
     }
-    for (int i = 0; i < nr; ++i)
-      for (int k = 0; k < nc; ++k) lists[(size_t)tr[i] * tiles1 + tc[k]].push_back((int32_t)m);
   }
-  std::vector<int32_t> tptr(lists.size() + 1, 0), tidx;
-  for (size_t t = 0; t < lists.size(); ++t) {
-    tptr[t + 1] = tptr[t] + (int32_t)lists[t].size();
-    tidx.insert(tidx.end(), lists[t].begin(), lists[t].end());
-  }
-  if (tidx.empty()) tidx.push_back(0);
   auto up = [&](void** dst, const void* src, size_t bytes) -> hipError_t {
     hipError_t r = hipMalloc(dst, bytes ? bytes : 8);
     if (r != hipSuccess || !bytes) return r;
@@ -381,8 +379,10 @@ static maxwell_status nufft_build(Plan& p, const maxwell_plan_desc& d) {
   if ((e = up((void**)&p.d_iphi, iphi.data(), iphi.size() * sizeof(float))) != hipSuccess) return hip_err(e);
   if ((e = up((void**)&p.d_base, base.data(), base.size() * sizeof(int2))) != hipSuccess) return hip_err(e);
   if ((e = up((void**)&p.d_wts, wts.data(), wts.size() * sizeof(float))) != hipSuccess) return hip_err(e);
-  if ((e = up((void**)&p.d_tptr, tptr.data(), tptr.size() * sizeof(int32_t))) != hipSuccess) return hip_err(e);
-  if ((e = up((void**)&p.d_tidx, tidx.data(), tidx.size() * sizeof(int32_t))) != hipSuccess) return hip_err(e);
+  if ((e = up((void**)&p.d_cptr, cptr.data(), cptr.size() * sizeof(int32_t))) != hipSuccess) return hip_err(e);
+  if ((e = up((void**)&p.d_sperm, sperm.data(), sperm.size() * sizeof(int32_t))) != hipSuccess) return hip_err(e);
+  if ((e = up((void**)&p.d_scol, scol.data(), scol.size() * sizeof(int32_t))) != hipSuccess) return hip_err(e);
+  if ((e = up((void**)&p.d_swts, swts.data(), swts.size() * sizeof(float))) != hipSuccess) return hip_err(e);
   return MAXWELL_OK;
 }
 
@@ -576,6 +576,8 @@ maxwell_status plan_build(Plan& p, const maxwell_plan_desc& d, const maxwell_bas
   if (p.sampling == MAXWELL_NONCARTESIAN) {
     p.off_G = off;
     off += al((size_t)p.J * p.g[0] * p.g[1] * 8);
+    p.off_Ys = off;
+    off += al(spread_stage_bytes(p.J, p.M));
   }
   if (p.core_direct) {
     p.off_cpart = off;
@@ -598,13 +600,17 @@ void plan_release(Plan& p) {
   if (p.d_iphi) (void)hipFree(p.d_iphi);
   if (p.d_base) (void)hipFree(p.d_base);
   if (p.d_wts) (void)hipFree(p.d_wts);
-  if (p.d_tptr) (void)hipFree(p.d_tptr);
-  if (p.d_tidx) (void)hipFree(p.d_tidx);
+  if (p.d_cptr) (void)hipFree(p.d_cptr);
+  if (p.d_sperm) (void)hipFree(p.d_sperm);
+  if (p.d_scol) (void)hipFree(p.d_scol);
+  if (p.d_swts) (void)hipFree(p.d_swts);
   p.d_iphi = nullptr;
   p.d_base = nullptr;
   p.d_wts = nullptr;
-  p.d_tptr = nullptr;
-  p.d_tidx = nullptr;
+  p.d_cptr = nullptr;
+  p.d_sperm = nullptr;
+  p.d_scol = nullptr;
+  p.d_swts = nullptr;
   for (auto e : p.timing.ev_start) (void)hipEventDestroy(e);
   for (auto e : p.timing.ev_stop) (void)hipEventDestroy(e);
   p.timing = Timing();
@@ -834,7 +840,7 @@ hipError_t run_adjoint(const Plan& p, const float2* x, const float2* c, const fl
   if (p.sampling == MAXWELL_NONCARTESIAN) {
     const NufftArgs na = nufft_args(p);
     float2* G = wsp<float2>(ws, p.off_G);
-    if ((e = TIMED("nufft_spread", spread_launch(na, y, alpha, scale_dev, G, st))) != hipSuccess) return e;
+    if ((e = TIMED("nufft_spread", spread_launch(na, y, alpha, scale_dev, wsp<float2>(ws, p.off_Ys), G, st))) != hipSuccess) return e;
     if ((e = fft_grid(p, G, +1, st)) != hipSuccess) return e;
     if ((e = TIMED("nufft_crop", crop_deapod_launch(na, G, Kb, st))) != hipSuccess) return e;
     alpha = 1.0f;  // the scale was applied by the spread
