@@ -22,7 +22,8 @@ namespace mx {
 namespace {
 
 constexpr int NT = 256;
-constexpr int TILE = 8192;          // complex elements per LDS tile at most (before padding)
+constexpr int TILE = 4096;          // complex elements per LDS tile at most (before padding):
+                                    // with the twiddles, about 40 KB, four workgroups per CU
 constexpr int TW_LDS_MAX = 1024;    // twiddle tables up to this length are staged in LDS
 
 // complex elements of the LDS tile for T lines of length n
@@ -59,37 +60,74 @@ __global__ __launch_bounds__(NT) void fft_axis_kernel(FftAxisArgs a) {
     Tvalid = (int)((a.inner - t0) < tg.T ? (a.inner - t0) : tg.T);
   }
   const int total = tg.T * n;
-  // ---- load (with optional image premultiply and the input chessboard sign)
-  for (int e = threadIdx.x; e < total; e += NT) {
-    int l, i;
-    if (a.inner == 1) { l = e / n; i = e % n; } else { i = e / tg.T; l = e % tg.T; }
-    float2 v = make_float2(0.f, 0.f);
-    if (l < Tvalid) {
-      int64_t gidx, o, t;
-      if (a.inner == 1) { o = o0 + l; t = 0; } else { o = o0; t = t0 + l; }
-      gidx = (o * a.n + i) * a.inner + t;
-      v = a.src[gidx];
+  // element e of the tile: (line, index) = (e / n, e % n) for contiguous lines, else
+  // (e % T, e / T), so that consecutive threads touch consecutive addresses
+  const FastDiv fd = fast_div((uint32_t)(a.inner == 1 ? n : tg.T));
+  // ---- load (with optional image premultiply and the input chessboard sign); LU
+  // elements per thread are loaded before any is stored, so their latencies overlap
+  // (an element past the tile reads the tile's first element and is masked to zero)
+  constexpr int LU = 8;
+  const int64_t gbase = a.inner == 1 ? o0 * a.n * a.inner : o0 * a.n * a.inner + t0;
+  for (int e0 = threadIdx.x; e0 < total; e0 += NT * LU) {
+    float2 v[LU], pm[LU];
+    uint32_t keep[LU];
+    int li[LU];
+#pragma unroll
+    for (int u = 0; u < LU; ++u) {
+      const int e = e0 + u * NT;
+      const int ec = e < total ? e : 0;
+      const int qd = (int)fdiv(ec, fd), rm = ec - qd * (int)fd.d;
+      const int l = a.inner == 1 ? qd : rm, i = a.inner == 1 ? rm : qd;
+      const bool ok = e < total && l < Tvalid;
+      keep[u] = ok ? ((i & 1) ? 0xffffffffu : 0x7fffffffu) : 0u;  // sign bit kept only for odd i
+      li[u] = e < total ? l * tg.LS + i * tg.ES : -1;
+      const int64_t gidx = ok ? gbase + (int64_t)l * (a.inner == 1 ? a.n : 1) + (int64_t)i * a.inner : gbase;
+      v[u] = a.src[gidx];
       if (a.premul) {
-        const int64_t img = ((o % a.outer_per_coil) * a.n + i) * a.inner + t;
-        v = cmul(v, a.premul[img]);
+        const int64_t o = a.inner == 1 ? o0 + (ok ? l : 0) : o0;
+        const int64_t oc = a.outer < 0x7fffffffLL ? (int64_t)((uint32_t)o % (uint32_t)a.outer_per_coil)
+                                                  : o % a.outer_per_coil;
+        const int64_t t = a.inner == 1 ? 0 : t0 + (ok ? l : 0);
+        pm[u] = a.premul[(oc * a.n + (ok ? i : 0)) * a.inner + t];
       }
-      if (i & 1) v = make_float2(-v.x, -v.y);
     }
-    lds[l * tg.LS + i * tg.ES] = v;
+#pragma unroll
+    for (int u = 0; u < LU; ++u) {
+      if (li[u] < 0) continue;
+      float2 x = v[u];
+      if (a.premul) x = cmul(x, pm[u]);
+      // odd i: negate (flip the sign bit); invalid: zero (clear every bit)
+      const uint32_t flip = keep[u] == 0xffffffffu ? 0x80000000u : 0u;
+      const uint32_t mask = keep[u] ? 0xffffffffu : 0u;
+      x.x = __uint_as_float((__float_as_uint(x.x) ^ flip) & mask);
+      x.y = __uint_as_float((__float_as_uint(x.y) ^ flip) & mask);
+      lds[li[u]] = x;
+    }
   }
   __syncthreads();
   lds_fft_lines<NT, TILE>(lds, tg, n, a.radix, a.nrad, tw, a.dir);
   // ---- store with the output chessboard sign, global sign and n^{-1/2}
   const float scale = (((n / 2) & 1) ? -1.f : 1.f) * rsqrtf((float)n);
-  for (int e = threadIdx.x; e < total; e += NT) {
-    int l, i;
-    if (a.inner == 1) { l = e / n; i = e % n; } else { i = e / tg.T; l = e % tg.T; }
-    if (l >= Tvalid) continue;
-    int64_t o, t;
-    if (a.inner == 1) { o = o0 + l; t = 0; } else { o = o0; t = t0 + l; }
-    float2 v = lds[l * tg.LS + i * tg.ES];
-    const float s = (i & 1) ? -scale : scale;
-    a.data[(o * a.n + i) * a.inner + t] = cscale(v, s);
+  for (int e0 = threadIdx.x; e0 < total; e0 += NT * LU) {
+    float2 v[LU];
+#pragma unroll
+    for (int u = 0; u < LU; ++u) {
+      const int e = e0 + u * NT;
+      const int ec = e < total ? e : 0;
+      const int qd = (int)fdiv(ec, fd), rm = ec - qd * (int)fd.d;
+      const int l = a.inner == 1 ? qd : rm, i = a.inner == 1 ? rm : qd;
+      v[u] = lds[l * tg.LS + i * tg.ES];
+    }
+#pragma unroll
+    for (int u = 0; u < LU; ++u) {
+      const int e = e0 + u * NT;
+      const int ec = e < total ? e : 0;
+      const int qd = (int)fdiv(ec, fd), rm = ec - qd * (int)fd.d;
+      const int l = a.inner == 1 ? qd : rm, i = a.inner == 1 ? rm : qd;
+      if (e >= total || l >= Tvalid) continue;
+      const float s = (i & 1) ? -scale : scale;
+      a.data[gbase + (int64_t)l * (a.inner == 1 ? a.n : 1) + (int64_t)i * a.inner] = cscale(v[u], s);
+    }
   }
 }
 
@@ -113,14 +151,15 @@ int fft_factorise(int64_t n, int* radix) {
 }
 
 // Lines per workgroup: enough workgroups to spread a small transform over the whole
-// chip (about 1024), at most 64 lines or TILE elements per tile, and for strided lines
-// at least 8 adjacent ones (64-byte runs per load).
+// chip (about 1024), at most 64 lines or TILE elements per tile (small tiles keep
+// several workgroups resident per CU), and for strided lines at least 8 adjacent ones
+// (64-byte runs per load) where the tile allows.
 hipError_t fft_axis_launch(const FftAxisArgs& args, hipStream_t st) {
   FftAxisArgs a = args;
   const int n = (int)a.n;
   const bool contiguous = a.inner == 1;
   const bool twl = n <= TW_LDS_MAX;
-  int Tmax = (TILE - (twl ? n : 0)) / (contiguous ? n + 1 : n);
+  int Tmax = TILE / n;
   if (Tmax > 64) Tmax = 64;
   if (Tmax < 1) Tmax = 1;
   const int64_t lines = a.outer * a.inner;

@@ -122,6 +122,22 @@ __device__ __forceinline__ void dft_small<5>(float2 (&v)[5], int dir) {
   v[3] = csub(t2, ru2);
 }
 
+// Division of x < 2^31 by a divisor 1 <= d < 2^20 known only at run time, as a
+// multiply-high, an add and a shift (Granlund and Montgomery, "Division by invariant
+// integers using multiplication", 1994): with l = ceil(log2 d) and
+// m = floor(2^32 (2^l - d) / d) + 1, x / d = (umulhi(x, m) + x) >> l.  The quotient
+// for m is taken in FP64, exact here: the numerator is below 2^53 and a fractional
+// part, at least 1/d, stays clear of the rounding error.
+struct FastDiv {
+  uint32_t d, m, l;
+};
+__host__ __device__ inline FastDiv fast_div(uint32_t d) {
+  const uint32_t l = d > 1 ? 32u - (uint32_t)__builtin_clz(d - 1) : 0u;
+  const double q = 4294967296.0 * (double)((1ull << l) - d) / (double)d;
+  return {d, (uint32_t)q + 1u, l};
+}
+__device__ __forceinline__ uint32_t fdiv(uint32_t x, const FastDiv& f) { return (__umulhi(x, f.m) + x) >> f.l; }
+
 // Line geometry of a tile held in LDS: element i of line l sits at l*LS + i*ES.
 struct LdsLines {
   int T;       // number of lines
@@ -133,9 +149,10 @@ struct LdsLines {
 // ceil(CHUNK / (R NTHREADS)) butterflies in registers between the two barriers.
 // Consecutive threads take consecutive lines.
 template <int R, int NTHREADS, int CHUNK>
-__device__ __forceinline__ void stockham_pass(float2* lds, const LdsLines& tg, int l0, int Tc, int n, int Ns,
-                                     const float2* __restrict__ tw, int dir) {
+__device__ __forceinline__ void stockham_pass(float2* lds, const LdsLines& tg, int l0, const FastDiv& fTc, int n,
+                                              const FastDiv& fNs, const float2* __restrict__ tw, int dir) {
   constexpr int MAXQ = (CHUNK / R + NTHREADS - 1) / NTHREADS;
+  const int Tc = (int)fTc.d, Ns = (int)fNs.d;
   const int nR = n / R;
   const int nb = Tc * nR;
   const int stride_tw = n / (Ns * R);
@@ -144,11 +161,12 @@ __device__ __forceinline__ void stockham_pass(float2* lds, const LdsLines& tg, i
   for (int q = 0; q < MAXQ; ++q) {
     const int bf = threadIdx.x + q * NTHREADS;
     if (bf < nb) {
-      const int l = l0 + bf % Tc, j = bf / Tc;
+      const int j = (int)fdiv(bf, fTc);
+      const int l = l0 + bf - j * Tc;
       const int base = l * tg.LS;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[q][r] = lds[base + (j + r * nR) * tg.ES];
-      const int k = j % Ns;
+      const int k = j - (int)fdiv(j, fNs) * Ns;
 #pragma unroll
       for (int r = 1; r < R; ++r) {
         float2 w = tw[k * r * stride_tw];
@@ -163,9 +181,11 @@ __device__ __forceinline__ void stockham_pass(float2* lds, const LdsLines& tg, i
   for (int q = 0; q < MAXQ; ++q) {
     const int bf = threadIdx.x + q * NTHREADS;
     if (bf < nb) {
-      const int l = l0 + bf % Tc, j = bf / Tc;
+      const int j = (int)fdiv(bf, fTc);
+      const int l = l0 + bf - j * Tc;
       const int base = l * tg.LS;
-      const int idxD = (j / Ns) * Ns * R + (j % Ns);
+      const int jq = (int)fdiv(j, fNs);
+      const int idxD = jq * Ns * R + (j - jq * Ns);
 #pragma unroll
       for (int r = 0; r < R; ++r) lds[base + (idxD + r * Ns) * tg.ES] = v[q][r];
     }
@@ -183,17 +203,21 @@ __device__ __forceinline__ void lds_fft_lines(float2* lds, const LdsLines& tg, i
   int Tc = CHUNK / n;
   if (Tc < 1) Tc = 1;
   if (Tc > tg.T) Tc = tg.T;
+  const FastDiv fTc = fast_div((uint32_t)Tc);
+  const int tail = tg.T % Tc;
+  const FastDiv fTail = fast_div((uint32_t)(tail ? tail : 1));
   int Ns = 1;
   for (int p = 0; p < nrad; ++p) {
     const int R = radix[p];
+    const FastDiv fNs = fast_div((uint32_t)Ns);
     for (int l0 = 0; l0 < tg.T; l0 += Tc) {
-      const int tc = (tg.T - l0) < Tc ? (tg.T - l0) : Tc;
+      const FastDiv& ft = (tg.T - l0) < Tc ? fTail : fTc;
       switch (R) {
-        case 8: stockham_pass<8, NTHREADS, CHUNK>(lds, tg, l0, tc, n, Ns, tw, dir); break;
-        case 4: stockham_pass<4, NTHREADS, CHUNK>(lds, tg, l0, tc, n, Ns, tw, dir); break;
-        case 2: stockham_pass<2, NTHREADS, CHUNK>(lds, tg, l0, tc, n, Ns, tw, dir); break;
-        case 3: stockham_pass<3, NTHREADS, CHUNK>(lds, tg, l0, tc, n, Ns, tw, dir); break;
-        default: stockham_pass<5, NTHREADS, CHUNK>(lds, tg, l0, tc, n, Ns, tw, dir); break;
+        case 8: stockham_pass<8, NTHREADS, CHUNK>(lds, tg, l0, ft, n, fNs, tw, dir); break;
+        case 4: stockham_pass<4, NTHREADS, CHUNK>(lds, tg, l0, ft, n, fNs, tw, dir); break;
+        case 2: stockham_pass<2, NTHREADS, CHUNK>(lds, tg, l0, ft, n, fNs, tw, dir); break;
+        case 3: stockham_pass<3, NTHREADS, CHUNK>(lds, tg, l0, ft, n, fNs, tw, dir); break;
+        default: stockham_pass<5, NTHREADS, CHUNK>(lds, tg, l0, ft, n, fNs, tw, dir); break;
       }
     }
     Ns *= R;

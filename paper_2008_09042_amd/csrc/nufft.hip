@@ -60,25 +60,31 @@ __global__ void crop_deapod_kernel(NufftArgs a, const float2* __restrict__ grid,
 }
 
 // y[j][m] = c * sum_{t0, t1} w0[m][t0] w1[m][t1] Grid[j][(b0 + t0) mod g0][(b1 + t1) mod g1]
-__global__ void degrid_kernel(NufftArgs a, const float2* __restrict__ grid, float2* __restrict__ y) {
+// The width is a template argument so the W x W taps unroll and their loads are all in
+// flight together.
+template <int W>
+__global__ __launch_bounds__(NT) void degrid_kernel(NufftArgs a, const float2* __restrict__ grid,
+                                                    float2* __restrict__ y) {
   const int64_t G = (int64_t)a.g0 * a.g1;
   const int64_t total = a.M * a.J;
-  const int W = a.W;
   for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
     const int64_t j = e / a.M, m = e % a.M;
     const int2 b = a.base[m];
     const float* w0 = a.wts + m * 2 * W;
     const float* w1 = w0 + W;
     const float2* gj = grid + j * G;
+    int col[W];
+#pragma unroll
+    for (int t1 = 0; t1 < W; ++t1) col[t1] = b.y + t1 < a.g1 ? b.y + t1 : b.y + t1 - a.g1;
     float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
     for (int t0 = 0; t0 < W; ++t0) {
-      int ga = b.x + t0;
-      if (ga >= a.g0) ga -= a.g0;
+      const int ga = b.x + t0 < a.g0 ? b.x + t0 : b.x + t0 - a.g0;
+      const float2* gr = gj + (int64_t)ga * a.g1;
       float2 row = make_float2(0.f, 0.f);
+#pragma unroll
       for (int t1 = 0; t1 < W; ++t1) {
-        int gb = b.y + t1;
-        if (gb >= a.g1) gb -= a.g1;
-        const float2 gv = gj[(int64_t)ga * a.g1 + gb];
+        const float2 gv = gr[col[t1]];
         row.x += w1[t1] * gv.x;
         row.y += w1[t1] * gv.y;
       }
@@ -218,10 +224,10 @@ __global__ __launch_bounds__(8 * SPC) void spread_kernel(NufftArgs a, const floa
     const int32_t* cp = a.cell_ptr + (int64_t)row * a.g1;
     const int lo = c - W + 1;
     if (lo >= 0) {
-      spread_range<JG, 4>(a, ys, Jp, jo, c, t0, cp[lo], cp[c + 1], acc);
+      spread_range<JG, 2>(a, ys, Jp, jo, c, t0, cp[lo], cp[c + 1], acc);
     } else {
-      spread_range<JG, 4>(a, ys, Jp, jo, c, t0, cp[a.g1 + lo], cp[a.g1], acc);
-      spread_range<JG, 4>(a, ys, Jp, jo, c, t0, cp[0], cp[c + 1], acc);
+      spread_range<JG, 2>(a, ys, Jp, jo, c, t0, cp[a.g1 + lo], cp[a.g1], acc);
+      spread_range<JG, 2>(a, ys, Jp, jo, c, t0, cp[0], cp[c + 1], acc);
     }
   }
 #pragma unroll
@@ -270,7 +276,17 @@ hipError_t crop_deapod_launch(const NufftArgs& a, const float2* grid, float2* ou
 
 hipError_t degrid_launch(const NufftArgs& a, const float2* grid, float2* y, hipStream_t st) {
   if (a.M * a.J == 0) return hipSuccess;
-  hipLaunchKernelGGL(degrid_kernel, dim3(grid_for(a.M * a.J)), dim3(NT), 0, st, a, grid, y);
+  const dim3 gr(grid_for(a.M * a.J));
+  switch (a.W) {
+    case 2: hipLaunchKernelGGL(degrid_kernel<2>, gr, dim3(NT), 0, st, a, grid, y); break;
+    case 3: hipLaunchKernelGGL(degrid_kernel<3>, gr, dim3(NT), 0, st, a, grid, y); break;
+    case 4: hipLaunchKernelGGL(degrid_kernel<4>, gr, dim3(NT), 0, st, a, grid, y); break;
+    case 5: hipLaunchKernelGGL(degrid_kernel<5>, gr, dim3(NT), 0, st, a, grid, y); break;
+    case 6: hipLaunchKernelGGL(degrid_kernel<6>, gr, dim3(NT), 0, st, a, grid, y); break;
+    case 7: hipLaunchKernelGGL(degrid_kernel<7>, gr, dim3(NT), 0, st, a, grid, y); break;
+    case 8: hipLaunchKernelGGL(degrid_kernel<8>, gr, dim3(NT), 0, st, a, grid, y); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
