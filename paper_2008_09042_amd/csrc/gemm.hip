@@ -58,35 +58,33 @@ __device__ inline void tile_coords(const GemmArgs& g, int splits, int64_t kchunk
   t.B = g.B + b * g.b_bs;
 }
 
-template <int BK>
-__device__ inline void load_a(const GemmArgs& g, const TileCtx& t, int64_t k0, float (*AR)[BM + PAD],
-                              float (*AI)[BM + PAD]) {
-  const bool kfast = (g.a_ks == 1);
-  for (int e = threadIdx.x; e < BM * BK; e += NT) {
-    int mi, ki;
-    if (kfast) { mi = e / BK; ki = e % BK; } else { ki = e / BM; mi = e % BM; }
-    const int64_t m = t.m0 + mi, k = k0 + ki;
-    float2 v = make_float2(0.f, 0.f);
-    if (m < g.M && k < t.kend) v = t.A[m * g.a_ms + k * g.a_ks];
-    AR[ki][mi] = v.x;
-    AI[ki][mi] = g.conjA ? -v.y : v.y;
+// One operand stage held in registers between its global load and its LDS store, so the
+// loads of the next stage are in flight while the current one is multiplied.  Element e of
+// a ROWS x BK stage walks the operand's unit-stride dimension (k when ks == 1, else the
+// row); an element outside the operand reads the operand's first element and is zeroed.
+template <int ROWS, int BK>
+struct Stage {
+  static constexpr int CNT = ROWS * BK / NT;
+  float2 v[CNT];
+  __device__ static void coords(int u, bool kfast, int& ri, int& ki) {
+    const int e = threadIdx.x + u * NT;
+    if (kfast) { ri = e / BK; ki = e % BK; } else { ki = e / ROWS; ri = e % ROWS; }
   }
-}
-
-template <int BK>
-__device__ inline void load_b(const GemmArgs& g, const TileCtx& t, int64_t k0, float (*BR)[BN + PAD],
-                              float (*BI)[BN + PAD]) {
-  const bool nfast = (g.b_ns == 1);
-  for (int e = threadIdx.x; e < BK * BN; e += NT) {
-    int ki, ni;
-    if (nfast) { ki = e / BN; ni = e % BN; } else { ni = e / BK; ki = e % BK; }
-    const int64_t n = t.n0 + ni, k = k0 + ki;
-    float2 v = make_float2(0.f, 0.f);
-    if (n < g.N && k < t.kend) v = t.B[k * g.b_ks + n * g.b_ns];
-    BR[ki][ni] = v.x;
-    BI[ki][ni] = g.conjB ? -v.y : v.y;
+  __device__ void fetch(const float2* P, int64_t r0, int64_t rows, int64_t rs, int64_t ks, int64_t k0,
+                        int64_t kend) {
+    const bool kfast = ks == 1;
+#pragma unroll
+    for (int u = 0; u < CNT; ++u) {
+      int ri, ki;
+      coords(u, kfast, ri, ki);
+      const int64_t r = r0 + ri, k = k0 + ki;
+      const bool ok = r < rows && k < kend;
+      const float2 x = P[ok ? r * rs + k * ks : 0];
+      const uint32_t m = ok ? 0xffffffffu : 0u;
+      v[u] = make_float2(__uint_as_float(__float_as_uint(x.x) & m), __uint_as_float(__float_as_uint(x.y) & m));
+    }
   }
-}
+};
 
 __device__ inline void store_tile(const GemmArgs& g, const TileCtx& t, int64_t b, int sp, int splits,
                                   float2* partial, f32x4 (&accR)[2][2], f32x4 (&accI)[2][2]) {
@@ -125,10 +123,33 @@ __global__ __launch_bounds__(NT) void cgemm_f32_kernel(GemmArgs g, int splits, i
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) { accR[i][j] = f32x4{0, 0, 0, 0}; accI[i][j] = f32x4{0, 0, 0, 0}; }
 
+  Stage<BM, BK32> sa;
+  Stage<BN, BK32> sb;
+  const bool akf = g.a_ks == 1, bkf = g.b_ks == 1;
+  if (t.kbeg < t.kend) {
+    sa.fetch(t.A, t.m0, g.M, g.a_ms, g.a_ks, t.kbeg, t.kend);
+    sb.fetch(t.B, t.n0, g.N, g.b_ns, g.b_ks, t.kbeg, t.kend);
+  }
   for (int64_t k0 = t.kbeg; k0 < t.kend; k0 += BK32) {
-    load_a<BK32>(g, t, k0, AR, AI);
-    load_b<BK32>(g, t, k0, BR, BI);
+#pragma unroll
+    for (int u = 0; u < Stage<BM, BK32>::CNT; ++u) {
+      int mi, ki;
+      Stage<BM, BK32>::coords(u, akf, mi, ki);
+      AR[ki][mi] = sa.v[u].x;
+      AI[ki][mi] = g.conjA ? -sa.v[u].y : sa.v[u].y;
+    }
+#pragma unroll
+    for (int u = 0; u < Stage<BN, BK32>::CNT; ++u) {
+      int ni, ki;
+      Stage<BN, BK32>::coords(u, bkf, ni, ki);
+      BR[ki][ni] = sb.v[u].x;
+      BI[ki][ni] = g.conjB ? -sb.v[u].y : sb.v[u].y;
+    }
     __syncthreads();
+    if (k0 + BK32 < t.kend) {
+      sa.fetch(t.A, t.m0, g.M, g.a_ms, g.a_ks, k0 + BK32, t.kend);
+      sb.fetch(t.B, t.n0, g.N, g.b_ns, g.b_ks, k0 + BK32, t.kend);
+    }
 #pragma unroll
     for (int kk = 0; kk < BK32; kk += 4) {
       const int kr = kk + (lane >> 4), c = lane & 15;
@@ -186,30 +207,38 @@ __global__ __launch_bounds__(NT) void cgemm_bf16s_kernel(GemmArgs g, int splits,
     for (int j = 0; j < 2; ++j) { accR[i][j] = f32x4{0, 0, 0, 0}; accI[i][j] = f32x4{0, 0, 0, 0}; }
 
   const bool akfast = (g.a_ks == 1), bkfast = (g.b_ks == 1);
+  Stage<BM, BKS> sa;
+  Stage<BN, BKS> sb;
+  if (t.kbeg < t.kend) {
+    sa.fetch(t.A, t.m0, g.M, g.a_ms, g.a_ks, t.kbeg, t.kend);
+    sb.fetch(t.B, t.n0, g.N, g.b_ns, g.b_ks, t.kbeg, t.kend);
+  }
   for (int64_t k0 = t.kbeg; k0 < t.kend; k0 += BKS) {
-    for (int e = threadIdx.x; e < BM * BKS; e += NT) {
+#pragma unroll
+    for (int u = 0; u < Stage<BM, BKS>::CNT; ++u) {
       int mi, ki;
-      if (akfast) { mi = e / BKS; ki = e % BKS; } else { ki = e / BM; mi = e % BM; }
-      const int64_t m = t.m0 + mi, k = k0 + ki;
-      float2 v = make_float2(0.f, 0.f);
-      if (m < g.M && k < t.kend) v = t.A[m * g.a_ms + k * g.a_ks];
+      Stage<BM, BKS>::coords(u, akfast, mi, ki);
+      float2 v = sa.v[u];
       if (g.conjA) v.y = -v.y;
       uint16_t h, l;
       split_pair(v.x, h, l); As[0][mi][ki] = h; As[1][mi][ki] = l;
       split_pair(v.y, h, l); As[2][mi][ki] = h; As[3][mi][ki] = l;
     }
-    for (int e = threadIdx.x; e < BKS * BN; e += NT) {
-      int ki, ni;
-      if (bkfast) { ni = e / BKS; ki = e % BKS; } else { ki = e / BN; ni = e % BN; }
-      const int64_t n = t.n0 + ni, k = k0 + ki;
-      float2 v = make_float2(0.f, 0.f);
-      if (n < g.N && k < t.kend) v = t.B[k * g.b_ks + n * g.b_ns];
+#pragma unroll
+    for (int u = 0; u < Stage<BN, BKS>::CNT; ++u) {
+      int ni, ki;
+      Stage<BN, BKS>::coords(u, bkfast, ni, ki);
+      float2 v = sb.v[u];
       if (g.conjB) v.y = -v.y;
       uint16_t h, l;
       split_pair(v.x, h, l); Bs[0][ni][ki] = h; Bs[1][ni][ki] = l;
       split_pair(v.y, h, l); Bs[2][ni][ki] = h; Bs[3][ni][ki] = l;
     }
     __syncthreads();
+    if (k0 + BKS < t.kend) {
+      sa.fetch(t.A, t.m0, g.M, g.a_ms, g.a_ks, k0 + BKS, t.kend);
+      sb.fetch(t.B, t.n0, g.N, g.b_ns, g.b_ks, k0 + BKS, t.kend);
+    }
     // one 16x16x32 step covers the whole BKS = 32 stage
     const int c = lane & 15, kq = (lane >> 4) * 8;
     bf16x8 a[2][4], bb[2][4];
