@@ -55,8 +55,12 @@ __global__ __launch_bounds__(NT) void fft_axis_kernel(FftAxisArgs a) {
     tg.LS = 1;
     tg.ES = tg.T;
     const int64_t chunks = (a.inner + tg.T - 1) / tg.T;
-    o0 = blockIdx.x / chunks;
-    t0 = (blockIdx.x % chunks) * tg.T;
+    // consecutive chunks (adjacent columns, which share cache lines) go to one XCD: the
+    // hardware deals workgroups round-robin over the 8 XCDs, each with its own L2
+    int64_t bid = blockIdx.x;
+    if ((gridDim.x & 7) == 0) bid = (int64_t)(blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+    o0 = bid / chunks;
+    t0 = (bid % chunks) * tg.T;
     Tvalid = (int)((a.inner - t0) < tg.T ? (a.inner - t0) : tg.T);
   }
   const int total = tg.T * n;
