@@ -213,6 +213,40 @@ maxwell_status maxwell_grad(maxwell_plan_t plan, const maxwell_complex64* x,
                             maxwell_complex64* gx, maxwell_complex64* gc, double* loss_dev,
                             void* ws, size_t ws_bytes, void* stream);
 
+/* Gauss-Newton step of the joint image / coefficient solve (Sec. II-B, Eq. (6): the
+ * linearised misfit plus alpha_n ||p + dp||^2 + beta_n sum ||a_k + da_k||^2, minimised by
+ * conjugate gradients on its normal equations).
+ *
+ * maxwell_jvp: the Jacobian-vector product of Eq. (7) at (x, c),
+ *     y_j = F_s( (B c_j) (.) dx + x (.) (B dc_j) )       dx: [N], dc: [J][K], y: [J][M]
+ *   computed as E(dx, c) + E(x, dc) (E is bilinear).
+ * maxwell_normal: the normal operator at (x, c),
+ *     (ox, oc) = J^H (w (.) J[dx, dc]) + (lambda_x dx, lambda_c dc)
+ *   with the plan's data weights w (1 when the plan has none).  For the objective of
+ *   Eq. (6) (1/2 on the misfit, none on the penalties) lambda_x = 2 alpha_n and
+ *   lambda_c = 2 beta_n.  Hermitian; positive definite when both lambdas are > 0.
+ * maxwell_cg: iters steps of conjugate gradients from zero on
+ *     normal(dx, dc) = (bx, bc)
+ *   with the step lengths and direction factors from inner products Re <a, b> over both
+ *   blocks accumulated in FP64 (fixed-order reductions, no atomics).  rr_dev (device,
+ *   iters + 1 doubles, may be NULL) receives <r_k, r_k> for k = 0..iters (r_0 = b).  The
+ *   scalars stay on the device: nothing synchronises with the host and the call can be
+ *   captured.  A zero <d, A d> or <r, r> gives a zero step.  iters in [0, 100000].
+ * Errors: null or misaligned required pointers, non-finite lambdas, overlapping outputs
+ * and inputs, a workspace smaller than maxwell_plan_workspace_size.  The workspace holds
+ * every intermediate (the JVP result, three CG vectors of N + J K entries, FP64 scalars). */
+maxwell_status maxwell_jvp(maxwell_plan_t plan, const maxwell_complex64* x, const maxwell_complex64* c,
+                           const maxwell_complex64* dx, const maxwell_complex64* dc, maxwell_complex64* y,
+                           void* ws, size_t ws_bytes, void* stream);
+maxwell_status maxwell_normal(maxwell_plan_t plan, const maxwell_complex64* x, const maxwell_complex64* c,
+                              const maxwell_complex64* dx, const maxwell_complex64* dc, float lambda_x,
+                              float lambda_c, maxwell_complex64* ox, maxwell_complex64* oc, void* ws,
+                              size_t ws_bytes, void* stream);
+maxwell_status maxwell_cg(maxwell_plan_t plan, const maxwell_complex64* x, const maxwell_complex64* c,
+                          const maxwell_complex64* bx, const maxwell_complex64* bc, float lambda_x,
+                          float lambda_c, int32_t iters, maxwell_complex64* dx, maxwell_complex64* dc,
+                          double* rr_dev, void* ws, size_t ws_bytes, void* stream);
+
 /* Batches of independent slices (the batched serving form of the operator: many 2D
  * problems of uneven sizes, each with its own plan, basis and sampling, Sec. II-B per
  * slice).

@@ -30,7 +30,7 @@ EXPORTS = [
     "maxwell_basis_apply", "maxwell_basis_apply_adjoint", "maxwell_encode", "maxwell_adjoint",
     "maxwell_forward_loss", "maxwell_forward_transfer", "maxwell_adjoint_transfer", "maxwell_grad",
     "maxwell_last_error", "maxwell_version", "maxwell_batch_create", "maxwell_batch_workspace_size",
-    "maxwell_batch_grad", "maxwell_batch_destroy",
+    "maxwell_batch_grad", "maxwell_batch_destroy", "maxwell_jvp", "maxwell_normal", "maxwell_cg",
     "maxwell_plan_set_timing", "maxwell_plan_timing",
 ]
 
@@ -115,6 +115,13 @@ def load(path: str = LIB_PATH):
     lib.maxwell_batch_destroy.restype = None
     lib.maxwell_grad.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.maxwell_grad.restype = st
+    lib.maxwell_jvp.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.maxwell_jvp.restype = st
+    lib.maxwell_normal.argtypes = [vp, vp, vp, vp, vp, ctypes.c_float, ctypes.c_float, vp, vp, vp, sz, vp]
+    lib.maxwell_normal.restype = st
+    lib.maxwell_cg.argtypes = [vp, vp, vp, vp, vp, ctypes.c_float, ctypes.c_float, ctypes.c_int32, vp, vp, vp,
+                               vp, sz, vp]
+    lib.maxwell_cg.restype = st
     lib.maxwell_plan_set_timing.argtypes = [vp, ctypes.c_int]
     lib.maxwell_plan_set_timing.restype = st
     lib.maxwell_plan_timing.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int),

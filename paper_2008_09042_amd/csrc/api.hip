@@ -438,6 +438,78 @@ maxwell_status maxwell_grad(maxwell_plan_t plan, const maxwell_complex64* x, con
   return MAXWELL_OK;
 }
 
+maxwell_status maxwell_jvp(maxwell_plan_t plan, const maxwell_complex64* x, const maxwell_complex64* c,
+                           const maxwell_complex64* dx, const maxwell_complex64* dc, maxwell_complex64* y, void* ws,
+                           size_t ws_bytes, void* stream) {
+  if (!plan) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "plan is null");
+  const Plan* p = reinterpret_cast<const Plan*>(plan);
+  Check ck(p);
+  ck.in(x, p->bytes_x(), "x");
+  ck.in(c, p->bytes_c(), "c");
+  ck.in(dx, p->bytes_x(), "dx");
+  ck.in(dc, p->bytes_c(), "dc");
+  ck.out(y, p->bytes_y(), "y");
+  ck.ws(ws, ws_bytes);
+  maxwell_status s = ck.finish();
+  if (s != MAXWELL_OK) return s;
+  HIP_TRY(run_jvp(*p, reinterpret_cast<const float2*>(x), reinterpret_cast<const float2*>(c),
+                  reinterpret_cast<const float2*>(dx), reinterpret_cast<const float2*>(dc), reinterpret_cast<float2*>(y),
+                  ws, (hipStream_t)stream),
+          "jvp");
+  return MAXWELL_OK;
+}
+
+maxwell_status maxwell_normal(maxwell_plan_t plan, const maxwell_complex64* x, const maxwell_complex64* c,
+                              const maxwell_complex64* dx, const maxwell_complex64* dc, float lambda_x, float lambda_c,
+                              maxwell_complex64* ox, maxwell_complex64* oc, void* ws, size_t ws_bytes, void* stream) {
+  if (!plan) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "plan is null");
+  if (!std::isfinite(lambda_x) || !std::isfinite(lambda_c))
+    return fail(MAXWELL_ERR_INVALID_ARGUMENT, "lambda_x and lambda_c must be finite");
+  const Plan* p = reinterpret_cast<const Plan*>(plan);
+  Check ck(p);
+  ck.in(x, p->bytes_x(), "x");
+  ck.in(c, p->bytes_c(), "c");
+  ck.in(dx, p->bytes_x(), "dx");
+  ck.in(dc, p->bytes_c(), "dc");
+  ck.out(ox, p->bytes_x(), "ox");
+  ck.out(oc, p->bytes_c(), "oc");
+  ck.ws(ws, ws_bytes);
+  maxwell_status s = ck.finish();
+  if (s != MAXWELL_OK) return s;
+  HIP_TRY(run_normal(*p, reinterpret_cast<const float2*>(x), reinterpret_cast<const float2*>(c),
+                     reinterpret_cast<const float2*>(dx), reinterpret_cast<const float2*>(dc), lambda_x, lambda_c,
+                     reinterpret_cast<float2*>(ox), reinterpret_cast<float2*>(oc), ws, (hipStream_t)stream),
+          "normal");
+  return MAXWELL_OK;
+}
+
+maxwell_status maxwell_cg(maxwell_plan_t plan, const maxwell_complex64* x, const maxwell_complex64* c,
+                          const maxwell_complex64* bx, const maxwell_complex64* bc, float lambda_x, float lambda_c,
+                          int32_t iters, maxwell_complex64* dx, maxwell_complex64* dc, double* rr_dev, void* ws,
+                          size_t ws_bytes, void* stream) {
+  if (!plan) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "plan is null");
+  if (!std::isfinite(lambda_x) || !std::isfinite(lambda_c))
+    return fail(MAXWELL_ERR_INVALID_ARGUMENT, "lambda_x and lambda_c must be finite");
+  if (iters < 0 || iters > 100000) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "iters must be in [0, 100000]");
+  const Plan* p = reinterpret_cast<const Plan*>(plan);
+  Check ck(p);
+  ck.in(x, p->bytes_x(), "x");
+  ck.in(c, p->bytes_c(), "c");
+  ck.in(bx, p->bytes_x(), "bx");
+  ck.in(bc, p->bytes_c(), "bc");
+  ck.out(dx, p->bytes_x(), "dx");
+  ck.out(dc, p->bytes_c(), "dc");
+  ck.out(rr_dev, (size_t)(iters + 1) * sizeof(double), "rr_dev", false);
+  ck.ws(ws, ws_bytes);
+  maxwell_status s = ck.finish();
+  if (s != MAXWELL_OK) return s;
+  HIP_TRY(run_cg(*p, reinterpret_cast<const float2*>(x), reinterpret_cast<const float2*>(c),
+                 reinterpret_cast<const float2*>(bx), reinterpret_cast<const float2*>(bc), lambda_x, lambda_c, iters,
+                 reinterpret_cast<float2*>(dx), reinterpret_cast<float2*>(dc), rr_dev, ws, (hipStream_t)stream),
+          "cg");
+  return MAXWELL_OK;
+}
+
 }  // extern "C"
 
 // ------------------------------------------------------------------ batches of slices

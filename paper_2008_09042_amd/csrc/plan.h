@@ -74,6 +74,7 @@ struct Plan {
   size_t ws_bytes = 0;
   size_t off_S = 0, off_K = 0, off_tA = 0, off_tB = 0, off_E = 0, off_gemm = 0, off_part = 0;
   size_t off_T1 = 0, off_T3 = 0, off_xt = 0, off_Z = 0, off_gxp = 0, off_T3b = 0, off_T1b = 0, off_G = 0, off_Ys = 0, off_cpart = 0;
+  size_t off_U = 0, off_cg = 0;  // Gauss-Newton / CG: JVP result; r, d, q, FP64 scalars
   int part_blocks = 0;
 
   size_t bytes_x() const { return (size_t)N * 8; }
@@ -111,5 +112,13 @@ hipError_t run_forward_loss(const Plan& p, const float2* x, const float2* c, con
                             double* loss, void* ws, hipStream_t st, bool transfer = false);
 hipError_t run_grad(const Plan& p, const float2* x, const float2* c, const float2* y, float2* gx, float2* gc,
                     double* loss, void* ws, hipStream_t st);
+// Gauss-Newton step: Jacobian-vector product, normal operator, conjugate gradients
+constexpr int CG_SCALARS = 8;
+hipError_t run_jvp(const Plan& p, const float2* x, const float2* c, const float2* dx, const float2* dc, float2* y,
+                   void* ws, hipStream_t st);
+hipError_t run_normal(const Plan& p, const float2* x, const float2* c, const float2* dx, const float2* dc,
+                      float lam_x, float lam_c, float2* ox, float2* oc, void* ws, hipStream_t st);
+hipError_t run_cg(const Plan& p, const float2* x, const float2* c, const float2* bx, const float2* bc, float lam_x,
+                  float lam_c, int iters, float2* dx, float2* dc, double* rr, void* ws, hipStream_t st);
 
 }  // namespace mx

@@ -18,6 +18,7 @@
 #include "fused.h"
 #include "mode3.h"
 #include "nufft.h"
+#include "solver.h"
 #include "plan.h"
 
 namespace mx {
@@ -588,6 +589,11 @@ maxwell_status plan_build(Plan& p, const maxwell_plan_desc& d, const maxwell_bas
   p.part_blocks = residual_blocks((int64_t)p.J * p.M);
   if (p.fused) p.part_blocks = std::max(p.part_blocks, line_blocks(p.J, p.L));
   p.off_part = off; off += al((size_t)p.part_blocks * sizeof(double));
+  // Gauss-Newton / CG: the JVP result, the work vectors r, d, q ([N | J K] each), and the
+  // FP64 scalars and inner-product partials
+  const size_t V = ((size_t)p.N + (size_t)p.J * (size_t)p.K) * 8;
+  p.off_U = off; off += al(JM);
+  p.off_cg = off; off += 3 * al(V) + al(CG_SCALARS * sizeof(double)) + al(DOT_BLOCKS * sizeof(double));
   p.ws_bytes = off;
   return MAXWELL_OK;
 }
@@ -865,6 +871,63 @@ hipError_t run_grad(const Plan& p, const float2* x, const float2* c, const float
   if (e != hipSuccess) return e;
   if (!want) return hipSuccess;
   return run_adjoint(p, x, c, r, 2.0f, nullptr, gx, gc, ws, st, true, true);
+}
+
+// ---- Gauss-Newton step (Sec. II-B, Eq. (6) and Eq. (7))
+
+// J[dx, dc] = E(dx, c) + E(x, dc): E is bilinear, so the Jacobian-vector product of Eq. (7)
+// is two encodes; the second goes through the E region of the workspace.
+hipError_t run_jvp(const Plan& p, const float2* x, const float2* c, const float2* dx, const float2* dc, float2* y,
+                   void* ws, hipStream_t st) {
+  hipError_t e = run_encode(p, dx, c, y, ws, st);
+  if (e != hipSuccess) return e;
+  float2* E = wsp<float2>(ws, p.off_E);
+  if ((e = run_encode(p, x, dc, E, ws, st)) != hipSuccess) return e;
+  return TIMED("jvp_sum", caxpy_launch(y, E, 1.0f, (int64_t)p.J * p.M, st));
+}
+
+// (ox, oc) = J^H (w (.) J[dx, dc]) + (lam_x dx, lam_c dc)
+hipError_t run_normal(const Plan& p, const float2* x, const float2* c, const float2* dx, const float2* dc,
+                      float lam_x, float lam_c, float2* ox, float2* oc, void* ws, hipStream_t st) {
+  float2* u = wsp<float2>(ws, p.off_U);
+  hipError_t e = run_jvp(p, x, c, dx, dc, u, ws, st);
+  if (e != hipSuccess) return e;
+  if (p.d_w && (e = TIMED("weights", weight_rows_launch(u, p.d_w, p.M, p.J, st))) != hipSuccess) return e;
+  if ((e = run_adjoint(p, x, c, u, 1.0f, nullptr, ox, oc, ws, st, false, false)) != hipSuccess) return e;
+  if ((e = TIMED("normal_axpy", caxpy_launch(ox, dx, lam_x, p.N, st))) != hipSuccess) return e;
+  return TIMED("normal_axpy", caxpy_launch(oc, dc, lam_c, (int64_t)p.J * p.K, st));
+}
+
+// iters steps of conjugate gradients from zero on normal(dv) = b (the caller's bx, bc);
+// rr (optional, device, iters + 1 doubles) receives <r_k, r_k>.  All scalars stay on the
+// device (FP64); nothing synchronises with the host.
+hipError_t run_cg(const Plan& p, const float2* x, const float2* c, const float2* bx, const float2* bc, float lam_x,
+                  float lam_c, int iters, float2* dx, float2* dc, double* rr, void* ws, hipStream_t st) {
+  const int64_t N = p.N, JK = (int64_t)p.J * p.K, n = N + JK;
+  const size_t V = al((size_t)n * 8);
+  char* base = wsp<char>(ws, p.off_cg);
+  float2* r = reinterpret_cast<float2*>(base);
+  float2* d = reinterpret_cast<float2*>(base + V);
+  float2* q = reinterpret_cast<float2*>(base + 2 * V);
+  double* sc = reinterpret_cast<double*>(base + 3 * V);
+  double *rho = sc, *rho_new = sc + 1, *dq = sc + 2, *alpha = sc + 3, *beta = sc + 4;
+  double* part = reinterpret_cast<double*>(base + 3 * V + al(CG_SCALARS * sizeof(double)));
+  hipError_t e;
+  if ((e = zero_split_launch(dx, dc, N, JK, st)) != hipSuccess) return e;
+  if ((e = copy_split_launch(r, r + N, bx, bc, N, JK, st)) != hipSuccess) return e;
+  if ((e = copy_split_launch(d, d + N, bx, bc, N, JK, st)) != hipSuccess) return e;
+  if ((e = TIMED("cg_dot", dot_launch(r, r, n, part, rho, st))) != hipSuccess) return e;
+  if (rr && (e = copy_scalar_launch(rho, rr, st)) != hipSuccess) return e;
+  for (int k = 0; k < iters; ++k) {
+    if ((e = run_normal(p, x, c, d, d + N, lam_x, lam_c, q, q + N, ws, st)) != hipSuccess) return e;
+    if ((e = TIMED("cg_dot", dot_launch(d, q, n, part, dq, st))) != hipSuccess) return e;
+    if ((e = cg_alpha_launch(rho, dq, alpha, st)) != hipSuccess) return e;
+    if ((e = TIMED("cg_update", cg_xr_launch(dx, dc, N, JK, r, d, q, alpha, st))) != hipSuccess) return e;
+    if ((e = TIMED("cg_dot", dot_launch(r, r, n, part, rho_new, st))) != hipSuccess) return e;
+    if ((e = cg_beta_launch(rho, rho_new, beta, rr ? rr + k + 1 : nullptr, st)) != hipSuccess) return e;
+    if ((e = TIMED("cg_update", cg_d_launch(d, r, n, beta, st))) != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace mx

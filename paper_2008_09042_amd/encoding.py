@@ -260,6 +260,45 @@ class MaxwellPlan:
                                       ws, nb, _stream()))
         return loss, gx, gc
 
+    # ---- Gauss-Newton step (Sec. II-B, Eq. (6) and Eq. (7))
+    def jvp(self, x, c, dx, dc):
+        """J[dx, dc] at (x, c): F_s((B c_j) dx + x (B dc_j)) -> [J][M]."""
+        x = self._in(x, self.dims, "x")
+        c = self._in(c, (self.J, self.K), "c")
+        dx = self._in(dx, self.dims, "dx")
+        dc = self._in(dc, (self.J, self.K), "dc")
+        y = self._new((self.J, self.M))
+        ws, nb = self._wsargs()
+        L.check(self.lib.maxwell_jvp(self.handle, _ptr(x), _ptr(c), _ptr(dx), _ptr(dc), _ptr(y), ws, nb, _stream()))
+        return y
+
+    def normal(self, x, c, dx, dc, lambda_x: float, lambda_c: float):
+        """J^H (w J[dx, dc]) + (lambda_x dx, lambda_c dc) at (x, c)."""
+        x = self._in(x, self.dims, "x")
+        c = self._in(c, (self.J, self.K), "c")
+        dx = self._in(dx, self.dims, "dx")
+        dc = self._in(dc, (self.J, self.K), "dc")
+        ox = self._new(self.dims)
+        oc = self._new((self.J, self.K))
+        ws, nb = self._wsargs()
+        L.check(self.lib.maxwell_normal(self.handle, _ptr(x), _ptr(c), _ptr(dx), _ptr(dc), float(lambda_x),
+                                        float(lambda_c), _ptr(ox), _ptr(oc), ws, nb, _stream()))
+        return ox, oc
+
+    def cg(self, x, c, bx, bc, lambda_x: float, lambda_c: float, iters: int):
+        """iters CG steps from zero on normal(dv) = b -> (dx, dc, rr) with rr[k] = <r_k, r_k> (FP64)."""
+        x = self._in(x, self.dims, "x")
+        c = self._in(c, (self.J, self.K), "c")
+        bx = self._in(bx, self.dims, "bx")
+        bc = self._in(bc, (self.J, self.K), "bc")
+        dx = self._new(self.dims)
+        dc = self._new((self.J, self.K))
+        rr = torch.empty(int(iters) + 1, dtype=torch.float64, device=self.device)
+        ws, nb = self._wsargs()
+        L.check(self.lib.maxwell_cg(self.handle, _ptr(x), _ptr(c), _ptr(bx), _ptr(bc), float(lambda_x),
+                                    float(lambda_c), int(iters), _ptr(dx), _ptr(dc), _ptr(rr), ws, nb, _stream()))
+        return dx, dc, rr
+
 
 class MaxwellBatch:
     """Gradients of many independent slices (each a MaxwellPlan) in one call.

@@ -201,6 +201,10 @@ def test_null_arguments(lib):
             == L.MAXWELL_ERR_INVALID_ARGUMENT)
     assert lib.maxwell_basis_apply(None, z, z, None, 0, None) == L.MAXWELL_ERR_INVALID_ARGUMENT
     assert lib.maxwell_basis_apply_adjoint(None, z, z, None, 0, None) == L.MAXWELL_ERR_INVALID_ARGUMENT
+    assert lib.maxwell_jvp(None, z, z, z, z, z, None, 0, None) == L.MAXWELL_ERR_INVALID_ARGUMENT
+    assert lib.maxwell_normal(None, z, z, z, z, 0.1, 0.1, z, z, None, 0, None) == L.MAXWELL_ERR_INVALID_ARGUMENT
+    assert (lib.maxwell_cg(None, z, z, z, z, 0.1, 0.1, 3, z, z, None, None, 0, None)
+            == L.MAXWELL_ERR_INVALID_ARGUMENT)
     assert lib.maxwell_plan_set_timing(None, 1) == L.MAXWELL_ERR_INVALID_ARGUMENT
     assert "plan is null" in lib.maxwell_last_error().decode()
 
