@@ -41,9 +41,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", default="bf16_split", choices=["bf16_split", "fp32"])
-    ap.add_argument("--workload", default="cart3d", choices=["cart3d", "batch"],
+    ap.add_argument("--workload", default="cart3d", choices=["cart3d", "batch", "gn"],
                     help="cart3d: the headline 128^3 Tucker workload; batch: 64 uneven 2D slices with "
-                         "dense bases through one captured graph")
+                         "dense bases through one captured graph; gn: conjugate-gradient steps of the "
+                         "Gauss-Newton normal equations on the 128^3 Tucker workload")
+    ap.add_argument("--cg-iters", type=int, default=10, help="gn workload: CG steps per timed call")
     ap.add_argument("--branches", type=int, default=4, help="batch workload: concurrent branches")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the second-precision run")
@@ -276,6 +278,64 @@ def bench_batch(args, torch):
     print(json.dumps(out), flush=True)
 
 
+def bench_gn(args, torch):
+    """Gauss-Newton step of the joint solve on the 128^3 Tucker workload: maxwell_cg with
+    cg-iters steps per call, each step one normal-operator application (two encodes for the
+    JVP, one adjoint with B c recomputed, the shift) plus the FP64 inner products.  Prints
+    one JSON line (coil-images/s = J x normal-operator applications per second)."""
+    from paper_2008_09042_amd.encoding import MaxwellPlan
+    dev = torch.device("cuda:0")
+    p = make_inputs()
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(np.asarray(a).astype(np.complex64))).to(dev)  # noqa: E731
+    U = [T(u) for u in p.U]
+    core = T(p.core)
+    res = {}
+    for prec in ([args.precision] if args.no_compare else [args.precision] +
+                 [q for q in ("bf16_split", "fp32") if q != args.precision]):
+        plan = MaxwellPlan(p.dims, p.J, U=U, core=core, mask_idx=p.mask_idx, precision=prec, device=dev)
+        x0, c0 = T(p.x0), T(p.c0)
+        y = plan.encode(T(p.x_true), T(p.c_true)).contiguous()
+        _, bx, bc = plan.grad(x0, c0, y)  # right-hand side of the shape of a Gauss-Newton step
+        bx, bc = -0.5 * bx, -0.5 * bc
+        ox, oc = plan.normal(x0, c0, bx, bc, 0.0, 0.0)
+        q = (torch.vdot(bx.reshape(-1), ox.reshape(-1)).real + torch.vdot(bc.reshape(-1), oc.reshape(-1)).real) / (
+            torch.linalg.vector_norm(bx) ** 2 + torch.linalg.vector_norm(bc) ** 2)
+        lam = float(0.2 * q)
+        it = args.cg_iters
+        ms, wall = time_steps(lambda: plan.cg(x0, c0, bx, bc, lam, lam, it), args.steps, args.warmup, torch)
+        res[prec] = ms / it
+        log(f"[bench] gn {prec}: {ms:.3f} ms per {it} CG steps ({ms / it:.3f} ms per normal-operator "
+            f"application, {p.J * it * 1000.0 / ms:.0f} coil-images/s)")
+        if prec == args.precision:
+            plan.set_timing(True)
+            plan.cg(x0, c0, bx, bc, lam, lam, it)
+            torch.cuda.synchronize()
+            kt = plan.timing()
+            plan.set_timing(False)
+            log("[bench] gn kernel timing (us per launch): " +
+                ", ".join(f"{k} {1000 * t / n:.1f}x{n // it}" for k, (n, t) in kt.items() if n))
+        del plan
+    ms_it = res[args.precision]
+    out = {
+        "metric": "Gauss-Newton normal-operator applications/sec x coils (coil-images/s)",
+        "value": p.J * 1000.0 / ms_it,
+        "unit": "coil-images/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_it * args.cg_iters,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16-split" if args.precision == "bf16_split" else "f32",
+        "data": "synthetic (seeded phantom, Tucker basis, Poisson-disc mask; no datasets)",
+        "config": {"workload": "gn_" + WORKLOAD, "cg_iters_per_step": args.cg_iters,
+                   "step": "maxwell_cg: CG steps on (J^H J + lambda) dv = b, FP64 inner products on the device"},
+        "ms_per_cg_iteration": {k: v for k, v in res.items()},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.traffic_from:
@@ -289,6 +349,9 @@ def main():
     from paper_2008_09042_amd.encoding import MaxwellDataFidelity, MaxwellPlan
     if args.workload == "batch":
         bench_batch(args, torch)
+        return
+    if args.workload == "gn":
+        bench_gn(args, torch)
         return
 
     dev = torch.device("cuda:0")

@@ -15,9 +15,10 @@ basis     dense and Tucker basis apply and adjoint (Sec. II-B Eq. (5); Sec. II-E
 nufft     Kaiser-Bessel NUFFT type 2 / type 1 and the exact NDFT (Sec. III-B, radial F)
 encoding  encoding operator, Jacobian adjoint, JVP, loss and gradient (Sec. II-B)
 solver    Gauss-Newton normal operator and conjugate gradients of the IRGN step (Sec. II-B, Eq. (6))
+admm      SENSE with fixed maps, ball projection, TV prox and the constrained ADMM (Sec. II-C)
 
 Every public function is pinned by ``tests/test_oracle_pins.py`` and
-``tests/test_oracle_solver.py`` against
+``tests/test_oracle_solver.py`` and ``tests/test_oracle_admm.py`` against
 brute force, closed forms, invariants or library special cases.
 """
 from .dft import centred_dft, centred_idft  # noqa: F401
