@@ -247,6 +247,51 @@ maxwell_status maxwell_cg(maxwell_plan_t plan, const maxwell_complex64* x, const
                           float lambda_c, int32_t iters, maxwell_complex64* dx, maxwell_complex64* dc,
                           double* rr_dev, void* ws, size_t ws_bytes, void* stream);
 
+/* SENSE with fixed maps and the constrained density reconstruction (Sec. II-C): with the
+ * coil maps S [J][N] (device) fixed, minimise TV(p) subject to ||y_k - F_s S_k p|| <= eps_k.
+ * General-path plans only (maxwell_plan_path() == "general"; a fused plan gives
+ * MAXWELL_ERR_UNSUPPORTED); the plan's basis is not used by these calls.
+ *
+ * maxwell_sense_encode:  y_k = F_s(S_k (.) x)                                  y: [J][M]
+ * maxwell_sense_adjoint: gx = sum_k conj(S_k) (.) F_s^H y_k                     gx: [N]
+ * maxwell_sense_normal:  out = x + sum_k conj(S_k) (.) F_s^H F_s (S_k (.) x)    (the
+ *   p-update operator of the ADMM iteration, I + A^H A restricted to the data blocks)
+ * maxwell_tv_prox: x = argmin 1/2 ||x - z||^2 + lambda TV(x), TV(x) = sum over pixels of
+ *   sqrt(sum_d |x[i + e_d] - x[i]|^2) (forward differences, zero at the last index of each
+ *   axis; real and imaginary parts coupled), by iters steps of Chambolle's dual projection
+ *   (step 1 / (4 ndim)) from a zero dual field.  lambda >= 0 (0 returns z).
+ * maxwell_ball_project: z_k = y_k + eps_k (w_k - y_k) / max(||w_k - y_k||, eps_k) per coil,
+ *   eps_dev = J device floats >= 0 (the distance in FP64).
+ * maxwell_sense_admm: iters steps of the scaled ADMM of Sec. II-C with A = [I; F_s S_k]:
+ *     z_0 = prox_{TV / rho}(p + u_0)          (tv_iters Chambolle steps)
+ *     z_k = ball projection of F_s S_k p + u_k
+ *     p  += CG (cg_iters steps from zero) on (I + sum S^H F^H F S) dp = z_0 - u_0
+ *           + sum S_k^H F^H (z_k - u_k) - (I + sum S^H F^H F S) p
+ *     u  += A p - z
+ *   then residual balancing of rho (primal r = ||A p - z||, dual s = rho ||A^H (z - z_prev)||:
+ *   rho doubles and u halves when r > 10 s, the reverse when s > 10 r).  p starts at the
+ *   SENSE combination sum S^H F^H y, z and u at zero, rho at rho0 > 0.  hist_dev (device,
+ *   iters x 3 doubles, may be NULL) receives (rho, r, s) of each step.  All norms are FP64
+ *   and stay on the device: no host synchronisation; the call can be captured.
+ * Errors: null or misaligned required pointers, bad lambda / rho0 / iteration counts,
+ * overlapping outputs and inputs, a workspace smaller than maxwell_plan_workspace_size
+ * (which includes the ADMM state on general-path plans).                               */
+maxwell_status maxwell_sense_encode(maxwell_plan_t plan, const maxwell_complex64* S, const maxwell_complex64* x,
+                                    maxwell_complex64* y, void* ws, size_t ws_bytes, void* stream);
+maxwell_status maxwell_sense_adjoint(maxwell_plan_t plan, const maxwell_complex64* S, const maxwell_complex64* y,
+                                     maxwell_complex64* gx, void* ws, size_t ws_bytes, void* stream);
+maxwell_status maxwell_sense_normal(maxwell_plan_t plan, const maxwell_complex64* S, const maxwell_complex64* x,
+                                    maxwell_complex64* out, void* ws, size_t ws_bytes, void* stream);
+maxwell_status maxwell_tv_prox(maxwell_plan_t plan, const maxwell_complex64* z, float lambda, int32_t iters,
+                               maxwell_complex64* x, void* ws, size_t ws_bytes, void* stream);
+maxwell_status maxwell_ball_project(maxwell_plan_t plan, const maxwell_complex64* w, const maxwell_complex64* y,
+                                    const float* eps_dev, maxwell_complex64* z, void* ws, size_t ws_bytes,
+                                    void* stream);
+maxwell_status maxwell_sense_admm(maxwell_plan_t plan, const maxwell_complex64* S, const maxwell_complex64* y,
+                                  const float* eps_dev, float rho0, int32_t iters, int32_t cg_iters,
+                                  int32_t tv_iters, maxwell_complex64* p_out, double* hist_dev, void* ws,
+                                  size_t ws_bytes, void* stream);
+
 /* Batches of independent slices (the batched serving form of the operator: many 2D
  * problems of uneven sizes, each with its own plan, basis and sampling, Sec. II-B per
  * slice).

@@ -31,6 +31,8 @@ EXPORTS = [
     "maxwell_forward_loss", "maxwell_forward_transfer", "maxwell_adjoint_transfer", "maxwell_grad",
     "maxwell_last_error", "maxwell_version", "maxwell_batch_create", "maxwell_batch_workspace_size",
     "maxwell_batch_grad", "maxwell_batch_destroy", "maxwell_jvp", "maxwell_normal", "maxwell_cg",
+    "maxwell_sense_encode", "maxwell_sense_adjoint", "maxwell_sense_normal", "maxwell_tv_prox",
+    "maxwell_ball_project", "maxwell_sense_admm",
     "maxwell_plan_set_timing", "maxwell_plan_timing",
 ]
 
@@ -122,6 +124,16 @@ def load(path: str = LIB_PATH):
     lib.maxwell_cg.argtypes = [vp, vp, vp, vp, vp, ctypes.c_float, ctypes.c_float, ctypes.c_int32, vp, vp, vp,
                                vp, sz, vp]
     lib.maxwell_cg.restype = st
+    for f in ("maxwell_sense_encode", "maxwell_sense_adjoint", "maxwell_sense_normal"):
+        getattr(lib, f).argtypes = [vp, vp, vp, vp, vp, sz, vp]
+        getattr(lib, f).restype = st
+    lib.maxwell_tv_prox.argtypes = [vp, vp, ctypes.c_float, ctypes.c_int32, vp, vp, sz, vp]
+    lib.maxwell_tv_prox.restype = st
+    lib.maxwell_ball_project.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.maxwell_ball_project.restype = st
+    lib.maxwell_sense_admm.argtypes = [vp, vp, vp, vp, ctypes.c_float, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_int32, vp, vp, vp, sz, vp]
+    lib.maxwell_sense_admm.restype = st
     lib.maxwell_plan_set_timing.argtypes = [vp, ctypes.c_int]
     lib.maxwell_plan_set_timing.restype = st
     lib.maxwell_plan_timing.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int),

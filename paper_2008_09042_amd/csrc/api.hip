@@ -510,6 +510,132 @@ maxwell_status maxwell_cg(maxwell_plan_t plan, const maxwell_complex64* x, const
   return MAXWELL_OK;
 }
 
+// ---- SENSE with fixed maps and the constrained reconstruction (general path)
+
+static maxwell_status need_general(const Plan* p) {
+  if (p->fused)
+    return fail(MAXWELL_ERR_UNSUPPORTED, "SENSE / ADMM calls need a plan on the general path (maxwell_plan_path)");
+  return MAXWELL_OK;
+}
+
+maxwell_status maxwell_sense_encode(maxwell_plan_t plan, const maxwell_complex64* S, const maxwell_complex64* x,
+                                    maxwell_complex64* y, void* ws, size_t ws_bytes, void* stream) {
+  if (!plan) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "plan is null");
+  const Plan* p = reinterpret_cast<const Plan*>(plan);
+  if (maxwell_status g = need_general(p)) return g;
+  Check ck(p);
+  ck.in(S, p->bytes_S(), "S");
+  ck.in(x, p->bytes_x(), "x");
+  ck.out(y, p->bytes_y(), "y");
+  ck.ws(ws, ws_bytes);
+  maxwell_status s = ck.finish();
+  if (s != MAXWELL_OK) return s;
+  HIP_TRY(run_sense_encode(*p, reinterpret_cast<const float2*>(S), reinterpret_cast<const float2*>(x),
+                           reinterpret_cast<float2*>(y), ws, (hipStream_t)stream),
+          "sense_encode");
+  return MAXWELL_OK;
+}
+
+maxwell_status maxwell_sense_adjoint(maxwell_plan_t plan, const maxwell_complex64* S, const maxwell_complex64* y,
+                                     maxwell_complex64* gx, void* ws, size_t ws_bytes, void* stream) {
+  if (!plan) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "plan is null");
+  const Plan* p = reinterpret_cast<const Plan*>(plan);
+  if (maxwell_status g = need_general(p)) return g;
+  Check ck(p);
+  ck.in(S, p->bytes_S(), "S");
+  ck.in(y, p->bytes_y(), "y");
+  ck.out(gx, p->bytes_x(), "gx");
+  ck.ws(ws, ws_bytes);
+  maxwell_status s = ck.finish();
+  if (s != MAXWELL_OK) return s;
+  HIP_TRY(run_sense_adjoint(*p, reinterpret_cast<const float2*>(S), reinterpret_cast<const float2*>(y),
+                            reinterpret_cast<float2*>(gx), ws, (hipStream_t)stream),
+          "sense_adjoint");
+  return MAXWELL_OK;
+}
+
+maxwell_status maxwell_sense_normal(maxwell_plan_t plan, const maxwell_complex64* S, const maxwell_complex64* x,
+                                    maxwell_complex64* out, void* ws, size_t ws_bytes, void* stream) {
+  if (!plan) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "plan is null");
+  const Plan* p = reinterpret_cast<const Plan*>(plan);
+  if (maxwell_status g = need_general(p)) return g;
+  Check ck(p);
+  ck.in(S, p->bytes_S(), "S");
+  ck.in(x, p->bytes_x(), "x");
+  ck.out(out, p->bytes_x(), "out");
+  ck.ws(ws, ws_bytes);
+  maxwell_status s = ck.finish();
+  if (s != MAXWELL_OK) return s;
+  HIP_TRY(run_sense_normal(*p, reinterpret_cast<const float2*>(S), reinterpret_cast<const float2*>(x),
+                           reinterpret_cast<float2*>(out), ws, (hipStream_t)stream),
+          "sense_normal");
+  return MAXWELL_OK;
+}
+
+maxwell_status maxwell_tv_prox(maxwell_plan_t plan, const maxwell_complex64* z, float lambda, int32_t iters,
+                               maxwell_complex64* x, void* ws, size_t ws_bytes, void* stream) {
+  if (!plan) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "plan is null");
+  if (!std::isfinite(lambda) || lambda < 0.f) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "lambda must be finite and >= 0");
+  if (iters < 0 || iters > 100000) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "iters must be in [0, 100000]");
+  const Plan* p = reinterpret_cast<const Plan*>(plan);
+  if (maxwell_status g = need_general(p)) return g;
+  Check ck(p);
+  ck.in(z, p->bytes_x(), "z");
+  ck.out(x, p->bytes_x(), "x");
+  ck.ws(ws, ws_bytes);
+  maxwell_status s = ck.finish();
+  if (s != MAXWELL_OK) return s;
+  HIP_TRY(run_tv_prox(*p, reinterpret_cast<const float2*>(z), lambda, iters, reinterpret_cast<float2*>(x), ws,
+                      (hipStream_t)stream),
+          "tv_prox");
+  return MAXWELL_OK;
+}
+
+maxwell_status maxwell_ball_project(maxwell_plan_t plan, const maxwell_complex64* w, const maxwell_complex64* y,
+                                    const float* eps_dev, maxwell_complex64* z, void* ws, size_t ws_bytes,
+                                    void* stream) {
+  if (!plan) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "plan is null");
+  const Plan* p = reinterpret_cast<const Plan*>(plan);
+  if (maxwell_status g = need_general(p)) return g;
+  Check ck(p);
+  ck.in(w, p->bytes_y(), "w");
+  ck.in(y, p->bytes_y(), "y");
+  ck.in(eps_dev, (size_t)p->J * sizeof(float), "eps_dev");
+  ck.out(z, p->bytes_y(), "z");
+  ck.ws(ws, ws_bytes);
+  maxwell_status s = ck.finish();
+  if (s != MAXWELL_OK) return s;
+  HIP_TRY(run_ball_project(*p, reinterpret_cast<const float2*>(w), reinterpret_cast<const float2*>(y), eps_dev,
+                           reinterpret_cast<float2*>(z), ws, (hipStream_t)stream),
+          "ball_project");
+  return MAXWELL_OK;
+}
+
+maxwell_status maxwell_sense_admm(maxwell_plan_t plan, const maxwell_complex64* S, const maxwell_complex64* y,
+                                  const float* eps_dev, float rho0, int32_t iters, int32_t cg_iters, int32_t tv_iters,
+                                  maxwell_complex64* p_out, double* hist_dev, void* ws, size_t ws_bytes,
+                                  void* stream) {
+  if (!plan) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "plan is null");
+  if (!std::isfinite(rho0) || !(rho0 > 0.f)) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "rho0 must be finite and > 0");
+  if (iters < 0 || iters > 100000 || cg_iters < 0 || cg_iters > 100000 || tv_iters < 0 || tv_iters > 100000)
+    return fail(MAXWELL_ERR_INVALID_ARGUMENT, "iteration counts must be in [0, 100000]");
+  const Plan* p = reinterpret_cast<const Plan*>(plan);
+  if (maxwell_status g = need_general(p)) return g;
+  Check ck(p);
+  ck.in(S, p->bytes_S(), "S");
+  ck.in(y, p->bytes_y(), "y");
+  ck.in(eps_dev, (size_t)p->J * sizeof(float), "eps_dev");
+  ck.out(p_out, p->bytes_x(), "p_out");
+  ck.out(hist_dev, (size_t)iters * 3 * sizeof(double), "hist_dev", false);
+  ck.ws(ws, ws_bytes);
+  maxwell_status s = ck.finish();
+  if (s != MAXWELL_OK) return s;
+  HIP_TRY(run_admm(*p, reinterpret_cast<const float2*>(S), reinterpret_cast<const float2*>(y), eps_dev, rho0, iters,
+                   cg_iters, tv_iters, reinterpret_cast<float2*>(p_out), hist_dev, ws, (hipStream_t)stream),
+          "sense_admm");
+  return MAXWELL_OK;
+}
+
 }  // extern "C"
 
 // ------------------------------------------------------------------ batches of slices

@@ -80,7 +80,7 @@ __global__ void adjoint_combine_kernel(const float2* __restrict__ S, float2* __r
   float s = alpha;
   if (scale_dev) s *= *scale_dev;
   for (int64_t n = blockIdx.x * (int64_t)NT + threadIdx.x; n < N; n += (int64_t)gridDim.x * NT) {
-    const float2 xn = x[n];
+    const float2 xn = want_h ? x[n] : make_float2(0.f, 0.f);
     float2 acc = make_float2(0.f, 0.f);
     for (int j = 0; j < J; ++j) {
       const float2 gv = g[(int64_t)j * N + n];

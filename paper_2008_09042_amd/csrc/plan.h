@@ -75,6 +75,7 @@ struct Plan {
   size_t off_S = 0, off_K = 0, off_tA = 0, off_tB = 0, off_E = 0, off_gemm = 0, off_part = 0;
   size_t off_T1 = 0, off_T3 = 0, off_xt = 0, off_Z = 0, off_gxp = 0, off_T3b = 0, off_T1b = 0, off_G = 0, off_Ys = 0, off_cpart = 0;
   size_t off_U = 0, off_cg = 0;  // Gauss-Newton / CG: JVP result; r, d, q, FP64 scalars
+  size_t off_admm = 0;           // SENSE / ADMM state (general path only)
   int part_blocks = 0;
 
   size_t bytes_x() const { return (size_t)N * 8; }
@@ -120,5 +121,15 @@ hipError_t run_normal(const Plan& p, const float2* x, const float2* c, const flo
                       float lam_x, float lam_c, float2* ox, float2* oc, void* ws, hipStream_t st);
 hipError_t run_cg(const Plan& p, const float2* x, const float2* c, const float2* bx, const float2* bc, float lam_x,
                   float lam_c, int iters, float2* dx, float2* dc, double* rr, void* ws, hipStream_t st);
+// SENSE with fixed maps S [J][N] and the constrained reconstruction (general path only)
+constexpr int ADMM_SCALARS = 8;
+hipError_t run_sense_encode(const Plan& p, const float2* S, const float2* x, float2* y, void* ws, hipStream_t st);
+hipError_t run_sense_adjoint(const Plan& p, const float2* S, const float2* y, float2* gx, void* ws, hipStream_t st);
+hipError_t run_sense_normal(const Plan& p, const float2* S, const float2* x, float2* out, void* ws, hipStream_t st);
+hipError_t run_tv_prox(const Plan& p, const float2* z, float lam, int iters, float2* x, void* ws, hipStream_t st);
+hipError_t run_ball_project(const Plan& p, const float2* w, const float2* y, const float* eps, float2* z, void* ws,
+                            hipStream_t st);
+hipError_t run_admm(const Plan& p, const float2* S, const float2* y, const float* eps, float rho0, int iters,
+                    int cg_iters, int tv_iters, float2* pimg, double* hist, void* ws, hipStream_t st);
 
 }  // namespace mx

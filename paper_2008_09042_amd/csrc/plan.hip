@@ -19,6 +19,7 @@
 #include "mode3.h"
 #include "nufft.h"
 #include "solver.h"
+#include "admm.h"
 #include "plan.h"
 
 namespace mx {
@@ -594,6 +595,15 @@ maxwell_status plan_build(Plan& p, const maxwell_plan_desc& d, const maxwell_bas
   const size_t V = ((size_t)p.N + (size_t)p.J * (size_t)p.K) * 8;
   p.off_U = off; off += al(JM);
   p.off_cg = off; off += 3 * al(V) + al(CG_SCALARS * sizeof(double)) + al(DOT_BLOCKS * sizeof(double));
+  if (!p.fused) {
+    // SENSE / ADMM (general path): 6 + ndim image-sized buffers (z0 twice, u0, two
+    // temporaries, the TV field d, the TV dual field P), 5 sample-sized ones (F S p, z_k
+    // twice, u_k, a temporary), the ball-projection partials and the ADMM scalars
+    const size_t NB = al((size_t)p.N * 8);
+    p.off_admm = off;
+    off += (6 + p.ndim) * NB + 5 * al(JM) + al((size_t)ball_part_doubles(p.J) * sizeof(double)) +
+           al(ADMM_SCALARS * sizeof(double));
+  }
   p.ws_bytes = off;
   return MAXWELL_OK;
 }
@@ -800,12 +810,9 @@ static hipError_t fused_adjoint(const Plan& p, const float2* x, const float2* c,
   return hipSuccess;
 }
 
-hipError_t run_encode(const Plan& p, const float2* x, const float2* c, float2* y, void* ws, hipStream_t st) {
-  if (p.fused) return fused_forward(p, x, c, nullptr, y, nullptr, ws, st, false);
-  float2* S = wsp<float2>(ws, p.off_S);
-  float2* Kb = wsp<float2>(ws, p.off_K);
-  hipError_t e = run_basis_apply(p, c, S, ws, st);
-  if (e != hipSuccess) return e;
+// y = F_s(S (.) x) for coil maps S [J][N] already in memory (general path)
+static hipError_t encode_maps(const Plan& p, const float2* S, const float2* x, float2* y, void* ws, hipStream_t st) {
+  hipError_t e;
   if (p.sampling == MAXWELL_NONCARTESIAN) {
     const NufftArgs na = nufft_args(p);
     float2* G = wsp<float2>(ws, p.off_G);
@@ -813,8 +820,17 @@ hipError_t run_encode(const Plan& p, const float2* x, const float2* c, float2* y
     if ((e = fft_grid(p, G, -1, st)) != hipSuccess) return e;
     return TIMED("nufft_degrid", degrid_launch(na, G, y, st));
   }
+  float2* Kb = wsp<float2>(ws, p.off_K);
   if ((e = fft_image(p, S, Kb, -1, x, st)) != hipSuccess) return e;
   return TIMED("gather", gather_launch(Kb, p.N, p.d_mask, p.M, p.J, y, st));
+}
+
+hipError_t run_encode(const Plan& p, const float2* x, const float2* c, float2* y, void* ws, hipStream_t st) {
+  if (p.fused) return fused_forward(p, x, c, nullptr, y, nullptr, ws, st, false);
+  float2* S = wsp<float2>(ws, p.off_S);
+  hipError_t e = run_basis_apply(p, c, S, ws, st);
+  if (e != hipSuccess) return e;
+  return encode_maps(p, S, x, y, ws, st);
 }
 
 hipError_t run_forward_loss(const Plan& p, const float2* x, const float2* c, const float2* y, float2* r,
@@ -833,6 +849,30 @@ hipError_t run_forward_loss(const Plan& p, const float2* x, const float2* c, con
   return hipSuccess;
 }
 
+// gx = s sum_j conj(S_j) (.) F_s^H y_j for coil maps S [J][N] (general path), s = alpha *
+// (*scale_dev); with want_h the K region of the workspace is left holding
+// h_j = s conj(x) (.) F_s^H y_j, the input of the basis adjoint.
+static hipError_t adjoint_maps(const Plan& p, const float2* S, const float2* x, const float2* y, float alpha,
+                               const float* scale_dev, float2* gx, bool want_h, void* ws, hipStream_t st) {
+  float2* Kb = wsp<float2>(ws, p.off_K);
+  hipError_t e;
+  if (p.sampling == MAXWELL_NONCARTESIAN) {
+    const NufftArgs na = nufft_args(p);
+    float2* G = wsp<float2>(ws, p.off_G);
+    if ((e = TIMED("nufft_spread", spread_launch(na, y, alpha, scale_dev, wsp<float2>(ws, p.off_Ys), G, st))) !=
+        hipSuccess)
+      return e;
+    if ((e = fft_grid(p, G, +1, st)) != hipSuccess) return e;
+    if ((e = TIMED("nufft_crop", crop_deapod_launch(na, G, Kb, st))) != hipSuccess) return e;
+    alpha = 1.0f;  // the scale was applied by the spread
+    scale_dev = nullptr;
+  } else {
+    if ((e = TIMED("scatter", scatter_launch(y, p.M, p.d_inv, p.N, p.J, Kb, st))) != hipSuccess) return e;
+    if ((e = fft_image(p, Kb, Kb, +1, nullptr, st)) != hipSuccess) return e;
+  }
+  return TIMED("adjoint_combine", adjoint_combine_launch(S, Kb, x, p.N, p.J, alpha, scale_dev, gx, want_h ? 1 : 0, st));
+}
+
 hipError_t run_adjoint(const Plan& p, const float2* x, const float2* c, const float2* y, float alpha,
                        const float* scale_dev, float2* gx, float2* gc, void* ws, hipStream_t st,
                        bool maps_ready, bool transfer) {
@@ -843,20 +883,7 @@ hipError_t run_adjoint(const Plan& p, const float2* x, const float2* c, const fl
   if (gx && !maps_ready) {
     if ((e = run_basis_apply(p, c, S, ws, st)) != hipSuccess) return e;
   }
-  if (p.sampling == MAXWELL_NONCARTESIAN) {
-    const NufftArgs na = nufft_args(p);
-    float2* G = wsp<float2>(ws, p.off_G);
-    if ((e = TIMED("nufft_spread", spread_launch(na, y, alpha, scale_dev, wsp<float2>(ws, p.off_Ys), G, st))) != hipSuccess) return e;
-    if ((e = fft_grid(p, G, +1, st)) != hipSuccess) return e;
-    if ((e = TIMED("nufft_crop", crop_deapod_launch(na, G, Kb, st))) != hipSuccess) return e;
-    alpha = 1.0f;  // the scale was applied by the spread
-    scale_dev = nullptr;
-  } else {
-    if ((e = TIMED("scatter", scatter_launch(y, p.M, p.d_inv, p.N, p.J, Kb, st))) != hipSuccess) return e;
-    if ((e = fft_image(p, Kb, Kb, +1, nullptr, st)) != hipSuccess) return e;
-  }
-  e = TIMED("adjoint_combine", adjoint_combine_launch(S, Kb, x, p.N, p.J, alpha, scale_dev, gx, gc ? 1 : 0, st));
-  if (e != hipSuccess) return e;
+  if ((e = adjoint_maps(p, S, x, y, alpha, scale_dev, gx, gc != nullptr, ws, st)) != hipSuccess) return e;
   if (gc) return run_basis_adjoint(p, Kb, gc, 1.0f, nullptr, ws, st);
   return hipSuccess;
 }
@@ -898,13 +925,16 @@ hipError_t run_normal(const Plan& p, const float2* x, const float2* c, const flo
   return TIMED("normal_axpy", caxpy_launch(oc, dc, lam_c, (int64_t)p.J * p.K, st));
 }
 
-// iters steps of conjugate gradients from zero on normal(dv) = b (the caller's bx, bc);
-// rr (optional, device, iters + 1 doubles) receives <r_k, r_k>.  All scalars stay on the
-// device (FP64); nothing synchronises with the host.
-hipError_t run_cg(const Plan& p, const float2* x, const float2* c, const float2* bx, const float2* bc, float lam_x,
-                  float lam_c, int iters, float2* dx, float2* dc, double* rr, void* ws, hipStream_t st) {
-  const int64_t N = p.N, JK = (int64_t)p.J * p.K, n = N + JK;
-  const size_t V = al((size_t)n * 8);
+// iters steps of conjugate gradients from zero on apply(dv) = b for a vector of two blocks
+// (n0 and n1 entries: the caller's x0 / x1, b0 / b1); rr (optional, device, iters + 1
+// doubles) receives <r_k, r_k>.  The work vectors r, d, q ([n0 | n1] each) and the FP64
+// scalars sit in the CG region of the workspace; nothing synchronises with the host.
+// apply(d0, d1, q0, q1) must not touch that region.
+template <class Apply>
+static hipError_t cg_loop(const Plan& p, Apply apply, int64_t n0, int64_t n1, const float2* b0, const float2* b1,
+                          int iters, float2* x0, float2* x1, double* rr, void* ws, hipStream_t st) {
+  const int64_t n = n0 + n1;
+  const size_t V = al(((size_t)p.N + (size_t)p.J * (size_t)p.K) * 8);
   char* base = wsp<char>(ws, p.off_cg);
   float2* r = reinterpret_cast<float2*>(base);
   float2* d = reinterpret_cast<float2*>(base + V);
@@ -913,19 +943,146 @@ hipError_t run_cg(const Plan& p, const float2* x, const float2* c, const float2*
   double *rho = sc, *rho_new = sc + 1, *dq = sc + 2, *alpha = sc + 3, *beta = sc + 4;
   double* part = reinterpret_cast<double*>(base + 3 * V + al(CG_SCALARS * sizeof(double)));
   hipError_t e;
-  if ((e = zero_split_launch(dx, dc, N, JK, st)) != hipSuccess) return e;
-  if ((e = copy_split_launch(r, r + N, bx, bc, N, JK, st)) != hipSuccess) return e;
-  if ((e = copy_split_launch(d, d + N, bx, bc, N, JK, st)) != hipSuccess) return e;
+  if ((e = zero_split_launch(x0, x1, n0, n1, st)) != hipSuccess) return e;
+  if ((e = copy_split_launch(r, r + n0, b0, b1, n0, n1, st)) != hipSuccess) return e;
+  if ((e = copy_split_launch(d, d + n0, b0, b1, n0, n1, st)) != hipSuccess) return e;
   if ((e = TIMED("cg_dot", dot_launch(r, r, n, part, rho, st))) != hipSuccess) return e;
   if (rr && (e = copy_scalar_launch(rho, rr, st)) != hipSuccess) return e;
   for (int k = 0; k < iters; ++k) {
-    if ((e = run_normal(p, x, c, d, d + N, lam_x, lam_c, q, q + N, ws, st)) != hipSuccess) return e;
+    if ((e = apply(d, d + n0, q, q + n0)) != hipSuccess) return e;
     if ((e = TIMED("cg_dot", dot_launch(d, q, n, part, dq, st))) != hipSuccess) return e;
     if ((e = cg_alpha_launch(rho, dq, alpha, st)) != hipSuccess) return e;
-    if ((e = TIMED("cg_update", cg_xr_launch(dx, dc, N, JK, r, d, q, alpha, st))) != hipSuccess) return e;
+    if ((e = TIMED("cg_update", cg_xr_launch(x0, x1, n0, n1, r, d, q, alpha, st))) != hipSuccess) return e;
     if ((e = TIMED("cg_dot", dot_launch(r, r, n, part, rho_new, st))) != hipSuccess) return e;
     if ((e = cg_beta_launch(rho, rho_new, beta, rr ? rr + k + 1 : nullptr, st)) != hipSuccess) return e;
     if ((e = TIMED("cg_update", cg_d_launch(d, r, n, beta, st))) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t run_cg(const Plan& p, const float2* x, const float2* c, const float2* bx, const float2* bc, float lam_x,
+                  float lam_c, int iters, float2* dx, float2* dc, double* rr, void* ws, hipStream_t st) {
+  auto apply = [&](const float2* d0, const float2* d1, float2* q0, float2* q1) {
+    return run_normal(p, x, c, d0, d1, lam_x, lam_c, q0, q1, ws, st);
+  };
+  return cg_loop(p, apply, p.N, (int64_t)p.J * p.K, bx, bc, iters, dx, dc, rr, ws, st);
+}
+
+// ---- SENSE with fixed maps and the constrained reconstruction (Sec. II-C)
+
+hipError_t run_sense_encode(const Plan& p, const float2* S, const float2* x, float2* y, void* ws, hipStream_t st) {
+  return encode_maps(p, S, x, y, ws, st);
+}
+
+hipError_t run_sense_adjoint(const Plan& p, const float2* S, const float2* y, float2* gx, void* ws, hipStream_t st) {
+  return adjoint_maps(p, S, nullptr, y, 1.0f, nullptr, gx, false, ws, st);
+}
+
+// out = x + sum_j conj(S_j) (.) F_s^H F_s (S_j (.) x), the p-update operator of the ADMM
+hipError_t run_sense_normal(const Plan& p, const float2* S, const float2* x, float2* out, void* ws, hipStream_t st) {
+  float2* u = wsp<float2>(ws, p.off_U);
+  hipError_t e = encode_maps(p, S, x, u, ws, st);
+  if (e != hipSuccess) return e;
+  if ((e = adjoint_maps(p, S, nullptr, u, 1.0f, nullptr, out, false, ws, st)) != hipSuccess) return e;
+  return TIMED("sense_axpy", caxpy_launch(out, x, 1.0f, p.N, st));
+}
+
+namespace {
+struct AdmmWs {
+  float2 *z0a, *z0b, *u0, *tN, *tN2, *dfield, *P;
+  float2 *Fp, *zka, *zkb, *uk, *tM;
+  double *part, *dist, *r2, *s2, *rho, *ufac;
+};
+AdmmWs admm_ws(const Plan& p, void* ws) {
+  AdmmWs a;
+  const size_t NB = al((size_t)p.N * 8), MB = al((size_t)p.J * (size_t)p.M * 8);
+  char* b = wsp<char>(ws, p.off_admm);
+  float2** nb[] = {&a.z0a, &a.z0b, &a.u0, &a.tN, &a.tN2, &a.dfield};
+  for (auto q : nb) { *q = reinterpret_cast<float2*>(b); b += NB; }
+  a.P = reinterpret_cast<float2*>(b);
+  b += p.ndim * NB;
+  float2** mb[] = {&a.Fp, &a.zka, &a.zkb, &a.uk, &a.tM};
+  for (auto q : mb) { *q = reinterpret_cast<float2*>(b); b += MB; }
+  a.part = reinterpret_cast<double*>(b);
+  a.dist = a.part + (size_t)ball_part_doubles(p.J) - p.J;
+  b += al((size_t)ball_part_doubles(p.J) * sizeof(double));
+  double* sc = reinterpret_cast<double*>(b);
+  a.r2 = sc; a.s2 = sc + 1; a.rho = sc + 2; a.ufac = sc + 3;
+  return a;
+}
+}  // namespace
+
+hipError_t run_tv_prox(const Plan& p, const float2* z, float lam, int iters, float2* x, void* ws, hipStream_t st) {
+  const AdmmWs a = admm_ws(p, ws);
+  return TIMED("tv_prox", tv_prox_launch(p.ndim, p.n, z, nullptr, lam, iters, a.P, a.dfield, x, st));
+}
+
+hipError_t run_ball_project(const Plan& p, const float2* w, const float2* y, const float* eps, float2* z, void* ws,
+                            hipStream_t st) {
+  const AdmmWs a = admm_ws(p, ws);
+  return TIMED("ball", ball_project_launch(w, y, eps, p.M, p.J, a.part, a.dist, z, st));
+}
+
+// The scaled ADMM iteration of Sec. II-C (z_0 prox, z_k ball projections, p-update by CG
+// on I + S^H F^H F S from the current p, dual update, residual-balanced rho).  p starts at
+// the SENSE combination S^H F^H y; z and u at zero.
+hipError_t run_admm(const Plan& p, const float2* S, const float2* y, const float* eps, float rho0, int iters,
+                    int cg_iters, int tv_iters, float2* pimg, double* hist, void* ws, hipStream_t st) {
+  AdmmWs a = admm_ws(p, ws);
+  const int64_t N = p.N, JM = (int64_t)p.J * p.M;
+  double* part = wsp<double>(ws, p.off_cg + 3 * al(((size_t)p.N + (size_t)p.J * (size_t)p.K) * 8) +
+                                     al(CG_SCALARS * sizeof(double)));
+  hipError_t e;
+  if ((e = run_sense_adjoint(p, S, y, pimg, ws, st)) != hipSuccess) return e;
+  if ((e = zero_split_launch(a.z0a, a.u0, N, N, st)) != hipSuccess) return e;
+  if ((e = zero_split_launch(a.zka, a.uk, JM, JM, st)) != hipSuccess) return e;
+  if ((e = set_scalar_launch(a.rho, (double)rho0, st)) != hipSuccess) return e;
+  if ((e = run_sense_encode(p, S, pimg, a.Fp, ws, st)) != hipSuccess) return e;
+  float2 *z0 = a.z0a, *z0p = a.z0b, *zk = a.zka, *zkp = a.zkb;
+  auto sense_op = [&](const float2* d0, const float2*, float2* q0, float2*) {
+    return run_sense_normal(p, S, d0, q0, ws, st);
+  };
+  for (int it = 0; it < iters; ++it) {
+    std::swap(z0, z0p);  // z0p, zkp: the previous iterates
+    std::swap(zk, zkp);
+    // z0 = prox_{TV / rho}(p + u0)
+    if ((e = lincomb_launch(a.tN, pimg, 1.f, a.u0, 1.f, N, st)) != hipSuccess) return e;
+    if ((e = TIMED("tv_prox", tv_prox_launch(p.ndim, p.n, a.tN, a.rho, 0.f, tv_iters, a.P, a.dfield, z0, st))) !=
+        hipSuccess)
+      return e;
+    // z_k = ball projection of F S p + u_k
+    if ((e = lincomb_launch(a.tM, a.Fp, 1.f, a.uk, 1.f, JM, st)) != hipSuccess) return e;
+    if ((e = TIMED("ball", ball_project_launch(a.tM, y, eps, p.M, p.J, a.part, a.dist, zk, st))) != hipSuccess)
+      return e;
+    // rhs = z0 - u0 + S^H F^H (z_k - u_k);  res = rhs - (I + S^H F^H F S) p
+    if ((e = lincomb_launch(a.tM, zk, 1.f, a.uk, -1.f, JM, st)) != hipSuccess) return e;
+    if ((e = run_sense_adjoint(p, S, a.tM, a.tN, ws, st)) != hipSuccess) return e;
+    if ((e = caxpy_launch(a.tN, z0, 1.f, N, st)) != hipSuccess) return e;
+    if ((e = caxpy_launch(a.tN, a.u0, -1.f, N, st)) != hipSuccess) return e;
+    if ((e = run_sense_normal(p, S, pimg, a.tN2, ws, st)) != hipSuccess) return e;
+    if ((e = caxpy_launch(a.tN, a.tN2, -1.f, N, st)) != hipSuccess) return e;
+    // p += CG(res)
+    if ((e = cg_loop(p, sense_op, N, 0, a.tN, nullptr, cg_iters, a.tN2, nullptr, nullptr, ws, st)) != hipSuccess)
+      return e;
+    if ((e = caxpy_launch(pimg, a.tN2, 1.f, N, st)) != hipSuccess) return e;
+    if ((e = run_sense_encode(p, S, pimg, a.Fp, ws, st)) != hipSuccess) return e;
+    // u += A p - z
+    if ((e = caxpy_launch(a.u0, pimg, 1.f, N, st)) != hipSuccess) return e;
+    if ((e = caxpy_launch(a.u0, z0, -1.f, N, st)) != hipSuccess) return e;
+    if ((e = caxpy_launch(a.uk, a.Fp, 1.f, JM, st)) != hipSuccess) return e;
+    if ((e = caxpy_launch(a.uk, zk, -1.f, JM, st)) != hipSuccess) return e;
+    // primal residual ||A p - z||^2 and dual residual ||A^H (z - z_prev)||^2 (before rho)
+    if ((e = lincomb_launch(a.tN, pimg, 1.f, z0, -1.f, N, st)) != hipSuccess) return e;
+    if ((e = lincomb_launch(a.tM, a.Fp, 1.f, zk, -1.f, JM, st)) != hipSuccess) return e;
+    if ((e = dot2_launch(a.tN, a.tM, N, JM, part, a.r2, st)) != hipSuccess) return e;
+    if ((e = lincomb_launch(a.tM, zk, 1.f, zkp, -1.f, JM, st)) != hipSuccess) return e;
+    if ((e = run_sense_adjoint(p, S, a.tM, a.tN, ws, st)) != hipSuccess) return e;
+    if ((e = caxpy_launch(a.tN, z0, 1.f, N, st)) != hipSuccess) return e;
+    if ((e = caxpy_launch(a.tN, z0p, -1.f, N, st)) != hipSuccess) return e;
+    if ((e = dot_launch(a.tN, a.tN, N, part, a.s2, st)) != hipSuccess) return e;
+    if ((e = admm_rho_launch(a.r2, a.s2, a.rho, a.ufac, hist ? hist + 3 * it : nullptr, st)) != hipSuccess) return e;
+    if ((e = scale_dev_launch(a.u0, N, a.ufac, st)) != hipSuccess) return e;
+    if ((e = scale_dev_launch(a.uk, JM, a.ufac, st)) != hipSuccess) return e;
   }
   return hipSuccess;
 }

@@ -17,6 +17,9 @@ hipError_t copy_split_launch(float2* d0, float2* d1, const float2* s0, const flo
 hipError_t zero_split_launch(float2* d0, float2* d1, int64_t n0, int64_t n1, hipStream_t st);
 // *out = Re <a, b> over n entries in FP64; part holds DOT_BLOCKS doubles
 hipError_t dot_launch(const float2* a, const float2* b, int64_t n, double* part, double* out, hipStream_t st);
+// *out = ||(a0 | a1)||^2 in FP64 over the two blocks
+hipError_t dot2_launch(const float2* a0, const float2* a1, int64_t n0, int64_t n1, double* part, double* out,
+                       hipStream_t st);
 // *alpha = *rho / *dq (0 if *dq == 0)
 hipError_t cg_alpha_launch(const double* rho, const double* dq, double* alpha, hipStream_t st);
 // (x0 | x1) += alpha d, r -= alpha q

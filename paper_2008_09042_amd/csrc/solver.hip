@@ -187,6 +187,14 @@ hipError_t dot_launch(const float2* a, const float2* b, int64_t n, double* part,
   return hipGetLastError();
 }
 
+hipError_t dot2_launch(const float2* a0, const float2* a1, int64_t n0, int64_t n1, double* part, double* out,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(dot_partial_kernel, dim3(DOT_BLOCKS), dim3(NT), 0, st, CSplit{a0, a1, n0, n1},
+                     CSplit{a0, a1, n0, n1}, part);
+  hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(NT), 0, st, part, DOT_BLOCKS, out);
+  return hipGetLastError();
+}
+
 hipError_t cg_alpha_launch(const double* rho, const double* dq, double* alpha, hipStream_t st) {
   hipLaunchKernelGGL(cg_alpha_kernel, dim3(1), dim3(64), 0, st, rho, dq, alpha);
   return hipGetLastError();

@@ -299,6 +299,59 @@ class MaxwellPlan:
                                     float(lambda_c), int(iters), _ptr(dx), _ptr(dc), _ptr(rr), ws, nb, _stream()))
         return dx, dc, rr
 
+    # ---- SENSE with fixed maps and the constrained reconstruction (Sec. II-C; general path)
+    def sense_encode(self, S, x):
+        S = self._in(S, (self.J, self.N), "S")
+        x = self._in(x, self.dims, "x")
+        y = self._new((self.J, self.M))
+        ws, nb = self._wsargs()
+        L.check(self.lib.maxwell_sense_encode(self.handle, _ptr(S), _ptr(x), _ptr(y), ws, nb, _stream()))
+        return y
+
+    def sense_adjoint(self, S, y):
+        S = self._in(S, (self.J, self.N), "S")
+        y = self._in(y, (self.J, self.M), "y")
+        gx = self._new(self.dims)
+        ws, nb = self._wsargs()
+        L.check(self.lib.maxwell_sense_adjoint(self.handle, _ptr(S), _ptr(y), _ptr(gx), ws, nb, _stream()))
+        return gx
+
+    def sense_normal(self, S, x):
+        S = self._in(S, (self.J, self.N), "S")
+        x = self._in(x, self.dims, "x")
+        out = self._new(self.dims)
+        ws, nb = self._wsargs()
+        L.check(self.lib.maxwell_sense_normal(self.handle, _ptr(S), _ptr(x), _ptr(out), ws, nb, _stream()))
+        return out
+
+    def tv_prox(self, z, lam: float, iters: int):
+        z = self._in(z, self.dims, "z")
+        x = self._new(self.dims)
+        ws, nb = self._wsargs()
+        L.check(self.lib.maxwell_tv_prox(self.handle, _ptr(z), float(lam), int(iters), _ptr(x), ws, nb, _stream()))
+        return x
+
+    def ball_project(self, w, y, eps):
+        w = self._in(w, (self.J, self.M), "w")
+        y = self._in(y, (self.J, self.M), "y")
+        eps = torch.as_tensor(eps, dtype=torch.float32, device=self.device).contiguous()
+        z = self._new((self.J, self.M))
+        ws, nb = self._wsargs()
+        L.check(self.lib.maxwell_ball_project(self.handle, _ptr(w), _ptr(y), _ptr(eps), _ptr(z), ws, nb, _stream()))
+        return z
+
+    def sense_admm(self, S, y, eps, rho0: float, iters: int, cg_iters: int, tv_iters: int):
+        """-> (p, hist) with hist[k] = (rho, primal residual, dual residual) (FP64)."""
+        S = self._in(S, (self.J, self.N), "S")
+        y = self._in(y, (self.J, self.M), "y")
+        eps = torch.as_tensor(eps, dtype=torch.float32, device=self.device).contiguous()
+        p = self._new(self.dims)
+        hist = torch.empty((int(iters), 3), dtype=torch.float64, device=self.device)
+        ws, nb = self._wsargs()
+        L.check(self.lib.maxwell_sense_admm(self.handle, _ptr(S), _ptr(y), _ptr(eps), float(rho0), int(iters),
+                                            int(cg_iters), int(tv_iters), _ptr(p), _ptr(hist), ws, nb, _stream()))
+        return p, hist
+
 
 class MaxwellBatch:
     """Gradients of many independent slices (each a MaxwellPlan) in one call.

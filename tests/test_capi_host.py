@@ -205,6 +205,12 @@ def test_null_arguments(lib):
     assert lib.maxwell_normal(None, z, z, z, z, 0.1, 0.1, z, z, None, 0, None) == L.MAXWELL_ERR_INVALID_ARGUMENT
     assert (lib.maxwell_cg(None, z, z, z, z, 0.1, 0.1, 3, z, z, None, None, 0, None)
             == L.MAXWELL_ERR_INVALID_ARGUMENT)
+    for f in ("maxwell_sense_encode", "maxwell_sense_adjoint", "maxwell_sense_normal"):
+        assert getattr(lib, f)(None, z, z, z, None, 0, None) == L.MAXWELL_ERR_INVALID_ARGUMENT
+    assert lib.maxwell_tv_prox(None, z, 0.1, 5, z, None, 0, None) == L.MAXWELL_ERR_INVALID_ARGUMENT
+    assert lib.maxwell_ball_project(None, z, z, z, z, None, 0, None) == L.MAXWELL_ERR_INVALID_ARGUMENT
+    assert (lib.maxwell_sense_admm(None, z, z, z, 1.0, 3, 3, 3, z, None, None, 0, None)
+            == L.MAXWELL_ERR_INVALID_ARGUMENT)
     assert lib.maxwell_plan_set_timing(None, 1) == L.MAXWELL_ERR_INVALID_ARGUMENT
     assert "plan is null" in lib.maxwell_last_error().decode()
 

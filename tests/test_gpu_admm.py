@@ -1,0 +1,120 @@
+"""GPU parity of SENSE with fixed maps and the constrained reconstruction (maxwell_sense_*,
+maxwell_tv_prox, maxwell_ball_project, maxwell_sense_admm) against the FP64 oracle
+(oracle.admm) on the same seeded, complex64-rounded inputs.
+
+Bars (relative L2, FP64 reference):
+* SENSE encode / adjoint / normal operator: one FP32 operator application, 1e-5.
+* Ball projection: elementwise after an FP64 distance, 1e-6.
+* TV prox, 30 Chambolle steps: each step is nonexpansive in the dual field, so FP32 rounding
+  (about 6e-8 per operation) accumulates at most linearly: 1e-5.
+* ADMM, 8 outer steps of (20 TV steps, 6 CG steps): the composition of the above; the bar is
+  ten times the operator bar per outer step bounded at 1e-3 for the image, and the rho
+  sequence (a discrete decision per step) must match exactly.
+Cases: Cartesian 2D, radial 2D (KB NUFFT), Cartesian 3D; maps B c_k scaled to order-one
+sensitivities.  A fused-path plan is refused with MAXWELL_ERR_UNSUPPORTED.
+"""
+import numpy as np
+import pytest
+import torch
+
+from _common import Case, c64, rel
+from oracle.admm import admm, ball_project, sense_adjoint, sense_encode, sense_normal, tv_prox
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+CASES = {
+    "cart2d_48x40_J4": dict(seed=301, dims=(48, 40), J=4, K=9, basis="dense", frac=0.4),
+    "radial_32x24_J3": dict(seed=302, dims=(32, 24), J=3, K=9, mask="radial", spokes=9),
+    "cart3d_16x12x10_J3": dict(seed=303, dims=(16, 12, 10), ranks=(5, 4, 3), J=3, K=7, basis="tucker",
+                               mask="random", frac=0.4),
+}
+_cache = {}
+
+
+def get_case(name):
+    if name not in _cache:
+        cs = Case(**CASES[name])
+        S = cs.op.coil_maps(cs.c0)
+        cs.S = c64(S / np.sqrt(np.mean(np.sum(np.abs(S) ** 2, axis=0))))
+        cs.ys = c64(sense_encode(cs.op, cs.S, cs.x_true))
+        rng = np.random.default_rng(5)
+        cs.ys = c64(cs.ys + 0.02 * np.linalg.norm(cs.ys) / np.sqrt(cs.ys.size)
+                    * (rng.normal(size=cs.ys.shape) + 1j * rng.normal(size=cs.ys.shape)))
+        cs.eps = np.float32(0.1 * np.linalg.norm(cs.ys, axis=1)).astype(np.float64)
+        _cache[name] = cs
+    return _cache[name]
+
+
+def T(a):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a).astype(np.complex64))).to(DEV)
+
+
+def H(t):
+    return t.detach().cpu().numpy().astype(np.complex128)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a visible ROCm GPU"
+    yield
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_sense_operators(name):
+    cs = get_case(name)
+    print(f"[case] {name} sense operators", flush=True)
+    plan = cs.plan("fp32")
+    S, x = T(cs.S), T(cs.x0)
+    assert rel(H(plan.sense_encode(S, x)), sense_encode(cs.op, cs.S, cs.x0)) <= 1e-5
+    assert rel(H(plan.sense_adjoint(S, T(cs.ys))), sense_adjoint(cs.op, cs.S, cs.ys)) <= 1e-5
+    assert rel(H(plan.sense_normal(S, x)), sense_normal(cs.op, cs.S, cs.x0)) <= 1e-5
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_ball_and_tv_prox(name):
+    cs = get_case(name)
+    print(f"[case] {name} ball / tv prox", flush=True)
+    plan = cs.plan("fp32")
+    rng = np.random.default_rng(6)
+    w = c64(cs.ys + 0.05 * (rng.normal(size=cs.ys.shape) + 1j * rng.normal(size=cs.ys.shape)))
+    eps = cs.eps.copy()
+    eps[0] = 1e3  # one coil inside its ball
+    z = H(plan.ball_project(T(w), T(cs.ys), eps))
+    assert rel(z, ball_project(w, cs.ys, eps)) <= 1e-6
+    for lam in (0.0, 0.05, 0.3):
+        xg = H(plan.tv_prox(T(cs.x0), lam, 30))
+        xr = tv_prox(cs.x0, lam, 30)
+        assert rel(xg, xr) <= 1e-5, lam
+
+
+# rho0 = 0.02 and 50 make rho adapt (doubling, halving) in the first steps
+@pytest.mark.parametrize("name,rho0", [(n, 1.0) for n in CASES] + [("cart2d_48x40_J4", 0.02),
+                                                                     ("cart2d_48x40_J4", 50.0)])
+def test_sense_admm(name, rho0):
+    cs = get_case(name)
+    print(f"[case] {name} admm rho0 {rho0}", flush=True)
+    plan = cs.plan("fp32")
+    p, hist = plan.sense_admm(T(cs.S), T(cs.ys), cs.eps, rho0, 8, 6, 20)
+    torch.cuda.synchronize()
+    p_ref, hist_ref = admm(cs.op, cs.S, cs.ys, cs.eps, rho0, 8, 6, 20)
+    hist = hist.cpu().numpy()
+    err = rel(H(p).reshape(-1), p_ref)
+    print(f"[case] image error {err:.3g}; rho {hist[:, 0]} vs {hist_ref[:, 0]}", flush=True)
+    assert np.array_equal(hist[:, 0], hist_ref[:, 0])
+    assert err <= 1e-3
+    assert np.max(np.abs(hist[:, 1:] - hist_ref[:, 1:]) / hist_ref[:, 1:]) <= 1e-3
+    # repeatable bit for bit
+    p2, _ = plan.sense_admm(T(cs.S), T(cs.ys), cs.eps, rho0, 8, 6, 20)
+    assert torch.equal(p, p2)
+
+
+def test_fused_plan_is_refused():
+    from paper_2008_09042_amd import _lib as L
+    cs = Case(seed=304, dims=(32, 32, 16), ranks=(5, 5, 4), J=2, K=5, basis="tucker", mask="lines3d", frac=0.3)
+    plan = cs.plan("fp32")
+    assert plan.path == "fused-tucker-lines"
+    with pytest.raises(L.MaxwellError, match="general path") as ei:
+        plan.tv_prox(T(cs.x0), 0.1, 3)
+    assert ei.value.status == L.MAXWELL_ERR_UNSUPPORTED
