@@ -41,10 +41,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", default="bf16_split", choices=["bf16_split", "fp32"])
-    ap.add_argument("--workload", default="cart3d", choices=["cart3d", "batch", "gn"],
+    ap.add_argument("--workload", default="cart3d", choices=["cart3d", "batch", "gn", "admm"],
                     help="cart3d: the headline 128^3 Tucker workload; batch: 64 uneven 2D slices with "
                          "dense bases through one captured graph; gn: conjugate-gradient steps of the "
-                         "Gauss-Newton normal equations on the 128^3 Tucker workload")
+                         "Gauss-Newton normal equations on the 128^3 Tucker workload; admm: constrained "
+                         "TV-SENSE reconstruction steps on the 2D 256^2 workload")
     ap.add_argument("--cg-iters", type=int, default=10, help="gn workload: CG steps per timed call")
     ap.add_argument("--branches", type=int, default=4, help="batch workload: concurrent branches")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -336,6 +337,58 @@ def bench_gn(args, torch):
     print(json.dumps(out), flush=True)
 
 
+def bench_admm(args, torch):
+    """Constrained TV-SENSE reconstruction (Sec. II-C) on the 2D Cartesian 256^2 workload
+    (32 coils, variable-density mask): maxwell_sense_admm with 10 outer steps per call, each
+    20 TV steps and 5 CG steps.  Coil maps: the workload's basis times its coefficients,
+    scaled to order-one sensitivities.  Prints one JSON line."""
+    from paper_2008_09042_amd.encoding import MaxwellPlan
+    from synth import CONFIGS, make_problem
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    p = make_problem(2, **CONFIGS[2])
+    log(f"[bench] inputs generated in {time.time() - t0:.1f}s: dims {p.dims} J {p.J} K {p.K} M {p.M}")
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(np.asarray(a).astype(np.complex64))).to(dev)  # noqa: E731
+    plan = MaxwellPlan(p.dims, p.J, B=T(p.B), mask_idx=p.mask_idx, precision="fp32", device=dev)
+    S = plan.basis_apply(T(p.c_true))
+    S = (S / torch.sqrt(torch.mean(torch.sum(S.abs() ** 2, dim=0)))).contiguous()
+    y = plan.sense_encode(S, T(p.x_true))
+    noise = T(p.noise)
+    y = (y + noise * (0.01 * torch.linalg.vector_norm(y) / torch.linalg.vector_norm(noise))).contiguous()
+    eps = (1.05 * 0.01 * torch.linalg.vector_norm(y, dim=1)).float()
+    outer, cg_it, tv_it = 10, 5, 20
+    ms, wall = time_steps(lambda: plan.sense_admm(S, y, eps, 1.0, outer, cg_it, tv_it), args.steps, args.warmup,
+                          torch)
+    plan.set_timing(True)
+    plan.sense_admm(S, y, eps, 1.0, outer, cg_it, tv_it)
+    torch.cuda.synchronize()
+    kt = plan.timing()
+    plan.set_timing(False)
+    log(f"[bench] admm: {ms:.3f} ms per {outer} ADMM steps ({ms / outer:.3f} ms per step)")
+    log("[bench] admm kernel timing (us per launch, launches per ADMM step): " +
+        ", ".join(f"{k} {1000 * t / n:.1f}x{n / outer:g}" for k, (n, t) in kt.items() if n))
+    # every ADMM step applies F_s S (and its adjoint) cg_it + 4 times per coil
+    applies = outer * (cg_it + 4) * p.J
+    out = {
+        "metric": "constrained TV-SENSE ADMM steps/sec (Sec. II-C), x coils",
+        "value": outer * p.J * 1000.0 / ms,
+        "unit": "coil-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded phantom, smooth dense basis maps, variable-density mask; no datasets)",
+        "config": {"workload": "admm_cart2d_256_j32", "admm_steps_per_call": outer, "cg_steps": cg_it,
+                   "tv_steps": tv_it, "step": "maxwell_sense_admm call"},
+        "coil_operator_applications_per_s": applies * 1000.0 / ms,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.traffic_from:
@@ -352,6 +405,9 @@ def main():
         return
     if args.workload == "gn":
         bench_gn(args, torch)
+        return
+    if args.workload == "admm":
+        bench_admm(args, torch)
         return
 
     dev = torch.device("cuda:0")

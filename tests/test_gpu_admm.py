@@ -98,7 +98,8 @@ def test_sense_admm(name, rho0):
     plan = cs.plan("fp32")
     p, hist = plan.sense_admm(T(cs.S), T(cs.ys), cs.eps, rho0, 8, 6, 20)
     torch.cuda.synchronize()
-    p_ref, hist_ref = admm(cs.op, cs.S, cs.ys, cs.eps, rho0, 8, 6, 20)
+    # the library takes rho0 as a float: the oracle starts from the same value
+    p_ref, hist_ref = admm(cs.op, cs.S, cs.ys, cs.eps, float(np.float32(rho0)), 8, 6, 20)
     hist = hist.cpu().numpy()
     err = rel(H(p).reshape(-1), p_ref)
     print(f"[case] image error {err:.3g}; rho {hist[:, 0]} vs {hist_ref[:, 0]}", flush=True)
