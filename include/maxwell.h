@@ -247,6 +247,21 @@ maxwell_status maxwell_cg(maxwell_plan_t plan, const maxwell_complex64* x, const
                           float lambda_c, int32_t iters, maxwell_complex64* dx, maxwell_complex64* dc,
                           double* rr_dev, void* ws, size_t ws_bytes, void* stream);
 
+/* Extra bilinear terms (multi-map; Sec. IV-A, forward model extensions): nmaps in [1, 64]
+ * map sets, each with its own image x_i and coefficients c_i,
+ *     y_j = F_s( sum_i (B c_{i,j}) (.) x_i ) = sum_i E(x_i, c_i)_j
+ * x: nmaps x [N], c: nmaps x [J][K] (contiguous), y: [J][M].
+ * maxwell_multi_encode: y.
+ * maxwell_multi_grad: loss = sum w |y_model - y|^2 (FP64) and, for every map set,
+ *   (gx_i, gc_i) = 2 J_i^H (w (.) r), r = y_model - y; gx (nmaps x [N]), gc (nmaps x [J][K])
+ *   and loss_dev may each be NULL.  B c_i is recomputed for the adjoints.             */
+maxwell_status maxwell_multi_encode(maxwell_plan_t plan, int32_t nmaps, const maxwell_complex64* x,
+                                    const maxwell_complex64* c, maxwell_complex64* y, void* ws, size_t ws_bytes,
+                                    void* stream);
+maxwell_status maxwell_multi_grad(maxwell_plan_t plan, int32_t nmaps, const maxwell_complex64* x,
+                                  const maxwell_complex64* c, const maxwell_complex64* y, maxwell_complex64* gx,
+                                  maxwell_complex64* gc, double* loss_dev, void* ws, size_t ws_bytes, void* stream);
+
 /* SENSE with fixed maps and the constrained density reconstruction (Sec. II-C): with the
  * coil maps S [J][N] (device) fixed, minimise TV(p) subject to ||y_k - F_s S_k p|| <= eps_k.
  * General-path plans only (maxwell_plan_path() == "general"; a fused plan gives

@@ -159,3 +159,21 @@ class Oracle:
         f = float(np.sum(wr[None, :] * np.abs(r) ** 2))
         gx, gc = self.adjoint(x, c, 2.0 * wr[None, :] * r)
         return f, gx, gc
+
+
+# ---- extra bilinear terms (multi-map), Sec. IV-A "Forward model extensions"
+def multi_encode(op: Oracle, xs, cs) -> np.ndarray:
+    """y_j = F_s( sum_m (B c_{m,j}) (.) x_m ) = sum_m E(x_m, c_m): one image and one set of
+    coefficients per map set (F_s is linear)."""
+    return sum(op.encode(x, c) for x, c in zip(xs, cs))
+
+
+def multi_loss_and_grad(op: Oracle, xs, cs, y, w=None):
+    """f = sum_j sum_m w_m |sum_maps E(x_i, c_i)_jm - y_jm|^2 and the packed real gradient
+    2 J_i^H (w (.) r) with respect to every (x_i, c_i)."""
+    y = np.asarray(y, dtype=np.complex128)
+    r = multi_encode(op, xs, cs) - y
+    wr = np.ones(r.shape[1]) if w is None else np.asarray(w, dtype=np.float64)
+    f = float(np.sum(wr[None, :] * np.abs(r) ** 2))
+    grads = [op.adjoint(x, c, 2.0 * wr[None, :] * r) for x, c in zip(xs, cs)]
+    return f, [g[0] for g in grads], [g[1] for g in grads]

@@ -32,7 +32,7 @@ EXPORTS = [
     "maxwell_last_error", "maxwell_version", "maxwell_batch_create", "maxwell_batch_workspace_size",
     "maxwell_batch_grad", "maxwell_batch_destroy", "maxwell_jvp", "maxwell_normal", "maxwell_cg",
     "maxwell_sense_encode", "maxwell_sense_adjoint", "maxwell_sense_normal", "maxwell_tv_prox",
-    "maxwell_ball_project", "maxwell_sense_admm",
+    "maxwell_ball_project", "maxwell_sense_admm", "maxwell_multi_encode", "maxwell_multi_grad",
     "maxwell_plan_set_timing", "maxwell_plan_timing",
 ]
 
@@ -134,6 +134,10 @@ def load(path: str = LIB_PATH):
     lib.maxwell_sense_admm.argtypes = [vp, vp, vp, vp, ctypes.c_float, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_int32, vp, vp, vp, sz, vp]
     lib.maxwell_sense_admm.restype = st
+    lib.maxwell_multi_encode.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, sz, vp]
+    lib.maxwell_multi_encode.restype = st
+    lib.maxwell_multi_grad.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.maxwell_multi_grad.restype = st
     lib.maxwell_plan_set_timing.argtypes = [vp, ctypes.c_int]
     lib.maxwell_plan_set_timing.restype = st
     lib.maxwell_plan_timing.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int),

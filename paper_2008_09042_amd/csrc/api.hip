@@ -510,6 +510,50 @@ maxwell_status maxwell_cg(maxwell_plan_t plan, const maxwell_complex64* x, const
   return MAXWELL_OK;
 }
 
+// ---- extra bilinear terms (multi-map)
+
+maxwell_status maxwell_multi_encode(maxwell_plan_t plan, int32_t nmaps, const maxwell_complex64* x,
+                                    const maxwell_complex64* c, maxwell_complex64* y, void* ws, size_t ws_bytes,
+                                    void* stream) {
+  if (!plan) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "plan is null");
+  if (nmaps < 1 || nmaps > 64) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "nmaps must be in [1, 64]");
+  const Plan* p = reinterpret_cast<const Plan*>(plan);
+  Check ck(p);
+  ck.in(x, nmaps * p->bytes_x(), "x");
+  ck.in(c, nmaps * p->bytes_c(), "c");
+  ck.out(y, p->bytes_y(), "y");
+  ck.ws(ws, ws_bytes);
+  maxwell_status s = ck.finish();
+  if (s != MAXWELL_OK) return s;
+  HIP_TRY(run_multi_encode(*p, nmaps, reinterpret_cast<const float2*>(x), reinterpret_cast<const float2*>(c),
+                           reinterpret_cast<float2*>(y), ws, (hipStream_t)stream),
+          "multi_encode");
+  return MAXWELL_OK;
+}
+
+maxwell_status maxwell_multi_grad(maxwell_plan_t plan, int32_t nmaps, const maxwell_complex64* x,
+                                  const maxwell_complex64* c, const maxwell_complex64* y, maxwell_complex64* gx,
+                                  maxwell_complex64* gc, double* loss_dev, void* ws, size_t ws_bytes, void* stream) {
+  if (!plan) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "plan is null");
+  if (nmaps < 1 || nmaps > 64) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "nmaps must be in [1, 64]");
+  const Plan* p = reinterpret_cast<const Plan*>(plan);
+  Check ck(p);
+  ck.in(x, nmaps * p->bytes_x(), "x");
+  ck.in(c, nmaps * p->bytes_c(), "c");
+  ck.in(y, p->bytes_y(), "y");
+  ck.out(gx, nmaps * p->bytes_x(), "gx", false);
+  ck.out(gc, nmaps * p->bytes_c(), "gc", false);
+  ck.out(loss_dev, sizeof(double), "loss_dev", false);
+  ck.ws(ws, ws_bytes);
+  maxwell_status s = ck.finish();
+  if (s != MAXWELL_OK) return s;
+  HIP_TRY(run_multi_grad(*p, nmaps, reinterpret_cast<const float2*>(x), reinterpret_cast<const float2*>(c),
+                         reinterpret_cast<const float2*>(y), reinterpret_cast<float2*>(gx),
+                         reinterpret_cast<float2*>(gc), loss_dev, ws, (hipStream_t)stream),
+          "multi_grad");
+  return MAXWELL_OK;
+}
+
 // ---- SENSE with fixed maps and the constrained reconstruction (general path)
 
 static maxwell_status need_general(const Plan* p) {

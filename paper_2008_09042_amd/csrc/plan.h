@@ -121,6 +121,11 @@ hipError_t run_normal(const Plan& p, const float2* x, const float2* c, const flo
                       float lam_x, float lam_c, float2* ox, float2* oc, void* ws, hipStream_t st);
 hipError_t run_cg(const Plan& p, const float2* x, const float2* c, const float2* bx, const float2* bc, float lam_x,
                   float lam_c, int iters, float2* dx, float2* dc, double* rr, void* ws, hipStream_t st);
+// extra bilinear terms: n map sets, x n x [N], c n x [J][K]
+hipError_t run_multi_encode(const Plan& p, int n, const float2* x, const float2* c, float2* y, void* ws,
+                            hipStream_t st);
+hipError_t run_multi_grad(const Plan& p, int n, const float2* x, const float2* c, const float2* y, float2* gx,
+                          float2* gc, double* loss, void* ws, hipStream_t st);
 // SENSE with fixed maps S [J][N] and the constrained reconstruction (general path only)
 constexpr int ADMM_SCALARS = 8;
 hipError_t run_sense_encode(const Plan& p, const float2* S, const float2* x, float2* y, void* ws, hipStream_t st);

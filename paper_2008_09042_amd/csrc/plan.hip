@@ -1087,4 +1087,40 @@ hipError_t run_admm(const Plan& p, const float2* S, const float2* y, const float
   return hipSuccess;
 }
 
+// ---- extra bilinear terms (multi-map, Sec. IV-A): y = sum_i E(x_i, c_i)
+
+// y = sum over the n map sets of E(x_i, c_i); x: n x [N], c: n x [J][K]
+hipError_t run_multi_encode(const Plan& p, int n, const float2* x, const float2* c, float2* y, void* ws,
+                            hipStream_t st) {
+  const int64_t JK = (int64_t)p.J * p.K, JM = (int64_t)p.J * p.M;
+  hipError_t e = run_encode(p, x, c, y, ws, st);
+  float2* E = wsp<float2>(ws, p.off_E);
+  for (int i = 1; i < n && e == hipSuccess; ++i) {
+    if ((e = run_encode(p, x + (int64_t)i * p.N, c + (int64_t)i * JK, E, ws, st)) != hipSuccess) return e;
+    e = TIMED("multi_sum", caxpy_launch(y, E, 1.0f, JM, st));
+  }
+  return e;
+}
+
+// f = sum w |sum_i E(x_i, c_i) - y|^2 and (gx_i, gc_i) = 2 J_i^H (w (.) r) for every map set
+hipError_t run_multi_grad(const Plan& p, int n, const float2* x, const float2* c, const float2* y, float2* gx,
+                          float2* gc, double* loss, void* ws, hipStream_t st) {
+  const int64_t JK = (int64_t)p.J * p.K;
+  float2* r = wsp<float2>(ws, p.off_U);
+  double* part = wsp<double>(ws, p.off_part);
+  hipError_t e = run_multi_encode(p, n, x, c, r, ws, st);
+  if (e != hipSuccess) return e;
+  if ((e = TIMED("residual", residual_launch(r, y, p.d_w, p.M, p.J, r, part, st))) != hipSuccess) return e;
+  if (loss && (e = TIMED("reduce_loss", reduce_loss_launch(part, residual_blocks((int64_t)p.J * p.M), loss, st))) !=
+                  hipSuccess)
+    return e;
+  if (!gx && !gc) return hipSuccess;
+  for (int i = 0; i < n; ++i)
+    if ((e = run_adjoint(p, x + (int64_t)i * p.N, c + (int64_t)i * JK, r, 2.0f, nullptr,
+                         gx ? gx + (int64_t)i * p.N : nullptr, gc ? gc + (int64_t)i * JK : nullptr, ws, st, false,
+                         false)) != hipSuccess)
+      return e;
+  return hipSuccess;
+}
+
 }  // namespace mx

@@ -299,6 +299,31 @@ class MaxwellPlan:
                                     float(lambda_c), int(iters), _ptr(dx), _ptr(dc), _ptr(rr), ws, nb, _stream()))
         return dx, dc, rr
 
+    # ---- extra bilinear terms (multi-map)
+    def multi_encode(self, xs, cs):
+        """sum_i E(x_i, c_i); xs: [n, *dims], cs: [n, J, K]."""
+        n = int(xs.shape[0])
+        xs = self._in(xs, (n,) + tuple(self.dims), "xs")
+        cs = self._in(cs, (n, self.J, self.K), "cs")
+        y = self._new((self.J, self.M))
+        ws, nb = self._wsargs()
+        L.check(self.lib.maxwell_multi_encode(self.handle, n, _ptr(xs), _ptr(cs), _ptr(y), ws, nb, _stream()))
+        return y
+
+    def multi_grad(self, xs, cs, y):
+        """(loss, gxs [n, *dims], gcs [n, J, K]) of sum w |sum_i E(x_i, c_i) - y|^2."""
+        n = int(xs.shape[0])
+        xs = self._in(xs, (n,) + tuple(self.dims), "xs")
+        cs = self._in(cs, (n, self.J, self.K), "cs")
+        y = self._in(y, (self.J, self.M), "y")
+        gx = self._new((n,) + tuple(self.dims))
+        gc = self._new((n, self.J, self.K))
+        loss = torch.empty((), dtype=torch.float64, device=self.device)
+        ws, nb = self._wsargs()
+        L.check(self.lib.maxwell_multi_grad(self.handle, n, _ptr(xs), _ptr(cs), _ptr(y), _ptr(gx), _ptr(gc),
+                                            _ptr(loss), ws, nb, _stream()))
+        return loss, gx, gc
+
     # ---- SENSE with fixed maps and the constrained reconstruction (Sec. II-C; general path)
     def sense_encode(self, S, x):
         S = self._in(S, (self.J, self.N), "S")

@@ -211,6 +211,8 @@ def test_null_arguments(lib):
     assert lib.maxwell_ball_project(None, z, z, z, z, None, 0, None) == L.MAXWELL_ERR_INVALID_ARGUMENT
     assert (lib.maxwell_sense_admm(None, z, z, z, 1.0, 3, 3, 3, z, None, None, 0, None)
             == L.MAXWELL_ERR_INVALID_ARGUMENT)
+    assert lib.maxwell_multi_encode(None, 2, z, z, z, None, 0, None) == L.MAXWELL_ERR_INVALID_ARGUMENT
+    assert lib.maxwell_multi_grad(None, 2, z, z, z, z, z, None, None, 0, None) == L.MAXWELL_ERR_INVALID_ARGUMENT
     assert lib.maxwell_plan_set_timing(None, 1) == L.MAXWELL_ERR_INVALID_ARGUMENT
     assert "plan is null" in lib.maxwell_last_error().decode()
 

@@ -1,5 +1,6 @@
-"""GPU parity of the Gauss-Newton step (maxwell_jvp, maxwell_normal, maxwell_cg) against the
-FP64 oracle (oracle.solver) on the same seeded, complex64-rounded inputs.
+"""GPU parity of the Gauss-Newton step (maxwell_jvp, maxwell_normal, maxwell_cg) and of the
+multi-map operator (maxwell_multi_encode, maxwell_multi_grad) against the FP64 oracle
+(oracle.solver, oracle.encoding) on the same seeded, complex64-rounded inputs.
 
 * JVP and normal operator: one operator application each, so the operator bar applies
   (relative L2, FP32 <= 1e-5, BF16-split <= 1e-4).
@@ -139,3 +140,34 @@ def test_cg_graph_replays():
         assert torch.equal(dx, ref[0]) and torch.equal(dc, ref[1]) and torch.equal(rr, ref[2]), f"replay {k}"
         again = plan.cg(x, c, bx, bc, *cs.lam, ITERS)  # eager work between replays
         assert torch.equal(again[0], ref[0])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16_split"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_multi_map(name, prec):
+    """Two map sets (extra bilinear terms): encode, loss and every map set's gradient at the
+    operator bar; one map set equals maxwell_grad bit for bit."""
+    from oracle.encoding import multi_encode, multi_loss_and_grad
+    cs = get_case(name)
+    print(f"[case] {name} {prec} multi-map", flush=True)
+    plan = cs.plan(prec)
+    rng = np.random.default_rng(17)
+    x2 = c64(0.5 * (rng.normal(size=cs.dims) + 1j * rng.normal(size=cs.dims)))
+    c2 = c64(rng.normal(size=(cs.J, cs.K)) + 1j * rng.normal(size=(cs.J, cs.K)))
+    xs = T(np.stack([cs.x0, x2]))
+    cc = T(np.stack([cs.c0, c2]))
+    y = T(cs.y)
+    E = H(plan.multi_encode(xs, cc))
+    assert rel(E, multi_encode(cs.op, [cs.x0, x2], [cs.c0, c2])) <= TOL[prec]
+    loss, gx, gc = plan.multi_grad(xs, cc, y)
+    f_ref, gx_ref, gc_ref = multi_loss_and_grad(cs.op, [cs.x0, x2], [cs.c0, c2], cs.y, cs.w)
+    assert abs(float(loss.item()) - f_ref) / f_ref <= TOL[prec]
+    for i in range(2):
+        assert rel(H(gx[i]), gx_ref[i]) <= TOL[prec], i
+        assert rel(H(gc[i]), gc_ref[i]) <= TOL[prec], i
+    # a single map set: the same loss and gradient as the plain call (to the operator bar;
+    # the multi-map residual goes through the sample-order path)
+    l1, gx1, gc1 = plan.multi_grad(xs[:1].contiguous(), cc[:1].contiguous(), y)
+    l0, gx0, gc0 = plan.grad(T(cs.x0), T(cs.c0), y)
+    assert abs(float(l1.item()) - float(l0.item())) <= TOL[prec] * float(l0.item())
+    assert rel(H(gx1[0]), H(gx0)) <= TOL[prec] and rel(H(gc1[0]), H(gc0)) <= TOL[prec]

@@ -420,3 +420,30 @@ def test_config_generators_shapes():
     assert traj.shape == (32768, 2) and np.max(np.abs(traj)) <= 128
     w = ramp_dcf(traj, (256, 256), 512)
     assert abs(w.max() - 1.0) < 1e-15 and w.min() > 0
+
+
+# ---------------------------------------------------------------- multi-map (extra bilinear terms)
+def test_multi_map_reduces_and_matches_finite_differences():
+    from oracle.encoding import multi_encode, multi_loss_and_grad
+    op, x, c = small_cartesian_dense()
+    rng = np.random.default_rng(21)
+    x2 = complex_normal(rng, x.shape)
+    c2 = coefficients(rng, *c.shape)
+    y = complex_normal(rng, (c.shape[0], op.mask_idx.size))
+    # one map set is the plain operator; a zero second image changes nothing
+    assert rel(multi_encode(op, [x], [c]), op.encode(x, c)) < 1e-14
+    assert rel(multi_encode(op, [x, 0 * x2], [c, c2]), op.encode(x, c)) < 1e-14
+    # the loss is quadratic along a direction in (x, x2) with c, c2 fixed: exact central difference
+    f, gxs, gcs = multi_loss_and_grad(op, [x, x2], [c, c2], y)
+    d1, d2 = complex_normal(rng, x.shape), complex_normal(rng, x.shape)
+    h = 0.3
+    fp = multi_loss_and_grad(op, [x + h * d1, x2 + h * d2], [c, c2], y)[0]
+    fm = multi_loss_and_grad(op, [x - h * d1, x2 - h * d2], [c, c2], y)[0]
+    dd = np.real(np.vdot(gxs[0], d1) + np.vdot(gxs[1], d2))
+    assert abs((fp - fm) / (2 * h) - dd) < 1e-10 * abs(dd)
+    # and along the coefficients of the second map set
+    e2 = complex_normal(rng, c.shape)
+    fp = multi_loss_and_grad(op, [x, x2], [c, c2 + h * e2], y)[0]
+    fm = multi_loss_and_grad(op, [x, x2], [c, c2 - h * e2], y)[0]
+    dd = np.real(np.vdot(gcs[1], e2))
+    assert abs((fp - fm) / (2 * h) - dd) < 1e-10 * abs(dd)
