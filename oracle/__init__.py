@@ -16,9 +16,11 @@ nufft     Kaiser-Bessel NUFFT type 2 / type 1 and the exact NDFT (Sec. III-B, ra
 encoding  encoding operator, Jacobian adjoint, JVP, loss and gradient (Sec. II-B)
 solver    Gauss-Newton normal operator and conjugate gradients of the IRGN step (Sec. II-B, Eq. (6))
 admm      SENSE with fixed maps, ball projection, TV prox and the constrained ADMM (Sec. II-C)
+compress  accuracy-controlled Tucker compression of a dense basis by ST-HOSVD (Sec. II-E)
 
 Every public function is pinned by ``tests/test_oracle_pins.py`` and
-``tests/test_oracle_solver.py`` and ``tests/test_oracle_admm.py`` against
+``tests/test_oracle_solver.py``, ``tests/test_oracle_admm.py`` and
+``tests/test_oracle_compress.py`` against
 brute force, closed forms, invariants or library special cases.
 """
 from .dft import centred_dft, centred_idft  # noqa: F401
