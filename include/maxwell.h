@@ -247,6 +247,23 @@ maxwell_status maxwell_cg(maxwell_plan_t plan, const maxwell_complex64* x, const
                           float lambda_c, int32_t iters, maxwell_complex64* dx, maxwell_complex64* dc,
                           double* rr_dev, void* ws, size_t ws_bytes, void* stream);
 
+/* Accuracy-controlled Tucker compression of a dense basis (Sec. II-E, Eqs. (truncated_tucker)
+ * and (tucker_error)): B [N][K] (device), N = dims[0] dims[1] dims[2], read as the tensor
+ * T [n0][n1][n2][K]; the sequentially truncated HOSVD keeps, for modes 0, 1, 2 in turn, the
+ * fewest left singular vectors of the current tensor's mode unfolding whose discarded squared
+ * singular values sum to at most eps^2 ||T||^2 / 3 (Gram matrices and their Jacobi
+ * eigendecomposition in FP64, mode products on the matrix cores in FP32), so that
+ * ||T - core x1 U0 x2 U1 x3 U2|| <= eps ||T||.  Outputs (device, caller-owned):
+ *   U0, U1, U2  [dims[m]][ranks[m]] row-major, each with capacity dims[m]^2 entries;
+ *   core        [ranks[0]][ranks[1]][ranks[2]][K], capacity N K entries;
+ * and on the host ranks[3] and dropped[3] (the discarded squared norm per mode; may be
+ * NULL).  The result is the input of a Tucker basis descriptor.  Preprocessing, not a
+ * compute call: it allocates device memory, synchronises with the host and frees before
+ * returning.  eps in [0, 1); dims in [1, 4096].                                        */
+maxwell_status maxwell_tucker_compress(const int64_t* dims, int64_t K, const maxwell_complex64* B, float eps,
+                                       maxwell_complex64* U0, maxwell_complex64* U1, maxwell_complex64* U2,
+                                       maxwell_complex64* core, int64_t* ranks, double* dropped, void* stream);
+
 /* Extra bilinear terms (multi-map; Sec. IV-A, forward model extensions): nmaps in [1, 64]
  * map sets, each with its own image x_i and coefficients c_i,
  *     y_j = F_s( sum_i (B c_{i,j}) (.) x_i ) = sum_i E(x_i, c_i)_j

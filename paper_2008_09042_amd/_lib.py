@@ -33,6 +33,7 @@ EXPORTS = [
     "maxwell_batch_grad", "maxwell_batch_destroy", "maxwell_jvp", "maxwell_normal", "maxwell_cg",
     "maxwell_sense_encode", "maxwell_sense_adjoint", "maxwell_sense_normal", "maxwell_tv_prox",
     "maxwell_ball_project", "maxwell_sense_admm", "maxwell_multi_encode", "maxwell_multi_grad",
+    "maxwell_tucker_compress",
     "maxwell_plan_set_timing", "maxwell_plan_timing",
 ]
 
@@ -138,6 +139,9 @@ def load(path: str = LIB_PATH):
     lib.maxwell_multi_encode.restype = st
     lib.maxwell_multi_grad.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.maxwell_multi_grad.restype = st
+    lib.maxwell_tucker_compress.argtypes = [ctypes.POINTER(i64), i64, vp, ctypes.c_float, vp, vp, vp, vp,
+                                            ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double), vp]
+    lib.maxwell_tucker_compress.restype = st
     lib.maxwell_plan_set_timing.argtypes = [vp, ctypes.c_int]
     lib.maxwell_plan_set_timing.restype = st
     lib.maxwell_plan_timing.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int),

@@ -12,6 +12,7 @@
 #include "../../include/maxwell.h"
 #include "common.h"
 #include "plan.h"
+#include "compress.h"
 
 using namespace mx;
 
@@ -507,6 +508,30 @@ maxwell_status maxwell_cg(maxwell_plan_t plan, const maxwell_complex64* x, const
                  reinterpret_cast<const float2*>(bx), reinterpret_cast<const float2*>(bc), lambda_x, lambda_c, iters,
                  reinterpret_cast<float2*>(dx), reinterpret_cast<float2*>(dc), rr_dev, ws, (hipStream_t)stream),
           "cg");
+  return MAXWELL_OK;
+}
+
+// ---- accuracy-controlled Tucker compression of a dense basis
+
+maxwell_status maxwell_tucker_compress(const int64_t* dims, int64_t K, const maxwell_complex64* B, float eps,
+                                       maxwell_complex64* U0, maxwell_complex64* U1, maxwell_complex64* U2,
+                                       maxwell_complex64* core, int64_t* ranks, double* dropped, void* stream) {
+  if (!dims || !B || !U0 || !U1 || !U2 || !core || !ranks)
+    return fail(MAXWELL_ERR_INVALID_ARGUMENT, "null argument (dims, B, U0..U2, core and ranks are required)");
+  for (int m = 0; m < 3; ++m)
+    if (dims[m] < 1 || dims[m] > 4096) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "dims must be in [1, 4096]");
+  if (K < 1) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "K must be >= 1");
+  if (!std::isfinite(eps) || eps < 0.f || eps >= 1.f) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "eps must be in [0, 1)");
+  const void* ptrs[] = {B, U0, U1, U2, core};
+  for (const void* q : ptrs)
+    if (!aligned8(q)) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "device buffers must be 8-byte aligned");
+  float2* U[3] = {reinterpret_cast<float2*>(U0), reinterpret_cast<float2*>(U1), reinterpret_cast<float2*>(U2)};
+  double drop[3] = {0.0, 0.0, 0.0};
+  HIP_TRY(tucker_compress_run(dims, K, reinterpret_cast<const float2*>(B), (double)eps, U,
+                              reinterpret_cast<float2*>(core), ranks, drop, (hipStream_t)stream),
+          "tucker_compress");
+  if (dropped)
+    for (int m = 0; m < 3; ++m) dropped[m] = drop[m];
   return MAXWELL_OK;
 }
 

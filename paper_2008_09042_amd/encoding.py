@@ -521,3 +521,29 @@ class MaxwellDataFidelity(torch.autograd.Function):
         gx, gc = ctx.plan.adjoint_transfer(x, c, t, alpha=2.0, scale=scale, want_gx=ctx.needs_input_grad[0],
                                            want_gc=ctx.needs_input_grad[1])
         return gx, gc, None, None
+
+
+def tucker_compress(B: torch.Tensor, dims, eps: float):
+    """Accuracy-controlled Tucker form of a dense basis B [N, K] (complex64, on a GPU):
+    -> ([U0, U1, U2] with U_m [n_m, r_m], core [r0, r1, r2, K], ranks, dropped squared norms)."""
+    lib = L.load()
+    if not isinstance(B, torch.Tensor) or B.dtype != torch.complex64 or B.dim() != 2:
+        raise ValueError("B must be a complex64 [N, K] tensor")
+    dims = [int(d) for d in dims]
+    N, K = int(B.shape[0]), int(B.shape[1])
+    if int(np.prod(dims)) != N:
+        raise ValueError("prod(dims) must equal B.shape[0]")
+    B = B.contiguous()
+    dev = B.device
+    U = [torch.empty((d, d), dtype=torch.complex64, device=dev) for d in dims]
+    core = torch.empty((N * K,), dtype=torch.complex64, device=dev)
+    d64 = (ctypes.c_int64 * 3)(*dims)
+    ranks = (ctypes.c_int64 * 3)()
+    dropped = (ctypes.c_double * 3)()
+    with torch.cuda.device(dev):
+        L.check(lib.maxwell_tucker_compress(d64, K, _ptr(B), float(eps), _ptr(U[0]), _ptr(U[1]), _ptr(U[2]),
+                                            _ptr(core), ranks, dropped, _stream()))
+    r = [int(v) for v in ranks]
+    Us = [U[m].reshape(-1)[: dims[m] * r[m]].reshape(dims[m], r[m]).clone() for m in range(3)]
+    core = core[: r[0] * r[1] * r[2] * K].reshape(r[0], r[1], r[2], K).clone()
+    return Us, core, r, [float(v) for v in dropped]

@@ -213,6 +213,12 @@ def test_null_arguments(lib):
             == L.MAXWELL_ERR_INVALID_ARGUMENT)
     assert lib.maxwell_multi_encode(None, 2, z, z, z, None, 0, None) == L.MAXWELL_ERR_INVALID_ARGUMENT
     assert lib.maxwell_multi_grad(None, 2, z, z, z, z, z, None, None, 0, None) == L.MAXWELL_ERR_INVALID_ARGUMENT
+    r3 = (ctypes.c_int64 * 3)()
+    d3 = (ctypes.c_int64 * 3)(4, 4, 4)
+    assert lib.maxwell_tucker_compress(None, 2, z, 0.1, z, z, z, z, r3, None, None) == L.MAXWELL_ERR_INVALID_ARGUMENT
+    assert lib.maxwell_tucker_compress(d3, 2, z, 1.5, z, z, z, z, r3, None, None) == L.MAXWELL_ERR_INVALID_ARGUMENT
+    assert "eps" in lib.maxwell_last_error().decode()
+    assert lib.maxwell_tucker_compress(d3, 0, z, 0.1, z, z, z, z, r3, None, None) == L.MAXWELL_ERR_INVALID_ARGUMENT
     assert lib.maxwell_plan_set_timing(None, 1) == L.MAXWELL_ERR_INVALID_ARGUMENT
     assert "plan is null" in lib.maxwell_last_error().decode()
 
