@@ -333,7 +333,8 @@ maxwell_status maxwell_sense_admm(maxwell_plan_t plan, const maxwell_complex64* 
  *   Creates the branches' streams (default priority) and events; the only batch call that
  *   allocates.
  * maxwell_batch_workspace_size: bytes of the batch workspace (the slices' plan workspaces
- *   side by side, each 256-byte aligned).
+ *   side by side, each 256-byte aligned, and, when every plan has the same J and K, the
+ *   per-frame partials of maxwell_batch_grad_shared).
  * maxwell_batch_grad: maxwell_grad of every slice i on its own buffers x[i], c[i], y[i] ->
  *   gx[i], gc[i], loss_dev[i] (x, c, y: host arrays of n device pointers; gx, gc, loss_dev:
  *   host arrays of n device pointers or NULL, entries may be NULL).  Every slice is
@@ -351,6 +352,20 @@ maxwell_status maxwell_batch_grad(maxwell_batch_t batch, const maxwell_complex64
                                   maxwell_complex64* const* gc, double* const* loss_dev, void* ws,
                                   size_t ws_bytes, void* stream);
 void maxwell_batch_destroy(maxwell_batch_t batch);
+
+/* Frames with shared coefficients (dynamic or multi-contrast data, the remark after the
+ * constrained problem of Sec. II-C and the end of Sec. II-B: per frame t its own image x_t and
+ * sampling (one plan per frame), one coefficient set c shared by all frames):
+ *     loss = sum_t f_t(x_t, c),   gx_t = grad of f_t in x_t,   gc = sum_t (grad of f_t in c)
+ * every frame as in maxwell_grad, then gc and the loss summed over the frames in frame order
+ * (fixed order, no atomics).  The batch's plans must share J and K (else
+ * MAXWELL_ERR_INVALID_ARGUMENT); its workspace size already includes the per-frame
+ * partials.  x, y, gx: host arrays of n device pointers (gx may be NULL); c, gc, loss_dev:
+ * single device pointers (gc, loss_dev may be NULL).  Capturable like maxwell_batch_grad. */
+maxwell_status maxwell_batch_grad_shared(maxwell_batch_t batch, const maxwell_complex64* const* x,
+                                         const maxwell_complex64* c, const maxwell_complex64* const* y,
+                                         maxwell_complex64* const* gx, maxwell_complex64* gc, double* loss_dev,
+                                         void* ws, size_t ws_bytes, void* stream);
 
 /* Kernel timing for benchmarks.  enable != 0 clears the plan's records and
  * starts recording: every kernel launch made by a compute call of this plan is

@@ -33,7 +33,7 @@ EXPORTS = [
     "maxwell_batch_grad", "maxwell_batch_destroy", "maxwell_jvp", "maxwell_normal", "maxwell_cg",
     "maxwell_sense_encode", "maxwell_sense_adjoint", "maxwell_sense_normal", "maxwell_tv_prox",
     "maxwell_ball_project", "maxwell_sense_admm", "maxwell_multi_encode", "maxwell_multi_grad",
-    "maxwell_tucker_compress",
+    "maxwell_tucker_compress", "maxwell_batch_grad_shared",
     "maxwell_plan_set_timing", "maxwell_plan_timing",
 ]
 
@@ -114,6 +114,8 @@ def load(path: str = LIB_PATH):
     pa = ctypes.POINTER(vp)
     lib.maxwell_batch_grad.argtypes = [vp, pa, pa, pa, pa, pa, pa, vp, sz, vp]
     lib.maxwell_batch_grad.restype = st
+    lib.maxwell_batch_grad_shared.argtypes = [vp, pa, vp, pa, pa, vp, vp, vp, sz, vp]
+    lib.maxwell_batch_grad_shared.restype = st
     lib.maxwell_batch_destroy.argtypes = [vp]
     lib.maxwell_batch_destroy.restype = None
     lib.maxwell_grad.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]

@@ -13,6 +13,7 @@
 #include "common.h"
 #include "plan.h"
 #include "compress.h"
+#include "solver.h"
 
 using namespace mx;
 
@@ -719,6 +720,9 @@ struct Batch {
   std::vector<const Plan*> plans;
   std::vector<size_t> off;   // workspace offset of each slice (256-aligned)
   size_t ws_total = 0;
+  // shared-coefficient form (frames of one J x K): per-frame gc and loss after the slices
+  bool same_jk = false;
+  size_t off_gc = 0, off_loss = 0, gc_stride = 0;
   std::vector<hipStream_t> streams;
   std::vector<hipEvent_t> join;
   hipEvent_t fork = nullptr;
@@ -762,6 +766,16 @@ maxwell_status maxwell_batch_create(const maxwell_plan_t* plans, int32_t n, int3
     b->plans.push_back(p);
     b->off.push_back(off);
     off += align256(p->ws_bytes);
+  }
+  b->same_jk = true;
+  for (int i = 1; i < n; ++i)
+    b->same_jk = b->same_jk && b->plans[i]->J == b->plans[0]->J && b->plans[i]->K == b->plans[0]->K;
+  if (b->same_jk) {
+    b->gc_stride = (size_t)b->plans[0]->J * (size_t)b->plans[0]->K;
+    b->off_gc = off;
+    off += align256(b->gc_stride * (size_t)n * 8);
+    b->off_loss = off;
+    off += align256((size_t)n * sizeof(double));
   }
   b->ws_total = off;
   // longest-processing-time assignment of slices to branches
@@ -841,6 +855,53 @@ maxwell_status maxwell_batch_grad(maxwell_batch_t batch, const maxwell_complex64
     HIP_TRY(hipEventRecord(b->join[k], bs), "batch_grad join");
     HIP_TRY(hipStreamWaitEvent(st, b->join[k], 0), "batch_grad join");
   }
+  return MAXWELL_OK;
+}
+
+maxwell_status maxwell_batch_grad_shared(maxwell_batch_t batch, const maxwell_complex64* const* x,
+                                         const maxwell_complex64* c, const maxwell_complex64* const* y,
+                                         maxwell_complex64* const* gx, maxwell_complex64* gc, double* loss_dev,
+                                         void* ws, size_t ws_bytes, void* stream) {
+  if (!batch) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "batch is null");
+  Batch* b = reinterpret_cast<Batch*>(batch);
+  if (!b->same_jk) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "shared coefficients need plans with one J and one K");
+  if (!x || !c || !y) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "x, c and y are required");
+  if (ws_bytes < b->ws_total) return fail(MAXWELL_ERR_WORKSPACE_TOO_SMALL, "workspace smaller than maxwell_batch_workspace_size");
+  if (!ws) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "workspace is null");
+  if (reinterpret_cast<uintptr_t>(ws) & 255u) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "workspace must be 256-byte aligned");
+  const int n = (int)b->plans.size();
+  char* w = static_cast<char*>(ws);
+  float2* gcp = reinterpret_cast<float2*>(w + b->off_gc);
+  double* lp = reinterpret_cast<double*>(w + b->off_loss);
+  for (int i = 0; i < n; ++i) {
+    const Plan* p = b->plans[i];
+    Check ck(p);
+    ck.in(x[i], p->bytes_x(), "x");
+    ck.in(c, p->bytes_c(), "c");
+    ck.in(y[i], p->bytes_y(), "y");
+    ck.out(gx ? gx[i] : nullptr, p->bytes_x(), "gx", false);
+    ck.out(gc, p->bytes_c(), "gc", false);
+    ck.out(loss_dev, sizeof(double), "loss_dev", false);
+    ck.ws(w + b->off[i], ws_bytes - b->off[i]);
+    const maxwell_status s = ck.finish();
+    if (s != MAXWELL_OK) return fail(s, "frame " + std::to_string(i) + ": " + g_last_error);
+  }
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipEventRecord(b->fork, st), "batch_grad_shared fork");
+  for (size_t k = 0; k < b->streams.size(); ++k) {
+    hipStream_t bs = b->streams[k];
+    HIP_TRY(hipStreamWaitEvent(bs, b->fork, 0), "batch_grad_shared fork");
+    for (int i : b->branch[k])
+      HIP_TRY(run_grad(*b->plans[i], reinterpret_cast<const float2*>(x[i]), reinterpret_cast<const float2*>(c),
+                       reinterpret_cast<const float2*>(y[i]), gx ? reinterpret_cast<float2*>(gx[i]) : nullptr,
+                       gc ? gcp + (size_t)i * b->gc_stride : nullptr, loss_dev ? lp + i : nullptr, w + b->off[i], bs),
+              "batch_grad_shared");
+    HIP_TRY(hipEventRecord(b->join[k], bs), "batch_grad_shared join");
+    HIP_TRY(hipStreamWaitEvent(st, b->join[k], 0), "batch_grad_shared join");
+  }
+  if (gc) HIP_TRY(sum_rows_launch(reinterpret_cast<float2*>(gc), gcp, n, (int64_t)b->gc_stride, (int64_t)b->gc_stride, st),
+                  "batch_grad_shared sum");
+  if (loss_dev) HIP_TRY(sum_doubles_launch(loss_dev, lp, n, 1, st), "batch_grad_shared sum");
   return MAXWELL_OK;
 }
 

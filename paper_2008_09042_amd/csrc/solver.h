@@ -30,5 +30,8 @@ hipError_t cg_beta_launch(double* rho, const double* rho_new, double* beta, doub
 // d = r + beta d
 hipError_t cg_d_launch(float2* d, const float2* r, int64_t n, const double* beta, hipStream_t st);
 hipError_t copy_scalar_launch(const double* src, double* dst, hipStream_t st);
+// out = sum over i < n of part[i * stride .. + len) in index order; the same for FP64 scalars
+hipError_t sum_rows_launch(float2* out, const float2* part, int n, int64_t stride, int64_t len, hipStream_t st);
+hipError_t sum_doubles_launch(double* out, const double* part, int n, int64_t stride, hipStream_t st);
 
 }  // namespace mx

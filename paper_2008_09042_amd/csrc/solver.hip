@@ -152,6 +152,27 @@ __global__ void copy_scalar_kernel(const double* __restrict__ src, double* __res
   if (threadIdx.x == 0) *dst = *src;
 }
 
+// out[e] = sum_i part[i * stride + e] in index order (plain FP32 adds)
+__global__ void sum_rows_kernel(float2* __restrict__ out, const float2* __restrict__ part, int n, int64_t stride,
+                                int64_t len) {
+  for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < len; e += (int64_t)gridDim.x * NT) {
+    float2 s = part[e];
+    for (int i = 1; i < n; ++i) {
+      const float2 v = part[(int64_t)i * stride + e];
+      s.x = s.x + v.x;
+      s.y = s.y + v.y;
+    }
+    out[e] = s;
+  }
+}
+
+__global__ void sum_doubles_kernel(double* __restrict__ out, const double* __restrict__ part, int n, int64_t stride) {
+  if (threadIdx.x != 0) return;
+  double s = part[0];
+  for (int i = 1; i < n; ++i) s += part[(int64_t)i * stride];
+  *out = s;
+}
+
 }  // namespace
 
 hipError_t caxpy_launch(float2* y, const float2* x, float a, int64_t n, hipStream_t st) {
@@ -215,6 +236,18 @@ hipError_t cg_beta_launch(double* rho, const double* rho_new, double* beta, doub
 hipError_t cg_d_launch(float2* d, const float2* r, int64_t n, const double* beta, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(cg_d_kernel, dim3(grid_for(n)), dim3(NT), 0, st, d, r, n, beta);
+  return hipGetLastError();
+}
+
+hipError_t sum_rows_launch(float2* out, const float2* part, int n, int64_t stride, int64_t len, hipStream_t st) {
+  if (len <= 0 || n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(sum_rows_kernel, dim3(grid_for(len)), dim3(NT), 0, st, out, part, n, stride, len);
+  return hipGetLastError();
+}
+
+hipError_t sum_doubles_launch(double* out, const double* part, int n, int64_t stride, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(sum_doubles_kernel, dim3(1), dim3(64), 0, st, out, part, n, stride);
   return hipGetLastError();
 }
 

@@ -449,6 +449,23 @@ class MaxwellBatch:
         self._call(xs, cs, ys, loss, gx, gc)
         return loss, gx, gc
 
+    def grad_shared(self, xs, c, ys):
+        """Frames sharing one coefficient set c: (summed loss FP64, [gx_t], gc summed over the
+        frames in frame order) via maxwell_batch_grad_shared."""
+        xs, cs, ys = self._inputs(xs, [c] * len(self.plans), ys)
+        c = cs[0]
+        p0 = self.plans[0]
+        gx = [p._new(p.dims) for p in self.plans]
+        gc = p0._new((p0.J, p0.K))
+        loss = torch.zeros((), dtype=torch.float64, device=self.device)
+        n = len(self.plans)
+        P = ctypes.c_void_p * n
+        ptrs = lambda ts: P(*[t.data_ptr() for t in ts])  # noqa: E731
+        L.check(self.lib.maxwell_batch_grad_shared(self.handle, ptrs(xs), _ptr(c), ptrs(ys), ptrs(gx), _ptr(gc),
+                                                   _ptr(loss), ctypes.c_void_p(self.ws.data_ptr()), self.ws_bytes,
+                                                   _stream()))
+        return loss, gx, gc
+
     def capture(self, xs, cs, ys):
         """Record the batch gradient on these buffers into one graph."""
         given = list(xs) + list(cs) + list(ys)

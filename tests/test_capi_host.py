@@ -196,6 +196,8 @@ def test_null_arguments(lib):
     pz = (ctypes.c_void_p * 1)(FAKE)
     assert (lib.maxwell_batch_grad(None, pz, pz, pz, None, None, None, None, 0, None)
             == L.MAXWELL_ERR_INVALID_ARGUMENT)
+    assert (lib.maxwell_batch_grad_shared(None, pz, z, pz, None, None, None, None, 0, None)
+            == L.MAXWELL_ERR_INVALID_ARGUMENT)
     lib.maxwell_batch_destroy(None)  # no-op
     assert (lib.maxwell_adjoint_transfer(None, z, z, z, 1.0, None, z, z, None, 0, None)
             == L.MAXWELL_ERR_INVALID_ARGUMENT)

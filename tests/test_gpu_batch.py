@@ -112,3 +112,40 @@ def test_batch_graph_replays():
     for a, b in zip([new_ref[0]] + new_ref[1] + new_ref[2], [out[0]] + out[1] + out[2]):
         assert torch.equal(a, b)
     assert not torch.equal(new_ref[0], ref[0])
+
+
+def test_frames_with_shared_coefficients():
+    """Dynamic / multi-contrast frames: one plan per frame (own mask), own images, one shared
+    coefficient set.  Summed loss, per-frame gx and summed gc against the oracle, and equal
+    bit for bit to the frames' own maxwell_grad calls summed in frame order."""
+    from paper_2008_09042_amd.encoding import MaxwellBatch, MaxwellPlan
+    from _common import Case
+    print("[case] 3 frames sharing coefficients", flush=True)
+    frames = [Case(seed=61 + t, dims=(48, 40), J=4, K=9, basis="dense", frac=0.3, weights=True) for t in range(3)]
+    B = frames[0].B
+    for f in frames[1:]:  # one basis for all frames; each frame keeps its own mask, image, data
+        f.B = B
+        f.op = Oracle(f.dims, B=B, mask_idx=f.mask)
+    c = frames[0].c0
+    plans = [MaxwellPlan(f.dims, f.J, B=T(B), mask_idx=f.mask, weights=f.w, precision="fp32", device=DEV)
+             for f in frames]
+    batch = MaxwellBatch(plans, branches=2)
+    xs = [T(f.x0) for f in frames]
+    ys = [T(f.y) for f in frames]
+    loss, gx, gc = batch.grad_shared(xs, T(c), ys)
+    torch.cuda.synchronize()
+    f_ref, gc_ref, gx_ref = 0.0, 0.0, []
+    for f in frames:
+        fr, gxr, gcr = f.op.loss_and_grad(f.x0, c, f.y, f.w)
+        f_ref += fr
+        gc_ref = gc_ref + gcr
+        gx_ref.append(gxr)
+    assert abs(float(loss.item()) - f_ref) / f_ref <= TOL["fp32"]
+    assert rel(H(gc), gc_ref) <= TOL["fp32"]
+    for t in range(3):
+        assert rel(H(gx[t]), gx_ref[t]) <= TOL["fp32"]
+    singles = [p.grad(x, T(c), y) for p, x, y in zip(plans, xs, ys)]
+    s = singles[0][2] + singles[1][2] + singles[2][2]
+    assert torch.equal(gc, s)
+    assert float(loss.item()) == float(singles[0][0].item()) + float(singles[1][0].item()) + float(singles[2][0].item())
+
