@@ -223,11 +223,17 @@ def bench_batch(args, torch):
     log(f"[bench] {len(ps)} slices generated in {time.time() - t0:.1f}s")
     T = lambda a: torch.from_numpy(np.ascontiguousarray(np.asarray(a).astype(np.complex64))).to(dev)  # noqa: E731
     plans, xs, cs, ys = [], [], [], []
+    other = [q for q in ("bf16_split", "fp32") if q != args.precision][0]
+    other_plans = []
     t0 = time.time()
     for p in ps:
         kw = dict(mask_idx=p.mask_idx) if p.sampling == "cartesian" else dict(traj=p.traj)
-        plans.append(MaxwellPlan(p.dims, p.J, B=T(p.B), **kw, weights=p.weights, precision=args.precision,
+        Bd = T(p.B)
+        plans.append(MaxwellPlan(p.dims, p.J, B=Bd, **kw, weights=p.weights, precision=args.precision,
                                  device=dev))
+        if not args.no_compare:  # the same slices at the other precision, on the same device bases
+            other_plans.append(MaxwellPlan(p.dims, p.J, B=Bd, **kw, weights=p.weights, precision=other,
+                                           device=dev))
         p.B = None  # the host copy is no longer needed
         xs.append(T(p.x0))
         cs.append(T(p.c0))
@@ -241,6 +247,14 @@ def bench_batch(args, torch):
     batch.capture(xs, cs, ys)
     ms, wall = time_steps(batch.replay, args.steps, args.warmup, torch)
     log(f"[bench] batch: {ms:.3f} ms/step graph ({coils * 1000.0 / ms:.0f} coil-images/s), eager {eager_ms:.3f} ms")
+    compare = None
+    if other_plans:
+        ob = MaxwellBatch(other_plans, branches=args.branches)
+        ob.capture(xs, cs, ys)
+        oms, _ = time_steps(ob.replay, args.steps, args.warmup, torch)
+        compare = {"precision": other, "ms_per_step": oms, "value": coils * 1000.0 / oms}
+        log(f"[bench] batch {other}: {oms:.3f} ms/step graph ({coils * 1000.0 / oms:.0f} coil-images/s)")
+        del ob
     # per-slice latency: each slice's gradient alone (device events), median of 5
     lat = []
     st = torch.cuda.current_stream()
@@ -273,6 +287,7 @@ def bench_batch(args, torch):
                    "cartesian_slices": sum(p.sampling == "cartesian" for p in ps),
                    "step": "one graph replay: loss + gradient of every slice (B c recomputed)"},
         "eager_ms_per_step": eager_ms,
+        "other_precision": compare,
         "basis_stream_gbs": 3.0 * basis_bytes / (ms * 1e-3) / 1e9,
         "slice_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                              "min": float(lat.min()), "max": float(lat.max()), "sum": float(lat.sum())},

@@ -5,10 +5,11 @@
 
 namespace mx {
 
-// x = prox of lam TV at z (lam = 1 / *rho_dev when rho_dev is given, else lam); P holds
-// nd * N complex values (the dual field), dfield N; iters Chambolle steps from P = 0.
+// x = prox of lam TV at z (lam = 1 / *rho_dev when rho_dev is given, else lam); P and P2 hold
+// nd * N complex values each (the dual field, double-buffered); iters Chambolle steps from
+// P = 0, one launch per step.
 hipError_t tv_prox_launch(int nd, const int64_t* n, const float2* z, const double* rho_dev, float lam, int iters,
-                          float2* P, float2* dfield, float2* x, hipStream_t st);
+                          float2* P, float2* P2, float2* x, hipStream_t st);
 // z_j = y_j + eps_j (w_j - y_j) / max(||w_j - y_j||, eps_j); part holds ball_part_doubles(J)
 // doubles (per-coil partial sums, then the distances)
 hipError_t ball_project_launch(const float2* w, const float2* y, const float* eps, int64_t M, int J, double* part,

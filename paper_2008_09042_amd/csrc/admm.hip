@@ -7,14 +7,17 @@
 // (J. Math. Imaging Vis. 20, 2004) from a zero dual field P (ndim components per pixel):
 //     d = div P - z / lam;   g = grad d;   P <- (P + tau g) / (1 + tau |g|),   tau = 1/(4 ndim)
 // and returns x = z - lam div P, with div = -grad^H.  lam = 1 / rho is read from device memory
-// (rho adapts inside the ADMM loop).  One thread per pixel; the divergence and gradient read
-// the neighbours along each axis directly (they are L2-resident between the two kernels).
+// (rho adapts inside the ADMM loop).  One launch per step: each thread recomputes d at its
+// pixel and at its forward neighbours from the previous dual field (double-buffered), so the
+// divergence and the gradient need no barrier between them.
 //
 // Ball projection (the closed form of the paper): z_k = y_k + eps_k (w_k - y_k) /
 // max(||w_k - y_k||, eps_k), with the per-coil distance accumulated in FP64 by a fixed-order
 // two-stage reduction.
 #include "solver.h"
 #include "admm.h"
+
+#include <utility>
 
 namespace mx {
 
@@ -61,22 +64,45 @@ __global__ void tv_div_kernel(Dims g, const float2* __restrict__ P, const float2
   }
 }
 
-// P <- (P + tau grad d) / (1 + tau |grad d|)
-__global__ void tv_dual_kernel(Dims g, float2* __restrict__ P, const float2* __restrict__ dfield, float tau) {
+// One Chambolle step in one pass: Pout = (Pin + tau grad d) / (1 + tau |grad d|) with
+// d = div Pin - z / lam recomputed at the pixel and at its forward neighbours (Pin is only
+// read, so the step needs no grid-wide barrier between the divergence and the gradient).
+__device__ __forceinline__ float2 tv_d_at(const Dims& g, const float2* __restrict__ P, const float2* __restrict__ z,
+                                          float inv_lam, int64_t i, const int64_t (&c)[3]) {
+  float2 dv = make_float2(0.f, 0.f);
+  for (int d = 0; d < g.nd; ++d) {
+    const float2* Pd = P + d * g.N;
+    if (c[d] < g.n[d] - 1) dv = cadd(dv, Pd[i]);
+    if (c[d] > 0) dv = csub(dv, Pd[i - g.stride[d]]);
+  }
+  const float2 zi = z[i];
+  return make_float2(dv.x - zi.x * inv_lam, dv.y - zi.y * inv_lam);
+}
+
+__global__ void tv_step_kernel(Dims g, const float2* __restrict__ Pin, float2* __restrict__ Pout,
+                               const float2* __restrict__ z, const double* __restrict__ rho, float lam_fixed,
+                               float tau) {
+  const float inv_lam = rho ? (float)*rho : 1.f / lam_fixed;
   for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < g.N; i += (int64_t)gridDim.x * NT) {
     int64_t c[3];
     coords(g, i, c);
-    const float2 di = dfield[i];
+    const float2 di = tv_d_at(g, Pin, z, inv_lam, i, c);
     float2 gr[3];
     float m2 = 0.f;
     for (int d = 0; d < g.nd; ++d) {
-      gr[d] = c[d] < g.n[d] - 1 ? csub(dfield[i + g.stride[d]], di) : make_float2(0.f, 0.f);
+      if (c[d] < g.n[d] - 1) {
+        int64_t cn[3] = {c[0], c[1], c[2]};
+        cn[d] += 1;
+        gr[d] = csub(tv_d_at(g, Pin, z, inv_lam, i + g.stride[d], cn), di);
+      } else {
+        gr[d] = make_float2(0.f, 0.f);
+      }
       m2 += gr[d].x * gr[d].x + gr[d].y * gr[d].y;
     }
     const float inv = 1.f / (1.f + tau * sqrtf(m2));
     for (int d = 0; d < g.nd; ++d) {
-      float2 pv = P[d * g.N + i];
-      P[d * g.N + i] = make_float2((pv.x + tau * gr[d].x) * inv, (pv.y + tau * gr[d].y) * inv);
+      const float2 pv = Pin[d * g.N + i];
+      Pout[d * g.N + i] = make_float2((pv.x + tau * gr[d].x) * inv, (pv.y + tau * gr[d].y) * inv);
     }
   }
 }
@@ -184,18 +210,19 @@ Dims make_dims(int nd, const int64_t* n) {
 }  // namespace
 
 hipError_t tv_prox_launch(int nd, const int64_t* n, const float2* z, const double* rho_dev, float lam, int iters,
-                          float2* P, float2* dfield, float2* x, hipStream_t st) {
+                          float2* P, float2* P2, float2* x, hipStream_t st) {
   const Dims g = make_dims(nd, n);
   const unsigned gr = grid_for(g.N);
   const float tau = 1.f / (4.f * (float)nd);
   if (!rho_dev && !(lam > 0.f)) return copy_split_launch(x, nullptr, z, nullptr, g.N, 0, st);  // prox of 0
   hipError_t e = zero_split_launch(P, nullptr, (int64_t)nd * g.N, 0, st);
   if (e != hipSuccess) return e;
+  float2 *pin = P, *pout = P2;
   for (int k = 0; k < iters; ++k) {
-    hipLaunchKernelGGL(tv_div_kernel, dim3(gr), dim3(NT), 0, st, g, P, z, rho_dev, lam, 0, dfield);
-    hipLaunchKernelGGL(tv_dual_kernel, dim3(gr), dim3(NT), 0, st, g, P, dfield, tau);
+    hipLaunchKernelGGL(tv_step_kernel, dim3(gr), dim3(NT), 0, st, g, pin, pout, z, rho_dev, lam, tau);
+    std::swap(pin, pout);
   }
-  hipLaunchKernelGGL(tv_div_kernel, dim3(gr), dim3(NT), 0, st, g, P, z, rho_dev, lam, 1, x);
+  hipLaunchKernelGGL(tv_div_kernel, dim3(gr), dim3(NT), 0, st, g, pin, z, rho_dev, lam, 1, x);
   return hipGetLastError();
 }
 

@@ -109,18 +109,27 @@ __device__ double block_sum(double v, double* red) {
   return s;
 }
 
-// G (n x n, Hermitian, FP64) -> diag(G) = eigenvalues, V = eigenvectors (columns)
-__global__ __launch_bounds__(JT) void jacobi_kernel(z64* __restrict__ G, z64* __restrict__ V, int n, int max_sweeps,
+// G (n x n, Hermitian, FP64) -> diag(G) = eigenvalues, V = eigenvectors (columns).
+// MAXP bounds the pairs per round (n <= 2 MAXP); LDS_RESIDENT: G and V are copied into
+// dynamic LDS (2 n^2 complex doubles) for the sweeps and back at the end.
+template <int MAXP, bool LDS_RESIDENT>
+__global__ __launch_bounds__(JT) void jacobi_kernel(z64* __restrict__ Gg, z64* __restrict__ Vg, int n, int max_sweeps,
                                                    int* __restrict__ sweeps_done) {
+  extern __shared__ z64 dyn[];
   __shared__ double red[JT];
-  __shared__ int pp[2048], pq[2048];
-  __shared__ double pc[2048], ps[2048];
-  __shared__ z64 pe[2048];
+  __shared__ int pp[MAXP], pq[MAXP];
+  __shared__ double pc[MAXP], ps[MAXP];
+  __shared__ z64 pe[MAXP];
   const int n2 = n + (n & 1);
   const int npair = n2 / 2;
+  // leading dimension: rows padded by one entry in LDS, so that a column walk spreads over banks
+  const int ld = LDS_RESIDENT ? n + 1 : n;
+  z64* G = LDS_RESIDENT ? dyn : Gg;
+  z64* V = LDS_RESIDENT ? dyn + (int64_t)n * ld : Vg;
   for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += JT) {
     const int a = (int)(e / n), b = (int)(e % n);
-    V[e] = {a == b ? 1.0 : 0.0, 0.0};
+    V[(int64_t)a * ld + b] = {a == b ? 1.0 : 0.0, 0.0};
+    if (LDS_RESIDENT) G[(int64_t)a * ld + b] = Gg[e];
   }
   __syncthreads();
   int sweep = 0;
@@ -128,7 +137,8 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(z64* __restrict__ G, z64* __
     double off = 0.0, dia = 0.0;
     for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += JT) {
       const int a = (int)(e / n), b = (int)(e % n);
-      const double m2 = G[e].x * G[e].x + G[e].y * G[e].y;
+      const z64 g = G[(int64_t)a * ld + b];
+      const double m2 = g.x * g.x + g.y * g.y;
       if (a == b) dia += m2; else off += m2;
     }
     off = block_sum(off, red);
@@ -143,8 +153,8 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(z64* __restrict__ G, z64* __
         double cs = 1.0, sn = 0.0;
         z64 ph = {1.0, 0.0};
         if (q < n) {
-          const double a = G[(int64_t)p * n + p].x, b = G[(int64_t)q * n + q].x;
-          const z64 c = G[(int64_t)p * n + q];
+          const double a = G[(int64_t)p * ld + p].x, b = G[(int64_t)q * ld + q].x;
+          const z64 c = G[(int64_t)p * ld + q];
           const double ac = sqrt(c.x * c.x + c.y * c.y);
           if (ac > 1e-300 && ac > 1e-18 * sqrt(fabs(a * b))) {
             const double tau = (b - a) / (2.0 * ac);
@@ -158,8 +168,9 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(z64* __restrict__ G, z64* __
       }
       __syncthreads();
       // columns p, q of G and V:  col_p <- cs col_p - sn conj(e) col_q;  col_q <- sn col_p + cs conj(e) col_q
+      // (consecutive threads take different pairs of one row)
       for (int64_t w = threadIdx.x; w < (int64_t)npair * n; w += JT) {
-        const int k = (int)(w / n), i = (int)(w % n);
+        const int i = (int)(w / npair), k = (int)(w % npair);
         const int q = pq[k];
         if (q < 0 || ps[k] == 0.0) continue;
         const int p = pp[k];
@@ -167,9 +178,9 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(z64* __restrict__ G, z64* __
         const z64 ec = zconj(pe[k]);
         for (int mat = 0; mat < 2; ++mat) {
           z64* M = mat == 0 ? G : V;
-          const z64 gp = M[(int64_t)i * n + p], gq = zmul(ec, M[(int64_t)i * n + q]);
-          M[(int64_t)i * n + p] = zadd(zscale(gp, cs), zscale(gq, -sn));
-          M[(int64_t)i * n + q] = zadd(zscale(gp, sn), zscale(gq, cs));
+          const z64 gp = M[(int64_t)i * ld + p], gq = zmul(ec, M[(int64_t)i * ld + q]);
+          M[(int64_t)i * ld + p] = zadd(zscale(gp, cs), zscale(gq, -sn));
+          M[(int64_t)i * ld + q] = zadd(zscale(gp, sn), zscale(gq, cs));
         }
       }
       __syncthreads();
@@ -180,11 +191,19 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(z64* __restrict__ G, z64* __
         if (q < 0 || ps[k] == 0.0) continue;
         const int p = pp[k];
         const double cs = pc[k], sn = ps[k];
-        const z64 gp = G[(int64_t)p * n + j], gq = zmul(pe[k], G[(int64_t)q * n + j]);
-        G[(int64_t)p * n + j] = zadd(zscale(gp, cs), zscale(gq, -sn));
-        G[(int64_t)q * n + j] = zadd(zscale(gp, sn), zscale(gq, cs));
+        const z64 gp = G[(int64_t)p * ld + j], gq = zmul(pe[k], G[(int64_t)q * ld + j]);
+        G[(int64_t)p * ld + j] = zadd(zscale(gp, cs), zscale(gq, -sn));
+        G[(int64_t)q * ld + j] = zadd(zscale(gp, sn), zscale(gq, cs));
       }
       __syncthreads();
+    }
+  }
+  if (LDS_RESIDENT) {
+    __syncthreads();
+    for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += JT) {
+      const int a = (int)(e / n), b = (int)(e % n);
+      Gg[e] = G[(int64_t)a * ld + b];
+      Vg[e] = V[(int64_t)a * ld + b];
     }
   }
   if (threadIdx.x == 0) *sweeps_done = sweep;
@@ -252,7 +271,12 @@ hipError_t tucker_compress_run(const int64_t* dims, int64_t K, const float2* B, 
                        part.as<z64>());
     hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)std::min<int64_t>(((int64_t)n * n + 255) / 256, 4096)),
                        dim3(256), 0, st, part.as<z64>(), n, nchunk, G.as<z64>());
-    hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(JT), 0, st, G.as<z64>(), V.as<z64>(), n, 60, sw.as<int>());
+    if (n <= 64)  // both matrices, rows padded by one, fit in LDS (about 130 KiB)
+      hipLaunchKernelGGL((jacobi_kernel<32, true>), dim3(1), dim3(JT), 2 * (size_t)n * (n + 1) * sizeof(z64), st,
+                         G.as<z64>(), V.as<z64>(), n, 60, sw.as<int>());
+    else
+      hipLaunchKernelGGL((jacobi_kernel<2048, false>), dim3(1), dim3(JT), 0, st, G.as<z64>(), V.as<z64>(), n, 60,
+                         sw.as<int>());
     if ((e = hipGetLastError()) != hipSuccess) return e;
     std::vector<z64> hG((size_t)n * n), hV((size_t)n * n);
     if ((e = hipMemcpyAsync(hG.data(), G.p, hG.size() * sizeof(z64), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;

@@ -596,12 +596,12 @@ maxwell_status plan_build(Plan& p, const maxwell_plan_desc& d, const maxwell_bas
   p.off_U = off; off += al(JM);
   p.off_cg = off; off += 3 * al(V) + al(CG_SCALARS * sizeof(double)) + al(DOT_BLOCKS * sizeof(double));
   if (!p.fused) {
-    // SENSE / ADMM (general path): 6 + ndim image-sized buffers (z0 twice, u0, two
-    // temporaries, the TV field d, the TV dual field P), 5 sample-sized ones (F S p, z_k
+    // SENSE / ADMM (general path): 5 + 2 ndim image-sized buffers (z0 twice, u0, two
+    // temporaries, the TV dual field twice), 5 sample-sized ones (F S p, z_k
     // twice, u_k, a temporary), the ball-projection partials and the ADMM scalars
     const size_t NB = al((size_t)p.N * 8);
     p.off_admm = off;
-    off += (6 + p.ndim) * NB + 5 * al(JM) + al((size_t)ball_part_doubles(p.J) * sizeof(double)) +
+    off += (5 + 2 * p.ndim) * NB + 5 * al(JM) + al((size_t)ball_part_doubles(p.J) * sizeof(double)) +
            al(ADMM_SCALARS * sizeof(double));
   }
   p.ws_bytes = off;
@@ -989,7 +989,7 @@ hipError_t run_sense_normal(const Plan& p, const float2* S, const float2* x, flo
 
 namespace {
 struct AdmmWs {
-  float2 *z0a, *z0b, *u0, *tN, *tN2, *dfield, *P;
+  float2 *z0a, *z0b, *u0, *tN, *tN2, *P, *P2;
   float2 *Fp, *zka, *zkb, *uk, *tM;
   double *part, *dist, *r2, *s2, *rho, *ufac;
 };
@@ -997,9 +997,11 @@ AdmmWs admm_ws(const Plan& p, void* ws) {
   AdmmWs a;
   const size_t NB = al((size_t)p.N * 8), MB = al((size_t)p.J * (size_t)p.M * 8);
   char* b = wsp<char>(ws, p.off_admm);
-  float2** nb[] = {&a.z0a, &a.z0b, &a.u0, &a.tN, &a.tN2, &a.dfield};
+  float2** nb[] = {&a.z0a, &a.z0b, &a.u0, &a.tN, &a.tN2};
   for (auto q : nb) { *q = reinterpret_cast<float2*>(b); b += NB; }
   a.P = reinterpret_cast<float2*>(b);
+  b += p.ndim * NB;
+  a.P2 = reinterpret_cast<float2*>(b);
   b += p.ndim * NB;
   float2** mb[] = {&a.Fp, &a.zka, &a.zkb, &a.uk, &a.tM};
   for (auto q : mb) { *q = reinterpret_cast<float2*>(b); b += MB; }
@@ -1014,7 +1016,7 @@ AdmmWs admm_ws(const Plan& p, void* ws) {
 
 hipError_t run_tv_prox(const Plan& p, const float2* z, float lam, int iters, float2* x, void* ws, hipStream_t st) {
   const AdmmWs a = admm_ws(p, ws);
-  return TIMED("tv_prox", tv_prox_launch(p.ndim, p.n, z, nullptr, lam, iters, a.P, a.dfield, x, st));
+  return TIMED("tv_prox", tv_prox_launch(p.ndim, p.n, z, nullptr, lam, iters, a.P, a.P2, x, st));
 }
 
 hipError_t run_ball_project(const Plan& p, const float2* w, const float2* y, const float* eps, float2* z, void* ws,
@@ -1047,7 +1049,7 @@ hipError_t run_admm(const Plan& p, const float2* S, const float2* y, const float
     std::swap(zk, zkp);
     // z0 = prox_{TV / rho}(p + u0)
     if ((e = lincomb_launch(a.tN, pimg, 1.f, a.u0, 1.f, N, st)) != hipSuccess) return e;
-    if ((e = TIMED("tv_prox", tv_prox_launch(p.ndim, p.n, a.tN, a.rho, 0.f, tv_iters, a.P, a.dfield, z0, st))) !=
+    if ((e = TIMED("tv_prox", tv_prox_launch(p.ndim, p.n, a.tN, a.rho, 0.f, tv_iters, a.P, a.P2, z0, st))) !=
         hipSuccess)
       return e;
     // z_k = ball projection of F S p + u_k
