@@ -452,7 +452,7 @@ def main():
         traffic_from(args.traffic_from[0], args.traffic_from[1], args.copy_probe or 256)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1 "
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; --gpus must be 1 "
                                    "(the coil-sharded multi-GPU design is documented but not built)"}))
         sys.exit(2)
     import torch

@@ -60,7 +60,7 @@ typedef struct maxwell_batch_s* maxwell_batch_t;
 typedef enum {
   MAXWELL_OK = 0,
   MAXWELL_ERR_INVALID_ARGUMENT = -1,   /* null/misaligned pointer, bad size, overlap, bad mask */
-  MAXWELL_ERR_UNSUPPORTED = -2,        /* valid request this build does not implement        */
+  MAXWELL_ERR_UNSUPPORTED = -2,        /* valid request the library does not implement       */
   MAXWELL_ERR_OUT_OF_MEMORY = -3,      /* plan_create could not allocate its tables           */
   MAXWELL_ERR_HIP = -4,                /* a HIP runtime call failed                           */
   MAXWELL_ERR_WORKSPACE_TOO_SMALL = -5 /* ws_bytes < maxwell_plan_workspace_size()            */
