@@ -41,12 +41,13 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", default="bf16_split", choices=["bf16_split", "fp32"])
-    ap.add_argument("--workload", default="cart3d", choices=["cart3d", "batch", "gn", "admm", "compress"],
+    ap.add_argument("--workload", default="cart3d", choices=["cart3d", "batch", "gn", "admm", "compress", "kernels2d"],
                     help="cart3d: the headline 128^3 Tucker workload; batch: 64 uneven 2D slices with "
                          "dense bases through one captured graph; gn: conjugate-gradient steps of the "
                          "Gauss-Newton normal equations on the 128^3 Tucker workload; admm: constrained "
                          "TV-SENSE reconstruction steps on the 2D 256^2 workload; compress: Tucker "
-                         "compression of a smooth dense 3D basis")
+                         "compression of a smooth dense 3D basis; kernels2d: per-kernel roofline "
+                         "figures of the general path on the 2D Cartesian and radial workloads")
     ap.add_argument("--cg-iters", type=int, default=10, help="gn workload: CG steps per timed call")
     ap.add_argument("--branches", type=int, default=4, help="batch workload: concurrent branches")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -446,6 +447,79 @@ def bench_compress(args, torch):
     print(json.dumps(out), flush=True)
 
 
+def bench_kernels2d(args, torch):
+    """Per-kernel roofline figures of the general path (dense basis GEMMs on the matrix cores,
+    axis FFTs, Cartesian sampling, KB gridding) on the 2D Cartesian 256^2 (32 coils, K 200)
+    and radial 256^2 (16 coils, K 128, 64 spokes x 512) workloads, from the in-library HIP
+    events over `steps` gradient evaluations.  Achieved = algorithmic work / average launch
+    time; algorithmic bytes count each array once (complex64 8 B, FP32 4 B, index 4 B).
+    Prints one JSON line."""
+    from paper_2008_09042_amd.encoding import MaxwellPlan
+    from synth import CONFIGS, make_problem
+    dev = torch.device("cuda:0")
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(np.asarray(a).astype(np.complex64))).to(dev)  # noqa: E731
+    res = {}
+    for cfg in (2, 3):
+        p = make_problem(cfg, **CONFIGS[cfg])
+        name = CONFIGS[cfg]["name"]
+        kw = dict(mask_idx=p.mask_idx) if p.traj is None else dict(traj=p.traj, weights=p.weights)
+        N, J, K, M = int(np.prod(p.dims)), p.J, p.K, p.M
+        for prec in ("bf16_split", "fp32"):
+            plan = MaxwellPlan(p.dims, J, B=T(p.B), **kw, precision=prec, device=dev)
+            x, c, y = T(p.x0), T(p.c0), T(p.noise)
+            for _ in range(args.warmup):
+                plan.grad(x, c, y)
+            torch.cuda.synchronize()
+            plan.set_timing(True)
+            for _ in range(args.steps):
+                plan.grad(x, c, y)
+            torch.cuda.synchronize()
+            kt = plan.timing()
+            plan.set_timing(False)
+            G = (2 * p.dims[0]) * (2 * p.dims[1]) if p.traj is not None else 0
+            gemm_flops = 8.0 * J * N * K
+            gemm_bytes = 8.0 * (N * K + J * K + J * N)
+            fft_n = G if G else N
+            work = {
+                "gemm_dense_apply": ("mfma", gemm_flops, PEAKS_TFLOPS["bf16" if prec == "bf16_split" else "fp32"],
+                                     gemm_bytes),
+                "gemm_dense_adjoint": ("mfma", gemm_flops, PEAKS_TFLOPS["bf16" if prec == "bf16_split" else "fp32"],
+                                       gemm_bytes),
+                "fft_axis": ("hbm", 16.0 * J * fft_n, None, None),
+                "gather": ("hbm", 8.0 * J * M * 2 + 4.0 * M, None, None),
+                "scatter": ("hbm", 8.0 * J * (M + N) + 4.0 * N, None, None),
+                "nufft_degrid": ("hbm", 8.0 * J * (G + M) + M * (8.0 + 48.0), None, None),
+                "nufft_spread": ("hbm", 8.0 * J * (G + 2 * M) + M * (64.0 + 8.0) + 4.0 * G, None, None),
+                "nufft_pad": ("hbm", 8.0 * J * (N + G) + 8.0 * N, None, None),
+                "nufft_crop": ("hbm", 8.0 * J * (N + G), None, None),
+                "adjoint_combine": ("hbm", 8.0 * (3 * J * N + 2 * N), None, None),
+                "residual": ("hbm", 8.0 * J * M * 3 + 4.0 * M, None, None),
+            }
+            out = {}
+            for k, (n_launch, ms) in kt.items():
+                if not n_launch or k not in work:
+                    continue
+                us = 1000.0 * ms / n_launch
+                bound, amount, peak, byts = work[k]
+                if bound == "mfma":
+                    tf = amount / (us * 1e-6) / 1e12
+                    out[k] = {"us": round(us, 1), "bound": "mfma", "achieved_tflops": round(tf, 2),
+                              "peak_tflops": peak, "frac": round(tf / peak, 4),
+                              "hbm_gbs": round(byts / (us * 1e-6) / 1e9, 1),
+                              "hbm_frac": round(byts / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 3)}
+                else:
+                    gbs = amount / (us * 1e-6) / 1e9
+                    out[k] = {"us": round(us, 1), "bound": "hbm", "achieved_gbs": round(gbs, 1),
+                              "peak_gbs": HBM_PEAK_GBS, "frac": round(gbs / HBM_PEAK_GBS, 3)}
+            res[f"{name}/{prec}"] = out
+            log(f"[bench] {name} {prec}: " + ", ".join(
+                f"{k} {v['us']}us {v.get('achieved_gbs', v.get('achieved_tflops'))}"
+                f"{'GB/s' if v['bound'] == 'hbm' else 'TF/s'} ({100 * v['frac']:.1f}%)" for k, v in out.items()))
+            del plan
+    print(json.dumps({"metric": "per-kernel roofline fractions, general path", "workload": "kernels2d",
+                      "steps": args.steps, "kernels": res}), flush=True)
+
+
 def main():
     args = parse()
     if args.traffic_from:
@@ -468,6 +542,9 @@ def main():
         return
     if args.workload == "compress":
         bench_compress(args, torch)
+        return
+    if args.workload == "kernels2d":
+        bench_kernels2d(args, torch)
         return
 
     dev = torch.device("cuda:0")

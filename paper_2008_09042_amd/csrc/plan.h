@@ -76,6 +76,8 @@ struct Plan {
   size_t off_T1 = 0, off_T3 = 0, off_xt = 0, off_Z = 0, off_gxp = 0, off_T3b = 0, off_T1b = 0, off_G = 0, off_Ys = 0, off_cpart = 0;
   size_t off_U = 0, off_cg = 0;  // Gauss-Newton / CG: JVP result; r, d, q, FP64 scalars
   size_t off_admm = 0;           // SENSE / ADMM state (general path only)
+  size_t off_cfrag = 0;          // dense apply: fragment-ordered coefficients (0: generic GEMM)
+  size_t off_adjp = 0;           // dense adjoint: row-chunk partials of the streaming kernel
   int part_blocks = 0;
 
   size_t bytes_x() const { return (size_t)N * 8; }

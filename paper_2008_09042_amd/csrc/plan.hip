@@ -20,6 +20,7 @@
 #include "nufft.h"
 #include "solver.h"
 #include "admm.h"
+#include "skinny.h"
 #include "plan.h"
 
 namespace mx {
@@ -585,6 +586,15 @@ maxwell_status plan_build(Plan& p, const maxwell_plan_desc& d, const maxwell_bas
     p.off_cpart = off;
     off += al(core_adj_part_bytes(p.cg.R, p.cg.K, p.J));
   }
+  if (p.basis_kind == MAXWELL_BASIS_DENSE && skinny_apply_supported(p.N, p.K, p.J) &&
+      (reinterpret_cast<uintptr_t>(p.dense) & 15u) == 0) {
+    p.off_cfrag = off;
+    off += al(skinny_frag_bytes(p.K, p.J));
+    if (p.J <= 16) {  // one coil block: the streaming adjoint beats the tiled GEMM (measured)
+      p.off_adjp = off;
+      off += al(skinny_adjoint_bytes(p.N, p.K, p.J));
+    }
+  }
   p.off_E = off; off += al(JM);
   p.off_gemm = off; off += al(gemm_ws);
   p.part_blocks = residual_blocks((int64_t)p.J * p.M);
@@ -688,8 +698,12 @@ static hipError_t core_adjoint(const Plan& p, const float2* T1b, float2* gc, flo
 
 hipError_t run_basis_apply(const Plan& p, const float2* c, float2* S, void* ws, hipStream_t st) {
   void* gws = wsp<void>(ws, p.off_gemm);
-  if (p.basis_kind == MAXWELL_BASIS_DENSE)
+  if (p.basis_kind == MAXWELL_BASIS_DENSE) {
+    if (p.off_cfrag)  // streaming kernel for few coils
+      return TIMED("gemm_dense_apply", skinny_apply_launch(p.dense, p.N, p.K, c, p.J, p.precision,
+                                                           wsp<void>(ws, p.off_cfrag), S, st));
     return TIMED("gemm_dense_apply", gemm_launch(dense_apply_args(p, c, S), p.precision, gws, st));
+  }
   GemmArgs g[4];
   tucker_apply_args(p, c, wsp<float2>(ws, p.off_tA), wsp<float2>(ws, p.off_tB), S, g);
   hipError_t e0 = core_forward(p, c, wsp<float2>(ws, p.off_tA), ws, st);
@@ -704,6 +718,9 @@ hipError_t run_basis_apply(const Plan& p, const float2* c, float2* S, void* ws, 
 hipError_t run_basis_adjoint(const Plan& p, const float2* S, float2* c, float alpha, const float* alpha_dev,
                              void* ws, hipStream_t st) {
   void* gws = wsp<void>(ws, p.off_gemm);
+  if (p.basis_kind == MAXWELL_BASIS_DENSE && p.off_adjp)  // streaming kernel for up to 16 coils
+    return TIMED("gemm_dense_adjoint", skinny_adjoint_launch(p.dense, p.N, p.K, S, p.J, p.precision, alpha,
+                                                             alpha_dev, wsp<void>(ws, p.off_adjp), c, st));
   if (p.basis_kind == MAXWELL_BASIS_DENSE) {
     GemmArgs g = dense_adjoint_args(p, S, c);
     g.alpha = alpha;

@@ -20,6 +20,10 @@ CASES = {
     "dense2d_48x40_J5_K37": dict(seed=101, dims=(48, 40), J=5, K=37, basis="dense", weights=True),
     "dense2d_64x64_J8_K32_c1shape": dict(seed=102, dims=(64, 64), J=8, K=32, basis="dense"),
     "dense2d_30x20_radix35": dict(seed=103, dims=(30, 20), J=3, K=9, basis="dense"),
+    # dense apply streaming kernel: three and four coil blocks, a ragged K16 step, N not a
+    # multiple of its 64-row wave share
+    "dense2d_40x36_J40_K24": dict(seed=120, dims=(40, 36), J=40, K=24, basis="dense", weights=True),
+    "dense2d_30x30_J64_K20": dict(seed=121, dims=(30, 30), J=64, K=20, basis="dense"),
     "tucker3d_24x20x18_r7x5x6_K13": dict(seed=104, dims=(24, 20, 18), ranks=(7, 5, 6), J=3, K=13,
                                          basis="tucker", mask="lines3d", frac=0.3, weights=True),
     "tucker3d_12x10x6_radix35": dict(seed=105, dims=(12, 10, 6), ranks=(4, 3, 5), J=2, K=7,
