@@ -125,7 +125,11 @@ typedef struct {
 
 /* Build a plan: validates the geometry, copies host tables, builds twiddle
  * and sampling tables on the device, and (BF16_SPLIT) a split copy of the
- * basis.  Allocates device memory; not capturable.                          */
+ * basis.  Allocates device memory; not capturable.  Environment read here:
+ * MAXWELL_GEMM_AUTOTUNE=0 skips timing the dense-basis GEMM splits;
+ * MAXWELL_SPREAD_SPLIT=n (NONCARTESIAN) sets the per-lane sample count above
+ * which a block of the gridding adjoint goes to its split kernel (default 48;
+ * results agree to rounding either way).                                    */
 maxwell_status maxwell_plan_create(const maxwell_plan_desc* desc, const maxwell_basis_desc* basis,
                                    maxwell_plan_t* plan_out);
 

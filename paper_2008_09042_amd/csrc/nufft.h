@@ -19,11 +19,25 @@ struct NufftArgs {
   const int32_t* s_perm;      // [M] original index of each sorted sample
   const int32_t* s_col;       // [M] first-tap column of each sorted sample
   const float* s_wts;         // [M][16] tap weights of each sorted sample: axis 0 in [0, W), axis 1 in [8, 8 + W)
+  // spread blocks (SPREAD_ROWS grid rows, 64 columns) in which some lane's sample sequence
+  // exceeds the split threshold: skipped by the plain kernel, their rows taken one by one
+  // by the split kernel
+  const uint8_t* s_heavy;     // [ceil(g0 / SPREAD_ROWS) * ceil(g1 / 64)] 1 for a split block (may be null)
+  const int32_t* s_hlist;     // [n_heavy] split rows: row * ceil(g1 / 64) + column block
+  int n_heavy;
   float cscale;               // sqrt(g0 g1 / (n0 n1)): unitary DFT -> the operator's scaling
 };
 
 // Coils per spread workgroup, and the bytes of the staging buffer the spread needs.
 int spread_group(int J);
+// Grid columns per spread block, and the default length of a grid point's sample sequence
+// above which its block is split (MAXWELL_SPREAD_SPLIT in the environment at plan creation
+// overrides it).
+constexpr int SPREAD_COLS = 64;
+#ifndef SPREAD_ROWS
+#define SPREAD_ROWS 2   // grid rows per wave of the plain spread kernel
+#endif
+constexpr int SPREAD_SPLIT_DEFAULT = 48;
 size_t spread_stage_bytes(int J, int64_t M);
 hipError_t pad_deapod_launch(const NufftArgs& a, const float2* S, const float2* x, float2* grid, hipStream_t st);
 hipError_t crop_deapod_launch(const NufftArgs& a, const float2* grid, float2* out, hipStream_t st);

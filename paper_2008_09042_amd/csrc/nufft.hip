@@ -103,12 +103,14 @@ __global__ __launch_bounds__(NT) void degrid_kernel(NufftArgs a, const float2* _
 // coil-minor and padded to a whole number of coil groups, so a thread reads each sample's
 // JG values as one contiguous run.
 //
-// A workgroup covers one grid row, 64 columns and JG coils with W waves: wave t0 sums the
-// row window r - t0 for every lane's column, and the W partial sums are added in t0 order
-// through LDS.  Splitting the windows over waves shortens the longest chain of dependent
-// loads (the grid points near the centre of a radial trajectory see hundreds of samples).
-// Fixed summation order, no atomics.
-constexpr int SPC = 64;             // grid columns per workgroup (one per lane)
+// A wave covers one grid row, 64 columns (one per lane) and JG coils: each lane takes the W
+// row windows of its column in t0 order as one sequence of samples, with two samples' loads in
+// flight, and writes its sums (fixed order, no atomics, no LDS).  Most grid points see a few
+// samples, so the wave's time is the latency of a few dependent loads; one wave per block
+// keeps the whole grid resident at once.  The blocks whose longest sequence is long (the
+// dense centre of a radial trajectory, where a grid point sees hundreds of samples) are
+// marked at plan time and taken by the split kernel below instead.
+constexpr int SPC = SPREAD_COLS;    // grid columns per workgroup (one per lane)
 constexpr int STG = 64;             // samples per staging workgroup
 constexpr int SREC = 16;            // floats per sorted-sample weight record: w0 [0, 8), w1 [8, 16)
 
@@ -147,16 +149,17 @@ __device__ __forceinline__ float pick8(float4 lo, float4 hi, int t) {
   return v;
 }
 
-// acc += sum over sorted samples s in [s, e) of w0[t0] w1[c - col] ys[s][jo .. jo + JG).  The
-// loads of U samples depend on s only and are all issued before any is used; the whole w1
-// record is loaded and the tap picked in registers (the empty asm keeps the compiler from
-// turning the pick back into a load that waits on col).
+// acc += sum over the sorted samples s + k step + u (u < U, k >= 0) in [s, e) of
+// w0[t0] w1[c - col] ys[.][jo .. jo + JG).  The loads of U samples depend on the position
+// only and are all issued before any is used; the whole w1 record is loaded and the tap
+// picked in registers (the empty asm keeps the compiler from turning the pick back into a
+// load that waits on col).
 template <int JG, int U>
 __device__ __forceinline__ void spread_range(const NufftArgs& a, const float2* __restrict__ ys, int Jp, int jo,
-                                             int c, int t0, int s, int e, float2 (&acc)[JG]) {
+                                             int c, int t0, int s, int e, int step, float2 (&acc)[JG]) {
   const float4* rec = reinterpret_cast<const float4*>(a.s_wts);
   constexpr int YV = JG >= 2 ? JG / 2 : 1;
-  for (; s < e; s += U) {
+  for (; s < e; s += step) {
     int col[U];
     float w0[U];
     float4 w1l[U], w1h[U];
@@ -201,20 +204,191 @@ __device__ __forceinline__ void spread_range(const NufftArgs& a, const float2* _
   }
 }
 
-// One workgroup per (coil group, grid row, 64 columns): W waves, one per row window.
-template <int JG>
-__global__ __launch_bounds__(8 * SPC) void spread_kernel(NufftArgs a, const float2* __restrict__ ys, int Jp,
-                                                         float alpha, const float* __restrict__ scale_dev,
-                                                         float2* __restrict__ grid) {
-  __shared__ float2 part[8][JG][SPC];
+// One wave per (coil group, R grid rows, 64 columns); four waves per workgroup.  Output row
+// r0 + i of a lane takes the samples of cell rows r0 + i - t0 (t0 < W); over its R rows the
+// lane walks the W + R - 1 cell rows r0 + R - 1 - t (t = 0 .. W + R - 2) once, in t order,
+// and adds each sample to every row i with tap t0 = i - R + 1 + t in [0, W): one load of a
+// sample's values serves up to R outputs.
+template <int JG, int W, int R, int U>
+__global__ __launch_bounds__(256) void spread_flat_kernel(NufftArgs a, const float2* __restrict__ ys, int Jp,
+                                                          float alpha, const float* __restrict__ scale_dev,
+                                                          float2* __restrict__ grid) {
+  constexpr int NW = W + R - 1;  // cell rows walked
   const int bc = (a.g1 + SPC - 1) / SPC;
-  const int nblk = a.g0 * bc;
-  const int jg = blockIdx.x / nblk, blk = blockIdx.x % nblk;
-  const int r = blk / bc, c0 = (blk % bc) * SPC;
-  const int t0 = threadIdx.x / SPC, lane = threadIdx.x % SPC;
-  const int c = c0 + lane;
+  const int64_t nblk = (int64_t)((a.g0 + R - 1) / R) * bc;
+  const int64_t id = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+  if (id >= nblk * (Jp / JG)) return;
+  const int jg = (int)(id / nblk), blk = (int)(id % nblk);
+  if (a.s_heavy && a.s_heavy[blk]) return;  // rows taken by the split kernel
+  const int r0 = (blk / bc) * R, c = (blk % bc) * SPC + threadIdx.x % 64;
+  if (c >= a.g1) return;  // no barrier or cross-lane operation follows
   const int jo = jg * JG;
-  const int W = a.W;
+  // cell row t contributes [rb[2 t], + len) then [rb[2 t + 1], + len) (the second one
+  // non-empty only at the column wrap); all offsets are loaded unconditionally
+  int rb[2 * NW], cum[2 * NW + 1];
+  {
+    const int lo = c - W + 1;
+    const int i0 = lo >= 0 ? lo : a.g1 + lo, i1 = lo >= 0 ? c + 1 : a.g1, i3 = lo >= 0 ? 0 : c + 1;
+    int v0[NW], v1[NW], v2[NW], v3[NW];
+#pragma unroll
+    for (int t = 0; t < NW; ++t) {
+      const int row = ((r0 + R - 1 - t) % a.g0 + a.g0) % a.g0;
+      const int32_t* cp = a.cell_ptr + (int64_t)row * a.g1;
+      v0[t] = cp[i0];
+      v1[t] = cp[i1];
+      v2[t] = cp[0];
+      v3[t] = cp[i3];
+    }
+    cum[0] = 0;
+#pragma unroll
+    for (int t = 0; t < NW; ++t) {
+      rb[2 * t] = v0[t];
+      cum[2 * t + 1] = cum[2 * t] + (v1[t] - v0[t]);
+      rb[2 * t + 1] = v2[t];
+      cum[2 * t + 2] = cum[2 * t + 1] + (v3[t] - v2[t]);
+    }
+  }
+  const int total = cum[2 * NW];
+  const float4* rec = reinterpret_cast<const float4*>(a.s_wts);
+  constexpr int YV = JG >= 2 ? JG / 2 : 1;
+  float2 acc[R][JG];
+#pragma unroll
+  for (int i = 0; i < R; ++i)
+#pragma unroll
+    for (int q = 0; q < JG; ++q) acc[i][q] = make_float2(0.f, 0.f);
+  for (int k = 0; k < total; k += U) {
+    int col[U], tw[U];
+    float4 w0l[U], w0h[U], w1l[U], w1h[U];
+    float4 yv[U][YV];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int kk = min(k + u, total - 1);
+      // the last range whose start is at or before kk holds it (empty ranges are passed over)
+      int su = rb[0] + kk, t = 0;
+#pragma unroll
+      for (int j = 1; j < 2 * NW; ++j)
+        if (kk >= cum[j]) {
+          su = rb[j] + (kk - cum[j]);
+          t = j / 2;
+        }
+      tw[u] = t;
+      col[u] = a.s_col[su];
+      if constexpr (R == 1) {
+        w0l[u] = make_float4(a.s_wts[(int64_t)su * SREC + t], 0.f, 0.f, 0.f);
+        w0h[u] = w0l[u];
+      } else {
+        w0l[u] = rec[(int64_t)su * (SREC / 4) + 0];
+        w0h[u] = rec[(int64_t)su * (SREC / 4) + 1];
+      }
+      w1l[u] = rec[(int64_t)su * (SREC / 4) + 2];
+      w1h[u] = rec[(int64_t)su * (SREC / 4) + 3];
+      const float2* yr = ys + (int64_t)su * Jp + jo;
+      if constexpr (JG == 1) {
+        const float2 v = yr[0];
+        yv[u][0] = make_float4(v.x, v.y, 0.f, 0.f);
+      } else {
+#pragma unroll
+        for (int q = 0; q < YV; ++q) yv[u][q] = reinterpret_cast<const float4*>(yr)[q];
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      asm volatile("" : "+v"(w0l[u].x), "+v"(w0l[u].y), "+v"(w0l[u].z), "+v"(w0l[u].w));
+      asm volatile("" : "+v"(w0h[u].x), "+v"(w0h[u].y), "+v"(w0h[u].z), "+v"(w0h[u].w));
+      asm volatile("" : "+v"(w1l[u].x), "+v"(w1l[u].y), "+v"(w1l[u].z), "+v"(w1l[u].w));
+      asm volatile("" : "+v"(w1h[u].x), "+v"(w1h[u].y), "+v"(w1h[u].z), "+v"(w1h[u].w));
+      int t1 = c - col[u];
+      if (t1 < 0) t1 += a.g1;
+      const float w1 = (k + u < total ? 1.f : 0.f) * pick8(w1l[u], w1h[u], t1);
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const int t0 = i - R + 1 + tw[u];
+        float w0;
+        if constexpr (R == 1) {
+          w0 = w0l[u].x;
+        } else {
+          w0 = (t0 >= 0 && t0 < W) ? pick8(w0l[u], w0h[u], t0) : 0.f;
+        }
+        const float w = w0 * w1;
+        if constexpr (JG == 1) {
+          acc[i][0].x += w * yv[u][0].x;
+          acc[i][0].y += w * yv[u][0].y;
+        } else {
+#pragma unroll
+          for (int q = 0; q < YV; ++q) {
+            acc[i][2 * q].x += w * yv[u][q].x;
+            acc[i][2 * q].y += w * yv[u][q].y;
+            acc[i][2 * q + 1].x += w * yv[u][q].z;
+            acc[i][2 * q + 1].y += w * yv[u][q].w;
+          }
+        }
+      }
+    }
+  }
+  float sc = alpha * a.cscale;
+  if (scale_dev) sc *= *scale_dev;
+  const int64_t G = (int64_t)a.g0 * a.g1;
+#pragma unroll
+  for (int i = 0; i < R; ++i)
+#pragma unroll
+    for (int q = 0; q < JG; ++q)
+      if (r0 + i < a.g0 && jo + q < a.J)
+        grid[(int64_t)(jo + q) * G + (int64_t)(r0 + i) * a.g1 + c] = cscale(acc[i][q], sc);
+}
+
+template <int JG, int W>
+void launch_flat(const NufftArgs& a, const float2* ys, int Jp, float alpha, const float* scale_dev, float2* grid,
+                 hipStream_t st) {
+  constexpr int R = SPREAD_ROWS;
+  const int64_t waves = (int64_t)((a.g0 + R - 1) / R) * ((a.g1 + SPC - 1) / SPC) * (Jp / JG);
+  hipLaunchKernelGGL((spread_flat_kernel<JG, W, R, 2>), dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, a, ys,
+                     Jp, alpha, scale_dev, grid);
+}
+
+template <int JG>
+void launch_flat_w(const NufftArgs& a, const float2* ys, int Jp, float alpha, const float* scale_dev, float2* grid,
+                   hipStream_t st) {
+  switch (a.W) {
+    case 1: launch_flat<JG, 1>(a, ys, Jp, alpha, scale_dev, grid, st); break;
+    case 2: launch_flat<JG, 2>(a, ys, Jp, alpha, scale_dev, grid, st); break;
+    case 3: launch_flat<JG, 3>(a, ys, Jp, alpha, scale_dev, grid, st); break;
+    case 4: launch_flat<JG, 4>(a, ys, Jp, alpha, scale_dev, grid, st); break;
+    case 5: launch_flat<JG, 5>(a, ys, Jp, alpha, scale_dev, grid, st); break;
+    case 6: launch_flat<JG, 6>(a, ys, Jp, alpha, scale_dev, grid, st); break;
+    case 7: launch_flat<JG, 7>(a, ys, Jp, alpha, scale_dev, grid, st); break;
+    default: launch_flat<JG, 8>(a, ys, Jp, alpha, scale_dev, grid, st); break;
+  }
+}
+
+// Split kernel for the blocks with long sample chains (the dense centre of a radial
+// trajectory).  A workgroup takes SCOL = 64 / L columns of one such block and JG coils with
+// W * S waves; each column's window for row offset t0 is shared by S waves and L lanes of a
+// wave, which take every (S L)-th pair of samples, so the longest chain is S L times shorter.
+// The W S L partial sums of an output are added through LDS in the order (t0, wave
+// share, lane share): fixed, no atomics.
+constexpr int SPL = 8;              // lane shares per column
+constexpr int SCOL = SPC / SPL;     // columns per split workgroup
+
+__host__ __device__ constexpr int split_waves(int W) { return 12 / W > 1 ? 12 / W : 1; }
+
+template <int JG>
+__global__ __launch_bounds__(1024) void spread_split_kernel(NufftArgs a, const float2* __restrict__ ys, int Jp,
+                                                            float alpha, const float* __restrict__ scale_dev,
+                                                            float2* __restrict__ grid) {
+  extern __shared__ float2 spart[];  // [W S][JG][64]
+  const int W = a.W, S = split_waves(W);
+  const int bc = (a.g1 + SPC - 1) / SPC;
+  const int per_g = a.n_heavy * SPL;
+  const int jg = blockIdx.x / per_g, rem = blockIdx.x % per_g;
+  const int blk = a.s_hlist[rem / SPL];
+  const int r = blk / bc, c0 = (blk % bc) * SPC + (rem % SPL) * SCOL;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int t0 = wave % W, ws = wave / W;
+  const int cc = lane % SCOL, ls = lane / SCOL;
+  const int share = ws * SPL + ls, nshare = S * SPL;
+  const int c = c0 + cc;
+  const int jo = jg * JG;
   float2 acc[JG];
 #pragma unroll
   for (int q = 0; q < JG; ++q) acc[q] = make_float2(0.f, 0.f);
@@ -224,26 +398,29 @@ __global__ __launch_bounds__(8 * SPC) void spread_kernel(NufftArgs a, const floa
     const int32_t* cp = a.cell_ptr + (int64_t)row * a.g1;
     const int lo = c - W + 1;
     if (lo >= 0) {
-      spread_range<JG, 2>(a, ys, Jp, jo, c, t0, cp[lo], cp[c + 1], acc);
+      spread_range<JG, 2>(a, ys, Jp, jo, c, t0, cp[lo] + 2 * share, cp[c + 1], 2 * nshare, acc);
     } else {
-      spread_range<JG, 2>(a, ys, Jp, jo, c, t0, cp[a.g1 + lo], cp[a.g1], acc);
-      spread_range<JG, 2>(a, ys, Jp, jo, c, t0, cp[0], cp[c + 1], acc);
+      spread_range<JG, 2>(a, ys, Jp, jo, c, t0, cp[a.g1 + lo] + 2 * share, cp[a.g1], 2 * nshare, acc);
+      spread_range<JG, 2>(a, ys, Jp, jo, c, t0, cp[0] + 2 * share, cp[c + 1], 2 * nshare, acc);
     }
   }
 #pragma unroll
-  for (int q = 0; q < JG; ++q) part[t0][q][lane] = acc[q];
+  for (int q = 0; q < JG; ++q) spart[((int64_t)wave * JG + q) * 64 + lane] = acc[q];
   __syncthreads();
   float sc = alpha * a.cscale;
   if (scale_dev) sc *= *scale_dev;
   const int64_t G = (int64_t)a.g0 * a.g1;
-  for (int o = threadIdx.x; o < JG * SPC; o += W * SPC) {
-    const int q = o / SPC, l = o % SPC;
+  for (int o = threadIdx.x; o < JG * SCOL; o += blockDim.x) {
+    const int q = o / SCOL, l = o % SCOL;
     if (c0 + l >= a.g1 || jo + q >= a.J) continue;
-    float2 v = part[0][q][l];
-    for (int t = 1; t < W; ++t) {
-      v.x += part[t][q][l].x;
-      v.y += part[t][q][l].y;
-    }
+    float2 v = make_float2(0.f, 0.f);
+    for (int t = 0; t < W; ++t)
+      for (int w2 = 0; w2 < S; ++w2)
+        for (int l2 = 0; l2 < SPL; ++l2) {
+          const float2 p = spart[((int64_t)(t + W * w2) * JG + q) * 64 + l + SCOL * l2];
+          v.x += p.x;
+          v.y += p.y;
+        }
     grid[(int64_t)(jo + q) * G + (int64_t)r * a.g1 + c0 + l] = cscale(v, sc);
   }
 }
@@ -297,13 +474,22 @@ hipError_t spread_launch(const NufftArgs& a, const float2* y, float alpha, const
   if (a.W < 1 || a.W > 8) return hipErrorInvalidValue;
   if (a.M > 0)
     hipLaunchKernelGGL(spread_stage_kernel, dim3((unsigned)((a.M + STG - 1) / STG)), dim3(NT), 0, st, a, y, Jp, ys);
-  const unsigned nblk = (unsigned)((int64_t)a.g0 * ((a.g1 + SPC - 1) / SPC) * (Jp / jg));
-  const dim3 blk(SPC * a.W);
   switch (jg) {
-    case 1: hipLaunchKernelGGL(spread_kernel<1>, dim3(nblk), blk, 0, st, a, ys, Jp, alpha, scale_dev, grid); break;
-    case 2: hipLaunchKernelGGL(spread_kernel<2>, dim3(nblk), blk, 0, st, a, ys, Jp, alpha, scale_dev, grid); break;
-    case 4: hipLaunchKernelGGL(spread_kernel<4>, dim3(nblk), blk, 0, st, a, ys, Jp, alpha, scale_dev, grid); break;
-    default: hipLaunchKernelGGL(spread_kernel<8>, dim3(nblk), blk, 0, st, a, ys, Jp, alpha, scale_dev, grid); break;
+    case 1: launch_flat_w<1>(a, ys, Jp, alpha, scale_dev, grid, st); break;
+    case 2: launch_flat_w<2>(a, ys, Jp, alpha, scale_dev, grid, st); break;
+    case 4: launch_flat_w<4>(a, ys, Jp, alpha, scale_dev, grid, st); break;
+    default: launch_flat_w<8>(a, ys, Jp, alpha, scale_dev, grid, st); break;
+  }
+  if (a.n_heavy > 0) {
+    const int S = split_waves(a.W);
+    const dim3 sg((unsigned)((int64_t)a.n_heavy * SPL * (Jp / jg))), sb(64 * a.W * S);
+    const size_t lds = (size_t)a.W * S * jg * 64 * sizeof(float2);
+    switch (jg) {
+      case 1: hipLaunchKernelGGL(spread_split_kernel<1>, sg, sb, lds, st, a, ys, Jp, alpha, scale_dev, grid); break;
+      case 2: hipLaunchKernelGGL(spread_split_kernel<2>, sg, sb, lds, st, a, ys, Jp, alpha, scale_dev, grid); break;
+      case 4: hipLaunchKernelGGL(spread_split_kernel<4>, sg, sb, lds, st, a, ys, Jp, alpha, scale_dev, grid); break;
+      default: hipLaunchKernelGGL(spread_split_kernel<8>, sg, sb, lds, st, a, ys, Jp, alpha, scale_dev, grid); break;
+    }
   }
   return hipGetLastError();
 }

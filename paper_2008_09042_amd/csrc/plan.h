@@ -67,6 +67,9 @@ struct Plan {
   int32_t* d_sperm = nullptr;    // [M] original index of each sorted sample
   int32_t* d_scol = nullptr;     // [M] first-tap column of each sorted sample
   float* d_swts = nullptr;       // [M][16] tap weights in sorted order (axis 1 from slot 8)
+  uint8_t* d_sheavy = nullptr;   // [g0 ceil(g1 / 64)] spread blocks taken by the split kernel
+  int32_t* d_shlist = nullptr;   // [n_heavy] their indices
+  int n_heavy = 0;
   float2* d_twg[2] = {nullptr, nullptr};  // grid twiddles
   int nradg[2] = {0, 0};
   int radixg[2][12];

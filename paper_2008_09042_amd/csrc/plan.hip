@@ -11,6 +11,7 @@
 // of one call.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -194,6 +195,7 @@ NufftArgs nufft_args(const Plan& p) {
   a.iphi0 = p.d_iphi; a.iphi1 = p.d_iphi + p.n[0];
   a.base = p.d_base; a.wts = p.d_wts;
   a.cell_ptr = p.d_cptr; a.s_perm = p.d_sperm; a.s_col = p.d_scol; a.s_wts = p.d_swts;
+  a.s_heavy = p.n_heavy ? p.d_sheavy : nullptr; a.s_hlist = p.d_shlist; a.n_heavy = p.n_heavy;
   a.cscale = p.kscale;
   return a;
 }
@@ -374,6 +376,45 @@ static maxwell_status nufft_build(Plan& p, const maxwell_plan_desc& d) {
       }
     }
   }
+  // Longest sample sequence of each plain spread block (SPREAD_ROWS grid rows from r0,
+  // SPREAD_COLS columns): a lane of column c walks the W + R - 1 cell rows r0 + R - 1 - t and
+  // in each the W cells c - W + 1 .. c.  Blocks above the threshold go, row by row, to the
+  // split kernel.
+  int split_min = SPREAD_SPLIT_DEFAULT;
+  if (const char* env = std::getenv("MAXWELL_SPREAD_SPLIT")) split_min = std::max(0, std::atoi(env));
+  constexpr int R = SPREAD_ROWS;
+  const int bc = (p.g[1] + SPREAD_COLS - 1) / SPREAD_COLS;
+  const int nrg = (p.g[0] + R - 1) / R;
+  std::vector<uint8_t> heavy((size_t)nrg * bc, 0);
+  std::vector<int32_t> hlist;
+  {
+    std::vector<int32_t> win(ncell);  // samples in the W cells ending at (row, c)
+    for (int r = 0; r < p.g[0]; ++r)
+      for (int c = 0; c < p.g[1]; ++c) {
+        int32_t n = 0;
+        for (int t = 0; t < W; ++t) {
+          const int cc = ((c - t) % p.g[1] + p.g[1]) % p.g[1];
+          const size_t q = (size_t)r * p.g[1] + cc;
+          n += cptr[q + 1] - cptr[q];
+        }
+        win[(size_t)r * p.g[1] + c] = n;
+      }
+    for (int rg = 0; rg < nrg; ++rg)
+      for (int b = 0; b < bc; ++b) {
+        int32_t longest = 0;
+        for (int c = b * SPREAD_COLS; c < std::min(p.g[1], (b + 1) * SPREAD_COLS); ++c) {
+          int32_t n = 0;
+          for (int t = 0; t < W + R - 1; ++t)
+            n += win[(size_t)(((rg * R + R - 1 - t) % p.g[0] + p.g[0]) % p.g[0]) * p.g[1] + c];
+          longest = std::max(longest, n);
+        }
+        if (longest > split_min) {
+          heavy[(size_t)rg * bc + b] = 1;
+          for (int r = rg * R; r < std::min(p.g[0], rg * R + R); ++r) hlist.push_back(r * bc + b);
+        }
+      }
+  }
+  p.n_heavy = (int)hlist.size();
   auto up = [&](void** dst, const void* src, size_t bytes) -> hipError_t {
     hipError_t r = hipMalloc(dst, bytes ? bytes : 8);
     if (r != hipSuccess || !bytes) return r;
@@ -386,6 +427,8 @@ static maxwell_status nufft_build(Plan& p, const maxwell_plan_desc& d) {
   if ((e = up((void**)&p.d_sperm, sperm.data(), sperm.size() * sizeof(int32_t))) != hipSuccess) return hip_err(e);
   if ((e = up((void**)&p.d_scol, scol.data(), scol.size() * sizeof(int32_t))) != hipSuccess) return hip_err(e);
   if ((e = up((void**)&p.d_swts, swts.data(), swts.size() * sizeof(float))) != hipSuccess) return hip_err(e);
+  if ((e = up((void**)&p.d_sheavy, heavy.data(), heavy.size())) != hipSuccess) return hip_err(e);
+  if ((e = up((void**)&p.d_shlist, hlist.data(), hlist.size() * sizeof(int32_t))) != hipSuccess) return hip_err(e);
   return MAXWELL_OK;
 }
 
@@ -630,6 +673,8 @@ void plan_release(Plan& p) {
   if (p.d_sperm) (void)hipFree(p.d_sperm);
   if (p.d_scol) (void)hipFree(p.d_scol);
   if (p.d_swts) (void)hipFree(p.d_swts);
+  if (p.d_sheavy) (void)hipFree(p.d_sheavy);
+  if (p.d_shlist) (void)hipFree(p.d_shlist);
   p.d_iphi = nullptr;
   p.d_base = nullptr;
   p.d_wts = nullptr;
@@ -637,6 +682,9 @@ void plan_release(Plan& p) {
   p.d_sperm = nullptr;
   p.d_scol = nullptr;
   p.d_swts = nullptr;
+  p.d_sheavy = nullptr;
+  p.d_shlist = nullptr;
+  p.n_heavy = 0;
   for (auto e : p.timing.ev_start) (void)hipEventDestroy(e);
   for (auto e : p.timing.ev_stop) (void)hipEventDestroy(e);
   p.timing = Timing();
