@@ -12,12 +12,11 @@ struct NufftArgs {
   int64_t M;                  // samples per coil
   const float* iphi0;         // [n0] 1 / Phi((r0 - n0/2) / g0)
   const float* iphi1;         // [n1]
-  const int2* base;           // [M] grid index of the first tap on each axis (wrapped)
-  const float* wts;           // [M][2][W] tap weights phi(u - g) per axis
-  // the samples sorted by the cell (row-major) of their first tap, for the spread
+  // the samples sorted by the cell (row-major) of their first tap (spread and degrid)
   const int32_t* cell_ptr;    // [g0 * g1 + 1] CSR offsets of the cells into the sorted order
   const int32_t* s_perm;      // [M] original index of each sorted sample
   const int32_t* s_col;       // [M] first-tap column of each sorted sample
+  const int2* s_base;         // [M] first-tap (row, column) of each sorted sample
   const float* s_wts;         // [M][16] tap weights of each sorted sample: axis 0 in [0, W), axis 1 in [8, 8 + W)
   // spread blocks (SPREAD_ROWS grid rows, 64 columns) in which some lane's sample sequence
   // exceeds the split threshold: skipped by the plain kernel, their rows taken one by one

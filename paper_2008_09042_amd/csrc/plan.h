@@ -61,12 +61,11 @@ struct Plan {
   int W = 0;                     // kernel width
   float kscale = 1.0f;           // sqrt(g0 g1 / N)
   float* d_iphi = nullptr;       // [n0 + n1] inverse deapodisation per axis
-  int2* d_base = nullptr;        // [M] first tap per axis (wrapped grid index)
-  float* d_wts = nullptr;        // [M][2][W] tap weights
   int32_t* d_cptr = nullptr;     // [g0 g1 + 1] samples sorted by first-tap cell (CSR)
   int32_t* d_sperm = nullptr;    // [M] original index of each sorted sample
   int32_t* d_scol = nullptr;     // [M] first-tap column of each sorted sample
   float* d_swts = nullptr;       // [M][16] tap weights in sorted order (axis 1 from slot 8)
+  int2* d_sbase = nullptr;       // [M] first-tap (row, column) in sorted order
   uint8_t* d_sheavy = nullptr;   // [g0 ceil(g1 / 64)] spread blocks taken by the split kernel
   int32_t* d_shlist = nullptr;   // [n_heavy] their indices
   int n_heavy = 0;

@@ -193,8 +193,7 @@ NufftArgs nufft_args(const Plan& p) {
   a.g0 = p.g[0]; a.g1 = p.g[1];
   a.J = p.J; a.W = p.W; a.M = p.M;
   a.iphi0 = p.d_iphi; a.iphi1 = p.d_iphi + p.n[0];
-  a.base = p.d_base; a.wts = p.d_wts;
-  a.cell_ptr = p.d_cptr; a.s_perm = p.d_sperm; a.s_col = p.d_scol; a.s_wts = p.d_swts;
+  a.cell_ptr = p.d_cptr; a.s_perm = p.d_sperm; a.s_col = p.d_scol; a.s_wts = p.d_swts; a.s_base = p.d_sbase;
   a.s_heavy = p.n_heavy ? p.d_sheavy : nullptr; a.s_hlist = p.d_shlist; a.n_heavy = p.n_heavy;
   a.cscale = p.kscale;
   return a;
@@ -361,6 +360,7 @@ static maxwell_status nufft_build(Plan& p, const maxwell_plan_desc& d) {
   // counting sort of the samples by first-tap cell (stable: equal cells keep sample order)
   const size_t ncell = (size_t)p.g[0] * p.g[1];
   std::vector<int32_t> cptr(ncell + 1, 0), sperm((size_t)M), scol((size_t)M);
+  std::vector<int2> sbase((size_t)M);
   std::vector<float> swts((size_t)M * 16, 0.f);  // per sorted sample: w0 in [0, 8), w1 in [8, 16)
   for (int64_t m = 0; m < M; ++m) ++cptr[(size_t)cell[m] + 1];
   for (size_t q = 0; q < ncell; ++q) cptr[q + 1] += cptr[q];
@@ -370,6 +370,7 @@ static maxwell_status nufft_build(Plan& p, const maxwell_plan_desc& d) {
       const int32_t s = fill[cell[m]]++;
       sperm[s] = (int32_t)m;
       scol[s] = base[m].y;
+      sbase[s] = base[m];
       for (int t = 0; t < W; ++t) {
         swts[(size_t)s * 16 + t] = wts[(size_t)m * 2 * W + t];
         swts[(size_t)s * 16 + 8 + t] = wts[(size_t)m * 2 * W + W + t];
@@ -421,12 +422,11 @@ static maxwell_status nufft_build(Plan& p, const maxwell_plan_desc& d) {
     return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
   };
   if ((e = up((void**)&p.d_iphi, iphi.data(), iphi.size() * sizeof(float))) != hipSuccess) return hip_err(e);
-  if ((e = up((void**)&p.d_base, base.data(), base.size() * sizeof(int2))) != hipSuccess) return hip_err(e);
-  if ((e = up((void**)&p.d_wts, wts.data(), wts.size() * sizeof(float))) != hipSuccess) return hip_err(e);
   if ((e = up((void**)&p.d_cptr, cptr.data(), cptr.size() * sizeof(int32_t))) != hipSuccess) return hip_err(e);
   if ((e = up((void**)&p.d_sperm, sperm.data(), sperm.size() * sizeof(int32_t))) != hipSuccess) return hip_err(e);
   if ((e = up((void**)&p.d_scol, scol.data(), scol.size() * sizeof(int32_t))) != hipSuccess) return hip_err(e);
   if ((e = up((void**)&p.d_swts, swts.data(), swts.size() * sizeof(float))) != hipSuccess) return hip_err(e);
+  if ((e = up((void**)&p.d_sbase, sbase.data(), sbase.size() * sizeof(int2))) != hipSuccess) return hip_err(e);
   if ((e = up((void**)&p.d_sheavy, heavy.data(), heavy.size())) != hipSuccess) return hip_err(e);
   if ((e = up((void**)&p.d_shlist, hlist.data(), hlist.size() * sizeof(int32_t))) != hipSuccess) return hip_err(e);
   return MAXWELL_OK;
@@ -667,21 +667,19 @@ void plan_release(Plan& p) {
     p.d_twg[ax] = nullptr;
   }
   if (p.d_iphi) (void)hipFree(p.d_iphi);
-  if (p.d_base) (void)hipFree(p.d_base);
-  if (p.d_wts) (void)hipFree(p.d_wts);
   if (p.d_cptr) (void)hipFree(p.d_cptr);
   if (p.d_sperm) (void)hipFree(p.d_sperm);
   if (p.d_scol) (void)hipFree(p.d_scol);
   if (p.d_swts) (void)hipFree(p.d_swts);
+  if (p.d_sbase) (void)hipFree(p.d_sbase);
   if (p.d_sheavy) (void)hipFree(p.d_sheavy);
   if (p.d_shlist) (void)hipFree(p.d_shlist);
   p.d_iphi = nullptr;
-  p.d_base = nullptr;
-  p.d_wts = nullptr;
   p.d_cptr = nullptr;
   p.d_sperm = nullptr;
   p.d_scol = nullptr;
   p.d_swts = nullptr;
+  p.d_sbase = nullptr;
   p.d_sheavy = nullptr;
   p.d_shlist = nullptr;
   p.n_heavy = 0;
