@@ -485,7 +485,11 @@ def bench_kernels2d(args, torch):
                                      gemm_bytes),
                 "gemm_dense_adjoint": ("mfma", gemm_flops, PEAKS_TFLOPS["bf16" if prec == "bf16_split" else "fp32"],
                                        gemm_bytes),
-                "fft_axis": ("hbm", 16.0 * J * fft_n, None, None),
+                # Cartesian: the mask is applied in the last forward and the first inverse
+                # pass (8 B per element in, 8 B per sample and 4 B of inverse mask per point
+                # out, and the reverse), so the four passes move 48 J N + 16 J M + 8 N bytes
+                "fft_axis": ("hbm", 16.0 * J * fft_n if G else (48.0 * J * N + 16.0 * J * M + 8.0 * N) / 4, None,
+                             None),
                 "gather": ("hbm", 8.0 * J * M * 2 + 4.0 * M, None, None),
                 "scatter": ("hbm", 8.0 * J * (M + N) + 4.0 * N, None, None),
                 "nufft_degrid": ("hbm", 8.0 * J * (G + M) + M * (8.0 + 48.0), None, None),

@@ -62,6 +62,14 @@ struct FftAxisArgs {
   int nrad; int radix[12];
   // optional image premultiply (forward, first axis pass): m = x[img_index] * src
   const float2* premul; int64_t outer_per_coil;
+  // optional Cartesian sampling fused into the pass (index p within a coil of N elements,
+  // coil j): the first inverse pass reads samples[j][inv[p]] (zero where inv[p] < 0) in
+  // place of src; the last forward pass writes samples[j][inv[p]] for inv[p] >= 0 in place
+  // of data.  Needs J N < 2^32 and M > 0.
+  const int32_t* in_inv; const float2* in_samples;
+  const int32_t* out_inv; float2* out_samples;
+  int64_t coil_elems, nsamples;  // N, M
+  uint32_t coil_magic, coil_shift;  // multiply-high division by N (set by fft_axis_launch)
   int lines;              // lines per workgroup (set by fft_axis_launch)
 };
 hipError_t fft_axis_launch(const FftAxisArgs& a, hipStream_t st);

@@ -29,8 +29,9 @@ constexpr int TW_LDS_MAX = 1024;    // twiddle tables up to this length are stag
 // complex elements of the LDS tile for T lines of length n
 __host__ __device__ inline int tile_elems(int n, int T, bool contiguous) { return contiguous ? T * (n + 1) : T * n; }
 
-// TWL: the twiddle table is copied into LDS behind the tile.
-template <bool TWL>
+// TWL: the twiddle table is copied into LDS behind the tile.  SMP: 1 the input comes from
+// the samples through the inverse mask, 2 the output goes to them.
+template <bool TWL, int SMP>
 __global__ __launch_bounds__(NT) void fft_axis_kernel(FftAxisArgs a) {
   extern __shared__ float2 lds[];
   const int n = (int)a.n;
@@ -67,6 +68,7 @@ __global__ __launch_bounds__(NT) void fft_axis_kernel(FftAxisArgs a) {
   // element e of the tile: (line, index) = (e / n, e % n) for contiguous lines, else
   // (e % T, e / T), so that consecutive threads touch consecutive addresses
   const FastDiv fd = fast_div((uint32_t)(a.inner == 1 ? n : tg.T));
+  const FastDiv fN = {(uint32_t)a.coil_elems, a.coil_magic, a.coil_shift};
   // ---- load (with optional image premultiply and the input chessboard sign); LU
   // elements per thread are loaded before any is stored, so their latencies overlap
   // (an element past the tile reads the tile's first element and is masked to zero)
@@ -86,7 +88,16 @@ __global__ __launch_bounds__(NT) void fft_axis_kernel(FftAxisArgs a) {
       keep[u] = ok ? ((i & 1) ? 0xffffffffu : 0x7fffffffu) : 0u;  // sign bit kept only for odd i
       li[u] = e < total ? l * tg.LS + i * tg.ES : -1;
       const int64_t gidx = ok ? gbase + (int64_t)l * (a.inner == 1 ? a.n : 1) + (int64_t)i * a.inner : gbase;
-      v[u] = a.src[gidx];
+      if constexpr (SMP == 1) {
+        // the sample of this k-space point, or zero: both loads unconditional (index 0 when
+        // unsampled), the zero applied by the mask below
+        const uint32_t f = (uint32_t)gidx, j = fdiv(f, fN), pp = f - j * (uint32_t)fN.d;
+        const int m = a.in_inv[pp];
+        v[u] = a.in_samples[(int64_t)j * a.nsamples + (m >= 0 ? m : 0)];
+        if (m < 0) keep[u] = 0u;
+      } else {
+        v[u] = a.src[gidx];
+      }
       if (a.premul) {
         const int64_t o = a.inner == 1 ? o0 + (ok ? l : 0) : o0;
         const int64_t oc = a.outer < 0x7fffffffLL ? (int64_t)((uint32_t)o % (uint32_t)a.outer_per_coil)
@@ -130,7 +141,14 @@ __global__ __launch_bounds__(NT) void fft_axis_kernel(FftAxisArgs a) {
       const int l = a.inner == 1 ? qd : rm, i = a.inner == 1 ? rm : qd;
       if (e >= total || l >= Tvalid) continue;
       const float s = (i & 1) ? -scale : scale;
-      a.data[gbase + (int64_t)l * (a.inner == 1 ? a.n : 1) + (int64_t)i * a.inner] = cscale(v[u], s);
+      const int64_t gidx = gbase + (int64_t)l * (a.inner == 1 ? a.n : 1) + (int64_t)i * a.inner;
+      if constexpr (SMP == 2) {
+        const uint32_t f = (uint32_t)gidx, j = fdiv(f, fN), pp = f - j * (uint32_t)fN.d;
+        const int m = a.out_inv[pp];
+        if (m >= 0) a.out_samples[(int64_t)j * a.nsamples + m] = cscale(v[u], s);
+      } else {
+        a.data[gidx] = cscale(v[u], s);
+      }
     }
   }
 }
@@ -176,10 +194,28 @@ hipError_t fft_axis_launch(const FftAxisArgs& args, hipStream_t st) {
   const int64_t blocks = contiguous ? (a.outer + T - 1) / T : a.outer * ((a.inner + T - 1) / T);
   if (blocks <= 0) return hipSuccess;
   const size_t lds = (size_t)(tile_elems(n, a.lines, contiguous) + (twl ? n : 0)) * sizeof(float2);
-  if (twl)
-    hipLaunchKernelGGL(fft_axis_kernel<true>, dim3((unsigned)blocks), dim3(NT), lds, st, a);
-  else
-    hipLaunchKernelGGL(fft_axis_kernel<false>, dim3((unsigned)blocks), dim3(NT), lds, st, a);
+  const int smp = a.in_inv ? 1 : a.out_inv ? 2 : 0;
+  if (smp && (a.in_inv && a.out_inv)) return hipErrorInvalidValue;
+  // element indices j N + p below 2^31, so the multiply-high division of the flat index by
+  // N is exact; its magic number in integer arithmetic (Granlund and Montgomery)
+  if (smp && (a.nsamples <= 0 || a.coil_elems <= 0 || a.outer / a.outer_per_coil * a.coil_elems > 0x7fffffffLL))
+    return hipErrorInvalidValue;
+  if (smp) {
+    const uint64_t d = (uint64_t)a.coil_elems;
+    uint32_t l = 0;
+    while ((1ull << l) < d) ++l;
+    a.coil_shift = l;
+    a.coil_magic = (uint32_t)((((1ull << l) - d) << 32) / d + 1);
+  }
+  const dim3 gr((unsigned)blocks), bl(NT);
+  switch (smp * 2 + (twl ? 1 : 0)) {
+    case 1: hipLaunchKernelGGL((fft_axis_kernel<true, 0>), gr, bl, lds, st, a); break;
+    case 0: hipLaunchKernelGGL((fft_axis_kernel<false, 0>), gr, bl, lds, st, a); break;
+    case 3: hipLaunchKernelGGL((fft_axis_kernel<true, 1>), gr, bl, lds, st, a); break;
+    case 2: hipLaunchKernelGGL((fft_axis_kernel<false, 1>), gr, bl, lds, st, a); break;
+    case 5: hipLaunchKernelGGL((fft_axis_kernel<true, 2>), gr, bl, lds, st, a); break;
+    default: hipLaunchKernelGGL((fft_axis_kernel<false, 2>), gr, bl, lds, st, a); break;
+  }
   return hipGetLastError();
 }
 

@@ -148,8 +148,11 @@ template <typename T>
 T* wsp(void* ws, size_t off) { return reinterpret_cast<T*>(reinterpret_cast<char*>(ws) + off); }
 
 // Centred unitary DFT over every axis of J stacked arrays of shape dims[0..nd).
+// Axis passes over [J][dims]; optionally the first pass reads the samples through the inverse
+// mask (in_samples [J][M]) and the last writes them (out_samples).
 hipError_t fft_dims(const Plan& p, const float2* src, float2* dst, int dir, const float2* premul, int nd,
-                    const int64_t* dims, float2* const* tw, const int* nrad, const int (*radix)[12], hipStream_t st) {
+                    const int64_t* dims, float2* const* tw, const int* nrad, const int (*radix)[12], hipStream_t st,
+                    const float2* in_samples = nullptr, float2* out_samples = nullptr) {
   const float2* cur = src;
   for (int t = 0; t < nd; ++t) {
     const int d = nd - 1 - t;
@@ -169,6 +172,16 @@ hipError_t fft_dims(const Plan& p, const float2* src, float2* dst, int dir, cons
     a.nrad = nrad[d];
     for (int q = 0; q < nrad[d]; ++q) a.radix[q] = radix[d][q];
     a.premul = (t == 0) ? premul : nullptr;
+    if (t == 0 && in_samples) {
+      a.in_inv = p.d_inv;
+      a.in_samples = in_samples;
+    }
+    if (t == nd - 1 && out_samples) {
+      a.out_inv = p.d_inv;
+      a.out_samples = out_samples;
+    }
+    a.coil_elems = p.N;
+    a.nsamples = p.M;
     hipError_t e = TIMED("fft_axis", fft_axis_launch(a, st));
     if (e != hipSuccess) return e;
     cur = dst;
@@ -873,6 +886,12 @@ static hipError_t fused_adjoint(const Plan& p, const float2* x, const float2* c,
   return hipSuccess;
 }
 
+// The Cartesian mask is applied inside the first inverse and the last forward FFT pass
+// (no separate gather or scatter) when there are samples and J N < 2^31.
+static bool fuse_sampling(const Plan& p) {
+  return p.sampling == MAXWELL_CARTESIAN && p.M > 0 && p.ndim >= 2 && p.d_inv && (int64_t)p.J * p.N < 0x7fffffffLL;
+}
+
 // y = F_s(S (.) x) for coil maps S [J][N] already in memory (general path)
 static hipError_t encode_maps(const Plan& p, const float2* S, const float2* x, float2* y, void* ws, hipStream_t st) {
   hipError_t e;
@@ -884,6 +903,8 @@ static hipError_t encode_maps(const Plan& p, const float2* S, const float2* x, f
     return TIMED("nufft_degrid", degrid_launch(na, G, y, st));
   }
   float2* Kb = wsp<float2>(ws, p.off_K);
+  if (fuse_sampling(p))  // the last pass writes the sampled points straight to y
+    return fft_dims(p, S, Kb, -1, x, p.ndim, p.n, p.d_tw, p.nrad, p.radix, st, nullptr, y);
   if ((e = fft_image(p, S, Kb, -1, x, st)) != hipSuccess) return e;
   return TIMED("gather", gather_launch(Kb, p.N, p.d_mask, p.M, p.J, y, st));
 }
@@ -930,8 +951,14 @@ static hipError_t adjoint_maps(const Plan& p, const float2* S, const float2* x, 
     alpha = 1.0f;  // the scale was applied by the spread
     scale_dev = nullptr;
   } else {
-    if ((e = TIMED("scatter", scatter_launch(y, p.M, p.d_inv, p.N, p.J, Kb, st))) != hipSuccess) return e;
-    if ((e = fft_image(p, Kb, Kb, +1, nullptr, st)) != hipSuccess) return e;
+    if (fuse_sampling(p)) {  // the first pass reads the samples through the inverse mask
+      if ((e = fft_dims(p, Kb, Kb, +1, nullptr, p.ndim, p.n, p.d_tw, p.nrad, p.radix, st, y, nullptr)) !=
+          hipSuccess)
+        return e;
+    } else {
+      if ((e = TIMED("scatter", scatter_launch(y, p.M, p.d_inv, p.N, p.J, Kb, st))) != hipSuccess) return e;
+      if ((e = fft_image(p, Kb, Kb, +1, nullptr, st)) != hipSuccess) return e;
+    }
   }
   return TIMED("adjoint_combine", adjoint_combine_launch(S, Kb, x, p.N, p.J, alpha, scale_dev, gx, want_h ? 1 : 0, st));
 }
