@@ -22,8 +22,9 @@ struct NufftArgs {
   // exceeds the split threshold: skipped by the plain kernel, their rows taken one by one
   // by the split kernel
   const uint8_t* s_heavy;     // [ceil(g0 / SPREAD_ROWS) * ceil(g1 / 64)] 1 for a split block (may be null)
-  const int32_t* s_hlist;     // [n_heavy] split rows: row * ceil(g1 / 64) + column block
-  int n_heavy;
+  const int32_t* s_hlist;     // [n_heavy] split rows: row * ceil(g1 / 64) + column block; the
+                              // first n_med from blocks at most 4x over the threshold
+  int n_heavy, n_med;
   float cscale;               // sqrt(g0 g1 / (n0 n1)): unitary DFT -> the operator's scaling
 };
 

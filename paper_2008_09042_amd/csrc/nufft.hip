@@ -369,11 +369,10 @@ void launch_flat_w(const NufftArgs& a, const float2* ys, int Jp, float alpha, co
 // Split kernel for the blocks with long sample chains (the dense centre of a radial
 // trajectory).  A workgroup takes SCOL = 64 / L columns of one such block and JG coils with
 // W * S waves; each column's window for row offset t0 is shared by S waves and L lanes of a
-// wave, which take every (S L)-th pair of samples, so the longest chain is S L times shorter.
+// wave, which take every (S L)-th pair of samples, so the longest chain is S L times shorter
+// (L = 2 for the moderately long blocks, 8 for the longest).
 // The W S L partial sums of an output are added through LDS in the order (t0, wave
 // share, lane share): fixed, no atomics.
-constexpr int SPL = 8;              // lane shares per column
-constexpr int SCOL = SPC / SPL;     // columns per split workgroup
 
 __host__ __device__ constexpr int split_waves(int W) { return 12 / W > 1 ? 12 / W : 1; }
 
@@ -384,10 +383,22 @@ __global__ __launch_bounds__(1024) void spread_split_kernel(NufftArgs a, const f
   extern __shared__ float2 spart[];  // [W S][JG][64]
   const int W = a.W, S = split_waves(W);
   const int bc = (a.g1 + SPC - 1) / SPC;
-  const int per_g = a.n_heavy * SPL;
-  const int jg = blockIdx.x / per_g, rem = blockIdx.x % per_g;
-  const int blk = a.s_hlist[rem / SPL];
-  const int r = blk / bc, c0 = (blk % bc) * SPC + (rem % SPL) * SCOL;
+  // per coil group: 2 workgroups for each of the first n_med rows, 8 for each of the others
+  const int per_g = 2 * a.n_med + 8 * (a.n_heavy - a.n_med);
+  const int jg = blockIdx.x / per_g;
+  int rem = blockIdx.x % per_g, SPL = 2, h;
+  if (rem < 2 * a.n_med) {
+    h = rem / 2;
+    rem %= 2;
+  } else {
+    rem -= 2 * a.n_med;
+    SPL = 8;
+    h = a.n_med + rem / 8;
+    rem %= 8;
+  }
+  const int SCOL = SPC / SPL;  // columns per workgroup
+  const int blk = a.s_hlist[h];
+  const int r = blk / bc, c0 = (blk % bc) * SPC + rem * SCOL;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int t0 = wave % W, ws = wave / W;
   const int cc = lane % SCOL, ls = lane / SCOL;
@@ -485,9 +496,9 @@ hipError_t spread_launch(const NufftArgs& a, const float2* y, float alpha, const
     case 4: launch_flat_w<4>(a, ys, Jp, alpha, scale_dev, grid, st); break;
     default: launch_flat_w<8>(a, ys, Jp, alpha, scale_dev, grid, st); break;
   }
-  if (a.n_heavy > 0) {
+  if (a.n_heavy > 0) {  // one launch for both kinds of split rows
     const int S = split_waves(a.W);
-    const dim3 sg((unsigned)((int64_t)a.n_heavy * SPL * (Jp / jg))), sb(64 * a.W * S);
+    const dim3 sg((unsigned)((int64_t)(2 * a.n_med + 8 * (a.n_heavy - a.n_med)) * (Jp / jg))), sb(64 * a.W * S);
     const size_t lds = (size_t)a.W * S * jg * 64 * sizeof(float2);
     switch (jg) {
       case 1: hipLaunchKernelGGL(spread_split_kernel<1>, sg, sb, lds, st, a, ys, Jp, alpha, scale_dev, grid); break;

@@ -68,7 +68,7 @@ struct Plan {
   int2* d_sbase = nullptr;       // [M] first-tap (row, column) in sorted order
   uint8_t* d_sheavy = nullptr;   // [g0 ceil(g1 / 64)] spread blocks taken by the split kernel
   int32_t* d_shlist = nullptr;   // [n_heavy] their indices
-  int n_heavy = 0;
+  int n_heavy = 0, n_med = 0;
   float2* d_twg[2] = {nullptr, nullptr};  // grid twiddles
   int nradg[2] = {0, 0};
   int radixg[2][12];

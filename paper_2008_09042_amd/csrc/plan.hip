@@ -208,6 +208,7 @@ NufftArgs nufft_args(const Plan& p) {
   a.iphi0 = p.d_iphi; a.iphi1 = p.d_iphi + p.n[0];
   a.cell_ptr = p.d_cptr; a.s_perm = p.d_sperm; a.s_col = p.d_scol; a.s_wts = p.d_swts; a.s_base = p.d_sbase;
   a.s_heavy = p.n_heavy ? p.d_sheavy : nullptr; a.s_hlist = p.d_shlist; a.n_heavy = p.n_heavy;
+  a.n_med = p.n_med;
   a.cscale = p.kscale;
   return a;
 }
@@ -400,7 +401,7 @@ static maxwell_status nufft_build(Plan& p, const maxwell_plan_desc& d) {
   const int bc = (p.g[1] + SPREAD_COLS - 1) / SPREAD_COLS;
   const int nrg = (p.g[0] + R - 1) / R;
   std::vector<uint8_t> heavy((size_t)nrg * bc, 0);
-  std::vector<int32_t> hlist;
+  std::vector<int32_t> hlist, hot;  // split rows of moderately long and of the longest blocks
   {
     std::vector<int32_t> win(ncell);  // samples in the W cells ending at (row, c)
     for (int r = 0; r < p.g[0]; ++r)
@@ -424,10 +425,13 @@ static maxwell_status nufft_build(Plan& p, const maxwell_plan_desc& d) {
         }
         if (longest > split_min) {
           heavy[(size_t)rg * bc + b] = 1;
-          for (int r = rg * R; r < std::min(p.g[0], rg * R + R); ++r) hlist.push_back(r * bc + b);
+          std::vector<int32_t>& dst = longest > 4 * std::max(split_min, 1) ? hot : hlist;
+          for (int r = rg * R; r < std::min(p.g[0], rg * R + R); ++r) dst.push_back(r * bc + b);
         }
       }
   }
+  p.n_med = (int)hlist.size();
+  hlist.insert(hlist.end(), hot.begin(), hot.end());
   p.n_heavy = (int)hlist.size();
   auto up = [&](void** dst, const void* src, size_t bytes) -> hipError_t {
     hipError_t r = hipMalloc(dst, bytes ? bytes : 8);
@@ -696,6 +700,7 @@ void plan_release(Plan& p) {
   p.d_sheavy = nullptr;
   p.d_shlist = nullptr;
   p.n_heavy = 0;
+  p.n_med = 0;
   for (auto e : p.timing.ev_start) (void)hipEventDestroy(e);
   for (auto e : p.timing.ev_stop) (void)hipEventDestroy(e);
   p.timing = Timing();
