@@ -61,9 +61,9 @@ def parse():
 
 
 def make_inputs():
-    from synth import CONFIGS, make_problem
+    from synth import problem
     t0 = time.time()
-    p = make_problem(4, **CONFIGS[4])
+    p = problem("cart3d_128_tucker40x300_j32")
     log(f"[bench] inputs generated in {time.time() - t0:.1f}s: dims {p.dims} J {p.J} K {p.K} M {p.M}")
     return p
 
@@ -220,7 +220,7 @@ def bench_batch(args, torch):
     from synth import BATCH, slice_problems
     dev = torch.device("cuda:0")
     t0 = time.time()
-    ps = slice_problems(config=5, n_slices=BATCH["n_slices"])
+    ps = slice_problems(seed=5, n_slices=BATCH["n_slices"])
     log(f"[bench] {len(ps)} slices generated in {time.time() - t0:.1f}s")
     T = lambda a: torch.from_numpy(np.ascontiguousarray(np.asarray(a).astype(np.complex64))).to(dev)  # noqa: E731
     plans, xs, cs, ys = [], [], [], []
@@ -360,10 +360,10 @@ def bench_admm(args, torch):
     20 TV steps and 5 CG steps.  Coil maps: the workload's basis times its coefficients,
     scaled to order-one sensitivities.  Prints one JSON line."""
     from paper_2008_09042_amd.encoding import MaxwellPlan
-    from synth import CONFIGS, make_problem
+    from synth import problem
     dev = torch.device("cuda:0")
     t0 = time.time()
-    p = make_problem(2, **CONFIGS[2])
+    p = problem("cart2d_256_dense200_j32")
     log(f"[bench] inputs generated in {time.time() - t0:.1f}s: dims {p.dims} J {p.J} K {p.K} M {p.M}")
     T = lambda a: torch.from_numpy(np.ascontiguousarray(np.asarray(a).astype(np.complex64))).to(dev)  # noqa: E731
     plan = MaxwellPlan(p.dims, p.J, B=T(p.B), mask_idx=p.mask_idx, precision="fp32", device=dev)
@@ -455,13 +455,12 @@ def bench_kernels2d(args, torch):
     time; algorithmic bytes count each array once (complex64 8 B, FP32 4 B, index 4 B).
     Prints one JSON line."""
     from paper_2008_09042_amd.encoding import MaxwellPlan
-    from synth import CONFIGS, make_problem
+    from synth import problem
     dev = torch.device("cuda:0")
     T = lambda a: torch.from_numpy(np.ascontiguousarray(np.asarray(a).astype(np.complex64))).to(dev)  # noqa: E731
     res = {}
-    for cfg in (2, 3):
-        p = make_problem(cfg, **CONFIGS[cfg])
-        name = CONFIGS[cfg]["name"]
+    for name in ("cart2d_256_dense200_j32", "radial2d_256_dense128_j16"):
+        p = problem(name)
         kw = dict(mask_idx=p.mask_idx) if p.traj is None else dict(traj=p.traj, weights=p.weights)
         N, J, K, M = int(np.prod(p.dims)), p.J, p.K, p.M
         for prec in ("bf16_split", "fp32"):

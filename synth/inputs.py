@@ -1,8 +1,9 @@
 """Seeded input generators (NumPy, FP64).
 
-Every random draw comes from ``rng_for(config, role)``, a
-``numpy.random.Generator`` seeded by ``SeedSequence([config, role])``, so the
-same (config, role) pair always yields the same data on any machine.
+Every random draw comes from ``rng_for(seed, role)``, a
+``numpy.random.Generator`` seeded by ``SeedSequence([seed, role])``, so the
+same (seed, role) pair always yields the same data on any machine; each
+workload carries its own seed.
 
 Roles: 1 phantom, 2 basis, 3 true coefficients, 4 mask / trajectory,
 5 noise, 6 evaluation point (x0, c0), 7 finite-difference directions.
@@ -41,14 +42,14 @@ __all__ = [
     "rng_for", "complex_normal", "pixel_coords", "phantom", "smooth_dense_basis",
     "smooth_factor", "tucker_basis", "coefficients", "line_mask", "poisson_disc_plane",
     "plane_mask_to_lines", "plane_mask_to_indices", "golden_angle_radial", "ramp_dcf",
-    "unit_noise", "noise_scale_for_snr", "Problem", "make_problem", "CONFIGS",
+    "unit_noise", "noise_scale_for_snr", "Problem", "make_problem", "problem", "WORKLOADS",
     "BATCH", "slice_rng", "vd_random_mask", "slice_problems",
 ]
 
 
-def rng_for(config: int, role: int) -> np.random.Generator:
-    """Generator for one (config, role) pair."""
-    return np.random.default_rng(np.random.SeedSequence([int(config), int(role)]))
+def rng_for(seed: int, role: int) -> np.random.Generator:
+    """Generator for one (seed, role) pair."""
+    return np.random.default_rng(np.random.SeedSequence([int(seed), int(role)]))
 
 
 def complex_normal(rng: np.random.Generator, shape) -> np.ndarray:
@@ -357,7 +358,7 @@ class Problem:
         return int(self.traj.shape[0])
 
 
-def make_problem(config: int, name: str, dims, J: int, K: int, basis_kind: str = "dense",
+def make_problem(seed: int, name: str, dims, J: int, K: int, basis_kind: str = "dense",
                  degree: int = 6, kmax: float = 3.0, ranks=None, sampling: str = "cartesian",
                  mask: str = "lines", R: float = 4.0, centre: int = 16, n_spokes: int = 64,
                  n_read: Optional[int] = None, snr_db: float = 40.0) -> Problem:
@@ -365,12 +366,12 @@ def make_problem(config: int, name: str, dims, J: int, K: int, basis_kind: str =
     dims = tuple(int(n) for n in dims)
     p = Problem(name=name, dims=dims, J=J, K=K, basis_kind=basis_kind, sampling=sampling,
                 snr_db=snr_db)
-    rb = rng_for(config, ROLE_BASIS)
+    rb = rng_for(seed, ROLE_BASIS)
     if basis_kind == "dense":
         p.B = smooth_dense_basis(rb, dims, K, degree, kmax)
     else:
         p.U, p.core = tucker_basis(rb, dims, ranks, K, degree, kmax)
-    rs = rng_for(config, ROLE_SAMPLING)
+    rs = rng_for(seed, ROLE_SAMPLING)
     if sampling == "cartesian":
         if mask == "lines":
             p.mask_idx = line_mask(dims, int(R), centre)
@@ -387,33 +388,39 @@ def make_problem(config: int, name: str, dims, J: int, K: int, basis_kind: str =
         nr = n_read if n_read is not None else 2 * max(dims)
         p.traj = golden_angle_radial(dims, n_spokes, nr)
         p.weights = ramp_dcf(p.traj, dims, nr)
-    p.x_true = phantom(rng_for(config, ROLE_PHANTOM), dims)
-    p.c_true = coefficients(rng_for(config, ROLE_CTRUE), J, K)
-    p.noise = unit_noise(rng_for(config, ROLE_NOISE), J, p.M)
-    re = rng_for(config, ROLE_EVAL)
+    p.x_true = phantom(rng_for(seed, ROLE_PHANTOM), dims)
+    p.c_true = coefficients(rng_for(seed, ROLE_CTRUE), J, K)
+    p.noise = unit_noise(rng_for(seed, ROLE_NOISE), J, p.M)
+    re = rng_for(seed, ROLE_EVAL)
     p.x0 = phantom(re, dims)
     p.c0 = coefficients(re, J, K)
     return p
 
 
-# The five workloads.  Each entry is the keyword set for make_problem.
-CONFIGS = {
-    1: dict(name="cart2d_64_dense32_j8", dims=(64, 64), J=8, K=32, basis_kind="dense",
-            degree=6, kmax=3.0, sampling="cartesian", mask="lines", R=4, centre=16),
-    2: dict(name="cart2d_256_dense200_j32", dims=(256, 256), J=32, K=200, basis_kind="dense",
-            degree=10, kmax=5.0, sampling="cartesian", mask="pd2d", R=6.0, centre=24),
-    3: dict(name="radial2d_256_dense128_j16", dims=(256, 256), J=16, K=128, basis_kind="dense",
-            degree=10, kmax=5.0, sampling="radial", n_spokes=64, n_read=512),
-    4: dict(name="cart3d_128_tucker40x300_j32", dims=(128, 128, 128), J=32, K=300,
-            basis_kind="tucker", ranks=(40, 40, 40), degree=6, kmax=3.0, sampling="cartesian",
-            mask="pd3d", R=8.0, centre=20),
-}
+# The single-problem workloads by name (image, basis, coils), each with its own seed; each
+# entry is the keyword set for make_problem.
+WORKLOADS = {w["name"]: w for w in (
+    dict(seed=1, name="cart2d_64_dense32_j8", dims=(64, 64), J=8, K=32, basis_kind="dense",
+         degree=6, kmax=3.0, sampling="cartesian", mask="lines", R=4, centre=16),
+    dict(seed=2, name="cart2d_256_dense200_j32", dims=(256, 256), J=32, K=200, basis_kind="dense",
+         degree=10, kmax=5.0, sampling="cartesian", mask="pd2d", R=6.0, centre=24),
+    dict(seed=3, name="radial2d_256_dense128_j16", dims=(256, 256), J=16, K=128, basis_kind="dense",
+         degree=10, kmax=5.0, sampling="radial", n_spokes=64, n_read=512),
+    dict(seed=4, name="cart3d_128_tucker40x300_j32", dims=(128, 128, 128), J=32, K=300,
+         basis_kind="tucker", ranks=(40, 40, 40), degree=6, kmax=3.0, sampling="cartesian",
+         mask="pd3d", R=8.0, centre=20),
+)}
+
+
+def problem(name: str) -> Problem:
+    """The named workload's seeded problem."""
+    return make_problem(**WORKLOADS[name])
 
 
 # ---------------------------------------------------------------- batched slices
 # Many independent 2D problems of uneven sizes, each with its own dense basis, coils and
 # sampling (the batched serving form).  Slice i draws everything from
-# SeedSequence([config, role, i]).  Two departures from the single-problem recipe keep the
+# SeedSequence([seed, role, i]).  Two departures from the single-problem recipe keep the
 # generation of 64 slices (3.8 GB of bases) to seconds: the bases are i.i.d. complex
 # Gaussian columns scaled by 1/sqrt(N) (near-orthonormal for N >> K; their content does not
 # change the work, their size does), and the Cartesian masks are variable-density random
@@ -423,8 +430,8 @@ BATCH = dict(name="batch64_slices_dense", n_slices=64, sizes=(128, 192, 256, 320
              Ks=(64, 128, 256))
 
 
-def slice_rng(config: int, role: int, i: int) -> np.random.Generator:
-    return np.random.default_rng(np.random.SeedSequence([int(config), int(role), int(i)]))
+def slice_rng(seed: int, role: int, i: int) -> np.random.Generator:
+    return np.random.default_rng(np.random.SeedSequence([int(seed), int(role), int(i)]))
 
 
 def vd_random_mask(rng: np.random.Generator, shape: Sequence[int], R: float, centre: int) -> np.ndarray:
@@ -450,19 +457,19 @@ def vd_random_mask(rng: np.random.Generator, shape: Sequence[int], R: float, cen
     return np.flatnonzero(m.reshape(-1)).astype(np.int64)
 
 
-def slice_problems(config: int = 5, n_slices: int = 64, sizes=BATCH["sizes"], Js=BATCH["Js"],
+def slice_problems(seed: int = 5, n_slices: int = 64, sizes=BATCH["sizes"], Js=BATCH["Js"],
                    Ks=BATCH["Ks"], spokes=(32, 128)) -> List[Problem]:
     """The batched-slices workload: n_slices seeded 2D problems (see the block comment)."""
     out = []
     for i in range(n_slices):
-        rp = slice_rng(config, ROLE_SAMPLING, i)
+        rp = slice_rng(seed, ROLE_SAMPLING, i)
         dims = (int(rp.choice(sizes)), int(rp.choice(sizes)))
         J, K = int(rp.choice(Js)), int(rp.choice(Ks))
         cart = bool(rp.uniform() < 0.5)
         p = Problem(name=f"slice{i}", dims=dims, J=J, K=K, basis_kind="dense",
                     sampling="cartesian" if cart else "radial")
         N = dims[0] * dims[1]
-        rb = slice_rng(config, ROLE_BASIS, i)
+        rb = slice_rng(seed, ROLE_BASIS, i)
         p.B = ((rb.standard_normal((N, K), dtype=np.float32)
                 + 1j * rb.standard_normal((N, K), dtype=np.float32)) / np.float32(math.sqrt(2.0 * N)))
         if cart:
@@ -473,10 +480,10 @@ def slice_problems(config: int = 5, n_slices: int = 64, sizes=BATCH["sizes"], Js
             nr = 2 * max(dims)
             p.traj = golden_angle_radial(dims, ns, nr)
             p.weights = ramp_dcf(p.traj, dims, nr)
-        p.x_true = phantom(slice_rng(config, ROLE_PHANTOM, i), dims)
-        p.c_true = coefficients(slice_rng(config, ROLE_CTRUE, i), J, K)
-        p.noise = unit_noise(slice_rng(config, ROLE_NOISE, i), J, p.M)
-        re = slice_rng(config, ROLE_EVAL, i)
+        p.x_true = phantom(slice_rng(seed, ROLE_PHANTOM, i), dims)
+        p.c_true = coefficients(slice_rng(seed, ROLE_CTRUE, i), J, K)
+        p.noise = unit_noise(slice_rng(seed, ROLE_NOISE, i), J, p.M)
+        re = slice_rng(seed, ROLE_EVAL, i)
         p.x0 = phantom(re, dims)
         p.c0 = coefficients(re, J, K)
         out.append(p)

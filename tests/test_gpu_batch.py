@@ -34,7 +34,7 @@ def H(t):
 def slices():
     """Six small slices (seeded): sizes 32..64, J 2..4, K 5..12, both sampling kinds."""
     if "p" not in _cache:
-        ps = slice_problems(config=55, n_slices=6, sizes=(32, 48, 64), Js=(2, 3, 4), Ks=(5, 9, 12), spokes=(6, 12))
+        ps = slice_problems(seed=55, n_slices=6, sizes=(32, 48, 64), Js=(2, 3, 4), Ks=(5, 9, 12), spokes=(6, 12))
         data = []
         for p in ps:
             kw = dict(mask_idx=p.mask_idx) if p.sampling == "cartesian" else dict(traj=p.traj.astype(np.float32).astype(np.float64))

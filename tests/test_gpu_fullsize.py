@@ -13,7 +13,7 @@ import torch
 
 from _common import TOL, c64, rel
 from oracle import Oracle
-from synth import CONFIGS, make_problem
+from synth import problem as make
 
 pytestmark = pytest.mark.gpu
 
@@ -29,10 +29,10 @@ def H(t):
     return t.detach().cpu().numpy().astype(np.complex128)
 
 
-def problem(cfg):
+def problem(name):
     """Seeded full-size problem, complex64-rounded, with its oracle and measured data."""
-    if cfg not in _cache:
-        p = make_problem(cfg, **CONFIGS[cfg])
+    if name not in _cache:
+        p = make(name)
         kw = dict(mask_idx=p.mask_idx)
         if p.sampling == "radial":
             p.traj = p.traj.astype(np.float32).astype(np.float64)
@@ -45,13 +45,13 @@ def problem(cfg):
         op = Oracle(p.dims, **basis, **kw)
         y = op.encode(c64(p.x_true), c64(p.c_true))
         y = c64(y + 10 ** (-p.snr_db / 20) * np.linalg.norm(y) / np.linalg.norm(p.noise) * p.noise)
-        _cache[cfg] = (p, basis, kw, w, op, y)
-    return _cache[cfg]
+        _cache[name] = (p, basis, kw, w, op, y)
+    return _cache[name]
 
 
-def gpu_grad(cfg, prec):
+def gpu_grad(name, prec):
     from paper_2008_09042_amd.encoding import MaxwellDataFidelity, MaxwellPlan
-    p, basis, kw, w, op, y = problem(cfg)
+    p, basis, kw, w, op, y = problem(name)
     gbasis = {k: ([T(u) for u in v] if isinstance(v, list) else T(v)) for k, v in basis.items()}
     plan = MaxwellPlan(p.dims, p.J, **gbasis, **kw, weights=w, precision=prec, device=DEV)
     x = T(p.x0).requires_grad_(True)
@@ -70,15 +70,15 @@ def _gpu():
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16_split"])
-@pytest.mark.parametrize("cfg", [1, 2, 3, 4])
-def test_fullsize_gradient(cfg, prec):
-    name = CONFIGS[cfg]["name"]
+@pytest.mark.parametrize("name", ["cart2d_64_dense32_j8", "cart2d_256_dense200_j32", "radial2d_256_dense128_j16",
+                                  "cart3d_128_tucker40x300_j32"])
+def test_fullsize_gradient(name, prec):
     print(f"[case] {name} {prec}", flush=True)
-    p, basis, kw, w, op, y = problem(cfg)
-    plan, f, gx, gc = gpu_grad(cfg, prec)
-    if cfg == 4:
+    p, basis, kw, w, op, y = problem(name)
+    plan, f, gx, gc = gpu_grad(name, prec)
+    if p.basis_kind == "tucker":
         assert plan.path == "fused-tucker-lines"
-    key = ("ref", cfg)
+    key = ("ref", name)
     if key not in _cache:
         _cache[key] = op.loss_and_grad(c64(p.x0), c64(p.c0), y, w)
     f_ref, gx_ref, gc_ref = _cache[key]
@@ -90,9 +90,9 @@ def test_fullsize_gradient(cfg, prec):
 def test_fullsize_directional_derivative():
     """GPU gradient vs a central difference of the GPU loss (256^2 Cartesian, FP32)."""
     from paper_2008_09042_amd.encoding import MaxwellDataFidelity
-    cfg = 2
-    p, basis, kw, w, op, y = problem(cfg)
-    plan, f0, gx, gc = gpu_grad(cfg, "fp32")
+    name = "cart2d_256_dense200_j32"
+    p, basis, kw, w, op, y = problem(name)
+    plan, f0, gx, gc = gpu_grad(name, "fp32")
     rng = np.random.default_rng(11)
     dx = rng.normal(size=p.x0.shape) + 1j * rng.normal(size=p.x0.shape)
     dc = rng.normal(size=p.c0.shape) + 1j * rng.normal(size=p.c0.shape)

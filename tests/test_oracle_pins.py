@@ -16,8 +16,8 @@ from scipy.integrate import quad
 
 import oracle
 from oracle import Oracle
-from synth import (coefficients, complex_normal, golden_angle_radial, make_problem, phantom,
-                   rng_for, smooth_dense_basis, tucker_basis, CONFIGS, ramp_dcf)
+from synth import (coefficients, complex_normal, golden_angle_radial, phantom, problem,
+                   rng_for, smooth_dense_basis, tucker_basis, ramp_dcf)
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -414,7 +414,7 @@ def test_nufft_kernel_tie_break():
 
 # ---------------------------------------------------------------- input generators
 def test_config_generators_shapes():
-    p = make_problem(1, **CONFIGS[1])
+    p = problem("cart2d_64_dense32_j8")
     assert p.M == 28 * 64 and p.B.shape == (4096, 32)
     traj = golden_angle_radial((256, 256), 64, 512)
     assert traj.shape == (32768, 2) and np.max(np.abs(traj)) <= 128
