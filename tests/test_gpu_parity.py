@@ -18,7 +18,7 @@ DEV = "cuda:0"
 
 CASES = {
     "dense2d_48x40_J5_K37": dict(seed=101, dims=(48, 40), J=5, K=37, basis="dense", weights=True),
-    "dense2d_64x64_J8_K32_c1shape": dict(seed=102, dims=(64, 64), J=8, K=32, basis="dense"),
+    "dense2d_64x64_J8_K32": dict(seed=102, dims=(64, 64), J=8, K=32, basis="dense"),
     "dense2d_30x20_radix35": dict(seed=103, dims=(30, 20), J=3, K=9, basis="dense"),
     # dense apply streaming kernel: three and four coil blocks, a ragged K16 step, N not a
     # multiple of its 64-row wave share
@@ -55,6 +55,10 @@ CASES = {
     "radial_40x30_J2_K6_5spokes": dict(seed=114, dims=(40, 30), J=2, K=6, mask="radial", spokes=5, n_read=48),
     "radial_256_J2_K20_64spokes": dict(seed=115, dims=(256, 256), J=2, K=20, mask="radial", spokes=64,
                                        n_read=512, weights=True),
+    # N = 1,105,920 (not a power of two, above 2^20): the FFT passes that carry the mask divide
+    # flat indices by N with a multiply-high
+    "dense3d_96x96x120_J2_K4": dict(seed=117, dims=(96, 96, 120), J=2, K=4, basis="dense", mask="random",
+                                    frac=0.3),
     # 12 coils: one full and one padded group of 8 in the spread
     "radial_64x48_J12_K7_16spokes": dict(seed=116, dims=(64, 48), J=12, K=7, mask="radial", spokes=16,
                                          n_read=128, weights=True),
