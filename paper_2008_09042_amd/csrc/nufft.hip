@@ -490,11 +490,14 @@ hipError_t spread_launch(const NufftArgs& a, const float2* y, float alpha, const
   if (a.W < 1 || a.W > 8) return hipErrorInvalidValue;
   if (a.M > 0)
     hipLaunchKernelGGL(spread_stage_kernel, dim3((unsigned)((a.M + STG - 1) / STG)), dim3(NT), 0, st, a, y, Jp, ys);
-  switch (jg) {
+  // the plain kernel takes 16 coils per lane where the padded coil count allows (one walk
+  // of a sample sequence serves twice the coils; 150 vs 156 us at 32 coils, 128 spokes)
+  switch (Jp % 16 == 0 ? 16 : jg) {
     case 1: launch_flat_w<1>(a, ys, Jp, alpha, scale_dev, grid, st); break;
     case 2: launch_flat_w<2>(a, ys, Jp, alpha, scale_dev, grid, st); break;
     case 4: launch_flat_w<4>(a, ys, Jp, alpha, scale_dev, grid, st); break;
-    default: launch_flat_w<8>(a, ys, Jp, alpha, scale_dev, grid, st); break;
+    case 8: launch_flat_w<8>(a, ys, Jp, alpha, scale_dev, grid, st); break;
+    default: launch_flat_w<16>(a, ys, Jp, alpha, scale_dev, grid, st); break;
   }
   if (a.n_heavy > 0) {  // one launch for both kinds of split rows
     const int S = split_waves(a.W);
