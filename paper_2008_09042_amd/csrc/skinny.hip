@@ -1,6 +1,8 @@
 // Dense basis apply and adjoint for few coils: S_j = B c_j (paper Sec. II-B, Eq. (5)) and
-// c_j = B^H h_j (the basis block of J_G^H) with B [N][K] row-major and J <= 64.  The product streams B once from HBM (J flops per byte, far below
-// the matrix cores' ridge point), so the kernel is built for the stream: no LDS staging.
+// c_j = B^H h_j (the basis block of J_G^H) with B [N][K] row-major, J <= 64 for the apply
+// and J <= 16 for the adjoint (the plan chooses; larger J takes the tiled GEMM).  Each
+// product streams B once from HBM (J flops per byte, far below the matrix cores' ridge
+// point), so the kernels are built for the stream: no LDS staging of B.
 //
 // Written as S^T = B c^T on 16 x 16 complex tiles (mfma_frag.h): the A operand of a K16 step
 // is 16 rows of B, and lane l (row l % 16, group g = l / 16) holds B[n][k0 + 4g .. +3], 32
@@ -14,8 +16,8 @@
 // A operand (rows k, reduction n) is conj(B) read down four rows per lane (each load of a
 // wave covers 128 contiguous bytes of four rows), the B operand is h, 32 contiguous bytes per
 // lane.  A workgroup's four waves take four consecutive row chunks of one 64-column group of
-// B and add their tiles through LDS; the workgroup partials are summed over the chunks in
-// chunk order by a second kernel (no atomics).  Workgroups of one row chunk and different
+// B and add their tiles through LDS; a second kernel sums the workgroup partials over the
+// chunks in a fixed order (no atomics).  Workgroups of one row chunk and different
 // column groups are dealt to one XCD, so the rows they share are fetched into one L2.
 #include "mfma_frag.h"
 #include "skinny.h"
