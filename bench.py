@@ -534,6 +534,15 @@ def main():
         sys.exit(2)
     import torch
     from paper_2008_09042_amd.encoding import MaxwellDataFidelity, MaxwellPlan
+    if args.copy_probe:
+        # one streaming kernel that reads and writes exactly MIB MiB (float32 scale by 2), the
+        # calibration of the byte counters
+        n = args.copy_probe * 2**20 // 4
+        src = torch.ones(n, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.mul(src, 2.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     if args.workload == "batch":
         bench_batch(args, torch)
         return
@@ -551,14 +560,6 @@ def main():
         return
 
     dev = torch.device("cuda:0")
-    if args.copy_probe:
-        # one streaming kernel that reads and writes exactly MIB MiB (float32 scale by 2)
-        n = args.copy_probe * 2**20 // 4
-        src = torch.ones(n, device=dev)
-        dst = torch.empty_like(src)
-        torch.mul(src, 2.0, out=dst)
-        torch.cuda.synchronize()
-        del src, dst
     p = make_inputs()
     T = lambda a: torch.from_numpy(np.ascontiguousarray(np.asarray(a).astype(np.complex64))).to(dev)  # noqa: E731
     U = [T(u) for u in p.U]
