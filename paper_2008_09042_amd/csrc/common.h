@@ -67,6 +67,10 @@ struct FftAxisArgs {
   // place of src; the last forward pass writes samples[j][inv[p]] for inv[p] >= 0 in place
   // of data.  Needs J N < 2^32 and M > 0.
   const int32_t* in_inv; const float2* in_samples;
+  // optional for the reading pass: the sorted mask [M] and, per line of the last axis within
+  // a coil, the first sample at or after it [N / n + 1]; with them a tile of whole lines of
+  // one coil places its samples directly (no inverse-mask lookup per point)
+  const int32_t* in_mask; const int32_t* in_lptr;
   const int32_t* out_inv; float2* out_samples;
   int64_t coil_elems, nsamples;  // N, M
   uint32_t coil_magic, coil_shift;  // multiply-high division by N (set by fft_axis_launch)

@@ -74,7 +74,26 @@ __global__ __launch_bounds__(NT) void fft_axis_kernel(FftAxisArgs a) {
   // (an element past the tile reads the tile's first element and is masked to zero)
   constexpr int LU = 8;
   const int64_t gbase = a.inner == 1 ? o0 * a.n * a.inner : o0 * a.n * a.inner + t0;
-  for (int e0 = threadIdx.x; e0 < total; e0 += NT * LU) {
+  if constexpr (SMP == 3) {
+    // whole lines l0 .. l0 + T - 1 of coil j (contiguous axis): zero the tile, then put the
+    // tile's samples, one contiguous range of the sorted mask, at their points
+    for (int e = threadIdx.x; e < tg.T * tg.LS; e += NT) lds[e] = make_float2(0.f, 0.f);
+    __syncthreads();
+    const int64_t j = o0 / a.outer_per_coil, l0 = o0 % a.outer_per_coil;
+    const int lo = a.in_lptr[l0], hi = a.in_lptr[l0 + Tvalid];
+    const int64_t first = l0 * a.n;
+    for (int sm = lo + threadIdx.x; sm < hi; sm += NT) {
+      const uint32_t pp = (uint32_t)(a.in_mask[sm] - first);
+      const int l = (int)fdiv(pp, fd), i = (int)pp - l * n;
+      float2 x = a.in_samples[j * a.nsamples + sm];
+      if (i & 1) {
+        x.x = -x.x;
+        x.y = -x.y;
+      }
+      lds[l * tg.LS + i] = x;
+    }
+  }
+  for (int e0 = threadIdx.x; SMP != 3 && e0 < total; e0 += NT * LU) {
     float2 v[LU], pm[LU];
     uint32_t keep[LU];
     int li[LU];
@@ -194,7 +213,10 @@ hipError_t fft_axis_launch(const FftAxisArgs& args, hipStream_t st) {
   const int64_t blocks = contiguous ? (a.outer + T - 1) / T : a.outer * ((a.inner + T - 1) / T);
   if (blocks <= 0) return hipSuccess;
   const size_t lds = (size_t)(tile_elems(n, a.lines, contiguous) + (twl ? n : 0)) * sizeof(float2);
-  const int smp = a.in_inv ? 1 : a.out_inv ? 2 : 0;
+  int smp = a.in_inv ? 1 : a.out_inv ? 2 : 0;
+  // the reading pass places whole lines' samples directly when every tile holds lines of
+  // one coil only
+  if (smp == 1 && contiguous && a.in_mask && a.in_lptr && a.outer_per_coil % T == 0) smp = 3;
   if (smp && (a.in_inv && a.out_inv)) return hipErrorInvalidValue;
   // element indices j N + p below 2^31, so the multiply-high division of the flat index by
   // N is exact; its magic number in integer arithmetic (Granlund and Montgomery)
@@ -209,6 +231,8 @@ hipError_t fft_axis_launch(const FftAxisArgs& args, hipStream_t st) {
   }
   const dim3 gr((unsigned)blocks), bl(NT);
   switch (smp * 2 + (twl ? 1 : 0)) {
+    case 7: hipLaunchKernelGGL((fft_axis_kernel<true, 3>), gr, bl, lds, st, a); break;
+    case 6: hipLaunchKernelGGL((fft_axis_kernel<false, 3>), gr, bl, lds, st, a); break;
     case 1: hipLaunchKernelGGL((fft_axis_kernel<true, 0>), gr, bl, lds, st, a); break;
     case 0: hipLaunchKernelGGL((fft_axis_kernel<false, 0>), gr, bl, lds, st, a); break;
     case 3: hipLaunchKernelGGL((fft_axis_kernel<true, 1>), gr, bl, lds, st, a); break;

@@ -37,6 +37,7 @@ struct Plan {
   // device tables owned by the plan
   int32_t* d_mask = nullptr;   // [M] linear k-space index of each sample
   int32_t* d_inv = nullptr;    // [N] sample position of each grid point, -1 if unsampled
+  int32_t* d_lptr = nullptr;   // [N / n_last + 1] first sample at or after each last-axis line
   float* d_w = nullptr;        // [M] data weights or null (w = 1)
   float2* d_tw[3] = {nullptr, nullptr, nullptr};  // twiddle tables per axis
   int nrad[3] = {0, 0, 0};

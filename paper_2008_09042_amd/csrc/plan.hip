@@ -175,6 +175,8 @@ hipError_t fft_dims(const Plan& p, const float2* src, float2* dst, int dir, cons
     if (t == 0 && in_samples) {
       a.in_inv = p.d_inv;
       a.in_samples = in_samples;
+      a.in_mask = p.d_mask;
+      a.in_lptr = p.d_lptr;
     }
     if (t == nd - 1 && out_samples) {
       a.out_inv = p.d_inv;
@@ -568,6 +570,14 @@ maxwell_status plan_build(Plan& p, const maxwell_plan_desc& d, const maxwell_bas
     if ((e = hipMalloc(&p.d_inv, p.N * sizeof(int32_t))) != hipSuccess) return hip_err(e);
     if ((e = hipMemcpy(p.d_inv, inv.data(), p.N * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess)
       return hip_err(e);
+    // samples before each line of the last axis (the mask is strictly ascending)
+    const int64_t nl = p.n[p.ndim - 1], lines = p.N / nl;
+    std::vector<int32_t> lptr(lines + 1, 0);
+    for (int64_t m = 0; m < p.M; ++m) ++lptr[d.mask_idx[m] / nl + 1];
+    for (int64_t l = 0; l < lines; ++l) lptr[l + 1] += lptr[l];
+    if ((e = hipMalloc(&p.d_lptr, lptr.size() * sizeof(int32_t))) != hipSuccess) return hip_err(e);
+    if ((e = hipMemcpy(p.d_lptr, lptr.data(), lptr.size() * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess)
+      return hip_err(e);
   }
   if (d.weights && p.M > 0) {
     if ((e = hipMalloc(&p.d_w, p.M * sizeof(float))) != hipSuccess) return hip_err(e);
@@ -710,6 +720,7 @@ void plan_release(Plan& p) {
   }
   if (p.d_mask) (void)hipFree(p.d_mask);
   if (p.d_inv) (void)hipFree(p.d_inv);
+  if (p.d_lptr) (void)hipFree(p.d_lptr);
   if (p.d_w) (void)hipFree(p.d_w);
   if (p.d_pos) (void)hipFree(p.d_pos);
   if (p.d_frag) (void)hipFree(p.d_frag);
@@ -718,6 +729,7 @@ void plan_release(Plan& p) {
   p.d_core_split = nullptr;
   p.d_mask = nullptr;
   p.d_inv = nullptr;
+  p.d_lptr = nullptr;
   p.d_w = nullptr;
   p.d_pos = nullptr;
 }
