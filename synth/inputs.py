@@ -21,9 +21,12 @@ arithmetic of the method):
 """
 from __future__ import annotations
 
+import ctypes
 import dataclasses
 import itertools
 import math
+import os
+import subprocess
 from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
@@ -43,7 +46,7 @@ __all__ = [
     "smooth_factor", "tucker_basis", "coefficients", "line_mask", "poisson_disc_plane",
     "plane_mask_to_lines", "plane_mask_to_indices", "golden_angle_radial", "ramp_dcf",
     "unit_noise", "noise_scale_for_snr", "Problem", "make_problem", "problem", "WORKLOADS",
-    "BATCH", "slice_rng", "vd_random_mask", "slice_problems",
+    "BATCH", "slice_rng", "slice_problems", "build_native", "smooth_params",
 ]
 
 
@@ -130,6 +133,17 @@ def phantom(rng: np.random.Generator, dims: Sequence[int], n_ellipses: int = 10)
     return mag * np.exp(1j * phi)
 
 
+def smooth_params(rng: np.random.Generator, nd: int, ncols: int, degree: int, kmax: float):
+    """Random parameters of the smooth columns: (monomial exponents, complex coefficients
+    (n_monomials, ncols), wave vectors (ncols, nd) uniform in the ball |k| <= kmax)."""
+    exps = _monomial_exponents(nd, degree)
+    coef = complex_normal(rng, (len(exps), ncols))
+    dirs = rng.normal(size=(ncols, nd))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    rad = kmax * rng.uniform(0.0, 1.0, size=ncols) ** (1.0 / nd)
+    return exps, coef, dirs * rad[:, None]
+
+
 def _smooth_columns(rng: np.random.Generator, dims: Sequence[int], ncols: int,
                     degree: int, kmax: float) -> np.ndarray:
     """Columns poly_q(2r) * exp(2 pi i k_q . r), flattened C-order, shape (N, ncols).
@@ -142,7 +156,7 @@ def _smooth_columns(rng: np.random.Generator, dims: Sequence[int], ncols: int,
     N = int(np.prod(dims))
     coords = [c.reshape(-1) for c in np.meshgrid(*[(np.arange(n) - n // 2) / n for n in dims],
                                                  indexing="ij")]
-    exps = _monomial_exponents(nd, degree)
+    exps, coef, kvec = smooth_params(rng, nd, ncols, degree, kmax)
     mono = np.empty((N, len(exps)))
     for t, e in enumerate(exps):
         v = np.ones(N)
@@ -150,12 +164,6 @@ def _smooth_columns(rng: np.random.Generator, dims: Sequence[int], ncols: int,
             if e[d]:
                 v = v * (2.0 * coords[d]) ** e[d]
         mono[:, t] = v
-    coef = complex_normal(rng, (len(exps), ncols))
-    # uniform in the nd-ball of radius kmax
-    dirs = rng.normal(size=(ncols, nd))
-    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
-    rad = kmax * rng.uniform(0.0, 1.0, size=ncols) ** (1.0 / nd)
-    kvec = dirs * rad[:, None]
     phase = np.zeros((N, ncols))
     for d in range(nd):
         phase += np.outer(coords[d], kvec[:, d])
@@ -209,8 +217,45 @@ def line_mask(dims: Sequence[int], step: int, centre: int) -> np.ndarray:
     return (rows[:, None] * n1 + np.arange(n1, dtype=np.int64)[None, :]).reshape(-1)
 
 
+_PD_LIB = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpdisc.so")
+_pd_lib = None
+
+
+def build_native() -> str:
+    """Compile the dart-throwing helper (pdisc.c) next to this file with the host compiler."""
+    src = os.path.join(os.path.dirname(_PD_LIB), "pdisc.c")
+    tmp = _PD_LIB + ".tmp"
+    subprocess.run(["gcc", "-O2", "-shared", "-fPIC", "-o", tmp, src, "-lm"], check=True)
+    os.replace(tmp, _PD_LIB)
+    return _PD_LIB
+
+
+def _pd_native():
+    global _pd_lib
+    if _pd_lib is None and os.path.exists(_PD_LIB):
+        lib = ctypes.CDLL(_PD_LIB)
+        lib.pd_throw.restype = ctypes.c_int64
+        lib.pd_throw.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
+                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        _pd_lib = lib
+    return _pd_lib
+
+
+def _pd_throw_native(cen: np.ndarray, ii: np.ndarray, jj: np.ndarray, dmin: np.ndarray) -> List[int]:
+    occ = np.ascontiguousarray(cen, dtype=np.uint8)
+    i32 = np.ascontiguousarray(ii, dtype=np.int32)
+    j32 = np.ascontiguousarray(jj, dtype=np.int32)
+    d64 = np.ascontiguousarray(dmin, dtype=np.float64)
+    acc = np.empty(i32.size, dtype=np.int64)
+    n = _pd_native().pd_throw(cen.shape[0], cen.shape[1], occ.ctypes.data, i32.size, i32.ctypes.data,
+                              j32.ctypes.data, d64.ctypes.data, acc.ctypes.data)
+    if n < 0:
+        raise MemoryError("pd_throw")
+    return acc[:n].tolist()
+
+
 def poisson_disc_plane(rng: np.random.Generator, shape: Sequence[int], R: float,
-                       centre: int) -> np.ndarray:
+                       centre: int, native: Optional[bool] = None) -> np.ndarray:
     """Variable-density Poisson-disc mask over a 2D plane (boolean array).
 
     The centre ``centre x centre`` block is fully sampled.  Other points are
@@ -220,7 +265,13 @@ def poisson_disc_plane(rng: np.random.Generator, shape: Sequence[int], R: float,
     bisection so that at least round(n0*n1/R) points (centre included) are
     accepted; the first accepted points in acceptance order are kept to hit
     that count exactly.
+
+    The acceptance pass runs in the C helper (pdisc.c) when it is built, else in the loop
+    below; both give the same mask.  native=False forces the loop, native=True the helper.
     """
+    use_native = (_pd_native() is not None) if native is None else bool(native)
+    if use_native and _pd_native() is None:
+        raise RuntimeError("libpdisc.so is not built (synth.build_native())")
     n0, n1 = int(shape[0]), int(shape[1])
     target = int(round(n0 * n1 / R))
     cen = np.zeros((n0, n1), dtype=bool)
@@ -236,9 +287,11 @@ def poisson_disc_plane(rng: np.random.Generator, shape: Sequence[int], R: float,
     rho = np.sqrt(((ii - n0 // 2) / (n0 / 2.0)) ** 2 + ((jj - n1 // 2) / (n1 / 2.0)) ** 2) / math.sqrt(2.0)
 
     def throw(s: float):
+        dmin = s * (1.0 + 3.0 * rho)
+        if use_native:
+            return _pd_throw_native(cen, ii, jj, dmin)
         occ = cen.copy()
         acc = []
-        dmin = s * (1.0 + 3.0 * rho)
         for t in range(ii.size):
             i, j, d = int(ii[t]), int(jj[t]), float(dmin[t])
             w = int(math.ceil(d))
@@ -346,6 +399,7 @@ class Problem:
     snr_db: float = 40.0
     x0: Optional[np.ndarray] = None
     c0: Optional[np.ndarray] = None
+    basis_params: Optional[tuple] = None  # (exponents, coef, kvec) when not materialised
 
     @property
     def N(self) -> int:
@@ -420,45 +474,22 @@ def problem(name: str) -> Problem:
 # ---------------------------------------------------------------- batched slices
 # Many independent 2D problems of uneven sizes, each with its own dense basis, coils and
 # sampling (the batched serving form).  Slice i draws everything from
-# SeedSequence([seed, role, i]).  Two departures from the single-problem recipe keep the
-# generation of 64 slices (3.8 GB of bases) to seconds: the bases are i.i.d. complex
-# Gaussian columns scaled by 1/sqrt(N) (near-orthonormal for N >> K; their content does not
-# change the work, their size does), and the Cartesian masks are variable-density random
-# (Bernoulli with a density falling as (1 - r)^2 over the normalised radius, plus a fully
-# sampled centre) rather than Poisson-disc.
+# SeedSequence([seed, role, i]).  Bases follow the single-problem recipe (smooth columns of
+# degree <= 10 and |k| <= 5, QR-orthonormalised); Cartesian slices take a variable-density
+# Poisson-disc mask with a fully sampled centre of max(16, n/10)^2.  With
+# materialise_basis=False only the basis parameters are drawn (p.basis_params), so that a
+# caller can evaluate the columns and their QR elsewhere (64 bases of up to 102,400 x 256
+# take minutes of host time).
 BATCH = dict(name="batch64_slices_dense", n_slices=64, sizes=(128, 192, 256, 320), Js=(8, 16, 32),
-             Ks=(64, 128, 256))
+             Ks=(64, 128, 256), degree=10, kmax=5.0)
 
 
 def slice_rng(seed: int, role: int, i: int) -> np.random.Generator:
     return np.random.default_rng(np.random.SeedSequence([int(seed), int(role), int(i)]))
 
 
-def vd_random_mask(rng: np.random.Generator, shape: Sequence[int], R: float, centre: int) -> np.ndarray:
-    """Sorted linear indices of a variable-density random 2D mask with about N/R samples."""
-    ny, nx = (int(n) for n in shape)
-    ky = (np.arange(ny) - ny // 2) / (ny / 2)
-    kx = (np.arange(nx) - nx // 2) / (nx / 2)
-    r = np.minimum(np.sqrt(ky[:, None] ** 2 + kx[None, :] ** 2), 1.0)
-    dens = (1.0 - r) ** 2
-    c0y, c0x = ny // 2 - centre // 2, nx // 2 - centre // 2
-    core = np.zeros((ny, nx), dtype=bool)
-    core[max(c0y, 0):c0y + centre, max(c0x, 0):c0x + centre] = True
-    want = max(ny * nx / R - core.sum(), 0.0)
-    lo, hi = 0.0, 1e6
-    for _ in range(60):  # scale s with sum(min(1, s dens)) = want outside the centre
-        s = 0.5 * (lo + hi)
-        if np.minimum(1.0, s * dens)[~core].sum() < want:
-            lo = s
-        else:
-            hi = s
-    p = np.minimum(1.0, hi * dens)
-    m = core | (rng.uniform(size=(ny, nx)) < p)
-    return np.flatnonzero(m.reshape(-1)).astype(np.int64)
-
-
 def slice_problems(seed: int = 5, n_slices: int = 64, sizes=BATCH["sizes"], Js=BATCH["Js"],
-                   Ks=BATCH["Ks"], spokes=(32, 128)) -> List[Problem]:
+                   Ks=BATCH["Ks"], spokes=(32, 128), materialise_basis: bool = True) -> List[Problem]:
     """The batched-slices workload: n_slices seeded 2D problems (see the block comment)."""
     out = []
     for i in range(n_slices):
@@ -468,13 +499,15 @@ def slice_problems(seed: int = 5, n_slices: int = 64, sizes=BATCH["sizes"], Js=B
         cart = bool(rp.uniform() < 0.5)
         p = Problem(name=f"slice{i}", dims=dims, J=J, K=K, basis_kind="dense",
                     sampling="cartesian" if cart else "radial")
-        N = dims[0] * dims[1]
         rb = slice_rng(seed, ROLE_BASIS, i)
-        p.B = ((rb.standard_normal((N, K), dtype=np.float32)
-                + 1j * rb.standard_normal((N, K), dtype=np.float32)) / np.float32(math.sqrt(2.0 * N)))
+        if materialise_basis:
+            p.B = smooth_dense_basis(rb, dims, K, BATCH["degree"], BATCH["kmax"])
+        else:
+            p.basis_params = smooth_params(rb, 2, K, BATCH["degree"], BATCH["kmax"])
         if cart:
             R = float(rp.uniform(3.0, 8.0))
-            p.mask_idx = vd_random_mask(rp, dims, R, max(16, max(dims) // 10))
+            plane = poisson_disc_plane(rp, dims, R, max(16, max(dims) // 10))
+            p.mask_idx = plane_mask_to_indices(plane)
         else:
             ns = int(rp.integers(spokes[0], spokes[1] + 1))
             nr = 2 * max(dims)

@@ -447,3 +447,17 @@ def test_multi_map_reduces_and_matches_finite_differences():
     fm = multi_loss_and_grad(op, [x, x2], [c, c2 - h * e2], y)[0]
     dd = np.real(np.vdot(gcs[1], e2))
     assert abs((fp - fm) / (2 * h) - dd) < 1e-10 * abs(dd)
+
+
+def test_poisson_disc_helper_matches_the_loop():
+    """Input generation: the C dart-throwing helper gives the same masks as the Python loop."""
+    from synth import poisson_disc_plane, rng_for
+    import synth.inputs as si
+    if si._pd_native() is None:
+        import pytest
+        pytest.skip("libpdisc.so not built")
+    for shape, R, c in [((40, 56), 4.0, 8), ((64, 48), 6.0, 12), ((30, 30), 2.5, 4)]:
+        a = poisson_disc_plane(rng_for(9, 4), shape, R, c, native=False)
+        b = poisson_disc_plane(rng_for(9, 4), shape, R, c, native=True)
+        assert np.array_equal(a, b)
+        assert int(b.sum()) == int(round(shape[0] * shape[1] / R))
