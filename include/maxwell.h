@@ -143,7 +143,7 @@ maxwell_status maxwell_plan_workspace_size(maxwell_plan_t plan, size_t* bytes);
 /* Which kernel sequence the plan runs (a static string owned by the library):
  *   "fused-tucker-lines"  3D Tucker basis, mask made of full lines along the last
  *                         axis, n0 and n1 multiples of 16 and <= 128, n2 <= 256,
- *                         r0, r1 <= 64: per-plane fused kernels, no [J][N] arrays;
+ *                         r0, r1 <= 48: per-plane fused kernels, no [J][N] arrays;
  *   "general"             any other geometry: basis apply, per-axis FFT, gather.
  * NULL for a NULL plan.                                                       */
 const char* maxwell_plan_path(maxwell_plan_t plan);
@@ -391,6 +391,16 @@ const char* maxwell_last_error(void);
 
 /* Library version string, e.g. "maxwell-gfx950 0.1".                          */
 const char* maxwell_version(void);
+
+/* Diagnostic: the device BF16 split of the BF16_SPLIT products (see maxwell_precision),
+ * applied to n FP32 values x (device): hi[i] = bf16(x[i]), lo[i] = bf16(x[i] - hi[i]),
+ * both round to nearest even, as BF16 bit patterns (device uint16 arrays of n entries).
+ * variant 0: the packed hardware converts of the matrix-core tiles (plane kernels,
+ * fragment-ordered operands); 1: the tiled GEMM's operand split (n must be even: the
+ * values are complex pairs); 2: the core planes' split.  Asynchronous on stream;
+ * n = 0 does nothing; x, hi, lo must not overlap.                                       */
+maxwell_status maxwell_bf16_split(const float* x, int64_t n, int32_t variant, uint16_t* hi, uint16_t* lo,
+                                  void* stream);
 
 #ifdef __cplusplus
 }

@@ -34,7 +34,7 @@ EXPORTS = [
     "maxwell_sense_encode", "maxwell_sense_adjoint", "maxwell_sense_normal", "maxwell_tv_prox",
     "maxwell_ball_project", "maxwell_sense_admm", "maxwell_multi_encode", "maxwell_multi_grad",
     "maxwell_tucker_compress", "maxwell_batch_grad_shared",
-    "maxwell_plan_set_timing", "maxwell_plan_timing",
+    "maxwell_plan_set_timing", "maxwell_plan_timing", "maxwell_bf16_split",
 ]
 
 
@@ -154,6 +154,8 @@ def load(path: str = LIB_PATH):
     lib.maxwell_last_error.restype = ctypes.c_char_p
     lib.maxwell_version.argtypes = []
     lib.maxwell_version.restype = ctypes.c_char_p
+    lib.maxwell_bf16_split.argtypes = [vp, i64, ctypes.c_int32, vp, vp, vp]
+    lib.maxwell_bf16_split.restype = st
     _lib = lib
     return lib
 

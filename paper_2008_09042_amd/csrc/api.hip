@@ -136,6 +136,25 @@ const char* maxwell_last_error(void) { return g_last_error.c_str(); }
 
 const char* maxwell_version(void) { return "maxwell-gfx950 0.1"; }
 
+maxwell_status maxwell_bf16_split(const float* x, int64_t n, int32_t variant, uint16_t* hi, uint16_t* lo,
+                                  void* stream) {
+  if (n < 0 || n > ((int64_t)1 << 40)) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "n out of range");
+  if (variant < 0 || variant > 2) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "variant must be 0, 1 or 2");
+  if (variant == 1 && (n & 1)) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "variant 1 splits complex pairs: n must be even");
+  if (n == 0) return MAXWELL_OK;
+  if (!x || !hi || !lo) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "null pointer");
+  if ((reinterpret_cast<uintptr_t>(x) & (variant == 1 ? 7u : 3u)) || (reinterpret_cast<uintptr_t>(hi) & 1u) ||
+      (reinterpret_cast<uintptr_t>(lo) & 1u))
+    return fail(MAXWELL_ERR_INVALID_ARGUMENT, "misaligned pointer");
+  const uintptr_t xs = reinterpret_cast<uintptr_t>(x), xe = xs + (uintptr_t)n * 4;
+  const uintptr_t hs = reinterpret_cast<uintptr_t>(hi), he = hs + (uintptr_t)n * 2;
+  const uintptr_t ls = reinterpret_cast<uintptr_t>(lo), le = ls + (uintptr_t)n * 2;
+  if ((xs < he && hs < xe) || (xs < le && ls < xe) || (hs < le && ls < he))
+    return fail(MAXWELL_ERR_INVALID_ARGUMENT, "x, hi and lo must not overlap");
+  HIP_TRY(bf16_split_diag_launch(x, n, variant, hi, lo, (hipStream_t)stream), "bf16_split");
+  return MAXWELL_OK;
+}
+
 maxwell_status maxwell_plan_create(const maxwell_plan_desc* desc, const maxwell_basis_desc* basis,
                                    maxwell_plan_t* plan_out) {
   if (!plan_out) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "plan_out is null");

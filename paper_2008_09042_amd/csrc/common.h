@@ -49,6 +49,9 @@ hipError_t gemm_launch(const GemmArgs& g, int precision, void* ws, hipStream_t s
 // BF16 split of an FP32 complex array into hi/lo planes (used for constant bases).
 hipError_t split_bf16_launch(const float2* src, int64_t count, uint16_t* hi, uint16_t* lo,
                              hipStream_t st);
+// The device splits (hardware converts, GEMM operand split, core split) on n FP32 values.
+hipError_t bf16_split_diag_launch(const float* x, int64_t n, int variant, uint16_t* hi, uint16_t* lo,
+                                  hipStream_t st);
 
 // ---------------------------------------------------------------- FFT
 // Transform along one axis of data laid out [outer][n][inner] (complex elements).

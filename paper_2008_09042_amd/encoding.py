@@ -155,13 +155,22 @@ class MaxwellPlan:
 
     # ---- argument checks (shape / dtype / device / contiguity)
     def _in(self, t: torch.Tensor, shape, name):
+        """A complex64 input on the plan's device of exactly `shape`, or a flat view of it
+        (1-D with the same number of elements); any other shape is refused (a transposed
+        image would otherwise be read in the wrong order)."""
         if not isinstance(t, torch.Tensor):
             raise TypeError(f"{name} must be a torch tensor")
         if t.dtype != torch.complex64 or t.device != self.device:
             raise ValueError(f"{name} must be complex64 on {self.device}")
-        if tuple(t.shape) != tuple(shape) and t.numel() != int(np.prod(shape)):
-            raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+        shape = tuple(int(v) for v in shape)
+        if tuple(t.shape) != shape and not (t.dim() == 1 and t.numel() == int(np.prod(shape))):
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {shape} (or a flat view)")
         return t.contiguous()
+
+    def bf16_split(self, x: torch.Tensor, variant: int = 0):
+        """Diagnostic: the device BF16 split of float32 values x -> (hi, lo) as int16 bit
+        patterns (maxwell_bf16_split)."""
+        return bf16_split(x, variant)
 
     def _new(self, shape):
         return torch.empty(shape, dtype=torch.complex64, device=self.device)
@@ -491,6 +500,25 @@ class MaxwellBatch:
         return self._out
 
 
+def _like(g: Optional[torch.Tensor], t: torch.Tensor):
+    """A gradient in the shape of its input (the input may be a flat view)."""
+    return None if g is None else g.reshape(t.shape)
+
+
+def bf16_split(x: torch.Tensor, variant: int = 0):
+    """The device BF16 split (maxwell_bf16_split) of a float32 tensor on a GPU:
+    hi = bf16(x), lo = bf16(x - hi) as int16 tensors holding the bit patterns."""
+    lib = L.load()
+    if not isinstance(x, torch.Tensor) or x.dtype != torch.float32 or x.device.type != "cuda":
+        raise ValueError("x must be a float32 tensor on a GPU")
+    x = x.contiguous().reshape(-1)
+    hi = torch.empty(x.shape, dtype=torch.int16, device=x.device)
+    lo = torch.empty_like(hi)
+    with torch.cuda.device(x.device):
+        L.check(lib.maxwell_bf16_split(_ptr(x), x.numel(), int(variant), _ptr(hi), _ptr(lo), _stream()))
+    return hi, lo
+
+
 class MaxwellEncode(torch.autograd.Function):
     """y = E(x, c); backward applies the Jacobian adjoint J^H to the incoming gradient.
 
@@ -509,7 +537,7 @@ class MaxwellEncode(torch.autograd.Function):
         x, c = ctx.saved_tensors
         gx, gc = ctx.plan.adjoint(x, c, gy.contiguous(), want_gx=ctx.needs_input_grad[0],
                                   want_gc=ctx.needs_input_grad[1])
-        return gx, gc, None
+        return _like(gx, x), _like(gc, c), None
 
 
 class MaxwellDataFidelity(torch.autograd.Function):
@@ -537,7 +565,7 @@ class MaxwellDataFidelity(torch.autograd.Function):
         scale = gloss.detach().to(torch.float32).reshape(1)
         gx, gc = ctx.plan.adjoint_transfer(x, c, t, alpha=2.0, scale=scale, want_gx=ctx.needs_input_grad[0],
                                            want_gc=ctx.needs_input_grad[1])
-        return gx, gc, None, None
+        return _like(gx, x), _like(gc, c), None, None
 
 
 def tucker_compress(B: torch.Tensor, dims, eps: float):

@@ -22,6 +22,30 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
 
 
+def maxrel(a, b, coils=False):
+    """Largest max|a - b| / max|b|: per coil (rows of the leading axis) when coils, else over
+    the whole tensor.  A coil whose reference is all zero is compared in absolute terms."""
+    b = np.asarray(b, dtype=np.complex128)
+    a = np.asarray(a, dtype=np.complex128).reshape(b.shape)
+    if not coils or b.ndim == 0:
+        a, b = a.reshape(1, -1), b.reshape(1, -1)
+    else:
+        a, b = a.reshape(b.shape[0], -1), b.reshape(b.shape[0], -1)
+    if b.shape[1] == 0:
+        return 0.0
+    err = np.abs(a - b).max(axis=1)
+    ref = np.abs(b).max(axis=1)
+    return float(np.max(np.where(ref > 0, err / np.where(ref > 0, ref, 1.0), err)))
+
+
+def assert_close(a, b, tol, coils=False, what=""):
+    """Parity bar on an output: the relative L2 error over the whole tensor and the max-abs
+    error relative to max|ref| (per coil for coil-indexed outputs) are both <= tol."""
+    e2, em = rel(a, b), maxrel(a, b, coils)
+    assert e2 <= tol and em <= tol, f"{what}: rel L2 {e2:.3e}, max-abs/max|ref| {em:.3e}, bar {tol:.0e}"
+    return e2, em
+
+
 class Case:
     """A seeded problem with complex64-rounded inputs and its FP64 oracle."""
 
@@ -41,7 +65,9 @@ class Case:
             self.B = None
         rs = rng_for(seed, 4)
         self.traj = None
-        if mask == "radial":
+        if not isinstance(mask, str):
+            self.mask = np.asarray(mask, dtype=np.int64)
+        elif mask == "radial":
             nr = n_read if n_read is not None else 2 * max(dims)
             # both sides see the float32-rounded trajectory
             self.traj = golden_angle_radial(dims, spokes, nr).astype(np.float32).astype(np.float64)
@@ -59,7 +85,7 @@ class Case:
         elif mask == "empty":
             self.mask = np.zeros(0, dtype=np.int64)
         else:
-            self.mask = np.asarray(mask, dtype=np.int64)
+            raise ValueError(mask)
         if self.traj is None:
             self.M = int(self.mask.size)
             self.w = rs.uniform(0.2, 1.0, size=self.M).astype(np.float32).astype(np.float64) if weights else None

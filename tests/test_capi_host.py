@@ -28,7 +28,7 @@ def lib():
 
 def header_functions():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"\b(maxwell_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(maxwell_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_exports_every_declared_function(lib):
@@ -242,3 +242,21 @@ def test_plan_needs_a_gpu():
     from paper_2008_09042_amd.encoding import MaxwellPlan
     with pytest.raises(RuntimeError, match="GPU"):
         MaxwellPlan((8, 8), 1, B=np.ones((64, 1)), mask_idx=np.arange(4))
+
+
+def test_bf16_split_validation(lib):
+    """maxwell_bf16_split checks its arguments on the host before any HIP call."""
+    import ctypes
+    fake = ctypes.c_void_p(0x10000)
+    other = ctypes.c_void_p(0x20000)
+    third = ctypes.c_void_p(0x30000)
+    assert lib.maxwell_bf16_split(None, 0, 0, None, None, None) == L.MAXWELL_OK
+    assert lib.maxwell_bf16_split(None, 8, 0, other, third, None) == L.MAXWELL_ERR_INVALID_ARGUMENT
+    assert lib.maxwell_bf16_split(fake, 7, 1, other, third, None) == L.MAXWELL_ERR_INVALID_ARGUMENT
+    assert "even" in lib.maxwell_last_error().decode()
+    assert lib.maxwell_bf16_split(fake, 8, 3, other, third, None) == L.MAXWELL_ERR_INVALID_ARGUMENT
+    assert lib.maxwell_bf16_split(fake, -1, 0, other, third, None) == L.MAXWELL_ERR_INVALID_ARGUMENT
+    # hi overlapping x
+    assert lib.maxwell_bf16_split(fake, 1 << 20, 0, ctypes.c_void_p(0x10000 + 64), third, None) == \
+        L.MAXWELL_ERR_INVALID_ARGUMENT
+    assert "overlap" in lib.maxwell_last_error().decode()

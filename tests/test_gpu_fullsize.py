@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 import torch
 
-from _common import TOL, c64, rel
+from _common import TOL, assert_close, c64, maxrel, rel
 from oracle import Oracle
 from synth import problem as make
 
@@ -82,8 +82,9 @@ def test_fullsize_gradient(name, prec):
     if key not in _cache:
         _cache[key] = op.loss_and_grad(c64(p.x0), c64(p.c0), y, w)
     f_ref, gx_ref, gc_ref = _cache[key]
-    errs = (abs(f - f_ref) / f_ref, rel(gx, gx_ref), rel(gc, gc_ref))
-    print(f"[case] {name} {prec}: loss {errs[0]:.2e} gx {errs[1]:.2e} gc {errs[2]:.2e}", flush=True)
+    errs = (abs(f - f_ref) / f_ref, rel(gx, gx_ref), rel(gc, gc_ref), maxrel(gx, gx_ref), maxrel(gc, gc_ref, coils=True))
+    print(f"[case] {name} {prec}: loss {errs[0]:.2e} gx {errs[1]:.2e} gc {errs[2]:.2e} "
+          f"max-abs gx {errs[3]:.2e} gc (per coil) {errs[4]:.2e}", flush=True)
     assert max(errs) <= TOL[prec], errs
 
 
