@@ -9,7 +9,8 @@ struct PlaneArgs {
   int n0, n1, n2, r0, r1, r0p, r1p;  // r0p, r1p: ranks rounded up to 16
   int J, L, G;                       // coils, sampled lines, coils per workgroup
   const float2* T3;                  // [J][n2][r0][r1]  (core x_4 c x_3 U2)
-  const float2* xt;                  // [n2][n0][n1]     image, readout axis first
+  const float2* xt;                  // [n2][n0][n1]     image, readout axis first, times the
+                                     //                  chessboard sign (-1)^(i0 + i1)
   const int32_t* pos;                // [L]  k0 * n1 + k1 of each sampled line
   float2* Z;                         // [J][n2][L]  plane-DFT samples (fwd out / adj in)
   float2* T3b;                       // [J][n2][r0][r1] adjoint out (or null)
@@ -56,7 +57,9 @@ hipError_t plane_adj_launch(const PlaneArgs& a, hipStream_t st);
 int line_blocks(int J, int64_t L);
 hipError_t line_fwd_launch(const LineArgs& a, hipStream_t st);
 hipError_t line_adj_launch(const LineArgs& a, hipStream_t st);
-hipError_t transpose_launch(const float2* x, int64_t R, int64_t C, float2* xt, hipStream_t st);
+// xt = x^T (R x C -> C x R); with n1_sign > 0 each row r = i0 n1_sign + i1 of x is multiplied
+// by (-1)^(i0 + i1), the plane kernels' input chessboard sign (n1_sign even).
+hipError_t transpose_launch(const float2* x, int64_t R, int64_t C, int n1_sign, float2* xt, hipStream_t st);
 hipError_t reduce_transpose_launch(const float2* part, int ngrp, int64_t R, int64_t C, float alpha,
                                    const float* scale_dev, float2* gx, hipStream_t st);
 

@@ -827,7 +827,7 @@ static hipError_t fused_prepare(const Plan& p, const float2* x, const float2* c,
                                         p.precision, gws, st));
   }
   if (e != hipSuccess) return e;
-  return TIMED("transpose_x", transpose_launch(x, p.n[0] * p.n[1], p.n[2], wsp<float2>(ws, p.off_xt), st));
+  return TIMED("transpose_x", transpose_launch(x, p.n[0] * p.n[1], p.n[2], (int)p.n[1], wsp<float2>(ws, p.off_xt), st));
 }
 
 // out: E (y null) or the weighted residual; with `transfer` (y given) the residual goes out
@@ -858,7 +858,7 @@ static hipError_t fused_adjoint(const Plan& p, const float2* x, const float2* c,
     if (gx) {
       if ((e = fused_prepare(p, x, c, ws, st)) != hipSuccess) return e;
     } else {
-      e = TIMED("transpose_x", transpose_launch(x, p.n[0] * p.n[1], p.n[2], wsp<float2>(ws, p.off_xt), st));
+      e = TIMED("transpose_x", transpose_launch(x, p.n[0] * p.n[1], p.n[2], (int)p.n[1], wsp<float2>(ws, p.off_xt), st));
       if (e != hipSuccess) return e;
     }
   }

@@ -49,7 +49,7 @@ constexpr int FFT_CHUNK_ADJ = PMAX * PMAX / 2;   // (the adjoint holds P and gx 
 constexpr int SCAT = 4;                          // samples per thread loaded ahead of the scatter
 
 // ---------------------------------------------------------------- plane geometry
-template <int N0, int N1>
+template <int N0, int N1, int RB>
 struct Geo {
   int n0, n1, n2, r0, r1, PS;
   int n0b, n1b, r0b, r1b;  // 16-blocks of each extent
@@ -62,8 +62,8 @@ struct Geo {
     PS = n1 + 1;
     n0b = n0 / 16;
     n1b = n1 / 16;
-    r0b = a.r0p / 16;
-    r1b = a.r1p / 16;
+    r0b = RB ? RB : a.r0p / 16;
+    r1b = RB ? RB : a.r1p / 16;
   }
 };
 
@@ -76,8 +76,8 @@ struct Share {
   bool on;
 };
 
-template <int N0, int N1>
-__device__ __forceinline__ Share plane_share(const Geo<N0, N1>& g) {
+template <int N0, int N1, int RB>
+__device__ __forceinline__ Share plane_share(const Geo<N0, N1, RB>& g) {
   const int wave = threadIdx.x >> 6;
   Share s;
   s.q = NWAVE / g.n1b;
@@ -100,8 +100,8 @@ __device__ __forceinline__ void plane_block(int ngrp, int n2, int& i2, int& grp)
   grp = l % ngrp;
 }
 
-template <int N0, int N1>
-__device__ __forceinline__ void load_twiddles(const PlaneArgs& a, const Geo<N0, N1>& g, float2* lds) {
+template <int N0, int N1, int RB>
+__device__ __forceinline__ void load_twiddles(const PlaneArgs& a, const Geo<N0, N1, RB>& g, float2* lds) {
   float2* tw0 = lds + TW_OFF;
   float2* tw1 = tw0 + PMAX;
   for (int e = threadIdx.x; e < g.n0; e += PT) tw0[e] = a.tw0[e];
@@ -110,8 +110,8 @@ __device__ __forceinline__ void load_twiddles(const PlaneArgs& a, const Geo<N0, 
 
 // 2D centred DFT of the plane (chessboard signs applied by the caller); ends synchronised.
 // CH elements of a pass are held in registers at a time.
-template <int CH, int N0, int N1>
-__device__ __forceinline__ void plane_fft(const PlaneArgs& a, const Geo<N0, N1>& g, float2* lds, int dir) {
+template <int CH, int N0, int N1, int RB>
+__device__ __forceinline__ void plane_fft(const PlaneArgs& a, const Geo<N0, N1, RB>& g, float2* lds, int dir) {
   const float2* tw0 = lds + TW_OFF;
   const float2* tw1 = tw0 + PMAX;
   int tid = threadIdx.x;  // opaque: the passes' addresses are not hoisted out of the coil loop
@@ -155,8 +155,8 @@ struct WSlots {
   unsigned p[4];  // entry (q, t) in bits 16 (t & 1) of p[2 q + t / 2]; 0xffff for padding
 };
 
-template <int N0, int N1>
-__device__ __forceinline__ WSlots w_slots(const Geo<N0, N1>& g, int tid) {
+template <int N0, int N1, int RB>
+__device__ __forceinline__ WSlots w_slots(const Geo<N0, N1, RB>& g, int tid) {
   WSlots w;
   const int nfl = g.r0b * g.r1b * 64;  // (o block, step, lane) entries
 #pragma unroll
@@ -180,8 +180,8 @@ __device__ __forceinline__ WSlots w_slots(const Geo<N0, N1>& g, int tid) {
   return w;
 }
 
-template <int N0, int N1>
-__device__ __forceinline__ void w_load(const PlaneArgs& a, const Geo<N0, N1>& g, int j, int i2, const WSlots& sl,
+template <int N0, int N1, int RB>
+__device__ __forceinline__ void w_load(const PlaneArgs& a, const Geo<N0, N1, RB>& g, int j, int i2, const WSlots& sl,
                                        WPrefetch& w) {
   const float2* src = a.T3 + ((size_t)j * g.n2 + i2) * g.r0 * g.r1;
 #pragma unroll
@@ -199,8 +199,8 @@ __device__ __forceinline__ void w_load(const PlaneArgs& a, const Geo<N0, N1>& g,
     }
 }
 
-template <int PREC, int N0, int N1>
-__device__ __forceinline__ void w_store(const Geo<N0, N1>& g, float2* lds, int tid, const WPrefetch& w) {
+template <int PREC, int N0, int N1, int RB>
+__device__ __forceinline__ void w_store(const Geo<N0, N1, RB>& g, float2* lds, int tid, const WPrefetch& w) {
   const int nfl = g.r0b * g.r1b * 64;
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
@@ -214,8 +214,8 @@ __device__ __forceinline__ void w_store(const Geo<N0, N1>& g, float2* lds, int t
 
 // V[:, cb] = W U1^T[:, cb] (W staged) for the wave's column block, as the B operands (one
 // per K16 step over p0) of P = U0 V.  u1: this column block's U1^T fragments.
-template <int PREC, int N0, int N1>
-__device__ __forceinline__ void coil_v(const Geo<N0, N1>& g, const float2* lds, int lane,
+template <int PREC, int N0, int N1, int RB>
+__device__ __forceinline__ void coil_v(const Geo<N0, N1, RB>& g, const float2* lds, int lane,
                                        const typename Tile<PREC>::B (&u1)[3], typename Tile<PREC>::B (&vb)[3]) {
   f32x4 cr[3], ci[3];
 #pragma unroll
@@ -233,8 +233,8 @@ __device__ __forceinline__ void coil_v(const Geo<N0, N1>& g, const float2* lds, 
 
 // P tiles of the wave's share: P[rb][cb] = sum_s U0[rb][s] V[s][cb], U0 staged in the
 // plane region, V in registers.
-template <int PREC, int N0, int N1>
-__device__ __forceinline__ void coil_p(const Geo<N0, N1>& g, const float2* lds, const Share& sh, int lane,
+template <int PREC, int N0, int N1, int RB>
+__device__ __forceinline__ void coil_p(const Geo<N0, N1, RB>& g, const float2* lds, const Share& sh, int lane,
                                        const typename Tile<PREC>::B (&vb)[3], f32x4 (&pr)[8], f32x4 (&pi)[8]) {
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
@@ -254,8 +254,8 @@ __device__ __forceinline__ void coil_p(const Geo<N0, N1>& g, const float2* lds, 
 // block w % n0b over a 1 / q share of the K16 steps over i1.  conj(U1) is staged through
 // two LDS step buffers, each thread carrying the pieces of the next two steps in
 // registers (loads issued two steps ahead).  Ends synchronised.
-template <int PREC, int N0, int N1>
-__device__ __forceinline__ void adjoint_w(const PlaneArgs& a, const Geo<N0, N1>& g, int j, int i2, float2* lds,
+template <int PREC, int N0, int N1, int RB>
+__device__ __forceinline__ void adjoint_w(const PlaneArgs& a, const Geo<N0, N1, RB>& g, int j, int i2, float2* lds,
                                           int lane, int tid) {
   const int wave = threadIdx.x >> 6, grp = lane >> 4;
   const int qy = NWAVE / g.n0b, yb = wave % g.n0b, kq = wave / g.n0b;
@@ -356,8 +356,8 @@ __device__ __forceinline__ void adjoint_w(const PlaneArgs& a, const Geo<N0, N1>&
 // Per coil: W (and in the adjoint the coil's samples) loaded early; U0 (fragment order,
 // the whole factor) staged in the plane region and W in the stage region; V = W U1^T for
 // the wave's column block into registers, then the wave's P tiles.
-template <int PREC, int N0, int N1>
-__device__ __forceinline__ void coil_map(const PlaneArgs& a, const Geo<N0, N1>& g, float2* lds, const Share& sh,
+template <int PREC, int N0, int N1, int RB>
+__device__ __forceinline__ void coil_map(const PlaneArgs& a, const Geo<N0, N1, RB>& g, float2* lds, const Share& sh,
                                          int lane, int tid, const WPrefetch& w, f32x4 (&pr)[8], f32x4 (&pi)[8]) {
   // the column block's U1^T fragments, in flight across the stores
   typename Tile<PREC>::B u1[3];
@@ -378,10 +378,10 @@ __device__ __forceinline__ void coil_map(const PlaneArgs& a, const Geo<N0, N1>& 
   __syncthreads();  // U0 is consumed; the plane region is free
 }
 
-template <int PREC, int N0, int N1>
+template <int PREC, int N0, int N1, int RB>
 __global__ __launch_bounds__(PT) void plane_fwd_kernel(PlaneArgs a) {
   __shared__ float2 lds[LDS_ELEMS];
-  const Geo<N0, N1> g(a);
+  const Geo<N0, N1, RB> g(a);
   const int ngrp = (a.J + a.G - 1) / a.G;
   int i2, gi;
   plane_block(ngrp, g.n2, i2, gi);
@@ -415,7 +415,7 @@ __global__ __launch_bounds__(PT) void plane_fwd_kernel(PlaneArgs a) {
     f32x4 pr[8], pi[8];
     coil_map<PREC>(a, g, lds, sh, lane, tid, w, pr, pi);
     if (j + 1 < j1) w_load(a, g, j + 1, i2, wsl, w);
-    // m = x (.) P with the input chessboard sign
+    // m = x (.) P; the input chessboard sign of the centred DFT is carried by xt
     if (sh.on) {
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
@@ -425,9 +425,7 @@ __global__ __launch_bounds__(PT) void plane_fwd_kernel(PlaneArgs a) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int i0 = 16 * rb + 4 * grp + r;
-            float2 v = cmul(make_float2(pr[i][r], pi[i][r]), xr[i][r]);
-            if ((i0 + i1) & 1) v = make_float2(-v.x, -v.y);
-            lds[i0 * g.PS + i1] = v;
+            lds[i0 * g.PS + i1] = cmul(make_float2(pr[i][r], pi[i][r]), xr[i][r]);
           }
         }
       }
@@ -454,10 +452,10 @@ __global__ __launch_bounds__(PT) void plane_fwd_kernel(PlaneArgs a) {
   }
 }
 
-template <int PREC, int N0, int N1>
+template <int PREC, int N0, int N1, int RB>
 __global__ __launch_bounds__(PT) void plane_adj_kernel(PlaneArgs a) {
   __shared__ float2 lds[LDS_ELEMS];
-  const Geo<N0, N1> g(a);
+  const Geo<N0, N1, RB> g(a);
   const int ngrp = (a.J + a.G - 1) / a.G;
   int i2, gi;
   plane_block(ngrp, g.n2, i2, gi);
@@ -510,8 +508,10 @@ __global__ __launch_bounds__(PT) void plane_adj_kernel(PlaneArgs a) {
     }
     __syncthreads();
     plane_fft<FFT_CHUNK_ADJ>(a, g, lds, +1);
-    // g (output chessboard sign); gx += conj(P) g in registers; h = conj(x) g into the plane.
-    // x in two batches of four tiles, each batch's loads issued together.
+    // g = s g' (g' the plane after the transform, s the output chessboard sign):
+    // gx += conj(P) s g' in registers; h = conj(x) s g' = conj(s x) g' into the plane, s x
+    // being what xt holds.  x in two batches of four tiles, each batch's loads issued
+    // together.
     if (sh.on) {
 #pragma unroll
       for (int hb = 0; hb < 2; ++hb) {
@@ -541,10 +541,10 @@ __global__ __launch_bounds__(PT) void plane_adj_kernel(PlaneArgs a) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
               const int i0 = 16 * rb + 4 * grp + r;
-              float2 gv = gvs[ii][r];
-              if ((i0 + i1) & 1) gv = make_float2(-gv.x, -gv.y);
+              const float2 gv = gvs[ii][r];
               if (want_gx) {
-                const float2 c = cmulc(make_float2(pr[i][r], pi[i][r]), gv);
+                float2 c = cmulc(make_float2(pr[i][r], pi[i][r]), gv);
+                if ((i0 + i1) & 1) c = make_float2(-c.x, -c.y);
                 gr[i][r] += c.x;
                 gim[i][r] += c.y;
               }
@@ -717,14 +717,20 @@ __global__ __launch_bounds__(LNT) void line_adj_kernel(LineArgs a) {
 // ---------------------------------------------------------------- transposes
 constexpr int TT = 32;
 
-// xt[c][r] = x[r][c] for an R x C matrix (complex)
-__global__ void transpose_kernel(const float2* __restrict__ x, int64_t R, int64_t C, float2* __restrict__ xt) {
+// xt[c][r] = s(r) x[r][c] for an R x C matrix (complex).  With n1 > 0 (even), r = i0 n1 + i1
+// and s(r) = (-1)^(i0 + i1), the input chessboard sign of the centred plane DFT; else s = 1.
+__global__ void transpose_kernel(const float2* __restrict__ x, int64_t R, int64_t C, int n1, float2* __restrict__ xt) {
   __shared__ float2 t[TT][TT + 1];
   const int64_t tr = (int64_t)blockIdx.y * TT, tc = (int64_t)blockIdx.x * TT;
   const int tx = threadIdx.x % TT, ty = threadIdx.x / TT;
   for (int k = ty; k < TT; k += 256 / TT) {
     const int64_t r = tr + k, c = tc + tx;
-    if (r < R && c < C) t[k][tx] = x[r * C + c];
+    if (r < R && c < C) {
+      float2 v = x[r * C + c];
+      // n1 even: i0 + i1 = r - i0 (n1 - 1) has the parity of r + i0
+      if (n1 > 0 && ((r + r / n1) & 1)) v = make_float2(-v.x, -v.y);
+      t[k][tx] = v;
+    }
   }
   __syncthreads();
   for (int k = ty; k < TT; k += 256 / TT) {
@@ -759,15 +765,19 @@ template <int PREC>
 hipError_t plane_launch_prec(const PlaneArgs& a, bool adj, hipStream_t st) {
   const int ngrp = (a.J + a.G - 1) / a.G;
   const dim3 grid((unsigned)(a.n2 * ngrp)), block(PT);
-  if (a.n0 == 128 && a.n1 == 128) {
-    if (adj) hipLaunchKernelGGL((plane_adj_kernel<PREC, 128, 128>), grid, block, 0, st, a);
-    else hipLaunchKernelGGL((plane_fwd_kernel<PREC, 128, 128>), grid, block, 0, st, a);
+  // ranks in (32, 48] (three K16 blocks each) take compile-time rank blocks at 128 x 128
+  const bool rb3 = a.r0p == 48 && a.r1p == 48;
+  if (a.n0 == 128 && a.n1 == 128 && rb3 && !adj) {
+    hipLaunchKernelGGL((plane_fwd_kernel<PREC, 128, 128, 3>), grid, block, 0, st, a);
+  } else if (a.n0 == 128 && a.n1 == 128) {
+    if (adj) hipLaunchKernelGGL((plane_adj_kernel<PREC, 128, 128, 0>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((plane_fwd_kernel<PREC, 128, 128, 0>), grid, block, 0, st, a);
   } else if (a.n0 == 64 && a.n1 == 64) {
-    if (adj) hipLaunchKernelGGL((plane_adj_kernel<PREC, 64, 64>), grid, block, 0, st, a);
-    else hipLaunchKernelGGL((plane_fwd_kernel<PREC, 64, 64>), grid, block, 0, st, a);
+    if (adj) hipLaunchKernelGGL((plane_adj_kernel<PREC, 64, 64, 0>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((plane_fwd_kernel<PREC, 64, 64, 0>), grid, block, 0, st, a);
   } else {
-    if (adj) hipLaunchKernelGGL((plane_adj_kernel<PREC, 0, 0>), grid, block, 0, st, a);
-    else hipLaunchKernelGGL((plane_fwd_kernel<PREC, 0, 0>), grid, block, 0, st, a);
+    if (adj) hipLaunchKernelGGL((plane_adj_kernel<PREC, 0, 0, 0>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((plane_fwd_kernel<PREC, 0, 0, 0>), grid, block, 0, st, a);
   }
   return hipGetLastError();
 }
@@ -798,9 +808,9 @@ hipError_t line_adj_launch(const LineArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t transpose_launch(const float2* x, int64_t R, int64_t C, float2* xt, hipStream_t st) {
+hipError_t transpose_launch(const float2* x, int64_t R, int64_t C, int n1_sign, float2* xt, hipStream_t st) {
   dim3 grid((unsigned)((C + TT - 1) / TT), (unsigned)((R + TT - 1) / TT));
-  hipLaunchKernelGGL(transpose_kernel, grid, dim3(256), 0, st, x, R, C, xt);
+  hipLaunchKernelGGL(transpose_kernel, grid, dim3(256), 0, st, x, R, C, n1_sign, xt);
   return hipGetLastError();
 }
 
