@@ -191,12 +191,24 @@ def kernel_work(name, p, prec):
     return table.get(name)
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(p, coils=32, repeats=2):
-    """The FP64 oracle on host cores: `repeats` gradient evaluations over `coils` coils."""
+    """The FP64 oracle on host cores: `repeats` gradient evaluations over `coils` coils, with BLAS
+    threads and scipy.fft workers both set to the cores in the process affinity mask."""
+    import scipy.fft
     import threadpoolctl
     from oracle import Oracle
     ncores = len(os.sched_getaffinity(0))
-    with threadpoolctl.threadpool_limits(limits=ncores):
+    with threadpoolctl.threadpool_limits(limits=ncores), scipy.fft.set_workers(ncores):
         info = threadpoolctl.threadpool_info()
         threads = max([i.get("num_threads", 1) for i in info] + [1])
         op = Oracle(p.dims, U=p.U, core=p.core, mask_idx=p.mask_idx)
@@ -206,10 +218,22 @@ def cpu_baseline(p, coils=32, repeats=2):
         for _ in range(repeats):
             op.loss_and_grad(p.x0, p.c0[:coils], y)
         dt = time.perf_counter() - t0
-    return {"value": repeats * coils / dt, "unit": "coil-images/s", "cores": int(threads), "kind": "oracle",
+    return {"value": repeats * coils / dt, "unit": "coil-images/s", "cores": int(max(threads, ncores)),
+            "kind": "oracle", "cpu": cpu_model(),
             "sample": f"{repeats} FP64 gradient evaluations over {coils} of the 32 coils at 128^3 "
-                      f"(Tucker 40^3 x 300, 262,144 samples/coil): {dt:.1f} s; NumPy FFT single-threaded, "
+                      f"(Tucker 40^3 x 300, 262,144 samples/coil): {dt:.1f} s; scipy.fft workers = {ncores}, "
                       f"BLAS threads = {threads}"}
+
+
+# The paper's only timed operator (Supporting Table S1): one Tucker-basis matrix-vector product
+# (q = 75 / 200 / 500 columns, FOV 192 x 192 x 170, eps_t = 1e-4), with its hardware.  Context,
+# not a target: a different operator (the basis product alone, one coil) on other machines.
+PAPER_CONTEXT = {
+    "source": "Supporting Table S1, Tucker basis MVP time (s) at q = 75 / 200 / 500, FOV 192x192x170",
+    "tucker_mvp_s_gpu": {"q75": 0.6, "q200": 1.1, "q500": 2.9, "hardware": "Tesla V100, PyTorch, CUDA 10.1"},
+    "tucker_mvp_s_cpu": {"q75": 18.9, "q200": 50.4, "q500": 127.1, "hardware": "Intel Xeon"},
+    "dense_mvp_s_gpu": {"q75": 0.1, "hardware": "Tesla V100 (q = 200, 500 do not fit)"},
+}
 
 
 def device_smooth_basis(torch, dims, params, dev):
@@ -596,6 +620,7 @@ def main():
 
     results = {}
     grads = {}
+    kernels_by_prec = {}
     order = [args.precision] + ([] if args.no_compare else [q for q in ("bf16_split", "fp32") if q != args.precision])
     for prec in order:
         plan = plans[prec]
@@ -613,16 +638,15 @@ def main():
         results[prec] = ms
         grads[prec] = (x.grad.clone(), c.grad.clone())
         log(f"[bench] {prec}: {ms:.3f} ms/step ({p.J * 1000.0 / ms:.0f} coil-images/s), wall {wall:.2f}s")
-        if prec == args.precision:
-            # same K steps again with per-kernel HIP events recorded by the library on the launch stream
-            plan.set_timing(True)
-            ms_t, _ = time_steps(step, args.steps, 0, torch)
-            kt = plan.timing()
-            plan.set_timing(False)
-            kernels = {k: {"launches": n, "avg_us": 1000.0 * t / n} for k, (n, t) in kt.items() if n}
-            log(f"[bench] kernel timing pass: {ms_t:.3f} ms/step; " +
-                ", ".join(f"{k} {v['avg_us']:.1f}us x{v['launches']}" for k, v in
-                          sorted(kernels.items(), key=lambda kv: -kv[1]["avg_us"] * kv[1]["launches"])))
+        # same K steps again with per-kernel HIP events recorded by the library on the launch stream
+        plan.set_timing(True)
+        ms_t, _ = time_steps(step, args.steps, 0, torch)
+        kt = plan.timing()
+        plan.set_timing(False)
+        kernels_by_prec[prec] = {k: {"launches": n, "avg_us": 1000.0 * t / n} for k, (n, t) in kt.items() if n}
+        log(f"[bench] {prec} kernel timing pass: {ms_t:.3f} ms/step; " +
+            ", ".join(f"{k} {v['avg_us']:.1f}us x{v['launches']}" for k, v in
+                      sorted(kernels_by_prec[prec].items(), key=lambda kv: -kv[1]["avg_us"] * kv[1]["launches"])))
 
     prec = args.precision
     ms = results[prec]
@@ -650,6 +674,7 @@ def main():
         out["bf16_split_vs_fp32_rel_diff"] = {
             "gx": float(torch.linalg.vector_norm(gxs - gx32) / torch.linalg.vector_norm(gx32)),
             "gc": float(torch.linalg.vector_norm(gcs - gc32) / torch.linalg.vector_norm(gc32))}
+    kernels = kernels_by_prec[prec]
     dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"])
     work = kernel_work(dom, p, prec)
     if work is not None:
@@ -659,7 +684,21 @@ def main():
         out["roofline"] = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
                            "frac": achieved / peak, "traffic": recorded_traffic(dom),
                            "per_launch": amount, "avg_launch_us": kernels[dom]["avg_us"]}
+    if "fp32" in kernels_by_prec:
+        # the basis-apply kernels of the FP32 plan against the FP32 matrix-core peak (algorithmic
+        # flops: 8 per complex multiply-accumulate of the mode products each kernel performs)
+        k32 = kernels_by_prec["fp32"]
+        out["roofline_fp32"] = {}
+        for name in ("plane_fwd", "plane_adj"):
+            if name in k32:
+                bound, unit, amount, peak = kernel_work(name, p, "fp32")
+                achieved = amount / (k32[name]["avg_us"] * 1e-6) / 1e12
+                out["roofline_fp32"][name] = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+                                              "frac": achieved / peak, "per_launch": amount,
+                                              "avg_launch_us": k32[name]["avg_us"]}
+        out["kernels_fp32"] = k32
     out["kernels"] = kernels
+    out["paper_context"] = PAPER_CONTEXT
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on the host (bounded sample) ...")
         out["cpu_baseline"] = cpu_baseline(p)

@@ -27,6 +27,7 @@ import math
 from typing import Sequence
 
 import numpy as np
+import scipy.fft
 from scipy.special import i0
 
 
@@ -107,7 +108,7 @@ def nufft_type2(img: np.ndarray, traj: np.ndarray, W: int = 6, sigma: float = 2.
     pad[sl] = pre
     # (iii) centred DFT, unnormalised
     axes = tuple(range(nd))
-    grid = np.fft.fftshift(np.fft.fftn(np.fft.ifftshift(pad, axes=axes), axes=axes), axes=axes)
+    grid = scipy.fft.fftshift(scipy.fft.fftn(scipy.fft.ifftshift(pad, axes=axes), axes=axes), axes=axes)
     # (iv) interpolate
     idx, wts = _taps(np.asarray(traj, dtype=np.float64), gdims, W, sigma, beta)
     M = traj.shape[0]
@@ -151,7 +152,7 @@ def nufft_type1(y: np.ndarray, traj: np.ndarray, dims: Sequence[int], W: int = 6
     grid = (gre + 1j * gim).reshape(gdims)
     # adjoint of (iii): the conjugate-transposed unnormalised DFT = Gtot * inverse DFT
     axes = tuple(range(nd))
-    pad = np.fft.fftshift(np.fft.ifftn(np.fft.ifftshift(grid, axes=axes), axes=axes),
+    pad = scipy.fft.fftshift(scipy.fft.ifftn(scipy.fft.ifftshift(grid, axes=axes), axes=axes),
                           axes=axes) * Gtot
     # adjoint of (ii): crop
     sl = tuple(slice(G // 2 - n // 2, G // 2 - n // 2 + n) for G, n in zip(gdims, dims))

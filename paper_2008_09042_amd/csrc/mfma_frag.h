@@ -1,7 +1,9 @@
 // Matrix-core tiles and fragment-ordered operands shared by the HIP kernels.
 //
 // Complex products on the matrix cores.  FP32: each complex product is four real
-// products on v_mfma_f32_16x16x4_f32.  BF16_SPLIT: the complex product over K is
+// products on v_mfma_f32_16x16x4_f32 (cmfma), or three in the accumulator form Tile<0>::Acc
+// (Re = sum ar br - sum ai bi, Im = sum (ar + ai)(br + bi) - sum ar br - sum ai bi, the
+// three-multiplication complex product).  BF16_SPLIT: the complex product over K is
 // written as two real products over 2K (real-block form): with a' = (Re a_0, Im a_0,
 // Re a_1, ...), Re c = a'.(Re b_0, -Im b_0, ...) and Im c = a'.(Im b_0, Re b_0, ...);
 // every real operand is split into hi = bf16(v), lo = bf16(v - hi) and each real
@@ -103,10 +105,15 @@ struct Tile<1> {  // BF16 split in the real-block form
   static __device__ __forceinline__ void mma(f32x4& cr, f32x4& ci, const A& a, const B& b) {
     mfma6(cr, ci, a.h, a.l, b.rh, b.rl, b.ih, b.il);
   }
+  // accumulator form (the same products here)
+  struct Acc { f32x4 r, i; };
+  static __device__ __forceinline__ Acc zero() { return Acc{z4(), z4()}; }
+  static __device__ __forceinline__ void mma(Acc& c, const A& a, const B& b) { mma(c.r, c.i, a, b); }
+  static __device__ __forceinline__ void finish(const Acc& c, f32x4& cr, f32x4& ci) { cr = c.r; ci = c.i; }
 };
 
 template <>
-struct Tile<0> {  // FP32: four real products per complex product; sub-step t uses k = 4 g + t
+struct Tile<0> {  // FP32; sub-step t uses k = 4 g + t (mma: four real products, Acc form: three)
   struct A { float2 v[4]; };
   struct B { float2 v[4]; };
   static __device__ __forceinline__ A make_a(const float2 (&v)[4]) { return A{{v[0], v[1], v[2], v[3]}}; }
@@ -114,6 +121,22 @@ struct Tile<0> {  // FP32: four real products per complex product; sub-step t us
   static __device__ __forceinline__ void mma(f32x4& cr, f32x4& ci, const A& a, const B& b) {
 #pragma unroll
     for (int t = 0; t < 4; ++t) cmfma(cr, ci, a.v[t], b.v[t]);
+  }
+  // accumulator form: three real products per complex product (p1 = sum ar br,
+  // p2 = sum ai bi, p3 = sum (ar + ai)(br + bi)); finish forms Re = p1 - p2, Im = p3 - p1 - p2
+  struct Acc { f32x4 p1, p2, p3; };
+  static __device__ __forceinline__ Acc zero() { return Acc{z4(), z4(), z4()}; }
+  static __device__ __forceinline__ void mma(Acc& c, const A& a, const B& b) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      c.p1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[t].x, b.v[t].x, c.p1, 0, 0, 0);
+      c.p2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[t].y, b.v[t].y, c.p2, 0, 0, 0);
+      c.p3 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[t].x + a.v[t].y, b.v[t].x + b.v[t].y, c.p3, 0, 0, 0);
+    }
+  }
+  static __device__ __forceinline__ void finish(const Acc& c, f32x4& cr, f32x4& ci) {
+    cr = c.p1 - c.p2;
+    ci = c.p3 - c.p1 - c.p2;
   }
 };
 

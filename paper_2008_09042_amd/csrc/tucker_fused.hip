@@ -217,18 +217,22 @@ __device__ __forceinline__ void w_store(const Geo<N0, N1, RB>& g, float2* lds, i
 template <int PREC, int N0, int N1, int RB>
 __device__ __forceinline__ void coil_v(const Geo<N0, N1, RB>& g, const float2* lds, int lane,
                                        const typename Tile<PREC>::B (&u1)[3], typename Tile<PREC>::B (&vb)[3]) {
-  f32x4 cr[3], ci[3];
+  typename Tile<PREC>::Acc c[3];
 #pragma unroll
-  for (int m = 0; m < 3; ++m) { cr[m] = z4(); ci[m] = z4(); }
+  for (int m = 0; m < 3; ++m) c[m] = Tile<PREC>::zero();
 #pragma unroll
   for (int s = 0; s < 3; ++s)
     if (s < g.r1b) {
 #pragma unroll
       for (int m = 0; m < 3; ++m)
-        if (m < g.r0b) Tile<PREC>::mma(cr[m], ci[m], frag_a<PREC>(lds + STAGE_OFF, g.r1b, m, s, lane), u1[s]);
+        if (m < g.r0b) Tile<PREC>::mma(c[m], frag_a<PREC>(lds + STAGE_OFF, g.r1b, m, s, lane), u1[s]);
     }
 #pragma unroll
-  for (int m = 0; m < 3; ++m) vb[m] = tile_as_b<PREC>(cr[m], ci[m]);
+  for (int m = 0; m < 3; ++m) {
+    f32x4 cr, ci;
+    Tile<PREC>::finish(c[m], cr, ci);
+    vb[m] = tile_as_b<PREC>(cr, ci);
+  }
 }
 
 // P tiles of the wave's share: P[rb][cb] = sum_s U0[rb][s] V[s][cb], U0 staged in the
@@ -238,14 +242,14 @@ __device__ __forceinline__ void coil_p(const Geo<N0, N1, RB>& g, const float2* l
                                        const typename Tile<PREC>::B (&vb)[3], f32x4 (&pr)[8], f32x4 (&pi)[8]) {
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
-    pr[i] = z4();
-    pi[i] = z4();
+    typename Tile<PREC>::Acc c = Tile<PREC>::zero();
     const int rb = sh.part + i * sh.q;
     if (sh.on && rb < g.n0b) {
 #pragma unroll
       for (int s = 0; s < 3; ++s)
-        if (s < g.r0b) Tile<PREC>::mma(pr[i], pi[i], frag_a<PREC>(lds, g.r0b, rb, s, lane), vb[s]);
+        if (s < g.r0b) Tile<PREC>::mma(c, frag_a<PREC>(lds, g.r0b, rb, s, lane), vb[s]);
     }
+    Tile<PREC>::finish(c, pr[i], pi[i]);
   }
 }
 
@@ -278,9 +282,9 @@ __device__ __forceinline__ void adjoint_w(const PlaneArgs& a, const Geo<N0, N1, 
       if (two) q[tid + PT] = p1;
     }
   };
-  f32x4 yr[3], yi[3];
+  typename Tile<PREC>::Acc yc[3];
 #pragma unroll
-  for (int nb = 0; nb < 3; ++nb) { yr[nb] = z4(); yi[nb] = z4(); }
+  for (int nb = 0; nb < 3; ++nb) yc[nb] = Tile<PREC>::zero();
   const int i0 = 16 * yb + (lane & 15);
   auto compute = [&](int s) {
     if (on && (s % qy) == kq) {
@@ -292,7 +296,7 @@ __device__ __forceinline__ void adjoint_w(const PlaneArgs& a, const Geo<N0, N1, 
 #pragma unroll
       for (int nb = 0; nb < 3; ++nb)
         if (nb < g.r1b) {
-          Tile<PREC>::mma(yr[nb], yi[nb], av, frag_b<PREC>(buf, g.r1b, nb, 0, lane));
+          Tile<PREC>::mma(yc[nb], av, frag_b<PREC>(buf, g.r1b, nb, 0, lane));
           __builtin_amdgcn_sched_barrier(0);  // one B fragment live at a time
         }
     }
@@ -322,7 +326,11 @@ __device__ __forceinline__ void adjoint_w(const PlaneArgs& a, const Geo<N0, N1, 
     typename Tile<PREC>::B yf[3];
 #pragma unroll
     for (int nb = 0; nb < 3; ++nb)
-      if (nb < g.r1b) yf[nb] = tile_as_b<PREC>(yr[nb], yi[nb]);
+      if (nb < g.r1b) {
+        f32x4 yr, yi;
+        Tile<PREC>::finish(yc[nb], yr, yi);
+        yf[nb] = tile_as_b<PREC>(yr, yi);
+      }
 #pragma unroll
     for (int mb = 0; mb < 3; ++mb)
       if (mb < g.r0b) {
@@ -330,8 +338,10 @@ __device__ __forceinline__ void adjoint_w(const PlaneArgs& a, const Geo<N0, N1, 
 #pragma unroll
         for (int nb = 0; nb < 3; ++nb)
           if (nb < g.r1b) {
-            f32x4 wr = z4(), wi = z4();
-            Tile<PREC>::mma(wr, wi, ua, yf[nb]);
+            typename Tile<PREC>::Acc wc = Tile<PREC>::zero();
+            Tile<PREC>::mma(wc, ua, yf[nb]);
+            f32x4 wr, wi;
+            Tile<PREC>::finish(wc, wr, wi);
 #pragma unroll
             for (int r = 0; r < 4; ++r)
               lds[((wave * 3 + mb) * 3 + nb) * 256 + (4 * grp + r) * 16 + (lane & 15)] = make_float2(wr[r], wi[r]);
