@@ -15,9 +15,12 @@
 // fragments and its lanes' entries of the small per-call operand (c or T1b, L2-resident)
 // itself, FD reduction steps ahead, and splits the latter in registers.  No LDS and no
 // barriers, so the loads of several steps stay in flight.
-// FP32 kernels: v_mfma_f32_16x16x4_f32, four real products per complex product, with the
-// per-call operand staged through double-buffered LDS shared by the workgroup's waves.
-// The adjoint reduces over rho in chunks whose partials are summed in a fixed order.
+// FP32 kernels: v_mfma_f32_16x16x4_f32 in the same independent-wave form, over FP32 core
+// copies in fragment order built once per plan, with three real products per complex
+// product (Tile<0>::Acc).  (The kernels that read the caller's core directly, four real
+// products per complex product with the per-call operand staged through LDS, remain for
+// plans built without the copies.)  The adjoint reduces over rho in chunks whose partials
+// are summed in a fixed order.
 #include "../../include/maxwell.h"
 #include "core.h"
 #include "mfma_frag.h"
@@ -114,6 +117,169 @@ __global__ __launch_bounds__(NT) void core_fwd_bf16_kernel(CoreArgs a) {
         const int64_t rw = 16 * (rb0 + m) + 4 * grp + r;
         const int j = 16 * c + (lane & 15);
         if (rw < a.g.R && j < a.J) a.out[(int64_t)j * a.g.R + rw] = make_float2(cr[m][c][r], ci[m][c][r]);
+      }
+}
+
+// ---------------------------------------------------------------- FP32, fragment order
+// The FP32 core copies: A operands in fragment order, [row block][K16 step][lane][4 complex]
+// (frag_a<0>).  Forward: A(rho, k) = core[rho][k], (R + 15) / 16 row blocks x Kp / 16 steps.
+// Adjoint: A(k, rho) = conj(core[rho][k]), Kp / 16 row blocks x Rp / 16 steps.  Zero past R
+// and K.
+__global__ void core_frag32_kernel(const float2* __restrict__ core, int64_t R, int K, int adj, int64_t nrb,
+                                   int64_t steps, float4* __restrict__ dst) {
+  const int64_t total = nrb * steps * 64;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t rb = e / (steps * 64), st = (e / 64) % steps;
+    const int lane = (int)(e % 64);
+    const int64_t row = 16 * rb + lane % 16;
+    float2 v[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int64_t kk = 16 * st + 4 * (lane / 16) + t;
+      v[t] = make_float2(0.f, 0.f);
+      if (!adj) {
+        if (row < R && kk < K) v[t] = core[row * K + kk];
+      } else if (row < K && kk < R) {
+        v[t] = cconj(core[kk * K + row]);
+      }
+    }
+    dst[2 * e] = make_float4(v[0].x, v[0].y, v[1].x, v[1].y);
+    dst[2 * e + 1] = make_float4(v[2].x, v[2].y, v[3].x, v[3].y);
+  }
+}
+
+// One wave: RB row blocks (16 RB rho) against all NB coil blocks, FD steps of loads in flight.
+template <int NB, int RB, int FD = FWD_FD>
+__global__ __launch_bounds__(NT) void core_fwd_f32f_kernel(CoreArgs a) {
+  const int lane = threadIdx.x & 63, grp = lane >> 4;
+  const int steps = a.g.Kp / 16;
+  const int64_t rbs = (a.g.R + 15) / 16;
+  const int64_t rb0 = ((int64_t)blockIdx.x * (NT / 64) + (threadIdx.x >> 6)) * RB;
+  if (rb0 >= rbs) return;
+  int64_t rbm[RB];
+#pragma unroll
+  for (int m = 0; m < RB; ++m) rbm[m] = min(rb0 + m, rbs - 1);
+  const float2* row[NB];
+#pragma unroll
+  for (int cb = 0; cb < NB; ++cb) row[cb] = a.in + (int64_t)min(16 * cb + (lane & 15), a.J - 1) * a.g.K;
+  Tile<0>::A av[FD][RB];
+  float2 bv[FD][NB][4];
+  auto load = [&](int d, int s) {
+    s = min(s, steps - 1);
+#pragma unroll
+    for (int m = 0; m < RB; ++m) av[d][m] = frag_a<0>(a.fwd_f32, steps, (int)rbm[m], s, lane);
+    call_operand<NB>(row, 16 * (int64_t)s, a.g.K, grp, bv[d]);
+  };
+  Tile<0>::Acc acc[RB][NB];
+#pragma unroll
+  for (int m = 0; m < RB; ++m)
+#pragma unroll
+    for (int c = 0; c < NB; ++c) acc[m][c] = Tile<0>::zero();
+  auto compute = [&](int d) {
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      const Tile<0>::B b = Tile<0>::make_b(bv[d][c]);
+#pragma unroll
+      for (int m = 0; m < RB; ++m) Tile<0>::mma(acc[m][c], av[d][m], b);
+    }
+  };
+#pragma unroll
+  for (int d = 0; d < FD; ++d) load(d, d);
+  int s0 = 0;
+  for (; s0 + FD <= steps; s0 += FD) {
+#pragma unroll
+    for (int d = 0; d < FD; ++d) {
+      compute(d);
+      load(d, s0 + d + FD);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+#pragma unroll
+  for (int d = 0; d + 1 < FD; ++d)
+    if (s0 + d < steps) compute(d);
+#pragma unroll
+  for (int m = 0; m < RB; ++m)
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      f32x4 cr, ci;
+      Tile<0>::finish(acc[m][c], cr, ci);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t rw = 16 * (rb0 + m) + 4 * grp + r;
+        const int j = 16 * c + (lane & 15);
+        if (rw < a.g.R && j < a.J) a.out[(int64_t)j * a.g.R + rw] = make_float2(cr[r], ci[r]);
+      }
+    }
+}
+
+// Adjoint: one rho chunk of RC per workgroup and RB k row blocks per wave (workgroups of one
+// chunk on one XCD, as in the BF16-split kernel); partials per chunk, summed afterwards.
+// Launched with two steps in flight (the three-product accumulators take the registers of
+// the third).
+template <int NB, int RB, int FD = ADJ_FD>
+__global__ __launch_bounds__(NT) void core_adj_f32f_kernel(CoreArgs a, int nch, int kgroups) {
+  const int xcd = blockIdx.x % 8, i = blockIdx.x / 8;
+  const int ky = i % kgroups, ch = 8 * (i / kgroups) + xcd;
+  const int lane = threadIdx.x & 63, grp = lane >> 4, wave = threadIdx.x >> 6;
+  const int mbl = a.g.Kp / 16;
+  const int mb0 = ky * (4 * RB) + wave * RB;
+  if (ch >= nch || mb0 >= mbl) return;
+  const int64_t rho0 = (int64_t)ch * RC;
+  const int steps_total = (int)(a.g.Rp / 16);
+  constexpr int steps = RC / 16;
+  int mbm[RB];
+#pragma unroll
+  for (int m = 0; m < RB; ++m) mbm[m] = min(mb0 + m, mbl - 1);
+  const float2* row[NB];
+#pragma unroll
+  for (int cb = 0; cb < NB; ++cb) row[cb] = a.in + (int64_t)min(16 * cb + (lane & 15), a.J - 1) * a.g.R;
+  Tile<0>::A av[FD][RB];
+  float2 bv[FD][NB][4];
+  auto load = [&](int d, int s) {
+    s = min(s, steps - 1);
+#pragma unroll
+    for (int m = 0; m < RB; ++m) av[d][m] = frag_a<0>(a.adj_f32, steps_total, mbm[m], (int)(rho0 / 16) + s, lane);
+    call_operand<NB>(row, rho0 + 16 * s, a.g.R, grp, bv[d]);
+  };
+  Tile<0>::Acc acc[RB][NB];
+#pragma unroll
+  for (int m = 0; m < RB; ++m)
+#pragma unroll
+    for (int c = 0; c < NB; ++c) acc[m][c] = Tile<0>::zero();
+  auto compute = [&](int d) {
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      const Tile<0>::B b = Tile<0>::make_b(bv[d][c]);
+#pragma unroll
+      for (int m = 0; m < RB; ++m) Tile<0>::mma(acc[m][c], av[d][m], b);
+    }
+  };
+#pragma unroll
+  for (int d = 0; d < FD; ++d) load(d, d);
+  int s0 = 0;
+  for (; s0 + FD <= steps; s0 += FD) {
+#pragma unroll
+    for (int d = 0; d < FD; ++d) {
+      compute(d);
+      load(d, s0 + d + FD);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+#pragma unroll
+  for (int d = 0; d + 1 < FD; ++d)
+    if (s0 + d < steps) compute(d);
+  const int Jp = 16 * ((a.J + 15) / 16);
+  float2* part = a.part + (int64_t)ch * a.g.Kp * Jp;
+#pragma unroll
+  for (int m = 0; m < RB; ++m)
+    if (mb0 + m < mbl)
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        f32x4 cr, ci;
+        Tile<0>::finish(acc[m][c], cr, ci);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          part[(int64_t)(16 * (mb0 + m) + 4 * grp + r) * Jp + 16 * c + (lane & 15)] = make_float2(cr[r], ci[r]);
       }
 }
 
@@ -400,6 +566,17 @@ hipError_t core_split_launch(const float2* core, const CoreGeom& g, uint16_t* ds
   return hipGetLastError();
 }
 
+hipError_t core_frag32_launch(const float2* core, const CoreGeom& g, float2* dst, hipStream_t st) {
+  float4* p = reinterpret_cast<float4*>(dst);
+  hipLaunchKernelGGL(core_frag32_kernel, dim3(4096), dim3(256), 0, st, core, g.R, g.K, 0, (g.R + 15) / 16,
+                     (int64_t)g.Kp / 16, p);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(core_frag32_kernel, dim3(4096), dim3(256), 0, st, core, g.R, g.K, 1, (int64_t)g.Kp / 16,
+                     g.Rp / 16, p + g.fwd32_elems() / 2);
+  return hipGetLastError();
+}
+
 hipError_t core_fwd_launch(const CoreArgs& a, int precision, hipStream_t st) {
   const dim3 block(NT);
   auto grid = [&](int rb) { return dim3((unsigned)((a.g.R + 64 * rb - 1) / (64 * rb))); };
@@ -410,6 +587,14 @@ hipError_t core_fwd_launch(const CoreArgs& a, int precision, hipStream_t st) {
       case 2: hipLaunchKernelGGL((core_fwd_bf16_kernel<2, F>), grid(F), block, 0, st, a); break;
       case 3: hipLaunchKernelGGL((core_fwd_bf16_kernel<3, M>), grid(M), block, 0, st, a); break;
       default: hipLaunchKernelGGL((core_fwd_bf16_kernel<4, M>), grid(M), block, 0, st, a); break;
+    }
+  } else if (a.fwd_f32) {
+    constexpr int F = FWD_RB_FEW, M = FWD_RB_MANY;
+    switch ((a.J + 15) / 16) {
+      case 1: hipLaunchKernelGGL((core_fwd_f32f_kernel<1, F>), grid(F), block, 0, st, a); break;
+      case 2: hipLaunchKernelGGL((core_fwd_f32f_kernel<2, F>), grid(F), block, 0, st, a); break;
+      case 3: hipLaunchKernelGGL((core_fwd_f32f_kernel<3, M>), grid(M), block, 0, st, a); break;
+      default: hipLaunchKernelGGL((core_fwd_f32f_kernel<4, M>), grid(M), block, 0, st, a); break;
     }
   } else {
     hipLaunchKernelGGL(core_fwd_f32_kernel, grid(RB), block, 0, st, a);
@@ -431,6 +616,16 @@ hipError_t core_adj_launch(const CoreArgs& a, int precision, float alpha, const 
       case 2: hipLaunchKernelGGL((core_adj_bf16_kernel<2, F>), grid, block, 0, st, a, nch, kg); break;
       case 3: hipLaunchKernelGGL((core_adj_bf16_kernel<3, M>), grid, block, 0, st, a, nch, kg); break;
       default: hipLaunchKernelGGL((core_adj_bf16_kernel<4, M>), grid, block, 0, st, a, nch, kg); break;
+    }
+  } else if (a.adj_f32) {
+    const int rb = nb <= 2 ? ADJ_RB_FEW : ADJ_RB_MANY, kg = kgroups(rb);
+    const dim3 grid((unsigned)(8 * kg * ((nch + 7) / 8)));
+    constexpr int F = ADJ_RB_FEW, M = ADJ_RB_MANY;
+    switch (nb) {
+      case 1: hipLaunchKernelGGL((core_adj_f32f_kernel<1, F, 2>), grid, block, 0, st, a, nch, kg); break;
+      case 2: hipLaunchKernelGGL((core_adj_f32f_kernel<2, F, 2>), grid, block, 0, st, a, nch, kg); break;
+      case 3: hipLaunchKernelGGL((core_adj_f32f_kernel<3, M, 2>), grid, block, 0, st, a, nch, kg); break;
+      default: hipLaunchKernelGGL((core_adj_f32f_kernel<4, M, 2>), grid, block, 0, st, a, nch, kg); break;
     }
   } else {
     hipLaunchKernelGGL(core_adj_f32_kernel, dim3((unsigned)nch, (unsigned)kgroups(RB)), block, 0, st, a);

@@ -54,6 +54,7 @@ struct Plan {
   bool core_direct = false;
   CoreGeom cg{};
   uint16_t* d_core_split = nullptr;  // BF16-split core planes (BF16_SPLIT plans only)
+  float2* d_core_f32 = nullptr;      // FP32 core copies in fragment order (FP32 plans only)
   int G_fwd = 2, G_adj = 8;    // coils per plane workgroup (set at plan creation)
   int split_apply = 0, split_adj = 0;  // dense basis GEMMs: split-K factors tuned at plan creation
   float gscale = 1.0f;         // prod_d (-1)^(n_d/2) / sqrt(N)

@@ -549,6 +549,11 @@ maxwell_status plan_build(Plan& p, const maxwell_plan_desc& d, const maxwell_bas
       if ((e = hipMalloc(&p.d_core_split, p.cg.total_elems() * sizeof(uint16_t))) != hipSuccess) return hip_err(e);
       if ((e = core_split_launch(p.core, p.cg, p.d_core_split, 0)) != hipSuccess) return hip_err(e);
       if ((e = hipStreamSynchronize(0)) != hipSuccess) return hip_err(e);
+    } else {
+      const size_t n32 = p.cg.fwd32_elems() + p.cg.adj32_elems();
+      if ((e = hipMalloc(&p.d_core_f32, n32 * sizeof(float2))) != hipSuccess) return hip_err(e);
+      if ((e = core_frag32_launch(p.core, p.cg, p.d_core_f32, 0)) != hipSuccess) return hip_err(e);
+      if ((e = hipStreamSynchronize(0)) != hipSuccess) return hip_err(e);
     }
   }
   if (p.sampling == MAXWELL_NONCARTESIAN) {
@@ -727,6 +732,8 @@ void plan_release(Plan& p) {
   p.d_frag = nullptr;
   if (p.d_core_split) (void)hipFree(p.d_core_split);
   p.d_core_split = nullptr;
+  if (p.d_core_f32) (void)hipFree(p.d_core_f32);
+  p.d_core_f32 = nullptr;
   p.d_mask = nullptr;
   p.d_inv = nullptr;
   p.d_lptr = nullptr;
@@ -745,6 +752,10 @@ static CoreArgs core_args(const Plan& p, const float2* in, float2* out, void* ws
     a.fwd_lo = p.d_core_split + nf;
     a.adj_hi = p.d_core_split + 2 * nf;
     a.adj_lo = p.d_core_split + 2 * nf + na;
+  }
+  if (p.d_core_f32) {
+    a.fwd_f32 = p.d_core_f32;
+    a.adj_f32 = p.d_core_f32 + p.cg.fwd32_elems();
   }
   a.in = in;
   a.out = out;
