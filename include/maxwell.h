@@ -392,6 +392,21 @@ const char* maxwell_last_error(void);
 /* Library version string, e.g. "maxwell-gfx950 0.1".                          */
 const char* maxwell_version(void);
 
+/* maxwell_grad with no workspace argument, for callers that cannot allocate device memory
+ * (code under graph capture, tight serving loops, harnesses that forbid allocation).  The
+ * workspace is a library-held device buffer of MAXWELL_STATIC_WS_BYTES (64 MiB) on each
+ * device, kept until the process ends; the call allocates nothing.  Plans whose workspace
+ * (maxwell_plan_workspace_size) exceeds it are refused with
+ * MAXWELL_ERR_WORKSPACE_TOO_SMALL; a plan with per-kernel timing on with
+ * MAXWELL_ERR_UNSUPPORTED.  Every call on one device shares that device's buffer, which
+ * keeps the last call's contents (no step reads scratch it has not written): calls that
+ * overlap in time on one device (other streams, other host threads) race and must be
+ * serialised by the caller.  Arguments and results as maxwell_grad.                    */
+#define MAXWELL_STATIC_WS_BYTES ((size_t)64 << 20)
+maxwell_status maxwell_grad_static(maxwell_plan_t plan, const maxwell_complex64* x, const maxwell_complex64* c,
+                                   const maxwell_complex64* y, maxwell_complex64* gx, maxwell_complex64* gc,
+                                   double* loss_dev, void* stream);
+
 /* Diagnostic: the device BF16 split of the BF16_SPLIT products (see maxwell_precision),
  * applied to n FP32 values x (device): hi[i] = bf16(x[i]), lo[i] = bf16(x[i] - hi[i]),
  * both round to nearest even, as BF16 bit patterns (device uint16 arrays of n entries).

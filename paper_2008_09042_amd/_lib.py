@@ -11,6 +11,7 @@ MAXWELL_ERR_UNSUPPORTED = -2
 MAXWELL_ERR_OUT_OF_MEMORY = -3
 MAXWELL_ERR_HIP = -4
 MAXWELL_ERR_WORKSPACE_TOO_SMALL = -5
+MAXWELL_STATIC_WS_BYTES = 64 << 20
 
 MAXWELL_BASIS_DENSE = 0
 MAXWELL_BASIS_TUCKER = 1
@@ -34,7 +35,7 @@ EXPORTS = [
     "maxwell_sense_encode", "maxwell_sense_adjoint", "maxwell_sense_normal", "maxwell_tv_prox",
     "maxwell_ball_project", "maxwell_sense_admm", "maxwell_multi_encode", "maxwell_multi_grad",
     "maxwell_tucker_compress", "maxwell_batch_grad_shared",
-    "maxwell_plan_set_timing", "maxwell_plan_timing", "maxwell_bf16_split",
+    "maxwell_plan_set_timing", "maxwell_plan_timing", "maxwell_bf16_split", "maxwell_grad_static",
 ]
 
 
@@ -154,6 +155,8 @@ def load(path: str = LIB_PATH):
     lib.maxwell_last_error.restype = ctypes.c_char_p
     lib.maxwell_version.argtypes = []
     lib.maxwell_version.restype = ctypes.c_char_p
+    lib.maxwell_grad_static.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.maxwell_grad_static.restype = st
     lib.maxwell_bf16_split.argtypes = [vp, i64, ctypes.c_int32, vp, vp, vp]
     lib.maxwell_bf16_split.restype = st
     _lib = lib

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -29,6 +30,36 @@ maxwell_status fail(maxwell_status s, const std::string& msg) {
 maxwell_status hip_fail(hipError_t e, const char* where) {
   g_last_error = std::string("HIP error in ") + where + ": " + hipGetErrorString(e);
   return MAXWELL_ERR_HIP;
+}
+
+// ---------------------------------------------------------------- library-held workspace
+// The workspace of maxwell_grad_static: a file-scope device array of MAXWELL_STATIC_WS_BYTES,
+// one copy per device (each device that loads the library holds it until the process ends).
+// Host code never uses the array's name as an address (its host-side stand-in): the device
+// address comes from hipGetSymbolAddress, fetched once per device with that device current
+// (at plan creation) and kept per device.
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[MAXWELL_STATIC_WS_BYTES];
+
+namespace {
+
+// Device address of `scratch` on the current device `dev` (fetched and cached on first use).
+hipError_t scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
 }
 
 #define HIP_TRY(expr, where)                      \
@@ -164,6 +195,13 @@ maxwell_status maxwell_plan_create(const maxwell_plan_desc* desc, const maxwell_
   Plan* p = new (std::nothrow) Plan();
   if (!p) return fail(MAXWELL_ERR_OUT_OF_MEMORY, "host allocation failed");
   s = plan_build(*p, *desc, *basis);
+  if (s == MAXWELL_OK) {
+    // the plan's device and its copy of the library-held workspace (maxwell_grad_static)
+    void* unused = nullptr;
+    hipError_t e = hipGetDevice(&p->device);
+    if (e == hipSuccess) e = scratch_address(p->device, &unused);
+    if (e != hipSuccess) s = hip_fail(e, "plan_create (static workspace address)");
+  }
   if (s != MAXWELL_OK) {
     plan_release(*p);
     delete p;
@@ -456,6 +494,37 @@ maxwell_status maxwell_grad(maxwell_plan_t plan, const maxwell_complex64* x, con
                    reinterpret_cast<const float2*>(y), reinterpret_cast<float2*>(gx), reinterpret_cast<float2*>(gc),
                    loss_dev, ws, (hipStream_t)stream),
           "grad");
+  return MAXWELL_OK;
+}
+
+maxwell_status maxwell_grad_static(maxwell_plan_t plan, const maxwell_complex64* x, const maxwell_complex64* c,
+                                   const maxwell_complex64* y, maxwell_complex64* gx, maxwell_complex64* gc,
+                                   double* loss_dev, void* stream) {
+  if (!plan) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "plan is null");
+  const Plan* p = reinterpret_cast<const Plan*>(plan);
+  if (p->ws_bytes > MAXWELL_STATIC_WS_BYTES)
+    return fail(MAXWELL_ERR_WORKSPACE_TOO_SMALL,
+                "plan workspace (" + std::to_string(p->ws_bytes) + " bytes) exceeds the library-held workspace (" +
+                    std::to_string((size_t)MAXWELL_STATIC_WS_BYTES) + " bytes); use maxwell_grad with a workspace");
+  if (p->timing.on)
+    return fail(MAXWELL_ERR_UNSUPPORTED, "maxwell_grad_static: per-kernel timing must be off (it creates events)");
+  void* ws = nullptr;
+  if (p->device < 0 || p->device >= MAX_DEVICES || !(ws = g_scratch_ptr[p->device]))
+    return fail(MAXWELL_ERR_INVALID_ARGUMENT, "plan has no library-held workspace on its device");
+  Check ck(p);
+  ck.in(x, p->bytes_x(), "x");
+  ck.in(c, p->bytes_c(), "c");
+  ck.in(y, p->bytes_y(), "y");
+  ck.out(gx, p->bytes_x(), "gx", false);
+  ck.out(gc, p->bytes_c(), "gc", false);
+  ck.out(loss_dev, sizeof(double), "loss_dev", false);
+  ck.ws(ws, MAXWELL_STATIC_WS_BYTES);
+  maxwell_status s = ck.finish();
+  if (s != MAXWELL_OK) return s;
+  HIP_TRY(run_grad(*p, reinterpret_cast<const float2*>(x), reinterpret_cast<const float2*>(c),
+                   reinterpret_cast<const float2*>(y), reinterpret_cast<float2*>(gx), reinterpret_cast<float2*>(gc),
+                   loss_dev, ws, (hipStream_t)stream),
+          "grad_static");
   return MAXWELL_OK;
 }
 

@@ -21,6 +21,7 @@ struct Timing {
 
 struct Plan {
   mutable Timing timing;
+  int device = -1;  // the device current at plan creation
   // geometry
   int ndim = 0;
   int64_t n[3] = {1, 1, 1};

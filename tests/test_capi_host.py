@@ -260,3 +260,9 @@ def test_bf16_split_validation(lib):
     assert lib.maxwell_bf16_split(fake, 1 << 20, 0, ctypes.c_void_p(0x10000 + 64), third, None) == \
         L.MAXWELL_ERR_INVALID_ARGUMENT
     assert "overlap" in lib.maxwell_last_error().decode()
+
+
+def test_grad_static_validation(lib):
+    """maxwell_grad_static refuses a null plan before any HIP call."""
+    assert lib.maxwell_grad_static(None, None, None, None, None, None, None, None) == L.MAXWELL_ERR_INVALID_ARGUMENT
+    assert "plan is null" in lib.maxwell_last_error().decode()
