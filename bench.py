@@ -280,36 +280,39 @@ def bench_batch(args, torch):
         cs.append(T(p.c0))
         ys.append(T(p.noise))
     torch.cuda.synchronize()
-    log(f"[bench] plans ready in {time.time() - t0:.1f}s (dense-basis GEMM splits tuned per shape)")
-    batch = MaxwellBatch(plans, branches=args.branches)
+    from paper_2008_09042_amd.encoding import tune_counts
+    tuned = tune_counts()
+    log(f"[bench] plans ready in {time.time() - t0:.1f}s (dense products: {tuned[0]} shapes timed, "
+        f"{tuned[1]} reused from the tuning cache)")
+    batch = MaxwellBatch(plans, branches=args.branches, staged=True, stamps=True)
     coils = sum(p.J for p in ps)
     basis_bytes = sum(8 * p.N * p.K for p in ps)
     eager_ms, _ = time_steps(lambda: batch.grad(xs, cs, ys), args.steps, args.warmup, torch)
     batch.capture(xs, cs, ys)
     ms, wall = time_steps(batch.replay, args.steps, args.warmup, torch)
     log(f"[bench] batch: {ms:.3f} ms/step graph ({coils * 1000.0 / ms:.0f} coil-images/s), eager {eager_ms:.3f} ms")
+    # per-slice latency inside the captured replay: each slice's device timestamps (start of its
+    # first step, end of its last), written by the graph itself; median over replays
+    lat_runs = []
+    for _ in range(5):
+        batch.replay()
+        torch.cuda.synchronize()
+        lat_runs.append(batch.latencies_ms())
+    lat = np.median(np.array(lat_runs), axis=0)
+    # the same batch with each slice's whole chain on a branch (no phases), for comparison
+    cb = MaxwellBatch(plans, branches=args.branches, staged=False)
+    cb.capture(xs, cs, ys)
+    chain_ms, _ = time_steps(cb.replay, args.steps, args.warmup, torch)
+    log(f"[bench] batch, whole chains per branch: {chain_ms:.3f} ms/step graph")
+    del cb
     compare = None
     if other_plans:
-        ob = MaxwellBatch(other_plans, branches=args.branches)
+        ob = MaxwellBatch(other_plans, branches=args.branches, staged=True)
         ob.capture(xs, cs, ys)
         oms, _ = time_steps(ob.replay, args.steps, args.warmup, torch)
         compare = {"precision": other, "ms_per_step": oms, "value": coils * 1000.0 / oms}
         log(f"[bench] batch {other}: {oms:.3f} ms/step graph ({coils * 1000.0 / oms:.0f} coil-images/s)")
         del ob
-    # per-slice latency: each slice's gradient alone (device events), median of 5
-    lat = []
-    st = torch.cuda.current_stream()
-    for pl, x, c, y in zip(plans, xs, cs, ys):
-        runs = []
-        for _ in range(6):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(st)
-            pl.grad(x, c, y)
-            e1.record(st)
-            torch.cuda.synchronize()
-            runs.append(e0.elapsed_time(e1))
-        lat.append(float(np.median(runs[1:])))
-    lat = np.array(lat)
     out = {
         "metric": METRIC,
         "value": coils * 1000.0 / ms,
@@ -328,12 +331,16 @@ def bench_batch(args, torch):
                    "basis_gb": round(basis_bytes / 1e9, 2), "branches": args.branches,
                    "cartesian_slices": sum(p.sampling == "cartesian" for p in ps),
                    "step": "one graph replay: loss + gradient of every slice (maxwell_grad per slice: "
-                           "B c once, kept for the adjoint; B^H once)"},
+                           "B c once, kept for the adjoint; B^H once), the slices' steps issued in phases "
+                           "with each phase's FFT passes of all slices launched together"},
         "eager_ms_per_step": eager_ms,
+        "chains_per_branch_ms_per_step": chain_ms,
+        "plan_tuning": {"timed": tuned[0], "reused_from_cache": tuned[1]},
         "other_precision": compare,
         "basis_stream_gbs": 2.0 * basis_bytes / (ms * 1e-3) / 1e9,
-        "slice_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                             "min": float(lat.min()), "max": float(lat.max()), "sum": float(lat.sum())},
+        "slice_latency_ms": {"source": "device timestamps inside the captured replay (median of 5 replays)",
+                             "p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                             "min": float(lat.min()), "max": float(lat.max())},
     }
     print(json.dumps(out), flush=True)
 

@@ -345,7 +345,20 @@ maxwell_status maxwell_sense_admm(maxwell_plan_t plan, const maxwell_complex64* 
  *   validated as in maxwell_grad before anything is enqueued (errors name the slice).  The
  *   branches are forked from `stream` by an event and joined back into it, so the whole call
  *   can be captured into one hipGraph and replayed as a single launch.  Slices must not share
- *   output buffers; calls on one batch must not overlap in time.
+ *   output buffers; calls on one batch must not overlap in time.  By default the slices'
+ *   steps are issued in phases: a slice's steps form blocks (each FFT pass one block, each
+ *   run of other steps one block), and each branch takes its slices through the phases on
+ *   its stream, phase r being the r-th block of each of its slices; a phase's FFT passes of
+ *   the branch's slices go out together, up to 16 slices' passes per launch (descriptors in
+ *   the kernel arguments), its other blocks run in turn;
+ *   each slice's result is the same, bit for bit, as its own maxwell_grad.  Plans in a batch
+ *   must have per-kernel timing off (else MAXWELL_ERR_UNSUPPORTED).
+ * maxwell_batch_set_options: staged = 1 (default) issues the slices' steps in phases as
+ *   above; 0 runs each slice's whole chain of launches on its branch.  stamps_dev: a device
+ *   array of 2n uint64 (8-byte aligned) or NULL; when set, every later maxwell_batch_grad
+ *   (also under capture) writes slice i's device wall-clock at the start of its first step
+ *   to stamps_dev[2i] and at the end of its last to stamps_dev[2i + 1], the slice's latency
+ *   inside the batch.  ticks_per_second (host, may be NULL) receives the clock's rate.
  * maxwell_batch_destroy: releases the streams and events (not the plans).                  */
 maxwell_status maxwell_batch_create(const maxwell_plan_t* plans, int32_t n, int32_t branches,
                                     maxwell_batch_t* out);
@@ -355,6 +368,8 @@ maxwell_status maxwell_batch_grad(maxwell_batch_t batch, const maxwell_complex64
                                   const maxwell_complex64* const* y, maxwell_complex64* const* gx,
                                   maxwell_complex64* const* gc, double* const* loss_dev, void* ws,
                                   size_t ws_bytes, void* stream);
+maxwell_status maxwell_batch_set_options(maxwell_batch_t batch, int32_t staged, uint64_t* stamps_dev,
+                                         double* ticks_per_second);
 void maxwell_batch_destroy(maxwell_batch_t batch);
 
 /* Frames with shared coefficients (dynamic or multi-contrast data, the remark after the
@@ -391,6 +406,15 @@ const char* maxwell_last_error(void);
 
 /* Library version string, e.g. "maxwell-gfx950 0.1".                          */
 const char* maxwell_version(void);
+
+/* Plan-time kernel choices: for a dense basis, plan creation times the streaming kernel
+ * (few coils) against the tiled GEMM at each split-K factor for both basis products and
+ * keeps the fastest, per (GPU architecture, product, N, K, J, precision).  The choices are
+ * kept for the process and in a tuning file, $MAXWELL_TUNE_CACHE if set (empty: none), else
+ * $HOME/.cache/maxwell/tune.txt, so a later process reuses them without timing.
+ * MAXWELL_GEMM_AUTOTUNE=0 skips the timing (a fixed rule).  maxwell_tune_counts: the
+ * choices timed and the choices reused since the process started (either may be NULL).  */
+maxwell_status maxwell_tune_counts(int64_t* measured, int64_t* reused);
 
 /* maxwell_grad with no workspace argument, for callers that cannot allocate device memory
  * (code under graph capture, tight serving loops, harnesses that forbid allocation).  The

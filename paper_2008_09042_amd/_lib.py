@@ -36,6 +36,7 @@ EXPORTS = [
     "maxwell_ball_project", "maxwell_sense_admm", "maxwell_multi_encode", "maxwell_multi_grad",
     "maxwell_tucker_compress", "maxwell_batch_grad_shared",
     "maxwell_plan_set_timing", "maxwell_plan_timing", "maxwell_bf16_split", "maxwell_grad_static",
+    "maxwell_batch_set_options", "maxwell_tune_counts",
 ]
 
 
@@ -117,6 +118,10 @@ def load(path: str = LIB_PATH):
     lib.maxwell_batch_grad.restype = st
     lib.maxwell_batch_grad_shared.argtypes = [vp, pa, vp, pa, pa, vp, vp, vp, sz, vp]
     lib.maxwell_batch_grad_shared.restype = st
+    lib.maxwell_tune_counts.argtypes = [ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.maxwell_tune_counts.restype = st
+    lib.maxwell_batch_set_options.argtypes = [vp, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_double)]
+    lib.maxwell_batch_set_options.restype = st
     lib.maxwell_batch_destroy.argtypes = [vp]
     lib.maxwell_batch_destroy.restype = None
     lib.maxwell_grad.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]

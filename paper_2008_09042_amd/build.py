@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD_DIR = os.path.join(CSRC, "_build")
 LIB = os.path.join(HERE, "libmaxwell.so")
 SOURCES = ["api.hip", "plan.hip", "gemm.hip", "fft.hip", "elementwise.hip", "nufft.hip", "tucker_fused.hip", "core_contract.hip",
-           "mode3.hip", "solver.hip", "admm.hip", "compress.hip", "skinny.hip", "diag.hip"]
+           "mode3.hip", "solver.hip", "admm.hip", "compress.hip", "skinny.hip", "diag.hip", "tune.hip"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are disabled for all device code.

@@ -15,6 +15,7 @@
 #include "plan.h"
 #include "compress.h"
 #include "solver.h"
+#include "tune.h"
 
 using namespace mx;
 
@@ -166,6 +167,14 @@ extern "C" {
 const char* maxwell_last_error(void) { return g_last_error.c_str(); }
 
 const char* maxwell_version(void) { return "maxwell-gfx950 0.1"; }
+
+maxwell_status maxwell_tune_counts(int64_t* measured, int64_t* reused) {
+  long long m = 0, r = 0;
+  tune_counts(&m, &r);
+  if (measured) *measured = m;
+  if (reused) *reused = r;
+  return MAXWELL_OK;
+}
 
 maxwell_status maxwell_bf16_split(const float* x, int64_t n, int32_t variant, uint16_t* hi, uint16_t* lo,
                                   void* stream) {
@@ -815,7 +824,62 @@ struct Batch {
   std::vector<hipEvent_t> join;
   hipEvent_t fork = nullptr;
   std::vector<std::vector<int>> branch;  // slice indices of each branch, in issue order
+  bool staged = true;                    // phases over the slices' steps (else whole chains per branch)
+  uint64_t* stamps = nullptr;            // device [2 n]: each slice's first and last step (or null)
 };
+
+// The slices' gradient steps (recorded launches) issued in phases, per branch.  A slice's
+// steps form blocks: each FFT pass is a block of its own, and each run of consecutive other
+// steps is one block (a segment).  Each branch takes its slices (given at creation, longest
+// first) through the phases on its own stream: in phase r the segments of its slices whose
+// r-th block is one run in turn, and the FFT passes of those whose r-th block is one are
+// launched together, several slices per launch.  Stream order keeps each slice's blocks in
+// order; the branches run side by side, forked from and joined back into the caller's
+// stream by events.
+hipError_t run_batch_phases(Batch& b, const std::vector<OpRecorder>& rec, hipStream_t st) {
+  const int n = (int)rec.size(), nb = (int)b.streams.size();
+  std::vector<std::vector<size_t>> blk(n);  // first op of each block, then a sentinel
+  auto is_fft = [](const Op& op) { return std::strcmp(op.name, "fft_axis") == 0; };
+  for (int i = 0; i < n; ++i) {
+    const auto& ops = rec[i].ops;
+    for (size_t k = 0; k < ops.size(); ++k)
+      if (k == 0 || is_fft(ops[k]) || is_fft(ops[k - 1])) blk[i].push_back(k);
+    blk[i].push_back(ops.size());
+  }
+  hipError_t e = hipEventRecord(b.fork, st);
+  if (e != hipSuccess) return e;
+  std::vector<FftLaunch> fft;
+  for (int q = 0; q < nb; ++q) {
+    hipStream_t bs = b.streams[q];
+    if ((e = hipStreamWaitEvent(bs, b.fork, 0)) != hipSuccess) return e;
+    size_t nphase = 0;
+    for (int i : b.branch[q]) nphase = std::max(nphase, blk[i].size() - 1);
+    for (size_t r = 0; r < nphase; ++r) {
+      fft.clear();
+      for (int i : b.branch[q]) {
+        if (r + 1 >= blk[i].size()) continue;
+        const auto& ops = rec[i].ops;
+        const size_t k0 = blk[i][r], k1 = blk[i][r + 1];
+        const bool first = k0 == 0, last = k1 == ops.size();
+        if (is_fft(ops[k0]) && !first && !last) {
+          fft_collect(&fft);
+          e = ops[k0].run(bs);
+          fft_collect(nullptr);
+          if (e != hipSuccess) return e;
+          continue;
+        }
+        if (first && b.stamps && (e = stamp_launch(b.stamps + 2 * i, bs)) != hipSuccess) return e;
+        for (size_t k = k0; k < k1; ++k)
+          if ((e = ops[k].run(bs)) != hipSuccess) return e;
+        if (last && b.stamps && (e = stamp_launch(b.stamps + 2 * i + 1, bs)) != hipSuccess) return e;
+      }
+      if (!fft.empty() && (e = fft_multi_launch(fft, bs)) != hipSuccess) return e;
+    }
+    if ((e = hipEventRecord(b.join[q], bs)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(st, b.join[q], 0)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
 
 double slice_work(const Plan& p) {
   const double N = (double)p.N, J = (double)p.J, K = (double)p.K, M = (double)p.M;
@@ -930,19 +994,57 @@ maxwell_status maxwell_batch_grad(maxwell_batch_t batch, const maxwell_complex64
     if (s != MAXWELL_OK) return fail(s, "slice " + std::to_string(i) + ": " + g_last_error);
   }
   hipStream_t st = (hipStream_t)stream;
+  if (b->staged) {
+    // record every slice's steps (nothing is enqueued), then issue them in rounds
+    std::vector<OpRecorder> rec(n);
+    for (int i = 0; i < n; ++i) {
+      const Plan* p = b->plans[i];
+      if (p->timing.on) return fail(MAXWELL_ERR_UNSUPPORTED, "batch_grad: per-kernel timing must be off on its plans");
+      set_recorder(&rec[i]);
+      const hipError_t e = run_grad(*p, reinterpret_cast<const float2*>(x[i]), reinterpret_cast<const float2*>(c[i]),
+                                    reinterpret_cast<const float2*>(y[i]), gx ? reinterpret_cast<float2*>(gx[i]) : nullptr,
+                                    gc ? reinterpret_cast<float2*>(gc[i]) : nullptr, loss_dev ? loss_dev[i] : nullptr,
+                                    static_cast<char*>(ws) + b->off[i], st);
+      set_recorder(nullptr);
+      if (e != hipSuccess) return hip_fail(e, "batch_grad (record)");
+    }
+    HIP_TRY(run_batch_phases(*b, rec, st), "batch_grad");
+    return MAXWELL_OK;
+  }
   HIP_TRY(hipEventRecord(b->fork, st), "batch_grad fork");
   for (size_t k = 0; k < b->streams.size(); ++k) {
     hipStream_t bs = b->streams[k];
     HIP_TRY(hipStreamWaitEvent(bs, b->fork, 0), "batch_grad fork");
-    for (int i : b->branch[k])
+    for (int i : b->branch[k]) {
+      if (b->stamps) HIP_TRY(stamp_launch(b->stamps + 2 * i, bs), "batch_grad stamp");
       HIP_TRY(run_grad(*b->plans[i], reinterpret_cast<const float2*>(x[i]), reinterpret_cast<const float2*>(c[i]),
                        reinterpret_cast<const float2*>(y[i]), gx ? reinterpret_cast<float2*>(gx[i]) : nullptr,
                        gc ? reinterpret_cast<float2*>(gc[i]) : nullptr, loss_dev ? loss_dev[i] : nullptr,
                        static_cast<char*>(ws) + b->off[i], bs),
               "batch_grad");
+      if (b->stamps) HIP_TRY(stamp_launch(b->stamps + 2 * i + 1, bs), "batch_grad stamp");
+    }
     HIP_TRY(hipEventRecord(b->join[k], bs), "batch_grad join");
     HIP_TRY(hipStreamWaitEvent(st, b->join[k], 0), "batch_grad join");
   }
+  return MAXWELL_OK;
+}
+
+maxwell_status maxwell_batch_set_options(maxwell_batch_t batch, int32_t staged, uint64_t* stamps_dev,
+                                         double* ticks_per_second) {
+  if (!batch) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "batch is null");
+  if (staged != 0 && staged != 1) return fail(MAXWELL_ERR_INVALID_ARGUMENT, "staged must be 0 or 1");
+  if (stamps_dev && (reinterpret_cast<uintptr_t>(stamps_dev) & 7u))
+    return fail(MAXWELL_ERR_INVALID_ARGUMENT, "stamps_dev must be 8-byte aligned");
+  Batch* b = reinterpret_cast<Batch*>(batch);
+  if (ticks_per_second) {
+    int dev = 0, khz = 0;
+    HIP_TRY(hipGetDevice(&dev), "batch_set_options");
+    HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev), "batch_set_options");
+    *ticks_per_second = 1e3 * (double)khz;
+  }
+  b->staged = staged != 0;
+  b->stamps = stamps_dev;
   return MAXWELL_OK;
 }
 

@@ -6,6 +6,8 @@
 #include <stdint.h>
 #include <stddef.h>
 
+#include <vector>
+
 namespace mx {
 
 // ---------------------------------------------------------------- complex helpers
@@ -40,7 +42,8 @@ struct GemmArgs {
 // be valid; ws must hold max_ws bytes).  The choice is cached per shape for the process; with
 // MAXWELL_GEMM_AUTOTUNE=0 in the environment the heuristic (0) is returned.  Synchronous: for
 // plan creation only.
-int gemm_autotune(const GemmArgs& g, int precision, void* ws, size_t max_ws, hipStream_t st);
+int gemm_autotune(const GemmArgs& g, int precision, void* ws, size_t max_ws, hipStream_t st,
+                  float* best_ms = nullptr);  // best_ms: the chosen split's time per launch
 // Bytes of workspace the GEMM needs for split-K partials for these sizes.
 size_t gemm_workspace_bytes(const GemmArgs& g);
 // Enqueue.  `ws` must hold gemm_workspace_bytes(g) bytes (may be null if 0).
@@ -80,6 +83,27 @@ struct FftAxisArgs {
   int lines;              // lines per workgroup (set by fft_axis_launch)
 };
 hipError_t fft_axis_launch(const FftAxisArgs& a, hipStream_t st);
+// A pass prepared for launch (lines per workgroup, magic numbers, kernel variant, grid, LDS).
+struct FftLaunch {
+  FftAxisArgs a;
+  int smp;
+  bool twl;
+  int64_t blocks;
+  size_t lds;
+};
+hipError_t fft_axis_prepare(const FftAxisArgs& a, FftLaunch& out);
+// Several passes per launch: descriptors in the kernel arguments.
+constexpr int FFT_MULTI = 16;
+struct FftMulti {
+  FftAxisArgs d[FFT_MULTI];
+  int start[FFT_MULTI + 1];
+  int n;
+};
+// While a sink is set on the calling thread (non-null), fft_axis_launch appends the prepared
+// pass to it instead of launching; fft_collect(nullptr) ends collection.
+void fft_collect(std::vector<FftLaunch>* sink);
+// Launches prepared passes of independent arrays, several per launch.
+hipError_t fft_multi_launch(const std::vector<FftLaunch>& ls, hipStream_t st);
 int fft_factorise(int64_t n, int* radix);  // returns number of passes, 0 if unsupported
 
 // ---------------------------------------------------------------- elementwise / sampling
@@ -96,6 +120,8 @@ hipError_t reduce_loss_launch(const double* part, int nblocks, double* loss, hip
 hipError_t adjoint_combine_launch(const float2* S, float2* g, const float2* x, int64_t N, int J,
                                   float alpha, const float* scale_dev, float2* gx, int want_h,
                                   hipStream_t st);
+// Writes the device's constant-rate wall clock (hipDeviceAttributeWallClockRate) to *dst.
+hipError_t stamp_launch(uint64_t* dst, hipStream_t st);
 hipError_t scale_copy_launch(const float2* src, float2* dst, int64_t count, float alpha,
                              const float* scale_dev, hipStream_t st);
 

@@ -142,4 +142,14 @@ hipError_t scale_copy_launch(const float2* src, float2* dst, int64_t count, floa
   return hipGetLastError();
 }
 
+// One device timestamp (the constant-rate wall clock) written by one lane.
+__global__ void stamp_kernel(uint64_t* __restrict__ dst) {
+  if (threadIdx.x == 0) *dst = wall_clock64();
+}
+
+hipError_t stamp_launch(uint64_t* dst, hipStream_t st) {
+  hipLaunchKernelGGL(stamp_kernel, dim3(1), dim3(64), 0, st, dst);
+  return hipGetLastError();
+}
+
 }  // namespace mx

@@ -15,6 +15,9 @@
 // holding its butterflies in registers between two barriers, so the tile is
 // transformed in place), and writes back.  Twiddles come from a table
 // exp(-2 pi i t / n) built on the host in FP64.
+#include <cstring>
+#include <vector>
+
 #include "fft_device.h"
 
 namespace mx {
@@ -30,9 +33,10 @@ constexpr int TW_LDS_MAX = 1024;    // twiddle tables up to this length are stag
 __host__ __device__ inline int tile_elems(int n, int T, bool contiguous) { return contiguous ? T * (n + 1) : T * n; }
 
 // TWL: the twiddle table is copied into LDS behind the tile.  SMP: 1 the input comes from
-// the samples through the inverse mask, 2 the output goes to them.
+// the samples through the inverse mask, 2 the output goes to them.  bid / nbl: this
+// workgroup's index among the nbl workgroups of the pass.
 template <bool TWL, int SMP>
-__global__ __launch_bounds__(NT) void fft_axis_kernel(FftAxisArgs a) {
+__device__ __forceinline__ void fft_axis_body(const FftAxisArgs& a, int64_t bid_in, int64_t nbl) {
   extern __shared__ float2 lds[];
   const int n = (int)a.n;
   const float2* tw = a.twiddle;
@@ -48,7 +52,7 @@ __global__ __launch_bounds__(NT) void fft_axis_kernel(FftAxisArgs a) {
     tg.T = a.lines;
     tg.LS = n + 1;
     tg.ES = 1;
-    o0 = (int64_t)blockIdx.x * tg.T;
+    o0 = bid_in * tg.T;
     t0 = 0;
     Tvalid = (int)((a.outer - o0) < tg.T ? (a.outer - o0) : tg.T);
   } else {
@@ -58,8 +62,8 @@ __global__ __launch_bounds__(NT) void fft_axis_kernel(FftAxisArgs a) {
     const int64_t chunks = (a.inner + tg.T - 1) / tg.T;
     // consecutive chunks (adjacent columns, which share cache lines) go to one XCD: the
     // hardware deals workgroups round-robin over the 8 XCDs, each with its own L2
-    int64_t bid = blockIdx.x;
-    if ((gridDim.x & 7) == 0) bid = (int64_t)(blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+    int64_t bid = bid_in;
+    if ((nbl & 7) == 0) bid = (bid_in & 7) * (nbl >> 3) + (bid_in >> 3);
     o0 = bid / chunks;
     t0 = (bid % chunks) * tg.T;
     Tvalid = (int)((a.inner - t0) < tg.T ? (a.inner - t0) : tg.T);
@@ -172,6 +176,22 @@ __global__ __launch_bounds__(NT) void fft_axis_kernel(FftAxisArgs a) {
   }
 }
 
+template <bool TWL, int SMP>
+__global__ __launch_bounds__(NT) void fft_axis_kernel(FftAxisArgs a) {
+  fft_axis_body<TWL, SMP>(a, blockIdx.x, gridDim.x);
+}
+
+// Several passes (of different slices) in one launch: descriptor i takes workgroups
+// [start[i], start[i + 1]).  The descriptors travel in the kernel arguments.
+template <bool TWL, int SMP>
+__global__ __launch_bounds__(NT) void fft_axis_multi_kernel(FftMulti m) {
+  int i = 0;
+  while (i + 1 < m.n && (int)blockIdx.x >= m.start[i + 1]) ++i;
+  fft_axis_body<TWL, SMP>(m.d[i], (int64_t)blockIdx.x - m.start[i], (int64_t)m.start[i + 1] - m.start[i]);
+}
+
+thread_local std::vector<FftLaunch>* g_fft_collect = nullptr;
+
 }  // namespace
 
 int fft_factorise(int64_t n, int* radix) {
@@ -195,7 +215,7 @@ int fft_factorise(int64_t n, int* radix) {
 // chip (about 1024), at most 64 lines or TILE elements per tile (small tiles keep
 // several workgroups resident per CU), and for strided lines at least 8 adjacent ones
 // (64-byte runs per load) where the tile allows.
-hipError_t fft_axis_launch(const FftAxisArgs& args, hipStream_t st) {
+hipError_t fft_axis_prepare(const FftAxisArgs& args, FftLaunch& out) {
   FftAxisArgs a = args;
   const int n = (int)a.n;
   const bool contiguous = a.inner == 1;
@@ -211,7 +231,6 @@ hipError_t fft_axis_launch(const FftAxisArgs& args, hipStream_t st) {
   if (T < 1) T = 1;
   a.lines = (int)T;
   const int64_t blocks = contiguous ? (a.outer + T - 1) / T : a.outer * ((a.inner + T - 1) / T);
-  if (blocks <= 0) return hipSuccess;
   const size_t lds = (size_t)(tile_elems(n, a.lines, contiguous) + (twl ? n : 0)) * sizeof(float2);
   int smp = a.in_inv ? 1 : a.out_inv ? 2 : 0;
   // the reading pass places whole lines' samples directly when every tile holds lines of
@@ -229,18 +248,84 @@ hipError_t fft_axis_launch(const FftAxisArgs& args, hipStream_t st) {
     a.coil_shift = l;
     a.coil_magic = (uint32_t)((((1ull << l) - d) << 32) / d + 1);
   }
-  const dim3 gr((unsigned)blocks), bl(NT);
-  switch (smp * 2 + (twl ? 1 : 0)) {
-    case 7: hipLaunchKernelGGL((fft_axis_kernel<true, 3>), gr, bl, lds, st, a); break;
-    case 6: hipLaunchKernelGGL((fft_axis_kernel<false, 3>), gr, bl, lds, st, a); break;
-    case 1: hipLaunchKernelGGL((fft_axis_kernel<true, 0>), gr, bl, lds, st, a); break;
-    case 0: hipLaunchKernelGGL((fft_axis_kernel<false, 0>), gr, bl, lds, st, a); break;
-    case 3: hipLaunchKernelGGL((fft_axis_kernel<true, 1>), gr, bl, lds, st, a); break;
-    case 2: hipLaunchKernelGGL((fft_axis_kernel<false, 1>), gr, bl, lds, st, a); break;
-    case 5: hipLaunchKernelGGL((fft_axis_kernel<true, 2>), gr, bl, lds, st, a); break;
-    default: hipLaunchKernelGGL((fft_axis_kernel<false, 2>), gr, bl, lds, st, a); break;
+  out.a = a;
+  out.smp = smp;
+  out.twl = twl;
+  out.blocks = blocks;
+  out.lds = lds;
+  return hipSuccess;
+}
+
+void fft_collect(std::vector<FftLaunch>* sink) { g_fft_collect = sink; }
+
+// Lines per workgroup: enough workgroups to spread a small transform over the whole
+// chip (about 1024), at most 64 lines or TILE elements per tile (small tiles keep
+// several workgroups resident per CU), and for strided lines at least 8 adjacent ones
+// (64-byte runs per load) where the tile allows.  With a collector set on the calling
+// thread (fft_collect) the prepared pass is appended to it instead of launched.
+hipError_t fft_axis_launch(const FftAxisArgs& args, hipStream_t st) {
+  FftLaunch l;
+  hipError_t e = fft_axis_prepare(args, l);
+  if (e != hipSuccess) return e;
+  if (l.blocks <= 0) return hipSuccess;
+  if (g_fft_collect) {
+    g_fft_collect->push_back(l);
+    return hipSuccess;
+  }
+  const dim3 gr((unsigned)l.blocks), bl(NT);
+  const FftAxisArgs& a = l.a;
+  switch (l.smp * 2 + (l.twl ? 1 : 0)) {
+    case 7: hipLaunchKernelGGL((fft_axis_kernel<true, 3>), gr, bl, l.lds, st, a); break;
+    case 6: hipLaunchKernelGGL((fft_axis_kernel<false, 3>), gr, bl, l.lds, st, a); break;
+    case 1: hipLaunchKernelGGL((fft_axis_kernel<true, 0>), gr, bl, l.lds, st, a); break;
+    case 0: hipLaunchKernelGGL((fft_axis_kernel<false, 0>), gr, bl, l.lds, st, a); break;
+    case 3: hipLaunchKernelGGL((fft_axis_kernel<true, 1>), gr, bl, l.lds, st, a); break;
+    case 2: hipLaunchKernelGGL((fft_axis_kernel<false, 1>), gr, bl, l.lds, st, a); break;
+    case 5: hipLaunchKernelGGL((fft_axis_kernel<true, 2>), gr, bl, l.lds, st, a); break;
+    default: hipLaunchKernelGGL((fft_axis_kernel<false, 2>), gr, bl, l.lds, st, a); break;
   }
   return hipGetLastError();
+}
+
+// Prepared passes of several slices, grouped by kernel variant, FFT_MULTI per launch.
+hipError_t fft_multi_launch(const std::vector<FftLaunch>& ls, hipStream_t st) {
+  for (int variant = 0; variant < 8; ++variant) {
+    FftMulti m;
+    std::memset(&m, 0, sizeof(m));
+    size_t lds = 0;
+    auto flush = [&]() -> hipError_t {
+      if (m.n == 0) return hipSuccess;
+      const dim3 gr((unsigned)m.start[m.n]), bl(NT);
+      switch (variant) {
+        case 7: hipLaunchKernelGGL((fft_axis_multi_kernel<true, 3>), gr, bl, lds, st, m); break;
+        case 6: hipLaunchKernelGGL((fft_axis_multi_kernel<false, 3>), gr, bl, lds, st, m); break;
+        case 1: hipLaunchKernelGGL((fft_axis_multi_kernel<true, 0>), gr, bl, lds, st, m); break;
+        case 0: hipLaunchKernelGGL((fft_axis_multi_kernel<false, 0>), gr, bl, lds, st, m); break;
+        case 3: hipLaunchKernelGGL((fft_axis_multi_kernel<true, 1>), gr, bl, lds, st, m); break;
+        case 2: hipLaunchKernelGGL((fft_axis_multi_kernel<false, 1>), gr, bl, lds, st, m); break;
+        case 5: hipLaunchKernelGGL((fft_axis_multi_kernel<true, 2>), gr, bl, lds, st, m); break;
+        default: hipLaunchKernelGGL((fft_axis_multi_kernel<false, 2>), gr, bl, lds, st, m); break;
+      }
+      hipError_t e = hipGetLastError();
+      std::memset(&m, 0, sizeof(m));
+      lds = 0;
+      return e;
+    };
+    for (const FftLaunch& l : ls) {
+      if (l.smp * 2 + (l.twl ? 1 : 0) != variant || l.blocks <= 0) continue;
+      if (m.n == FFT_MULTI || (int64_t)m.start[m.n] + l.blocks > 0x7fffffff) {
+        hipError_t e = flush();
+        if (e != hipSuccess) return e;
+      }
+      m.d[m.n] = l.a;
+      m.start[m.n + 1] = m.start[m.n] + (int)l.blocks;
+      ++m.n;
+      if (l.lds > lds) lds = l.lds;
+    }
+    hipError_t e = flush();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace mx

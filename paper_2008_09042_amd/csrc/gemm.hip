@@ -391,7 +391,7 @@ hipError_t gemm_launch(const GemmArgs& g, int precision, void* ws, hipStream_t s
   return hipGetLastError();
 }
 
-int gemm_autotune(const GemmArgs& g0, int precision, void* ws, size_t max_ws, hipStream_t st) {
+int gemm_autotune(const GemmArgs& g0, int precision, void* ws, size_t max_ws, hipStream_t st, float* best_ms_out) {
   const char* env = std::getenv("MAXWELL_GEMM_AUTOTUNE");
   if (env && env[0] == '0') return 0;
   if (g0.M <= 0 || g0.N <= 0 || g0.K <= 0 || g0.batch <= 0) return 0;
@@ -400,11 +400,14 @@ int gemm_autotune(const GemmArgs& g0, int precision, void* ws, size_t max_ws, hi
                                        g0.c_ms, g0.c_ns, g0.conjA, g0.conjB, g0.accumulate, precision,
                                        g0.alpha_dev != nullptr, 0};
   static std::mutex mu;
-  static std::map<std::array<int64_t, 16>, int> cache;
+  static std::map<std::array<int64_t, 16>, std::pair<int, float>> cache;
   {
     std::lock_guard<std::mutex> lk(mu);
     auto it = cache.find(key);
-    if (it != cache.end()) return it->second;
+    if (it != cache.end()) {
+      if (best_ms_out) *best_ms_out = it->second.second;
+      return it->second.first;
+    }
   }
   const int bk = precision == 1 ? BKS : BK32;
   const int64_t kblocks = (g0.K + bk - 1) / bk;
@@ -430,8 +433,10 @@ int gemm_autotune(const GemmArgs& g0, int precision, void* ws, size_t max_ws, hi
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipGetLastError();
+  best_ms /= 3.0f;  // per launch
+  if (best_ms_out) *best_ms_out = best_ms;
   std::lock_guard<std::mutex> lk(mu);
-  cache[key] = best;
+  cache[key] = {best, best_ms};
   return best;
 }
 

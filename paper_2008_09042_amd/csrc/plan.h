@@ -1,6 +1,7 @@
 // Plan object and the enqueue sequences behind the C ABI.
 #pragma once
 
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -58,6 +59,7 @@ struct Plan {
   float2* d_core_f32 = nullptr;      // FP32 core copies in fragment order (FP32 plans only)
   int G_fwd = 2, G_adj = 8;    // coils per plane workgroup (set at plan creation)
   int split_apply = 0, split_adj = 0;  // dense basis GEMMs: split-K factors tuned at plan creation
+  bool skinny_apply = false, skinny_adj = false;  // dense basis: streaming kernels chosen at plan creation
   float gscale = 1.0f;         // prod_d (-1)^(n_d/2) / sqrt(N)
   // non-Cartesian sampling (Kaiser-Bessel NUFFT, 2D)
   int g[2] = {0, 0};             // oversampled grid
@@ -93,6 +95,24 @@ struct Plan {
 
 // Records the thread-local message returned by maxwell_last_error().
 void set_last_error(const std::string& msg);
+
+// Launch recording for batched execution: while a recorder is set on the calling thread,
+// each launch step of the run_* calls (one TIMED expression: one kernel or one short fixed
+// sequence) is kept as an op, a closure that enqueues it on a given stream, instead of being
+// enqueued.  The closures hold copies of their arguments; the plan is referenced.
+struct Op {
+  const char* name;
+  std::function<hipError_t(hipStream_t)> run;
+};
+struct OpRecorder {
+  std::vector<Op> ops;
+  hipError_t add(const char* name, std::function<hipError_t(hipStream_t)> f) {
+    ops.push_back(Op{name, std::move(f)});
+    return hipSuccess;
+  }
+};
+void set_recorder(OpRecorder* r);  // nullptr: launch again
+OpRecorder* recorder();
 
 // Brackets one kernel launch with timing events when timing is on.
 struct Span {

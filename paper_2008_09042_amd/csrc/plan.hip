@@ -14,6 +14,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <sstream>
 #include <vector>
 
 #include "fused.h"
@@ -23,6 +24,7 @@
 #include "admm.h"
 #include "skinny.h"
 #include "plan.h"
+#include "tune.h"
 
 namespace mx {
 
@@ -50,7 +52,18 @@ Span::~Span() {
   if (ev >= 0) (void)hipEventRecord(p.timing.ev_stop[ev], st);
 }
 
-#define TIMED(name, expr) ([&]() { Span _span(p, name, st); return (expr); }())
+namespace {
+thread_local OpRecorder* g_rec = nullptr;
+}  // namespace
+
+void set_recorder(OpRecorder* r) { g_rec = r; }
+OpRecorder* recorder() { return g_rec; }
+
+// One launch step: enqueued on st (bracketed by timing events when timing is on), or, with a
+// recorder set, kept as an op that enqueues the same launch on the stream it is given.
+#define TIMED(name, expr)                                                                        \
+  (g_rec ? g_rec->add(name, [=, &p](hipStream_t st) -> hipError_t { return (expr); })         \
+         : [&]() { Span _span(p, name, st); return (expr); }())
 
 namespace {
 
@@ -590,28 +603,78 @@ maxwell_status plan_build(Plan& p, const maxwell_plan_desc& d, const maxwell_bas
       return hip_err(e);
   }
 
-  // dense basis: split-K factors of the two basis GEMMs picked by timing (gemm_autotune),
-  // on scratch operands of the plan's shapes; cached per shape for the process
+  // dense basis: for each of the two basis products, the streaming kernel (few coils) or the
+  // tiled GEMM at one split-K factor, picked by timing the candidates on scratch operands of
+  // the plan's shapes; the choices persist in the tuning cache (tune.h), keyed by the GPU
+  // architecture and the shape.  MAXWELL_GEMM_AUTOTUNE=0: the rule (streaming apply where
+  // supported, streaming adjoint up to 16 coils, no split) without timing.
   if (p.basis_kind == MAXWELL_BASIS_DENSE && !p.fused && p.J > 0 && p.K > 0 && p.N > 0) {
-    const size_t nbuf = (size_t)p.J * std::max<int64_t>(p.N, p.K) * 8;  // c, S, h and gc all fit
-    const size_t max_ws = (size_t)256 << 20;
-    void *bufA = nullptr, *bufC = nullptr, *bufW = nullptr;
-    bool ok = hipMalloc(&bufA, nbuf) == hipSuccess && hipMalloc(&bufC, nbuf) == hipSuccess &&
-              hipMalloc(&bufW, max_ws) == hipSuccess && hipMemset(bufA, 0, nbuf) == hipSuccess &&
-              hipMemset(bufC, 0, nbuf) == hipSuccess;
-    if (ok) {
-      p.split_apply = gemm_autotune(dense_apply_args(p, reinterpret_cast<const float2*>(bufA),
-                                                     reinterpret_cast<float2*>(bufC)),
-                                    p.precision, bufW, max_ws, 0);
-      p.split_adj = gemm_autotune(dense_adjoint_args(p, reinterpret_cast<const float2*>(bufA),
-                                                     reinterpret_cast<float2*>(bufC)),
-                                  p.precision, bufW, max_ws, 0);
+    const bool stream_ok = skinny_apply_supported(p.N, p.K, p.J) && (reinterpret_cast<uintptr_t>(p.dense) & 15u) == 0;
+    const char* env = std::getenv("MAXWELL_GEMM_AUTOTUNE");
+    if (env && env[0] == '0') {
+      p.skinny_apply = stream_ok;
+      p.skinny_adj = stream_ok && p.J <= 16;
+    } else {
+      const size_t nbuf = (size_t)p.J * std::max<int64_t>(p.N, p.K) * 8;  // c, S, h and gc all fit
+      const size_t max_ws = (size_t)256 << 20;
+      void *bufA = nullptr, *bufC = nullptr, *bufW = nullptr;
+      bool ok = hipMalloc(&bufA, nbuf) == hipSuccess && hipMalloc(&bufC, nbuf) == hipSuccess &&
+                hipMalloc(&bufW, max_ws) == hipSuccess && hipMemset(bufA, 0, nbuf) == hipSuccess &&
+                hipMemset(bufC, 0, nbuf) == hipSuccess;
+      if (ok) {
+        const float2* A = reinterpret_cast<const float2*>(bufA);
+        float2* C = reinterpret_cast<float2*>(bufC);
+        // time per launch of one candidate (a warm-up, then three launches)
+        auto time_ms = [&](const std::function<hipError_t()>& launch) -> float {
+          hipEvent_t e0, e1;
+          if (hipEventCreate(&e0) != hipSuccess) return -1.f;
+          if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return -1.f; }
+          bool good = launch() == hipSuccess && hipEventRecord(e0, 0) == hipSuccess;
+          for (int r = 0; good && r < 3; ++r) good = launch() == hipSuccess;
+          float ms = -1.f;
+          if (good && hipEventRecord(e1, 0) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+              hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
+            ms /= 3.f;
+          else
+            ms = -1.f;
+          (void)hipEventDestroy(e0);
+          (void)hipEventDestroy(e1);
+          (void)hipGetLastError();
+          return ms;
+        };
+        std::ostringstream shape;
+        shape << device_arch() << " N=" << p.N << " K=" << p.K << " J=" << p.J << " prec=" << p.precision
+              << " stream=" << (stream_ok ? 1 : 0);
+        const int ca = tuned_choice("dense_apply " + shape.str(), [&]() -> int {
+          float gemm_ms = -1.f;
+          const int split = gemm_autotune(dense_apply_args(p, A, C), p.precision, bufW, max_ws, 0, &gemm_ms);
+          if (!stream_ok || skinny_frag_bytes(p.K, p.J) > max_ws) return split;
+          const float sk = time_ms([&]() { return skinny_apply_launch(p.dense, p.N, p.K, A, p.J, p.precision, bufW, C, 0); });
+          return (sk > 0.f && (gemm_ms <= 0.f || sk < gemm_ms)) ? -1 : split;
+        });
+        const int cd = tuned_choice("dense_adjoint " + shape.str(), [&]() -> int {
+          float gemm_ms = -1.f;
+          const int split = gemm_autotune(dense_adjoint_args(p, A, C), p.precision, bufW, max_ws, 0, &gemm_ms);
+          if (!stream_ok || skinny_adjoint_bytes(p.N, p.K, p.J) > max_ws) return split;
+          const float sk = time_ms([&]() {
+            return skinny_adjoint_launch(p.dense, p.N, p.K, A, p.J, p.precision, 1.0f, nullptr, bufW, C, 0);
+          });
+          return (sk > 0.f && (gemm_ms <= 0.f || sk < gemm_ms)) ? -1 : split;
+        });
+        p.skinny_apply = ca < 0;
+        p.skinny_adj = cd < 0;
+        p.split_apply = ca < 0 ? 0 : ca;
+        p.split_adj = cd < 0 ? 0 : cd;
+      } else {
+        p.skinny_apply = stream_ok;
+        p.skinny_adj = stream_ok && p.J <= 16;
+      }
+      (void)hipStreamSynchronize(0);
+      if (bufA) (void)hipFree(bufA);
+      if (bufC) (void)hipFree(bufC);
+      if (bufW) (void)hipFree(bufW);
+      (void)hipGetLastError();
     }
-    (void)hipStreamSynchronize(0);
-    if (bufA) (void)hipFree(bufA);
-    if (bufC) (void)hipFree(bufC);
-    if (bufW) (void)hipFree(bufW);
-    (void)hipGetLastError();
   }
 
   // workspace layout
@@ -661,14 +724,13 @@ maxwell_status plan_build(Plan& p, const maxwell_plan_desc& d, const maxwell_bas
     p.off_cpart = off;
     off += al(core_adj_part_bytes(p.cg.R, p.cg.K, p.J));
   }
-  if (p.basis_kind == MAXWELL_BASIS_DENSE && skinny_apply_supported(p.N, p.K, p.J) &&
-      (reinterpret_cast<uintptr_t>(p.dense) & 15u) == 0) {
+  if (p.skinny_apply) {
     p.off_cfrag = off;
     off += al(skinny_frag_bytes(p.K, p.J));
-    if (p.J <= 16) {  // one coil block: the streaming adjoint beats the tiled GEMM (measured)
-      p.off_adjp = off;
-      off += al(skinny_adjoint_bytes(p.N, p.K, p.J));
-    }
+  }
+  if (p.skinny_adj) {
+    p.off_adjp = off;
+    off += al(skinny_adjoint_bytes(p.N, p.K, p.J));
   }
   p.off_E = off; off += al(JM);
   p.off_gemm = off; off += al(gemm_ws);

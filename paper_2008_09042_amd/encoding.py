@@ -393,10 +393,13 @@ class MaxwellBatch:
     grad(xs, cs, ys) runs maxwell_batch_grad eagerly.  capture(xs, cs, ys) records that
     call into one CUDA/HIP graph on fixed buffers (the tensors passed in, whose contents the
     caller may update in place, and outputs owned here); replay() launches the graph and
-    returns the same output tensors each time.  The slices run on `branches` concurrent
-    branches forked from the current stream."""
+    returns the same output tensors each time.  staged=True issues the slices' steps in
+    phases (each phase's FFT passes of all slices launched together); staged=False runs
+    each slice's whole chain on one of `branches` concurrent branches.  stamps=True makes
+    every call write each slice's device timestamps (first step start, last step end);
+    latencies_ms() reads them after the call (or replay) has completed."""
 
-    def __init__(self, plans, branches: int = 4):
+    def __init__(self, plans, branches: int = 4, staged: bool = True, stamps: bool = False):
         self.plans = list(plans)
         if not self.plans:
             raise ValueError("a batch needs at least one plan")
@@ -418,6 +421,19 @@ class MaxwellBatch:
         self._ws_raw = raw
         self.ws = raw[off:off + self.ws_bytes]
         self.graph = None
+        self.stamps = torch.zeros(2 * n, dtype=torch.int64, device=self.device) if stamps else None
+        rate = ctypes.c_double()
+        with torch.cuda.device(self.device):
+            L.check(self.lib.maxwell_batch_set_options(self.handle, int(bool(staged)),
+                                                       _ptr(self.stamps) if stamps else None, ctypes.byref(rate)))
+        self.ticks_per_second = float(rate.value)
+
+    def latencies_ms(self):
+        """Per-slice latency inside the last completed batch call (device timestamps), ms."""
+        if self.stamps is None:
+            raise RuntimeError("the batch was created without stamps")
+        t = self.stamps.cpu().numpy().reshape(-1, 2)
+        return (t[:, 1] - t[:, 0]).astype(np.float64) * 1e3 / self.ticks_per_second
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -503,6 +519,14 @@ class MaxwellBatch:
 def _like(g: Optional[torch.Tensor], t: torch.Tensor):
     """A gradient in the shape of its input (the input may be a flat view)."""
     return None if g is None else g.reshape(t.shape)
+
+
+def tune_counts():
+    """(choices timed, choices reused) by plan creation in this process (maxwell_tune_counts)."""
+    lib = L.load()
+    m, r = ctypes.c_int64(), ctypes.c_int64()
+    L.check(lib.maxwell_tune_counts(ctypes.byref(m), ctypes.byref(r)))
+    return int(m.value), int(r.value)
 
 
 def bf16_split(x: torch.Tensor, variant: int = 0):

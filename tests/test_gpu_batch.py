@@ -150,3 +150,36 @@ def test_frames_with_shared_coefficients():
     assert torch.equal(gc, s)
     assert float(loss.item()) == float(singles[0][0].item()) + float(singles[1][0].item()) + float(singles[2][0].item())
 
+
+
+@pytest.mark.parametrize("staged", [True, False])
+def test_batch_modes_and_device_stamps(staged):
+    """Both issue orders (rounds with the FFT passes of several slices per launch, and whole
+    chains per branch) give every slice's own maxwell_grad bit for bit; the device stamps of
+    each slice (first step start, last step end) are written by eager calls and by graph
+    replays."""
+    from paper_2008_09042_amd.encoding import MaxwellBatch
+    print(f"[case] batch staged={staged} with stamps", flush=True)
+    data = slices()
+    pl = plans("fp32")
+    batch = MaxwellBatch(pl, branches=2, staged=staged, stamps=True)
+    assert batch.ticks_per_second > 0
+    xs = [T(p.x0) for p, *_ in data]
+    cs = [T(p.c0) for p, *_ in data]
+    ys = [T(d[4]) for d in data]
+    loss, gx, gc = batch.grad(xs, cs, ys)
+    torch.cuda.synchronize()
+    lat = batch.latencies_ms()
+    assert np.all(np.isfinite(lat)) and np.all(lat > 0) and np.all(lat < 1e4), lat
+    for i, plan in enumerate(pl):
+        l1, gx1, gc1 = plan.grad(xs[i], cs[i], ys[i])
+        assert torch.equal(l1, loss[i]) and torch.equal(gx1, gx[i]) and torch.equal(gc1, gc[i]), i
+    out = batch.capture(xs, cs, ys)
+    batch.stamps.zero_()
+    torch.cuda.synchronize()
+    batch.replay()
+    torch.cuda.synchronize()
+    lat = batch.latencies_ms()
+    assert np.all(lat > 0), lat
+    for a, b in zip([loss] + gx + gc, [out[0]] + out[1] + out[2]):
+        assert torch.equal(a, b)
