@@ -45,7 +45,7 @@ constexpr int LDS_ELEMS = TW_OFF + 2 * PMAX;
 // the adjoint's Wb partials (8 waves x 9 tiles x 256) overwrite the plane and staging regions
 static_assert(NWAVE * 9 * 256 <= PLANE_ELEMS + STAGE_ELEMS, "Wb partials must fit");
 constexpr int FFT_CHUNK_FWD = PMAX * PMAX;       // elements per register chunk of a transform pass
-constexpr int FFT_CHUNK_ADJ = PMAX * PMAX / 2;   // (the adjoint holds P and gx across it)
+constexpr int FFT_CHUNK_ADJ = PMAX * PMAX / 2;   // (plane_adj_kernel holds P and gx across it)
 constexpr int SCAT = 4;                          // samples per thread loaded ahead of the scatter
 
 // ---------------------------------------------------------------- plane geometry
@@ -462,6 +462,31 @@ __global__ __launch_bounds__(PT) void plane_fwd_kernel(PlaneArgs a) {
   }
 }
 
+// The adjoint's coil map, formed after the transform one P tile at a time where gx uses
+// it (nothing of P is held across the transform): V = W U1^T for the wave's column block
+// (W staged), then per row block P = U0 V with U0's fragments read from memory three
+// steps ahead.
+template <int PREC, int N0, int N1, int RB>
+struct AdjMap {
+  typename Tile<PREC>::B vb[3];
+  typename Tile<PREC>::A ring[4];
+  int k;  // next (row block index, step) to load, 3 i + s over the wave's row blocks
+};
+
+template <int PREC, int N0, int N1, int RB>
+__device__ __forceinline__ void adj_map_load(const PlaneArgs& a, const Geo<N0, N1, RB>& g, const Share& sh, int lane,
+                                             AdjMap<PREC, N0, N1, RB>& m, int k) {
+  const int i = k / 3, s = k % 3, rb = sh.part + i * sh.q;
+  if (i < 8 && rb < g.n0b && s < g.r0b) m.ring[k & 3] = frag_a<PREC>(a.U0F, g.r0b, rb, s, lane);
+}
+
+// Adjoint plane kernel, two forms.  plane_adj_kernel (BF16-split plans) forms the coil map
+// before the transform, with U0 staged in the plane region, and holds P across it (the
+// transform then works in half-plane chunks).  plane_adj_late_kernel (FP32 plans) forms
+// each P tile after the transform where gx uses it, with U0 read from memory; its
+// transform holds whole passes.  Measured at 128 x 128 planes, the first is faster in
+// BF16-split (its matrix-core steps are short, so U0 read latency from memory shows) and
+// the second in FP32.
 template <int PREC, int N0, int N1, int RB>
 __global__ __launch_bounds__(PT) void plane_adj_kernel(PlaneArgs a) {
   __shared__ float2 lds[LDS_ELEMS];
@@ -561,6 +586,150 @@ __global__ __launch_bounds__(PT) void plane_adj_kernel(PlaneArgs a) {
               lds[i0 * g.PS + i1] = cmulc(xv[ii][r], gv);
             }
           }
+        }
+      }
+    }
+    __syncthreads();
+    if (a.T3b) adjoint_w<PREC>(a, g, j, i2, lds, lane, tid);
+  }
+  if (want_gx && sh.on) {
+    const int lane = threadIdx.x & 63, grp = lane >> 4;
+    float2* gxp = a.gxpart + ((size_t)gi * g.n2 + i2) * g.n0 * g.n1;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int rb = sh.part + i * sh.q;
+      if (rb < g.n0b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i0 = 16 * rb + 4 * grp + r, i1 = 16 * sh.cb + (lane & 15);
+          gxp[i0 * g.n1 + i1] = make_float2(gr[i][r], gim[i][r]);
+        }
+    }
+  }
+}
+
+template <int PREC, int N0, int N1, int RB>
+__global__ __launch_bounds__(PT) void plane_adj_late_kernel(PlaneArgs a) {
+  __shared__ float2 lds[LDS_ELEMS];
+  const Geo<N0, N1, RB> g(a);
+  const int ngrp = (a.J + a.G - 1) / a.G;
+  int i2, gi;
+  plane_block(ngrp, g.n2, i2, gi);
+  const float2* xp = a.xt + (size_t)i2 * g.n0 * g.n1;
+  const bool want_gx = a.gxpart != nullptr;
+  const Share sh = plane_share(g);
+  int zq[SCAT];  // sampled plane positions, the same for every coil
+#pragma unroll
+  for (int k = 0; k < SCAT; ++k) zq[k] = (int)threadIdx.x + k * PT < a.L ? a.pos[threadIdx.x + k * PT] : -1;
+  f32x4 gr[8], gim[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) { gr[i] = z4(); gim[i] = z4(); }
+  load_twiddles(a, g, lds);
+  for (int j = gi * a.G; j < a.J && j < (gi + 1) * a.G; ++j) {
+    int tid = threadIdx.x;  // opaque per coil, as in the forward kernel
+    asm volatile("" : "+v"(tid));
+    const int lane = tid & 63, grp = lane >> 4;
+    // this plane's samples (at most SCAT per thread) and W, loaded early
+    const float2* zi = a.Z + ((size_t)j * g.n2 + i2) * a.L;
+    float2 zv[SCAT];
+#pragma unroll
+    for (int k = 0; k < SCAT; ++k) {  // unconditional loads (L >= 1 on this path), as in w_load
+      const float2 v = zi[min(tid + k * PT, (int)a.L - 1)];
+      const float m = zq[k] >= 0 ? 1.f : 0.f;
+      zv[k] = make_float2(v.x * m, v.y * m);
+    }
+    if (want_gx) {
+      WPrefetch w;
+      w_load(a, g, j, i2, w_slots(g, tid), w);  // offsets recomputed: no registers held across coils
+      w_store<PREC>(g, lds, tid, w);              // the stage region is free (previous coil done)
+    }
+    // zero-filled scatter (with the chessboard sign)
+    for (int e = tid; e < g.n0 * g.PS; e += PT) lds[e] = make_float2(0.f, 0.f);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < SCAT; ++k)
+      if (zq[k] >= 0) {
+        const int k0 = zq[k] / g.n1, k1 = zq[k] - k0 * g.n1;
+        float2 v = zv[k];
+        if ((k0 + k1) & 1) v = make_float2(-v.x, -v.y);
+        lds[k0 * g.PS + k1] = v;
+      }
+    for (int l = tid + SCAT * PT; l < a.L; l += PT) {  // beyond the prefetched samples
+      const int q = a.pos[l];
+      const int k0 = q / g.n1, k1 = q - k0 * g.n1;
+      float2 v = zi[l];
+      if ((k0 + k1) & 1) v = make_float2(-v.x, -v.y);
+      lds[k0 * g.PS + k1] = v;
+    }
+    __syncthreads();
+    plane_fft<FFT_CHUNK_FWD>(a, g, lds, +1);  // nothing held across it but gx: whole passes
+    // g = s g' (g' the plane after the transform, s the output chessboard sign):
+    // gx += conj(P) s g' in registers; h = conj(x) s g' = conj(s x) g' into the plane, s x
+    // being what xt holds.  Each P tile is formed just before its use.
+    if (sh.on) {
+      AdjMap<PREC, N0, N1, RB> m;
+      if (want_gx) {
+        // V = W U1^T[:, cb], the U1^T fragment of the next step loaded during this one
+        typename Tile<PREC>::Acc cv[3];
+#pragma unroll
+        for (int mb = 0; mb < 3; ++mb) cv[mb] = Tile<PREC>::zero();
+        typename Tile<PREC>::B u1[2];
+        u1[0] = frag_b<PREC>(a.U1TF, g.n1b, sh.cb, 0, lane);
+#pragma unroll
+        for (int s = 0; s < 3; ++s)
+          if (s < g.r1b) {
+            if (s + 1 < g.r1b) u1[(s + 1) & 1] = frag_b<PREC>(a.U1TF, g.n1b, sh.cb, s + 1, lane);
+            if (s == 1)
+#pragma unroll
+              for (int k = 0; k < 3; ++k) adj_map_load(a, g, sh, lane, m, k);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int mb = 0; mb < 3; ++mb)
+              if (mb < g.r0b) Tile<PREC>::mma(cv[mb], frag_a<PREC>(lds + STAGE_OFF, g.r1b, mb, s, lane), u1[s & 1]);
+          }
+        if (g.r1b < 2)
+#pragma unroll
+          for (int k = 0; k < 3; ++k) adj_map_load(a, g, sh, lane, m, k);
+#pragma unroll
+        for (int mb = 0; mb < 3; ++mb) {
+          f32x4 cr, ci;
+          Tile<PREC>::finish(cv[mb], cr, ci);
+          m.vb[mb] = tile_as_b<PREC>(cr, ci);
+        }
+      }
+      const int i1 = 16 * sh.cb + (lane & 15);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int rb = sh.part + i * sh.q;
+        if (rb < g.n0b) {
+          float2 xv[4], gv[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            xv[r] = xp[(16 * rb + 4 * grp + r) * g.n1 + i1];
+            gv[r] = lds[(16 * rb + 4 * grp + r) * g.PS + i1];
+          }
+          if (want_gx) {
+            typename Tile<PREC>::Acc c = Tile<PREC>::zero();
+#pragma unroll
+            for (int s = 0; s < 3; ++s) {
+              adj_map_load(a, g, sh, lane, m, 3 * i + s + 3);
+              __builtin_amdgcn_sched_barrier(0);
+              if (s < g.r0b) Tile<PREC>::mma(c, m.ring[(3 * i + s) & 3], m.vb[s]);
+            }
+            f32x4 pr, pi;
+            Tile<PREC>::finish(c, pr, pi);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int i0 = 16 * rb + 4 * grp + r;
+              float2 cg = cmulc(make_float2(pr[r], pi[r]), gv[r]);
+              if ((i0 + i1) & 1) cg = make_float2(-cg.x, -cg.y);
+              gr[i][r] += cg.x;
+              gim[i][r] += cg.y;
+            }
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) lds[(16 * rb + 4 * grp + r) * g.PS + i1] = cmulc(xv[r], gv[r]);
+          __builtin_amdgcn_sched_barrier(0);
         }
       }
     }
@@ -771,6 +940,13 @@ __global__ void reduce_transpose_kernel(const float2* __restrict__ part, int ngr
   }
 }
 
+// The adjoint form by precision (see plane_adj_kernel).
+template <int PREC, int N0, int N1>
+void adj_launch(dim3 grid, dim3 block, const PlaneArgs& a, hipStream_t st) {
+  if constexpr (PREC == 0) hipLaunchKernelGGL((plane_adj_late_kernel<PREC, N0, N1, 0>), grid, block, 0, st, a);
+  else hipLaunchKernelGGL((plane_adj_kernel<PREC, N0, N1, 0>), grid, block, 0, st, a);
+}
+
 template <int PREC>
 hipError_t plane_launch_prec(const PlaneArgs& a, bool adj, hipStream_t st) {
   const int ngrp = (a.J + a.G - 1) / a.G;
@@ -780,13 +956,13 @@ hipError_t plane_launch_prec(const PlaneArgs& a, bool adj, hipStream_t st) {
   if (a.n0 == 128 && a.n1 == 128 && rb3 && !adj) {
     hipLaunchKernelGGL((plane_fwd_kernel<PREC, 128, 128, 3>), grid, block, 0, st, a);
   } else if (a.n0 == 128 && a.n1 == 128) {
-    if (adj) hipLaunchKernelGGL((plane_adj_kernel<PREC, 128, 128, 0>), grid, block, 0, st, a);
+    if (adj) adj_launch<PREC, 128, 128>(grid, block, a, st);
     else hipLaunchKernelGGL((plane_fwd_kernel<PREC, 128, 128, 0>), grid, block, 0, st, a);
   } else if (a.n0 == 64 && a.n1 == 64) {
-    if (adj) hipLaunchKernelGGL((plane_adj_kernel<PREC, 64, 64, 0>), grid, block, 0, st, a);
+    if (adj) adj_launch<PREC, 64, 64>(grid, block, a, st);
     else hipLaunchKernelGGL((plane_fwd_kernel<PREC, 64, 64, 0>), grid, block, 0, st, a);
   } else {
-    if (adj) hipLaunchKernelGGL((plane_adj_kernel<PREC, 0, 0, 0>), grid, block, 0, st, a);
+    if (adj) adj_launch<PREC, 0, 0>(grid, block, a, st);
     else hipLaunchKernelGGL((plane_fwd_kernel<PREC, 0, 0, 0>), grid, block, 0, st, a);
   }
   return hipGetLastError();
