@@ -45,7 +45,7 @@ constexpr int LDS_ELEMS = TW_OFF + 2 * PMAX;
 // the adjoint's Wb partials (8 waves x 9 tiles x 256) overwrite the plane and staging regions
 static_assert(NWAVE * 9 * 256 <= PLANE_ELEMS + STAGE_ELEMS, "Wb partials must fit");
 constexpr int FFT_CHUNK_FWD = PMAX * PMAX;       // elements per register chunk of a transform pass
-constexpr int FFT_CHUNK_ADJ = PMAX * PMAX / 2;   // (plane_adj_kernel holds P and gx across it)
+constexpr int FFT_CHUNK_ADJ = PMAX * PMAX / 2;   // run-time plane sizes in plane_adj_kernel (P and gx held)
 constexpr int SCAT = 4;                          // samples per thread loaded ahead of the scatter
 
 // ---------------------------------------------------------------- plane geometry
@@ -542,7 +542,8 @@ __global__ __launch_bounds__(PT) void plane_adj_kernel(PlaneArgs a) {
       lds[k0 * g.PS + k1] = v;
     }
     __syncthreads();
-    plane_fft<FFT_CHUNK_ADJ>(a, g, lds, +1);
+    // compile-time plane sizes: whole passes over wave-owned lines (fewer barriers)
+    plane_fft<(N0 != 0 ? FFT_CHUNK_FWD : FFT_CHUNK_ADJ)>(a, g, lds, +1);
     // g = s g' (g' the plane after the transform, s the output chessboard sign):
     // gx += conj(P) s g' in registers; h = conj(x) s g' = conj(s x) g' into the plane, s x
     // being what xt holds.  x in two batches of four tiles, each batch's loads issued
