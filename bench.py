@@ -41,13 +41,16 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", default="bf16_split", choices=["bf16_split", "fp32"])
-    ap.add_argument("--workload", default="cart3d", choices=["cart3d", "batch", "gn", "admm", "compress", "kernels2d"],
+    ap.add_argument("--workload", default="cart3d",
+                    choices=["cart3d", "batch", "gn", "admm", "compress", "kernels2d", "kernels2d_big"],
                     help="cart3d: the headline 128^3 Tucker workload; batch: 64 uneven 2D slices with "
                          "dense bases through one captured graph; gn: conjugate-gradient steps of the "
                          "Gauss-Newton normal equations on the 128^3 Tucker workload; admm: constrained "
                          "TV-SENSE reconstruction steps on the 2D 256^2 workload; compress: Tucker "
                          "compression of a smooth dense 3D basis; kernels2d: per-kernel roofline "
-                         "figures of the general path on the 2D Cartesian and radial workloads")
+                         "figures of the general path on the 2D Cartesian and radial workloads; "
+                         "kernels2d_big: the same with 128-coil stacks of 268 MB (above the "
+                         "last-level cache)")
     ap.add_argument("--cg-iters", type=int, default=10, help="gn workload: CG steps per timed call")
     ap.add_argument("--branches", type=int, default=4, help="batch workload: concurrent branches")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -496,7 +499,7 @@ def bench_compress(args, torch):
     print(json.dumps(out), flush=True)
 
 
-def bench_kernels2d(args, torch):
+def bench_kernels2d(args, torch, names=("cart2d_256_dense200_j32", "radial2d_256_dense128_j16")):
     """Per-kernel roofline figures of the general path (dense basis GEMMs on the matrix cores,
     axis FFTs, Cartesian sampling, KB gridding) on the 2D Cartesian 256^2 (32 coils, K 200)
     and radial 256^2 (16 coils, K 128, 64 spokes x 512) workloads, from the in-library HIP
@@ -508,8 +511,10 @@ def bench_kernels2d(args, torch):
     dev = torch.device("cuda:0")
     T = lambda a: torch.from_numpy(np.ascontiguousarray(np.asarray(a).astype(np.complex64))).to(dev)  # noqa: E731
     res = {}
-    for name in ("cart2d_256_dense200_j32", "radial2d_256_dense128_j16"):
+    for name in names:
+        t0 = time.time()
         p = problem(name)
+        log(f"[bench] {name}: inputs ready in {time.time() - t0:.1f}s")
         kw = dict(mask_idx=p.mask_idx) if p.traj is None else dict(traj=p.traj, weights=p.weights)
         N, J, K, M = int(np.prod(p.dims)), p.J, p.K, p.M
         for prec in ("bf16_split", "fp32"):
@@ -568,7 +573,7 @@ def bench_kernels2d(args, torch):
                 f"{k} {v['us']}us {v.get('achieved_gbs', v.get('achieved_tflops'))}"
                 f"{'GB/s' if v['bound'] == 'hbm' else 'TF/s'} ({100 * v['frac']:.1f}%)" for k, v in out.items()))
             del plan
-    print(json.dumps({"metric": "per-kernel roofline fractions, general path", "workload": "kernels2d",
+    print(json.dumps({"metric": "per-kernel roofline fractions, general path", "workload": "+".join(names),
                       "steps": args.steps, "kernels": res}), flush=True)
 
 
@@ -606,6 +611,9 @@ def main():
         return
     if args.workload == "kernels2d":
         bench_kernels2d(args, torch)
+        return
+    if args.workload == "kernels2d_big":
+        bench_kernels2d(args, torch, ("cart2d_512_dense16_j128", "radial2d_256_dense32_j128"))
         return
 
     dev = torch.device("cuda:0")

@@ -25,6 +25,7 @@ struct NufftArgs {
   const int32_t* s_hlist;     // [n_heavy] split rows: row * ceil(g1 / 64) + column block; the
                               // first n_med from blocks at most 4x over the threshold
   int n_heavy, n_med;
+  int spread_lds;             // plain spread blocks: 1 stage the samples through LDS, 0 walk them from memory
   float cscale;               // sqrt(g0 g1 / (n0 n1)): unitary DFT -> the operator's scaling
 };
 

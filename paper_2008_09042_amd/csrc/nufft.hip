@@ -342,13 +342,176 @@ __global__ __launch_bounds__(256) void spread_flat_kernel(NufftArgs a, const flo
         grid[(int64_t)(jo + q) * G + (int64_t)(r0 + i) * a.g1 + c] = cscale(acc[i][q], sc);
 }
 
+// The same blocks with the samples staged through LDS.  A wave's samples are the sorted
+// ranges of its W + R - 1 cell rows over the columns [c0 - W + 1, c0 + 64) (two ranges in a
+// row whose window wraps past column 0), taken as one sequence of `total` records.  The
+// wave stages 64 consecutive records at a time (one per lane, coalesced: column, the tap of
+// each of its R output rows, the W column taps, the JG coil values), the next chunk loaded
+// into registers while the current one is used; each lane then adds the records of its own
+// window, which are consecutive in every range.  Fixed order per grid point: ranges in
+// (cell row, wrapped part first) order, samples in sorted order, as in the plain kernel.
+template <int JG, int W, int R>
+__global__ __launch_bounds__(256) void spread_lds_kernel(NufftArgs a, const float2* __restrict__ ys, int Jp,
+                                                         float alpha, const float* __restrict__ scale_dev,
+                                                         float2* __restrict__ grid) {
+  constexpr int NW = W + R - 1;  // cell rows
+  constexpr int NS = 2 * NW;     // ranges: (cell row t, part p), p = 0 wrapped columns, 1 the rest
+  constexpr int YV = JG >= 2 ? JG / 2 : 1;
+  struct Chunk {
+    float2 y[SPC][JG];
+    float w1[W][SPC];
+    float w0[R][SPC];
+    int col[SPC];
+  };
+  __shared__ Chunk chunks[4];
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  Chunk& ck = chunks[wave];
+  const int bc = (a.g1 + SPC - 1) / SPC;
+  const int64_t nblk = (int64_t)((a.g0 + R - 1) / R) * bc;
+  const int64_t id = (int64_t)blockIdx.x * 4 + wave;
+  if (id >= nblk * (Jp / JG)) return;  // whole waves only: no workgroup barrier follows
+  const int jg = (int)(id / nblk), blk = (int)(id % nblk);
+  if (a.s_heavy && a.s_heavy[blk]) return;  // rows taken by the split kernel
+  const int r0 = (blk / bc) * R, c0 = (blk % bc) * SPC, c = c0 + lane;
+  const bool live = c < a.g1;
+  const int jo = jg * JG;
+  const int lo_w = c0 - W + 1, hi_w = min(c0 + SPC, a.g1);
+  // range starts, lengths and the lane's part of each (as offsets into the range)
+  int S[NS], cum[NS + 1];
+  unsigned lr[NS];  // the lane's part of range q: [lr & 0xffff, lr >> 16) (ranges hold < 65536 samples)
+  cum[0] = 0;
+#pragma unroll
+  for (int t = 0; t < NW; ++t) {
+    const int row = ((r0 + R - 1 - t) % a.g0 + a.g0) % a.g0;
+    const int32_t* cp = a.cell_ptr + (int64_t)row * a.g1;
+    const int lo = c - W + 1;
+    // part 0: columns [g1 + lo_w, g1), present when the wave's window wraps
+    const int s0 = lo_w < 0 ? cp[a.g1 + lo_w] : 0, e0 = lo_w < 0 ? cp[a.g1] : 0;
+    const int l0 = (live && lo < 0) ? cp[a.g1 + lo] : e0;
+    // part 1: columns [max(lo_w, 0), hi_w)
+    const int s1 = cp[max(lo_w, 0)], e1 = cp[hi_w];
+    const int l1 = live ? cp[max(lo, 0)] : e1, m1 = live ? cp[c + 1] : e1;
+    S[2 * t] = __builtin_amdgcn_readfirstlane(s0);
+    cum[2 * t + 1] = cum[2 * t] + __builtin_amdgcn_readfirstlane(e0 - s0);
+    lr[2 * t] = (unsigned)(l0 - s0) | ((unsigned)(e0 - s0) << 16);
+    S[2 * t + 1] = __builtin_amdgcn_readfirstlane(s1);
+    cum[2 * t + 2] = cum[2 * t + 1] + __builtin_amdgcn_readfirstlane(e1 - s1);
+    lr[2 * t + 1] = (unsigned)(l1 - s1) | ((unsigned)(m1 - s1) << 16);
+  }
+  const int total = cum[NS];
+  // one record into registers: the sequence position v (clamped) of this lane's chunk slot
+  struct Rec {
+    int col;
+    float w0[R], w1[W];
+    float4 y[YV];
+  };
+  const auto fetch = [&](int v) __attribute__((always_inline)) {
+    Rec r;
+    v = min(v, total - 1);
+    int sidx = S[0] + v, tr = 0;
+#pragma unroll
+    for (int q = 1; q < NS; ++q)
+      if (v >= cum[q]) {
+        sidx = S[q] + (v - cum[q]);
+        tr = q / 2;
+      }
+    r.col = a.s_col[sidx];
+    const float* wr = a.s_wts + (int64_t)sidx * SREC;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int t0 = i - R + 1 + tr;
+      r.w0[i] = wr[min(max(t0, 0), W - 1)] * ((t0 >= 0 && t0 < W) ? 1.f : 0.f);
+    }
+#pragma unroll
+    for (int k = 0; k < W; ++k) r.w1[k] = wr[8 + k];
+    const float2* yr = ys + (int64_t)sidx * Jp + jo;
+    if constexpr (JG == 1) {
+      const float2 v2 = yr[0];
+      r.y[0] = make_float4(v2.x, v2.y, 0.f, 0.f);
+    } else {
+#pragma unroll
+      for (int q = 0; q < YV; ++q) r.y[q] = reinterpret_cast<const float4*>(yr)[q];
+    }
+    return r;
+  };
+  const auto put = [&](const Rec& r) __attribute__((always_inline)) {
+    ck.col[lane] = r.col;
+#pragma unroll
+    for (int i = 0; i < R; ++i) ck.w0[i][lane] = r.w0[i];
+#pragma unroll
+    for (int k = 0; k < W; ++k) ck.w1[k][lane] = r.w1[k];
+    if constexpr (JG == 1) {
+      ck.y[lane][0] = make_float2(r.y[0].x, r.y[0].y);
+    } else {
+#pragma unroll
+      for (int q = 0; q < YV; ++q) reinterpret_cast<float4*>(ck.y[lane])[q] = r.y[q];
+    }
+  };
+  float2 acc[R][JG];
+#pragma unroll
+  for (int i = 0; i < R; ++i)
+#pragma unroll
+    for (int q = 0; q < JG; ++q) acc[i][q] = make_float2(0.f, 0.f);
+  Rec nx{};
+  if (total > 0) nx = fetch(lane);  // the loads of a chunk slot past the sequence repeat its last record
+  for (int v0 = 0; v0 < total; v0 += SPC) {
+    put(nx);
+    asm volatile("" ::: "memory");  // the wave's LDS accesses run in program order
+    if (v0 + SPC < total) nx = fetch(v0 + SPC + lane);
+    // this lane's records in the chunk, range by range
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+      const int b = max(cum[q] + (int)(lr[q] & 0xffffu), v0), e = min(cum[q] + (int)(lr[q] >> 16), v0 + SPC);
+      for (int k = b; k < e; ++k) {
+        const int l = k - v0;
+        int t1 = c - ck.col[l];
+        if (t1 < 0) t1 += a.g1;
+        const float w1 = ck.w1[t1][l];
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          const float w = ck.w0[i][l] * w1;
+          if constexpr (JG == 1) {
+            const float2 y = ck.y[l][0];
+            acc[i][0].x += w * y.x;
+            acc[i][0].y += w * y.y;
+          } else {
+#pragma unroll
+            for (int h = 0; h < YV; ++h) {
+              const float4 y = reinterpret_cast<const float4*>(ck.y[l])[h];
+              acc[i][2 * h].x += w * y.x;
+              acc[i][2 * h].y += w * y.y;
+              acc[i][2 * h + 1].x += w * y.z;
+              acc[i][2 * h + 1].y += w * y.w;
+            }
+          }
+        }
+      }
+    }
+    asm volatile("" ::: "memory");
+  }
+  if (!live) return;
+  float sc = alpha * a.cscale;
+  if (scale_dev) sc *= *scale_dev;
+  const int64_t G = (int64_t)a.g0 * a.g1;
+#pragma unroll
+  for (int i = 0; i < R; ++i)
+#pragma unroll
+    for (int q = 0; q < JG; ++q)
+      if (r0 + i < a.g0 && jo + q < a.J)
+        grid[(int64_t)(jo + q) * G + (int64_t)(r0 + i) * a.g1 + c] = cscale(acc[i][q], sc);
+}
+
 template <int JG, int W>
 void launch_flat(const NufftArgs& a, const float2* ys, int Jp, float alpha, const float* scale_dev, float2* grid,
                  hipStream_t st) {
   constexpr int R = SPREAD_ROWS;
   const int64_t waves = (int64_t)((a.g0 + R - 1) / R) * ((a.g1 + SPC - 1) / SPC) * (Jp / JG);
-  hipLaunchKernelGGL((spread_flat_kernel<JG, W, R, 2>), dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, a, ys,
-                     Jp, alpha, scale_dev, grid);
+  if (a.spread_lds)
+    hipLaunchKernelGGL((spread_lds_kernel<JG, W, R>), dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, a, ys, Jp,
+                       alpha, scale_dev, grid);
+  else
+    hipLaunchKernelGGL((spread_flat_kernel<JG, W, R, 2>), dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, a, ys,
+                       Jp, alpha, scale_dev, grid);
 }
 
 template <int JG>
@@ -490,9 +653,11 @@ hipError_t spread_launch(const NufftArgs& a, const float2* y, float alpha, const
   if (a.W < 1 || a.W > 8) return hipErrorInvalidValue;
   if (a.M > 0)
     hipLaunchKernelGGL(spread_stage_kernel, dim3((unsigned)((a.M + STG - 1) / STG)), dim3(NT), 0, st, a, y, Jp, ys);
-  // the plain kernel takes 16 coils per lane where the padded coil count allows (one walk
-  // of a sample sequence serves twice the coils; 150 vs 156 us at 32 coils, 128 spokes)
-  switch (Jp % 16 == 0 ? 16 : jg) {
+  // the plain kernel from memory takes 16 coils per lane where the padded coil count allows
+  // (one walk of a sample sequence serves twice the coils; 150 vs 156 us at 32 coils, 128
+  // spokes); through LDS, at most 8 (twice the waves in flight: 31 vs 43 us at 16 coils,
+  // 64 spokes; 4 coils take 39 us)
+  switch (a.spread_lds ? jg : Jp % 16 == 0 ? 16 : jg) {
     case 1: launch_flat_w<1>(a, ys, Jp, alpha, scale_dev, grid, st); break;
     case 2: launch_flat_w<2>(a, ys, Jp, alpha, scale_dev, grid, st); break;
     case 4: launch_flat_w<4>(a, ys, Jp, alpha, scale_dev, grid, st); break;

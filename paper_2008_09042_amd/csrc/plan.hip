@@ -224,6 +224,7 @@ NufftArgs nufft_args(const Plan& p) {
   a.cell_ptr = p.d_cptr; a.s_perm = p.d_sperm; a.s_col = p.d_scol; a.s_wts = p.d_swts; a.s_base = p.d_sbase;
   a.s_heavy = p.n_heavy ? p.d_sheavy : nullptr; a.s_hlist = p.d_shlist; a.n_heavy = p.n_heavy;
   a.n_med = p.n_med;
+  a.spread_lds = p.spread_lds ? 1 : 0;
   a.cscale = p.kscale;
   return a;
 }
@@ -412,6 +413,7 @@ static maxwell_status nufft_build(Plan& p, const maxwell_plan_desc& d) {
   // split kernel.
   int split_min = SPREAD_SPLIT_DEFAULT;
   if (const char* env = std::getenv("MAXWELL_SPREAD_SPLIT")) split_min = std::max(0, std::atoi(env));
+  if (const char* env = std::getenv("MAXWELL_SPREAD_LDS")) p.spread_lds = std::atoi(env) != 0;
   constexpr int R = SPREAD_ROWS;
   const int bc = (p.g[1] + SPREAD_COLS - 1) / SPREAD_COLS;
   const int nrg = (p.g[0] + R - 1) / R;

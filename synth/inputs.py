@@ -463,6 +463,12 @@ WORKLOADS = {w["name"]: w for w in (
     dict(seed=4, name="cart3d_128_tucker40x300_j32", dims=(128, 128, 128), J=32, K=300,
          basis_kind="tucker", ranks=(40, 40, 40), degree=6, kmax=3.0, sampling="cartesian",
          mask="pd3d", R=8.0, centre=20),
+    # coil stacks of 268 MB (above the 256 MB last-level cache), for the bandwidth of the axis
+    # FFT passes and the gridding when their arrays stream from HBM
+    dict(seed=6, name="cart2d_512_dense16_j128", dims=(512, 512), J=128, K=16, basis_kind="dense",
+         degree=10, kmax=5.0, sampling="cartesian", mask="pd2d", R=6.0, centre=48),
+    dict(seed=7, name="radial2d_256_dense32_j128", dims=(256, 256), J=128, K=32, basis_kind="dense",
+         degree=10, kmax=5.0, sampling="radial", n_spokes=64, n_read=512),
 )}
 
 

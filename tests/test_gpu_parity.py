@@ -205,6 +205,30 @@ def test_edge_full_and_empty_mask():
     assert float(gx.abs().max().item()) == 0.0 and float(gc.abs().max().item()) == 0.0
 
 
+@pytest.mark.parametrize("split", ["1000000", None])
+@pytest.mark.parametrize("name", ["radial_32x24_J3_K9_7spokes", "radial_40x30_J2_K6_5spokes",
+                                  "radial_256_J2_K20_64spokes", "radial_64x48_J12_K7_16spokes"])
+def test_radial_spread_through_lds(name, split, monkeypatch):
+    """The plain spread blocks stage their samples through LDS (MAXWELL_SPREAD_LDS, default 1)
+    or walk them from memory (0).  Both add the same products in the same order per grid
+    point, so the gradients agree bit for bit; the LDS form meets the oracle.  A split
+    threshold of 1000000 sends the dense centre to the plain kernel too (long ranges over
+    many staged chunks)."""
+    if split is not None:
+        monkeypatch.setenv("MAXWELL_SPREAD_SPLIT", split)
+    cs = get_case(name)
+    x, c, y = T(cs.x0), T(cs.c0), T(cs.y)
+    out = {}
+    for lds in ("1", "0"):
+        monkeypatch.setenv("MAXWELL_SPREAD_LDS", lds)
+        print(f"[case] {name} spread through LDS {lds}, split {split}", flush=True)
+        out[lds] = cs.plan("fp32").adjoint(x, c, y)
+    gx_ref, gc_ref = cs.op.adjoint(cs.x0, cs.c0, cs.y)
+    assert_close(H(out["1"][0]), gx_ref, TOL["fp32"], what="gx")
+    assert_close(H(out["1"][1]), gc_ref, TOL["fp32"], coils=True, what="gc")
+    assert torch.equal(out["1"][0], out["0"][0]) and torch.equal(out["1"][1], out["0"][1])
+
+
 @pytest.mark.parametrize("name", ["tucker3d_24x20x18_r7x5x6_K13", "fused_48x32x20_r9x13x5_K23_J5"])
 def test_repeatable_bitwise(name):
     """No atomics anywhere: two runs give identical bits."""
