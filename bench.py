@@ -548,7 +548,8 @@ def bench_kernels2d(args, torch, names=("cart2d_256_dense200_j32", "radial2d_256
                 "nufft_degrid": ("hbm", 8.0 * J * (G + M) + M * (8.0 + 48.0), None, None),
                 "nufft_spread": ("hbm", 8.0 * J * (G + 2 * M) + M * (64.0 + 8.0) + 4.0 * G, None, None),
                 "nufft_pad": ("hbm", 8.0 * J * (N + G) + 8.0 * N, None, None),
-                "nufft_crop": ("hbm", 8.0 * J * (N + G), None, None),
+                # the crop reads the central n0 x n1 window of each coil's grid, not the grid
+                "nufft_crop": ("hbm", 16.0 * J * N, None, None),
                 "adjoint_combine": ("hbm", 8.0 * (3 * J * N + 2 * N), None, None),
                 "residual": ("hbm", 8.0 * J * M * 3 + 4.0 * M, None, None),
             }
