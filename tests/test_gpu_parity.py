@@ -39,6 +39,9 @@ CASES = {
                                         basis="tucker", mask="lines3d", frac=0.125),
     "fused_64x64x32_r20_K30_J3": dict(seed=112, dims=(64, 64, 32), ranks=(20, 20, 7), J=3, K=30,
                                       basis="tucker", mask="lines3d", frac=0.2, weights=True),
+    # 128 x 128 planes with ranks below 33 (run-time rank blocks in both plane kernels)
+    "fused_128x128x32_r20x14x9_K30_J3": dict(seed=122, dims=(128, 128, 32), ranks=(20, 14, 9), J=3, K=30,
+                                             basis="tucker", mask="lines3d", frac=0.15, weights=True),
     # core contraction kernels: several rho chunks with a ragged tail, two k groups, 3 and 4
     # coil blocks; J = 65 takes the GEMM fallback
     "tucker3d_16x16x12_r9x10x11_K150_J37": dict(seed=116, dims=(16, 16, 12), ranks=(9, 10, 11), J=37, K=150,
@@ -65,7 +68,7 @@ CASES = {
 }
 FUSED = {"tucker3d_32x32x32_r12_K70_J4", "fused_48x32x20_r9x13x5_K23_J5", "fused_16x80x12_r3x17x4_K11_J3",
          "fused_128x128x64_r40_K60_J5", "fused_64x64x32_r20_K30_J3", "fused_32x32x16_r9x10x11_K150_J64",
-         "fused_32x16x80_r5x6x70_K9_J2"}
+         "fused_32x16x80_r5x6x70_K9_J2", "fused_128x128x32_r20x14x9_K30_J3"}
 
 _cache = {}
 
