@@ -487,7 +487,7 @@ __device__ __forceinline__ void adj_map_load(const PlaneArgs& a, const Geo<N0, N
 // transform holds whole passes.  Measured at 128 x 128 planes, the first is faster in
 // BF16-split (its matrix-core steps are short, so U0 read latency from memory shows) and
 // the second in FP32.
-template <int PREC, int N0, int N1, int RB>
+template <int PREC, int N0, int N1, int RB, bool FULL = false>
 __global__ __launch_bounds__(PT) void plane_adj_kernel(PlaneArgs a) {
   __shared__ float2 lds[LDS_ELEMS];
   const Geo<N0, N1, RB> g(a);
@@ -495,7 +495,7 @@ __global__ __launch_bounds__(PT) void plane_adj_kernel(PlaneArgs a) {
   int i2, gi;
   plane_block(ngrp, g.n2, i2, gi);
   const float2* xp = a.xt + (size_t)i2 * g.n0 * g.n1;
-  const bool want_gx = a.gxpart != nullptr;
+  const bool want_gx = FULL || a.gxpart != nullptr;  // FULL: gx and T3b both wanted, known at compile time
   const Share sh = plane_share(g);
   int zq[SCAT];  // sampled plane positions, the same for every coil
 #pragma unroll
@@ -591,7 +591,7 @@ __global__ __launch_bounds__(PT) void plane_adj_kernel(PlaneArgs a) {
       }
     }
     __syncthreads();
-    if (a.T3b) adjoint_w<PREC>(a, g, j, i2, lds, lane, tid);
+    if (FULL || a.T3b) adjoint_w<PREC>(a, g, j, i2, lds, lane, tid);
   }
   if (want_gx && sh.on) {
     const int lane = threadIdx.x & 63, grp = lane >> 4;
@@ -609,7 +609,7 @@ __global__ __launch_bounds__(PT) void plane_adj_kernel(PlaneArgs a) {
   }
 }
 
-template <int PREC, int N0, int N1, int RB>
+template <int PREC, int N0, int N1, int RB, bool FULL = false>
 __global__ __launch_bounds__(PT) void plane_adj_late_kernel(PlaneArgs a) {
   __shared__ float2 lds[LDS_ELEMS];
   const Geo<N0, N1, RB> g(a);
@@ -617,7 +617,7 @@ __global__ __launch_bounds__(PT) void plane_adj_late_kernel(PlaneArgs a) {
   int i2, gi;
   plane_block(ngrp, g.n2, i2, gi);
   const float2* xp = a.xt + (size_t)i2 * g.n0 * g.n1;
-  const bool want_gx = a.gxpart != nullptr;
+  const bool want_gx = FULL || a.gxpart != nullptr;  // FULL: gx and T3b both wanted, known at compile time
   const Share sh = plane_share(g);
   int zq[SCAT];  // sampled plane positions, the same for every coil
 #pragma unroll
@@ -735,7 +735,7 @@ __global__ __launch_bounds__(PT) void plane_adj_late_kernel(PlaneArgs a) {
       }
     }
     __syncthreads();
-    if (a.T3b) adjoint_w<PREC>(a, g, j, i2, lds, lane, tid);
+    if (FULL || a.T3b) adjoint_w<PREC>(a, g, j, i2, lds, lane, tid);
   }
   if (want_gx && sh.on) {
     const int lane = threadIdx.x & 63, grp = lane >> 4;
@@ -948,11 +948,15 @@ template <int PREC, int N0, int N1>
 void adj_launch(dim3 grid, dim3 block, const PlaneArgs& a, hipStream_t st) {
   constexpr int RB3 = N0 == 128 && N1 == 128 ? 3 : 0;
   const bool rb3 = RB3 == 3 && a.r0p == 48 && a.r1p == 48;
+  // with both outputs wanted (the gradient step) the output checks are compile-time too
+  const bool full = a.gxpart != nullptr && a.T3b != nullptr;
   if constexpr (PREC == 0) {
-    if (rb3) hipLaunchKernelGGL((plane_adj_late_kernel<PREC, N0, N1, RB3>), grid, block, 0, st, a);
+    if (rb3 && full) hipLaunchKernelGGL((plane_adj_late_kernel<PREC, N0, N1, RB3, true>), grid, block, 0, st, a);
+    else if (rb3) hipLaunchKernelGGL((plane_adj_late_kernel<PREC, N0, N1, RB3>), grid, block, 0, st, a);
     else hipLaunchKernelGGL((plane_adj_late_kernel<PREC, N0, N1, 0>), grid, block, 0, st, a);
   } else {
-    if (rb3) hipLaunchKernelGGL((plane_adj_kernel<PREC, N0, N1, RB3>), grid, block, 0, st, a);
+    if (rb3 && full) hipLaunchKernelGGL((plane_adj_kernel<PREC, N0, N1, RB3, true>), grid, block, 0, st, a);
+    else if (rb3) hipLaunchKernelGGL((plane_adj_kernel<PREC, N0, N1, RB3>), grid, block, 0, st, a);
     else hipLaunchKernelGGL((plane_adj_kernel<PREC, N0, N1, 0>), grid, block, 0, st, a);
   }
 }
