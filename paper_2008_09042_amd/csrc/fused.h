@@ -25,6 +25,8 @@ struct PlaneArgs {
   const void* U1TF;                  // B of V = W U1^T:      B(p1, i1) = U1[i1][p1]
   const void* U1CF;                  // B of Y = h conj(U1):  B(i1, p1) = conj(U1[i1][p1])
   const void* U0HF;                  // A of Wb = U0^H Y:     A(p0, i0) = conj(U0[i0][p0])
+  const void* U0SF;                  // U0F and U1TF with row i0 / column i1 times (-1)^i: the
+  const void* U1TSF;                 //   adjoint's coil map P' = s P carries the output sign s
 };
 
 struct LineArgs {
@@ -48,7 +50,8 @@ struct LineArgs {
 
 bool fused_supported(int64_t n0, int64_t n1, int64_t n2, int64_t r0, int64_t r1, int precision);
 // Fragment-ordered copy (see tucker_fused.hip) of O(o, k) = src[o * so + k * sk], conjugated
-// if conj, zero for o >= no or k >= nk, as an A (is_b = 0) or B (is_b = 1) operand.
+// if bit 0 of conj, times (-1)^o if bit 1, zero for o >= no or k >= nk, as an A (is_b = 0) or
+// B (is_b = 1) operand.
 size_t frag_operand_bytes(int no, int nk, int is_b, int precision);
 hipError_t frag_operand_launch(const float2* src, int no, int nk, int64_t so, int64_t sk, int conj, int is_b,
                                int precision, void* dst, hipStream_t st);

@@ -50,6 +50,7 @@ struct Plan {
   int32_t* d_pos = nullptr;    // [L] plane index k0 * n1 + k1 of each line
   void* d_frag = nullptr;      // fragment-ordered factor operands (one allocation)
   const void *U0F = nullptr, *U1TF = nullptr, *U1CF = nullptr, *U0HF = nullptr;
+  const void *U0SF = nullptr, *U1TSF = nullptr;  // with the adjoint's chessboard sign
   bool mode3_direct = false;   // dedicated third-mode product kernels (r2 <= 64)
   const void *U2F = nullptr, *U2CF = nullptr;
   // dedicated core contraction kernels (Tucker basis, J <= 64)

@@ -310,6 +310,8 @@ PlaneArgs plane_args(const Plan& p, void* ws, int G) {
   a.U1TF = p.U1TF;
   a.U1CF = p.U1CF;
   a.U0HF = p.U0HF;
+  a.U0SF = p.U0SF;
+  a.U1TSF = p.U1TSF;
   return a;
 }
 
@@ -538,16 +540,20 @@ maxwell_status plan_build(Plan& p, const maxwell_plan_desc& d, const maxwell_bas
     p.mode3_direct = mode3_supported(r2);
     const size_t bU2F = p.mode3_direct ? frag_operand_bytes(n2, r2, 0, pr) : 0;
     const size_t bU2CF = p.mode3_direct ? frag_operand_bytes(r2, n2, 1, pr) : 0;
-    if ((e = hipMalloc(&p.d_frag, bU0F + bU1TF + bU1CF + bU0HF + bU2F + bU2CF)) != hipSuccess) return hip_err(e);
+    if ((e = hipMalloc(&p.d_frag, 2 * (bU0F + bU1TF) + bU1CF + bU0HF + bU2F + bU2CF)) != hipSuccess) return hip_err(e);
     char* q = reinterpret_cast<char*>(p.d_frag);
     p.U0F = q; q += bU0F;
     p.U1TF = q; q += bU1TF;
+    p.U0SF = q; q += bU0F;
+    p.U1TSF = q; q += bU1TF;
     p.U1CF = q; q += bU1CF;
     p.U0HF = q; q += bU0HF;
     p.U2F = q; q += bU2F;
     p.U2CF = q;
     if ((e = frag_operand_launch(p.U[0], n0, r0, r0, 1, 0, 0, pr, const_cast<void*>(p.U0F), 0)) ||
         (e = frag_operand_launch(p.U[1], n1, r1, r1, 1, 0, 1, pr, const_cast<void*>(p.U1TF), 0)) ||
+        (e = frag_operand_launch(p.U[0], n0, r0, r0, 1, 2, 0, pr, const_cast<void*>(p.U0SF), 0)) ||
+        (e = frag_operand_launch(p.U[1], n1, r1, r1, 1, 2, 1, pr, const_cast<void*>(p.U1TSF), 0)) ||
         (e = frag_operand_launch(p.U[1], r1, n1, 1, r1, 1, 1, pr, const_cast<void*>(p.U1CF), 0)) ||
         (e = frag_operand_launch(p.U[0], r0, n0, 1, r0, 1, 0, pr, const_cast<void*>(p.U0HF), 0)))
       return hip_err(e);

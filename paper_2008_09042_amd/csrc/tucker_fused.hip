@@ -367,16 +367,17 @@ __device__ __forceinline__ void adjoint_w(const PlaneArgs& a, const Geo<N0, N1, 
 // the whole factor) staged in the plane region and W in the stage region; V = W U1^T for
 // the wave's column block into registers, then the wave's P tiles.
 template <int PREC, int N0, int N1, int RB>
-__device__ __forceinline__ void coil_map(const PlaneArgs& a, const Geo<N0, N1, RB>& g, float2* lds, const Share& sh,
-                                         int lane, int tid, const WPrefetch& w, f32x4 (&pr)[8], f32x4 (&pi)[8]) {
+__device__ __forceinline__ void coil_map(const void* u0f, const void* u1tf, const Geo<N0, N1, RB>& g, float2* lds,
+                                         const Share& sh, int lane, int tid, const WPrefetch& w, f32x4 (&pr)[8],
+                                         f32x4 (&pi)[8]) {
   // the column block's U1^T fragments, in flight across the stores
   typename Tile<PREC>::B u1[3];
 #pragma unroll
   for (int s = 0; s < 3; ++s)
-    if (s < g.r1b) u1[s] = frag_b<PREC>(a.U1TF, g.n1b, sh.cb, s, lane);
+    if (s < g.r1b) u1[s] = frag_b<PREC>(u1tf, g.n1b, sh.cb, s, lane);
   {
     const int n = g.n0b * g.r0b * 128;  // 16-byte pieces of U0 in fragment order (2 KiB a fragment)
-    const uint4* src = reinterpret_cast<const uint4*>(a.U0F);
+    const uint4* src = reinterpret_cast<const uint4*>(u0f);
     uint4* dst = reinterpret_cast<uint4*>(lds);
     for (int e = tid; e < n; e += PT) dst[e] = src[e];
   }
@@ -423,7 +424,7 @@ __global__ __launch_bounds__(PT) void plane_fwd_kernel(PlaneArgs a) {
     asm volatile("" : "+v"(tid));
     const int lane = tid & 63, grp = lane >> 4;
     f32x4 pr[8], pi[8];
-    coil_map<PREC>(a, g, lds, sh, lane, tid, w, pr, pi);
+    coil_map<PREC>(a.U0F, a.U1TF, g, lds, sh, lane, tid, w, pr, pi);
     if (j + 1 < j1) w_load(a, g, j + 1, i2, wsl, w);
     // m = x (.) P; the input chessboard sign of the centred DFT is carried by xt
     if (sh.on) {
@@ -477,7 +478,7 @@ template <int PREC, int N0, int N1, int RB>
 __device__ __forceinline__ void adj_map_load(const PlaneArgs& a, const Geo<N0, N1, RB>& g, const Share& sh, int lane,
                                              AdjMap<PREC, N0, N1, RB>& m, int k) {
   const int i = k / 3, s = k % 3, rb = sh.part + i * sh.q;
-  if (i < 8 && rb < g.n0b && s < g.r0b) m.ring[k & 3] = frag_a<PREC>(a.U0F, g.r0b, rb, s, lane);
+  if (i < 8 && rb < g.n0b && s < g.r0b) m.ring[k & 3] = frag_a<PREC>(a.U0SF, g.r0b, rb, s, lane);
 }
 
 // Adjoint plane kernel, two forms.  plane_adj_kernel (BF16-split plans) forms the coil map
@@ -521,7 +522,8 @@ __global__ __launch_bounds__(PT) void plane_adj_kernel(PlaneArgs a) {
     if (want_gx) {
       WPrefetch w;
       w_load(a, g, j, i2, w_slots(g, tid), w);  // offsets recomputed: no registers held across coils
-      coil_map<PREC>(a, g, lds, sh, lane, tid, w, pr, pi);  // B c recomputed
+      // B c recomputed, with U0 and U1 carrying the output chessboard sign: P' = s P
+      coil_map<PREC>(a.U0SF, a.U1TSF, g, lds, sh, lane, tid, w, pr, pi);
     }
     // zero-filled scatter (with the chessboard sign)
     for (int e = tid; e < g.n0 * g.PS; e += PT) lds[e] = make_float2(0.f, 0.f);
@@ -545,9 +547,9 @@ __global__ __launch_bounds__(PT) void plane_adj_kernel(PlaneArgs a) {
     // compile-time plane sizes: whole passes over wave-owned lines (fewer barriers)
     plane_fft<(N0 != 0 ? FFT_CHUNK_FWD : FFT_CHUNK_ADJ)>(a, g, lds, +1);
     // g = s g' (g' the plane after the transform, s the output chessboard sign):
-    // gx += conj(P) s g' in registers; h = conj(x) s g' = conj(s x) g' into the plane, s x
-    // being what xt holds.  x in two batches of four tiles, each batch's loads issued
-    // together.
+    // gx += conj(P) s g' = conj(P') g' in registers (P' = s P from the signed factors);
+    // h = conj(x) s g' = conj(s x) g' into the plane, s x being what xt holds.  x in two
+    // batches of four tiles, each batch's loads issued together.
     if (sh.on) {
 #pragma unroll
       for (int hb = 0; hb < 2; ++hb) {
@@ -578,9 +580,8 @@ __global__ __launch_bounds__(PT) void plane_adj_kernel(PlaneArgs a) {
             for (int r = 0; r < 4; ++r) {
               const int i0 = 16 * rb + 4 * grp + r;
               const float2 gv = gvs[ii][r];
-              if (want_gx) {
-                float2 c = cmulc(make_float2(pr[i][r], pi[i][r]), gv);
-                if ((i0 + i1) & 1) c = make_float2(-c.x, -c.y);
+              if (want_gx) {  // conj(P') g' = s conj(P) g'
+                const float2 c = cmulc(make_float2(pr[i][r], pi[i][r]), gv);
                 gr[i][r] += c.x;
                 gim[i][r] += c.y;
               }
@@ -675,11 +676,11 @@ __global__ __launch_bounds__(PT) void plane_adj_late_kernel(PlaneArgs a) {
 #pragma unroll
         for (int mb = 0; mb < 3; ++mb) cv[mb] = Tile<PREC>::zero();
         typename Tile<PREC>::B u1[2];
-        u1[0] = frag_b<PREC>(a.U1TF, g.n1b, sh.cb, 0, lane);
+        u1[0] = frag_b<PREC>(a.U1TSF, g.n1b, sh.cb, 0, lane);
 #pragma unroll
         for (int s = 0; s < 3; ++s)
           if (s < g.r1b) {
-            if (s + 1 < g.r1b) u1[(s + 1) & 1] = frag_b<PREC>(a.U1TF, g.n1b, sh.cb, s + 1, lane);
+            if (s + 1 < g.r1b) u1[(s + 1) & 1] = frag_b<PREC>(a.U1TSF, g.n1b, sh.cb, s + 1, lane);
             if (s == 1)
 #pragma unroll
               for (int k = 0; k < 3; ++k) adj_map_load(a, g, sh, lane, m, k);
@@ -720,10 +721,8 @@ __global__ __launch_bounds__(PT) void plane_adj_late_kernel(PlaneArgs a) {
             f32x4 pr, pi;
             Tile<PREC>::finish(c, pr, pi);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int i0 = 16 * rb + 4 * grp + r;
-              float2 cg = cmulc(make_float2(pr[r], pi[r]), gv[r]);
-              if ((i0 + i1) & 1) cg = make_float2(-cg.x, -cg.y);
+            for (int r = 0; r < 4; ++r) {  // conj(P') g' = s conj(P) g' (signed factors)
+              const float2 cg = cmulc(make_float2(pr[r], pi[r]), gv[r]);
               gr[i][r] += cg.x;
               gim[i][r] += cg.y;
             }
@@ -753,8 +752,8 @@ __global__ __launch_bounds__(PT) void plane_adj_late_kernel(PlaneArgs a) {
   }
 }
 
-// Plan-time fragment-ordered copy of O(o, k) = src[o * so + k * sk] (conjugated if conj),
-// zero for o >= no or k >= nk.  One thread per (o block, step, lane).
+// Plan-time fragment-ordered copy of O(o, k) = src[o * so + k * sk] (conjugated if bit 0 of
+// conj, times (-1)^o if bit 1), zero for o >= no or k >= nk.  One thread per (o block, step, lane).
 template <int PREC>
 __global__ void frag_operand_kernel(const float2* __restrict__ src, int no, int nk, int64_t so, int64_t sk, int conj,
                                     int is_b, void* dst) {
@@ -768,7 +767,8 @@ __global__ void frag_operand_kernel(const float2* __restrict__ src, int no, int 
     for (int t = 0; t < 4; ++t) {
       const int k = 16 * s + 4 * (lane >> 4) + t;
       v[t] = (o < no && k < nk) ? src[(int64_t)o * so + (int64_t)k * sk] : make_float2(0.f, 0.f);
-      if (conj) v[t].y = -v[t].y;
+      if (conj & 1) v[t].y = -v[t].y;
+      if ((conj & 2) && (o & 1)) v[t] = make_float2(-v[t].x, -v[t].y);
     }
     if (is_b) put_frag_b<PREC>(dst, obs, ob, s, lane, v);
     else put_frag_a<PREC>(dst, ks, ob, s, lane, v);
