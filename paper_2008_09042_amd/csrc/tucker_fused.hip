@@ -490,7 +490,7 @@ __device__ __forceinline__ void adj_map_load(const PlaneArgs& a, const Geo<N0, N
 // the second in FP32.
 template <int PREC, int N0, int N1, int RB, bool FULL = false>
 __global__ __launch_bounds__(PT) void plane_adj_kernel(PlaneArgs a) {
-  __shared__ float2 lds[LDS_ELEMS];
+  __shared__ __align__(16) float2 lds[LDS_ELEMS];
   const Geo<N0, N1, RB> g(a);
   const int ngrp = (a.J + a.G - 1) / a.G;
   int i2, gi;
@@ -526,7 +526,10 @@ __global__ __launch_bounds__(PT) void plane_adj_kernel(PlaneArgs a) {
       coil_map<PREC>(a.U0SF, a.U1TSF, g, lds, sh, lane, tid, w, pr, pi);
     }
     // zero-filled scatter (with the chessboard sign)
-    for (int e = tid; e < g.n0 * g.PS; e += PT) lds[e] = make_float2(0.f, 0.f);
+    {  // 16-byte stores (the plane region starts the 16-byte aligned LDS array); n0 PS is even
+      float4* z4p = reinterpret_cast<float4*>(lds);
+      for (int e = tid; e < g.n0 * g.PS / 2; e += PT) z4p[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < SCAT; ++k)
@@ -612,7 +615,7 @@ __global__ __launch_bounds__(PT) void plane_adj_kernel(PlaneArgs a) {
 
 template <int PREC, int N0, int N1, int RB, bool FULL = false>
 __global__ __launch_bounds__(PT) void plane_adj_late_kernel(PlaneArgs a) {
-  __shared__ float2 lds[LDS_ELEMS];
+  __shared__ __align__(16) float2 lds[LDS_ELEMS];
   const Geo<N0, N1, RB> g(a);
   const int ngrp = (a.J + a.G - 1) / a.G;
   int i2, gi;
@@ -646,7 +649,10 @@ __global__ __launch_bounds__(PT) void plane_adj_late_kernel(PlaneArgs a) {
       w_store<PREC>(g, lds, tid, w);              // the stage region is free (previous coil done)
     }
     // zero-filled scatter (with the chessboard sign)
-    for (int e = tid; e < g.n0 * g.PS; e += PT) lds[e] = make_float2(0.f, 0.f);
+    {  // 16-byte stores (the plane region starts the 16-byte aligned LDS array); n0 PS is even
+      float4* z4p = reinterpret_cast<float4*>(lds);
+      for (int e = tid; e < g.n0 * g.PS / 2; e += PT) z4p[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < SCAT; ++k)
