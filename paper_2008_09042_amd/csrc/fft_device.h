@@ -368,6 +368,58 @@ __device__ __forceinline__ void stockham_pass_wave(float2* lds, int LS, int ES, 
   }
 }
 
+// The last pass (Ns R = N, so butterfly column j has twiddle index k = j) over wave-owned
+// lines, with each lane keeping one column and stepping over lines: lane -> (column
+// lane % nR, line lane / nR + (64 / nR) q).  The lane's R - 1 twiddles are read once and serve
+// every butterfly it computes, where the general mapping reads or forms them per butterfly.
+// A quarter wave touches 16 consecutive columns of one line: conflict-free for unit and for
+// odd element strides.
+template <int N, int R, int NTHREADS, int CH, int TL, int QB = 0>
+__device__ __forceinline__ void stockham_last_pass_wave(float2* lds, int LS, int ES, const float2* tw, int dir,
+                                                        int tid) {
+  constexpr int nR = N / R;
+  constexpr int NW = NTHREADS / 64;
+  constexpr int Tc = CH / N < TL ? CH / N : TL;
+  constexpr int LPW = Tc / NW;
+  constexpr int LG = 64 / nR;  // lines of one q step
+  constexpr int MAXQ = LPW / LG;
+  static_assert(Tc % NW == 0 && TL % Tc == 0 && 64 % nR == 0 && LPW % LG == 0, "lane mapping");
+  const int wave = tid >> 6, lane = tid & 63;
+  const int j = lane % nR, lsub = lane / nR;
+  float2 w[R];
+#pragma unroll
+  for (int r = 1; r < R; ++r) {
+    w[r] = tw[j * r];  // w^(j r), j r < N
+    if (dir > 0) w[r].y = -w[r].y;
+  }
+  // a butterfly's outputs j + r Ns go where its inputs j + r nR were: each batch of QB line
+  // steps is read, transformed and written back before the next (fewer live registers)
+  constexpr int B = QB > 0 && QB < MAXQ ? QB : MAXQ;
+  static_assert(MAXQ % B == 0, "batches split the line steps evenly");
+  for (int l0 = 0; l0 < TL; l0 += Tc) {
+#pragma unroll
+    for (int q0 = 0; q0 < MAXQ; q0 += B) {
+      const int base = (l0 + wave * LPW + lsub + q0 * LG) * LS + j * ES;
+      float2 v[B][R];
+#pragma unroll
+      for (int q = 0; q < B; ++q) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[q][r] = lds[base + q * LG * LS + r * nR * ES];
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], w[r]);
+        dft_small<R>(v[q], dir);
+      }
+      asm volatile("" ::: "memory");
+#pragma unroll
+      for (int q = 0; q < B; ++q) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds[base + q * LG * LS + r * nR * ES] = v[q][r];
+      }
+      asm volatile("" ::: "memory");
+    }
+  }
+}
+
 // Whether wave-owned passes are free of LDS bank conflicts for an odd line stride: a
 // quarter wave (16 lanes) then reads 16 different lines at one butterfly column.
 template <int N, int NTHREADS, int CH, int TL>
@@ -378,11 +430,14 @@ constexpr bool wave_lines_fit() {
 
 // All passes of one transform over wave-owned lines (stockham_pass_wave): no workgroup
 // barrier inside; the caller synchronises before and after.
-template <int N, int NTHREADS, int CH, int TL>
+template <int N, int NTHREADS, int CH, int TL, int QB = 0>
 __device__ __forceinline__ void lds_fft_ct_wave(float2* lds, int LS, int ES, const float2* tw, int dir, int tid) {
   using P = CtPlan<N>;
   stockham_pass_wave<N, P::R0, 1, NTHREADS, CH, TL>(lds, LS, ES, tw, dir, tid);
-  if constexpr (P::P > 1) stockham_pass_wave<N, P::R1, P::R0, NTHREADS, CH, TL>(lds, LS, ES, tw, dir, tid);
+  if constexpr (P::P > 1) {
+    static_assert(P::R0 * P::R1 == N, "two passes: the second is the last");
+    stockham_last_pass_wave<N, P::R1, NTHREADS, CH, TL, QB>(lds, LS, ES, tw, dir, tid);
+  }
 }
 
 template <int N, int NTHREADS, int CH>

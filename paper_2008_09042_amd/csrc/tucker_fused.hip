@@ -110,7 +110,7 @@ __device__ __forceinline__ void load_twiddles(const PlaneArgs& a, const Geo<N0, 
 
 // 2D centred DFT of the plane (chessboard signs applied by the caller); ends synchronised.
 // CH elements of a pass are held in registers at a time.
-template <int CH, int N0, int N1, int RB>
+template <int CH, int N0, int N1, int RB, int QB = 0>
 __device__ __forceinline__ void plane_fft(const PlaneArgs& a, const Geo<N0, N1, RB>& g, float2* lds, int dir) {
   const float2* tw0 = lds + TW_OFF;
   const float2* tw1 = tw0 + PMAX;
@@ -120,7 +120,7 @@ __device__ __forceinline__ void plane_fft(const PlaneArgs& a, const Geo<N0, N1, 
   // least 16 lines per wave; otherwise every pass synchronises the workgroup
   auto rows = [&]() {
     if constexpr (N1 != 0 && wave_lines_fit<N1, PT, CH, N0>()) {
-      lds_fft_ct_wave<N1, PT, CH, N0>(lds, g.PS, 1, tw1, dir, tid);
+      lds_fft_ct_wave<N1, PT, CH, N0, QB>(lds, g.PS, 1, tw1, dir, tid);
       __syncthreads();
     } else if constexpr (N1 != 0) {
       lds_fft_ct<N1, PT, CH>(lds, g.n0, g.PS, 1, tw1, dir, tid);
@@ -131,7 +131,7 @@ __device__ __forceinline__ void plane_fft(const PlaneArgs& a, const Geo<N0, N1, 
   };
   auto cols = [&]() {
     if constexpr (N0 != 0 && wave_lines_fit<N0, PT, CH, N1>()) {
-      lds_fft_ct_wave<N0, PT, CH, N1>(lds, 1, g.PS, tw0, dir, tid);
+      lds_fft_ct_wave<N0, PT, CH, N1, QB>(lds, 1, g.PS, tw0, dir, tid);
       __syncthreads();
     } else if constexpr (N0 != 0) {
       lds_fft_ct<N0, PT, CH>(lds, g.n1, 1, g.PS, tw0, dir, tid);
@@ -548,7 +548,8 @@ __global__ __launch_bounds__(PT) void plane_adj_kernel(PlaneArgs a) {
     }
     __syncthreads();
     // compile-time plane sizes: whole passes over wave-owned lines (fewer barriers)
-    plane_fft<(N0 != 0 ? FFT_CHUNK_FWD : FFT_CHUNK_ADJ)>(a, g, lds, +1);
+    // last pass two line steps at a time: the map and gx stay in registers across it
+    plane_fft<(N0 != 0 ? FFT_CHUNK_FWD : FFT_CHUNK_ADJ), N0, N1, RB, 2>(a, g, lds, +1);
     // g = s g' (g' the plane after the transform, s the output chessboard sign):
     // gx += conj(P) s g' = conj(P') g' in registers (P' = s P from the signed factors);
     // h = conj(x) s g' = conj(s x) g' into the plane, s x being what xt holds.  x in two
