@@ -128,8 +128,9 @@ typedef struct {
  * basis.  Allocates device memory; not capturable.  Environment read here:
  * MAXWELL_GEMM_AUTOTUNE=0 skips timing the dense-basis GEMM splits;
  * MAXWELL_SPREAD_SPLIT=n (NONCARTESIAN) sets the per-lane sample count above
- * which a block of the gridding adjoint goes to its split kernel (default 48;
- * results agree to rounding either way).                                    */
+ * which a block of the gridding adjoint goes to its split rows (default 48;
+ * results agree to rounding either way); MAXWELL_SPREAD_SPLIT_PARTS=pm,ph
+ * (powers of two up to 64) the workgroups per split row (default 4,16).     */
 maxwell_status maxwell_plan_create(const maxwell_plan_desc* desc, const maxwell_basis_desc* basis,
                                    maxwell_plan_t* plan_out);
 

@@ -19,12 +19,13 @@ struct NufftArgs {
   const int2* s_base;         // [M] first-tap (row, column) of each sorted sample
   const float* s_wts;         // [M][16] tap weights of each sorted sample: axis 0 in [0, W), axis 1 in [8, 8 + W)
   // spread blocks (SPREAD_ROWS grid rows, 64 columns) in which some lane's sample sequence
-  // exceeds the split threshold: skipped by the plain kernel, their rows taken one by one
-  // by the split kernel
+  // exceeds the split threshold: skipped by the plain kernels, their rows taken one by one
+  // by the split-row workgroups
   const uint8_t* s_heavy;     // [ceil(g0 / SPREAD_ROWS) * ceil(g1 / 64)] 1 for a split block (may be null)
   const int32_t* s_hlist;     // [n_heavy] split rows: row * ceil(g1 / 64) + column block; the
                               // first n_med from blocks at most 4x over the threshold
   int n_heavy, n_med;
+  int split_pm, split_ph;     // column parts of a split row: rows of moderately long blocks, of the longest
   int spread_lds;             // plain spread blocks: 1 stage the samples through LDS, 0 walk them from memory
   float cscale;               // sqrt(g0 g1 / (n0 n1)): unitary DFT -> the operator's scaling
 };
@@ -39,6 +40,9 @@ constexpr int SPREAD_COLS = 64;
 #define SPREAD_ROWS 2   // grid rows per wave of the plain spread kernel
 #endif
 constexpr int SPREAD_SPLIT_DEFAULT = 48;
+// Column parts of a split row (each a workgroup over 64 / P columns): rows of blocks at most
+// four times over the threshold, and the longest (MAXWELL_SPREAD_SPLIT_PARTS=pm,ph overrides).
+constexpr int SPREAD_SPLIT_PM = 4, SPREAD_SPLIT_PH = 16;
 size_t spread_stage_bytes(int J, int64_t M);
 hipError_t pad_deapod_launch(const NufftArgs& a, const float2* S, const float2* x, float2* grid, hipStream_t st);
 hipError_t crop_deapod_launch(const NufftArgs& a, const float2* grid, float2* out, hipStream_t st);

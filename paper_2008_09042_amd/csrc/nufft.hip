@@ -115,7 +115,8 @@ __global__ __launch_bounds__(NT) void degrid_kernel(NufftArgs a, const float2* _
 // samples, so the wave's time is the latency of a few dependent loads; one wave per block
 // keeps the whole grid resident at once.  The blocks whose longest sequence is long (the
 // dense centre of a radial trajectory, where a grid point sees hundreds of samples) are
-// marked at plan time and taken by the split kernel below instead.
+// marked at plan time; their rows are split over many lanes per grid point (split rows,
+// below), in the same launch as the plain blocks when those are staged through LDS.
 constexpr int SPC = SPREAD_COLS;    // grid columns per workgroup (one per lane)
 constexpr int STG = 64;             // samples per staging workgroup
 
@@ -209,6 +210,154 @@ __device__ __forceinline__ void spread_range(const NufftArgs& a, const float2* _
   }
 }
 
+// Split rows: the rows of the blocks in which some grid point sees more samples than the
+// split threshold (the dense centre of a radial trajectory, where it sees hundreds).  One
+// workgroup of four waves takes one split row, SCOL = 64 / P of its block's columns and JG
+// coils, with P = split_pm for the rows of blocks at most four times over the threshold and
+// split_ph for the longest.  A column is shared by 4 P lanes (P per wave): a lane walks the
+// column's W row windows (cell row r - t0 for tap t0 = 0 .. W - 1, each the W cells ending at
+// the column) as one sequence of samples and takes every (4 P)-th group of U consecutive
+// positions.  The 4 P partial sums of an output are added through LDS (spart, 256 JG
+// entries) in share order: fixed, no atomics.  Used by the LDS plain kernel's launch (its
+// workgroups after the plain ones) and by spread_split_kernel, so both paths add the same
+// products in the same order.
+template <int JG, int W, int U>
+__device__ __forceinline__ void spread_split_block(const NufftArgs& a, const float2* __restrict__ ys, int Jp,
+                                                   float alpha, const float* __restrict__ scale_dev,
+                                                   float2* __restrict__ grid, int bid, float2* spart) {
+  const int bc = (a.g1 + SPC - 1) / SPC;
+  const int per_g = a.split_pm * a.n_med + a.split_ph * (a.n_heavy - a.n_med);
+  const int jg = bid / per_g;
+  int rem = bid - jg * per_g, P, h;
+  if (rem < a.split_pm * a.n_med) {
+    P = a.split_pm;
+    h = rem / P;
+    rem -= h * P;
+  } else {
+    rem -= a.split_pm * a.n_med;
+    P = a.split_ph;
+    h = a.n_med + rem / P;
+    rem -= (h - a.n_med) * P;
+  }
+  const int SCOL = SPC / P;
+  const int blk = a.s_hlist[h];
+  const int r = blk / bc, c0 = (blk % bc) * SPC + rem * SCOL;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int cc = lane % SCOL, ls = lane / SCOL;
+  const int share = wave * P + ls, nshare = 4 * P;
+  const bool live = c0 + cc < a.g1;
+  const int c = live ? c0 + cc : a.g1 - 1;  // a lane past the last column walks nothing
+  const int jo = jg * JG;
+  // row window t0 contributes [rb[2 t0], + len) then [rb[2 t0 + 1], + len) (the second one
+  // non-empty only at the column wrap); all offsets are loaded unconditionally
+  int rb[2 * W], cum[2 * W + 1];
+  {
+    const int lo = c - W + 1;
+    const int i0 = lo >= 0 ? lo : a.g1 + lo, i1 = lo >= 0 ? c + 1 : a.g1, i3 = lo >= 0 ? 0 : c + 1;
+    int v0[W], v1[W], v2[W], v3[W];
+#pragma unroll
+    for (int t = 0; t < W; ++t) {
+      const int row = ((r - t) % a.g0 + a.g0) % a.g0;
+      const int32_t* cp = a.cell_ptr + (int64_t)row * a.g1;
+      v0[t] = cp[i0];
+      v1[t] = cp[i1];
+      v2[t] = cp[0];
+      v3[t] = cp[i3];
+    }
+    cum[0] = 0;
+#pragma unroll
+    for (int t = 0; t < W; ++t) {
+      rb[2 * t] = v0[t];
+      cum[2 * t + 1] = cum[2 * t] + (v1[t] - v0[t]);
+      rb[2 * t + 1] = v2[t];
+      cum[2 * t + 2] = cum[2 * t + 1] + (v3[t] - v2[t]);
+    }
+  }
+  const int total = live ? cum[2 * W] : 0;
+  const float4* rec = reinterpret_cast<const float4*>(a.s_wts);
+  constexpr int YV = JG >= 2 ? JG / 2 : 1;
+  float2 acc[JG];
+#pragma unroll
+  for (int q = 0; q < JG; ++q) acc[q] = make_float2(0.f, 0.f);
+  for (int k = U * share; k < total; k += U * nshare) {
+    int col[U];
+    float w0[U];
+    float4 w1l[U], w1h[U];
+    float4 yv[U][YV];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int kk = min(k + u, total - 1);
+      // the last range whose start is at or before kk holds it (empty ranges are passed over)
+      int su = rb[0] + kk, t = 0;
+#pragma unroll
+      for (int j = 1; j < 2 * W; ++j)
+        if (kk >= cum[j]) {
+          su = rb[j] + (kk - cum[j]);
+          t = j / 2;
+        }
+      col[u] = a.s_col[su];
+      w0[u] = a.s_wts[(int64_t)su * SREC + t];
+      w1l[u] = rec[(int64_t)su * (SREC / 4) + 2];
+      w1h[u] = rec[(int64_t)su * (SREC / 4) + 3];
+      const float2* yr = ys + (int64_t)su * Jp + jo;
+      if constexpr (JG == 1) {
+        const float2 v = yr[0];
+        yv[u][0] = make_float4(v.x, v.y, 0.f, 0.f);
+      } else {
+#pragma unroll
+        for (int q = 0; q < YV; ++q) yv[u][q] = reinterpret_cast<const float4*>(yr)[q];
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      asm volatile("" : "+v"(w1l[u].x), "+v"(w1l[u].y), "+v"(w1l[u].z), "+v"(w1l[u].w));
+      asm volatile("" : "+v"(w1h[u].x), "+v"(w1h[u].y), "+v"(w1h[u].z), "+v"(w1h[u].w));
+      int t1 = c - col[u];
+      if (t1 < 0) t1 += a.g1;
+      const float w = (k + u < total ? w0[u] : 0.f) * pick8(w1l[u], w1h[u], t1);
+      if constexpr (JG == 1) {
+        acc[0].x += w * yv[u][0].x;
+        acc[0].y += w * yv[u][0].y;
+      } else {
+#pragma unroll
+        for (int q = 0; q < YV; ++q) {
+          acc[2 * q].x += w * yv[u][q].x;
+          acc[2 * q].y += w * yv[u][q].y;
+          acc[2 * q + 1].x += w * yv[u][q].z;
+          acc[2 * q + 1].y += w * yv[u][q].w;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < JG; ++q) spart[(int)threadIdx.x * JG + q] = acc[q];
+  __syncthreads();
+  float sc = alpha * a.cscale;
+  if (scale_dev) sc *= *scale_dev;
+  const int64_t G = (int64_t)a.g0 * a.g1;
+  for (int o = threadIdx.x; o < JG * SCOL; o += 256) {
+    const int q = o / SCOL, l = o % SCOL;
+    if (c0 + l >= a.g1 || jo + q >= a.J) continue;
+    float2 v = make_float2(0.f, 0.f);
+    for (int w = 0; w < 4; ++w)
+      for (int s2 = 0; s2 < P; ++s2) {
+        const float2 p = spart[(w * 64 + s2 * SCOL + l) * JG + q];
+        v.x += p.x;
+        v.y += p.y;
+      }
+    grid[(int64_t)(jo + q) * G + (int64_t)r * a.g1 + c0 + l] = cscale(v, sc);
+  }
+}
+
+template <int JG, int W>
+__global__ __launch_bounds__(256) void spread_split_kernel(NufftArgs a, const float2* __restrict__ ys, int Jp,
+                                                           float alpha, const float* __restrict__ scale_dev,
+                                                           float2* __restrict__ grid) {
+  __shared__ float2 spart[256 * JG];
+  spread_split_block<JG, W, 2>(a, ys, Jp, alpha, scale_dev, grid, (int)blockIdx.x, spart);
+}
+
 // One wave per (coil group, R grid rows, 64 columns); four waves per workgroup.  Output row
 // r0 + i of a lane takes the samples of cell rows r0 + i - t0 (t0 < W); over its R rows the
 // lane walks the W + R - 1 cell rows r0 + R - 1 - t (t = 0 .. W + R - 2) once, in t order,
@@ -224,7 +373,7 @@ __global__ __launch_bounds__(256) void spread_flat_kernel(NufftArgs a, const flo
   const int64_t id = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
   if (id >= nblk * (Jp / JG)) return;
   const int jg = (int)(id / nblk), blk = (int)(id % nblk);
-  if (a.s_heavy && a.s_heavy[blk]) return;  // rows taken by the split kernel
+  if (a.s_heavy && a.s_heavy[blk]) return;  // split rows, taken by spread_split_kernel
   const int r0 = (blk / bc) * R, c = (blk % bc) * SPC + threadIdx.x % 64;
   if (c >= a.g1) return;  // no barrier or cross-lane operation follows
   const int jo = jg * JG;
@@ -351,7 +500,7 @@ __global__ __launch_bounds__(256) void spread_flat_kernel(NufftArgs a, const flo
 // window, which are consecutive in every range.  Fixed order per grid point: ranges in
 // (cell row, wrapped part first) order, samples in sorted order, as in the plain kernel.
 template <int JG, int W, int R>
-__global__ __launch_bounds__(256) void spread_lds_kernel(NufftArgs a, const float2* __restrict__ ys, int Jp,
+__global__ __launch_bounds__(256, 4) void spread_lds_kernel(NufftArgs a, const float2* __restrict__ ys, int Jp,
                                                          float alpha, const float* __restrict__ scale_dev,
                                                          float2* __restrict__ grid) {
   constexpr int NW = W + R - 1;  // cell rows
@@ -368,10 +517,19 @@ __global__ __launch_bounds__(256) void spread_lds_kernel(NufftArgs a, const floa
   Chunk& ck = chunks[wave];
   const int bc = (a.g1 + SPC - 1) / SPC;
   const int64_t nblk = (int64_t)((a.g0 + R - 1) / R) * bc;
+  // workgroups past the plain blocks' take the split rows, with the chunk staging as their
+  // partial sums (uniform per workgroup, so the split rows' barrier is reached by all)
+  const int64_t nplain = (nblk * (Jp / JG) + 3) / 4;
+  if ((int64_t)blockIdx.x >= nplain) {
+    static_assert(sizeof(chunks) >= 256 * JG * sizeof(float2), "split partial sums fit the staging");
+    spread_split_block<JG, W, 2>(a, ys, Jp, alpha, scale_dev, grid, (int)(blockIdx.x - nplain),
+                                 reinterpret_cast<float2*>(chunks));
+    return;
+  }
   const int64_t id = (int64_t)blockIdx.x * 4 + wave;
   if (id >= nblk * (Jp / JG)) return;  // whole waves only: no workgroup barrier follows
   const int jg = (int)(id / nblk), blk = (int)(id % nblk);
-  if (a.s_heavy && a.s_heavy[blk]) return;  // rows taken by the split kernel
+  if (a.s_heavy && a.s_heavy[blk]) return;  // split rows, taken by the workgroups after these
   const int r0 = (blk / bc) * R, c0 = (blk % bc) * SPC, c = c0 + lane;
   const bool live = c < a.g1;
   const int jo = jg * JG;
@@ -399,10 +557,13 @@ __global__ __launch_bounds__(256) void spread_lds_kernel(NufftArgs a, const floa
     lr[2 * t + 1] = (unsigned)(l1 - s1) | ((unsigned)(m1 - s1) << 16);
   }
   const int total = cum[NS];
-  // one record into registers: the sequence position v (clamped) of this lane's chunk slot
+  // one record into registers: the sequence position v (clamped) of this lane's chunk slot.
+  // The R row taps and W column taps it uses are packed into whole vectors, so the record
+  // stays in registers.
+  constexpr int NP = (R + W + 3) / 4;
   struct Rec {
     int col;
-    float w0[R], w1[W];
+    float4 w[NP];  // row taps [0, R), column taps [R, R + W)
     float4 y[YV];
   };
   const auto fetch = [&](int v) __attribute__((always_inline)) {
@@ -416,14 +577,21 @@ __global__ __launch_bounds__(256) void spread_lds_kernel(NufftArgs a, const floa
         tr = q / 2;
       }
     r.col = a.s_col[sidx];
-    const float* wr = a.s_wts + (int64_t)sidx * SREC;
+    const float4* wr = reinterpret_cast<const float4*>(a.s_wts) + (int64_t)sidx * (SREC / 4);
+    const float4 w0l = wr[0], w0h = wr[1], w1l = wr[2], w1h = wr[3];
+    const float w1[8] = {w1l.x, w1l.y, w1l.z, w1l.w, w1h.x, w1h.y, w1h.z, w1h.w};
+    float t[4 * NP];
 #pragma unroll
     for (int i = 0; i < R; ++i) {
       const int t0 = i - R + 1 + tr;
-      r.w0[i] = wr[min(max(t0, 0), W - 1)] * ((t0 >= 0 && t0 < W) ? 1.f : 0.f);
+      t[i] = (t0 >= 0 && t0 < W) ? pick8(w0l, w0h, t0) : 0.f;
     }
 #pragma unroll
-    for (int k = 0; k < W; ++k) r.w1[k] = wr[8 + k];
+    for (int k = 0; k < W; ++k) t[R + k] = w1[k];
+#pragma unroll
+    for (int k = R + W; k < 4 * NP; ++k) t[k] = 0.f;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) r.w[p] = make_float4(t[4 * p], t[4 * p + 1], t[4 * p + 2], t[4 * p + 3]);
     const float2* yr = ys + (int64_t)sidx * Jp + jo;
     if constexpr (JG == 1) {
       const float2 v2 = yr[0];
@@ -436,10 +604,18 @@ __global__ __launch_bounds__(256) void spread_lds_kernel(NufftArgs a, const floa
   };
   const auto put = [&](const Rec& r) __attribute__((always_inline)) {
     ck.col[lane] = r.col;
+    float t[4 * NP];
 #pragma unroll
-    for (int i = 0; i < R; ++i) ck.w0[i][lane] = r.w0[i];
+    for (int p = 0; p < NP; ++p) {
+      t[4 * p] = r.w[p].x;
+      t[4 * p + 1] = r.w[p].y;
+      t[4 * p + 2] = r.w[p].z;
+      t[4 * p + 3] = r.w[p].w;
+    }
 #pragma unroll
-    for (int k = 0; k < W; ++k) ck.w1[k][lane] = r.w1[k];
+    for (int i = 0; i < R; ++i) ck.w0[i][lane] = t[i];
+#pragma unroll
+    for (int k = 0; k < W; ++k) ck.w1[k][lane] = t[R + k];
     if constexpr (JG == 1) {
       ck.y[lane][0] = make_float2(r.y[0].x, r.y[0].y);
     } else {
@@ -452,42 +628,45 @@ __global__ __launch_bounds__(256) void spread_lds_kernel(NufftArgs a, const floa
   for (int i = 0; i < R; ++i)
 #pragma unroll
     for (int q = 0; q < JG; ++q) acc[i][q] = make_float2(0.f, 0.f);
-  Rec nx{};
-  if (total > 0) nx = fetch(lane);  // the loads of a chunk slot past the sequence repeat its last record
-  for (int v0 = 0; v0 < total; v0 += SPC) {
-    put(nx);
-    asm volatile("" ::: "memory");  // the wave's LDS accesses run in program order
-    if (v0 + SPC < total) nx = fetch(v0 + SPC + lane);
-    // this lane's records in the chunk, range by range
+  if (total > 0) {
+    // the loads of a chunk slot past the sequence repeat its last record (the index is
+    // clamped), so the fetch is unconditional: the one after the last chunk goes unused
+    Rec nx = fetch(lane);
+    for (int v0 = 0; v0 < total; v0 += SPC) {
+      put(nx);
+      asm volatile("" ::: "memory");  // the wave's LDS accesses run in program order
+      nx = fetch(v0 + SPC + lane);
+      // this lane's records in the chunk, range by range
 #pragma unroll
-    for (int q = 0; q < NS; ++q) {
-      const int b = max(cum[q] + (int)(lr[q] & 0xffffu), v0), e = min(cum[q] + (int)(lr[q] >> 16), v0 + SPC);
-      for (int k = b; k < e; ++k) {
-        const int l = k - v0;
-        int t1 = c - ck.col[l];
-        if (t1 < 0) t1 += a.g1;
-        const float w1 = ck.w1[t1][l];
+      for (int q = 0; q < NS; ++q) {
+        const int b = max(cum[q] + (int)(lr[q] & 0xffffu), v0), e = min(cum[q] + (int)(lr[q] >> 16), v0 + SPC);
+        for (int k = b; k < e; ++k) {
+          const int l = k - v0;
+          int t1 = c - ck.col[l];
+          if (t1 < 0) t1 += a.g1;
+          const float w1 = ck.w1[t1][l];
 #pragma unroll
-        for (int i = 0; i < R; ++i) {
-          const float w = ck.w0[i][l] * w1;
-          if constexpr (JG == 1) {
-            const float2 y = ck.y[l][0];
-            acc[i][0].x += w * y.x;
-            acc[i][0].y += w * y.y;
-          } else {
+          for (int i = 0; i < R; ++i) {
+            const float w = ck.w0[i][l] * w1;
+            if constexpr (JG == 1) {
+              const float2 y = ck.y[l][0];
+              acc[i][0].x += w * y.x;
+              acc[i][0].y += w * y.y;
+            } else {
 #pragma unroll
-            for (int h = 0; h < YV; ++h) {
-              const float4 y = reinterpret_cast<const float4*>(ck.y[l])[h];
-              acc[i][2 * h].x += w * y.x;
-              acc[i][2 * h].y += w * y.y;
-              acc[i][2 * h + 1].x += w * y.z;
-              acc[i][2 * h + 1].y += w * y.w;
+              for (int h = 0; h < YV; ++h) {
+                const float4 y = reinterpret_cast<const float4*>(ck.y[l])[h];
+                acc[i][2 * h].x += w * y.x;
+                acc[i][2 * h].y += w * y.y;
+                acc[i][2 * h + 1].x += w * y.z;
+                acc[i][2 * h + 1].y += w * y.w;
+              }
             }
           }
         }
       }
+      asm volatile("" ::: "memory");
     }
-    asm volatile("" ::: "memory");
   }
   if (!live) return;
   float sc = alpha * a.cscale;
@@ -506,12 +685,22 @@ void launch_flat(const NufftArgs& a, const float2* ys, int Jp, float alpha, cons
                  hipStream_t st) {
   constexpr int R = SPREAD_ROWS;
   const int64_t waves = (int64_t)((a.g0 + R - 1) / R) * ((a.g1 + SPC - 1) / SPC) * (Jp / JG);
-  if (a.spread_lds)
-    hipLaunchKernelGGL((spread_lds_kernel<JG, W, R>), dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, a, ys, Jp,
-                       alpha, scale_dev, grid);
-  else
-    hipLaunchKernelGGL((spread_flat_kernel<JG, W, R, 2>), dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, a, ys,
-                       Jp, alpha, scale_dev, grid);
+  const int64_t plain = (waves + 3) / 4;
+  const int64_t split =
+      a.n_heavy > 0 ? (int64_t)(a.split_pm * a.n_med + a.split_ph * (a.n_heavy - a.n_med)) * (Jp / JG) : 0;
+  bool lds = false;
+  if constexpr (JG <= 8) lds = a.spread_lds != 0;  // the LDS form takes at most 8 coils per lane
+  if (lds) {  // one launch: the plain blocks' workgroups, then the split rows'
+    if constexpr (JG <= 8)
+      hipLaunchKernelGGL((spread_lds_kernel<JG, W, R>), dim3((unsigned)(plain + split)), dim3(256), 0, st, a, ys, Jp,
+                         alpha, scale_dev, grid);
+  } else {
+    hipLaunchKernelGGL((spread_flat_kernel<JG, W, R, 2>), dim3((unsigned)plain), dim3(256), 0, st, a, ys, Jp, alpha,
+                       scale_dev, grid);
+    if (split > 0)
+      hipLaunchKernelGGL((spread_split_kernel<JG, W>), dim3((unsigned)split), dim3(256), 0, st, a, ys, Jp, alpha,
+                         scale_dev, grid);
+  }
 }
 
 template <int JG>
@@ -526,81 +715,6 @@ void launch_flat_w(const NufftArgs& a, const float2* ys, int Jp, float alpha, co
     case 6: launch_flat<JG, 6>(a, ys, Jp, alpha, scale_dev, grid, st); break;
     case 7: launch_flat<JG, 7>(a, ys, Jp, alpha, scale_dev, grid, st); break;
     default: launch_flat<JG, 8>(a, ys, Jp, alpha, scale_dev, grid, st); break;
-  }
-}
-
-// Split kernel for the blocks with long sample chains (the dense centre of a radial
-// trajectory).  A workgroup takes SCOL = 64 / L columns of one such block and JG coils with
-// W * S waves; each column's window for row offset t0 is shared by S waves and L lanes of a
-// wave, which take every (S L)-th pair of samples, so the longest chain is S L times shorter
-// (L = 2 for the moderately long blocks, 8 for the longest).
-// The W S L partial sums of an output are added through LDS in the order (t0, wave
-// share, lane share): fixed, no atomics.
-
-__host__ __device__ constexpr int split_waves(int W) { return 12 / W > 1 ? 12 / W : 1; }
-
-template <int JG>
-__global__ __launch_bounds__(1024) void spread_split_kernel(NufftArgs a, const float2* __restrict__ ys, int Jp,
-                                                            float alpha, const float* __restrict__ scale_dev,
-                                                            float2* __restrict__ grid) {
-  extern __shared__ float2 spart[];  // [W S][JG][64]
-  const int W = a.W, S = split_waves(W);
-  const int bc = (a.g1 + SPC - 1) / SPC;
-  // per coil group: 2 workgroups for each of the first n_med rows, 8 for each of the others
-  const int per_g = 2 * a.n_med + 8 * (a.n_heavy - a.n_med);
-  const int jg = blockIdx.x / per_g;
-  int rem = blockIdx.x % per_g, SPL = 2, h;
-  if (rem < 2 * a.n_med) {
-    h = rem / 2;
-    rem %= 2;
-  } else {
-    rem -= 2 * a.n_med;
-    SPL = 8;
-    h = a.n_med + rem / 8;
-    rem %= 8;
-  }
-  const int SCOL = SPC / SPL;  // columns per workgroup
-  const int blk = a.s_hlist[h];
-  const int r = blk / bc, c0 = (blk % bc) * SPC + rem * SCOL;
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int t0 = wave % W, ws = wave / W;
-  const int cc = lane % SCOL, ls = lane / SCOL;
-  const int share = ws * SPL + ls, nshare = S * SPL;
-  const int c = c0 + cc;
-  const int jo = jg * JG;
-  float2 acc[JG];
-#pragma unroll
-  for (int q = 0; q < JG; ++q) acc[q] = make_float2(0.f, 0.f);
-  if (c < a.g1) {
-    int row = r - t0;
-    if (row < 0) row += a.g0;
-    const int32_t* cp = a.cell_ptr + (int64_t)row * a.g1;
-    const int lo = c - W + 1;
-    if (lo >= 0) {
-      spread_range<JG, 2>(a, ys, Jp, jo, c, t0, cp[lo] + 2 * share, cp[c + 1], 2 * nshare, acc);
-    } else {
-      spread_range<JG, 2>(a, ys, Jp, jo, c, t0, cp[a.g1 + lo] + 2 * share, cp[a.g1], 2 * nshare, acc);
-      spread_range<JG, 2>(a, ys, Jp, jo, c, t0, cp[0] + 2 * share, cp[c + 1], 2 * nshare, acc);
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < JG; ++q) spart[((int64_t)wave * JG + q) * 64 + lane] = acc[q];
-  __syncthreads();
-  float sc = alpha * a.cscale;
-  if (scale_dev) sc *= *scale_dev;
-  const int64_t G = (int64_t)a.g0 * a.g1;
-  for (int o = threadIdx.x; o < JG * SCOL; o += blockDim.x) {
-    const int q = o / SCOL, l = o % SCOL;
-    if (c0 + l >= a.g1 || jo + q >= a.J) continue;
-    float2 v = make_float2(0.f, 0.f);
-    for (int t = 0; t < W; ++t)
-      for (int w2 = 0; w2 < S; ++w2)
-        for (int l2 = 0; l2 < SPL; ++l2) {
-          const float2 p = spart[((int64_t)(t + W * w2) * JG + q) * 64 + l + SCOL * l2];
-          v.x += p.x;
-          v.y += p.y;
-        }
-    grid[(int64_t)(jo + q) * G + (int64_t)r * a.g1 + c0 + l] = cscale(v, sc);
   }
 }
 
@@ -663,17 +777,6 @@ hipError_t spread_launch(const NufftArgs& a, const float2* y, float alpha, const
     case 4: launch_flat_w<4>(a, ys, Jp, alpha, scale_dev, grid, st); break;
     case 8: launch_flat_w<8>(a, ys, Jp, alpha, scale_dev, grid, st); break;
     default: launch_flat_w<16>(a, ys, Jp, alpha, scale_dev, grid, st); break;
-  }
-  if (a.n_heavy > 0) {  // one launch for both kinds of split rows
-    const int S = split_waves(a.W);
-    const dim3 sg((unsigned)((int64_t)(2 * a.n_med + 8 * (a.n_heavy - a.n_med)) * (Jp / jg))), sb(64 * a.W * S);
-    const size_t lds = (size_t)a.W * S * jg * 64 * sizeof(float2);
-    switch (jg) {
-      case 1: hipLaunchKernelGGL(spread_split_kernel<1>, sg, sb, lds, st, a, ys, Jp, alpha, scale_dev, grid); break;
-      case 2: hipLaunchKernelGGL(spread_split_kernel<2>, sg, sb, lds, st, a, ys, Jp, alpha, scale_dev, grid); break;
-      case 4: hipLaunchKernelGGL(spread_split_kernel<4>, sg, sb, lds, st, a, ys, Jp, alpha, scale_dev, grid); break;
-      default: hipLaunchKernelGGL(spread_split_kernel<8>, sg, sb, lds, st, a, ys, Jp, alpha, scale_dev, grid); break;
-    }
   }
   return hipGetLastError();
 }

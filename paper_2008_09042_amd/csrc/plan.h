@@ -75,6 +75,7 @@ struct Plan {
   uint8_t* d_sheavy = nullptr;   // [g0 ceil(g1 / 64)] spread blocks taken by the split kernel
   int32_t* d_shlist = nullptr;   // [n_heavy] their indices
   int n_heavy = 0, n_med = 0;
+  int split_pm = 4, split_ph = 16;  // column parts of the split spread rows
   bool spread_lds = true;     // plain spread blocks through LDS ($MAXWELL_SPREAD_LDS=0: from memory)
   float2* d_twg[2] = {nullptr, nullptr};  // grid twiddles
   int nradg[2] = {0, 0};

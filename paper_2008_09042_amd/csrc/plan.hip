@@ -11,6 +11,7 @@
 // of one call.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <string>
@@ -224,6 +225,8 @@ NufftArgs nufft_args(const Plan& p) {
   a.cell_ptr = p.d_cptr; a.s_perm = p.d_sperm; a.s_col = p.d_scol; a.s_wts = p.d_swts; a.s_base = p.d_sbase;
   a.s_heavy = p.n_heavy ? p.d_sheavy : nullptr; a.s_hlist = p.d_shlist; a.n_heavy = p.n_heavy;
   a.n_med = p.n_med;
+  a.split_pm = p.split_pm;
+  a.split_ph = p.split_ph;
   a.spread_lds = p.spread_lds ? 1 : 0;
   a.cscale = p.kscale;
   return a;
@@ -416,6 +419,16 @@ static maxwell_status nufft_build(Plan& p, const maxwell_plan_desc& d) {
   int split_min = SPREAD_SPLIT_DEFAULT;
   if (const char* env = std::getenv("MAXWELL_SPREAD_SPLIT")) split_min = std::max(0, std::atoi(env));
   if (const char* env = std::getenv("MAXWELL_SPREAD_LDS")) p.spread_lds = std::atoi(env) != 0;
+  p.split_pm = SPREAD_SPLIT_PM;
+  p.split_ph = SPREAD_SPLIT_PH;
+  if (const char* env = std::getenv("MAXWELL_SPREAD_SPLIT_PARTS")) {
+    int pm = 0, ph = 0;
+    auto pow2 = [](int v) { return v >= 1 && v <= 64 && (v & (v - 1)) == 0; };
+    if (std::sscanf(env, "%d,%d", &pm, &ph) == 2 && pow2(pm) && pow2(ph)) {
+      p.split_pm = pm;
+      p.split_ph = ph;
+    }
+  }
   constexpr int R = SPREAD_ROWS;
   const int bc = (p.g[1] + SPREAD_COLS - 1) / SPREAD_COLS;
   const int nrg = (p.g[0] + R - 1) / R;
