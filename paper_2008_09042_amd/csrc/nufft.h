@@ -15,6 +15,7 @@ struct NufftArgs {
   // the samples sorted by the cell (row-major) of their first tap (spread and degrid)
   const int32_t* cell_ptr;    // [g0 * g1 + 1] CSR offsets of the cells into the sorted order
   const int32_t* s_perm;      // [M] original index of each sorted sample
+  const int32_t* s_inv;       // [M] sorted position of each sample (s_perm's inverse)
   const int32_t* s_col;       // [M] first-tap column of each sorted sample
   const int2* s_base;         // [M] first-tap (row, column) of each sorted sample
   const float* s_wts;         // [M][16] tap weights of each sorted sample: axis 0 in [0, W), axis 1 in [8, 8 + W)

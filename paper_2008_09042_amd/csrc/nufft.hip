@@ -118,28 +118,33 @@ __global__ __launch_bounds__(NT) void degrid_kernel(NufftArgs a, const float2* _
 // marked at plan time; their rows are split over many lanes per grid point (split rows,
 // below), in the same launch as the plain blocks when those are staged through LDS.
 constexpr int SPC = SPREAD_COLS;    // grid columns per workgroup (one per lane)
-constexpr int STG = 64;             // samples per staging workgroup
 
-// ys[s][j] = y[j][perm[s]] for j < J, 0 for J <= j < Jp
+// ys[inv[m]][j] = y[j][m] for j < J, 0 for J <= j < Jp.  A thread per sample m reads its
+// coils down the columns of y (coalesced over m across a wave; the inverse permutation's load
+// does not hold them up) and writes its Jp values as one contiguous run (a 128-byte line at 16
+// coils), 16 bytes at a time where Jp is even.
 __global__ __launch_bounds__(NT) void spread_stage_kernel(NufftArgs a, const float2* __restrict__ y, int Jp,
                                                           float2* __restrict__ ys) {
-  __shared__ float2 t[STG][33];
-  const int64_t s0 = (int64_t)blockIdx.x * STG;
-  const int ls = threadIdx.x % STG, lj = threadIdx.x / STG;
-  const int64_t s = s0 + ls;
-  const int m = s < a.M ? a.s_perm[s] : 0;
-  for (int j0 = 0; j0 < Jp; j0 += 32) {
-    for (int jj = lj; jj < 32; jj += NT / STG) {
-      const int j = j0 + jj;
-      t[ls][jj] = (j < a.J && s < a.M) ? y[(int64_t)j * a.M + m] : make_float2(0.f, 0.f);
+  const int64_t m = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (m >= a.M) return;
+  float2* dst = ys + (int64_t)a.s_inv[m] * Jp;
+  for (int j0 = 0; j0 < Jp; j0 += 8) {
+    float2 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = min(j0 + u, a.J - 1);  // in range; the value is dropped past J
+      v[u] = y[(int64_t)j * a.M + m];
+      if (j0 + u >= a.J) v[u] = make_float2(0.f, 0.f);
     }
-    __syncthreads();
-    const int jj = threadIdx.x % 32;
-    for (int q = threadIdx.x / 32; q < STG; q += NT / 32) {
-      const int64_t sq = s0 + q;
-      if (sq < a.M && j0 + jj < Jp) ys[sq * Jp + j0 + jj] = t[q][jj];
+    if ((Jp & 1) == 0) {
+#pragma unroll
+      for (int u = 0; u < 8; u += 2)
+        if (j0 + u < Jp) reinterpret_cast<float4*>(dst + j0)[u / 2] = make_float4(v[u].x, v[u].y, v[u + 1].x, v[u + 1].y);
+    } else {
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (j0 + u < Jp) dst[j0 + u] = v[u];
     }
-    __syncthreads();
   }
 }
 
@@ -766,7 +771,7 @@ hipError_t spread_launch(const NufftArgs& a, const float2* y, float alpha, const
   const int Jp = (a.J + jg - 1) / jg * jg;
   if (a.W < 1 || a.W > 8) return hipErrorInvalidValue;
   if (a.M > 0)
-    hipLaunchKernelGGL(spread_stage_kernel, dim3((unsigned)((a.M + STG - 1) / STG)), dim3(NT), 0, st, a, y, Jp, ys);
+    hipLaunchKernelGGL(spread_stage_kernel, dim3((unsigned)((a.M + NT - 1) / NT)), dim3(NT), 0, st, a, y, Jp, ys);
   // the plain kernel from memory takes 16 coils per lane where the padded coil count allows
   // (one walk of a sample sequence serves twice the coils; 150 vs 156 us at 32 coils, 128
   // spokes); through LDS, at most 8 (twice the waves in flight: 31 vs 43 us at 16 coils,

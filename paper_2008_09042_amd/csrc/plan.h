@@ -69,6 +69,7 @@ struct Plan {
   float* d_iphi = nullptr;       // [n0 + n1] inverse deapodisation per axis
   int32_t* d_cptr = nullptr;     // [g0 g1 + 1] samples sorted by first-tap cell (CSR)
   int32_t* d_sperm = nullptr;    // [M] original index of each sorted sample
+  int32_t* d_sinv = nullptr;     // [M] sorted position of each sample
   int32_t* d_scol = nullptr;     // [M] first-tap column of each sorted sample
   float* d_swts = nullptr;       // [M][16] tap weights in sorted order (axis 1 from slot 8)
   int2* d_sbase = nullptr;       // [M] first-tap (row, column) in sorted order

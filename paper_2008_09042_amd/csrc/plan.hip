@@ -222,7 +222,7 @@ NufftArgs nufft_args(const Plan& p) {
   a.g0 = p.g[0]; a.g1 = p.g[1];
   a.J = p.J; a.W = p.W; a.M = p.M;
   a.iphi0 = p.d_iphi; a.iphi1 = p.d_iphi + p.n[0];
-  a.cell_ptr = p.d_cptr; a.s_perm = p.d_sperm; a.s_col = p.d_scol; a.s_wts = p.d_swts; a.s_base = p.d_sbase;
+  a.cell_ptr = p.d_cptr; a.s_perm = p.d_sperm; a.s_inv = p.d_sinv; a.s_col = p.d_scol; a.s_wts = p.d_swts; a.s_base = p.d_sbase;
   a.s_heavy = p.n_heavy ? p.d_sheavy : nullptr; a.s_hlist = p.d_shlist; a.n_heavy = p.n_heavy;
   a.n_med = p.n_med;
   a.split_pm = p.split_pm;
@@ -473,6 +473,11 @@ static maxwell_status nufft_build(Plan& p, const maxwell_plan_desc& d) {
   if ((e = up((void**)&p.d_iphi, iphi.data(), iphi.size() * sizeof(float))) != hipSuccess) return hip_err(e);
   if ((e = up((void**)&p.d_cptr, cptr.data(), cptr.size() * sizeof(int32_t))) != hipSuccess) return hip_err(e);
   if ((e = up((void**)&p.d_sperm, sperm.data(), sperm.size() * sizeof(int32_t))) != hipSuccess) return hip_err(e);
+  {
+    std::vector<int32_t> sinv((size_t)M);
+    for (int64_t s = 0; s < M; ++s) sinv[(size_t)sperm[(size_t)s]] = (int32_t)s;
+    if ((e = up((void**)&p.d_sinv, sinv.data(), sinv.size() * sizeof(int32_t))) != hipSuccess) return hip_err(e);
+  }
   if ((e = up((void**)&p.d_scol, scol.data(), scol.size() * sizeof(int32_t))) != hipSuccess) return hip_err(e);
   if ((e = up((void**)&p.d_swts, swts.data(), swts.size() * sizeof(float))) != hipSuccess) return hip_err(e);
   if ((e = up((void**)&p.d_sbase, sbase.data(), sbase.size() * sizeof(int2))) != hipSuccess) return hip_err(e);
@@ -784,6 +789,7 @@ void plan_release(Plan& p) {
   if (p.d_iphi) (void)hipFree(p.d_iphi);
   if (p.d_cptr) (void)hipFree(p.d_cptr);
   if (p.d_sperm) (void)hipFree(p.d_sperm);
+  if (p.d_sinv) (void)hipFree(p.d_sinv);
   if (p.d_scol) (void)hipFree(p.d_scol);
   if (p.d_swts) (void)hipFree(p.d_swts);
   if (p.d_sbase) (void)hipFree(p.d_sbase);
@@ -792,6 +798,7 @@ void plan_release(Plan& p) {
   p.d_iphi = nullptr;
   p.d_cptr = nullptr;
   p.d_sperm = nullptr;
+  p.d_sinv = nullptr;
   p.d_scol = nullptr;
   p.d_swts = nullptr;
   p.d_sbase = nullptr;
