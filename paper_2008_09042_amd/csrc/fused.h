@@ -51,7 +51,8 @@ struct LineArgs {
 bool fused_supported(int64_t n0, int64_t n1, int64_t n2, int64_t r0, int64_t r1, int precision);
 // Fragment-ordered copy (see tucker_fused.hip) of O(o, k) = src[o * so + k * sk], conjugated
 // if bit 0 of conj, times (-1)^o if bit 1, zero for o >= no or k >= nk, as an A (is_b = 0) or
-// B (is_b = 1) operand.
+// B (is_b = 1) operand; bit 2 stores k in the FP32 rank order of a K16 block (position
+// 4 g + t holds k = g + 4 t of the block; FP32 only).
 size_t frag_operand_bytes(int no, int nk, int is_b, int precision);
 hipError_t frag_operand_launch(const float2* src, int no, int nk, int64_t so, int64_t sk, int conj, int is_b,
                                int precision, void* dst, hipStream_t st);

@@ -134,6 +134,15 @@ struct Tile<0> {  // FP32; sub-step t uses k = 4 g + t (mma: four real products,
       c.p3 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[t].x + a.v[t].y, b.v[t].x + b.v[t].y, c.p3, 0, 0, 0);
     }
   }
+  // sub-steps 0 and 1 only (the caller knows the others hold zeros)
+  static __device__ __forceinline__ void mma_half(Acc& c, const A& a, const B& b) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      c.p1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[t].x, b.v[t].x, c.p1, 0, 0, 0);
+      c.p2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[t].y, b.v[t].y, c.p2, 0, 0, 0);
+      c.p3 = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[t].x + a.v[t].y, b.v[t].x + b.v[t].y, c.p3, 0, 0, 0);
+    }
+  }
   static __device__ __forceinline__ void finish(const Acc& c, f32x4& cr, f32x4& ci) {
     cr = c.p1 - c.p2;
     ci = c.p3 - c.p1 - c.p2;

@@ -568,10 +568,11 @@ maxwell_status plan_build(Plan& p, const maxwell_plan_desc& d, const maxwell_bas
     p.U0HF = q; q += bU0HF;
     p.U2F = q; q += bU2F;
     p.U2CF = q;
-    if ((e = frag_operand_launch(p.U[0], n0, r0, r0, 1, 0, 0, pr, const_cast<void*>(p.U0F), 0)) ||
-        (e = frag_operand_launch(p.U[1], n1, r1, r1, 1, 0, 1, pr, const_cast<void*>(p.U1TF), 0)) ||
-        (e = frag_operand_launch(p.U[0], n0, r0, r0, 1, 2, 0, pr, const_cast<void*>(p.U0SF), 0)) ||
-        (e = frag_operand_launch(p.U[1], n1, r1, r1, 1, 2, 1, pr, const_cast<void*>(p.U1TSF), 0)) ||
+    const int kp = pr == 0 ? 4 : 0;  // FP32: the rank order of the plane kernels' rank reductions
+    if ((e = frag_operand_launch(p.U[0], n0, r0, r0, 1, kp, 0, pr, const_cast<void*>(p.U0F), 0)) ||
+        (e = frag_operand_launch(p.U[1], n1, r1, r1, 1, kp, 1, pr, const_cast<void*>(p.U1TF), 0)) ||
+        (e = frag_operand_launch(p.U[0], n0, r0, r0, 1, 2 | kp, 0, pr, const_cast<void*>(p.U0SF), 0)) ||
+        (e = frag_operand_launch(p.U[1], n1, r1, r1, 1, 2 | kp, 1, pr, const_cast<void*>(p.U1TSF), 0)) ||
         (e = frag_operand_launch(p.U[1], r1, n1, 1, r1, 1, 1, pr, const_cast<void*>(p.U1CF), 0)) ||
         (e = frag_operand_launch(p.U[0], r0, n0, 1, r0, 1, 0, pr, const_cast<void*>(p.U0HF), 0)))
       return hip_err(e);

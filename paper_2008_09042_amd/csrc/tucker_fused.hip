@@ -67,6 +67,27 @@ struct Geo {
   }
 };
 
+// Rank order inside a K16 block of the FP32 rank reductions (V = W U1^T over r1, P = U0 V
+// over r0): position 4 g + t (lane group g, sub-step t) holds rank g + 4 t of the block, in
+// W, in the U0 / U1^T fragments and, through W's rows, in V.  A last block holding at most
+// 8 ranks then has its padding in sub-steps 2 and 3, which rank_mma skips when the kernel is
+// built for it (HALF: compile-time rank blocks, both ranks in (32, 40]).  The sum runs over
+// the same products; BF16-split plans keep the natural order (one K16 block is one MFMA).
+__host__ __device__ constexpr int kperm(int q) { return (q >> 2) | ((q & 3) << 2); }
+
+template <int PREC>
+__device__ __forceinline__ void rank_mma(typename Tile<PREC>::Acc& c, const typename Tile<PREC>::A& a,
+                                         const typename Tile<PREC>::B& b, bool half) {
+  if constexpr (PREC == 0) {
+    if (half)
+      Tile<0>::mma_half(c, a, b);
+    else
+      Tile<0>::mma(c, a, b);
+  } else {
+    Tile<PREC>::mma(c, a, b);
+  }
+}
+
 // The wave's share of the plane: column block cb and row blocks part, part + q, ...
 // (every (row block, column block) tile has exactly one owner).  A whole column block per
 // wave lets the wave form its P tiles from its own V tiles (V = W U1^T for that column
@@ -155,7 +176,7 @@ struct WSlots {
   unsigned p[4];  // entry (q, t) in bits 16 (t & 1) of p[2 q + t / 2]; 0xffff for padding
 };
 
-template <int N0, int N1, int RB>
+template <int PREC, int N0, int N1, int RB>
 __device__ __forceinline__ WSlots w_slots(const Geo<N0, N1, RB>& g, int tid) {
   WSlots w;
   const int nfl = g.r0b * g.r1b * 64;  // (o block, step, lane) entries
@@ -164,13 +185,14 @@ __device__ __forceinline__ WSlots w_slots(const Geo<N0, N1, RB>& g, int tid) {
     const int e = tid + q * PT;
     const int f = e / 64, lane = e % 64;
     const int mb = f / g.r1b, s = f % g.r1b;
-    const int p0 = 16 * mb + (lane & 15);
+    const int p0 = 16 * mb + (PREC == 0 ? kperm(lane & 15) : (lane & 15));
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       unsigned pk = 0;
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
-        const int p1 = 16 * s + 4 * (lane >> 4) + 2 * h + b;
+        const int q1 = 4 * (lane >> 4) + 2 * h + b;
+        const int p1 = 16 * s + (PREC == 0 ? kperm(q1) : q1);
         const unsigned o = (e < nfl && p0 < g.r0 && p1 < g.r1) ? (unsigned)(p0 * g.r1 + p1) : 0xffffu;
         pk |= o << (16 * b);
       }
@@ -214,7 +236,7 @@ __device__ __forceinline__ void w_store(const Geo<N0, N1, RB>& g, float2* lds, i
 
 // V[:, cb] = W U1^T[:, cb] (W staged) for the wave's column block, as the B operands (one
 // per K16 step over p0) of P = U0 V.  u1: this column block's U1^T fragments.
-template <int PREC, int N0, int N1, int RB>
+template <int PREC, bool HALF, int N0, int N1, int RB>
 __device__ __forceinline__ void coil_v(const Geo<N0, N1, RB>& g, const float2* lds, int lane,
                                        const typename Tile<PREC>::B (&u1)[3], typename Tile<PREC>::B (&vb)[3]) {
   typename Tile<PREC>::Acc c[3];
@@ -225,7 +247,8 @@ __device__ __forceinline__ void coil_v(const Geo<N0, N1, RB>& g, const float2* l
     if (s < g.r1b) {
 #pragma unroll
       for (int m = 0; m < 3; ++m)
-        if (m < g.r0b) Tile<PREC>::mma(c[m], frag_a<PREC>(lds + STAGE_OFF, g.r1b, m, s, lane), u1[s]);
+        if (m < g.r0b)
+          rank_mma<PREC>(c[m], frag_a<PREC>(lds + STAGE_OFF, g.r1b, m, s, lane), u1[s], HALF && s == g.r1b - 1);
     }
 #pragma unroll
   for (int m = 0; m < 3; ++m) {
@@ -237,7 +260,7 @@ __device__ __forceinline__ void coil_v(const Geo<N0, N1, RB>& g, const float2* l
 
 // P tiles of the wave's share: P[rb][cb] = sum_s U0[rb][s] V[s][cb], U0 staged in the
 // plane region, V in registers.
-template <int PREC, int N0, int N1, int RB>
+template <int PREC, bool HALF, int N0, int N1, int RB>
 __device__ __forceinline__ void coil_p(const Geo<N0, N1, RB>& g, const float2* lds, const Share& sh, int lane,
                                        const typename Tile<PREC>::B (&vb)[3], f32x4 (&pr)[8], f32x4 (&pi)[8]) {
 #pragma unroll
@@ -247,7 +270,7 @@ __device__ __forceinline__ void coil_p(const Geo<N0, N1, RB>& g, const float2* l
     if (sh.on && rb < g.n0b) {
 #pragma unroll
       for (int s = 0; s < 3; ++s)
-        if (s < g.r0b) Tile<PREC>::mma(c, frag_a<PREC>(lds, g.r0b, rb, s, lane), vb[s]);
+        if (s < g.r0b) rank_mma<PREC>(c, frag_a<PREC>(lds, g.r0b, rb, s, lane), vb[s], HALF && s == g.r0b - 1);
     }
     Tile<PREC>::finish(c, pr[i], pi[i]);
   }
@@ -366,7 +389,7 @@ __device__ __forceinline__ void adjoint_w(const PlaneArgs& a, const Geo<N0, N1, 
 // Per coil: W (and in the adjoint the coil's samples) loaded early; U0 (fragment order,
 // the whole factor) staged in the plane region and W in the stage region; V = W U1^T for
 // the wave's column block into registers, then the wave's P tiles.
-template <int PREC, int N0, int N1, int RB>
+template <int PREC, bool HALF, int N0, int N1, int RB>
 __device__ __forceinline__ void coil_map(const void* u0f, const void* u1tf, const Geo<N0, N1, RB>& g, float2* lds,
                                          const Share& sh, int lane, int tid, const WPrefetch& w, f32x4 (&pr)[8],
                                          f32x4 (&pi)[8]) {
@@ -384,12 +407,12 @@ __device__ __forceinline__ void coil_map(const void* u0f, const void* u1tf, cons
   w_store<PREC>(g, lds, tid, w);
   __syncthreads();
   typename Tile<PREC>::B vb[3];
-  coil_v<PREC>(g, lds, lane, u1, vb);
-  coil_p<PREC>(g, lds, sh, lane, vb, pr, pi);
+  coil_v<PREC, HALF>(g, lds, lane, u1, vb);
+  coil_p<PREC, HALF>(g, lds, sh, lane, vb, pr, pi);
   __syncthreads();  // U0 is consumed; the plane region is free
 }
 
-template <int PREC, int N0, int N1, int RB>
+template <int PREC, int N0, int N1, int RB, bool HALF = false>
 __global__ __launch_bounds__(PT) void plane_fwd_kernel(PlaneArgs a) {
   __shared__ float2 lds[LDS_ELEMS];
   const Geo<N0, N1, RB> g(a);
@@ -403,7 +426,7 @@ __global__ __launch_bounds__(PT) void plane_fwd_kernel(PlaneArgs a) {
   for (int k = 0; k < SCAT; ++k) pq[k] = (int)threadIdx.x + k * PT < a.L ? a.pos[threadIdx.x + k * PT] : -1;
   load_twiddles(a, g, lds);
   const int j0 = gi * a.G, j1 = min(a.J, (gi + 1) * a.G);
-  const WSlots wsl = w_slots(g, (int)threadIdx.x);
+  const WSlots wsl = w_slots<PREC>(g, (int)threadIdx.x);
   WPrefetch w;  // W of the next coil, loaded one coil ahead
   if (j0 < j1) w_load(a, g, j0, i2, wsl, w);
   // the x values of the wave's share, the same for every coil: loaded once
@@ -424,7 +447,7 @@ __global__ __launch_bounds__(PT) void plane_fwd_kernel(PlaneArgs a) {
     asm volatile("" : "+v"(tid));
     const int lane = tid & 63, grp = lane >> 4;
     f32x4 pr[8], pi[8];
-    coil_map<PREC>(a.U0F, a.U1TF, g, lds, sh, lane, tid, w, pr, pi);
+    coil_map<PREC, HALF>(a.U0F, a.U1TF, g, lds, sh, lane, tid, w, pr, pi);
     if (j + 1 < j1) w_load(a, g, j + 1, i2, wsl, w);
     // m = x (.) P; the input chessboard sign of the centred DFT is carried by xt
     if (sh.on) {
@@ -521,9 +544,9 @@ __global__ __launch_bounds__(PT) void plane_adj_kernel(PlaneArgs a) {
     f32x4 pr[8], pi[8];
     if (want_gx) {
       WPrefetch w;
-      w_load(a, g, j, i2, w_slots(g, tid), w);  // offsets recomputed: no registers held across coils
+      w_load(a, g, j, i2, w_slots<PREC>(g, tid), w);  // offsets recomputed: no registers held across coils
       // B c recomputed, with U0 and U1 carrying the output chessboard sign: P' = s P
-      coil_map<PREC>(a.U0SF, a.U1TSF, g, lds, sh, lane, tid, w, pr, pi);
+      coil_map<PREC, false>(a.U0SF, a.U1TSF, g, lds, sh, lane, tid, w, pr, pi);
     }
     // zero-filled scatter (with the chessboard sign)
     {  // 16-byte stores (the plane region starts the 16-byte aligned LDS array); n0 PS is even
@@ -614,7 +637,7 @@ __global__ __launch_bounds__(PT) void plane_adj_kernel(PlaneArgs a) {
   }
 }
 
-template <int PREC, int N0, int N1, int RB, bool FULL = false>
+template <int PREC, int N0, int N1, int RB, bool FULL = false, bool HALF = false>
 __global__ __launch_bounds__(PT) void plane_adj_late_kernel(PlaneArgs a) {
   __shared__ __align__(16) float2 lds[LDS_ELEMS];
   const Geo<N0, N1, RB> g(a);
@@ -646,7 +669,7 @@ __global__ __launch_bounds__(PT) void plane_adj_late_kernel(PlaneArgs a) {
     }
     if (want_gx) {
       WPrefetch w;
-      w_load(a, g, j, i2, w_slots(g, tid), w);  // offsets recomputed: no registers held across coils
+      w_load(a, g, j, i2, w_slots<PREC>(g, tid), w);  // offsets recomputed: no registers held across coils
       w_store<PREC>(g, lds, tid, w);              // the stage region is free (previous coil done)
     }
     // zero-filled scatter (with the chessboard sign)
@@ -694,7 +717,9 @@ __global__ __launch_bounds__(PT) void plane_adj_late_kernel(PlaneArgs a) {
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int mb = 0; mb < 3; ++mb)
-              if (mb < g.r0b) Tile<PREC>::mma(cv[mb], frag_a<PREC>(lds + STAGE_OFF, g.r1b, mb, s, lane), u1[s & 1]);
+              if (mb < g.r0b)
+                rank_mma<PREC>(cv[mb], frag_a<PREC>(lds + STAGE_OFF, g.r1b, mb, s, lane), u1[s & 1],
+                               HALF && s == g.r1b - 1);
           }
         if (g.r1b < 2)
 #pragma unroll
@@ -723,7 +748,7 @@ __global__ __launch_bounds__(PT) void plane_adj_late_kernel(PlaneArgs a) {
             for (int s = 0; s < 3; ++s) {
               adj_map_load(a, g, sh, lane, m, 3 * i + s + 3);
               __builtin_amdgcn_sched_barrier(0);
-              if (s < g.r0b) Tile<PREC>::mma(c, m.ring[(3 * i + s) & 3], m.vb[s]);
+              if (s < g.r0b) rank_mma<PREC>(c, m.ring[(3 * i + s) & 3], m.vb[s], HALF && s == g.r0b - 1);
             }
             f32x4 pr, pi;
             Tile<PREC>::finish(c, pr, pi);
@@ -772,7 +797,7 @@ __global__ void frag_operand_kernel(const float2* __restrict__ src, int no, int 
     float2 v[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      const int k = 16 * s + 4 * (lane >> 4) + t;
+      const int k = 16 * s + ((conj & 4) ? kperm(4 * (lane >> 4) + t) : 4 * (lane >> 4) + t);
       v[t] = (o < no && k < nk) ? src[(int64_t)o * so + (int64_t)k * sk] : make_float2(0.f, 0.f);
       if (conj & 1) v[t].y = -v[t].y;
       if ((conj & 2) && (o & 1)) v[t] = make_float2(-v[t].x, -v[t].y);
@@ -958,7 +983,11 @@ void adj_launch(dim3 grid, dim3 block, const PlaneArgs& a, hipStream_t st) {
   // with both outputs wanted (the gradient step) the output checks are compile-time too
   const bool full = a.gxpart != nullptr && a.T3b != nullptr;
   if constexpr (PREC == 0) {
-    if (rb3 && full) hipLaunchKernelGGL((plane_adj_late_kernel<PREC, N0, N1, RB3, true>), grid, block, 0, st, a);
+    // ranks in (32, 40]: the last rank block's padding skipped at compile time
+    const bool half = a.r0 <= 40 && a.r1 <= 40;
+    if (rb3 && full && half)
+      hipLaunchKernelGGL((plane_adj_late_kernel<PREC, N0, N1, RB3, true, true>), grid, block, 0, st, a);
+    else if (rb3 && full) hipLaunchKernelGGL((plane_adj_late_kernel<PREC, N0, N1, RB3, true>), grid, block, 0, st, a);
     else if (rb3) hipLaunchKernelGGL((plane_adj_late_kernel<PREC, N0, N1, RB3>), grid, block, 0, st, a);
     else hipLaunchKernelGGL((plane_adj_late_kernel<PREC, N0, N1, 0>), grid, block, 0, st, a);
   } else {
@@ -975,7 +1004,10 @@ hipError_t plane_launch_prec(const PlaneArgs& a, bool adj, hipStream_t st) {
   // ranks in (32, 48] (three K16 blocks each) take compile-time rank blocks at 128 x 128
   const bool rb3 = a.r0p == 48 && a.r1p == 48;
   if (a.n0 == 128 && a.n1 == 128 && rb3 && !adj) {
-    hipLaunchKernelGGL((plane_fwd_kernel<PREC, 128, 128, 3>), grid, block, 0, st, a);
+    if (PREC == 0 && a.r0 <= 40 && a.r1 <= 40)  // FP32 ranks in (32, 40]: padding skipped
+      hipLaunchKernelGGL((plane_fwd_kernel<PREC, 128, 128, 3, PREC == 0>), grid, block, 0, st, a);
+    else
+      hipLaunchKernelGGL((plane_fwd_kernel<PREC, 128, 128, 3>), grid, block, 0, st, a);
   } else if (a.n0 == 128 && a.n1 == 128) {
     if (adj) adj_launch<PREC, 128, 128>(grid, block, a, st);
     else hipLaunchKernelGGL((plane_fwd_kernel<PREC, 128, 128, 0>), grid, block, 0, st, a);
