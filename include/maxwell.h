@@ -192,7 +192,11 @@ maxwell_status maxwell_forward_loss(maxwell_plan_t plan, const maxwell_complex64
  * for the weighted residual r = w (.) (E - y).  On the fused 3D Cartesian path
  * (maxwell_plan_path() == "fused-tucker-lines", whose readout axis is fully sampled) t is
  * r already taken back along the readout, the first factor of F_s^H in Eq. (5)'s adjoint,
- * computed while each line is on chip; on every other path t is r itself.            */
+ * computed while each line is on chip.  On the gridding (non-Cartesian) path, when J is a
+ * multiple of the gridding's coil group (8 for J >= 8, 4 for 3 <= J < 8, any J <= 2), t
+ * holds r in the gridding's sample order, coils innermost (t[s J + j] = r[j][m] for the
+ * sample m at position s of the plan's sort by grid cell), so that the adjoint reads it
+ * without a reordering pass.  On every other path t is r itself.                    */
 maxwell_status maxwell_forward_transfer(maxwell_plan_t plan, const maxwell_complex64* x,
                                         const maxwell_complex64* c, const maxwell_complex64* y,
                                         maxwell_complex64* t, double* loss_dev, void* ws,

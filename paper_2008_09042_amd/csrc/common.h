@@ -115,6 +115,10 @@ hipError_t scatter_launch(const float2* y, int64_t M, const int32_t* inv_mask, i
 int residual_blocks(int64_t total);
 hipError_t residual_launch(const float2* E, const float2* y, const float* w, int64_t M, int J,
                            float2* r, double* part, hipStream_t st);
+// The same residual at r[inv[m] J + j] (r must not alias E or y), with the same loss partials
+// (residual_blocks(M J) of them).
+hipError_t residual_ordered_launch(const float2* E, const float2* y, const float* w, int64_t M, int J,
+                                   const int32_t* inv, float2* r, double* part, hipStream_t st);
 hipError_t reduce_loss_launch(const double* part, int nblocks, double* loss, hipStream_t st);
 // gx[n] = s sum_j conj(S[j][n]) g[j][n] ; g[j][n] <- s conj(x[n]) g[j][n] (when h_inplace)
 hipError_t adjoint_combine_launch(const float2* S, float2* g, const float2* x, int64_t N, int J,

@@ -122,6 +122,60 @@ hipError_t residual_launch(const float2* E, const float2* y, const float* w, int
   return hipGetLastError();
 }
 
+// The residual of residual_kernel written in a sample order: r[inv[m] J + j].  A thread per
+// sample reads its coils down the columns of E and y (coalesced over m across a wave), eight
+// at a time, and writes its J values as one contiguous run, 16 bytes at a time when J is
+// even.  The loss partials are the same sums, per thread in (m, j) order.
+__global__ void residual_ordered_kernel(const float2* __restrict__ E, const float2* __restrict__ y,
+                                        const float* __restrict__ w, int64_t M, int J,
+                                        const int32_t* __restrict__ inv, float2* __restrict__ r,
+                                        double* __restrict__ part) {
+  __shared__ double red[NT];
+  double acc = 0.0;
+  for (int64_t m = blockIdx.x * (int64_t)NT + threadIdx.x; m < M; m += (int64_t)gridDim.x * NT) {
+    const float wm = w ? w[m] : 1.0f;
+    float2* dst = r + (int64_t)inv[m] * J;
+    for (int j0 = 0; j0 < J; j0 += 8) {  // eight coils' loads in flight together
+      float2 e[8], v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int j = min(j0 + u, J - 1);
+        e[u] = E[(int64_t)j * M + m];
+        v[u] = y[(int64_t)j * M + m];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const float2 d = csub(e[u], v[u]);
+        if (j0 + u < J) acc += (double)wm * ((double)d.x * d.x + (double)d.y * d.y);
+        e[u] = cscale(d, wm);
+      }
+      if ((J & 1) == 0) {
+#pragma unroll
+        for (int u = 0; u < 8; u += 2)
+          if (j0 + u < J) reinterpret_cast<float4*>(dst + j0)[u / 2] = make_float4(e[u].x, e[u].y, e[u + 1].x, e[u + 1].y);
+      } else {
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (j0 + u < J) dst[j0 + u] = e[u];
+      }
+    }
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+hipError_t residual_ordered_launch(const float2* E, const float2* y, const float* w, int64_t M, int J,
+                                   const int32_t* inv, float2* r, double* part, hipStream_t st) {
+  hipLaunchKernelGGL(residual_ordered_kernel, dim3(residual_blocks(M * J)), dim3(NT), 0, st, E, y, w, M, J, inv, r,
+                     part);
+  return hipGetLastError();
+}
+
 hipError_t reduce_loss_launch(const double* part, int nblocks, double* loss, hipStream_t st) {
   hipLaunchKernelGGL(reduce_loss_kernel, dim3(1), dim3(NT), 0, st, part, nblocks, loss);
   return hipGetLastError();

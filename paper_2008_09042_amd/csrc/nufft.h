@@ -49,7 +49,9 @@ hipError_t pad_deapod_launch(const NufftArgs& a, const float2* S, const float2* 
 hipError_t crop_deapod_launch(const NufftArgs& a, const float2* grid, float2* out, hipStream_t st);
 hipError_t degrid_launch(const NufftArgs& a, const float2* grid, float2* y, hipStream_t st);
 // grid = alpha * (*scale_dev) * spread(y); ys is a staging buffer of spread_stage_bytes(J, M).
+// With `staged`, y is already in the staging layout (sorted samples, coils innermost, J a
+// multiple of the coil group: ys[s][j] = y[j][perm[s]]) and ys is not used.
 hipError_t spread_launch(const NufftArgs& a, const float2* y, float alpha, const float* scale_dev, float2* ys,
-                         float2* grid, hipStream_t st);
+                         float2* grid, hipStream_t st, bool staged = false);
 
 }  // namespace mx

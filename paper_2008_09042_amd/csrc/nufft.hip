@@ -766,11 +766,14 @@ hipError_t degrid_launch(const NufftArgs& a, const float2* grid, float2* y, hipS
 }
 
 hipError_t spread_launch(const NufftArgs& a, const float2* y, float alpha, const float* scale_dev, float2* ys,
-                         float2* grid, hipStream_t st) {
+                         float2* grid, hipStream_t st, bool staged) {
   const int jg = spread_group(a.J);
   const int Jp = (a.J + jg - 1) / jg * jg;
   if (a.W < 1 || a.W > 8) return hipErrorInvalidValue;
-  if (a.M > 0)
+  if (staged) {
+    if (Jp != a.J) return hipErrorInvalidValue;
+    ys = const_cast<float2*>(y);  // read only
+  } else if (a.M > 0)
     hipLaunchKernelGGL(spread_stage_kernel, dim3((unsigned)((a.M + NT - 1) / NT)), dim3(NT), 0, st, a, y, Jp, ys);
   // the plain kernel from memory takes 16 coils per lane where the padded coil count allows
   // (one walk of a sample sequence serves twice the coils; 150 vs 156 us at 32 coils, 128

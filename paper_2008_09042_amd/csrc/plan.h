@@ -78,6 +78,7 @@ struct Plan {
   int n_heavy = 0, n_med = 0;
   int split_pm = 4, split_ph = 16;  // column parts of the split spread rows
   bool spread_lds = true;     // plain spread blocks through LDS ($MAXWELL_SPREAD_LDS=0: from memory)
+  bool ordered_transfer = false;  // gridding path: the transfer residual in the spread's sample order
   float2* d_twg[2] = {nullptr, nullptr};  // grid twiddles
   int nradg[2] = {0, 0};
   int radixg[2][12];

@@ -421,6 +421,8 @@ static maxwell_status nufft_build(Plan& p, const maxwell_plan_desc& d) {
   if (const char* env = std::getenv("MAXWELL_SPREAD_LDS")) p.spread_lds = std::atoi(env) != 0;
   p.split_pm = SPREAD_SPLIT_PM;
   p.split_ph = SPREAD_SPLIT_PH;
+  // coil groups that fill J: the spread reads a residual written in its sample order as is
+  p.ordered_transfer = p.J % spread_group(p.J) == 0;
   if (const char* env = std::getenv("MAXWELL_SPREAD_SPLIT_PARTS")) {
     int pm = 0, ph = 0;
     auto pow2 = [](int v) { return v >= 1 && v <= 64 && (v & (v - 1)) == 0; };
@@ -1047,7 +1049,14 @@ hipError_t run_forward_loss(const Plan& p, const float2* x, const float2* c, con
   }
   float2* E = wsp<float2>(ws, p.off_E);
   if ((e = run_encode(p, x, c, E, ws, st)) != hipSuccess) return e;
-  if ((e = TIMED("residual", residual_launch(E, y, p.d_w, p.M, p.J, r, part, st))) != hipSuccess) return e;
+  if (transfer && r && p.sampling == MAXWELL_NONCARTESIAN && p.ordered_transfer) {
+    // the transfer layout of the gridding path: the residual in the spread's sample order
+    const int32_t* inv = p.d_sinv;
+    if ((e = TIMED("residual", residual_ordered_launch(E, y, p.d_w, p.M, p.J, inv, r, part, st))) != hipSuccess)
+      return e;
+  } else if ((e = TIMED("residual", residual_launch(E, y, p.d_w, p.M, p.J, r, part, st))) != hipSuccess) {
+    return e;
+  }
   if (loss) return TIMED("reduce_loss", reduce_loss_launch(part, residual_blocks((int64_t)p.J * p.M), loss, st));
   return hipSuccess;
 }
@@ -1056,13 +1065,16 @@ hipError_t run_forward_loss(const Plan& p, const float2* x, const float2* c, con
 // (*scale_dev); with want_h the K region of the workspace is left holding
 // h_j = s conj(x) (.) F_s^H y_j, the input of the basis adjoint.
 static hipError_t adjoint_maps(const Plan& p, const float2* S, const float2* x, const float2* y, float alpha,
-                               const float* scale_dev, float2* gx, bool want_h, void* ws, hipStream_t st) {
+                               const float* scale_dev, float2* gx, bool want_h, void* ws, hipStream_t st,
+                               bool ordered = false) {
   float2* Kb = wsp<float2>(ws, p.off_K);
   hipError_t e;
   if (p.sampling == MAXWELL_NONCARTESIAN) {
     const NufftArgs na = nufft_args(p);
     float2* G = wsp<float2>(ws, p.off_G);
-    if ((e = TIMED("nufft_spread", spread_launch(na, y, alpha, scale_dev, wsp<float2>(ws, p.off_Ys), G, st))) !=
+    // `ordered`: y is a residual written in the spread's sample order (no staging pass)
+    if ((e = TIMED("nufft_spread", spread_launch(na, y, alpha, scale_dev, wsp<float2>(ws, p.off_Ys), G, st,
+                                                 ordered))) !=
         hipSuccess)
       return e;
     if ((e = fft_grid(p, G, +1, st)) != hipSuccess) return e;
@@ -1092,7 +1104,8 @@ hipError_t run_adjoint(const Plan& p, const float2* x, const float2* c, const fl
   if (gx && !maps_ready) {
     if ((e = run_basis_apply(p, c, S, ws, st)) != hipSuccess) return e;
   }
-  if ((e = adjoint_maps(p, S, x, y, alpha, scale_dev, gx, gc != nullptr, ws, st)) != hipSuccess) return e;
+  const bool ordered = transfer && p.sampling == MAXWELL_NONCARTESIAN && p.ordered_transfer;
+  if ((e = adjoint_maps(p, S, x, y, alpha, scale_dev, gx, gc != nullptr, ws, st, ordered)) != hipSuccess) return e;
   if (gc) return run_basis_adjoint(p, Kb, gc, 1.0f, nullptr, ws, st);
   return hipSuccess;
 }
@@ -1101,8 +1114,12 @@ hipError_t run_grad(const Plan& p, const float2* x, const float2* c, const float
                     double* loss, void* ws, hipStream_t st) {
   const bool want = gx || gc;
   // the residual in the transfer layout; on the fused path in place of the plane output
-  // (each line workgroup reads its lines before writing them)
-  float2* r = !want ? nullptr : p.fused ? wsp<float2>(ws, p.off_Z) : wsp<float2>(ws, p.off_E);
+  // (each line workgroup reads its lines before writing them); on the gridding path in the
+  // spread's sample order, in its staging region (a permuted write cannot be in place)
+  float2* r = !want                ? nullptr
+              : p.fused            ? wsp<float2>(ws, p.off_Z)
+              : p.sampling == MAXWELL_NONCARTESIAN && p.ordered_transfer ? wsp<float2>(ws, p.off_Ys)
+                                   : wsp<float2>(ws, p.off_E);
   hipError_t e = run_forward_loss(p, x, c, y, r, loss, ws, st, true);
   if (e != hipSuccess) return e;
   if (!want) return hipSuccess;
