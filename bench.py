@@ -93,7 +93,7 @@ KERNEL_SOURCES = {  # sources whose change invalidates a recorded traffic figure
     "plane_adj": ["tucker_fused.hip", "fused.h", "fft_device.h", "mfma_frag.h"],
     "plane_fwd": ["tucker_fused.hip", "fused.h", "fft_device.h", "mfma_frag.h"],
 }
-KERNEL_SYMBOLS = {"plane_adj": "plane_adj_kernel<1, 128, 128, 3, true>", "plane_fwd": "plane_fwd_kernel<1, 128, 128, 3>"}
+KERNEL_SYMBOLS = {"plane_adj": "plane_adj_kernel<1, 128, 128, 3, true>", "plane_fwd": "plane_fwd_kernel<1, 128, 128, 3, false>"}
 
 
 def source_hash(kernel):

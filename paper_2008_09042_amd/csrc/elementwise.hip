@@ -99,29 +99,6 @@ __global__ void scale_copy_kernel(const float2* __restrict__ src, float2* __rest
     dst[e] = cscale(src[e], s);
 }
 
-}  // namespace
-
-hipError_t gather_launch(const float2* kspace, int64_t N, const int32_t* idx, int64_t M, int J,
-                         float2* y, hipStream_t st) {
-  if (M * J == 0) return hipSuccess;
-  hipLaunchKernelGGL(gather_kernel, dim3(grid_for(M * J)), dim3(NT), 0, st, kspace, N, idx, M, J, y);
-  return hipGetLastError();
-}
-
-hipError_t scatter_launch(const float2* y, int64_t M, const int32_t* inv_mask, int64_t N, int J,
-                          float2* kspace, hipStream_t st) {
-  hipLaunchKernelGGL(scatter_kernel, dim3(grid_for(N * J)), dim3(NT), 0, st, y, M, inv_mask, N, J, kspace);
-  return hipGetLastError();
-}
-
-int residual_blocks(int64_t total) { return (int)grid_for(total, 2048); }
-
-hipError_t residual_launch(const float2* E, const float2* y, const float* w, int64_t M, int J,
-                           float2* r, double* part, hipStream_t st) {
-  hipLaunchKernelGGL(residual_kernel, dim3(residual_blocks(M * J)), dim3(NT), 0, st, E, y, w, M, J, r, part);
-  return hipGetLastError();
-}
-
 // The residual of residual_kernel written in a sample order: r[inv[m] J + j].  A thread per
 // sample reads its coils down the columns of E and y (coalesced over m across a wave), eight
 // at a time, and writes its J values as one contiguous run, 16 bytes at a time when J is
@@ -167,6 +144,29 @@ __global__ void residual_ordered_kernel(const float2* __restrict__ E, const floa
     __syncthreads();
   }
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+}  // namespace
+
+hipError_t gather_launch(const float2* kspace, int64_t N, const int32_t* idx, int64_t M, int J,
+                         float2* y, hipStream_t st) {
+  if (M * J == 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_kernel, dim3(grid_for(M * J)), dim3(NT), 0, st, kspace, N, idx, M, J, y);
+  return hipGetLastError();
+}
+
+hipError_t scatter_launch(const float2* y, int64_t M, const int32_t* inv_mask, int64_t N, int J,
+                          float2* kspace, hipStream_t st) {
+  hipLaunchKernelGGL(scatter_kernel, dim3(grid_for(N * J)), dim3(NT), 0, st, y, M, inv_mask, N, J, kspace);
+  return hipGetLastError();
+}
+
+int residual_blocks(int64_t total) { return (int)grid_for(total, 2048); }
+
+hipError_t residual_launch(const float2* E, const float2* y, const float* w, int64_t M, int J,
+                           float2* r, double* part, hipStream_t st) {
+  hipLaunchKernelGGL(residual_kernel, dim3(residual_blocks(M * J)), dim3(NT), 0, st, E, y, w, M, J, r, part);
+  return hipGetLastError();
 }
 
 hipError_t residual_ordered_launch(const float2* E, const float2* y, const float* w, int64_t M, int J,
