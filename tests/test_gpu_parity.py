@@ -65,6 +65,12 @@ CASES = {
     # 12 coils: one full and one padded group of 8 in the spread
     "radial_64x48_J12_K7_16spokes": dict(seed=116, dims=(64, 48), J=12, K=7, mask="radial", spokes=16,
                                          n_read=128, weights=True),
+    # coil groups that fill J: the gradient's residual is handed to the spread in its sample
+    # order (J = 1: scalar writes, one coil per lane; J = 8: one full group, 16-byte writes)
+    "radial_48x40_J1_K5_9spokes": dict(seed=123, dims=(48, 40), J=1, K=5, mask="radial", spokes=9,
+                                       n_read=96, weights=True),
+    "radial_64x64_J8_K6_12spokes": dict(seed=124, dims=(64, 64), J=8, K=6, mask="radial", spokes=12,
+                                        n_read=128),
 }
 FUSED = {"tucker3d_32x32x32_r12_K70_J4", "fused_48x32x20_r9x13x5_K23_J5", "fused_16x80x12_r3x17x4_K11_J3",
          "fused_128x128x64_r40_K60_J5", "fused_64x64x32_r20_K30_J3", "fused_32x32x16_r9x10x11_K150_J64",
