@@ -532,7 +532,6 @@ def bench_kernels2d(args, torch, names=("cart2d_256_dense200_j32", "radial2d_256
             G = (2 * p.dims[0]) * (2 * p.dims[1]) if p.traj is not None else 0
             gemm_flops = 8.0 * J * N * K
             gemm_bytes = 8.0 * (N * K + J * K + J * N)
-            fft_n = G if G else N
             work = {
                 "gemm_dense_apply": ("mfma", gemm_flops, PEAKS_TFLOPS["bf16" if prec == "bf16_split" else "fp32"],
                                      gemm_bytes),
@@ -541,15 +540,16 @@ def bench_kernels2d(args, torch, names=("cart2d_256_dense200_j32", "radial2d_256
                 # Cartesian: the mask is applied in the last forward and the first inverse
                 # pass (8 B per element in, 8 B per sample and 4 B of inverse mask per point
                 # out, and the reverse), so the four passes move 48 J N + 16 J M + 8 N bytes
-                "fft_axis": ("hbm", 16.0 * J * fft_n if G else (48.0 * J * N + 16.0 * J * M + 8.0 * N) / 4, None,
-                             None),
+                # gridding: the zero-pad and deapodisation are applied in the first forward pass
+                # (8 B per image element and coil in, the padded rows out) and the crop in the
+                # last inverse pass (only the g0 x n1 columns of the window read, the n0 x n1
+                # window out), so the four passes move 8 J (N + 5 G + g0 n1 + N) + 8 N bytes
+                "fft_axis": ("hbm", (8.0 * J * (2 * N + 5 * G + 2 * p.dims[0] * p.dims[1]) + 8.0 * N) / 4 if G
+                             else (48.0 * J * N + 16.0 * J * M + 8.0 * N) / 4, None, None),
                 "gather": ("hbm", 8.0 * J * M * 2 + 4.0 * M, None, None),
                 "scatter": ("hbm", 8.0 * J * (M + N) + 4.0 * N, None, None),
                 "nufft_degrid": ("hbm", 8.0 * J * (G + M) + M * (8.0 + 48.0), None, None),
                 "nufft_spread": ("hbm", 8.0 * J * (G + 2 * M) + M * (64.0 + 8.0) + 4.0 * G, None, None),
-                "nufft_pad": ("hbm", 8.0 * J * (N + G) + 8.0 * N, None, None),
-                # the crop reads the central n0 x n1 window of each coil's grid, not the grid
-                "nufft_crop": ("hbm", 16.0 * J * N, None, None),
                 "adjoint_combine": ("hbm", 8.0 * (3 * J * N + 2 * N), None, None),
                 "residual": ("hbm", 8.0 * J * M * 3 + 4.0 * M, None, None),
             }

@@ -32,7 +32,8 @@ constexpr int TW_LDS_MAX = 1024;    // twiddle tables up to this length are stag
 // complex elements of the LDS tile for T lines of length n
 __host__ __device__ inline int tile_elems(int n, int T, bool contiguous) { return contiguous ? T * (n + 1) : T * n; }
 
-// TWL: the twiddle table is copied into LDS behind the tile.  SMP: 1 the input comes from
+// TWL: the twiddle table is copied into LDS behind the tile.  SMP: 4 the input is the gridding
+// window (zero-pad), 5 the output is cropped to it (see FftAxisArgs); 1 the input comes from
 // the samples through the inverse mask, 2 the output goes to them.  bid / nbl: this
 // workgroup's index among the nbl workgroups of the pass.
 template <bool TWL, int SMP>
@@ -68,6 +69,12 @@ __device__ __forceinline__ void fft_axis_body(const FftAxisArgs& a, int64_t bid_
     t0 = (bid % chunks) * tg.T;
     Tvalid = (int)((a.inner - t0) < tg.T ? (a.inner - t0) : tg.T);
   }
+  if constexpr (SMP == 5) {
+    // cropping pass (strided lines = grid columns t0 .. t0 + Tvalid - 1): a tile wholly
+    // outside the window's columns has nothing to write (uniform per workgroup, before any
+    // barrier)
+    if (t0 + Tvalid <= a.woff1 || t0 >= a.woff1 + a.wn1) return;
+  }
   const int total = tg.T * n;
   // element e of the tile: (line, index) = (e / n, e % n) for contiguous lines, else
   // (e % T, e / T), so that consecutive threads touch consecutive addresses
@@ -78,6 +85,15 @@ __device__ __forceinline__ void fft_axis_body(const FftAxisArgs& a, int64_t bid_
   // (an element past the tile reads the tile's first element and is masked to zero)
   constexpr int LU = 8;
   const int64_t gbase = a.inner == 1 ? o0 * a.n * a.inner : o0 * a.n * a.inner + t0;
+  // pad mode: coil and row of the tile's first line, once per workgroup (a tile no taller
+  // than a coil's grid spans at most two coils)
+  int64_t pj0 = 0, pga0 = 0;
+  bool ptall = false;
+  if constexpr (SMP == 4) {
+    pj0 = o0 / a.outer_per_coil;
+    pga0 = o0 - pj0 * a.outer_per_coil;
+    ptall = tg.T > a.outer_per_coil;
+  }
   if constexpr (SMP == 3) {
     // whole lines l0 .. l0 + T - 1 of coil j (contiguous axis): zero the tile, then put the
     // tile's samples, one contiguous range of the sorted mask, at their points
@@ -118,10 +134,30 @@ __device__ __forceinline__ void fft_axis_body(const FftAxisArgs& a, int64_t bid_
         const int m = a.in_inv[pp];
         v[u] = a.in_samples[(int64_t)j * a.nsamples + (m >= 0 ? m : 0)];
         if (m < 0) keep[u] = 0u;
+      } else if constexpr (SMP == 4) {
+        // zero-padded, deapodised grid row ga of coil j (contiguous lines): the window's
+        // points read S x / (Phi0 Phi1), the rest are zero (loads clamped into the window)
+        int64_t j = pj0, ga = pga0 + (ok ? l : 0);  // the tile's lines are consecutive
+        if (ptall) {
+          const int64_t o = o0 + (ok ? l : 0);
+          j = o / a.outer_per_coil;
+          ga = o - j * a.outer_per_coil;
+        } else if (ga >= a.outer_per_coil) {
+          ga -= a.outer_per_coil;
+          ++j;
+        }
+        const int r0 = (int)ga - a.woff0, r1 = i - a.woff1;
+        const bool in = r0 >= 0 && r0 < a.wn0 && r1 >= 0 && r1 < a.wn1;
+        const int c0 = min(max(r0, 0), a.wn0 - 1), c1 = min(max(r1, 0), a.wn1 - 1);
+        const int64_t r = (int64_t)c0 * a.wn1 + c1;
+        const float2 sv = a.src[j * (int64_t)a.wn0 * a.wn1 + r], xv = a.premul[r];
+        const float w = a.iphi[c0] * a.iphi[a.wn0 + c1];
+        v[u] = cscale(cmul(sv, xv), w);
+        if (!in) keep[u] = 0u;
       } else {
         v[u] = a.src[gidx];
       }
-      if (a.premul) {
+      if (SMP != 4 && a.premul) {
         const int64_t o = a.inner == 1 ? o0 + (ok ? l : 0) : o0;
         const int64_t oc = a.outer < 0x7fffffffLL ? (int64_t)((uint32_t)o % (uint32_t)a.outer_per_coil)
                                                   : o % a.outer_per_coil;
@@ -133,7 +169,7 @@ __device__ __forceinline__ void fft_axis_body(const FftAxisArgs& a, int64_t bid_
     for (int u = 0; u < LU; ++u) {
       if (li[u] < 0) continue;
       float2 x = v[u];
-      if (a.premul) x = cmul(x, pm[u]);
+      if (SMP != 4 && a.premul) x = cmul(x, pm[u]);
       // odd i: negate (flip the sign bit); invalid: zero (clear every bit)
       const uint32_t flip = keep[u] == 0xffffffffu ? 0x80000000u : 0u;
       const uint32_t mask = keep[u] ? 0xffffffffu : 0u;
@@ -169,6 +205,11 @@ __device__ __forceinline__ void fft_axis_body(const FftAxisArgs& a, int64_t bid_
         const uint32_t f = (uint32_t)gidx, j = fdiv(f, fN), pp = f - j * (uint32_t)fN.d;
         const int m = a.out_inv[pp];
         if (m >= 0) a.out_samples[(int64_t)j * a.nsamples + m] = cscale(v[u], s);
+      } else if constexpr (SMP == 5) {
+        // only the window: row i, column t0 + l of coil o0, deapodised
+        const int r0 = i - a.woff0, r1 = (int)(t0 + l) - a.woff1;
+        if (r0 >= 0 && r0 < a.wn0 && r1 >= 0 && r1 < a.wn1)
+          a.crop_out[(o0 * a.wn0 + r0) * (int64_t)a.wn1 + r1] = cscale(v[u], s * a.iphi[r0] * a.iphi[a.wn0 + r1]);
       } else {
         a.data[gidx] = cscale(v[u], s);
       }
@@ -233,6 +274,12 @@ hipError_t fft_axis_prepare(const FftAxisArgs& args, FftLaunch& out) {
   const int64_t blocks = contiguous ? (a.outer + T - 1) / T : a.outer * ((a.inner + T - 1) / T);
   const size_t lds = (size_t)(tile_elems(n, a.lines, contiguous) + (twl ? n : 0)) * sizeof(float2);
   int smp = a.in_inv ? 1 : a.out_inv ? 2 : 0;
+  if (a.pad || a.crop_out) {  // the gridding window: pad on a first row pass, crop on a last column pass
+    if (smp || (a.pad && a.crop_out) || !a.iphi || a.wn0 < 1 || a.wn1 < 1) return hipErrorInvalidValue;
+    if (a.pad && (!contiguous || !a.src || !a.premul)) return hipErrorInvalidValue;
+    if (a.crop_out && contiguous) return hipErrorInvalidValue;
+    smp = a.pad ? 4 : 5;
+  }
   // the reading pass places whole lines' samples directly when every tile holds lines of
   // one coil only
   if (smp == 1 && contiguous && a.in_mask && a.in_lptr && a.outer_per_coil % T == 0) smp = 3;
@@ -275,6 +322,10 @@ hipError_t fft_axis_launch(const FftAxisArgs& args, hipStream_t st) {
   const dim3 gr((unsigned)l.blocks), bl(NT);
   const FftAxisArgs& a = l.a;
   switch (l.smp * 2 + (l.twl ? 1 : 0)) {
+    case 11: hipLaunchKernelGGL((fft_axis_kernel<true, 5>), gr, bl, l.lds, st, a); break;
+    case 10: hipLaunchKernelGGL((fft_axis_kernel<false, 5>), gr, bl, l.lds, st, a); break;
+    case 9: hipLaunchKernelGGL((fft_axis_kernel<true, 4>), gr, bl, l.lds, st, a); break;
+    case 8: hipLaunchKernelGGL((fft_axis_kernel<false, 4>), gr, bl, l.lds, st, a); break;
     case 7: hipLaunchKernelGGL((fft_axis_kernel<true, 3>), gr, bl, l.lds, st, a); break;
     case 6: hipLaunchKernelGGL((fft_axis_kernel<false, 3>), gr, bl, l.lds, st, a); break;
     case 1: hipLaunchKernelGGL((fft_axis_kernel<true, 0>), gr, bl, l.lds, st, a); break;
@@ -289,7 +340,7 @@ hipError_t fft_axis_launch(const FftAxisArgs& args, hipStream_t st) {
 
 // Prepared passes of several slices, grouped by kernel variant, FFT_MULTI per launch.
 hipError_t fft_multi_launch(const std::vector<FftLaunch>& ls, hipStream_t st) {
-  for (int variant = 0; variant < 8; ++variant) {
+  for (int variant = 0; variant < 12; ++variant) {
     FftMulti m;
     std::memset(&m, 0, sizeof(m));
     size_t lds = 0;
@@ -297,6 +348,10 @@ hipError_t fft_multi_launch(const std::vector<FftLaunch>& ls, hipStream_t st) {
       if (m.n == 0) return hipSuccess;
       const dim3 gr((unsigned)m.start[m.n]), bl(NT);
       switch (variant) {
+        case 11: hipLaunchKernelGGL((fft_axis_multi_kernel<true, 5>), gr, bl, lds, st, m); break;
+        case 10: hipLaunchKernelGGL((fft_axis_multi_kernel<false, 5>), gr, bl, lds, st, m); break;
+        case 9: hipLaunchKernelGGL((fft_axis_multi_kernel<true, 4>), gr, bl, lds, st, m); break;
+        case 8: hipLaunchKernelGGL((fft_axis_multi_kernel<false, 4>), gr, bl, lds, st, m); break;
         case 7: hipLaunchKernelGGL((fft_axis_multi_kernel<true, 3>), gr, bl, lds, st, m); break;
         case 6: hipLaunchKernelGGL((fft_axis_multi_kernel<false, 3>), gr, bl, lds, st, m); break;
         case 1: hipLaunchKernelGGL((fft_axis_multi_kernel<true, 0>), gr, bl, lds, st, m); break;

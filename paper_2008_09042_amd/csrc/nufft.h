@@ -45,8 +45,6 @@ constexpr int SPREAD_SPLIT_DEFAULT = 48;
 // four times over the threshold, and the longest (MAXWELL_SPREAD_SPLIT_PARTS=pm,ph overrides).
 constexpr int SPREAD_SPLIT_PM = 4, SPREAD_SPLIT_PH = 16;
 size_t spread_stage_bytes(int J, int64_t M);
-hipError_t pad_deapod_launch(const NufftArgs& a, const float2* S, const float2* x, float2* grid, hipStream_t st);
-hipError_t crop_deapod_launch(const NufftArgs& a, const float2* grid, float2* out, hipStream_t st);
 hipError_t degrid_launch(const NufftArgs& a, const float2* grid, float2* y, hipStream_t st);
 // grid = alpha * (*scale_dev) * spread(y); ys is a staging buffer of spread_stage_bytes(J, M).
 // With `staged`, y is already in the staging layout (sorted samples, coils innermost, J a

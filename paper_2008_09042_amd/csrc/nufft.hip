@@ -26,39 +26,6 @@ namespace {
 
 constexpr int NT = 256;
 
-// Grid[j][a][b] = S[j][r0][r1] x[r0][r1] / (Phi0[r0] Phi1[r1]) inside the centred
-// window of the oversampled grid, zero elsewhere.
-__global__ void pad_deapod_kernel(NufftArgs a, const float2* __restrict__ S, const float2* __restrict__ x,
-                                  float2* __restrict__ grid) {
-  const int64_t G = (int64_t)a.g0 * a.g1;
-  const int64_t total = G * a.J;
-  const int off0 = a.g0 / 2 - a.n0 / 2, off1 = a.g1 / 2 - a.n1 / 2;
-  for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
-    const int64_t j = e / G, q = e % G;
-    const int ga = (int)(q / a.g1), gb = (int)(q % a.g1);
-    const int r0 = ga - off0, r1 = gb - off1;
-    float2 v = make_float2(0.f, 0.f);
-    if (r0 >= 0 && r0 < a.n0 && r1 >= 0 && r1 < a.n1) {
-      const int64_t r = (int64_t)r0 * a.n1 + r1;
-      v = cscale(cmul(S[j * (int64_t)a.n0 * a.n1 + r], x[r]), a.iphi0[r0] * a.iphi1[r1]);
-    }
-    grid[e] = v;
-  }
-}
-
-// out[j][r] = scale * Grid[j][r + off] / (Phi0 Phi1)
-__global__ void crop_deapod_kernel(NufftArgs a, const float2* __restrict__ grid, float2* __restrict__ out) {
-  const int64_t N = (int64_t)a.n0 * a.n1, G = (int64_t)a.g0 * a.g1;
-  const int64_t total = N * a.J;
-  const int off0 = a.g0 / 2 - a.n0 / 2, off1 = a.g1 / 2 - a.n1 / 2;
-  for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
-    const int64_t j = e / N, r = e % N;
-    const int r0 = (int)(r / a.n1), r1 = (int)(r % a.n1);
-    const float2 v = grid[j * G + (int64_t)(r0 + off0) * a.g1 + (r1 + off1)];
-    out[e] = cscale(v, a.iphi0[r0] * a.iphi1[r1]);
-  }
-}
-
 constexpr int SREC = 16;            // floats per sorted-sample weight record: w0 [0, 8), w1 [8, 16)
 
 // y[j][m] = c * sum_{t0, t1} w0[m][t0] w1[m][t1] Grid[j][(b0 + t0) mod g0][(b1 + t1) mod g1],
@@ -737,16 +704,6 @@ int spread_group(int J) { return J >= 8 ? 8 : J > 2 ? 4 : J; }
 size_t spread_stage_bytes(int J, int64_t M) {
   const int jg = spread_group(J);
   return (size_t)M * (size_t)((J + jg - 1) / jg * jg) * sizeof(float2);
-}
-
-hipError_t pad_deapod_launch(const NufftArgs& a, const float2* S, const float2* x, float2* grid, hipStream_t st) {
-  hipLaunchKernelGGL(pad_deapod_kernel, dim3(grid_for((int64_t)a.g0 * a.g1 * a.J)), dim3(NT), 0, st, a, S, x, grid);
-  return hipGetLastError();
-}
-
-hipError_t crop_deapod_launch(const NufftArgs& a, const float2* grid, float2* out, hipStream_t st) {
-  hipLaunchKernelGGL(crop_deapod_kernel, dim3(grid_for((int64_t)a.n0 * a.n1 * a.J)), dim3(NT), 0, st, a, grid, out);
-  return hipGetLastError();
 }
 
 hipError_t degrid_launch(const NufftArgs& a, const float2* grid, float2* y, hipStream_t st) {

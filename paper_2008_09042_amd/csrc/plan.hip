@@ -210,9 +210,45 @@ hipError_t fft_image(const Plan& p, const float2* src, float2* dst, int dir, con
   return fft_dims(p, src, dst, dir, premul, p.ndim, p.n, p.d_tw, p.nrad, p.radix, st);
 }
 
-hipError_t fft_grid(const Plan& p, float2* data, int dir, hipStream_t st) {
+// The NUFFT's transform over the oversampled grid G [J][g0][g1], with its zero-pad and crop
+// folded into the passes: forward (dir < 0), the first pass (along rows) reads S x / (Phi0
+// Phi1) inside the centred n0 x n1 window in place of a padded grid; inverse (dir > 0), the last
+// pass (along columns) writes only the window, deapodised, to out [J][n0][n1], and skips the
+// columns outside it.
+hipError_t fft_grid_window(const Plan& p, const float2* S, const float2* x, float2* G, float2* out, int dir,
+                           hipStream_t st) {
   const int64_t dims[2] = {p.g[0], p.g[1]};
-  return fft_dims(p, data, data, dir, nullptr, 2, dims, p.d_twg, p.nradg, p.radixg, st);
+  for (int t = 0; t < 2; ++t) {
+    const int d = 1 - t;  // rows first, then columns
+    FftAxisArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.data = G;
+    a.src = G;
+    a.n = dims[d];
+    a.inner = d == 1 ? 1 : dims[1];
+    a.outer_per_coil = d == 1 ? dims[0] : 1;
+    a.outer = (int64_t)p.J * a.outer_per_coil;
+    a.dir = dir;
+    a.twiddle = p.d_twg[d];
+    a.nrad = p.nradg[d];
+    for (int q = 0; q < p.nradg[d]; ++q) a.radix[q] = p.radixg[d][q];
+    a.coil_elems = dims[0] * dims[1];
+    a.nsamples = p.M;
+    a.iphi = p.d_iphi;
+    a.woff0 = (int)(dims[0] / 2 - p.n[0] / 2);
+    a.woff1 = (int)(dims[1] / 2 - p.n[1] / 2);
+    a.wn0 = (int)p.n[0];
+    a.wn1 = (int)p.n[1];
+    if (dir < 0 && t == 0) {
+      a.src = S;
+      a.premul = x;
+      a.pad = 1;
+    }
+    if (dir > 0 && t == 1) a.crop_out = out;
+    hipError_t e = TIMED("fft_axis", fft_axis_launch(a, st));
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 NufftArgs nufft_args(const Plan& p) {
@@ -1019,8 +1055,7 @@ static hipError_t encode_maps(const Plan& p, const float2* S, const float2* x, f
   if (p.sampling == MAXWELL_NONCARTESIAN) {
     const NufftArgs na = nufft_args(p);
     float2* G = wsp<float2>(ws, p.off_G);
-    if ((e = TIMED("nufft_pad", pad_deapod_launch(na, S, x, G, st))) != hipSuccess) return e;
-    if ((e = fft_grid(p, G, -1, st)) != hipSuccess) return e;
+    if ((e = fft_grid_window(p, S, x, G, nullptr, -1, st)) != hipSuccess) return e;  // zero-pad in the first pass
     return TIMED("nufft_degrid", degrid_launch(na, G, y, st));
   }
   float2* Kb = wsp<float2>(ws, p.off_K);
@@ -1077,8 +1112,7 @@ static hipError_t adjoint_maps(const Plan& p, const float2* S, const float2* x, 
                                                  ordered))) !=
         hipSuccess)
       return e;
-    if ((e = fft_grid(p, G, +1, st)) != hipSuccess) return e;
-    if ((e = TIMED("nufft_crop", crop_deapod_launch(na, G, Kb, st))) != hipSuccess) return e;
+    if ((e = fft_grid_window(p, nullptr, nullptr, G, Kb, +1, st)) != hipSuccess) return e;  // crop in the last pass
     alpha = 1.0f;  // the scale was applied by the spread
     scale_dev = nullptr;
   } else {
