@@ -540,11 +540,12 @@ def bench_kernels2d(args, torch, names=("cart2d_256_dense200_j32", "radial2d_256
                 # Cartesian: the mask is applied in the last forward and the first inverse
                 # pass (8 B per element in, 8 B per sample and 4 B of inverse mask per point
                 # out, and the reverse), so the four passes move 48 J N + 16 J M + 8 N bytes
-                # gridding: the zero-pad and deapodisation are applied in the first forward pass
-                # (8 B per image element and coil in, the padded rows out) and the crop in the
-                # last inverse pass (only the g0 x n1 columns of the window read, the n0 x n1
-                # window out), so the four passes move 8 J (N + 5 G + g0 n1 + N) + 8 N bytes
-                "fft_axis": ("hbm", (8.0 * J * (2 * N + 5 * G + 2 * p.dims[0] * p.dims[1]) + 8.0 * N) / 4 if G
+                # gridding (g0 x g1 grid, n0 x n1 window): the first forward pass reads the
+                # window (8 B per image element and coil, and the image) and writes its n0 rows,
+                # the second reads them and writes the grid; the first inverse pass reads the
+                # grid and writes the window's n1 columns, the last reads them and writes the
+                # window: 8 J (2 N + 2 n0 g1 + 2 G + 2 g0 n1) + 8 N bytes in four passes
+                "fft_axis": ("hbm", (16.0 * J * (N + G + 2 * p.dims[0] * p.dims[1] * 2) + 8.0 * N) / 4 if G
                              else (48.0 * J * N + 16.0 * J * M + 8.0 * N) / 4, None, None),
                 "gather": ("hbm", 8.0 * J * M * 2 + 4.0 * M, None, None),
                 "scatter": ("hbm", 8.0 * J * (M + N) + 4.0 * N, None, None),

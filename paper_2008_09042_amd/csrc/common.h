@@ -82,16 +82,21 @@ struct FftAxisArgs {
   uint32_t coil_magic, coil_shift;  // multiply-high division by N (set by fft_axis_launch)
   int lines;              // lines per workgroup (set by fft_axis_launch)
   // optional gridding window (the NUFFT's zero-pad and crop with deapodisation, 2D grids of
-  // g0 x g1 with the centred wn0 x wn1 window at (woff0, woff1)):
-  //   pad  (first forward pass, along rows, with `pad` set): reads, in place of src,
-  //        src[j][r0][r1] premul[r0][r1] iphi[r0] iphi[wn0 + r1] inside the window, 0 outside
-  //        (src the coil maps [J][wn0][wn1], premul the image)
+  // g0 x g1 with the centred wn0 x wn1 window at (woff0, woff1)); grid rows and columns
+  // outside the window that no later pass reads are neither computed nor written:
+  //   win = WIN_PAD (first forward pass, along rows): reads, in place of src,
+  //        src[j][r0][r1] premul[r0][r1] iphi[r0] iphi[wn0 + r1] (src the coil maps
+  //        [J][wn0][wn1], premul the image); writes only the window's rows
+  //   win = WIN_ROWS_IN (second forward pass, along columns): rows outside the window are
+  //        taken as zero, not read
+  //   win = WIN_COLS_OUT (first inverse pass, along rows): writes only the window's columns
   //   crop (last inverse pass, along columns, with crop_out set): writes only the window,
   //        crop_out[j][r0][r1] = v iphi[r0] iphi[wn0 + r1], and skips columns outside it
   const float* iphi; float2* crop_out;
   int woff0, woff1, wn0, wn1;
-  int pad;
+  int win;
 };
+constexpr int WIN_PAD = 1, WIN_ROWS_IN = 2, WIN_COLS_OUT = 3;
 hipError_t fft_axis_launch(const FftAxisArgs& a, hipStream_t st);
 // A pass prepared for launch (lines per workgroup, magic numbers, kernel variant, grid, LDS).
 struct FftLaunch {

@@ -32,8 +32,17 @@ constexpr int TW_LDS_MAX = 1024;    // twiddle tables up to this length are stag
 // complex elements of the LDS tile for T lines of length n
 __host__ __device__ inline int tile_elems(int n, int T, bool contiguous) { return contiguous ? T * (n + 1) : T * n; }
 
+// Row ga of the grid of the line l of a pad-mode tile (contiguous lines of g0 rows per coil):
+// the tile starts at row pga0 of its coil; `tall` tiles span more than a coil.
+__device__ __forceinline__ int64_t pad_row(const FftAxisArgs& a, int64_t o0, int64_t pga0, bool tall, int l) {
+  if (tall) return (o0 + l) % a.outer_per_coil;
+  const int64_t ga = pga0 + l;
+  return ga >= a.outer_per_coil ? ga - a.outer_per_coil : ga;
+}
+
 // TWL: the twiddle table is copied into LDS behind the tile.  SMP: 4 the input is the gridding
-// window (zero-pad), 5 the output is cropped to it (see FftAxisArgs); 1 the input comes from
+// window (zero-pad), 6 rows outside it are zero, 7 only its columns are written, 5 the output
+// is cropped to it (see FftAxisArgs); 1 the input comes from
 // the samples through the inverse mask, 2 the output goes to them.  bid / nbl: this
 // workgroup's index among the nbl workgroups of the pass.
 template <bool TWL, int SMP>
@@ -93,6 +102,15 @@ __device__ __forceinline__ void fft_axis_body(const FftAxisArgs& a, int64_t bid_
     pj0 = o0 / a.outer_per_coil;
     pga0 = o0 - pj0 * a.outer_per_coil;
     ptall = tg.T > a.outer_per_coil;
+    // a tile of rows wholly outside the window has nothing to write: the next pass takes
+    // them as zero (uniform per workgroup, before any barrier).  Its rows are [pga0, end) of
+    // one coil, continued at row 0 of the next past the coil's last row.
+    if (!ptall) {
+      const int64_t end = pga0 + Tvalid, opc = a.outer_per_coil, w0 = a.woff0, w1 = a.woff0 + a.wn0;
+      bool any = pga0 < w1 && (end < opc ? end : opc) > w0;
+      if (end > opc) any = any || end - opc > w0;
+      if (!any) return;
+    }
   }
   if constexpr (SMP == 3) {
     // whole lines l0 .. l0 + T - 1 of coil j (contiguous axis): zero the tile, then put the
@@ -137,15 +155,9 @@ __device__ __forceinline__ void fft_axis_body(const FftAxisArgs& a, int64_t bid_
       } else if constexpr (SMP == 4) {
         // zero-padded, deapodised grid row ga of coil j (contiguous lines): the window's
         // points read S x / (Phi0 Phi1), the rest are zero (loads clamped into the window)
-        int64_t j = pj0, ga = pga0 + (ok ? l : 0);  // the tile's lines are consecutive
-        if (ptall) {
-          const int64_t o = o0 + (ok ? l : 0);
-          j = o / a.outer_per_coil;
-          ga = o - j * a.outer_per_coil;
-        } else if (ga >= a.outer_per_coil) {
-          ga -= a.outer_per_coil;
-          ++j;
-        }
+        const int lc = ok ? l : 0;  // the tile's lines are consecutive
+        const int64_t ga = pad_row(a, o0, pga0, ptall, lc);
+        const int64_t j = ptall ? (o0 + lc) / a.outer_per_coil : pj0 + (pga0 + lc >= a.outer_per_coil ? 1 : 0);
         const int r0 = (int)ga - a.woff0, r1 = i - a.woff1;
         const bool in = r0 >= 0 && r0 < a.wn0 && r1 >= 0 && r1 < a.wn1;
         const int c0 = min(max(r0, 0), a.wn0 - 1), c1 = min(max(r1, 0), a.wn1 - 1);
@@ -153,6 +165,13 @@ __device__ __forceinline__ void fft_axis_body(const FftAxisArgs& a, int64_t bid_
         const float2 sv = a.src[j * (int64_t)a.wn0 * a.wn1 + r], xv = a.premul[r];
         const float w = a.iphi[c0] * a.iphi[a.wn0 + c1];
         v[u] = cscale(cmul(sv, xv), w);
+        if (!in) keep[u] = 0u;
+      } else if constexpr (SMP == 6) {
+        // strided lines (grid columns), i the row: rows outside the window are zero and not
+        // read (their loads clamped to the window's edge rows of the same columns)
+        const bool in = i >= a.woff0 && i < a.woff0 + a.wn0;
+        const int ic = min(max(i, a.woff0), a.woff0 + a.wn0 - 1);
+        v[u] = a.src[gbase + (ok ? (int64_t)l + (int64_t)ic * a.inner : (int64_t)a.woff0 * a.inner)];
         if (!in) keep[u] = 0u;
       } else {
         v[u] = a.src[gidx];
@@ -205,6 +224,13 @@ __device__ __forceinline__ void fft_axis_body(const FftAxisArgs& a, int64_t bid_
         const uint32_t f = (uint32_t)gidx, j = fdiv(f, fN), pp = f - j * (uint32_t)fN.d;
         const int m = a.out_inv[pp];
         if (m >= 0) a.out_samples[(int64_t)j * a.nsamples + m] = cscale(v[u], s);
+      } else if constexpr (SMP == 4) {
+        // only the window's rows
+        const int64_t ga = pad_row(a, o0, pga0, ptall, l);
+        if (ga >= a.woff0 && ga < a.woff0 + a.wn0) a.data[gidx] = cscale(v[u], s);
+      } else if constexpr (SMP == 7) {
+        // contiguous lines (grid rows), i the column: only the window's columns
+        if (i >= a.woff1 && i < a.woff1 + a.wn1) a.data[gidx] = cscale(v[u], s);
       } else if constexpr (SMP == 5) {
         // only the window: row i, column t0 + l of coil o0, deapodised
         const int r0 = i - a.woff0, r1 = (int)(t0 + l) - a.woff1;
@@ -274,11 +300,18 @@ hipError_t fft_axis_prepare(const FftAxisArgs& args, FftLaunch& out) {
   const int64_t blocks = contiguous ? (a.outer + T - 1) / T : a.outer * ((a.inner + T - 1) / T);
   const size_t lds = (size_t)(tile_elems(n, a.lines, contiguous) + (twl ? n : 0)) * sizeof(float2);
   int smp = a.in_inv ? 1 : a.out_inv ? 2 : 0;
-  if (a.pad || a.crop_out) {  // the gridding window: pad on a first row pass, crop on a last column pass
-    if (smp || (a.pad && a.crop_out) || !a.iphi || a.wn0 < 1 || a.wn1 < 1) return hipErrorInvalidValue;
-    if (a.pad && (!contiguous || !a.src || !a.premul)) return hipErrorInvalidValue;
-    if (a.crop_out && contiguous) return hipErrorInvalidValue;
-    smp = a.pad ? 4 : 5;
+  if (a.win || a.crop_out) {
+    // the gridding window: pad on the first forward pass (rows), zero rows on the second
+    // (columns), window columns out of the first inverse pass (rows), crop on the last (columns)
+    if (smp || (a.win && a.crop_out) || a.win < 0 || a.win > WIN_COLS_OUT) return hipErrorInvalidValue;
+    const int64_t g0 = contiguous ? a.outer_per_coil : a.n, g1 = contiguous ? a.n : a.inner;
+    if (a.wn0 < 1 || a.wn1 < 1 || a.woff0 < 0 || a.woff1 < 0 || a.woff0 + a.wn0 > g0 || a.woff1 + a.wn1 > g1)
+      return hipErrorInvalidValue;
+    if (a.win == WIN_PAD && (!contiguous || !a.src || !a.premul || !a.iphi)) return hipErrorInvalidValue;
+    if (a.win == WIN_ROWS_IN && (contiguous || a.premul || a.outer_per_coil != 1)) return hipErrorInvalidValue;
+    if (a.win == WIN_COLS_OUT && (!contiguous || a.premul)) return hipErrorInvalidValue;
+    if (a.crop_out && (contiguous || !a.iphi || a.outer_per_coil != 1)) return hipErrorInvalidValue;
+    smp = a.crop_out ? 5 : a.win == WIN_PAD ? 4 : a.win == WIN_ROWS_IN ? 6 : 7;
   }
   // the reading pass places whole lines' samples directly when every tile holds lines of
   // one coil only
@@ -322,6 +355,10 @@ hipError_t fft_axis_launch(const FftAxisArgs& args, hipStream_t st) {
   const dim3 gr((unsigned)l.blocks), bl(NT);
   const FftAxisArgs& a = l.a;
   switch (l.smp * 2 + (l.twl ? 1 : 0)) {
+    case 15: hipLaunchKernelGGL((fft_axis_kernel<true, 7>), gr, bl, l.lds, st, a); break;
+    case 14: hipLaunchKernelGGL((fft_axis_kernel<false, 7>), gr, bl, l.lds, st, a); break;
+    case 13: hipLaunchKernelGGL((fft_axis_kernel<true, 6>), gr, bl, l.lds, st, a); break;
+    case 12: hipLaunchKernelGGL((fft_axis_kernel<false, 6>), gr, bl, l.lds, st, a); break;
     case 11: hipLaunchKernelGGL((fft_axis_kernel<true, 5>), gr, bl, l.lds, st, a); break;
     case 10: hipLaunchKernelGGL((fft_axis_kernel<false, 5>), gr, bl, l.lds, st, a); break;
     case 9: hipLaunchKernelGGL((fft_axis_kernel<true, 4>), gr, bl, l.lds, st, a); break;
@@ -340,7 +377,7 @@ hipError_t fft_axis_launch(const FftAxisArgs& args, hipStream_t st) {
 
 // Prepared passes of several slices, grouped by kernel variant, FFT_MULTI per launch.
 hipError_t fft_multi_launch(const std::vector<FftLaunch>& ls, hipStream_t st) {
-  for (int variant = 0; variant < 12; ++variant) {
+  for (int variant = 0; variant < 16; ++variant) {
     FftMulti m;
     std::memset(&m, 0, sizeof(m));
     size_t lds = 0;
@@ -348,6 +385,10 @@ hipError_t fft_multi_launch(const std::vector<FftLaunch>& ls, hipStream_t st) {
       if (m.n == 0) return hipSuccess;
       const dim3 gr((unsigned)m.start[m.n]), bl(NT);
       switch (variant) {
+        case 15: hipLaunchKernelGGL((fft_axis_multi_kernel<true, 7>), gr, bl, lds, st, m); break;
+        case 14: hipLaunchKernelGGL((fft_axis_multi_kernel<false, 7>), gr, bl, lds, st, m); break;
+        case 13: hipLaunchKernelGGL((fft_axis_multi_kernel<true, 6>), gr, bl, lds, st, m); break;
+        case 12: hipLaunchKernelGGL((fft_axis_multi_kernel<false, 6>), gr, bl, lds, st, m); break;
         case 11: hipLaunchKernelGGL((fft_axis_multi_kernel<true, 5>), gr, bl, lds, st, m); break;
         case 10: hipLaunchKernelGGL((fft_axis_multi_kernel<false, 5>), gr, bl, lds, st, m); break;
         case 9: hipLaunchKernelGGL((fft_axis_multi_kernel<true, 4>), gr, bl, lds, st, m); break;

@@ -212,9 +212,11 @@ hipError_t fft_image(const Plan& p, const float2* src, float2* dst, int dir, con
 
 // The NUFFT's transform over the oversampled grid G [J][g0][g1], with its zero-pad and crop
 // folded into the passes: forward (dir < 0), the first pass (along rows) reads S x / (Phi0
-// Phi1) inside the centred n0 x n1 window in place of a padded grid; inverse (dir > 0), the last
-// pass (along columns) writes only the window, deapodised, to out [J][n0][n1], and skips the
-// columns outside it.
+// Phi1) inside the centred n0 x n1 window in place of a padded grid and transforms and writes
+// only the window's rows, which are all the second pass (along columns) reads; inverse
+// (dir > 0), the first pass (along rows) writes only the window's columns, and the last (along
+// them) writes only the window, deapodised, to out [J][n0][n1].  Between the passes the rows
+// (columns) of G outside the window hold stale values that no pass reads.
 hipError_t fft_grid_window(const Plan& p, const float2* S, const float2* x, float2* G, float2* out, int dir,
                            hipStream_t st) {
   const int64_t dims[2] = {p.g[0], p.g[1]};
@@ -239,12 +241,18 @@ hipError_t fft_grid_window(const Plan& p, const float2* S, const float2* x, floa
     a.woff1 = (int)(dims[1] / 2 - p.n[1] / 2);
     a.wn0 = (int)p.n[0];
     a.wn1 = (int)p.n[1];
-    if (dir < 0 && t == 0) {
-      a.src = S;
-      a.premul = x;
-      a.pad = 1;
+    if (dir < 0) {
+      if (t == 0) {
+        a.src = S;
+        a.premul = x;
+        a.win = WIN_PAD;
+      } else {
+        a.win = WIN_ROWS_IN;
+      }
+    } else {
+      if (t == 0) a.win = WIN_COLS_OUT;
+      else a.crop_out = out;
     }
-    if (dir > 0 && t == 1) a.crop_out = out;
     hipError_t e = TIMED("fft_axis", fft_axis_launch(a, st));
     if (e != hipSuccess) return e;
   }
