@@ -287,21 +287,29 @@ def bench_batch(args, torch):
     tuned = tune_counts()
     log(f"[bench] plans ready in {time.time() - t0:.1f}s (dense products: {tuned[0]} shapes timed, "
         f"{tuned[1]} reused from the tuning cache)")
-    batch = MaxwellBatch(plans, branches=args.branches, staged=True, stamps=True)
+    batch = MaxwellBatch(plans, branches=args.branches, staged=True)
     coils = sum(p.J for p in ps)
     basis_bytes = sum(8 * p.N * p.K for p in ps)
     eager_ms, _ = time_steps(lambda: batch.grad(xs, cs, ys), args.steps, args.warmup, torch)
     batch.capture(xs, cs, ys)
     ms, wall = time_steps(batch.replay, args.steps, args.warmup, torch)
     log(f"[bench] batch: {ms:.3f} ms/step graph ({coils * 1000.0 / ms:.0f} coil-images/s), eager {eager_ms:.3f} ms")
-    # per-slice latency inside the captured replay: each slice's device timestamps (start of its
-    # first step, end of its last), written by the graph itself; median over replays
+    del batch
+    # per-slice latency inside a captured replay: the same batch with each slice's device
+    # timestamps (start of its first step, end of its last) written by the graph itself (two
+    # small kernels per slice, so its step is timed on its own); median over replays
+    sb = MaxwellBatch(plans, branches=args.branches, staged=True, stamps=True)
+    sb.capture(xs, cs, ys)
+    stamped_ms, _ = time_steps(sb.replay, args.steps, args.warmup, torch)
     lat_runs = []
     for _ in range(5):
-        batch.replay()
+        sb.replay()
         torch.cuda.synchronize()
-        lat_runs.append(batch.latencies_ms())
+        lat_runs.append(sb.latencies_ms())
     lat = np.median(np.array(lat_runs), axis=0)
+    log(f"[bench] batch with per-slice timestamps: {stamped_ms:.3f} ms/step graph; slice latency p50 "
+        f"{np.percentile(lat, 50):.3f} ms, p99 {np.percentile(lat, 99):.3f} ms")
+    del sb
     # the same batch with each slice's whole chain on a branch (no phases), for comparison
     cb = MaxwellBatch(plans, branches=args.branches, staged=False)
     cb.capture(xs, cs, ys)
@@ -338,10 +346,12 @@ def bench_batch(args, torch):
                            "with each phase's FFT passes of all slices launched together"},
         "eager_ms_per_step": eager_ms,
         "chains_per_branch_ms_per_step": chain_ms,
+        "stamped_ms_per_step": stamped_ms,
         "plan_tuning": {"timed": tuned[0], "reused_from_cache": tuned[1]},
         "other_precision": compare,
         "basis_stream_gbs": 2.0 * basis_bytes / (ms * 1e-3) / 1e9,
-        "slice_latency_ms": {"source": "device timestamps inside the captured replay (median of 5 replays)",
+        "slice_latency_ms": {"source": "device timestamps inside replays of the same batch captured with "
+                                       "them (median of 5 replays)",
                              "p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                              "min": float(lat.min()), "max": float(lat.max())},
     }

@@ -290,7 +290,11 @@ hipError_t fft_axis_prepare(const FftAxisArgs& args, FftLaunch& out) {
   int Tmax = TILE / n;
   if (Tmax > 64) Tmax = 64;
   if (Tmax < 1) Tmax = 1;
-  const int64_t lines = a.outer * a.inner;
+  // lines that carry work: the pad pass transforms only the window's rows (the other tiles
+  // exit at once)
+  int64_t lines = a.outer * a.inner;
+  if (a.win == WIN_PAD && contiguous && a.outer_per_coil > 0 && a.wn0 > 0 && a.wn0 < a.outer_per_coil)
+    lines = a.outer / a.outer_per_coil * a.wn0;
   int64_t T = (lines + 1023) / 1024;
   if (!contiguous && T < 8) T = 8;
   if (T > Tmax) T = Tmax;

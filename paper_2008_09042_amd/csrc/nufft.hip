@@ -37,7 +37,12 @@ __global__ __launch_bounds__(NT) void degrid_kernel(NufftArgs a, const float2* _
                                                     float2* __restrict__ y) {
   const int64_t G = (int64_t)a.g0 * a.g1;
   const int64_t total = a.M * a.J;
-  for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
+  // consecutive blocks (neighbouring samples, which read the same grid rows) go to one XCD:
+  // the hardware deals workgroups round-robin over the 8 XCDs, each with its own L2
+  const int64_t nb = gridDim.x;
+  int64_t bid = blockIdx.x;
+  if ((nb & 7) == 0) bid = (bid & 7) * (nb >> 3) + (bid >> 3);
+  for (int64_t e = bid * NT + threadIdx.x; e < total; e += nb * NT) {
     // samples in first-tap cell order, so the lanes of a wave read overlapping grid rows
     // (against sample order: 40 -> 24 us at 512^2, 16 coils, 64 spokes x 512)
     const int64_t j = e / a.M, s = e % a.M;
@@ -498,7 +503,12 @@ __global__ __launch_bounds__(256, 4) void spread_lds_kernel(NufftArgs a, const f
                                  reinterpret_cast<float2*>(chunks));
     return;
   }
-  const int64_t id = (int64_t)blockIdx.x * 4 + wave;
+  // consecutive plain workgroups (neighbouring row blocks, which read the same cell rows'
+  // samples) go to one XCD: the hardware deals workgroups round-robin over the 8 XCDs
+  int64_t bx = blockIdx.x;
+  const int64_t np8 = nplain & ~(int64_t)7;
+  if (bx < np8) bx = (bx & 7) * (np8 >> 3) + (bx >> 3);
+  const int64_t id = bx * 4 + wave;
   if (id >= nblk * (Jp / JG)) return;  // whole waves only: no workgroup barrier follows
   const int jg = (int)(id / nblk), blk = (int)(id % nblk);
   if (a.s_heavy && a.s_heavy[blk]) return;  // split rows, taken by the workgroups after these
