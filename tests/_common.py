@@ -50,8 +50,9 @@ class Case:
     """A seeded problem with complex64-rounded inputs and its FP64 oracle."""
 
     def __init__(self, seed, dims, J, K, basis="dense", ranks=None, mask="random", frac=0.35,
-                 weights=False, degree=4, kmax=2.0, spokes=None, n_read=None):
+                 weights=False, degree=4, kmax=2.0, spokes=None, n_read=None, oversamp=2.0, kb_width=6):
         self.dims = tuple(dims)
+        self.oversamp, self.kb_width = float(oversamp), int(kb_width)
         self.N = int(np.prod(dims))
         self.J, self.K = J, K
         rb = rng_for(seed, 2)
@@ -94,7 +95,8 @@ class Case:
         re = rng_for(seed, 6)
         self.x0 = c64(phantom(re, dims) + 0.1 * complex_normal(re, dims))
         self.c0 = c64(coefficients(re, J, K))
-        self.op = Oracle(dims, B=self.B, U=self.U, core=self.core, mask_idx=self.mask, traj=self.traj)
+        self.op = Oracle(dims, B=self.B, U=self.U, core=self.core, mask_idx=self.mask, traj=self.traj,
+                         kb_width=self.kb_width, oversamp=self.oversamp)
         y_clean = self.op.encode(self.x_true, self.c_true)
         noise = complex_normal(rng_for(seed, 5), (J, self.M))
         scale = 0.01 * np.linalg.norm(y_clean) / max(np.linalg.norm(noise), 1e-300)
@@ -103,6 +105,8 @@ class Case:
     def plan(self, precision="fp32"):
         from paper_2008_09042_amd.encoding import MaxwellPlan
         kw = dict(mask_idx=self.mask, traj=self.traj, weights=self.w, precision=precision)
+        if self.traj is not None:
+            kw.update(kb_width=self.kb_width, oversamp=self.oversamp)
         if self.B is not None:
             return MaxwellPlan(self.dims, self.J, B=self.B, **kw)
         return MaxwellPlan(self.dims, self.J, U=self.U, core=self.core, **kw)

@@ -71,6 +71,14 @@ CASES = {
                                        n_read=96, weights=True),
     "radial_64x64_J8_K6_12spokes": dict(seed=124, dims=(64, 64), J=8, K=6, mask="radial", spokes=12,
                                         n_read=128),
+    # other oversampling factors and kernel widths: the image window sits at other offsets of
+    # the grid (60 x 54 with the window at rows 10.., columns 9..; 80 x 60 at 8.., 6..), which
+    # the grid transform's pad, pruned and crop passes must honour; grid sizes with radices 3
+    # and 5
+    "radial_40x36_J3_K6_sigma1.5_W4": dict(seed=125, dims=(40, 36), J=3, K=6, mask="radial", spokes=10,
+                                           n_read=80, weights=True, oversamp=1.5, kb_width=4),
+    "radial_64x48_J9_K5_sigma1.25_W5": dict(seed=126, dims=(64, 48), J=9, K=5, mask="radial", spokes=14,
+                                            n_read=128, oversamp=1.25, kb_width=5),
 }
 FUSED = {"tucker3d_32x32x32_r12_K70_J4", "fused_48x32x20_r9x13x5_K23_J5", "fused_16x80x12_r3x17x4_K11_J3",
          "fused_128x128x64_r40_K60_J5", "fused_64x64x32_r20_K30_J3", "fused_32x32x16_r9x10x11_K150_J64",
@@ -216,7 +224,8 @@ def test_edge_full_and_empty_mask():
 
 @pytest.mark.parametrize("split", ["1000000", None])
 @pytest.mark.parametrize("name", ["radial_32x24_J3_K9_7spokes", "radial_40x30_J2_K6_5spokes",
-                                  "radial_256_J2_K20_64spokes", "radial_64x48_J12_K7_16spokes"])
+                                  "radial_256_J2_K20_64spokes", "radial_64x48_J12_K7_16spokes",
+                                  "radial_40x36_J3_K6_sigma1.5_W4", "radial_64x48_J9_K5_sigma1.25_W5"])
 def test_radial_spread_through_lds(name, split, monkeypatch):
     """The plain spread blocks stage their samples through LDS (MAXWELL_SPREAD_LDS, default 1)
     or walk them from memory (0).  Both add the same products in the same order per grid
@@ -282,7 +291,8 @@ def test_radial_adjoint_identity_on_gpu():
 
 @pytest.mark.parametrize("split", ["0", "1000000"])
 @pytest.mark.parametrize("name", ["radial_32x24_J3_K9_7spokes", "radial_40x30_J2_K6_5spokes",
-                                  "radial_256_J2_K20_64spokes", "radial_64x48_J12_K7_16spokes"])
+                                  "radial_256_J2_K20_64spokes", "radial_64x48_J12_K7_16spokes",
+                                  "radial_40x36_J3_K6_sigma1.5_W4", "radial_64x48_J9_K5_sigma1.25_W5"])
 def test_radial_spread_split_and_plain(name, split, monkeypatch):
     """The spread has a plain kernel and a split kernel for the blocks whose longest sample
     chain exceeds MAXWELL_SPREAD_SPLIT (read at plan creation; by default the dense centre of
