@@ -30,9 +30,9 @@ struct CoreArgs {
   CoreGeom g;
   int J;
   const float2* core;          // [R][K] (FP32 kernels)
-  const uint16_t* fwd_hi;      // forward planes (BF16-split kernels), fragment order over [R][KP]
+  const uint16_t* fwd_hi;      // forward planes (BF16-split kernels), fragment order over [R][KP], step-major
   const uint16_t* fwd_lo;
-  const uint16_t* adj_hi;      // adjoint planes: conj(core)^T, fragment order over [Kp][2 Rp]
+  const uint16_t* adj_hi;      // adjoint planes: conj(core)^T, fragment order over [Kp][2 Rp], chunk-step-major
   const uint16_t* adj_lo;
   const float2* fwd_f32;       // FP32 copies in fragment order (FP32 kernels; null: read `core`)
   const float2* adj_f32;

@@ -63,7 +63,7 @@ __global__ __launch_bounds__(NT) void core_fwd_bf16_kernel(CoreArgs a) {
   if (rb0 >= rbs) return;
   int64_t oa[RB];
 #pragma unroll
-  for (int m = 0; m < RB; ++m) oa[m] = min(rb0 + m, rbs - 1) * steps * 512 + lane * 8;
+  for (int m = 0; m < RB; ++m) oa[m] = min(rb0 + m, rbs - 1) * 512 + lane * 8;
   const float2* row[NB];
 #pragma unroll
   for (int cb = 0; cb < NB; ++cb) row[cb] = a.in + (int64_t)min(16 * cb + (lane & 15), a.J - 1) * a.g.K;
@@ -73,8 +73,8 @@ __global__ __launch_bounds__(NT) void core_fwd_bf16_kernel(CoreArgs a) {
     s = min(s, steps - 1);
 #pragma unroll
     for (int m = 0; m < RB; ++m) {
-      ah[d][m] = ld8(a.fwd_hi + oa[m] + (int64_t)s * 512);
-      al[d][m] = ld8(a.fwd_lo + oa[m] + (int64_t)s * 512);
+      ah[d][m] = ld8(a.fwd_hi + oa[m] + (int64_t)s * rbs * 512);
+      al[d][m] = ld8(a.fwd_lo + oa[m] + (int64_t)s * rbs * 512);
     }
     call_operand<NB>(row, 16 * (int64_t)s, a.g.K, grp, bv[d]);
   };
@@ -121,15 +121,19 @@ __global__ __launch_bounds__(NT) void core_fwd_bf16_kernel(CoreArgs a) {
 }
 
 // ---------------------------------------------------------------- FP32, fragment order
-// The FP32 core copies: A operands in fragment order, [row block][K16 step][lane][4 complex]
-// (frag_a<0>).  Forward: A(rho, k) = core[rho][k], (R + 15) / 16 row blocks x Kp / 16 steps.
+// The FP32 core copies: A operands in fragment order, [K16 step][row block][lane][4 complex]
+// (frag_a<0> with the step as its outer index; the adjoint's steps grouped by rho chunk as in
+// the BF16 planes).  Forward: A(rho, k) = core[rho][k], (R + 15) / 16 row blocks x Kp / 16 steps.
 // Adjoint: A(k, rho) = conj(core[rho][k]), Kp / 16 row blocks x Rp / 16 steps.  Zero past R
 // and K.
 __global__ void core_frag32_kernel(const float2* __restrict__ core, int64_t R, int K, int adj, int64_t nrb,
                                    int64_t steps, float4* __restrict__ dst) {
   const int64_t total = nrb * steps * 64;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t rb = e / (steps * 64), st = (e / 64) % steps;
+    // step-major, as the BF16 planes: forward [step][row block], adjoint [step within a rho
+    // chunk of RC][chunk][k row block]
+    const int64_t idx = e / 64, rb = idx % nrb, t = idx / nrb;
+    const int64_t st = !adj ? t : (t % (steps / (RC / 16))) * (RC / 16) + t / (steps / (RC / 16));
     const int lane = (int)(e % 64);
     const int64_t row = 16 * rb + lane % 16;
     float2 v[4];
@@ -167,7 +171,7 @@ __global__ __launch_bounds__(NT) void core_fwd_f32f_kernel(CoreArgs a) {
   auto load = [&](int d, int s) {
     s = min(s, steps - 1);
 #pragma unroll
-    for (int m = 0; m < RB; ++m) av[d][m] = frag_a<0>(a.fwd_f32, steps, (int)rbm[m], s, lane);
+    for (int m = 0; m < RB; ++m) av[d][m] = frag_a<0>(a.fwd_f32, (int)rbs, s, (int)rbm[m], lane);  // step-major
     call_operand<NB>(row, 16 * (int64_t)s, a.g.K, grp, bv[d]);
   };
   Tile<0>::Acc acc[RB][NB];
@@ -238,7 +242,8 @@ __global__ __launch_bounds__(NT) void core_adj_f32f_kernel(CoreArgs a, int nch, 
   auto load = [&](int d, int s) {
     s = min(s, steps - 1);
 #pragma unroll
-    for (int m = 0; m < RB; ++m) av[d][m] = frag_a<0>(a.adj_f32, steps_total, mbm[m], (int)(rho0 / 16) + s, lane);
+    // chunk-step-major: fragment (step s of chunk ch, k row block mb) at (s nch + ch) mbl + mb
+    for (int m = 0; m < RB; ++m) av[d][m] = frag_a<0>(a.adj_f32, mbl, s * (steps_total / steps) + ch, mbm[m], lane);
     call_operand<NB>(row, rho0 + 16 * s, a.g.R, grp, bv[d]);
   };
   Tile<0>::Acc acc[RB][NB];
@@ -356,9 +361,10 @@ __global__ __launch_bounds__(NT) void core_adj_bf16_kernel(CoreArgs a, int nch, 
   const int64_t rho0 = (int64_t)ch * RC;
   const int64_t steps_total = a.g.Rp / 16;
   constexpr int steps = RC / 16;
+  const int64_t nchp = steps_total / steps;  // chunks in the planes' order (Rp / RC)
   int64_t oa[RB];
 #pragma unroll
-  for (int m = 0; m < RB; ++m) oa[m] = ((int64_t)min(mb0 + m, mbl - 1) * steps_total + rho0 / 16) * 512 + lane * 8;
+  for (int m = 0; m < RB; ++m) oa[m] = ((int64_t)ch * mbl + min(mb0 + m, mbl - 1)) * 512 + lane * 8;
   const float2* row[NB];
 #pragma unroll
   for (int cb = 0; cb < NB; ++cb) row[cb] = a.in + (int64_t)min(16 * cb + (lane & 15), a.J - 1) * a.g.R;
@@ -368,8 +374,8 @@ __global__ __launch_bounds__(NT) void core_adj_bf16_kernel(CoreArgs a, int nch, 
     s = min(s, steps - 1);
 #pragma unroll
     for (int m = 0; m < RB; ++m) {
-      ah[d][m] = ld8(a.adj_hi + oa[m] + (int64_t)s * 512);
-      al[d][m] = ld8(a.adj_lo + oa[m] + (int64_t)s * 512);
+      ah[d][m] = ld8(a.adj_hi + oa[m] + (int64_t)s * nchp * mbl * 512);
+      al[d][m] = ld8(a.adj_lo + oa[m] + (int64_t)s * nchp * mbl * 512);
     }
     call_operand<NB>(row, rho0 + 16 * s, a.g.R, grp, bv[d]);
   };
@@ -510,7 +516,11 @@ __global__ void core_split_kernel(const float2* __restrict__ core, int64_t R, in
                                   int64_t steps, unsigned short* __restrict__ hi, unsigned short* __restrict__ lo) {
   const int64_t total = nrb * steps * 512;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t rb = e / (steps * 512), s = (e / 512) % steps;
+    // step-major, so that the waves of a contraction read one contiguous region per step:
+    // forward (mode 0) [step][row block][lane][8]; adjoint [step within a rho chunk of RC]
+    // [chunk][k row block][lane][8] (its waves each take RB k row blocks of one chunk)
+    const int64_t idx = e / 512, rb = idx % nrb, t = idx / nrb;
+    const int64_t s = mode == 0 ? t : (t % (steps / (RC / 16))) * (RC / 16) + t / (steps / (RC / 16));
     const int lane = (int)((e / 8) % 64), el = (int)(e % 8);
     const int64_t row = 16 * rb + lane % 16, kq = 32 * s + 8 * (lane / 16) + el;
     float f = 0.f;
