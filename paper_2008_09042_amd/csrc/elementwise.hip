@@ -99,42 +99,48 @@ __global__ void scale_copy_kernel(const float2* __restrict__ src, float2* __rest
     dst[e] = cscale(src[e], s);
 }
 
-// The residual of residual_kernel written in a sample order: r[inv[m] J + j].  A thread per
-// sample reads its coils down the columns of E and y (coalesced over m across a wave), eight
-// at a time, and writes its J values as one contiguous run, 16 bytes at a time when J is
-// even.  The loss partials are the same sums, per thread in (m, j) order.
+// The residual of residual_kernel written in a sample order: r[inv[m] J + j].  The work is
+// dealt in chunks of NT samples of one group of eight coils (blocks take chunks in grid-stride
+// order, so every block has work however many coils there are): a thread reads its sample's
+// eight coils down the columns of E and y (coalesced over m across a wave), all sixteen loads
+// in flight together, and writes them as one contiguous run at the sample's position, 16
+// bytes at a time when J is even.  The loss partials are per-thread sums in (chunk, coil)
+// order, added per block as in residual_kernel.
 __global__ void residual_ordered_kernel(const float2* __restrict__ E, const float2* __restrict__ y,
                                         const float* __restrict__ w, int64_t M, int J,
                                         const int32_t* __restrict__ inv, float2* __restrict__ r,
                                         double* __restrict__ part) {
   __shared__ double red[NT];
   double acc = 0.0;
-  for (int64_t m = blockIdx.x * (int64_t)NT + threadIdx.x; m < M; m += (int64_t)gridDim.x * NT) {
+  const int64_t cpg = (M + NT - 1) / NT;  // chunks per coil group
+  const int64_t nchunks = cpg * ((J + 7) / 8);
+  for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    const int64_t g = c / cpg, m = (c - g * cpg) * NT + threadIdx.x;
+    if (m >= M) continue;  // no barrier inside the loop
+    const int j0 = 8 * (int)g;
     const float wm = w ? w[m] : 1.0f;
     float2* dst = r + (int64_t)inv[m] * J;
-    for (int j0 = 0; j0 < J; j0 += 8) {  // eight coils' loads in flight together
-      float2 e[8], v[8];
+    float2 e[8], v[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int j = min(j0 + u, J - 1);
-        e[u] = E[(int64_t)j * M + m];
-        v[u] = y[(int64_t)j * M + m];
-      }
+    for (int u = 0; u < 8; ++u) {
+      const int j = min(j0 + u, J - 1);
+      e[u] = E[(int64_t)j * M + m];
+      v[u] = y[(int64_t)j * M + m];
+    }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const float2 d = csub(e[u], v[u]);
-        if (j0 + u < J) acc += (double)wm * ((double)d.x * d.x + (double)d.y * d.y);
-        e[u] = cscale(d, wm);
-      }
-      if ((J & 1) == 0) {
+    for (int u = 0; u < 8; ++u) {
+      const float2 d = csub(e[u], v[u]);
+      if (j0 + u < J) acc += (double)wm * ((double)d.x * d.x + (double)d.y * d.y);
+      e[u] = cscale(d, wm);
+    }
+    if ((J & 1) == 0) {
 #pragma unroll
-        for (int u = 0; u < 8; u += 2)
-          if (j0 + u < J) reinterpret_cast<float4*>(dst + j0)[u / 2] = make_float4(e[u].x, e[u].y, e[u + 1].x, e[u + 1].y);
-      } else {
+      for (int u = 0; u < 8; u += 2)
+        if (j0 + u < J) reinterpret_cast<float4*>(dst + j0)[u / 2] = make_float4(e[u].x, e[u].y, e[u + 1].x, e[u + 1].y);
+    } else {
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-          if (j0 + u < J) dst[j0 + u] = e[u];
-      }
+      for (int u = 0; u < 8; ++u)
+        if (j0 + u < J) dst[j0 + u] = e[u];
     }
   }
   red[threadIdx.x] = acc;
