@@ -73,21 +73,34 @@ __global__ void reduce_loss_kernel(const double* __restrict__ part, int nblocks,
   if (threadIdx.x == 0) *loss = red[0];
 }
 
+// GX: gx wanted (S read), H: h written in place of g.  Eight coils' loads are issued
+// together (clamped coil index; the coils past J are neither added nor written), and the
+// sum over j keeps its order, so gx is the same bits as one coil at a time.
+template <bool GX, bool H>
 __global__ void adjoint_combine_kernel(const float2* __restrict__ S, float2* __restrict__ g,
                                        const float2* __restrict__ x, int64_t N, int J, float alpha,
-                                       const float* __restrict__ scale_dev, float2* __restrict__ gx,
-                                       int want_h) {
+                                       const float* __restrict__ scale_dev, float2* __restrict__ gx) {
   float s = alpha;
   if (scale_dev) s *= *scale_dev;
   for (int64_t n = blockIdx.x * (int64_t)NT + threadIdx.x; n < N; n += (int64_t)gridDim.x * NT) {
-    const float2 xn = want_h ? x[n] : make_float2(0.f, 0.f);
+    const float2 xn = H ? x[n] : make_float2(0.f, 0.f);
     float2 acc = make_float2(0.f, 0.f);
-    for (int j = 0; j < J; ++j) {
-      const float2 gv = g[(int64_t)j * N + n];
-      if (gx) acc = cadd(acc, cmulc(S[(int64_t)j * N + n], gv));
-      if (want_h) g[(int64_t)j * N + n] = cscale(cmulc(xn, gv), s);
+    for (int j0 = 0; j0 < J; j0 += 8) {
+      float2 gv[8], sv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t j = min(j0 + u, J - 1);
+        gv[u] = g[j * N + n];
+        if (GX) sv[u] = S[j * N + n];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (j0 + u >= J) continue;
+        if (GX) acc = cadd(acc, cmulc(sv[u], gv[u]));
+        if (H) g[(int64_t)(j0 + u) * N + n] = cscale(cmulc(xn, gv[u]), s);
+      }
     }
-    if (gx) gx[n] = cscale(acc, s);
+    if (GX) gx[n] = cscale(acc, s);
   }
 }
 
@@ -190,8 +203,14 @@ hipError_t reduce_loss_launch(const double* part, int nblocks, double* loss, hip
 hipError_t adjoint_combine_launch(const float2* S, float2* g, const float2* x, int64_t N, int J,
                                   float alpha, const float* scale_dev, float2* gx, int want_h,
                                   hipStream_t st) {
-  hipLaunchKernelGGL(adjoint_combine_kernel, dim3(grid_for(N)), dim3(NT), 0, st, S, g, x, N, J, alpha,
-                     scale_dev, gx, want_h);
+  if (N <= 0 || J <= 0) return hipSuccess;
+  const dim3 gr(grid_for(N)), bl(NT);
+  if (gx && want_h)
+    hipLaunchKernelGGL((adjoint_combine_kernel<true, true>), gr, bl, 0, st, S, g, x, N, J, alpha, scale_dev, gx);
+  else if (gx)
+    hipLaunchKernelGGL((adjoint_combine_kernel<true, false>), gr, bl, 0, st, S, g, x, N, J, alpha, scale_dev, gx);
+  else if (want_h)
+    hipLaunchKernelGGL((adjoint_combine_kernel<false, true>), gr, bl, 0, st, S, g, x, N, J, alpha, scale_dev, gx);
   return hipGetLastError();
 }
 
