@@ -314,14 +314,25 @@ __device__ __forceinline__ void adjoint_w(const PlaneArgs& a, const Geo<N0, N1, 
       float2 hv[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) hv[t] = lds[i0 * g.PS + 16 * s + 4 * grp + t];
-      const typename Tile<PREC>::A av = Tile<PREC>::make_a(hv);
       const float4* buf = stage + (s & 1) * sp;
+      if constexpr (RB != 0) {
+        // compile-time rank blocks: the step's B fragments read together, so that their LDS
+        // latencies overlap
+        typename Tile<PREC>::B bf[RB];
 #pragma unroll
-      for (int nb = 0; nb < 3; ++nb)
-        if (nb < g.r1b) {
-          Tile<PREC>::mma(yc[nb], av, frag_b<PREC>(buf, g.r1b, nb, 0, lane));
-          __builtin_amdgcn_sched_barrier(0);  // one B fragment live at a time
-        }
+        for (int nb = 0; nb < RB; ++nb) bf[nb] = frag_b<PREC>(buf, RB, nb, 0, lane);
+        const typename Tile<PREC>::A av = Tile<PREC>::make_a(hv);
+#pragma unroll
+        for (int nb = 0; nb < RB; ++nb) Tile<PREC>::mma(yc[nb], av, bf[nb]);
+      } else {
+        const typename Tile<PREC>::A av = Tile<PREC>::make_a(hv);
+#pragma unroll
+        for (int nb = 0; nb < 3; ++nb)
+          if (nb < g.r1b) {
+            Tile<PREC>::mma(yc[nb], av, frag_b<PREC>(buf, g.r1b, nb, 0, lane));
+            __builtin_amdgcn_sched_barrier(0);  // one B fragment live at a time
+          }
+      }
     }
   };
   float4 o0, o1, e0, e1;  // pieces of the next odd and even steps
