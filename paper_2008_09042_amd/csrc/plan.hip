@@ -578,9 +578,10 @@ maxwell_status plan_build(Plan& p, const maxwell_plan_desc& d, const maxwell_bas
     p.fused = true;
     p.L = (int64_t)pos.size();
     {
-      // coils per plane workgroup: the largest group (up to 4 forward, 16 adjoint) that still
-      // gives every compute unit a workgroup; larger groups amortise the per-workgroup set-up
-      // and, in the adjoint, mean fewer gx partials to sum
+      // coils per plane workgroup: the largest group (up to 16) that still gives every
+      // compute unit a workgroup; larger groups amortise the per-workgroup set-up (the
+      // forward's x share, held in registers across the group's coils) and, in the adjoint,
+      // mean fewer gx partials to sum
       int dev = 0, cus = 256;
       if (hipGetDevice(&dev) == hipSuccess &&
           hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
@@ -590,7 +591,7 @@ maxwell_status plan_build(Plan& p, const maxwell_plan_desc& d, const maxwell_bas
         while (G > 1 && p.n[2] * ((p.J + G - 1) / G) < cus) G /= 2;
         return G;
       };
-      p.G_fwd = pick(4);
+      p.G_fwd = pick(16);
       p.G_adj = pick(16);
     }
     if ((e = hipMalloc(&p.d_pos, pos.size() * sizeof(int32_t))) != hipSuccess) return hip_err(e);

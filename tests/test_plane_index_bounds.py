@@ -1,8 +1,8 @@
 """Host-side bounds check of the fused plane kernels' launch geometry (no GPU).
 
 Restates, in NumPy, the index arithmetic of the plane kernels and their launch as the
-library writes it: the coil-group choice at plan creation (largest group up to 4 forward /
-16 adjoint that still gives every compute unit a workgroup), the grid of n2 * ngroups
+library writes it: the coil-group choice at plan creation (largest group up to 16 coils, in
+either kernel, that still gives every compute unit a workgroup), the grid of n2 * ngroups
 workgroups, the XCD-aware workgroup -> (plane i2, coil group) map, the coil range of a group,
 and the offsets of every per-(coil, plane) and per-(group, plane) block the kernels read or
 write.  Checks that every block lies inside the buffer the plan sizes for it and that each
@@ -40,7 +40,7 @@ def plane_block(ngrp, n2):
 ])
 def test_plane_kernel_blocks_stay_in_their_buffers(n0, n1, n2, r0, r1, J, L):
     N = n0 * n1 * n2
-    for kernel, gmax in (("fwd", 4), ("adj", 16)):
+    for kernel, gmax in (("fwd", 16), ("adj", 16)):
         G = pick(gmax, n2, J)
         G_adj = pick(16, n2, J)
         ngrp = (J + G - 1) // G
