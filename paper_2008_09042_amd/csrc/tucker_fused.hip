@@ -842,16 +842,32 @@ __global__ __launch_bounds__(LNT) void line_fwd_kernel(LineArgs a) {
   const int j = blockIdx.x / lblocks, l0 = (blockIdx.x % lblocks) * LT;
   const int n = N2 ? N2 : a.n2, ES = LT + 1;
   for (int e = threadIdx.x; e < n; e += LNT) tw[e] = a.tw2[e];
-  for (int e = threadIdx.x; e < n * LT; e += LNT) {
-    const int i2 = e / LT, l = e % LT;
-    float2 v = make_float2(0.f, 0.f);
-    if (l0 + l < a.L) v = a.Z[((size_t)j * n + i2) * a.L + l0 + l];
-    if (i2 & 1) v = make_float2(-v.x, -v.y);
-    tile[i2 * ES + l] = v;
-  }
-  // With the compile-time readout, the measured samples of this thread's outputs are
-  // loaded here, ahead of the transform (lines past L read line L - 1).
+  // With the compile-time readout, the thread's Z values are loaded together, unguarded (lines
+  // past L read line L - 1 and are zeroed), before any is stored; then the measured samples of
+  // its outputs, ahead of the transform.
   constexpr int YQ = N2 ? N2 * LT / LNT : 1;
+  if constexpr (N2 != 0) {
+    float2 zv[YQ];
+#pragma unroll
+    for (int q = 0; q < YQ; ++q) {
+      const int e = threadIdx.x + q * LNT, i2 = e / LT, l = e % LT;
+      zv[q] = a.Z[((size_t)j * n + i2) * a.L + min(l0 + l, (int)a.L - 1)];
+    }
+#pragma unroll
+    for (int q = 0; q < YQ; ++q) {
+      const int e = threadIdx.x + q * LNT, i2 = e / LT, l = e % LT;
+      const float m = l0 + l < a.L ? ((i2 & 1) ? -1.f : 1.f) : 0.f;
+      tile[i2 * ES + l] = make_float2(zv[q].x * m, zv[q].y * m);
+    }
+  } else {
+    for (int e = threadIdx.x; e < n * LT; e += LNT) {
+      const int i2 = e / LT, l = e % LT;
+      float2 v = make_float2(0.f, 0.f);
+      if (l0 + l < a.L) v = a.Z[((size_t)j * n + i2) * a.L + l0 + l];
+      if (i2 & 1) v = make_float2(-v.x, -v.y);
+      tile[i2 * ES + l] = v;
+    }
+  }
   float2 yv[YQ];
   if constexpr (N2 != 0) {
     if (a.y) {
