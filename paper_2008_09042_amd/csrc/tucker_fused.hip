@@ -934,12 +934,30 @@ __global__ __launch_bounds__(LNT) void line_adj_kernel(LineArgs a) {
   const int j = blockIdx.x / lblocks, l0 = (blockIdx.x % lblocks) * LT;
   const int n = N2 ? N2 : a.n2, ES = LT + 1;
   for (int e = threadIdx.x; e < n; e += LNT) tw[e] = a.tw2[e];
-  for (int e = threadIdx.x; e < n * LT; e += LNT) {
-    const int l = e / n, k2 = e % n;
-    float2 v = make_float2(0.f, 0.f);
-    if (l0 + l < a.L) v = a.yin[(size_t)j * a.M + (size_t)(l0 + l) * n + k2];
-    if (k2 & 1) v = make_float2(-v.x, -v.y);
-    tile[k2 * ES + l] = v;
+  if constexpr (N2 != 0) {
+    // the thread's samples loaded together and unguarded (lines past L read line L - 1 and
+    // are zeroed), as in the forward line kernel
+    constexpr int YQ = N2 * LT / LNT;
+    float2 yv[YQ];
+#pragma unroll
+    for (int q = 0; q < YQ; ++q) {
+      const int e = threadIdx.x + q * LNT, l = e / N2, k2 = e % N2;
+      yv[q] = a.yin[(size_t)j * a.M + (size_t)min(l0 + l, (int)a.L - 1) * N2 + k2];
+    }
+#pragma unroll
+    for (int q = 0; q < YQ; ++q) {
+      const int e = threadIdx.x + q * LNT, l = e / N2, k2 = e % N2;
+      const float m = l0 + l < a.L ? ((k2 & 1) ? -1.f : 1.f) : 0.f;
+      tile[k2 * ES + l] = make_float2(yv[q].x * m, yv[q].y * m);
+    }
+  } else {
+    for (int e = threadIdx.x; e < n * LT; e += LNT) {
+      const int l = e / n, k2 = e % n;
+      float2 v = make_float2(0.f, 0.f);
+      if (l0 + l < a.L) v = a.yin[(size_t)j * a.M + (size_t)(l0 + l) * n + k2];
+      if (k2 & 1) v = make_float2(-v.x, -v.y);
+      tile[k2 * ES + l] = v;
+    }
   }
   __syncthreads();
   line_fft<N2>(a, tile, tw, n, +1);
